@@ -1,0 +1,189 @@
+"""Physics pins of the oracle: Mie series (the paper's own validation, Sec. IV-A), the
+transparent-object identity, reproduction of interior fields by the internal equation,
+energy balance against Mie absorption, and the equivalence of the augmented, reduced and
+final (explicit-Y) systems.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+
+import meshgen
+from oracle import constants as C
+from oracle import mie
+from oracle import operators as O
+from oracle import quadrature as Q
+from oracle import systems as S
+
+_cache = {}
+
+
+def sphere(level, k0a, eps, eps_bg=1.0):
+    key = (level, k0a, complex(eps), complex(eps_bg))
+    if key not in _cache:
+        w = meshgen.sphere_workload(level, k0a, eps)
+        prob = S.Problem(w.freq_hz, w.eps_r, w.mu_r, w.sigma, eps_bg=eps_bg)
+        ops = S.assemble(w.xyz, w.tri, w.obj, prob)
+        b = S.rhs(ops, w.khat[0], w.pol[0])
+        _cache[key] = (w, ops, b, S.solve_augmented(ops, b))
+    return _cache[key]
+
+
+def rcs_error(level, k0a=1.0, eps=4.0):
+    w, ops, b, sol = sphere(level, k0a, eps)
+    th = np.linspace(0, math.pi, 61)
+    errs = []
+    for phi in (0.0, math.pi / 2):
+        rh = np.stack([np.sin(th) * np.cos(phi), np.sin(th) * np.sin(phi), np.cos(th)], 1)
+        s_bem = S.rcs(ops, sol, rh)
+        s_mie = mie.bistatic_rcs(eps, 1.0, ops.k0, th, phi)
+        errs.append(np.linalg.norm(s_bem - s_mie) / np.linalg.norm(s_mie))
+    return max(errs)
+
+
+def test_mie_rcs_converges():
+    """Bistatic RCS (phi = 0 and 90 deg) of the eps_r = 4, k0 a = 1 sphere: a few per cent at
+    320 triangles, and at least first-order decrease under refinement."""
+    e80, e320 = rcs_error(1), rcs_error(2)
+    print(f"RCS rel L2 error vs Mie: 80 tri {e80:.3e}, 320 tri {e320:.3e}")
+    assert e320 < 0.10
+    assert e80 / e320 > 1.6
+
+
+def test_transparent_object_identity():
+    """eps_c = eps_l, mu_r = mu_l: the equivalent and original problems coincide, so the
+    differential current vanishes and I_x e = b (final system with explicit Y)."""
+    w = meshgen.sphere_workload(1, 1.5, 2.0)
+    prob = S.Problem(w.freq_hz, [2.0 - 0.3j], [1.0], [0.0], eps_bg=2.0 - 0.3j)
+    ops = S.assemble(w.xyz, w.tri, w.obj, prob)
+    b = S.rhs(ops, w.khat[0], w.pol[0])
+    sol = S.solve_final(ops, b)
+    assert np.linalg.norm(sol.a - sol.a_eq) < 1e-12 * np.linalg.norm(sol.a)
+    assert np.linalg.norm(ops.Ix @ sol.e - b) < 1e-12 * np.linalg.norm(b)
+    rh = np.array([[0.0, 0.0, 1.0], [1.0, 0.0, 0.0]])
+    assert np.all(S.rcs(ops, sol, rh) < 1e-20)
+
+
+def test_printed_plus_K_is_inconsistent():
+    """Reading of the middle block of the final system: with +K as printed the solution no
+    longer satisfies the augmented (plain) equations; with -K it does to round-off."""
+    w, ops, b, ref = sphere(1, 1.0, 4.0)
+    A = S.final_matrix(ops)
+    ne = len(ops.topo.edges)
+    K = ops.K_int + 0.5 * ops.Ix
+    A_plus = A.copy()
+    A_plus[ne:2 * ne, ne:2 * ne] = +K
+    r = np.zeros(A.shape[0], complex)
+    r[:ne] = b
+    x = np.linalg.solve(A, r)
+    x_plus = np.linalg.solve(A_plus, r)
+    assert np.linalg.norm(x[:ne] - ref.a) < 1e-10 * np.linalg.norm(ref.a)
+    assert np.linalg.norm(x_plus[:ne] - ref.a) > 1e-2 * np.linalg.norm(ref.a)
+
+
+def test_augmented_reduced_final_agree():
+    w, ops, b, aug = sphere(1, 2.0, 2.5 - 0.1j)
+    a2, e2, q2 = S.solve_reduced_single(ops, b)
+    fin = S.solve_final(ops, b)
+    for got, want in ((a2, aug.a), (e2, aug.e), (q2, aug.q), (fin.a, aug.a), (fin.e, aug.e), (fin.q, aug.q),
+                      (fin.a_eq, aug.a_eq), (fin.q_eq, aug.q_eq)):
+        assert np.linalg.norm(got - want) < 1e-11 * np.linalg.norm(want)
+
+
+def _project_fields(ops, E_fun, H_fun):
+    """Galerkin projections: n x H on RWG (Gram solve), n x E on BC (I_x solve)."""
+    topo = ops.topo
+    V = O.tri_vertices(topo)
+    bq, wq = Q.q7()
+    pts = Q.points(V, bq)
+    ne = len(topo.edges)
+    gram = np.zeros((ne, ne))
+    rhs_h = np.zeros(ne, complex)
+    rhs_e = np.zeros(ne, complex)
+    Hs = H_fun(pts.reshape(-1, 3)).reshape(pts.shape)
+    Es = E_fun(pts.reshape(-1, 3)).reshape(pts.shape)
+    nxH = np.cross(topo.normal[:, None, :], Hs)
+    f = [topo.tri_signs[:, i][:, None, None] * (pts - V[:, i][:, None, :]) / (2 * topo.area[:, None, None])
+         for i in range(3)]
+    for i in range(3):
+        np.add.at(rhs_h, topo.tri_edges[:, i], topo.area * np.einsum("k,tkc,tkc->t", wq, f[i], nxH))
+        np.add.at(rhs_e, topo.tri_edges[:, i], topo.area * np.einsum("k,tkc,tkc->t", wq, f[i], Es))
+        for j in range(3):
+            np.add.at(gram, (topo.tri_edges[:, i], topo.tri_edges[:, j]),
+                      topo.area * np.einsum("k,tkc,tkc->t", wq, f[i], f[j]))
+    h = np.linalg.solve(gram, rhs_h)
+    e_coef = np.linalg.solve(ops.Ix, rhs_e)
+    return h, e_coef
+
+
+def _interior_residual(level):
+    w, ops, b, _ = sphere(level, 1.0, 4.0)
+    k = ops.k_int[0]
+    eta = C.ETA0 * np.sqrt(ops.mu_r[0] / ops.epsc[0])
+    kh = np.array([0.3, -0.5, 0.8]); kh /= np.linalg.norm(kh)
+    p = np.cross(kh, [1.0, 0.0, 0.0]); p /= np.linalg.norm(p)
+    E_fun = lambda r: p[None, :] * np.exp(-1j * k * (r @ kh))[:, None]
+    H_fun = lambda r: np.cross(kh, E_fun(r)) / eta
+    h, eps_coef = _project_fields(ops, E_fun, H_fun)
+    a = 1j * ops.k0 * h
+    e = eps_coef / C.ETA0
+    q = (ops.F @ ops.D @ a) / ops.k0 ** 2
+    Kf = ops.K_int + 0.5 * ops.Ix
+    lhs = ops.mu_r[0] * ops.LA_int @ a - (1 / ops.epsc[0]) * ops.D.T @ ops.Lphi_int @ ops.B @ q
+    res = np.linalg.norm(lhs - Kf @ e) / np.linalg.norm(Kf @ e)
+    flipped = np.linalg.norm(lhs - (-ops.K_int + 0.5 * ops.Ix) @ e) / np.linalg.norm(Kf @ e)
+    return res, flipped
+
+
+def test_interior_field_reproduction():
+    """A plane wave of the interior medium satisfies the internal equation (eq. AEFIEintdis,
+    row 1) up to discretisation error that falls under refinement; flipping the sign of K~
+    gives an O(1) residual (pins the gradient/jump reading of K)."""
+    r1, f1 = _interior_residual(1)
+    r2, f2 = _interior_residual(2)
+    print(f"interior residual: 80 tri {r1:.3e} (flipped K {f1:.3e}), 320 tri {r2:.3e} (flipped {f2:.3e})")
+    assert r2 < r1 and r2 < 0.1
+    assert f2 > 0.5
+
+
+def _absorbed_power(level, k0a, eps):
+    """P_abs = -1/2 Re oint (E x H*) . n dS from the surface unknowns (exact Q3 on sub-triangles)."""
+    w, ops, b, sol = sphere(level, k0a, eps)
+    topo, bary = ops.topo, ops.bary
+    idx, alpha, beta = O.bc_on_subtriangles(bary)
+    Jc = sol.H(ops.k0)          # n x H on RWG
+    Ec = sol.E()                # n x E on BC
+    b3, w3 = Q.q3()
+    P = 0.0
+    for s in range(len(bary.tri)):
+        t = bary.parent[s]
+        rp = Q.points(bary.xyz[bary.tri[s]], b3)
+        u = np.zeros((3, 3), complex)
+        for bb in range(idx.shape[1]):
+            n = idx[s, bb]
+            if n >= 0:
+                u += Ec[n] * (alpha[s, bb] * rp - beta[s, bb]) / (2 * bary.area[s])
+        J = np.zeros((3, 3), complex)
+        for i in range(3):
+            J += Jc[topo.tri_edges[t, i]] * topo.tri_signs[t, i] * (rp - topo.xyz[topo.tri[t, i]]) / (2 * topo.area[t])
+        Ht = np.cross(J, topo.normal[t][None, :])        # H_tan = J x n
+        P += bary.area[s] * np.sum(w3 * np.einsum("jc,jc->j", u, np.conj(Ht))).real
+    return -0.5 * P
+
+
+def test_energy_balance_against_mie():
+    # lossless object: no absorbed power (relative to the scattered power)
+    k0a = 1.0
+    pa = _absorbed_power(2, k0a, 4.0)
+    qe, qs, _ = mie.efficiencies(2.0, k0a)
+    p_sca = qs * math.pi / (2 * C.ETA0)
+    assert abs(pa) < 0.05 * p_sca
+    # lossy object: absorbed power matches the Mie absorption cross-section
+    eps = 2.5 - 0.5j
+    pa = _absorbed_power(2, k0a, eps)
+    qe, qs, _ = mie.efficiencies(np.sqrt(np.conj(eps)), k0a)
+    p_abs = (qe - qs) * math.pi / (2 * C.ETA0)
+    print(f"absorbed power: BEM {pa:.4e}, Mie {p_abs:.4e}")
+    assert pa > 0 and abs(pa - p_abs) < 0.1 * p_abs
