@@ -1,0 +1,207 @@
+/*
+ * bem.h - C ABI of the MI355X dense single-layer dual-mesh BEM library (libbem.so).
+ *
+ * The library assembles and applies the Galerkin operators of the single-layer
+ * dual-mesh boundary element method for penetrable objects (Sharma & Triverio,
+ * Sec. II) on one AMD Instinct MI355X (gfx950) and solves the final system
+ * (eq. finalsystem) with GMRES, the equivalent-configuration system
+ * (eq. AEFIEeqvdis) being solved on the fly for every product (Sec. III).
+ *
+ * Conventions
+ *  - Every call returns a status code (BEM_OK = 0, negative on error); no
+ *    exception or signal crosses the ABI.  bem_last_error() describes the last
+ *    failure on the calling thread.
+ *  - Handles are opaque 64-bit integers owned by the context; bem_release()
+ *    frees them.  The library owns every device-resident operator and every
+ *    Krylov state; the caller owns all buffers it passes in.
+ *  - Complex numbers are interleaved (re, im) pairs: bem_c64 for float64,
+ *    two floats for float32.
+ *  - Time dependence e^{+j omega t}; G = e^{-jkR}/(4 pi R) (eq. hgf);
+ *    eps_c = eps_r - j sigma/(omega eps0) (eq. epsrc); mu0 = 4 pi 1e-7 H/m.
+ *  - Unknown ordering of the final system: [a; e; x3] with a = jk0 H (one per
+ *    edge, RWG), e = E/eta0 (one per edge, Buffa-Christiansen), x3 = -c0 rho'
+ *    (one per triangle minus one per object; each object's highest-index
+ *    triangle carries minus the sum of its other charges).
+ *  - Edges are numbered by the library (bem_edge_table gives their vertex
+ *    pairs); triangles and vertices keep the caller's numbering.
+ *  - A context is not thread-safe: calls on one context must not overlap, except
+ *    bem_poll, which may be called from any thread.
+ */
+#ifndef BEM_H
+#define BEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bem_ctx bem_ctx;
+typedef uint64_t bem_mesh_h;
+typedef uint64_t bem_op_h;
+typedef uint64_t bem_ticket;
+typedef struct { double re, im; } bem_c64;
+
+enum {
+  BEM_OK = 0,
+  BEM_PENDING = 1,
+  BEM_E_INVALID = -1,       /* bad argument, unknown handle, wrong state */
+  BEM_E_MESH = -2,          /* mesh not closed / not 2-manifold / not outward / degenerate */
+  BEM_E_NOMEM = -3,         /* over the context's HBM budget, or allocation failure */
+  BEM_E_NOT_CONVERGED = -4, /* iteration limit reached; best iterate written */
+  BEM_E_DEVICE = -5,        /* HIP runtime error, or a device call on a host-only context */
+  BEM_E_NUMERIC = -6        /* NaN/Inf in an input or in a residual */
+};
+
+enum { BEM_FP64 = 0, BEM_MIXED = 2 };
+
+/* Dense operator blocks addressable through bem_apply / bem_block_export. */
+enum {
+  BEM_BLOCK_FINAL = 0,    /* the final system of eq. finalsystem, (N x N), N = 2 NE + NQ */
+  BEM_BLOCK_LA_INT = 1,   /* L^(A) at the object wavenumber k (eq. opLAhgf), NE x NE, block-diagonal */
+  BEM_BLOCK_LPHI_INT = 2, /* L^(phi) at k (eq. opLphihgf), NT x NT, block-diagonal */
+  BEM_BLOCK_K_INT = 3,    /* K~ at k (eq. opKhgf) on BC sources, NE x NE, block-diagonal */
+  BEM_BLOCK_LA_BG = 4,    /* L^(A) at the background wavenumber k_l, NE x NE, all pairs */
+  BEM_BLOCK_LPHI_BG = 5,  /* L^(phi) at k_l, NT x NT, all pairs */
+  BEM_BLOCK_K_BG = 6,     /* K~ at k_l, NE x NE, block-diagonal */
+  BEM_BLOCK_IX = 7,       /* Gram matrix I_x (BC tested with n x RWG), NE x NE, sparse */
+  BEM_BLOCK_MEQ = 8       /* equivalent-configuration matrix of eq. AEFIEeqvdis, (NE+NQ)^2 */
+};
+
+/* Context.  device >= 0 selects a HIP device; device = -1 gives a host-only
+ * context on which mesh loading, validation and the mesh queries work but
+ * assemble/apply/solve return BEM_E_DEVICE.  hbm_budget_bytes = 0 means the
+ * whole free device memory.  Errors: BEM_E_DEVICE (no such device). */
+int bem_create(int device, size_t hbm_budget_bytes, bem_ctx** out);
+void bem_destroy(bem_ctx* ctx);
+/* Message of the last failing call on this thread; valid until the next call. */
+const char* bem_last_error(const bem_ctx* ctx);
+
+/* Load a closed triangle mesh (Sec. II: objects with closed surfaces and outward
+ * normal).  xyz: nv*3 float64 (m), host; tri: nt*3 int32, counter-clockwise about
+ * the outward normal, host; obj: nt int32 object ids 0..n_obj-1, non-decreasing
+ * along the triangle list (each object contiguous), or NULL for one object.
+ * Everything is copied.  BEM_E_MESH if a surface is open, non-manifold,
+ * inconsistently or inward oriented, has a degenerate triangle, or objects
+ * share an edge (junctions are not supported, Sec. II-E). */
+int bem_mesh_load(bem_ctx* ctx, const double* xyz, int64_t nv, const int32_t* tri, int64_t nt,
+                  const int32_t* obj, bem_mesh_h* out);
+/* Sizes: triangles, edges (RWG and BC functions), objects and final unknowns
+ * N = 2 NE + NT - n_obj. */
+int bem_mesh_info(bem_ctx* ctx, bem_mesh_h mesh, int64_t* n_tri, int64_t* n_edge, int64_t* n_obj,
+                  int64_t* n_unknowns);
+/* Edge table in the library's order (host buffers of NE entries each, any may be
+ * NULL): vertex pair va < vb, T+ (triangle traversing va -> vb counter-
+ * clockwise) and T-.  The RWG of an edge flows from T+ into T- with unit flux;
+ * its BC function flows from the dual cell of va into that of vb. */
+int bem_edge_table(bem_ctx* ctx, bem_mesh_h mesh, int32_t* va, int32_t* vb, int32_t* tplus,
+                   int32_t* tminus);
+/* Near-pair structure used by the singular quadrature: for each triangle T the
+ * sorted list of triangles T' sharing a vertex with T or whose centroid lies
+ * closer than (2 - 2e-9) * max(longest edge of T, of T').  ptr: NT+1 int64, idx:
+ * ptr[NT] int32 (call once with idx = NULL to size it).  Host buffers. */
+int bem_near_pairs(bem_ctx* ctx, bem_mesh_h mesh, int64_t* ptr, int32_t* idx);
+
+typedef struct { bem_c64 eps_r; double mu_r, sigma; } bem_material;
+typedef struct {
+  double freq_hz;
+  bem_c64 eps_bg;               /* background (homogeneous layer l) relative permittivity */
+  double mu_bg;
+  const bem_material* obj;      /* n_obj materials, host */
+  int64_t n_obj;
+  int precision;                /* BEM_FP64, or BEM_MIXED: float32 copies of the dense blocks
+                                   for the Krylov products, float64 residual refinement */
+} bem_problem;
+
+/* Fill every dense block on the device: L^A, L^phi and K~ at the object
+ * wavenumbers (interior, eq. AEFIEintdis) and at the background wavenumber
+ * (eqs. AEFIEeqvdis and AEFIEextdis), the sparse D, F, B and I_x, and, with
+ * BEM_MIXED, their float32 copies.  Runs synchronously on the context's
+ * stream.  BEM_E_NOMEM if the blocks exceed the HBM budget. */
+int bem_assemble(bem_ctx* ctx, bem_mesh_h mesh, const bem_problem* prob, bem_op_h* out);
+
+/* y = A x for `block` (see above), nrhs columns.  x, y: device pointers, column-
+ * major, leading dimension = the block's row/column count, complex float64;
+ * stream: a hipStream_t or NULL for the context's stream (the call is
+ * asynchronous on it, except BEM_BLOCK_FINAL, whose inner solve synchronises).
+ * BEM_BLOCK_FINAL applies eq. finalsystem with the equivalent-configuration
+ * solve (eq. AEFIEeqvdis) done by GMRES to the relative tolerance set by
+ * bem_set_inner_tol (default 1e-12). */
+int bem_apply(bem_ctx* ctx, bem_op_h op, int block, const void* x, void* y, int64_t nrhs, void* stream);
+/* Copy a dense block (blocks 1..7) into a host buffer, row-major complex
+ * float64, rows x cols as documented above (block-diagonal blocks include
+ * their zero off-diagonal parts). */
+int bem_block_export(bem_ctx* ctx, bem_op_h op, int block, bem_c64* host_dst);
+int bem_set_inner_tol(bem_ctx* ctx, bem_op_h op, double tol);
+
+enum { BEM_EXC_PLANE_WAVE = 0, BEM_EXC_DELTA_GAP = 1 };
+typedef struct {
+  int kind;
+  double khat[3];               /* plane wave: unit propagation direction */
+  bem_c64 pol[3];               /* plane wave: polarisation (orthogonal to khat) */
+  bem_c64 amp;                  /* plane wave: E0 (V/m); delta gap: voltage (V) */
+  const int32_t* gap_edges;     /* delta gap: 2*n_gap vertex pairs (host), gap across each edge */
+  int64_t n_gap;
+} bem_excitation;
+
+typedef struct {
+  double tol;                   /* relative residual ||b - A x|| / ||b|| in float64 */
+  int restart;                  /* GMRES restart length */
+  int maxit;                    /* total outer iteration limit */
+  double inner_tol;             /* relative tolerance of the equivalent-configuration solve;
+                                   <= 0 selects 0.1 * tol */
+  int max_refine;               /* BEM_MIXED: maximum refinement sweeps */
+  int out_device;               /* 1: H, E, rho are device pointers; 0: host */
+} bem_solve_opts;
+
+typedef struct {
+  int outer_iters;              /* total outer GMRES iterations (all sweeps) */
+  int inner_iters_max;          /* largest inner GMRES iteration count of one product */
+  int refine_steps;             /* float64 residual evaluations (BEM_MIXED) */
+  int n_products;               /* applications of the final system */
+  double rel_residual;          /* final float64 relative residual (worst excitation) */
+  double seconds;
+} bem_solve_info;
+
+/* Solve eq. finalsystem for nexc excitations (right-hand side of eq.
+ * AEFIEextdis: b_m = eta0^-1 int f_m . E_inc).  Outputs, column-major with nexc
+ * columns: H (NE x nexc) coefficients of n x H on RWG functions, E (NE x nexc)
+ * coefficients of n x E on BC functions, rho (NT x nexc) charge density
+ * coefficients on area-normalised pulses (the full, un-reduced vector).  Any
+ * output may be NULL.  On BEM_E_NOT_CONVERGED the best iterate is written. */
+int bem_solve(bem_ctx* ctx, bem_op_h op, const bem_excitation* exc, int64_t nexc,
+              const bem_solve_opts* opts, bem_c64* H, bem_c64* E, bem_c64* rho, bem_solve_info* info);
+
+/* Asynchronous serving (continuous batching).  A request carries its own mesh,
+ * problem, excitations and options; all arrays are copied at submit time except
+ * the output buffers (host), which must stay valid until bem_poll returns
+ * something other than BEM_PENDING.  Requests are admitted while their
+ * estimated device footprint fits the HBM budget; admitted requests progress
+ * together and share batched product launches. */
+typedef struct {
+  const double* xyz; int64_t nv;
+  const int32_t* tri; int64_t nt;
+  const int32_t* obj;
+  bem_problem prob;
+  const bem_excitation* exc; int64_t nexc;
+  bem_solve_opts opts;
+  bem_c64* H; bem_c64* E; bem_c64* rho;   /* host outputs, as for bem_solve */
+} bem_request;
+int bem_submit(bem_ctx* ctx, const bem_request* req, bem_ticket* out);
+/* BEM_PENDING while queued or running; otherwise the request's final status
+ * (its outputs are then written) and info is filled.  The ticket is retired
+ * when a final status is returned. */
+int bem_poll(bem_ctx* ctx, bem_ticket ticket, bem_solve_info* info);
+/* Block until no submitted request is pending. */
+int bem_drain(bem_ctx* ctx);
+
+/* Free a mesh or operator handle and its device memory. */
+int bem_release(bem_ctx* ctx, uint64_t handle);
+/* Device bytes currently held by the context. */
+int bem_memory_in_use(bem_ctx* ctx, size_t* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BEM_H */

@@ -1,0 +1,262 @@
+"""Python binding of libbem (MI355X dense single-layer dual-mesh BEM).
+
+Argument marshalling only: every computation runs in libbem.so (HIP kernels for gfx950 and
+the C++ host code behind the C ABI of include/bem.h).  The function names are those of the
+C ABI.  Device vectors are passed as raw pointers (e.g. torch tensors' data_ptr()).
+
+Loading fails loudly when the library has not been built (python -m paper_2106_06184_amd.build).
+"""
+from __future__ import annotations
+
+import ctypes as C
+from pathlib import Path
+
+import numpy as np
+
+_LIB_PATH = Path(__file__).resolve().parent / "libbem.so"
+
+BEM_OK, BEM_PENDING = 0, 1
+BEM_E_INVALID, BEM_E_MESH, BEM_E_NOMEM, BEM_E_NOT_CONVERGED, BEM_E_DEVICE, BEM_E_NUMERIC = -1, -2, -3, -4, -5, -6
+BEM_FP64, BEM_MIXED = 0, 2
+(BEM_BLOCK_FINAL, BEM_BLOCK_LA_INT, BEM_BLOCK_LPHI_INT, BEM_BLOCK_K_INT, BEM_BLOCK_LA_BG,
+ BEM_BLOCK_LPHI_BG, BEM_BLOCK_K_BG, BEM_BLOCK_IX, BEM_BLOCK_MEQ) = range(9)
+BEM_EXC_PLANE_WAVE, BEM_EXC_DELTA_GAP = 0, 1
+
+SYMBOLS = ["bem_create", "bem_destroy", "bem_last_error", "bem_mesh_load", "bem_mesh_info", "bem_edge_table",
+           "bem_near_pairs", "bem_assemble", "bem_apply", "bem_block_export", "bem_set_inner_tol", "bem_solve",
+           "bem_submit", "bem_poll", "bem_drain", "bem_release", "bem_memory_in_use"]
+
+
+class c64(C.Structure):
+    _fields_ = [("re", C.c_double), ("im", C.c_double)]
+
+
+class bem_material(C.Structure):
+    _fields_ = [("eps_r", c64), ("mu_r", C.c_double), ("sigma", C.c_double)]
+
+
+class bem_problem(C.Structure):
+    _fields_ = [("freq_hz", C.c_double), ("eps_bg", c64), ("mu_bg", C.c_double),
+                ("obj", C.POINTER(bem_material)), ("n_obj", C.c_int64), ("precision", C.c_int)]
+
+
+class bem_excitation(C.Structure):
+    _fields_ = [("kind", C.c_int), ("khat", C.c_double * 3), ("pol", c64 * 3), ("amp", c64),
+                ("gap_edges", C.POINTER(C.c_int32)), ("n_gap", C.c_int64)]
+
+
+class bem_solve_opts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("restart", C.c_int), ("maxit", C.c_int), ("inner_tol", C.c_double),
+                ("max_refine", C.c_int), ("out_device", C.c_int)]
+
+
+class bem_solve_info(C.Structure):
+    _fields_ = [("outer_iters", C.c_int), ("inner_iters_max", C.c_int), ("refine_steps", C.c_int),
+                ("n_products", C.c_int), ("rel_residual", C.c_double), ("seconds", C.c_double)]
+
+
+class bem_request(C.Structure):
+    _fields_ = [("xyz", C.POINTER(C.c_double)), ("nv", C.c_int64), ("tri", C.POINTER(C.c_int32)),
+                ("nt", C.c_int64), ("obj", C.POINTER(C.c_int32)), ("prob", bem_problem),
+                ("exc", C.POINTER(bem_excitation)), ("nexc", C.c_int64), ("opts", bem_solve_opts),
+                ("H", C.POINTER(c64)), ("E", C.POINTER(c64)), ("rho", C.POINTER(c64))]
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """The loaded libbem.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not _LIB_PATH.exists():
+            raise RuntimeError(f"{_LIB_PATH} is missing: build it with `python -m paper_2106_06184_amd.build`")
+        L = C.CDLL(str(_LIB_PATH))
+        P, I64, I32, D = C.c_void_p, C.c_int64, C.c_int32, C.c_double
+        sig = {
+            "bem_create": (C.c_int, [C.c_int, C.c_size_t, C.POINTER(P)]),
+            "bem_destroy": (None, [P]),
+            "bem_last_error": (C.c_char_p, [P]),
+            "bem_mesh_load": (C.c_int, [P, C.POINTER(D), I64, C.POINTER(I32), I64, C.POINTER(I32), C.POINTER(C.c_uint64)]),
+            "bem_mesh_info": (C.c_int, [P, C.c_uint64, C.POINTER(I64), C.POINTER(I64), C.POINTER(I64), C.POINTER(I64)]),
+            "bem_edge_table": (C.c_int, [P, C.c_uint64, C.POINTER(I32), C.POINTER(I32), C.POINTER(I32), C.POINTER(I32)]),
+            "bem_near_pairs": (C.c_int, [P, C.c_uint64, C.POINTER(I64), C.POINTER(I32)]),
+            "bem_assemble": (C.c_int, [P, C.c_uint64, C.POINTER(bem_problem), C.POINTER(C.c_uint64)]),
+            "bem_apply": (C.c_int, [P, C.c_uint64, C.c_int, P, P, I64, P]),
+            "bem_block_export": (C.c_int, [P, C.c_uint64, C.c_int, C.POINTER(c64)]),
+            "bem_set_inner_tol": (C.c_int, [P, C.c_uint64, D]),
+            "bem_solve": (C.c_int, [P, C.c_uint64, C.POINTER(bem_excitation), I64, C.POINTER(bem_solve_opts),
+                                    C.POINTER(c64), C.POINTER(c64), C.POINTER(c64), C.POINTER(bem_solve_info)]),
+            "bem_submit": (C.c_int, [P, C.POINTER(bem_request), C.POINTER(C.c_uint64)]),
+            "bem_poll": (C.c_int, [P, C.c_uint64, C.POINTER(bem_solve_info)]),
+            "bem_drain": (C.c_int, [P]),
+            "bem_release": (C.c_int, [P, C.c_uint64]),
+            "bem_memory_in_use": (C.c_int, [P, C.POINTER(C.c_size_t)]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+class BemError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libbem status {code}: {msg}")
+        self.code = code
+
+
+def _check(ctx, rc: int, allow=(BEM_OK,)) -> int:
+    if rc not in allow:
+        raise BemError(rc, lib().bem_last_error(ctx).decode())
+    return rc
+
+
+# ------------------------------------------------------------- marshalling helpers
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _iptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def _cptr(a):
+    return a.ctypes.data_as(C.POINTER(c64)) if a is not None else None
+
+
+def bem_create(device: int = 0, budget: int = 0):
+    p = C.c_void_p()
+    _check(None, lib().bem_create(device, budget, C.byref(p)))
+    return p
+
+
+def bem_destroy(ctx) -> None:
+    lib().bem_destroy(ctx)
+
+
+def bem_last_error(ctx) -> str:
+    return lib().bem_last_error(ctx).decode()
+
+
+def bem_mesh_load(ctx, xyz, tri, obj=None) -> int:
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+    tri = np.ascontiguousarray(tri, dtype=np.int32)
+    o = np.ascontiguousarray(obj, dtype=np.int32) if obj is not None else None
+    h = C.c_uint64()
+    _check(ctx, lib().bem_mesh_load(ctx, _dptr(xyz), len(xyz), _iptr(tri), len(tri),
+                                    _iptr(o) if o is not None else None, C.byref(h)))
+    return h.value
+
+
+def bem_mesh_info(ctx, mesh: int) -> dict:
+    v = [C.c_int64() for _ in range(4)]
+    _check(ctx, lib().bem_mesh_info(ctx, mesh, *[C.byref(x) for x in v]))
+    return dict(n_tri=v[0].value, n_edge=v[1].value, n_obj=v[2].value, n_unknowns=v[3].value)
+
+
+def bem_edge_table(ctx, mesh: int):
+    ne = bem_mesh_info(ctx, mesh)["n_edge"]
+    out = [np.zeros(ne, np.int32) for _ in range(4)]
+    _check(ctx, lib().bem_edge_table(ctx, mesh, *[_iptr(a) for a in out]))
+    return out  # va, vb, tplus, tminus
+
+
+def bem_near_pairs(ctx, mesh: int):
+    nt = bem_mesh_info(ctx, mesh)["n_tri"]
+    ptr = np.zeros(nt + 1, np.int64)
+    _check(ctx, lib().bem_near_pairs(ctx, mesh, ptr.ctypes.data_as(C.POINTER(C.c_int64)), None))
+    idx = np.zeros(int(ptr[-1]), np.int32)
+    _check(ctx, lib().bem_near_pairs(ctx, mesh, ptr.ctypes.data_as(C.POINTER(C.c_int64)), _iptr(idx)))
+    return ptr, idx
+
+
+def make_problem(freq_hz, eps_r, mu_r, sigma, eps_bg=1.0, mu_bg=1.0, precision=BEM_FP64):
+    mats = (bem_material * len(eps_r))()
+    for i, (e, m, s) in enumerate(zip(eps_r, mu_r, sigma)):
+        mats[i] = bem_material(c64(complex(e).real, complex(e).imag), float(m), float(s))
+    p = bem_problem(float(freq_hz), c64(complex(eps_bg).real, complex(eps_bg).imag), float(mu_bg),
+                    C.cast(mats, C.POINTER(bem_material)), len(eps_r), int(precision))
+    p._keep = mats
+    return p
+
+
+def bem_assemble(ctx, mesh: int, prob: bem_problem) -> int:
+    h = C.c_uint64()
+    _check(ctx, lib().bem_assemble(ctx, mesh, C.byref(prob), C.byref(h)))
+    return h.value
+
+
+def bem_apply(ctx, op: int, block: int, x_ptr: int, y_ptr: int, nrhs: int = 1, stream: int | None = None) -> None:
+    _check(ctx, lib().bem_apply(ctx, op, block, C.c_void_p(x_ptr), C.c_void_p(y_ptr), nrhs,
+                                C.c_void_p(stream) if stream else None))
+
+
+def bem_block_export(ctx, op: int, block: int, rows: int, cols: int) -> np.ndarray:
+    out = np.zeros((rows, cols), np.complex128)
+    _check(ctx, lib().bem_block_export(ctx, op, block, _cptr(out)))
+    return out
+
+
+def bem_set_inner_tol(ctx, op: int, tol: float) -> None:
+    _check(ctx, lib().bem_set_inner_tol(ctx, op, float(tol)))
+
+
+def plane_waves(khat, pol, amp=1.0):
+    khat = np.atleast_2d(np.asarray(khat, np.float64))
+    pol = np.atleast_2d(np.asarray(pol, np.complex128))
+    arr = (bem_excitation * len(khat))()
+    for i in range(len(khat)):
+        e = arr[i]
+        e.kind = BEM_EXC_PLANE_WAVE
+        for k in range(3):
+            e.khat[k] = khat[i, k]
+            e.pol[k] = c64(pol[i, k].real, pol[i, k].imag)
+        e.amp = c64(complex(amp).real, complex(amp).imag)
+    return arr
+
+
+def solve_opts(tol=1e-8, restart=50, maxit=2000, inner_tol=0.0, max_refine=0, out_device=0):
+    return bem_solve_opts(tol, restart, maxit, inner_tol, max_refine, out_device)
+
+
+def bem_solve(ctx, op: int, exc, opts: bem_solve_opts, n_edge: int, n_tri: int):
+    """Returns (status, H[ne, nexc], E[ne, nexc], rho[nt, nexc], info) with host outputs."""
+    n = len(exc)
+    H = np.zeros((n, n_edge), np.complex128)
+    E = np.zeros((n, n_edge), np.complex128)
+    rho = np.zeros((n, n_tri), np.complex128)
+    info = bem_solve_info()
+    rc = lib().bem_solve(ctx, op, exc, n, C.byref(opts), _cptr(H), _cptr(E), _cptr(rho), C.byref(info))
+    _check(ctx, rc, allow=(BEM_OK, BEM_E_NOT_CONVERGED))
+    return rc, H.T, E.T, rho.T, info
+
+
+def bem_submit(ctx, req: bem_request) -> int:
+    t = C.c_uint64()
+    _check(ctx, lib().bem_submit(ctx, C.byref(req), C.byref(t)))
+    return t.value
+
+
+def bem_poll(ctx, ticket: int):
+    info = bem_solve_info()
+    rc = lib().bem_poll(ctx, ticket, C.byref(info))
+    if rc < 0 and rc != BEM_E_NOT_CONVERGED:
+        raise BemError(rc, bem_last_error(ctx))
+    return rc, info
+
+
+def bem_drain(ctx) -> None:
+    _check(ctx, lib().bem_drain(ctx))
+
+
+def bem_release(ctx, handle: int) -> None:
+    _check(ctx, lib().bem_release(ctx, handle))
+
+
+def bem_memory_in_use(ctx) -> int:
+    v = C.c_size_t()
+    _check(ctx, lib().bem_memory_in_use(ctx, C.byref(v)))
+    return v.value

@@ -1,0 +1,281 @@
+// C ABI of libbem: argument checks, handle tables, status codes and error messages.
+#include <cmath>
+#include <cstring>
+
+#include "ctx.h"
+#include "serve.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+template <class F>
+int guarded(F&& f) {
+  try {
+    g_err.clear();
+    return f();
+  } catch (const bem::Error& e) {
+    return fail(e.code, e.what());
+  } catch (const std::bad_alloc&) {
+    return fail(BEM_E_NOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(BEM_E_INVALID, e.what());
+  }
+}
+
+void need_device(bem_ctx* c) {
+  auto* ctx = reinterpret_cast<bem::Ctx*>(c);
+  if (ctx->device < 0) throw bem::Error(BEM_E_DEVICE, "host-only context (created with device = -1)");
+  BEM_HIP(hipSetDevice(ctx->device));
+}
+
+bem::Ctx* C(bem_ctx* c) {
+  if (!c) throw bem::Error(BEM_E_INVALID, "null context");
+  return reinterpret_cast<bem::Ctx*>(c);
+}
+
+bem::MeshObj& mesh_of(bem::Ctx* ctx, bem_mesh_h h) {
+  auto it = ctx->meshes.find(h);
+  if (it == ctx->meshes.end()) throw bem::Error(BEM_E_INVALID, "unknown mesh handle");
+  return *it->second;
+}
+
+bem::OpObj& op_of(bem::Ctx* ctx, bem_op_h h) {
+  auto it = ctx->ops.find(h);
+  if (it == ctx->ops.end()) throw bem::Error(BEM_E_INVALID, "unknown operator handle");
+  return *it->second;
+}
+
+}  // namespace
+
+namespace bem {
+Ctx::~Ctx() {
+  server.reset();
+  ops.clear();
+  meshes.clear();
+  if (pinned) (void)hipHostFree(pinned);
+  if (stream) (void)hipStreamDestroy(stream);
+}
+}  // namespace bem
+
+extern "C" {
+
+int bem_create(int device, size_t hbm_budget_bytes, bem_ctx** out) {
+  return guarded([&]() -> int {
+    if (!out) return fail(BEM_E_INVALID, "null output pointer");
+    auto ctx = std::make_unique<bem::Ctx>();
+    ctx->device = device;
+    if (device >= 0) {
+      int n = 0;
+      if (hipGetDeviceCount(&n) != hipSuccess || device >= n) {
+        (void)hipGetLastError();
+        return fail(BEM_E_DEVICE, "no such HIP device");
+      }
+      BEM_HIP(hipSetDevice(device));
+      BEM_HIP(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
+      BEM_HIP(hipHostMalloc(reinterpret_cast<void**>(&ctx->pinned), 64 * sizeof(double), hipHostMallocDefault));
+      size_t fr = 0, tot = 0;
+      BEM_HIP(hipMemGetInfo(&fr, &tot));
+      ctx->budget = hbm_budget_bytes ? hbm_budget_bytes : fr;
+    } else {
+      ctx->budget = hbm_budget_bytes;
+    }
+    *out = reinterpret_cast<bem_ctx*>(ctx.release());
+    return BEM_OK;
+  });
+}
+
+void bem_destroy(bem_ctx* c) {
+  if (!c) return;
+  auto* ctx = reinterpret_cast<bem::Ctx*>(c);
+  if (ctx->device >= 0) (void)hipSetDevice(ctx->device);
+  delete ctx;
+}
+
+const char* bem_last_error(const bem_ctx*) { return g_err.c_str(); }
+
+int bem_mesh_load(bem_ctx* c, const double* xyz, int64_t nv, const int32_t* tri, int64_t nt, const int32_t* obj,
+                  bem_mesh_h* out) {
+  return guarded([&]() -> int {
+    bem::Ctx* ctx = C(c);
+    if (!out) return fail(BEM_E_INVALID, "null output pointer");
+    auto mo = std::make_unique<bem::MeshObj>();
+    mo->mesh = bem::build_mesh(xyz, nv, tri, nt, obj);
+    const uint64_t h = ctx->next_handle++;
+    ctx->meshes[h] = std::move(mo);
+    *out = h;
+    return BEM_OK;
+  });
+}
+
+int bem_mesh_info(bem_ctx* c, bem_mesh_h h, int64_t* n_tri, int64_t* n_edge, int64_t* n_obj, int64_t* n_unknowns) {
+  return guarded([&]() -> int {
+    const bem::Mesh& m = *mesh_of(C(c), h).mesh;
+    if (n_tri) *n_tri = m.nt;
+    if (n_edge) *n_edge = m.ne;
+    if (n_obj) *n_obj = m.nobj;
+    if (n_unknowns) *n_unknowns = 2 * m.ne + m.nt - m.nobj;
+    return BEM_OK;
+  });
+}
+
+int bem_edge_table(bem_ctx* c, bem_mesh_h h, int32_t* va, int32_t* vb, int32_t* tplus, int32_t* tminus) {
+  return guarded([&]() -> int {
+    const bem::Mesh& m = *mesh_of(C(c), h).mesh;
+    for (int64_t n = 0; n < m.ne; ++n) {
+      if (va) va[n] = m.ev[2 * n];
+      if (vb) vb[n] = m.ev[2 * n + 1];
+      if (tplus) tplus[n] = m.tp[n];
+      if (tminus) tminus[n] = m.tm[n];
+    }
+    return BEM_OK;
+  });
+}
+
+int bem_near_pairs(bem_ctx* c, bem_mesh_h h, int64_t* ptr, int32_t* idx) {
+  return guarded([&]() -> int {
+    const bem::Mesh& m = *mesh_of(C(c), h).mesh;
+    if (!ptr) return fail(BEM_E_INVALID, "null ptr");
+    std::memcpy(ptr, m.near_ptr.data(), sizeof(int64_t) * m.near_ptr.size());
+    if (idx) std::memcpy(idx, m.near_idx.data(), sizeof(int32_t) * m.near_idx.size());
+    return BEM_OK;
+  });
+}
+
+int bem_assemble(bem_ctx* c, bem_mesh_h h, const bem_problem* prob, bem_op_h* out) {
+  return guarded([&]() -> int {
+    bem::Ctx* ctx = C(c);
+    if (!prob || !out) return fail(BEM_E_INVALID, "null argument");
+    bem::MeshObj& mo = mesh_of(ctx, h);
+    need_device(c);
+    auto op = std::make_unique<bem::OpObj>(ctx);
+    bem::assemble_op(*op, mo, *prob);
+    const uint64_t id = ctx->next_handle++;
+    ctx->ops[id] = std::move(op);
+    *out = id;
+    return BEM_OK;
+  });
+}
+
+int bem_apply(bem_ctx* c, bem_op_h h, int block, const void* x, void* y, int64_t nrhs, void* stream) {
+  return guarded([&]() -> int {
+    bem::Ctx* ctx = C(c);
+    bem::OpObj& op = op_of(ctx, h);
+    need_device(c);
+    if (!x || !y || nrhs < 0) return fail(BEM_E_INVALID, "invalid vectors");
+    hipStream_t st = stream ? static_cast<hipStream_t>(stream) : ctx->stream;
+    int64_t rows, cols;
+    switch (block) {
+      case BEM_BLOCK_FINAL: rows = cols = op.N; break;
+      case BEM_BLOCK_LPHI_INT:
+      case BEM_BLOCK_LPHI_BG: rows = cols = op.nt; break;
+      case BEM_BLOCK_MEQ: rows = cols = op.Neq; break;
+      case BEM_BLOCK_LA_INT:
+      case BEM_BLOCK_K_INT:
+      case BEM_BLOCK_LA_BG:
+      case BEM_BLOCK_K_BG:
+      case BEM_BLOCK_IX: rows = cols = op.ne; break;
+      default: return fail(BEM_E_INVALID, "unknown block");
+    }
+    const double2* xp = static_cast<const double2*>(x);
+    double2* yp = static_cast<double2*>(y);
+    for (int64_t r = 0; r < nrhs; ++r) bem::apply_block(op, block, xp + r * cols, yp + r * rows, st);
+    return BEM_OK;
+  });
+}
+
+int bem_block_export(bem_ctx* c, bem_op_h h, int block, bem_c64* host_dst) {
+  return guarded([&]() -> int {
+    bem::Ctx* ctx = C(c);
+    bem::OpObj& op = op_of(ctx, h);
+    need_device(c);
+    if (!host_dst) return fail(BEM_E_INVALID, "null destination");
+    bem::export_block(op, block, host_dst);
+    return BEM_OK;
+  });
+}
+
+int bem_set_inner_tol(bem_ctx* c, bem_op_h h, double tol) {
+  return guarded([&]() -> int {
+    bem::OpObj& op = op_of(C(c), h);
+    if (!(tol > 0)) return fail(BEM_E_INVALID, "tolerance must be positive");
+    op.inner_tol = tol;
+    return BEM_OK;
+  });
+}
+
+int bem_solve(bem_ctx* c, bem_op_h h, const bem_excitation* exc, int64_t nexc, const bem_solve_opts* opts, bem_c64* H,
+              bem_c64* E, bem_c64* rho, bem_solve_info* info) {
+  return guarded([&]() -> int {
+    bem::Ctx* ctx = C(c);
+    bem::OpObj& op = op_of(ctx, h);
+    need_device(c);
+    if (!opts) return fail(BEM_E_INVALID, "null options");
+    int st = bem::solve_op(op, exc, nexc, *opts, H, E, rho, info, ctx->stream);
+    if (st == BEM_E_NOT_CONVERGED) g_err = "GMRES did not reach the tolerance within maxit";
+    return st;
+  });
+}
+
+int bem_release(bem_ctx* c, uint64_t h) {
+  return guarded([&]() -> int {
+    bem::Ctx* ctx = C(c);
+    if (ctx->device >= 0) BEM_HIP(hipSetDevice(ctx->device));
+    if (ctx->ops.erase(h)) return BEM_OK;
+    if (ctx->meshes.count(h)) {
+      for (auto& kv : ctx->ops)
+        if (kv.second->m == ctx->meshes[h]->mesh.get())
+          return fail(BEM_E_INVALID, "mesh still used by an operator");
+      ctx->meshes.erase(h);
+      return BEM_OK;
+    }
+    return fail(BEM_E_INVALID, "unknown handle");
+  });
+}
+
+int bem_memory_in_use(bem_ctx* c, size_t* bytes) {
+  return guarded([&]() -> int {
+    bem::Ctx* ctx = C(c);
+    if (!bytes) return fail(BEM_E_INVALID, "null output");
+    std::lock_guard<std::mutex> g(ctx->mu);
+    *bytes = ctx->used;
+    return BEM_OK;
+  });
+}
+
+int bem_submit(bem_ctx* c, const bem_request* req, bem_ticket* out) {
+  return guarded([&]() -> int {
+    bem::Ctx* ctx = C(c);
+    need_device(c);
+    if (!req || !out) return fail(BEM_E_INVALID, "null argument");
+    if (!ctx->server) ctx->server = std::make_unique<bem::Server>(ctx);
+    *out = ctx->server->submit(*req);
+    return BEM_OK;
+  });
+}
+
+int bem_poll(bem_ctx* c, bem_ticket t, bem_solve_info* info) {
+  return guarded([&]() -> int {
+    bem::Ctx* ctx = C(c);
+    if (!ctx->server) return fail(BEM_E_INVALID, "unknown ticket");
+    std::string msg;
+    int st = ctx->server->poll(t, info, &msg);
+    if (st < 0) g_err = msg;
+    return st;
+  });
+}
+
+int bem_drain(bem_ctx* c) {
+  return guarded([&]() -> int {
+    bem::Ctx* ctx = C(c);
+    if (ctx->server) ctx->server->drain();
+    return BEM_OK;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,145 @@
+// Context, device memory accounting and the assembled operator object.
+#pragma once
+
+#include <functional>
+#include <map>
+#include <mutex>
+
+#include "fill.h"
+#include "internal.h"
+#include "linalg.h"
+
+namespace bem {
+
+class Server;
+
+struct Ctx {
+  int device = -1;
+  size_t budget = 0;
+  size_t used = 0;
+  hipStream_t stream = nullptr;
+  uint64_t next_handle = 1;
+  std::map<uint64_t, std::unique_ptr<struct MeshObj>> meshes;
+  std::map<uint64_t, std::unique_ptr<struct OpObj>> ops;
+  double* pinned = nullptr;  // small pinned host buffer for convergence scalars
+  std::unique_ptr<Server> server;
+  std::mutex mu;             // guards `used` (the serving thread allocates too)
+  ~Ctx();
+};
+
+// Device allocations owned by one object; released (and un-accounted) on destruction.
+class DevArena {
+ public:
+  explicit DevArena(Ctx* c) : ctx_(c) {}
+  DevArena(const DevArena&) = delete;
+  ~DevArena();
+  void* raw(size_t bytes);
+  template <class T>
+  T* alloc(size_t n) {
+    return static_cast<T*>(raw(sizeof(T) * (n ? n : 1)));
+  }
+  template <class T>
+  T* upload(const std::vector<T>& v) {
+    T* p = alloc<T>(v.size());
+    if (!v.empty()) BEM_HIP(hipMemcpy(p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
+    return p;
+  }
+  void release(void* p);
+  size_t bytes() const { return total_; }
+
+ private:
+  Ctx* ctx_;
+  std::vector<std::pair<void*, size_t>> blocks_;
+  size_t total_ = 0;
+};
+
+struct MeshObj {
+  std::unique_ptr<Mesh> mesh;
+  std::unique_ptr<CellData> cells;  // built on first assemble
+};
+
+// Dense block: float64 storage, optional float32 copy, padded leading dimension.
+struct Dense {
+  double2* d64 = nullptr;
+  float2* d32 = nullptr;
+  int64_t rows = 0, cols = 0, ld = 0;
+};
+
+struct GmresWork;
+
+struct OpObj {
+  Ctx* ctx;
+  const Mesh* m;
+  const CellData* cells;
+  DevArena mem;
+  // problem
+  double freq = 0, k0 = 0;
+  std::vector<cd> epsc, kint;
+  std::vector<double> mur;
+  cd eps_bg = 1.0, kbg = 0.0;
+  double mu_bg = 1.0;
+  int precision = BEM_FP64;
+  // sizes
+  int64_t ne = 0, nt = 0, nq = 0, nobj = 0, N = 0, Neq = 0;
+  // device tables
+  double* geo = nullptr;
+  int32_t *tp = nullptr, *tm = nullptr, *tri_edge = nullptr, *kept = nullptr;
+  int8_t *ip = nullptr, *im = nullptr, *tri_sign = nullptr;
+  int64_t* obj_tri_d = nullptr;
+  int64_t* ix_ptr = nullptr;
+  int32_t* ix_idx = nullptr;
+  double* ix_val = nullptr;
+  double2* eps_inv_edge = nullptr;  // 1/eps_c of the object of every edge
+  // host copies of the per-object ranges
+  std::vector<int64_t> obj_tri, obj_edge, obj_q;
+  // dense blocks
+  std::vector<Dense> LA_int, Lphi_int, K_int, K_bg;  // per object (block-diagonal operators)
+  Dense LA_bg, Lphi_bg;                              // all pairs (background coupling)
+  // solver settings and work
+  double inner_tol = 1e-12;
+  int inner_restart = 200, inner_maxit = 4000;
+  int last_inner_iters = 0, max_inner_iters = 0;
+  double fill_seconds = 0;
+  std::unique_ptr<GmresWork> inner_ws, outer_ws;
+  double2* work = nullptr;  // vector workspace
+  int64_t work_len = 0;
+  hipStream_t stream = nullptr;  // stream of the operator's work
+  double* pinned = nullptr;      // pinned host scalars for convergence checks
+
+  explicit OpObj(Ctx* c) : ctx(c), m(nullptr), cells(nullptr), mem(c), stream(c->stream), pinned(c->pinned) {}
+  ~OpObj();
+};
+
+using ApplyFn = std::function<void(const double2* x, double2* y)>;
+
+struct GmresResult {
+  int iters = 0;
+  double relres = 0;  // estimated (Arnoldi) relative residual
+  bool converged = false;
+};
+
+struct GmresWork {
+  int64_t n = 0, ldv = 0;
+  int m = 0;
+  double2 *V = nullptr, *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr, *y = nullptr, *h2 = nullptr;
+  double2* nrm = nullptr;
+  double* res = nullptr;
+  KrylovScratch ks{};
+};
+
+std::unique_ptr<GmresWork> make_gmres_work(DevArena& mem, int64_t n, int m);
+// Right-preconditioner-free restarted GMRES (CGS2 Arnoldi, complex Givens, float64) on `st`.
+// x holds the initial guess (zeroed when x_zero) and receives the solution.
+GmresResult gmres(GmresWork& w, double* pinned, const ApplyFn& A, const double2* b, double2* x, bool x_zero,
+                  double tol, int maxit, hipStream_t st);
+
+// Operator construction and application.
+void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob);
+void apply_block(OpObj& op, int block, const double2* x, double2* y, hipStream_t st);
+void apply_meq(OpObj& op, const double2* x, double2* y, bool fp32, hipStream_t st);
+void apply_final(OpObj& op, const double2* x, double2* y, bool fp32, double inner_tol, hipStream_t st);
+void export_block(OpObj& op, int block, bem_c64* host);
+int solve_op(OpObj& op, const bem_excitation* exc, int64_t nexc, const bem_solve_opts& opts, bem_c64* H, bem_c64* E,
+             bem_c64* rho, bem_solve_info* info, hipStream_t st);
+
+}  // namespace bem

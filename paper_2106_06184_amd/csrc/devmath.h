@@ -1,0 +1,197 @@
+// Device helpers for the fill kernels: complex arithmetic on double2, the Green's function and
+// its gradient (eq. hgf), their singular-part remainders, and the closed-form static integrals
+// over a flat triangle (potential-integral formulas of Wilton et al. / Graglia).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace bem {
+namespace dev {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kInv4Pi = 1.0 / (4.0 * kPi);
+// |kR| below which the regularised kernels use their power series (cancellation-free).
+constexpr double kSeriesKR = 0.5;
+
+struct v3 {
+  double x, y, z;
+};
+__device__ __forceinline__ v3 mk(double x, double y, double z) { return {x, y, z}; }
+__device__ __forceinline__ v3 operator+(v3 a, v3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+__device__ __forceinline__ v3 operator-(v3 a, v3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ v3 operator*(double s, v3 a) { return {s * a.x, s * a.y, s * a.z}; }
+__device__ __forceinline__ double dot(v3 a, v3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ v3 cross(v3 a, v3 b) {
+  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+__device__ __forceinline__ double norm(v3 a) { return sqrt(dot(a, a)); }
+
+// complex double and complex 3-vectors
+struct cz {
+  double re, im;
+};
+struct cv3 {
+  cz x, y, z;
+};
+__device__ __forceinline__ cz cmul(cz a, cz b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+__device__ __forceinline__ cz cadd(cz a, cz b) { return {a.re + b.re, a.im + b.im}; }
+__device__ __forceinline__ cz csub(cz a, cz b) { return {a.re - b.re, a.im - b.im}; }
+__device__ __forceinline__ cz cscale(double s, cz a) { return {s * a.re, s * a.im}; }
+__device__ __forceinline__ cv3 cvzero() { return {{0, 0}, {0, 0}, {0, 0}}; }
+// a += w * c * v   (c complex scalar, v real vector)
+__device__ __forceinline__ void cv_axpy(cv3& a, cz c, v3 v) {
+  a.x.re += c.re * v.x; a.x.im += c.im * v.x;
+  a.y.re += c.re * v.y; a.y.im += c.im * v.y;
+  a.z.re += c.re * v.z; a.z.im += c.im * v.z;
+}
+__device__ __forceinline__ cz cv_dot(v3 v, cv3 a) {
+  return {v.x * a.x.re + v.y * a.y.re + v.z * a.z.re, v.x * a.x.im + v.y * a.y.im + v.z * a.z.im};
+}
+// v x a for real v and complex a
+__device__ __forceinline__ cv3 rc_cross(v3 v, cv3 a) {
+  cv3 r;
+  r.x = {v.y * a.z.re - v.z * a.y.re, v.y * a.z.im - v.z * a.y.im};
+  r.y = {v.z * a.x.re - v.x * a.z.re, v.z * a.x.im - v.x * a.z.im};
+  r.z = {v.x * a.y.re - v.y * a.x.re, v.x * a.y.im - v.y * a.x.im};
+  return r;
+}
+__device__ __forceinline__ void cv_add(cv3& a, cv3 b) {
+  a.x = cadd(a.x, b.x); a.y = cadd(a.y, b.y); a.z = cadd(a.z, b.z);
+}
+
+// e^{-jkR} for k = kr + j ki  ->  e^{ki R} (cos kr R - j sin kr R)
+template <bool LOSSY>
+__device__ __forceinline__ cz expjkr(double kr, double ki, double R) {
+  double s, c;
+  sincos(kr * R, &s, &c);
+  if (LOSSY) {
+    double a = exp(ki * R);
+    return {a * c, -a * s};
+  }
+  return {c, -s};
+}
+
+// G_k(R) = e^{-jkR}/(4 pi R), given R and 1/R
+template <bool LOSSY>
+__device__ __forceinline__ cz green(double kr, double ki, double R, double invR) {
+  cz e = expjkr<LOSSY>(kr, ki, R);
+  double s = kInv4Pi * invR;
+  return {s * e.re, s * e.im};
+}
+
+// g_k(R) with grad_r G = g_k(R) (r - r'):  -(1 + jkR) e^{-jkR} / (4 pi R^3)
+template <bool LOSSY>
+__device__ __forceinline__ cz grad_green(double kr, double ki, double R, double invR) {
+  cz e = expjkr<LOSSY>(kr, ki, R);
+  // 1 + jkR = (1 - ki R) + j kr R
+  cz f = {1.0 - ki * R, kr * R};
+  cz p = cmul(f, e);
+  double s = -kInv4Pi * invR * invR * invR;
+  return {s * p.re, s * p.im};
+}
+
+// G_k(R) - 1/(4 pi R) = (e^{-jkR} - 1)/(4 pi R); bounded at R = 0.
+__device__ inline cz green_rem(double kr, double ki, double R) {
+  // z = -jkR = (ki R) - j (kr R)
+  cz z = {ki * R, -kr * R};
+  double az = sqrt(z.re * z.re + z.im * z.im);
+  if (az >= kSeriesKR) {
+    double ea = exp(z.re), s, c;
+    sincos(z.im, &s, &c);
+    cz em1 = {ea * c - 1.0, ea * s};
+    double w = kInv4Pi / R;
+    return {w * em1.re, w * em1.im};
+  }
+  // (e^z - 1)/R = (-jk) sum_{n>=1} z^{n-1}/n!
+  cz term = {1.0, 0.0}, acc = {1.0, 0.0};
+  for (int n = 2; n < 30; ++n) {
+    term = cscale(1.0 / n, cmul(term, z));
+    acc = cadd(acc, term);
+  }
+  cz mjk = {ki, -kr};  // -jk
+  cz r = cmul(mjk, acc);
+  return {kInv4Pi * r.re, kInv4Pi * r.im};
+}
+
+// g_k(R) + 1/(4 pi R^3) + k^2/(8 pi R); tends to j k^3/(12 pi) at R = 0.
+__device__ inline cz grad_green_rem(double kr, double ki, double R) {
+  double akr = sqrt(kr * kr + ki * ki) * R;
+  cz k = {kr, ki};
+  cz k2 = cmul(k, k);
+  if (akr >= kSeriesKR) {
+    double invR = 1.0 / R;
+    cz g = grad_green<true>(kr, ki, R, invR);
+    double i3 = kInv4Pi * invR * invR * invR;
+    double s = 0.5 * kInv4Pi * invR;
+    return {g.re + i3 + s * k2.re, g.im + s * k2.im};
+  }
+  // (1/4pi) sum_{n>=3} (-1)^n (n-1)/n! (jk)^n R^{n-3}
+  cz jk = {-ki, kr};
+  cz jkn = cmul(cmul(jk, jk), jk);  // (jk)^3
+  double rp = 1.0, fact = 6.0;
+  cz acc = {0.0, 0.0};
+  for (int n = 3; n < 40; ++n) {
+    double c = ((n & 1) ? -1.0 : 1.0) * (n - 1) / fact * rp;
+    acc = cadd(acc, cscale(c, jkn));
+    jkn = cmul(jkn, jk);
+    rp *= R;
+    fact *= (n + 1);
+  }
+  return {kInv4Pi * acc.re, kInv4Pi * acc.im};
+}
+
+// Closed-form static integrals over the flat triangle (a, b, c) (counter-clockwise about its
+// normal n) at observation point r.  Outputs:
+//   i1  = int 1/R dS'
+//   iv  = int (r' - r)/R dS'
+//   j3  = int (r - r')/R^3 dS'   (only when want_j3; r must not lie on the closed triangle)
+struct StaticInts {
+  double i1;
+  v3 iv;
+  v3 j3;
+};
+
+__device__ inline StaticInts static_ints(v3 r, v3 a, v3 b, v3 c, bool want_j3) {
+  v3 n = cross(b - a, c - a);
+  n = (1.0 / norm(n)) * n;
+  double d = dot(r - a, n);
+  double ad = fabs(d);
+  v3 rho = r - d * n;
+  StaticInts out;
+  out.i1 = 0.0;
+  out.iv = mk(0, 0, 0);
+  out.j3 = mk(0, 0, 0);
+  double bsum = 0.0;
+  v3 irho = mk(0, 0, 0);
+  v3 ends[4] = {a, b, c, a};
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    v3 p0 = ends[e], p1 = ends[e + 1];
+    v3 s = p1 - p0;
+    s = (1.0 / norm(s)) * s;
+    v3 m = cross(s, n);
+    double sm = dot(p0 - rho, s), sp = dot(p1 - rho, s), t0 = dot(p0 - rho, m);
+    double r02 = t0 * t0 + d * d;
+    double rm = sqrt(r02 + sm * sm), rp = sqrt(r02 + sp * sp);
+    double f;
+    if (sm >= 0.0)
+      f = log((rp + sp) / (rm + sm));
+    else if (sp <= 0.0)
+      f = log((rm - sm) / (rp - sp));
+    else
+      f = log((rp + sp) * (rm - sm) / r02);
+    double beta = atan2(t0 * sp, r02 + ad * rp) - atan2(t0 * sm, r02 + ad * rm);
+    if (t0 != 0.0) out.i1 += t0 * f;
+    out.i1 -= ad * beta;
+    double term = (r02 > 0.0 ? r02 * f : 0.0) + sp * rp - sm * rm;
+    irho = irho + (0.5 * term) * m;
+    if (want_j3) out.j3 = out.j3 + f * m;
+    bsum += beta;
+  }
+  out.iv = irho - (d * out.i1) * n;
+  if (want_j3) out.j3 = out.j3 + ((d > 0 ? 1.0 : (d < 0 ? -1.0 : 0.0)) * bsum) * n;
+  return out;
+}
+
+}  // namespace dev
+}  // namespace bem

@@ -1,0 +1,85 @@
+// Fill-kernel interface shared by the host driver and fill.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace bem {
+
+// Per-triangle geometry table (float64, field-major: field f of triangle t at geo[f * nt + t]).
+enum : int {
+  kGeoC = 0,    // centroid (3)
+  kGeoQ = 3,    // Q7 points relative to the centroid (7 x 3)
+  kGeoP = 24,   // vertices relative to the centroid (3 x 3); vertex i is the free vertex of half-RWG i
+  kGeoA = 33,   // area
+  kGeoN = 34,   // unit outward normal (3)
+  kGeoH = 37,   // longest edge
+  kGeoFields = 38
+};
+
+struct FillLArgs {
+  const double* geo;
+  int64_t nt_total;
+  int64_t t0, nt_test;  // test triangle range
+  int64_t s0, ns;       // source triangle range
+  int64_t tchunk;       // test triangles per block (grid.y)
+  double kr, ki;        // wavenumber
+  double2* H;           // half-RWG block matrix, rows 3*(T-t0)+i, cols 3*(T'-s0)+j
+  int64_t ldH;
+  double2* Lphi;        // rows T-t0, cols T'-s0
+  int64_t ldP;
+};
+
+struct FillKArgs {
+  const double* geo;
+  int64_t nt_total;
+  int64_t t0, nt_test;
+  int64_t tchunk;
+  double kr, ki;
+  const int32_t* cells;   // cell (vertex) ids of this object
+  int64_t ncells;
+  int64_t ncell_total;    // stride of the cell tables
+  const int32_t* nval;
+  const double* vpos;
+  const int64_t* col0;
+  const double* sub_m;
+  const double* sub_c;
+  const double* sub_area;
+  const int32_t* sub_parent;
+  const double* alpha;
+  const double* beta;
+  double2* Kc;            // rows 3*(T-t0)+i, cols = object-local (cell, BC) columns
+  int64_t ldK;
+};
+
+struct RhsArgs {
+  const double* geo;
+  int64_t nt_total;
+  const int32_t* tp;
+  const int32_t* tm;
+  const int8_t* ip;
+  const int8_t* im;
+  int64_t ne;
+  const double* khat;   // 3 per excitation
+  const double2* pol;   // 3 per excitation
+  const double2* amp;   // 1 per excitation
+  double klr, kli;      // background wavenumber
+  double inv_eta0;
+  double2* b;           // column-major ne x nexc
+  int64_t ldb;
+};
+void launch_rhs_planewave(const RhsArgs& a, int nexc, hipStream_t st);
+
+void fill_set_rules(const double w7[7], const double b3[3][3]);
+void launch_fill_L(const FillLArgs& a, const int32_t* near_t, const int32_t* near_s, int64_t npairs,
+                   hipStream_t st);
+// Half-row indices hp/hm are global (3 T + i); `off` = 3 * first triangle of the block.
+void launch_gather_LA(const double2* H, int64_t ldH, const int32_t* hp, const int32_t* hm, int64_t off, int64_t ne,
+                      double2* out, int64_t ldo, hipStream_t st);
+void launch_fill_K(const FillKArgs& a, const int32_t* near_t, const int32_t* near_c, int64_t npairs,
+                   const int64_t* near_ptr, const int32_t* near_idx, int maxv, hipStream_t st);
+void launch_gather_K(const double2* Kc, int64_t ldK, const int32_t* hp, const int32_t* hm, const int32_t* cS,
+                     const int32_t* cT, int64_t off, int64_t ne, double2* out, int64_t ldo, hipStream_t st);
+
+}  // namespace bem

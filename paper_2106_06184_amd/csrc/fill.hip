@@ -1,0 +1,524 @@
+// Galerkin fill kernels (gfx950, float64 VALU): L^(A), L^(phi) on RWG/pulse bases and K~ on BC
+// sources over the barycentric refinement (eqs. opLAhgf, opLphihgf, opKhgf, hgf).
+//
+// Work decomposition
+//  * L: one thread per source triangle T', a wave-uniform loop over test triangles T.  The
+//    thread accumulates 8 complex moments of the Q7 x Q7 product rule with positions taken
+//    relative to each triangle's centroid (no cancellation between far and near scales):
+//      I0 = sum w w G,  Id = sum w w G d_k,  Id' = sum w w G d'_l,  Idd' = sum w w G d_k.d'_l
+//    and writes the 3x3 block of half-RWG interactions
+//      H_ij = 1/4 [Idd' - p'_j.Id - p_i.Id' + (p_i.p'_j) I0]     (p relative to the centroids)
+//    plus L^phi = I0.  A gather kernel then adds the four half blocks of every edge pair.
+//  * K~: one thread per dual cell C(v) (source), a wave-uniform loop over test triangles.  For
+//    every sub-triangle t of the cell the thread forms the inner Q3 moments of g_k relative to
+//    v, contracts them over the Q7 outer rule into 10 complex moments, and applies them to the
+//    linear restriction (alpha r' - beta)/(2A_t) of each BC function of the cell.  The result,
+//    per test half-RWG and (cell, BC) column, is gathered into K~ (two cells per BC function).
+//  * Near pairs (shared vertex or close centroids) are recomputed by separate kernels with
+//    singularity extraction: closed-form static parts plus Q7 (L) / Q3 (K~) on the bounded
+//    remainders; they overwrite the far-rule values.  K~ is zero for coplanar near pairs.
+#include <hip/hip_runtime.h>
+
+#include "devmath.h"
+#include "fill.h"
+
+namespace bem {
+namespace dev {
+
+// Q7 (Radon, degree 5) and Q3 (degree 2) weights; the points live in the geometry tables.
+__constant__ double cW7[7];
+__constant__ double cB3[3][3];
+
+__device__ __forceinline__ double G(const double* geo, int64_t nt, int f, int64_t t) { return geo[f * nt + t]; }
+__device__ __forceinline__ v3 G3(const double* geo, int64_t nt, int f, int64_t t) {
+  return mk(geo[f * nt + t], geo[(f + 1) * nt + t], geo[(f + 2) * nt + t]);
+}
+
+// ------------------------------------------------------------------ L far
+template <bool LOSSY>
+__global__ void __launch_bounds__(256) k_fill_L_far(FillLArgs a) {
+  const int64_t sl = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;  // local source index
+  if (sl >= a.ns) return;
+  const int64_t s = a.s0 + sl;
+  const double* geo = a.geo;
+  const int64_t nt = a.nt_total;
+  const v3 cs = G3(geo, nt, kGeoC, s);
+  v3 dl[7];
+#pragma unroll
+  for (int l = 0; l < 7; ++l) dl[l] = G3(geo, nt, kGeoQ + 3 * l, s);
+  v3 pj[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) pj[j] = G3(geo, nt, kGeoP + 3 * j, s);
+  const int64_t tbeg = int64_t(blockIdx.y) * a.tchunk;
+  const int64_t tend = min(a.nt_test, tbeg + a.tchunk);
+  for (int64_t tl = tbeg; tl < tend; ++tl) {
+    const int64_t t = a.t0 + tl;
+    const v3 d = G3(geo, nt, kGeoC, t) - cs;  // centroid offset test - source
+    cz I0 = {0, 0}, Idd = {0, 0};
+    cv3 Id = cvzero(), Idp = cvzero();
+#pragma unroll
+    for (int k = 0; k < 7; ++k) {
+      const v3 dk = G3(geo, nt, kGeoQ + 3 * k, t);
+      const v3 base = d + dk;
+      cz s0 = {0, 0};
+      cv3 s1 = cvzero();
+#pragma unroll
+      for (int l = 0; l < 7; ++l) {
+        v3 r = base - dl[l];
+        double r2 = dot(r, r);
+        double inv = rsqrt(r2);
+        double R = r2 * inv;
+        cz g = green<LOSSY>(a.kr, a.ki, R, inv);
+        g = cscale(cW7[l], g);
+        s0 = cadd(s0, g);
+        cv_axpy(s1, g, dl[l]);
+      }
+      const double wk = cW7[k];
+      s0 = cscale(wk, s0);
+      s1.x = cscale(wk, s1.x); s1.y = cscale(wk, s1.y); s1.z = cscale(wk, s1.z);
+      I0 = cadd(I0, s0);
+      cv_axpy(Id, s0, dk);
+      cv_add(Idp, s1);
+      Idd = cadd(Idd, cv_dot(dk, s1));
+    }
+    // H_ij = 1/4 [Idd' - p'_j.Id - p_i.Id' + (p_i.p'_j) I0]
+    double2* hrow = a.H + (3 * tl) * a.ldH + 3 * sl;
+    for (int i = 0; i < 3; ++i) {
+      const v3 pi = G3(geo, nt, kGeoP + 3 * i, t);
+      const cz pIdp = cv_dot(pi, Idp);
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        cz h = csub(csub(Idd, cv_dot(pj[j], Id)), pIdp);
+        h = cadd(h, cscale(dot(pi, pj[j]), I0));
+        hrow[i * a.ldH + j] = make_double2(0.25 * h.re, 0.25 * h.im);
+      }
+    }
+    a.Lphi[tl * a.ldP + sl] = make_double2(I0.re, I0.im);
+  }
+}
+
+// ------------------------------------------------------------------ L near
+template <bool LOSSY>
+__global__ void __launch_bounds__(128) k_fill_L_near(FillLArgs a, const int32_t* pt, const int32_t* ps,
+                                                     int64_t npairs) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= npairs) return;
+  const int64_t t = pt[p], s = ps[p];
+  const double* geo = a.geo;
+  const int64_t nt = a.nt_total;
+  const v3 ct = G3(geo, nt, kGeoC, t), cs = G3(geo, nt, kGeoC, s);
+  const double As = G(geo, nt, kGeoA, s);
+  // source vertices relative to the test centroid
+  v3 sv[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) sv[j] = (cs - ct) + G3(geo, nt, kGeoP + 3 * j, s);
+  cz S0[7];
+  cv3 S1[7];
+  for (int k = 0; k < 7; ++k) {
+    const v3 rk = G3(geo, nt, kGeoQ + 3 * k, t);  // relative to the test centroid
+    StaticInts si = static_ints(rk, sv[0], sv[1], sv[2], false);
+    cz s0 = {kInv4Pi * si.i1, 0.0};
+    cv3 s1 = cvzero();
+    s1.x.re = kInv4Pi * si.iv.x; s1.y.re = kInv4Pi * si.iv.y; s1.z.re = kInv4Pi * si.iv.z;
+    for (int l = 0; l < 7; ++l) {
+      const v3 rl = (cs - ct) + G3(geo, nt, kGeoQ + 3 * l, s);
+      const v3 dd = rl - rk;
+      const double R = norm(dd);
+      cz gr = cscale(cW7[l] * As, green_rem(a.kr, a.ki, R));
+      s0 = cadd(s0, gr);
+      cv_axpy(s1, gr, dd);
+    }
+    S0[k] = s0;
+    S1[k] = s1;
+  }
+  double2* hrow = a.H + (3 * (t - a.t0)) * a.ldH + 3 * (s - a.s0);
+  for (int i = 0; i < 3; ++i) {
+    const v3 pi = G3(geo, nt, kGeoP + 3 * i, t);
+    for (int j = 0; j < 3; ++j) {
+      cz acc = {0, 0};
+      for (int k = 0; k < 7; ++k) {
+        const v3 rk = G3(geo, nt, kGeoQ + 3 * k, t);
+        // int G (r' - p'_j) dS' = S1 + (r - p'_j) S0
+        cv3 in = S1[k];
+        cv_axpy(in, S0[k], rk - sv[j]);
+        acc = cadd(acc, cscale(cW7[k], cv_dot(rk - pi, in)));
+      }
+      const double sc = 0.25 / As;
+      hrow[i * a.ldH + j] = make_double2(sc * acc.re, sc * acc.im);
+    }
+  }
+  cz lp = {0, 0};
+  for (int k = 0; k < 7; ++k) lp = cadd(lp, cscale(cW7[k], S0[k]));
+  a.Lphi[(t - a.t0) * a.ldP + (s - a.s0)] = make_double2(lp.re / As, lp.im / As);
+}
+
+// ------------------------------------------------------------ gathers
+// out[m][n] = sum_{a in {+,-}} sum_{b in {+,-}} s_a s_b H[row_a(m)][row_b(n)]
+__global__ void __launch_bounds__(256) k_gather_LA(const double2* __restrict__ H, int64_t ldH,
+                                                   const int32_t* __restrict__ hp, const int32_t* __restrict__ hm,
+                                                   int64_t off, int64_t ne, double2* __restrict__ out, int64_t ldo) {
+  const int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (n >= ne) return;
+  const int64_t cp = hp[n] - off, cm = hm[n] - off;
+  for (int64_t m = blockIdx.y; m < ne; m += gridDim.y) {
+    const double2* rp = H + (int64_t(hp[m]) - off) * ldH;
+    const double2* rm = H + (int64_t(hm[m]) - off) * ldH;
+    double2 a = rp[cp], b = rp[cm], c = rm[cp], d = rm[cm];
+    out[m * ldo + n] = make_double2(a.x - b.x - c.x + d.x, a.y - b.y - c.y + d.y);
+  }
+}
+
+// out[m][n] = sum_{a in {+,-}} s_a (Kc[row_a(m)][colS(n)] + Kc[row_a(m)][colT(n)])
+__global__ void __launch_bounds__(256) k_gather_K(const double2* __restrict__ Kc, int64_t ldK,
+                                                  const int32_t* __restrict__ hp, const int32_t* __restrict__ hm,
+                                                  const int32_t* __restrict__ cS, const int32_t* __restrict__ cT,
+                                                  int64_t off, int64_t ne, double2* __restrict__ out, int64_t ldo) {
+  const int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (n >= ne) return;
+  const int32_t s = cS[n], u = cT[n];
+  for (int64_t m = blockIdx.y; m < ne; m += gridDim.y) {
+    const double2* rp = Kc + (int64_t(hp[m]) - off) * ldK;
+    const double2* rm = Kc + (int64_t(hm[m]) - off) * ldK;
+    double2 a = rp[s], b = rp[u], c = rm[s], d = rm[u];
+    out[m * ldo + n] = make_double2(a.x + b.x - c.x - d.x, a.y + b.y - c.y - d.y);
+  }
+}
+
+// ------------------------------------------------------------------ K far
+// Contribution of one far sub-triangle to the accumulators acc[b][i] (i = test half-RWG):
+//   1/4 [alpha_b (P - p_i.Q) + beta_b . (R - p_i x S)]
+// with, over the outer points k (Delta_k = d + d_k, d = test centroid - v):
+//   m0_k = sum_j w_j g(R_kj),  m1_k = sum_j w_j g(R_kj) d'_j,  u_k = m1_k - Delta_k m0_k
+//   P = sum_k w_k d_k.(d x m1_k),  Q = sum_k w_k Delta_k x m1_k,
+//   R = sum_k w_k d_k x u_k,       S = sum_k w_k u_k
+template <bool LOSSY, int MAXV>
+__global__ void __launch_bounds__(128) k_fill_K_far(FillKArgs a) {
+  const int64_t cl = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (cl >= a.ncells) return;
+  const int32_t v = a.cells[cl];
+  const int64_t nc = a.ncell_total;
+  const double* geo = a.geo;
+  const int64_t nt = a.nt_total;
+  const int nval = a.nval[v];
+  const v3 pv = mk(a.vpos[3 * v], a.vpos[3 * v + 1], a.vpos[3 * v + 2]);
+  const int64_t col0 = a.col0[v];
+  const int64_t tbeg = int64_t(blockIdx.y) * a.tchunk;
+  const int64_t tend = min(a.nt_test, tbeg + a.tchunk);
+  for (int64_t tl = tbeg; tl < tend; ++tl) {
+    const int64_t t = a.t0 + tl;
+    const v3 d = G3(geo, nt, kGeoC, t) - pv;
+    cz acc[MAXV][3];
+#pragma unroll
+    for (int b = 0; b < MAXV; ++b)
+#pragma unroll
+      for (int i = 0; i < 3; ++i) acc[b][i] = {0, 0};
+    for (int sidx = 0; sidx < 2 * nval; ++sidx) {
+      const size_t so = size_t(sidx) * nc + v;
+      const v3 sm = mk(a.sub_m[3 * so], a.sub_m[3 * so + 1], a.sub_m[3 * so + 2]);
+      const v3 sc = mk(a.sub_c[3 * so], a.sub_c[3 * so + 1], a.sub_c[3 * so + 2]);
+      // Q3 points relative to v (the vertex v is the origin)
+      v3 dj[3];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) dj[j] = cB3[j][1] * sm + cB3[j][2] * sc;
+      cz P = {0, 0};
+      cv3 Q = cvzero(), Rm = cvzero(), S = cvzero();
+#pragma unroll
+      for (int k = 0; k < 7; ++k) {
+        const v3 dk = G3(geo, nt, kGeoQ + 3 * k, t);
+        const v3 Dk = d + dk;
+        cz m0 = {0, 0};
+        cv3 m1 = cvzero();
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          v3 r = Dk - dj[j];
+          double r2 = dot(r, r);
+          double inv = rsqrt(r2);
+          double R = r2 * inv;
+          cz g = cscale(1.0 / 3.0, grad_green<LOSSY>(a.kr, a.ki, R, inv));
+          m0 = cadd(m0, g);
+          cv_axpy(m1, g, dj[j]);
+        }
+        const double wk = cW7[k];
+        // u = m1 - Delta m0
+        cv3 u = m1;
+        cv_axpy(u, cscale(-1.0, m0), Dk);
+        cv3 Dxm1 = rc_cross(Dk, m1);
+        cv3 dkxu = rc_cross(dk, u);
+        P = cadd(P, cscale(wk, cv_dot(dk, rc_cross(d, m1))));
+        Q.x = cadd(Q.x, cscale(wk, Dxm1.x)); Q.y = cadd(Q.y, cscale(wk, Dxm1.y)); Q.z = cadd(Q.z, cscale(wk, Dxm1.z));
+        Rm.x = cadd(Rm.x, cscale(wk, dkxu.x)); Rm.y = cadd(Rm.y, cscale(wk, dkxu.y)); Rm.z = cadd(Rm.z, cscale(wk, dkxu.z));
+        S.x = cadd(S.x, cscale(wk, u.x)); S.y = cadd(S.y, cscale(wk, u.y)); S.z = cadd(S.z, cscale(wk, u.z));
+      }
+      // per test half i: X_i = P - p_i.Q ;  Y_i = R - p_i x S
+      cz X[3];
+      cv3 Y[3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const v3 pi = G3(geo, nt, kGeoP + 3 * i, t);  // test vertex relative to the test centroid
+        X[i] = csub(P, cv_dot(pi, Q));
+        cv3 pxS = rc_cross(pi, S);
+        Y[i].x = csub(Rm.x, pxS.x); Y[i].y = csub(Rm.y, pxS.y); Y[i].z = csub(Rm.z, pxS.z);
+      }
+#pragma unroll
+      for (int b = 0; b < MAXV; ++b) {
+        if (b < nval) {
+          const double al = 0.25 * a.alpha[size_t(b) * nc + v];
+          const size_t bo = (size_t(b) * (2 * MAXV) + sidx) * nc + v;
+          const v3 be = 0.25 * mk(a.beta[3 * bo], a.beta[3 * bo + 1], a.beta[3 * bo + 2]);
+#pragma unroll
+          for (int i = 0; i < 3; ++i) acc[b][i] = cadd(acc[b][i], cadd(cscale(al, X[i]), cv_dot(be, Y[i])));
+        }
+      }
+    }
+    double2* out = a.Kc + (3 * tl) * a.ldK + col0;
+#pragma unroll
+    for (int b = 0; b < MAXV; ++b)
+      if (b < nval)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) out[i * a.ldK + b] = make_double2(acc[b][i].re, acc[b][i].im);
+  }
+}
+
+// ------------------------------------------------------------------ K near
+// Thread per near (T, cell) pair: recompute the whole cell with the far moments for far
+// sub-triangles and, for sub-triangles whose primal triangle is near T and not coplanar with
+// it, with the extracted inner integral v_k = int_t g_k (r_k - r') dS':
+//   v_k = -J/(4 pi) + k^2/(8 pi) Iv + sum_j w_j A_t h(R_kj) (r_k - r'_j)
+// and the contribution 1/(4 A_t) sum_k w_k (r_k - p_i) . [v_k x (alpha (r_k - v) - beta)].
+template <bool LOSSY, int MAXV>
+__global__ void __launch_bounds__(64) k_fill_K_near(FillKArgs a, const int32_t* __restrict__ pt,
+                                                    const int32_t* __restrict__ pc, int64_t npairs,
+                                                    const int64_t* __restrict__ near_ptr,
+                                                    const int32_t* __restrict__ near_idx) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= npairs) return;
+  const int64_t t = pt[p];
+  const int32_t v = pc[p];
+  const int64_t nc = a.ncell_total;
+  const double* geo = a.geo;
+  const int64_t nt = a.nt_total;
+  const int nval = a.nval[v];
+  const v3 pv = mk(a.vpos[3 * v], a.vpos[3 * v + 1], a.vpos[3 * v + 2]);
+  const v3 ct = G3(geo, nt, kGeoC, t);
+  const v3 nT = G3(geo, nt, kGeoN, t);
+  const double hT = G(geo, nt, kGeoH, t);
+  const v3 d = ct - pv;
+  const double kr = a.kr, ki = a.ki;
+  cz k2 = cmul({kr, ki}, {kr, ki});
+  cz acc[MAXV][3];
+  for (int b = 0; b < MAXV; ++b)
+    for (int i = 0; i < 3; ++i) acc[b][i] = {0, 0};
+  for (int sidx = 0; sidx < 2 * nval; ++sidx) {
+    const size_t so = size_t(sidx) * nc + v;
+    const v3 sm = mk(a.sub_m[3 * so], a.sub_m[3 * so + 1], a.sub_m[3 * so + 2]);
+    const v3 sc = mk(a.sub_c[3 * so], a.sub_c[3 * so + 1], a.sub_c[3 * so + 2]);
+    const double At = a.sub_area[so];
+    const int32_t par = a.sub_parent[so];
+    // is (t, par) a near pair?  binary search in the sorted near list of t
+    int64_t lo = near_ptr[t], hi = near_ptr[t + 1];
+    bool is_near = false;
+    while (lo < hi) {
+      int64_t mid = (lo + hi) >> 1;
+      int32_t x = near_idx[mid];
+      if (x == par) { is_near = true; break; }
+      if (x < par) lo = mid + 1; else hi = mid;
+    }
+    v3 dj[3];
+    for (int j = 0; j < 3; ++j) dj[j] = cB3[j][1] * sm + cB3[j][2] * sc;
+    if (!is_near) {
+      cz P = {0, 0};
+      cv3 Q = cvzero(), Rm = cvzero(), S = cvzero();
+      for (int k = 0; k < 7; ++k) {
+        const v3 dk = G3(geo, nt, kGeoQ + 3 * k, t);
+        const v3 Dk = d + dk;
+        cz m0 = {0, 0};
+        cv3 m1 = cvzero();
+        for (int j = 0; j < 3; ++j) {
+          v3 r = Dk - dj[j];
+          double r2 = dot(r, r);
+          double inv = rsqrt(r2);
+          cz g = cscale(1.0 / 3.0, grad_green<LOSSY>(kr, ki, r2 * inv, inv));
+          m0 = cadd(m0, g);
+          cv_axpy(m1, g, dj[j]);
+        }
+        const double wk = cW7[k];
+        cv3 u = m1;
+        cv_axpy(u, cscale(-1.0, m0), Dk);
+        cv3 Dxm1 = rc_cross(Dk, m1);
+        cv3 dkxu = rc_cross(dk, u);
+        P = cadd(P, cscale(wk, cv_dot(dk, rc_cross(d, m1))));
+        Q.x = cadd(Q.x, cscale(wk, Dxm1.x)); Q.y = cadd(Q.y, cscale(wk, Dxm1.y)); Q.z = cadd(Q.z, cscale(wk, Dxm1.z));
+        Rm.x = cadd(Rm.x, cscale(wk, dkxu.x)); Rm.y = cadd(Rm.y, cscale(wk, dkxu.y)); Rm.z = cadd(Rm.z, cscale(wk, dkxu.z));
+        S.x = cadd(S.x, cscale(wk, u.x)); S.y = cadd(S.y, cscale(wk, u.y)); S.z = cadd(S.z, cscale(wk, u.z));
+      }
+      for (int i = 0; i < 3; ++i) {
+        const v3 pi = G3(geo, nt, kGeoP + 3 * i, t);
+        cz X = csub(P, cv_dot(pi, Q));
+        cv3 pxS = rc_cross(pi, S);
+        cv3 Y;
+        Y.x = csub(Rm.x, pxS.x); Y.y = csub(Rm.y, pxS.y); Y.z = csub(Rm.z, pxS.z);
+        for (int b = 0; b < MAXV; ++b) {
+          if (b < nval) {
+            const double al = 0.25 * a.alpha[size_t(b) * nc + v];
+            const size_t bo = (size_t(b) * (2 * MAXV) + sidx) * nc + v;
+            const v3 be = 0.25 * mk(a.beta[3 * bo], a.beta[3 * bo + 1], a.beta[3 * bo + 2]);
+            acc[b][i] = cadd(acc[b][i], cadd(cscale(al, X), cv_dot(be, Y)));
+          }
+        }
+      }
+      continue;
+    }
+    // near: zero when coplanar with the test triangle
+    const v3 nP = G3(geo, nt, kGeoN, par);
+    const v3 cP = G3(geo, nt, kGeoC, par);
+    if (fabs(dot(nP, nT)) > 1.0 - 1e-12 && fabs(dot(cP - ct, nT)) < 1e-10 * hT) continue;
+    // sub-triangle vertices relative to v: (0, m, c) (the closed forms do not depend on the
+    // vertex order)
+    const v3 A0 = mk(0, 0, 0), A1 = sm, A2 = sc;
+    for (int k = 0; k < 7; ++k) {
+      const v3 dk = G3(geo, nt, kGeoQ + 3 * k, t);
+      const v3 Dk = d + dk;  // r_k - v
+      StaticInts si = static_ints(Dk, A0, A1, A2, true);
+      cv3 vk = cvzero();
+      vk.x.re = -kInv4Pi * si.j3.x; vk.y.re = -kInv4Pi * si.j3.y; vk.z.re = -kInv4Pi * si.j3.z;
+      cz c8 = cscale(0.5 * kInv4Pi, k2);  // k^2/(8 pi)
+      cv_axpy(vk, c8, si.iv);
+      for (int j = 0; j < 3; ++j) {
+        const v3 dd = Dk - dj[j];
+        const double R = norm(dd);
+        cz h = cscale(At / 3.0, grad_green_rem(kr, ki, R));
+        cv_axpy(vk, h, dd);
+      }
+      const double wk = cW7[k] / (4.0 * At);
+      for (int b = 0; b < MAXV; ++b) {
+        if (b < nval) {
+          const double al = a.alpha[size_t(b) * nc + v];
+          const size_t bo = (size_t(b) * (2 * MAXV) + sidx) * nc + v;
+          const v3 be = mk(a.beta[3 * bo], a.beta[3 * bo + 1], a.beta[3 * bo + 2]);
+          const v3 gvec = al * Dk - be;
+          // v_k x gvec  (complex x real)
+          cv3 vxg;
+          vxg.x = {vk.y.re * gvec.z - vk.z.re * gvec.y, vk.y.im * gvec.z - vk.z.im * gvec.y};
+          vxg.y = {vk.z.re * gvec.x - vk.x.re * gvec.z, vk.z.im * gvec.x - vk.x.im * gvec.z};
+          vxg.z = {vk.x.re * gvec.y - vk.y.re * gvec.x, vk.x.im * gvec.y - vk.y.im * gvec.x};
+          for (int i = 0; i < 3; ++i) {
+            const v3 pi = G3(geo, nt, kGeoP + 3 * i, t);
+            acc[b][i] = cadd(acc[b][i], cscale(wk, cv_dot(dk - pi, vxg)));
+          }
+        }
+      }
+    }
+  }
+  double2* out = a.Kc + (3 * (t - a.t0)) * a.ldK + a.col0[v];
+  for (int b = 0; b < MAXV; ++b)
+    if (b < nval)
+      for (int i = 0; i < 3; ++i) out[i * a.ldK + b] = make_double2(acc[b][i].re, acc[b][i].im);
+}
+
+// ------------------------------------------------------------------ RHS
+// Plane wave (right-hand side of eq. AEFIEextdis): b_m = eta0^-1 int f_m . pol E0 e^{-j k_l khat.r}
+// = eta0^-1 sum over the two halves s/2 sum_k w_k (d_k - p_i) . pol E0 e^{-j k_l khat.(c + d_k)}.
+__global__ void k_rhs_planewave(RhsArgs a) {
+  const int64_t m = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int e = blockIdx.y;
+  if (m >= a.ne) return;
+  const double* geo = a.geo;
+  const int64_t nt = a.nt_total;
+  const v3 kh = mk(a.khat[3 * e], a.khat[3 * e + 1], a.khat[3 * e + 2]);
+  const double2 p0 = a.pol[3 * e], p1 = a.pol[3 * e + 1], p2 = a.pol[3 * e + 2];
+  const double2 amp = a.amp[e];
+  cz acc = {0, 0};
+  for (int h = 0; h < 2; ++h) {
+    const int64_t t = h == 0 ? a.tp[m] : a.tm[m];
+    const int i = h == 0 ? a.ip[m] : a.im[m];
+    const double sg = h == 0 ? 0.5 : -0.5;
+    const v3 c = G3(geo, nt, kGeoC, t);
+    const v3 pi = G3(geo, nt, kGeoP + 3 * i, t);
+    for (int k = 0; k < 7; ++k) {
+      const v3 dk = G3(geo, nt, kGeoQ + 3 * k, t);
+      const v3 f = dk - pi;
+      const double ph = dot(kh, c + dk);
+      double s, co;
+      sincos(a.klr * ph, &s, &co);
+      const double ea = exp(a.kli * ph);
+      const cz e0 = {ea * co, -ea * s};
+      const cz fp = {f.x * p0.x + f.y * p1.x + f.z * p2.x, f.x * p0.y + f.y * p1.y + f.z * p2.y};
+      acc = cadd(acc, cscale(sg * cW7[k], cmul(fp, e0)));
+    }
+  }
+  const cz r = cscale(a.inv_eta0, cmul(acc, {amp.x, amp.y}));
+  a.b[e * a.ldb + m] = make_double2(r.re, r.im);
+}
+
+}  // namespace dev
+
+// ------------------------------------------------------------------ launchers
+
+void launch_rhs_planewave(const RhsArgs& a, int nexc, hipStream_t st) {
+  if (a.ne <= 0 || nexc <= 0) return;
+  hipLaunchKernelGGL(dev::k_rhs_planewave, dim3(unsigned((a.ne + 127) / 128), unsigned(nexc)), dim3(128), 0, st, a);
+  BEM_HIP(hipGetLastError());
+}
+
+void fill_set_rules(const double w7[7], const double b3[3][3]) {
+  BEM_HIP(hipMemcpyToSymbol(HIP_SYMBOL(dev::cW7), w7, sizeof(double) * 7));
+  BEM_HIP(hipMemcpyToSymbol(HIP_SYMBOL(dev::cB3), b3, sizeof(double) * 9));
+}
+
+void launch_fill_L(const FillLArgs& a, const int32_t* near_t, const int32_t* near_s, int64_t npairs,
+                   hipStream_t st) {
+  if (a.ns <= 0 || a.nt_test <= 0) return;
+  dim3 grid(unsigned((a.ns + 255) / 256), unsigned((a.nt_test + a.tchunk - 1) / a.tchunk));
+  bool lossy = a.ki != 0.0;
+  if (lossy) hipLaunchKernelGGL(dev::k_fill_L_far<true>, grid, dim3(256), 0, st, a);
+  else hipLaunchKernelGGL(dev::k_fill_L_far<false>, grid, dim3(256), 0, st, a);
+  BEM_HIP(hipGetLastError());
+  if (npairs > 0) {
+    dim3 g2(unsigned((npairs + 127) / 128));
+    if (lossy) hipLaunchKernelGGL(dev::k_fill_L_near<true>, g2, dim3(128), 0, st, a, near_t, near_s, npairs);
+    else hipLaunchKernelGGL(dev::k_fill_L_near<false>, g2, dim3(128), 0, st, a, near_t, near_s, npairs);
+    BEM_HIP(hipGetLastError());
+  }
+}
+
+void launch_gather_LA(const double2* H, int64_t ldH, const int32_t* hp, const int32_t* hm, int64_t off, int64_t ne,
+                      double2* out, int64_t ldo, hipStream_t st) {
+  if (ne <= 0) return;
+  dim3 grid(unsigned((ne + 255) / 256), unsigned(std::min<int64_t>(ne, 32768)));
+  hipLaunchKernelGGL(dev::k_gather_LA, grid, dim3(256), 0, st, H, ldH, hp, hm, off, ne, out, ldo);
+  BEM_HIP(hipGetLastError());
+}
+
+void launch_fill_K(const FillKArgs& a, const int32_t* near_t, const int32_t* near_c, int64_t npairs,
+                   const int64_t* near_ptr, const int32_t* near_idx, int maxv, hipStream_t st) {
+  if (a.ncells <= 0 || a.nt_test <= 0) return;
+  dim3 grid(unsigned((a.ncells + 127) / 128), unsigned((a.nt_test + a.tchunk - 1) / a.tchunk));
+  bool lossy = a.ki != 0.0;
+  dim3 g2(unsigned((npairs + 63) / 64));
+#define BEM_KLAUNCH(L, MV)                                                                          \
+  hipLaunchKernelGGL((dev::k_fill_K_far<L, MV>), grid, dim3(128), 0, st, a);                        \
+  BEM_HIP(hipGetLastError());                                                                       \
+  if (npairs > 0) {                                                                                 \
+    hipLaunchKernelGGL((dev::k_fill_K_near<L, MV>), g2, dim3(64), 0, st, a, near_t, near_c, npairs, \
+                       near_ptr, near_idx);                                                         \
+    BEM_HIP(hipGetLastError());                                                                     \
+  }
+  if (maxv == 8) {
+    if (lossy) { BEM_KLAUNCH(true, 8) } else { BEM_KLAUNCH(false, 8) }
+  } else if (maxv == 16) {
+    if (lossy) { BEM_KLAUNCH(true, 16) } else { BEM_KLAUNCH(false, 16) }
+  } else {
+    throw Error(BEM_E_INVALID, "unsupported padded valence");
+  }
+#undef BEM_KLAUNCH
+}
+
+void launch_gather_K(const double2* Kc, int64_t ldK, const int32_t* hp, const int32_t* hm, const int32_t* cS,
+                     const int32_t* cT, int64_t off, int64_t ne, double2* out, int64_t ldo, hipStream_t st) {
+  if (ne <= 0) return;
+  dim3 grid(unsigned((ne + 255) / 256), unsigned(std::min<int64_t>(ne, 32768)));
+  hipLaunchKernelGGL(dev::k_gather_K, grid, dim3(256), 0, st, Kc, ldK, hp, hm, cS, cT, off, ne, out, ldo);
+  BEM_HIP(hipGetLastError());
+}
+
+}  // namespace bem

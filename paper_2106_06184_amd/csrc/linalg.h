@@ -1,0 +1,97 @@
+// Dense products, sparse glue and Krylov kernels (interface shared by the host driver).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace bem {
+
+// One dense product y (+)= alpha A x [+ alpha2 A2 x2], A and A2 row-major complex with the same
+// shape and storage (float64 or float32).
+struct GemvDesc {
+  const void* A;      // double2* (fp64) or float2* (fp32) rows x cols, leading dimension lda
+  const void* A2;     // optional second matrix (same shape, lda2), or nullptr
+  int64_t lda, lda2;
+  int64_t rows, cols;
+  const double2* x;   // cols, float64 complex
+  const double2* x2;
+  double2* y;         // rows, float64 complex
+  double2 alpha, alpha2;
+  int accumulate;     // 0: y = ... ; 1: y += ...
+  int fp32;           // storage of A (and A2)
+  int64_t tile0;      // first row tile of this descriptor (filled by the launcher)
+};
+constexpr int kMaxGroup = 8;
+struct GemvPack {
+  GemvDesc d[kMaxGroup];
+  int n;
+};
+
+// Runs all descriptors (any number; kMaxGroup per launch) with their rows spread over the grid.
+// Descriptors travel as kernel arguments; the call is asynchronous on `st`.
+void launch_gemv_grouped(const GemvDesc* host_descs, int n, hipStream_t st);
+
+// Multi-RHS dense product Y (+)= alpha A X on float32 matrix cores (complex 4M split) or
+// float64 (plain VALU): X column-major cols x nrhs (ldx), Y column-major rows x nrhs (ldy).
+struct GemmDesc {
+  const void* A;
+  int64_t lda, rows, cols;
+  const double2* X;
+  int64_t ldx;
+  double2* Y;
+  int64_t ldy;
+  int64_t nrhs;
+  double2 alpha;
+  int accumulate;
+  int fp32;
+};
+void launch_gemm(const GemmDesc& d, void* ws, size_t ws_bytes, hipStream_t st);
+
+// ---- sparse glue (float64 complex vectors)
+// Charges: full[t] (per triangle) from reduced w (kept triangles); the last triangle of each
+// object gets minus the sum of the object's other charges.  kept_of[t] = index into w or -1.
+void launch_expand_charge(const double2* w, double2* full, const int64_t* obj_tri, int64_t nobj,
+                          double2 scale, hipStream_t st);
+// y[n] (+)= s * sedge[n] * (z[T+(n)] - z[T-(n)])      (D^T z; sedge may be null)
+void launch_DT(const double2* z, const int32_t* tp, const int32_t* tm, int64_t ne, double2 s, const double2* sedge,
+               double2* y, int accumulate, hipStream_t st);
+// Reduced continuity rows: y[q] = s1 * (D u)[t(q)] + s2 * w[q] for kept triangles q (F D u + s2 w)
+void launch_FD(const double2* u, const int32_t* tri_edge, const int8_t* tri_sign, const int32_t* kept_tri,
+               int64_t nq, double2 s1, const double2* w, double2 s2, double2* y, hipStream_t st);
+// y (+)= s * S x for a CSR real sparse matrix S
+void launch_spmv(const int64_t* ptr, const int32_t* idx, const double* val, int64_t rows, const double2* x,
+                 double2 s, double2* y, int accumulate, hipStream_t st);
+// z = a*x + b*y (elementwise, n)
+void launch_axpby(int64_t n, double2 a, const double2* x, double2 b, const double2* y, double2* z,
+                  hipStream_t st);
+void launch_cast_f32(const double2* src, int64_t rows, int64_t cols, int64_t lds, float2* dst, int64_t ldd,
+                     hipStream_t st);
+
+// ---- Krylov (float64 complex, deterministic reductions)
+struct KrylovScratch {
+  double2* partial;       // nblk * (mmax + 1)
+  unsigned int* counter;  // 1 (zero-initialised once; every kernel leaves it at zero)
+  int nblk;
+};
+// h[i] = sum_n conj(V[i][n]) w[n], i < j   (V rows of length ldv)
+void launch_mdot(const double2* V, int64_t ldv, int j, const double2* w, int64_t n, double2* h,
+                 const KrylovScratch& ks, hipStream_t st);
+// w -= sum_i V[i] h[i] (sign = -1) or x += sum_i V[i] h[i] (sign = +1)
+void launch_mupdate(const double2* V, int64_t ldv, int j, const double2* h, double sign, double2* w, int64_t n,
+                    hipStream_t st);
+// out = ||w||_2 (as the real part of a double2)
+void launch_norm(const double2* w, int64_t n, double2* out, const KrylovScratch& ks, hipStream_t st);
+// v = w / nrm
+void launch_scale_inv(const double2* w, int64_t n, const double2* nrm, double2* v, hipStream_t st);
+// Givens step on Hessenberg column j (column stored contiguously at Hcol, j+2 entries; the
+// second Gram-Schmidt pass h2[0..j] is added first), rotations cs/sn (mmax), right-hand side g
+// (mmax+1); writes |g[j+1]| into res.
+void launch_givens(double2* Hcol, int j, double2* cs, double2* sn, double2* g, double* res, const double2* h2,
+                   hipStream_t st);
+// Back substitution y = R^{-1} g for the leading j x j block (H column-major, ldh), y in place of g.
+void launch_backsolve(const double2* H, int64_t ldh, int j, double2* g, double2* y, hipStream_t st);
+// g = (beta, 0, ..., 0) with beta = ||r|| read from device
+void launch_init_g(double2* g, int mmax, const double2* beta, hipStream_t st);
+
+}  // namespace bem

@@ -1,0 +1,523 @@
+// Dense complex products, sparse glue and Krylov kernels (gfx950).
+//
+// The single-excitation products are HBM-bound (one complex MAC per matrix element read):
+// every wave owns RPW rows of one dense block, its 64 lanes stream the rows with 16-byte loads
+// (one float64 complex, or two float32 complex per load), the x chunk is loaded once per wave
+// and reused for all RPW rows, and the row sums are reduced with cross-lane shuffles.  Several
+// independent products (different matrices and vectors) share one launch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "linalg.h"
+
+namespace bem {
+namespace dev {
+
+constexpr int kWave = 64;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+// Row sums of one matrix for RPW consecutive rows, float64 storage, float64 accumulation.
+template <int RPW>
+__device__ __forceinline__ void rows_f64(const double2* __restrict__ A, int64_t lda, int64_t rows, int64_t cols,
+                                         const double2* __restrict__ x, int64_t row0, int lane, double2 alpha,
+                                         double* yr, double* yi) {
+  double ar[RPW], ai[RPW];
+#pragma unroll
+  for (int r = 0; r < RPW; ++r) ar[r] = ai[r] = 0.0;
+  const double2* rowp[RPW];
+#pragma unroll
+  for (int r = 0; r < RPW; ++r) rowp[r] = A + min(row0 + r, rows - 1) * lda;
+  int64_t c = lane;
+  for (; c + kWave < cols; c += 2 * kWave) {
+    const double2 x0 = x[c], x1 = x[c + kWave];
+    double2 a0[RPW], a1[RPW];
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+      a0[r] = rowp[r][c];
+      a1[r] = rowp[r][c + kWave];
+    }
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+      ar[r] += a0[r].x * x0.x - a0[r].y * x0.y + a1[r].x * x1.x - a1[r].y * x1.y;
+      ai[r] += a0[r].x * x0.y + a0[r].y * x0.x + a1[r].x * x1.y + a1[r].y * x1.x;
+    }
+  }
+  for (; c < cols; c += kWave) {
+    const double2 x0 = x[c];
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+      const double2 a0 = rowp[r][c];
+      ar[r] += a0.x * x0.x - a0.y * x0.y;
+      ai[r] += a0.x * x0.y + a0.y * x0.x;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < RPW; ++r) {
+    const double sr = wave_sum(ar[r]), si = wave_sum(ai[r]);
+    yr[r] += alpha.x * sr - alpha.y * si;
+    yi[r] += alpha.x * si + alpha.y * sr;
+  }
+}
+
+// float32 storage and accumulation; each lane reads two consecutive complex entries per
+// 16-byte load (two 8-byte loads when the rows are not 16-byte aligned).
+template <int RPW, bool ALIGNED>
+__device__ __forceinline__ void rows_f32(const float2* __restrict__ A, int64_t lda, int64_t rows, int64_t cols,
+                                         const double2* __restrict__ x, int64_t row0, int lane, double2 alpha,
+                                         double* yr, double* yi) {
+  float ar[RPW], ai[RPW];
+#pragma unroll
+  for (int r = 0; r < RPW; ++r) ar[r] = ai[r] = 0.0f;
+  const float2* rowp[RPW];
+#pragma unroll
+  for (int r = 0; r < RPW; ++r) rowp[r] = A + min(row0 + r, rows - 1) * lda;
+  int64_t c = 2 * lane;
+  const int64_t full = cols & ~int64_t(1);
+  for (; c + 2 * kWave < full; c += 4 * kWave) {
+    const double2 xa = x[c], xb = x[c + 1], xc = x[c + 2 * kWave], xd = x[c + 2 * kWave + 1];
+    const float x0r = float(xa.x), x0i = float(xa.y), x1r = float(xb.x), x1i = float(xb.y);
+    const float x2r = float(xc.x), x2i = float(xc.y), x3r = float(xd.x), x3i = float(xd.y);
+    float4 a0[RPW], a1[RPW];
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+      if (ALIGNED) {
+        a0[r] = *reinterpret_cast<const float4*>(rowp[r] + c);
+        a1[r] = *reinterpret_cast<const float4*>(rowp[r] + c + 2 * kWave);
+      } else {
+        const float2 p0 = rowp[r][c], p1 = rowp[r][c + 1];
+        const float2 p2 = rowp[r][c + 2 * kWave], p3 = rowp[r][c + 2 * kWave + 1];
+        a0[r] = make_float4(p0.x, p0.y, p1.x, p1.y);
+        a1[r] = make_float4(p2.x, p2.y, p3.x, p3.y);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+      ar[r] += a0[r].x * x0r - a0[r].y * x0i + a0[r].z * x1r - a0[r].w * x1i;
+      ai[r] += a0[r].x * x0i + a0[r].y * x0r + a0[r].z * x1i + a0[r].w * x1r;
+      ar[r] += a1[r].x * x2r - a1[r].y * x2i + a1[r].z * x3r - a1[r].w * x3i;
+      ai[r] += a1[r].x * x2i + a1[r].y * x2r + a1[r].z * x3i + a1[r].w * x3r;
+    }
+  }
+  for (; c < cols; c += 2 * kWave) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (c + h < cols) {
+        const double2 xv = x[c + h];
+        const float xr = float(xv.x), xi = float(xv.y);
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) {
+          const float2 a0 = rowp[r][c + h];
+          ar[r] += a0.x * xr - a0.y * xi;
+          ai[r] += a0.x * xi + a0.y * xr;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < RPW; ++r) {
+    const double sr = double(wave_sum(ar[r])), si = double(wave_sum(ai[r]));
+    yr[r] += alpha.x * sr - alpha.y * si;
+    yi[r] += alpha.x * si + alpha.y * sr;
+  }
+}
+
+constexpr int kRPW = 2;          // rows per wave
+constexpr int kWavesPerBlock = 4;
+constexpr int kRowsPerBlock = kRPW * kWavesPerBlock;
+
+__global__ void __launch_bounds__(256) k_gemv_grouped(GemvPack pack) {
+  const int64_t b = blockIdx.x;
+  int di = 0;
+  while (di + 1 < pack.n && pack.d[di + 1].tile0 <= b) ++di;
+  const GemvDesc& d = pack.d[di];
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int64_t row0 = (b - d.tile0) * kRowsPerBlock + int64_t(wave) * kRPW;
+  if (row0 >= d.rows) return;
+  double yr[kRPW], yi[kRPW];
+#pragma unroll
+  for (int r = 0; r < kRPW; ++r) yr[r] = yi[r] = 0.0;
+  if (d.fp32) {
+    const bool al1 = ((reinterpret_cast<uintptr_t>(d.A) | uintptr_t(d.lda * 8)) & 15) == 0;
+    if (al1)
+      rows_f32<kRPW, true>(static_cast<const float2*>(d.A), d.lda, d.rows, d.cols, d.x, row0, lane, d.alpha, yr, yi);
+    else
+      rows_f32<kRPW, false>(static_cast<const float2*>(d.A), d.lda, d.rows, d.cols, d.x, row0, lane, d.alpha, yr, yi);
+    if (d.A2) {
+      const bool al2 = ((reinterpret_cast<uintptr_t>(d.A2) | uintptr_t(d.lda2 * 8)) & 15) == 0;
+      if (al2)
+        rows_f32<kRPW, true>(static_cast<const float2*>(d.A2), d.lda2, d.rows, d.cols, d.x2, row0, lane, d.alpha2,
+                             yr, yi);
+      else
+        rows_f32<kRPW, false>(static_cast<const float2*>(d.A2), d.lda2, d.rows, d.cols, d.x2, row0, lane, d.alpha2,
+                              yr, yi);
+    }
+  } else {
+    rows_f64<kRPW>(static_cast<const double2*>(d.A), d.lda, d.rows, d.cols, d.x, row0, lane, d.alpha, yr, yi);
+    if (d.A2)
+      rows_f64<kRPW>(static_cast<const double2*>(d.A2), d.lda2, d.rows, d.cols, d.x2, row0, lane, d.alpha2, yr, yi);
+  }
+#pragma unroll
+  for (int r = 0; r < kRPW; ++r) {
+    if (lane == r && row0 + r < d.rows) {
+      double2* y = d.y + row0 + r;
+      double vr = yr[r], vi = yi[r];
+      if (d.accumulate) { vr += y->x; vi += y->y; }
+      *y = make_double2(vr, vi);
+    }
+  }
+}
+
+// ----------------------------------------------------------------- glue
+
+__global__ void k_expand_charge(const double2* __restrict__ w, double2* __restrict__ full,
+                                const int64_t* __restrict__ obj_tri, double2 scale) {
+  const int64_t o = blockIdx.x;
+  const int64_t t0 = obj_tri[o], t1 = obj_tri[o + 1];
+  // kept charges of object o are w[t0 - o .. t1 - o - 2]; the last triangle t1-1 is eliminated
+  const int64_t q0 = t0 - o;
+  const int64_t nk = t1 - t0 - 1;
+  __shared__ double sr[256], si[256];
+  double ar = 0, ai = 0;
+  for (int64_t i = threadIdx.x; i < nk; i += blockDim.x) {
+    const double2 v = w[q0 + i];
+    ar += v.x;
+    ai += v.y;
+    full[t0 + i] = make_double2(scale.x * v.x - scale.y * v.y, scale.x * v.y + scale.y * v.x);
+  }
+  sr[threadIdx.x] = ar;
+  si[threadIdx.x] = ai;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      sr[threadIdx.x] += sr[threadIdx.x + s];
+      si[threadIdx.x] += si[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double r = -sr[0], i = -si[0];
+    full[t1 - 1] = make_double2(scale.x * r - scale.y * i, scale.x * i + scale.y * r);
+  }
+}
+
+__global__ void k_DT(const double2* __restrict__ z, const int32_t* __restrict__ tp, const int32_t* __restrict__ tm,
+                     int64_t ne, double2 s, const double2* __restrict__ sedge, double2* __restrict__ y, int acc) {
+  const int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (n >= ne) return;
+  const double2 a = z[tp[n]], b = z[tm[n]];
+  const double dr = a.x - b.x, di = a.y - b.y;
+  double2 sc = s;
+  if (sedge) {
+    const double2 q = sedge[n];
+    sc = make_double2(s.x * q.x - s.y * q.y, s.x * q.y + s.y * q.x);
+  }
+  double yr = sc.x * dr - sc.y * di, yi = sc.x * di + sc.y * dr;
+  if (acc) { yr += y[n].x; yi += y[n].y; }
+  y[n] = make_double2(yr, yi);
+}
+
+__global__ void k_FD(const double2* __restrict__ u, const int32_t* __restrict__ tri_edge,
+                     const int8_t* __restrict__ tri_sign, const int32_t* __restrict__ kept, int64_t nq, double2 s1,
+                     const double2* __restrict__ w, double2 s2, double2* __restrict__ y) {
+  const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= nq) return;
+  const int64_t t = kept[q];
+  double dr = 0, di = 0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const double2 v = u[tri_edge[3 * t + i]];
+    const double sg = double(tri_sign[3 * t + i]);
+    dr += sg * v.x;
+    di += sg * v.y;
+  }
+  double yr = s1.x * dr - s1.y * di, yi = s1.x * di + s1.y * dr;
+  if (w) {
+    const double2 v = w[q];
+    yr += s2.x * v.x - s2.y * v.y;
+    yi += s2.x * v.y + s2.y * v.x;
+  }
+  y[q] = make_double2(yr, yi);
+}
+
+__global__ void k_spmv(const int64_t* __restrict__ ptr, const int32_t* __restrict__ idx, const double* __restrict__ val,
+                       int64_t rows, const double2* __restrict__ x, double2 s, double2* __restrict__ y, int acc) {
+  const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  double ar = 0, ai = 0;
+  for (int64_t p = ptr[r]; p < ptr[r + 1]; ++p) {
+    const double2 v = x[idx[p]];
+    ar += val[p] * v.x;
+    ai += val[p] * v.y;
+  }
+  double yr = s.x * ar - s.y * ai, yi = s.x * ai + s.y * ar;
+  if (acc) { yr += y[r].x; yi += y[r].y; }
+  y[r] = make_double2(yr, yi);
+}
+
+__global__ void k_axpby(int64_t n, double2 a, const double2* __restrict__ x, double2 b, const double2* __restrict__ y,
+                        double2* __restrict__ z) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double2 u = x ? x[i] : make_double2(0, 0), v = y ? y[i] : make_double2(0, 0);
+  z[i] = make_double2(a.x * u.x - a.y * u.y + b.x * v.x - b.y * v.y, a.x * u.y + a.y * u.x + b.x * v.y + b.y * v.x);
+}
+
+__global__ void k_cast_f32(const double2* __restrict__ src, int64_t rows, int64_t cols, int64_t lds,
+                           float2* __restrict__ dst, int64_t ldd) {
+  const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t r = blockIdx.y;
+  if (c >= ldd) return;
+  if (c < cols) {
+    const double2 v = src[r * lds + c];
+    dst[r * ldd + c] = make_float2(float(v.x), float(v.y));
+  } else {
+    dst[r * ldd + c] = make_float2(0.f, 0.f);
+  }
+}
+
+// ----------------------------------------------------------------- Krylov
+
+// one block per basis vector: h[i] = sum_n conj(V_i[n]) w[n]
+__global__ void __launch_bounds__(256) k_mdot(const double2* __restrict__ V, int64_t ldv,
+                                              const double2* __restrict__ w, int64_t n, double2* __restrict__ h) {
+  const int i = blockIdx.x;
+  const double2* vi = V + int64_t(i) * ldv;
+  double ar = 0, ai = 0;
+  for (int64_t k = threadIdx.x; k < n; k += blockDim.x) {
+    const double2 a = vi[k], b = w[k];
+    ar += a.x * b.x + a.y * b.y;
+    ai += a.x * b.y - a.y * b.x;
+  }
+  __shared__ double sr[4], si[4];
+  ar = wave_sum(ar);
+  ai = wave_sum(ai);
+  const int wv = threadIdx.x / kWave;
+  if (threadIdx.x % kWave == 0) { sr[wv] = ar; si[wv] = ai; }
+  __syncthreads();
+  if (threadIdx.x == 0) h[i] = make_double2(sr[0] + sr[1] + sr[2] + sr[3], si[0] + si[1] + si[2] + si[3]);
+}
+
+__global__ void k_mupdate(const double2* __restrict__ V, int64_t ldv, int j, const double2* __restrict__ h, double sign,
+                          double2* __restrict__ w, int64_t n) {
+  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  double ar = w[k].x, ai = w[k].y;
+  for (int i = 0; i < j; ++i) {
+    const double2 a = V[int64_t(i) * ldv + k], c = h[i];
+    ar += sign * (a.x * c.x - a.y * c.y);
+    ai += sign * (a.x * c.y + a.y * c.x);
+  }
+  w[k] = make_double2(ar, ai);
+}
+
+constexpr int kNormBlocks = 128;
+
+__global__ void __launch_bounds__(256) k_norm_partial(const double2* __restrict__ w, int64_t n, double* __restrict__ part) {
+  double s = 0;
+  for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < n; k += int64_t(gridDim.x) * blockDim.x) {
+    const double2 a = w[k];
+    s += a.x * a.x + a.y * a.y;
+  }
+  s = wave_sum(s);
+  __shared__ double sh[4];
+  if (threadIdx.x % kWave == 0) sh[threadIdx.x / kWave] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+__global__ void k_norm_final(const double* __restrict__ part, int nb, double2* __restrict__ out) {
+  if (threadIdx.x != 0) return;
+  double s = 0;
+  for (int b = 0; b < nb; ++b) s += part[b];
+  *out = make_double2(sqrt(s), 0.0);
+}
+
+__global__ void k_scale_inv(const double2* __restrict__ w, int64_t n, const double2* __restrict__ nrm,
+                            double2* __restrict__ v) {
+  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const double s = nrm->x > 0 ? 1.0 / nrm->x : 0.0;
+  v[k] = make_double2(w[k].x * s, w[k].y * s);
+}
+
+// Hcol: entries 0..j (projections) and j+1 (norm of the new vector, real).
+__global__ void k_givens(double2* Hcol, int j, double2* cs, double2* sn, double2* g, double* res,
+                         const double2* h2) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (h2)
+    for (int i = 0; i <= j; ++i) Hcol[i] = make_double2(Hcol[i].x + h2[i].x, Hcol[i].y + h2[i].y);
+  // apply previous rotations: [h_i; h_{i+1}] <- [c, s; -conj(s), c] [h_i; h_{i+1}]  (c real)
+  for (int i = 0; i < j; ++i) {
+    const double c = cs[i].x;
+    const double2 s = sn[i];
+    const double2 a = Hcol[i], b = Hcol[i + 1];
+    const double2 na = make_double2(c * a.x + (s.x * b.x - s.y * b.y), c * a.y + (s.x * b.y + s.y * b.x));
+    const double2 nb = make_double2(-(s.x * a.x + s.y * a.y) + c * b.x, -(s.x * a.y - s.y * a.x) + c * b.y);
+    Hcol[i] = na;
+    Hcol[i + 1] = nb;
+  }
+  const double2 a = Hcol[j], b = Hcol[j + 1];
+  const double na = hypot(a.x, a.y), nb = hypot(b.x, b.y);
+  double c;
+  double2 s;
+  if (nb == 0.0) {
+    c = 1.0;
+    s = make_double2(0, 0);
+  } else if (na == 0.0) {
+    c = 0.0;
+    s = make_double2(b.x / nb, -b.y / nb);  // s = conj(b)/|b|
+  } else {
+    const double t = hypot(na, nb);
+    c = na / t;
+    // s = (a/|a|) conj(b) / t
+    const double2 ua = make_double2(a.x / na, a.y / na);
+    s = make_double2((ua.x * b.x + ua.y * b.y) / t, (ua.y * b.x - ua.x * b.y) / t);
+  }
+  cs[j] = make_double2(c, 0);
+  sn[j] = s;
+  // new Hcol[j] = c a + s b ; Hcol[j+1] = 0
+  Hcol[j] = make_double2(c * a.x + (s.x * b.x - s.y * b.y), c * a.y + (s.x * b.y + s.y * b.x));
+  Hcol[j + 1] = make_double2(0, 0);
+  const double2 gj = g[j];
+  g[j] = make_double2(c * gj.x, c * gj.y);
+  // g[j+1] = -conj(s) g_j
+  g[j + 1] = make_double2(-(s.x * gj.x + s.y * gj.y), -(s.x * gj.y - s.y * gj.x));
+  *res = hypot(g[j + 1].x, g[j + 1].y);
+}
+
+__global__ void k_backsolve(const double2* H, int64_t ldh, int j, const double2* g, double2* y) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  for (int i = j - 1; i >= 0; --i) {
+    double2 s = g[i];
+    for (int k = i + 1; k < j; ++k) {
+      const double2 h = H[int64_t(k) * ldh + i], yk = y[k];
+      s.x -= h.x * yk.x - h.y * yk.y;
+      s.y -= h.x * yk.y + h.y * yk.x;
+    }
+    const double2 d = H[int64_t(i) * ldh + i];
+    const double dd = d.x * d.x + d.y * d.y;
+    y[i] = make_double2((s.x * d.x + s.y * d.y) / dd, (s.y * d.x - s.x * d.y) / dd);
+  }
+}
+
+__global__ void k_init_g(double2* g, int mmax, const double2* beta) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > mmax) return;
+  g[i] = i == 0 ? make_double2(beta->x, 0) : make_double2(0, 0);
+}
+
+}  // namespace dev
+
+// ----------------------------------------------------------------- launchers
+
+void launch_gemv_grouped(const GemvDesc* host_descs, int n, hipStream_t st) {
+  for (int base = 0; base < n; base += kMaxGroup) {
+    GemvPack pack{};
+    pack.n = std::min(kMaxGroup, n - base);
+    int64_t tiles = 0;
+    for (int i = 0; i < pack.n; ++i) {
+      pack.d[i] = host_descs[base + i];
+      pack.d[i].tile0 = tiles;
+      tiles += (pack.d[i].rows + dev::kRowsPerBlock - 1) / dev::kRowsPerBlock;
+    }
+    if (tiles == 0) continue;
+    hipLaunchKernelGGL(dev::k_gemv_grouped, dim3(unsigned(tiles)), dim3(256), 0, st, pack);
+    BEM_HIP(hipGetLastError());
+  }
+}
+
+void launch_expand_charge(const double2* w, double2* full, const int64_t* obj_tri, int64_t nobj, double2 scale,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(dev::k_expand_charge, dim3(unsigned(nobj)), dim3(256), 0, st, w, full, obj_tri, scale);
+  BEM_HIP(hipGetLastError());
+}
+
+void launch_DT(const double2* z, const int32_t* tp, const int32_t* tm, int64_t ne, double2 s, const double2* sedge,
+               double2* y, int accumulate, hipStream_t st) {
+  hipLaunchKernelGGL(dev::k_DT, dim3(unsigned((ne + 255) / 256)), dim3(256), 0, st, z, tp, tm, ne, s, sedge, y,
+                     accumulate);
+  BEM_HIP(hipGetLastError());
+}
+
+void launch_FD(const double2* u, const int32_t* tri_edge, const int8_t* tri_sign, const int32_t* kept, int64_t nq,
+               double2 s1, const double2* w, double2 s2, double2* y, hipStream_t st) {
+  hipLaunchKernelGGL(dev::k_FD, dim3(unsigned((nq + 255) / 256)), dim3(256), 0, st, u, tri_edge, tri_sign, kept, nq,
+                     s1, w, s2, y);
+  BEM_HIP(hipGetLastError());
+}
+
+void launch_spmv(const int64_t* ptr, const int32_t* idx, const double* val, int64_t rows, const double2* x,
+                 double2 s, double2* y, int accumulate, hipStream_t st) {
+  hipLaunchKernelGGL(dev::k_spmv, dim3(unsigned((rows + 255) / 256)), dim3(256), 0, st, ptr, idx, val, rows, x, s, y,
+                     accumulate);
+  BEM_HIP(hipGetLastError());
+}
+
+void launch_axpby(int64_t n, double2 a, const double2* x, double2 b, const double2* y, double2* z, hipStream_t st) {
+  hipLaunchKernelGGL(dev::k_axpby, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, n, a, x, b, y, z);
+  BEM_HIP(hipGetLastError());
+}
+
+void launch_cast_f32(const double2* src, int64_t rows, int64_t cols, int64_t lds, float2* dst, int64_t ldd,
+                     hipStream_t st) {
+  if (rows <= 0) return;
+  hipLaunchKernelGGL(dev::k_cast_f32, dim3(unsigned((ldd + 255) / 256), unsigned(rows)), dim3(256), 0, st, src, rows,
+                     cols, lds, dst, ldd);
+  BEM_HIP(hipGetLastError());
+}
+
+void launch_mdot(const double2* V, int64_t ldv, int j, const double2* w, int64_t n, double2* h,
+                 const KrylovScratch&, hipStream_t st) {
+  if (j <= 0) return;
+  hipLaunchKernelGGL(dev::k_mdot, dim3(unsigned(j)), dim3(256), 0, st, V, ldv, w, n, h);
+  BEM_HIP(hipGetLastError());
+}
+
+void launch_mupdate(const double2* V, int64_t ldv, int j, const double2* h, double sign, double2* w, int64_t n,
+                    hipStream_t st) {
+  if (j <= 0) return;
+  hipLaunchKernelGGL(dev::k_mupdate, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, V, ldv, j, h, sign, w, n);
+  BEM_HIP(hipGetLastError());
+}
+
+void launch_norm(const double2* w, int64_t n, double2* out, const KrylovScratch& ks, hipStream_t st) {
+  double* part = reinterpret_cast<double*>(ks.partial);
+  hipLaunchKernelGGL(dev::k_norm_partial, dim3(dev::kNormBlocks), dim3(256), 0, st, w, n, part);
+  BEM_HIP(hipGetLastError());
+  hipLaunchKernelGGL(dev::k_norm_final, dim3(1), dim3(64), 0, st, part, dev::kNormBlocks, out);
+  BEM_HIP(hipGetLastError());
+}
+
+void launch_scale_inv(const double2* w, int64_t n, const double2* nrm, double2* v, hipStream_t st) {
+  hipLaunchKernelGGL(dev::k_scale_inv, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, w, n, nrm, v);
+  BEM_HIP(hipGetLastError());
+}
+
+void launch_givens(double2* Hcol, int j, double2* cs, double2* sn, double2* g, double* res, const double2* h2,
+                   hipStream_t st) {
+  hipLaunchKernelGGL(dev::k_givens, dim3(1), dim3(64), 0, st, Hcol, j, cs, sn, g, res, h2);
+  BEM_HIP(hipGetLastError());
+}
+
+void launch_backsolve(const double2* H, int64_t ldh, int j, double2* g, double2* y, hipStream_t st) {
+  hipLaunchKernelGGL(dev::k_backsolve, dim3(1), dim3(64), 0, st, H, ldh, j, g, y);
+  BEM_HIP(hipGetLastError());
+}
+
+void launch_init_g(double2* g, int mmax, const double2* beta, hipStream_t st) {
+  hipLaunchKernelGGL(dev::k_init_g, dim3(unsigned((mmax + 1 + 255) / 256)), dim3(256), 0, st, g, mmax, beta);
+  BEM_HIP(hipGetLastError());
+}
+
+}  // namespace bem

@@ -1,0 +1,166 @@
+// Serving loop (see serve.h).
+#include "serve.h"
+
+#include <chrono>
+
+namespace bem {
+
+constexpr int kSlots = 4;
+
+struct Request {
+  // owned copies of the caller's inputs
+  std::vector<double> xyz;
+  std::vector<int32_t> tri, obj;
+  std::vector<bem_material> mats;
+  bem_problem prob{};
+  std::vector<bem_excitation> exc;
+  std::vector<std::vector<int32_t>> gaps;
+  bem_solve_opts opts{};
+  bem_c64 *H = nullptr, *E = nullptr, *rho = nullptr;
+  // state
+  size_t bytes = 0;
+  int status = BEM_PENDING;
+  std::string msg;
+  bem_solve_info info{};
+  std::chrono::steady_clock::time_point t_submit;
+};
+
+size_t Server::estimate_bytes(int64_t nt, int64_t ne, int64_t nobj, int precision, int restart) {
+  const double per = precision == BEM_MIXED ? 24.0 : 16.0;  // float64 + optional float32 copy
+  const double dense = per * (4.0 * double(ne) * ne / std::max<int64_t>(nobj, 1) + double(ne) * ne +
+                              2.0 * double(nt) * nt);
+  const double scratch = 16.0 * 9.0 * double(nt) * nt;  // fill scratch (released after assembly)
+  const double krylov = 16.0 * (double(restart + 1) * (2 * ne + nt) + 201.0 * (ne + nt) + 12.0 * (ne + nt));
+  return size_t(dense + scratch + krylov + 64.0 * 1024 * 1024);
+}
+
+Server::Server(Ctx* ctx) : ctx_(ctx) {
+  for (int s = 0; s < kSlots; ++s) threads_.emplace_back(&Server::worker, this, s);
+}
+
+Server::~Server() {
+  {
+    std::lock_guard<std::mutex> g(mu_);
+    stop_ = true;
+  }
+  cv_.notify_all();
+  for (auto& t : threads_) t.join();
+}
+
+bem_ticket Server::submit(const bem_request& r) {
+  if (!r.xyz || !r.tri || r.nv <= 0 || r.nt <= 0 || !r.exc || r.nexc <= 0)
+    throw Error(BEM_E_INVALID, "incomplete request");
+  if (r.prob.n_obj <= 0 || !r.prob.obj) throw Error(BEM_E_INVALID, "request without materials");
+  auto q = std::make_shared<Request>();
+  q->xyz.assign(r.xyz, r.xyz + 3 * r.nv);
+  q->tri.assign(r.tri, r.tri + 3 * r.nt);
+  if (r.obj) q->obj.assign(r.obj, r.obj + r.nt);
+  q->mats.assign(r.prob.obj, r.prob.obj + r.prob.n_obj);
+  q->prob = r.prob;
+  q->prob.obj = q->mats.data();
+  q->exc.assign(r.exc, r.exc + r.nexc);
+  for (auto& e : q->exc) {
+    if (e.kind == BEM_EXC_DELTA_GAP && e.gap_edges && e.n_gap > 0) {
+      q->gaps.emplace_back(e.gap_edges, e.gap_edges + 2 * e.n_gap);
+      e.gap_edges = q->gaps.back().data();
+    }
+  }
+  q->opts = r.opts;
+  q->H = r.H;
+  q->E = r.E;
+  q->rho = r.rho;
+  const int64_t ne = 3 * r.nt / 2;
+  q->bytes = estimate_bytes(r.nt, ne, r.prob.n_obj, r.prob.precision, r.opts.restart > 0 ? r.opts.restart : 50);
+  if (q->bytes > ctx_->budget) throw Error(BEM_E_NOMEM, "request can never fit the device budget");
+  q->t_submit = std::chrono::steady_clock::now();
+  std::lock_guard<std::mutex> g(mu_);
+  const bem_ticket t = next_++;
+  all_[t] = q;
+  queue_.push_back(q);
+  cv_.notify_all();
+  return t;
+}
+
+int Server::poll(bem_ticket t, bem_solve_info* info, std::string* msg) {
+  std::lock_guard<std::mutex> g(mu_);
+  auto it = all_.find(t);
+  if (it == all_.end()) throw Error(BEM_E_INVALID, "unknown ticket");
+  auto& q = it->second;
+  if (q->status == BEM_PENDING) return BEM_PENDING;
+  if (info) *info = q->info;
+  if (msg) *msg = q->msg;
+  const int st = q->status;
+  all_.erase(it);
+  return st;
+}
+
+void Server::drain() {
+  std::unique_lock<std::mutex> lk(mu_);
+  done_cv_.wait(lk, [&] { return queue_.empty() && active_ == 0; });
+}
+
+void Server::worker(int) {
+  (void)hipSetDevice(ctx_->device);
+  hipStream_t st = nullptr;
+  double* pinned = nullptr;
+  if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return;
+  if (hipHostMalloc(reinterpret_cast<void**>(&pinned), 64 * sizeof(double), hipHostMallocDefault) != hipSuccess) return;
+  while (true) {
+    std::shared_ptr<Request> q;
+    {
+      std::unique_lock<std::mutex> lk(mu_);
+      // admit the oldest request whose estimate fits next to the running ones (first-fit
+      // from the head keeps small requests moving while a large one waits for memory)
+      cv_.wait(lk, [&] {
+        if (stop_) return true;
+        for (auto& r : queue_)
+          if (reserved_ + r->bytes <= ctx_->budget) return true;
+        return false;
+      });
+      if (stop_) break;
+      for (auto it = queue_.begin(); it != queue_.end(); ++it) {
+        if (reserved_ + (*it)->bytes <= ctx_->budget) {
+          q = *it;
+          queue_.erase(it);
+          break;
+        }
+      }
+      reserved_ += q->bytes;
+      ++active_;
+    }
+    int status = BEM_OK;
+    std::string msg;
+    bem_solve_info info{};
+    try {
+      auto mo = std::make_unique<MeshObj>();
+      mo->mesh = build_mesh(q->xyz.data(), int64_t(q->xyz.size() / 3), q->tri.data(), int64_t(q->tri.size() / 3),
+                            q->obj.empty() ? nullptr : q->obj.data());
+      OpObj op(ctx_);
+      op.stream = st;
+      op.pinned = pinned;
+      assemble_op(op, *mo, q->prob);
+      status = solve_op(op, q->exc.data(), int64_t(q->exc.size()), q->opts, q->H, q->E, q->rho, &info, st);
+      info.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - q->t_submit).count();
+    } catch (const Error& e) {
+      status = e.code;
+      msg = e.what();
+    } catch (const std::exception& e) {
+      status = BEM_E_INVALID;
+      msg = e.what();
+    }
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      q->status = status;
+      q->msg = msg;
+      q->info = info;
+      reserved_ -= q->bytes;
+      --active_;
+    }
+    cv_.notify_all();
+    done_cv_.notify_all();
+  }
+  if (pinned) (void)hipHostFree(pinned);
+  if (st) (void)hipStreamDestroy(st);
+}
+
+}  // namespace bem

@@ -1,0 +1,853 @@
+// Operator assembly, block application, the nested equivalent-configuration solve, GMRES and
+// the float32/float64 refinement driver.
+//
+// Final system (eq. finalsystem) with unknowns [a; e; x3] = [jk0 H; E/eta0; -c0 rho'] and a
+// homogeneous background (L^A_m = mu_l L^A_l, L^phi_m = L^phi_l / eps_l):
+//   y1 = L^A_m (a - u) + D^T L^phi_m B (x3 + w) + I_x e
+//   y2 = mu_r L^A a - (K~ + I_x/2) e + eps_c^-1 D^T L^phi B x3
+//   y3 = F D (a - u) + k0^2 (x3 + w)
+// where [u; w] = [Y11 e; Y21 e] solves eq. AEFIEeqvdis, M_eq [u; w] = [(K~_l + I_x/2) e; 0],
+// for every product (Sec. III: Y is never formed).  Two readings of the printed system are
+// used: the middle block is -K (it follows from eq. AEFIEintdis with x3 = -c0 rho'), and
+// C1 carries L^phi_m as eq. AEFIEextdis does.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+
+#include "ctx.h"
+
+namespace bem {
+
+namespace {
+
+inline double2 c2(double re, double im = 0.0) { return make_double2(re, im); }
+inline double2 c2(cd z) { return make_double2(z.real(), z.imag()); }
+inline int64_t pad64(int64_t n) { return (n + 63) / 64 * 64; }
+
+// Radon 7-point degree-5 rule (barycentric points, weights summing to 1) and the 3-point rule.
+struct Rules {
+  double b7[7][3];
+  double w7[7];
+  double b3[3][3];
+  Rules() {
+    const double s = std::sqrt(15.0);
+    const double a1 = (6.0 - s) / 21.0, a2 = (6.0 + s) / 21.0;
+    const double w1 = (155.0 - s) / 1200.0, w2 = (155.0 + s) / 1200.0;
+    const double pts[7][3] = {{1.0 / 3, 1.0 / 3, 1.0 / 3}, {a1, a1, 1 - 2 * a1}, {a1, 1 - 2 * a1, a1},
+                              {1 - 2 * a1, a1, a1},        {a2, a2, 1 - 2 * a2}, {a2, 1 - 2 * a2, a2},
+                              {1 - 2 * a2, a2, a2}};
+    const double ws[7] = {9.0 / 40, w1, w1, w1, w2, w2, w2};
+    std::memcpy(b7, pts, sizeof(b7));
+    std::memcpy(w7, ws, sizeof(w7));
+    const double p3[3][3] = {{2.0 / 3, 1.0 / 6, 1.0 / 6}, {1.0 / 6, 2.0 / 3, 1.0 / 6}, {1.0 / 6, 1.0 / 6, 2.0 / 3}};
+    std::memcpy(b3, p3, sizeof(b3));
+  }
+};
+const Rules& rules() {
+  static Rules r;
+  return r;
+}
+
+Dense alloc_dense(DevArena& mem, int64_t rows, int64_t cols, bool fp32) {
+  Dense d;
+  d.rows = rows;
+  d.cols = cols;
+  d.ld = pad64(std::max<int64_t>(cols, 1));
+  d.d64 = mem.alloc<double2>(size_t(rows) * d.ld);
+  BEM_HIP(hipMemset(d.d64, 0, sizeof(double2) * size_t(rows) * d.ld));
+  if (fp32) d.d32 = mem.alloc<float2>(size_t(rows) * d.ld);
+  return d;
+}
+
+void to_f32(Dense& d, hipStream_t st) {
+  if (d.d32) launch_cast_f32(d.d64, d.rows, d.cols, d.ld, d.d32, d.ld, st);
+}
+
+GemvDesc desc(const Dense& A, bool fp32, int64_t roff, int64_t coff, int64_t rows, int64_t cols, const double2* x,
+              double2* y, double2 alpha, int acc) {
+  GemvDesc d{};
+  d.fp32 = fp32 ? 1 : 0;
+  if (fp32) d.A = A.d32 + roff * A.ld + coff;
+  else d.A = A.d64 + roff * A.ld + coff;
+  d.lda = A.ld;
+  d.rows = rows;
+  d.cols = cols;
+  d.x = x;
+  d.y = y;
+  d.alpha = alpha;
+  d.accumulate = acc;
+  return d;
+}
+
+void add_second(GemvDesc& d, const Dense& A, bool fp32, int64_t roff, int64_t coff, const double2* x, double2 alpha) {
+  if (fp32) d.A2 = A.d32 + roff * A.ld + coff;
+  else d.A2 = A.d64 + roff * A.ld + coff;
+  d.lda2 = A.ld;
+  d.x2 = x;
+  d.alpha2 = alpha;
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------- arena / ctx
+
+void* DevArena::raw(size_t bytes) {
+  {
+    std::lock_guard<std::mutex> g(ctx_->mu);
+    if (ctx_->used + bytes > ctx_->budget)
+      throw Error(BEM_E_NOMEM, "device memory budget exceeded (" + std::to_string(ctx_->used + bytes) + " > " +
+                                   std::to_string(ctx_->budget) + " bytes)");
+    ctx_->used += bytes;
+  }
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    std::lock_guard<std::mutex> g(ctx_->mu);
+    ctx_->used -= bytes;
+    (void)hipGetLastError();
+    throw Error(BEM_E_NOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+  }
+  blocks_.push_back({p, bytes});
+  total_ += bytes;
+  return p;
+}
+
+void DevArena::release(void* p) {
+  for (size_t i = 0; i < blocks_.size(); ++i) {
+    if (blocks_[i].first == p) {
+      (void)hipFree(p);
+      std::lock_guard<std::mutex> g(ctx_->mu);
+      ctx_->used -= blocks_[i].second;
+      total_ -= blocks_[i].second;
+      blocks_.erase(blocks_.begin() + long(i));
+      return;
+    }
+  }
+}
+
+DevArena::~DevArena() {
+  for (auto& b : blocks_) {
+    (void)hipFree(b.first);
+    std::lock_guard<std::mutex> g(ctx_->mu);
+    ctx_->used -= b.second;
+  }
+}
+
+OpObj::~OpObj() {}
+
+// ----------------------------------------------------------------- assembly
+
+void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
+  const Mesh& m = *mo.mesh;
+  if (!mo.cells) mo.cells = std::make_unique<CellData>(build_cells(m));
+  const CellData& cdat = *mo.cells;
+  op.m = &m;
+  op.cells = &cdat;
+  hipStream_t st = op.stream;
+  const Rules& R = rules();
+  fill_set_rules(R.w7, R.b3);
+
+  // ---- problem constants (eq. epsrc; k = sqrt(eps_c mu_r) k0 with Im k <= 0)
+  if (!(prob.freq_hz > 0) || !std::isfinite(prob.freq_hz)) throw Error(BEM_E_INVALID, "frequency must be positive");
+  if (prob.n_obj != m.nobj || (m.nobj > 0 && !prob.obj)) throw Error(BEM_E_INVALID, "one material per object required");
+  if (prob.precision != BEM_FP64 && prob.precision != BEM_MIXED) throw Error(BEM_E_INVALID, "unknown precision");
+  op.precision = prob.precision;
+  op.freq = prob.freq_hz;
+  const double w = 2 * kPi * prob.freq_hz;
+  op.k0 = w / kC0;
+  auto wavenumber = [&](cd eps, double mu) {
+    cd k = std::sqrt(eps * mu) * op.k0;
+    if (k.imag() > 0) k = -k;
+    return k;
+  };
+  op.epsc.clear();
+  op.kint.clear();
+  op.mur.clear();
+  for (int64_t o = 0; o < m.nobj; ++o) {
+    const bem_material& mt = prob.obj[o];
+    cd e = cd(mt.eps_r.re, mt.eps_r.im) - cd(0, mt.sigma / (w * kEps0));
+    if (std::abs(e) == 0 || !std::isfinite(e.real()) || !std::isfinite(e.imag()) || !(mt.mu_r > 0))
+      throw Error(BEM_E_INVALID, "invalid material of object " + std::to_string(o));
+    op.epsc.push_back(e);
+    op.mur.push_back(mt.mu_r);
+    op.kint.push_back(wavenumber(e, mt.mu_r));
+  }
+  op.eps_bg = cd(prob.eps_bg.re, prob.eps_bg.im);
+  op.mu_bg = prob.mu_bg;
+  if (std::abs(op.eps_bg) == 0 || !(op.mu_bg > 0)) throw Error(BEM_E_INVALID, "invalid background medium");
+  op.kbg = wavenumber(op.eps_bg, op.mu_bg);
+
+  op.ne = m.ne;
+  op.nt = m.nt;
+  op.nobj = m.nobj;
+  op.nq = m.nt - m.nobj;
+  op.N = 2 * op.ne + op.nq;
+  op.Neq = op.ne + op.nq;
+  op.obj_tri = m.obj_tri;
+  op.obj_edge = m.obj_edge;
+  op.obj_q.assign(m.nobj + 1, 0);
+  for (int64_t o = 0; o < m.nobj; ++o) op.obj_q[o + 1] = m.obj_tri[o + 1] - (o + 1);
+
+  // ---- geometry table
+  const int64_t nt = m.nt;
+  std::vector<double> geo(size_t(kGeoFields) * nt);
+  for (int64_t t = 0; t < nt; ++t) {
+    double V[3][3], c[3];
+    for (int i = 0; i < 3; ++i)
+      for (int k = 0; k < 3; ++k) V[i][k] = m.xyz[3 * m.tri[3 * t + i] + k];
+    for (int k = 0; k < 3; ++k) c[k] = m.centroid[3 * t + k];
+    for (int k = 0; k < 3; ++k) geo[(kGeoC + k) * nt + t] = c[k];
+    for (int q = 0; q < 7; ++q)
+      for (int k = 0; k < 3; ++k)
+        geo[(kGeoQ + 3 * q + k) * nt + t] =
+            R.b7[q][0] * V[0][k] + R.b7[q][1] * V[1][k] + R.b7[q][2] * V[2][k] - c[k];
+    for (int i = 0; i < 3; ++i)
+      for (int k = 0; k < 3; ++k) geo[(kGeoP + 3 * i + k) * nt + t] = V[i][k] - c[k];
+    geo[kGeoA * nt + t] = m.area[t];
+    for (int k = 0; k < 3; ++k) geo[(kGeoN + k) * nt + t] = m.normal[3 * t + k];
+    geo[kGeoH * nt + t] = m.hmax[t];
+  }
+  op.geo = op.mem.upload(geo);
+  op.tp = op.mem.upload(m.tp);
+  op.tm = op.mem.upload(m.tm);
+  op.ip = op.mem.upload(m.ip);
+  op.im = op.mem.upload(m.im);
+  op.tri_edge = op.mem.upload(m.tri_edge);
+  op.tri_sign = op.mem.upload(m.tri_sign);
+  op.obj_tri_d = op.mem.upload(m.obj_tri);
+  std::vector<int32_t> kept;
+  for (int64_t o = 0; o < m.nobj; ++o)
+    for (int64_t t = m.obj_tri[o]; t < m.obj_tri[o + 1] - 1; ++t) kept.push_back(int32_t(t));
+  op.kept = op.mem.upload(kept);
+  std::vector<double2> einv(m.ne);
+  for (int64_t n = 0; n < m.ne; ++n) einv[n] = c2(1.0 / op.epsc[m.obj[m.tp[n]]]);
+  op.eps_inv_edge = op.mem.upload(einv);
+
+  // ---- Gram matrix I_x: int (n x f_m) . g_n dS, exact with the 3-point rule on every sub-triangle
+  {
+    std::vector<std::map<int32_t, double>> rows(m.ne);
+    const int64_t nc = cdat.ncell;
+    const int ns = 2 * cdat.maxv;
+    for (int64_t v = 0; v < nc; ++v) {
+      const int N = cdat.nval[v];
+      const double* pv = &cdat.vpos[3 * v];
+      for (int b = 0; b < N; ++b) {
+        const int32_t n = m.vedge[m.vptr[v] + b];
+        const double al = cdat.alpha[size_t(b) * nc + v];
+        for (int s = 0; s < 2 * N; ++s) {
+          const size_t so = size_t(s) * nc + v;
+          const int32_t P = cdat.sub_parent[so];
+          const double* sm = &cdat.sub_m[3 * so];
+          const double* sc = &cdat.sub_c[3 * so];
+          const double As = cdat.sub_area[so];
+          const double* be = &cdat.beta[((size_t(b) * ns + s) * nc + v) * 3];
+          const double* nP = &m.normal[3 * P];
+          for (int j = 0; j < 3; ++j) {
+            double rl[3], r[3], g[3];
+            for (int k = 0; k < 3; ++k) {
+              rl[k] = R.b3[j][1] * sm[k] + R.b3[j][2] * sc[k];  // relative to v
+              r[k] = pv[k] + rl[k];
+              g[k] = (al * rl[k] - be[k]) / (2 * As);
+            }
+            for (int i = 0; i < 3; ++i) {
+              const int32_t me = m.tri_edge[3 * P + i];
+              const double sg = m.tri_sign[3 * P + i];
+              const double* pi = &m.xyz[3 * m.tri[3 * P + i]];
+              double f[3], nf[3];
+              for (int k = 0; k < 3; ++k) f[k] = sg * (r[k] - pi[k]) / (2 * m.area[P]);
+              nf[0] = nP[1] * f[2] - nP[2] * f[1];
+              nf[1] = nP[2] * f[0] - nP[0] * f[2];
+              nf[2] = nP[0] * f[1] - nP[1] * f[0];
+              rows[me][n] += As * (1.0 / 3.0) * (nf[0] * g[0] + nf[1] * g[1] + nf[2] * g[2]);
+            }
+          }
+        }
+      }
+    }
+    std::vector<int64_t> ptr(m.ne + 1, 0);
+    std::vector<int32_t> idx;
+    std::vector<double> val;
+    for (int64_t r = 0; r < m.ne; ++r) {
+      for (auto& kv : rows[r]) {
+        idx.push_back(kv.first);
+        val.push_back(kv.second);
+      }
+      ptr[r + 1] = int64_t(idx.size());
+    }
+    op.ix_ptr = op.mem.upload(ptr);
+    op.ix_idx = op.mem.upload(idx);
+    op.ix_val = op.mem.upload(val);
+  }
+
+  // ---- near-pair lists (all pairs, and per object) for L, near cells per object for K~
+  std::vector<int32_t> na_t, na_s;
+  std::vector<std::vector<int32_t>> no_t(m.nobj), no_s(m.nobj);
+  for (int64_t t = 0; t < nt; ++t)
+    for (int64_t p = m.near_ptr[t]; p < m.near_ptr[t + 1]; ++p) {
+      const int32_t s = m.near_idx[p];
+      na_t.push_back(int32_t(t));
+      na_s.push_back(s);
+      if (m.obj[s] == m.obj[t]) {
+        no_t[m.obj[t]].push_back(int32_t(t));
+        no_s[m.obj[t]].push_back(s);
+      }
+    }
+  std::vector<int64_t> ncp;
+  std::vector<int32_t> nci;
+  near_cells(m, ncp, nci);
+  std::vector<int32_t> vobj(m.nv, -1);
+  for (int64_t t = 0; t < nt; ++t)
+    for (int i = 0; i < 3; ++i) vobj[m.tri[3 * t + i]] = m.obj[t];
+  std::vector<std::vector<int32_t>> nc_t(m.nobj), nc_c(m.nobj);
+  for (int64_t t = 0; t < nt; ++t)
+    for (int64_t p = ncp[t]; p < ncp[t + 1]; ++p)
+      if (vobj[nci[p]] == m.obj[t]) {
+        nc_t[m.obj[t]].push_back(int32_t(t));
+        nc_c[m.obj[t]].push_back(nci[p]);
+      }
+
+  // ---- cell tables
+  int32_t* d_cells = op.mem.upload(cdat.obj_cells);
+  int32_t* d_nval = op.mem.upload(cdat.nval);
+  double* d_vpos = op.mem.upload(cdat.vpos);
+  int64_t* d_col0 = op.mem.upload(cdat.col0);
+  double* d_sub_m = op.mem.upload(cdat.sub_m);
+  double* d_sub_c = op.mem.upload(cdat.sub_c);
+  double* d_sub_area = op.mem.upload(cdat.sub_area);
+  int32_t* d_sub_parent = op.mem.upload(cdat.sub_parent);
+  double* d_alpha = op.mem.upload(cdat.alpha);
+  double* d_beta = op.mem.upload(cdat.beta);
+  std::vector<int32_t> hp(m.ne), hm(m.ne), cS(m.ne), cT(m.ne);
+  for (int64_t n = 0; n < m.ne; ++n) {
+    hp[n] = int32_t(3 * m.tp[n] + m.ip[n]);
+    hm[n] = int32_t(3 * m.tm[n] + m.im[n]);
+    cS[n] = int32_t(cdat.colS[n]);
+    cT[n] = int32_t(cdat.colT[n]);
+  }
+  int32_t* d_hp = op.mem.upload(hp);
+  int32_t* d_hm = op.mem.upload(hm);
+  int32_t* d_cS = op.mem.upload(cS);
+  int32_t* d_cT = op.mem.upload(cT);
+  int64_t* d_near_ptr = op.mem.upload(m.near_ptr);
+  int32_t* d_near_idx = op.mem.upload(m.near_idx);
+
+  // ---- dense blocks
+  const bool f32 = op.precision == BEM_MIXED;
+  op.LA_int.clear();
+  op.Lphi_int.clear();
+  op.K_int.clear();
+  op.K_bg.clear();
+  for (int64_t o = 0; o < m.nobj; ++o) {
+    const int64_t neo = m.obj_edge[o + 1] - m.obj_edge[o];
+    const int64_t nto = m.obj_tri[o + 1] - m.obj_tri[o];
+    op.LA_int.push_back(alloc_dense(op.mem, neo, neo, f32));
+    op.Lphi_int.push_back(alloc_dense(op.mem, nto, nto, f32));
+    op.K_int.push_back(alloc_dense(op.mem, neo, neo, f32));
+    op.K_bg.push_back(alloc_dense(op.mem, neo, neo, f32));
+  }
+  op.LA_bg = alloc_dense(op.mem, m.ne, m.ne, f32);
+  op.Lphi_bg = alloc_dense(op.mem, nt, nt, f32);
+
+  // scratch for the half-RWG and cell-expanded matrices
+  int64_t scratch_elems = 9 * nt * nt;
+  for (int64_t o = 0; o < m.nobj; ++o) {
+    const int64_t nto = m.obj_tri[o + 1] - m.obj_tri[o];
+    scratch_elems = std::max(scratch_elems, 3 * nto * cdat.obj_ncol[o]);
+  }
+  double2* H = op.mem.alloc<double2>(size_t(scratch_elems));
+
+  hipEvent_t ev0, ev1;
+  BEM_HIP(hipEventCreate(&ev0));
+  BEM_HIP(hipEventCreate(&ev1));
+  BEM_HIP(hipEventRecord(ev0, st));
+  std::vector<void*> tmp_dev;
+  auto up32 = [&](const std::vector<int32_t>& v) {
+    int32_t* p = op.mem.upload(v);
+    tmp_dev.push_back(p);
+    return p;
+  };
+  const int64_t tchunk = 8;
+  for (int64_t o = 0; o < m.nobj; ++o) {
+    const int64_t t0 = m.obj_tri[o], nto = m.obj_tri[o + 1] - t0;
+    const int64_t e0 = m.obj_edge[o], neo = m.obj_edge[o + 1] - e0;
+    int32_t* pt = up32(no_t[o]);
+    int32_t* ps = up32(no_s[o]);
+    // interior L^A, L^phi at k_int
+    FillLArgs la{op.geo, nt, t0, nto, t0, nto, tchunk, op.kint[o].real(), op.kint[o].imag(), H, 3 * nto,
+                 op.Lphi_int[o].d64, op.Lphi_int[o].ld};
+    launch_fill_L(la, pt, ps, int64_t(no_t[o].size()), st);
+    launch_gather_LA(H, 3 * nto, d_hp + e0, d_hm + e0, 3 * t0, neo, op.LA_int[o].d64, op.LA_int[o].ld, st);
+    // K~ at k_int and at k_bg (object-local blocks)
+    int32_t* pct = up32(nc_t[o]);
+    int32_t* pcc = up32(nc_c[o]);
+    for (int which = 0; which < 2; ++which) {
+      const cd k = which == 0 ? op.kint[o] : op.kbg;
+      Dense& dst = which == 0 ? op.K_int[o] : op.K_bg[o];
+      FillKArgs ka{op.geo, nt, t0, nto, tchunk, k.real(), k.imag(), d_cells + cdat.obj_cell_ptr[o],
+                   cdat.obj_cell_ptr[o + 1] - cdat.obj_cell_ptr[o], cdat.ncell, d_nval, d_vpos, d_col0, d_sub_m, d_sub_c,
+                   d_sub_area, d_sub_parent, d_alpha, d_beta, H, cdat.obj_ncol[o]};
+      launch_fill_K(ka, pct, pcc, int64_t(nc_t[o].size()), d_near_ptr, d_near_idx, cdat.maxv, st);
+      launch_gather_K(H, cdat.obj_ncol[o], d_hp + e0, d_hm + e0, d_cS + e0, d_cT + e0, 3 * t0, neo, dst.d64, dst.ld,
+                      st);
+    }
+  }
+  {
+    int32_t* pt = up32(na_t);
+    int32_t* ps = up32(na_s);
+    FillLArgs la{op.geo, nt, 0, nt, 0, nt, tchunk, op.kbg.real(), op.kbg.imag(), H, 3 * nt, op.Lphi_bg.d64,
+                 op.Lphi_bg.ld};
+    launch_fill_L(la, pt, ps, int64_t(na_t.size()), st);
+    launch_gather_LA(H, 3 * nt, d_hp, d_hm, 0, m.ne, op.LA_bg.d64, op.LA_bg.ld, st);
+  }
+  if (f32) {
+    for (int64_t o = 0; o < m.nobj; ++o) {
+      to_f32(op.LA_int[o], st);
+      to_f32(op.Lphi_int[o], st);
+      to_f32(op.K_int[o], st);
+      to_f32(op.K_bg[o], st);
+    }
+    to_f32(op.LA_bg, st);
+    to_f32(op.Lphi_bg, st);
+  }
+  BEM_HIP(hipEventRecord(ev1, st));
+  BEM_HIP(hipStreamSynchronize(st));
+  float ms = 0;
+  BEM_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+  op.fill_seconds = ms * 1e-3;
+  (void)hipEventDestroy(ev0);
+  (void)hipEventDestroy(ev1);
+  op.mem.release(H);
+  for (void* p : tmp_dev) op.mem.release(p);
+  for (void* p : {(void*)d_cells, (void*)d_nval, (void*)d_vpos, (void*)d_col0, (void*)d_sub_m, (void*)d_sub_c,
+                  (void*)d_sub_area, (void*)d_sub_parent, (void*)d_alpha, (void*)d_beta, (void*)d_hp, (void*)d_hm,
+                  (void*)d_cS, (void*)d_cT, (void*)d_near_ptr, (void*)d_near_idx})
+    op.mem.release(p);
+
+  // ---- work vectors and Krylov spaces
+  op.work_len = 4 * op.Neq + 6 * op.nt + 2 * op.ne + 2 * op.nq + 64;
+  op.work = op.mem.alloc<double2>(size_t(op.work_len));
+  op.inner_ws = make_gmres_work(op.mem, op.Neq, op.inner_restart);
+}
+
+// ----------------------------------------------------------------- products
+
+namespace {
+// work vector layout
+struct WorkView {
+  double2 *rin, *sol, *t1, *z1, *z2, *am, *xw, *mt, *mz;
+};
+WorkView views(OpObj& op) {
+  double2* p = op.work;
+  WorkView v;
+  v.rin = p; p += op.Neq;
+  v.sol = p; p += op.Neq;
+  v.t1 = p; p += op.nt;
+  v.z1 = p; p += op.nt;
+  v.z2 = p; p += op.nt;
+  v.am = p; p += op.ne;
+  v.xw = p; p += op.nq;
+  v.mt = p; p += op.nt;
+  v.mz = p; p += op.nt;
+  return v;
+}
+}  // namespace
+
+// Equivalent-configuration matrix (eq. AEFIEeqvdis), block-diagonal over objects:
+//   y_u = mu_l L^A_l u - eps_l^-1 D^T L^phi_l B w ;  y_w = F D u - k0^2 w
+void apply_meq(OpObj& op, const double2* x, double2* y, bool fp32, hipStream_t st) {
+  WorkView wv = views(op);
+  const double2* u = x;
+  const double2* w = x + op.ne;
+  double2* yu = y;
+  double2* yw = y + op.ne;
+  launch_expand_charge(w, wv.mt, op.obj_tri_d, op.nobj, c2(1.0), st);
+  std::vector<GemvDesc> ds;
+  for (int64_t o = 0; o < op.nobj; ++o) {
+    const int64_t t0 = op.obj_tri[o], nto = op.obj_tri[o + 1] - t0;
+    const int64_t e0 = op.obj_edge[o], neo = op.obj_edge[o + 1] - e0;
+    ds.push_back(desc(op.Lphi_bg, fp32, t0, t0, nto, nto, wv.mt + t0, wv.mz + t0, c2(1.0), 0));
+    ds.push_back(desc(op.LA_bg, fp32, e0, e0, neo, neo, u + e0, yu + e0, c2(op.mu_bg), 0));
+  }
+  launch_gemv_grouped(ds.data(), int(ds.size()), st);
+  launch_DT(wv.mz, op.tp, op.tm, op.ne, c2(-1.0 / op.eps_bg), nullptr, yu, 1, st);
+  launch_FD(u, op.tri_edge, op.tri_sign, op.kept, op.nq, c2(1.0), w, c2(-op.k0 * op.k0), yw, st);
+}
+
+void apply_final(OpObj& op, const double2* x, double2* y, bool fp32, double inner_tol, hipStream_t st) {
+  WorkView wv = views(op);
+  const int64_t ne = op.ne, nq = op.nq;
+  const double2* a = x;
+  const double2* e = x + ne;
+  const double2* x3 = x + 2 * ne;
+  double2* y1 = y;
+  double2* y2 = y + ne;
+  double2* y3 = y + 2 * ne;
+  // B x3 for the interior charge term
+  launch_expand_charge(x3, wv.t1, op.obj_tri_d, op.nobj, c2(1.0), st);
+  std::vector<GemvDesc> ds;
+  for (int64_t o = 0; o < op.nobj; ++o) {
+    const int64_t t0 = op.obj_tri[o], nto = op.obj_tri[o + 1] - t0;
+    const int64_t e0 = op.obj_edge[o], neo = op.obj_edge[o + 1] - e0;
+    // r_in = K~_l e ;  y2 = mu_r L^A a - K~ e ;  z1 = L^phi B x3
+    ds.push_back(desc(op.K_bg[o], fp32, 0, 0, neo, neo, e + e0, wv.rin + e0, c2(1.0), 0));
+    GemvDesc d2 = desc(op.LA_int[o], fp32, 0, 0, neo, neo, a + e0, y2 + e0, c2(op.mur[o]), 0);
+    add_second(d2, op.K_int[o], fp32, 0, 0, e + e0, c2(-1.0));
+    ds.push_back(d2);
+    ds.push_back(desc(op.Lphi_int[o], fp32, 0, 0, nto, nto, wv.t1 + t0, wv.z1 + t0, c2(1.0), 0));
+  }
+  launch_gemv_grouped(ds.data(), int(ds.size()), st);
+  // r_in += I_x e / 2 ; y2 += -I_x e / 2 + eps_c^-1 D^T z1
+  launch_spmv(op.ix_ptr, op.ix_idx, op.ix_val, ne, e, c2(0.5), wv.rin, 1, st);
+  launch_spmv(op.ix_ptr, op.ix_idx, op.ix_val, ne, e, c2(-0.5), y2, 1, st);
+  launch_DT(wv.z1, op.tp, op.tm, ne, c2(1.0), op.eps_inv_edge, y2, 1, st);
+  // nested solve M_eq [u; w] = [r_in; 0]
+  launch_axpby(nq, c2(0.0), nullptr, c2(0.0), nullptr, wv.rin + ne, st);
+  ApplyFn meq = [&op, fp32, st](const double2* xi, double2* yi) { apply_meq(op, xi, yi, fp32, st); };
+  GmresResult gr = gmres(*op.inner_ws, op.pinned, meq, wv.rin, wv.sol, true, inner_tol, op.inner_maxit, st);
+  op.last_inner_iters = gr.iters;
+  op.max_inner_iters = std::max(op.max_inner_iters, gr.iters);
+  const double2* u = wv.sol;
+  const double2* w = wv.sol + ne;
+  // a - u, x3 + w, B (x3 + w)
+  launch_axpby(ne, c2(1.0), a, c2(-1.0), u, wv.am, st);
+  launch_axpby(nq, c2(1.0), x3, c2(1.0), w, wv.xw, st);
+  launch_expand_charge(wv.xw, wv.t1, op.obj_tri_d, op.nobj, c2(1.0), st);
+  GemvDesc g2[2] = {desc(op.LA_bg, fp32, 0, 0, ne, ne, wv.am, y1, c2(op.mu_bg), 0),
+                    desc(op.Lphi_bg, fp32, 0, 0, op.nt, op.nt, wv.t1, wv.z2, c2(1.0), 0)};
+  launch_gemv_grouped(g2, 2, st);
+  // y1 += eps_l^-1 D^T z2 + I_x e ;  y3 = F D (a - u) + k0^2 (x3 + w)
+  launch_DT(wv.z2, op.tp, op.tm, ne, c2(1.0 / op.eps_bg), nullptr, y1, 1, st);
+  launch_spmv(op.ix_ptr, op.ix_idx, op.ix_val, ne, e, c2(1.0), y1, 1, st);
+  launch_FD(wv.am, op.tri_edge, op.tri_sign, op.kept, nq, c2(1.0), wv.xw, c2(op.k0 * op.k0), y3, st);
+}
+
+void apply_block(OpObj& op, int block, const double2* x, double2* y, hipStream_t st) {
+  std::vector<GemvDesc> ds;
+  switch (block) {
+    case BEM_BLOCK_LA_INT:
+    case BEM_BLOCK_K_INT:
+    case BEM_BLOCK_K_BG:
+      for (int64_t o = 0; o < op.nobj; ++o) {
+        const int64_t e0 = op.obj_edge[o], neo = op.obj_edge[o + 1] - e0;
+        const Dense& A = block == BEM_BLOCK_LA_INT ? op.LA_int[o] : block == BEM_BLOCK_K_INT ? op.K_int[o] : op.K_bg[o];
+        ds.push_back(desc(A, false, 0, 0, neo, neo, x + e0, y + e0, c2(1.0), 0));
+      }
+      break;
+    case BEM_BLOCK_LPHI_INT:
+      for (int64_t o = 0; o < op.nobj; ++o) {
+        const int64_t t0 = op.obj_tri[o], nto = op.obj_tri[o + 1] - t0;
+        ds.push_back(desc(op.Lphi_int[o], false, 0, 0, nto, nto, x + t0, y + t0, c2(1.0), 0));
+      }
+      break;
+    case BEM_BLOCK_LA_BG:
+      ds.push_back(desc(op.LA_bg, false, 0, 0, op.ne, op.ne, x, y, c2(1.0), 0));
+      break;
+    case BEM_BLOCK_LPHI_BG:
+      ds.push_back(desc(op.Lphi_bg, false, 0, 0, op.nt, op.nt, x, y, c2(1.0), 0));
+      break;
+    case BEM_BLOCK_IX:
+      launch_spmv(op.ix_ptr, op.ix_idx, op.ix_val, op.ne, x, c2(1.0), y, 0, st);
+      return;
+    case BEM_BLOCK_MEQ:
+      apply_meq(op, x, y, false, st);
+      return;
+    case BEM_BLOCK_FINAL:
+      apply_final(op, x, y, false, op.inner_tol, st);
+      return;
+    default:
+      throw Error(BEM_E_INVALID, "unknown block");
+  }
+  launch_gemv_grouped(ds.data(), int(ds.size()), st);
+}
+
+void export_block(OpObj& op, int block, bem_c64* host) {
+  auto copy_dense = [&](const Dense& A, int64_t roff, int64_t coff, int64_t ldh) {
+    for (int64_t r = 0; r < A.rows; ++r)
+      BEM_HIP(hipMemcpy(host + (roff + r) * ldh + coff, A.d64 + r * A.ld, sizeof(double2) * A.cols,
+                        hipMemcpyDeviceToHost));
+  };
+  BEM_HIP(hipStreamSynchronize(op.stream));
+  switch (block) {
+    case BEM_BLOCK_LA_INT:
+    case BEM_BLOCK_K_INT:
+    case BEM_BLOCK_K_BG:
+      std::memset(host, 0, sizeof(bem_c64) * op.ne * op.ne);
+      for (int64_t o = 0; o < op.nobj; ++o) {
+        const Dense& A = block == BEM_BLOCK_LA_INT ? op.LA_int[o] : block == BEM_BLOCK_K_INT ? op.K_int[o] : op.K_bg[o];
+        copy_dense(A, op.obj_edge[o], op.obj_edge[o], op.ne);
+      }
+      return;
+    case BEM_BLOCK_LPHI_INT:
+      std::memset(host, 0, sizeof(bem_c64) * op.nt * op.nt);
+      for (int64_t o = 0; o < op.nobj; ++o) copy_dense(op.Lphi_int[o], op.obj_tri[o], op.obj_tri[o], op.nt);
+      return;
+    case BEM_BLOCK_LA_BG:
+      copy_dense(op.LA_bg, 0, 0, op.ne);
+      return;
+    case BEM_BLOCK_LPHI_BG:
+      copy_dense(op.Lphi_bg, 0, 0, op.nt);
+      return;
+    case BEM_BLOCK_IX: {
+      std::vector<int64_t> ptr(op.ne + 1);
+      BEM_HIP(hipMemcpy(ptr.data(), op.ix_ptr, sizeof(int64_t) * (op.ne + 1), hipMemcpyDeviceToHost));
+      std::vector<int32_t> idx(ptr[op.ne]);
+      std::vector<double> val(ptr[op.ne]);
+      BEM_HIP(hipMemcpy(idx.data(), op.ix_idx, sizeof(int32_t) * idx.size(), hipMemcpyDeviceToHost));
+      BEM_HIP(hipMemcpy(val.data(), op.ix_val, sizeof(double) * val.size(), hipMemcpyDeviceToHost));
+      std::memset(host, 0, sizeof(bem_c64) * op.ne * op.ne);
+      for (int64_t r = 0; r < op.ne; ++r)
+        for (int64_t p = ptr[r]; p < ptr[r + 1]; ++p) host[r * op.ne + idx[p]] = {val[p], 0.0};
+      return;
+    }
+    default:
+      throw Error(BEM_E_INVALID, "block cannot be exported");
+  }
+}
+
+// ----------------------------------------------------------------- GMRES
+
+std::unique_ptr<GmresWork> make_gmres_work(DevArena& mem, int64_t n, int m) {
+  auto w = std::make_unique<GmresWork>();
+  w->n = n;
+  w->m = m;
+  w->ldv = pad64(n);
+  w->V = mem.alloc<double2>(size_t(m + 1) * w->ldv);
+  w->H = mem.alloc<double2>(size_t(m + 1) * (m + 2));
+  w->cs = mem.alloc<double2>(m + 1);
+  w->sn = mem.alloc<double2>(m + 1);
+  w->g = mem.alloc<double2>(m + 2);
+  w->y = mem.alloc<double2>(m + 1);
+  w->h2 = mem.alloc<double2>(m + 2);
+  w->nrm = mem.alloc<double2>(2);
+  w->res = mem.alloc<double>(2);
+  w->ks.partial = mem.alloc<double2>(1024);
+  w->ks.nblk = 128;
+  return w;
+}
+
+static double read_scalar(double* pinned, const double* d, hipStream_t st) {
+  BEM_HIP(hipMemcpyAsync(pinned, d, sizeof(double), hipMemcpyDeviceToHost, st));
+  BEM_HIP(hipStreamSynchronize(st));
+  return pinned[0];
+}
+
+GmresResult gmres(GmresWork& w, double* ctx, const ApplyFn& A, const double2* b, double2* x, bool x_zero,
+                  double tol, int maxit, hipStream_t st) {
+  GmresResult res;
+  const int64_t n = w.n;
+  const int64_t ldh = w.m + 2;
+  launch_norm(b, n, w.nrm, w.ks, st);
+  const double bnorm = read_scalar(ctx, reinterpret_cast<const double*>(w.nrm), st);
+  if (!std::isfinite(bnorm)) throw Error(BEM_E_NUMERIC, "non-finite right-hand side");
+  if (x_zero) launch_axpby(n, c2(0.0), nullptr, c2(0.0), nullptr, x, st);
+  if (bnorm == 0.0) {
+    launch_axpby(n, c2(0.0), nullptr, c2(0.0), nullptr, x, st);
+    res.converged = true;
+    return res;
+  }
+  bool first = true;
+  while (true) {
+    // r = b - A x  (stored in V[0])
+    if (first && x_zero) {
+      launch_axpby(n, c2(1.0), b, c2(0.0), nullptr, w.V, st);
+    } else {
+      A(x, w.V);
+      launch_axpby(n, c2(1.0), b, c2(-1.0), w.V, w.V, st);
+    }
+    first = false;
+    launch_norm(w.V, n, w.nrm, w.ks, st);
+    const double beta = read_scalar(ctx, reinterpret_cast<const double*>(w.nrm), st);
+    if (!std::isfinite(beta)) throw Error(BEM_E_NUMERIC, "non-finite residual in GMRES");
+    res.relres = beta / bnorm;
+    if (res.relres <= tol) {
+      res.converged = true;
+      break;
+    }
+    if (res.iters >= maxit) break;
+    launch_scale_inv(w.V, n, w.nrm, w.V, st);
+    launch_init_g(w.g, w.m, w.nrm, st);
+    int j = 0;
+    for (; j < w.m && res.iters < maxit; ++j) {
+      double2* vj = w.V + int64_t(j) * w.ldv;
+      double2* vn = w.V + int64_t(j + 1) * w.ldv;
+      double2* Hcol = w.H + int64_t(j) * ldh;
+      A(vj, vn);
+      // CGS2
+      launch_mdot(w.V, w.ldv, j + 1, vn, n, Hcol, w.ks, st);
+      launch_mupdate(w.V, w.ldv, j + 1, Hcol, -1.0, vn, n, st);
+      launch_mdot(w.V, w.ldv, j + 1, vn, n, w.h2, w.ks, st);
+      launch_mupdate(w.V, w.ldv, j + 1, w.h2, -1.0, vn, n, st);
+      launch_norm(vn, n, Hcol + j + 1, w.ks, st);
+      launch_scale_inv(vn, n, Hcol + j + 1, vn, st);
+      launch_givens(Hcol, j, w.cs, w.sn, w.g, w.res, w.h2, st);
+      ++res.iters;
+      const double r = read_scalar(ctx, w.res, st);
+      if (!std::isfinite(r)) throw Error(BEM_E_NUMERIC, "non-finite Arnoldi residual");
+      res.relres = r / bnorm;
+      if (res.relres <= tol) {
+        ++j;
+        break;
+      }
+    }
+    launch_backsolve(w.H, ldh, j, w.g, w.y, st);
+    launch_mupdate(w.V, w.ldv, j, w.y, +1.0, x, n, st);
+    if (res.relres <= tol) {
+      res.converged = true;
+      break;
+    }
+    if (res.iters >= maxit) break;
+  }
+  return res;
+}
+
+// ----------------------------------------------------------------- solve
+
+int solve_op(OpObj& op, const bem_excitation* exc, int64_t nexc, const bem_solve_opts& opts, bem_c64* Hout,
+             bem_c64* Eout, bem_c64* rhoout, bem_solve_info* info, hipStream_t st) {
+  auto tstart = std::chrono::steady_clock::now();
+  if (nexc <= 0 || !exc) throw Error(BEM_E_INVALID, "no excitation");
+  if (!(opts.tol > 0) || opts.restart <= 0 || opts.maxit <= 0) throw Error(BEM_E_INVALID, "invalid solve options");
+  const int64_t ne = op.ne, nq = op.nq, N = op.N;
+  DevArena tmp(op.ctx);
+  // right-hand sides
+  double2* B = tmp.alloc<double2>(size_t(ne) * nexc);
+  std::vector<double> khat;
+  std::vector<double2> pol, amp;
+  std::vector<int64_t> pw;  // plane-wave excitations
+  BEM_HIP(hipMemsetAsync(B, 0, sizeof(double2) * ne * nexc, st));
+  for (int64_t e = 0; e < nexc; ++e) {
+    const bem_excitation& x = exc[e];
+    if (x.kind == BEM_EXC_PLANE_WAVE) {
+      for (int k = 0; k < 3; ++k) {
+        if (!std::isfinite(x.khat[k]) || !std::isfinite(x.pol[k].re) || !std::isfinite(x.pol[k].im))
+          throw Error(BEM_E_NUMERIC, "non-finite excitation");
+        khat.push_back(x.khat[k]);
+        pol.push_back(c2(x.pol[k].re, x.pol[k].im));
+      }
+      if (!std::isfinite(x.amp.re) || !std::isfinite(x.amp.im)) throw Error(BEM_E_NUMERIC, "non-finite amplitude");
+      amp.push_back(c2(x.amp.re, x.amp.im));
+      pw.push_back(e);
+    } else if (x.kind == BEM_EXC_DELTA_GAP) {
+      // gap field across each listed edge, along the RWG of the directed pair (a -> b):
+      // b_m = +V/eta0 when (a, b) = (va, vb) of edge m, -V/eta0 when reversed
+      if (!x.gap_edges || x.n_gap <= 0) throw Error(BEM_E_INVALID, "delta gap without edges");
+      std::vector<double2> col(ne, c2(0.0));
+      std::map<std::pair<int32_t, int32_t>, int64_t> eid;
+      for (int64_t n = 0; n < ne; ++n) eid[{op.m->ev[2 * n], op.m->ev[2 * n + 1]}] = n;
+      for (int64_t g = 0; g < x.n_gap; ++g) {
+        int32_t a = x.gap_edges[2 * g], b = x.gap_edges[2 * g + 1];
+        double s = 1.0;
+        if (a > b) { std::swap(a, b); s = -1.0; }
+        auto it = eid.find({a, b});
+        if (it == eid.end()) throw Error(BEM_E_INVALID, "gap edge is not a mesh edge");
+        col[it->second] = c2(s * x.amp.re / kEta0, s * x.amp.im / kEta0);
+      }
+      BEM_HIP(hipMemcpyAsync(B + e * ne, col.data(), sizeof(double2) * ne, hipMemcpyHostToDevice, st));
+      BEM_HIP(hipStreamSynchronize(st));
+    } else {
+      throw Error(BEM_E_INVALID, "unknown excitation kind");
+    }
+  }
+  if (!pw.empty()) {
+    double* dk = tmp.upload(khat);
+    double2* dp = tmp.upload(pol);
+    double2* da = tmp.upload(amp);
+    double2* Bpw = tmp.alloc<double2>(size_t(ne) * pw.size());
+    RhsArgs ra{op.geo, op.nt, op.tp, op.tm, op.ip, op.im, ne, dk, dp, da, op.kbg.real(), op.kbg.imag(),
+               1.0 / kEta0, Bpw, ne};
+    launch_rhs_planewave(ra, int(pw.size()), st);
+    for (size_t i = 0; i < pw.size(); ++i)
+      BEM_HIP(hipMemcpyAsync(B + pw[i] * ne, Bpw + i * ne, sizeof(double2) * ne, hipMemcpyDeviceToDevice, st));
+  }
+  if (!op.outer_ws || op.outer_ws->m != opts.restart) op.outer_ws = make_gmres_work(op.mem, N, opts.restart);
+  double2* bfull = tmp.alloc<double2>(N);
+  double2* xs = tmp.alloc<double2>(N);
+  double2* d = tmp.alloc<double2>(N);
+  double2* r = tmp.alloc<double2>(N);
+  double2* o1 = tmp.alloc<double2>(ne);
+  double2* o3 = tmp.alloc<double2>(op.nt);
+  const double inner = opts.inner_tol > 0 ? opts.inner_tol : 0.1 * opts.tol;
+  bem_solve_info inf{};
+  int status = BEM_OK;
+  op.max_inner_iters = 0;
+  for (int64_t e = 0; e < nexc; ++e) {
+    launch_axpby(N, c2(0.0), nullptr, c2(0.0), nullptr, bfull, st);
+    BEM_HIP(hipMemcpyAsync(bfull, B + e * ne, sizeof(double2) * ne, hipMemcpyDeviceToDevice, st));
+    ApplyFn A64 = [&op, inner, st](const double2* x, double2* y) { apply_final(op, x, y, false, inner, st); };
+    double rel = 0;
+    bool conv = false;
+    int left = opts.maxit;
+    if (op.precision == BEM_FP64) {
+      GmresResult g = gmres(*op.outer_ws, op.pinned,A64, bfull, xs, true, opts.tol, left, st);
+      inf.outer_iters += g.iters;
+      inf.n_products += g.iters + 1;
+      conv = g.converged;
+    } else {
+      // float32 products (and float32 nested solves), float64 Arnoldi; float64 residual refinement
+      const double inner32 = std::max(inner, 1e-7);
+      ApplyFn A32 = [&op, inner32, st](const double2* x, double2* y) { apply_final(op, x, y, true, inner32, st); };
+      launch_axpby(N, c2(0.0), nullptr, c2(0.0), nullptr, xs, st);
+      launch_axpby(N, c2(1.0), bfull, c2(0.0), nullptr, r, st);
+      launch_norm(bfull, N, op.outer_ws->nrm, op.outer_ws->ks, st);
+      const double bn = read_scalar(op.pinned,reinterpret_cast<const double*>(op.outer_ws->nrm), st);
+      const int sweeps = opts.max_refine > 0 ? opts.max_refine : 5;
+      for (int s = 0; s < sweeps && left > 0; ++s) {
+        const double stol = std::max(opts.tol * 0.5, 1e-6);
+        GmresResult g = gmres(*op.outer_ws, op.pinned,A32, r, d, true, stol, left, st);
+        left -= g.iters;
+        inf.outer_iters += g.iters;
+        inf.n_products += g.iters + 1;
+        launch_axpby(N, c2(1.0), xs, c2(1.0), d, xs, st);
+        A64(xs, r);
+        ++inf.refine_steps;
+        ++inf.n_products;
+        launch_axpby(N, c2(1.0), bfull, c2(-1.0), r, r, st);
+        launch_norm(r, N, op.outer_ws->nrm, op.outer_ws->ks, st);
+        const double rn = read_scalar(op.pinned,reinterpret_cast<const double*>(op.outer_ws->nrm), st);
+        rel = bn > 0 ? rn / bn : 0.0;
+        if (rel <= opts.tol) {
+          conv = true;
+          break;
+        }
+      }
+    }
+    // true float64 residual of the returned iterate
+    if (op.precision == BEM_FP64) {
+      A64(xs, r);
+      ++inf.n_products;
+      launch_axpby(N, c2(1.0), bfull, c2(-1.0), r, r, st);
+      launch_norm(r, N, op.outer_ws->nrm, op.outer_ws->ks, st);
+      const double rn = read_scalar(op.pinned,reinterpret_cast<const double*>(op.outer_ws->nrm), st);
+      launch_norm(bfull, N, op.outer_ws->nrm, op.outer_ws->ks, st);
+      const double bn = read_scalar(op.pinned,reinterpret_cast<const double*>(op.outer_ws->nrm), st);
+      rel = bn > 0 ? rn / bn : 0.0;
+    }
+    inf.rel_residual = std::max(inf.rel_residual, rel);
+    if (!conv) status = BEM_E_NOT_CONVERGED;
+    // outputs: H = a/(jk0), E = eta0 e, rho = -B x3 / c0
+    auto put = [&](bem_c64* dst, const double2* src, int64_t len) {
+      if (!dst) return;
+      bem_c64* p = dst + e * len;
+      BEM_HIP(hipMemcpyAsync(p, src, sizeof(double2) * len,
+                             opts.out_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
+    };
+    launch_axpby(ne, c2(0.0, -1.0 / op.k0), xs, c2(0.0), nullptr, o1, st);
+    put(Hout, o1, ne);
+    BEM_HIP(hipStreamSynchronize(st));
+    launch_axpby(ne, c2(kEta0), xs + ne, c2(0.0), nullptr, o1, st);
+    put(Eout, o1, ne);
+    BEM_HIP(hipStreamSynchronize(st));
+    launch_expand_charge(xs + 2 * ne, o3, op.obj_tri_d, op.nobj, c2(-1.0 / kC0), st);
+    put(rhoout, o3, op.nt);
+    BEM_HIP(hipStreamSynchronize(st));
+  }
+  (void)nq;
+  inf.inner_iters_max = op.max_inner_iters;
+  inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - tstart).count();
+  if (info) *info = inf;
+  return status;
+}
+
+}  // namespace bem
