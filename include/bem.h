@@ -104,6 +104,13 @@ int bem_edge_table(bem_ctx* ctx, bem_mesh_h mesh, int32_t* va, int32_t* vb, int3
 int bem_near_pairs(bem_ctx* ctx, bem_mesh_h mesh, int64_t* ptr, int32_t* idx);
 
 typedef struct { bem_c64 eps_r; double mu_r, sigma; } bem_material;
+
+/* How the equivalent-configuration system (eq. AEFIEeqvdis) is solved inside every product
+ * (Sec. III): directly (its inverse is formed once per assembly; the paper's route for small
+ * objects) or by nested GMRES (its route for large objects); AUTO picks direct while every
+ * object's system has at most 16384 unknowns. */
+enum { BEM_INNER_AUTO = 0, BEM_INNER_GMRES = 1, BEM_INNER_DIRECT = 2 };
+
 typedef struct {
   double freq_hz;
   bem_c64 eps_bg;               /* background (homogeneous layer l) relative permittivity */
@@ -112,6 +119,10 @@ typedef struct {
   int64_t n_obj;
   int precision;                /* BEM_FP64, or BEM_MIXED: float32 copies of the dense blocks
                                    for the Krylov products, float64 residual refinement */
+  int inner_mode;               /* BEM_INNER_* */
+  int precond;                  /* 1: block preconditioner of eq. pcext for the final system
+                                   (and its equivalent-configuration counterpart for the nested
+                                   GMRES), built at assembly; 0: none */
 } bem_problem;
 
 /* Fill every dense block on the device: L^A, L^phi and K~ at the object
@@ -195,6 +206,25 @@ int bem_submit(bem_ctx* ctx, const bem_request* req, bem_ticket* out);
 int bem_poll(bem_ctx* ctx, bem_ticket ticket, bem_solve_info* info);
 /* Block until no submitted request is pending. */
 int bem_drain(bem_ctx* ctx);
+
+/* Statistics of an assembled operator: device time of the whole fill (all wavenumbers, near
+ * corrections and gathers), bytes of the float64 dense blocks written, Green's-function and
+ * gradient evaluations of the quadrature, and device bytes held by the operator. */
+typedef struct {
+  double fill_seconds;
+  double fill_bytes;
+  double kernel_evals;
+  double device_bytes;
+} bem_op_stats;
+int bem_op_stats_get(bem_ctx* ctx, bem_op_h op, bem_op_stats* out);
+
+/* Opt-in kernel timing (all contexts of the process).  When enabled, HIP events are recorded
+ * on the launch stream around every fill, gather and dense-product launch, together with the
+ * launch's algorithmic bytes and work.  Enabling clears the counters.  Classes: 0 float64
+ * products, 1 float32 products, 2 L fill, 3 K~ fill, 4 near corrections, 5 gathers, 6 matrix-
+ * core products.  bem_profile_read waits for the recorded events. */
+int bem_profile_enable(int on);
+int bem_profile_read(int kernel_class, int64_t* launches, double* ms, double* bytes, double* work);
 
 /* Free a mesh or operator handle and its device memory. */
 int bem_release(bem_ctx* ctx, uint64_t handle);

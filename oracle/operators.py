@@ -122,11 +122,12 @@ def coplanar(topo: Topology, t: int, others: np.ndarray) -> np.ndarray:
 
 # --------------------------------------------------------------- L^A, L^phi
 
-def fill_L(topo: Topology, k: complex, near=None, outer_rule=None, inner_rule=None):
+def fill_L(topo: Topology, k: complex, near=None, outer_rule=None, inner_rule=None, test_subset=None):
     """Return (LA, Lphi) at wavenumber k.
 
     outer_rule / inner_rule override Q7 for the near pairs only (used by the
-    convergence pins); far pairs always use Q7 x Q7.
+    convergence pins); far pairs always use Q7 x Q7.  test_subset restricts the rows that
+    are filled to the given test triangles (used to time a bounded sample).
     """
     nt, ne = len(topo.tri), len(topo.edges)
     V = tri_vertices(topo)
@@ -140,7 +141,7 @@ def fill_L(topo: Topology, k: complex, near=None, outer_rule=None, inner_rule=No
     LA = np.zeros((ne, ne), dtype=np.complex128)
     Lphi = np.zeros((nt, nt), dtype=np.complex128)
     free = V                                       # free vertex of half i = vertex i
-    for t in range(nt):
+    for t in (range(nt) if test_subset is None else test_subset):
         far_idx = np.nonzero(~near[t])[0]
         near_idx = np.nonzero(near[t])[0]
         si = topo.tri_signs[t].astype(np.float64)
@@ -223,7 +224,7 @@ def bc_on_subtriangles(bary: Barycentric):
 
 
 def fill_K(topo: Topology, bary: Barycentric, k: complex, near=None, bcdata=None,
-           outer_rule=None, inner_rule=None):
+           outer_rule=None, inner_rule=None, test_subset=None):
     """K~ (NE x NE) at wavenumber k, BC sources on the barycentric refinement."""
     nt, ne = len(topo.tri), len(topo.edges)
     V = tri_vertices(topo)
@@ -246,7 +247,7 @@ def fill_K(topo: Topology, bary: Barycentric, k: complex, near=None, bcdata=None
     gval = gval * valid[:, :, None, None]
     K = np.zeros((ne, ne), dtype=np.complex128)
     parent = bary.parent
-    for t in range(nt):
+    for t in (range(nt) if test_subset is None else test_subset):
         rk = Q.points(V[t], bq)                                       # (7, 3)
         fi = topo.tri_signs[t][:, None, None] * (rk[None, :, :] - V[t][:, None, :]) / (2 * A[t])  # (3i,7k,3)
         far_sub = ~near[t][parent]

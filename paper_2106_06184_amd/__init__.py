@@ -24,7 +24,14 @@ BEM_EXC_PLANE_WAVE, BEM_EXC_DELTA_GAP = 0, 1
 
 SYMBOLS = ["bem_create", "bem_destroy", "bem_last_error", "bem_mesh_load", "bem_mesh_info", "bem_edge_table",
            "bem_near_pairs", "bem_assemble", "bem_apply", "bem_block_export", "bem_set_inner_tol", "bem_solve",
-           "bem_submit", "bem_poll", "bem_drain", "bem_release", "bem_memory_in_use"]
+           "bem_submit", "bem_poll", "bem_drain", "bem_release", "bem_memory_in_use", "bem_op_stats_get",
+           "bem_profile_enable", "bem_profile_read"]
+KC_GEMV_F64, KC_GEMV_F32, KC_FILL_L, KC_FILL_K, KC_FILL_NEAR, KC_GATHER, KC_GEMM_F32 = range(7)
+
+
+class bem_op_stats(C.Structure):
+    _fields_ = [("fill_seconds", C.c_double), ("fill_bytes", C.c_double), ("kernel_evals", C.c_double),
+                ("device_bytes", C.c_double)]
 
 
 class c64(C.Structure):
@@ -35,9 +42,13 @@ class bem_material(C.Structure):
     _fields_ = [("eps_r", c64), ("mu_r", C.c_double), ("sigma", C.c_double)]
 
 
+BEM_INNER_AUTO, BEM_INNER_GMRES, BEM_INNER_DIRECT = 0, 1, 2
+
+
 class bem_problem(C.Structure):
     _fields_ = [("freq_hz", C.c_double), ("eps_bg", c64), ("mu_bg", C.c_double),
-                ("obj", C.POINTER(bem_material)), ("n_obj", C.c_int64), ("precision", C.c_int)]
+                ("obj", C.POINTER(bem_material)), ("n_obj", C.c_int64), ("precision", C.c_int),
+                ("inner_mode", C.c_int), ("precond", C.c_int)]
 
 
 class bem_excitation(C.Structure):
@@ -92,6 +103,9 @@ def lib() -> C.CDLL:
             "bem_drain": (C.c_int, [P]),
             "bem_release": (C.c_int, [P, C.c_uint64]),
             "bem_memory_in_use": (C.c_int, [P, C.POINTER(C.c_size_t)]),
+            "bem_op_stats_get": (C.c_int, [P, C.c_uint64, C.POINTER(bem_op_stats)]),
+            "bem_profile_enable": (C.c_int, [C.c_int]),
+            "bem_profile_read": (C.c_int, [C.c_int, C.POINTER(I64), C.POINTER(D), C.POINTER(D), C.POINTER(D)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -173,12 +187,13 @@ def bem_near_pairs(ctx, mesh: int):
     return ptr, idx
 
 
-def make_problem(freq_hz, eps_r, mu_r, sigma, eps_bg=1.0, mu_bg=1.0, precision=BEM_FP64):
+def make_problem(freq_hz, eps_r, mu_r, sigma, eps_bg=1.0, mu_bg=1.0, precision=BEM_FP64,
+                 inner_mode=BEM_INNER_AUTO, precond=1):
     mats = (bem_material * len(eps_r))()
     for i, (e, m, s) in enumerate(zip(eps_r, mu_r, sigma)):
         mats[i] = bem_material(c64(complex(e).real, complex(e).imag), float(m), float(s))
     p = bem_problem(float(freq_hz), c64(complex(eps_bg).real, complex(eps_bg).imag), float(mu_bg),
-                    C.cast(mats, C.POINTER(bem_material)), len(eps_r), int(precision))
+                    C.cast(mats, C.POINTER(bem_material)), len(eps_r), int(precision), int(inner_mode), int(precond))
     p._keep = mats
     return p
 
@@ -254,6 +269,22 @@ def bem_drain(ctx) -> None:
 
 def bem_release(ctx, handle: int) -> None:
     _check(ctx, lib().bem_release(ctx, handle))
+
+
+def bem_op_stats_get(ctx, op: int) -> dict:
+    s = bem_op_stats()
+    _check(ctx, lib().bem_op_stats_get(ctx, op, C.byref(s)))
+    return {f: getattr(s, f) for f, _ in bem_op_stats._fields_}
+
+
+def bem_profile_enable(on: bool) -> None:
+    _check(None, lib().bem_profile_enable(1 if on else 0))
+
+
+def bem_profile_read(kernel_class: int) -> dict:
+    n, ms, by, wk = C.c_int64(), C.c_double(), C.c_double(), C.c_double()
+    _check(None, lib().bem_profile_read(kernel_class, C.byref(n), C.byref(ms), C.byref(by), C.byref(wk)))
+    return dict(launches=n.value, ms=ms.value, bytes=by.value, work=wk.value)
 
 
 def bem_memory_in_use(ctx) -> int:

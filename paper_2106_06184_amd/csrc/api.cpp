@@ -3,6 +3,7 @@
 #include <cstring>
 
 #include "ctx.h"
+#include "prof.h"
 #include "serve.h"
 
 namespace {
@@ -244,6 +245,37 @@ int bem_memory_in_use(bem_ctx* c, size_t* bytes) {
     if (!bytes) return fail(BEM_E_INVALID, "null output");
     std::lock_guard<std::mutex> g(ctx->mu);
     *bytes = ctx->used;
+    return BEM_OK;
+  });
+}
+
+int bem_op_stats_get(bem_ctx* c, bem_op_h h, bem_op_stats* out) {
+  return guarded([&]() -> int {
+    bem::OpObj& op = op_of(C(c), h);
+    if (!out) return fail(BEM_E_INVALID, "null output");
+    out->fill_seconds = op.fill_seconds;
+    out->fill_bytes = op.fill_bytes;
+    out->kernel_evals = op.kernel_evals;
+    out->device_bytes = double(op.mem.bytes());
+    return BEM_OK;
+  });
+}
+
+int bem_profile_enable(int on) {
+  return guarded([&]() -> int {
+    bem::Profiler::get().enable(on != 0);
+    return BEM_OK;
+  });
+}
+
+int bem_profile_read(int cls, int64_t* launches, double* ms, double* bytes, double* work) {
+  return guarded([&]() -> int {
+    if (cls < 0 || cls >= bem::KC_COUNT) return fail(BEM_E_INVALID, "unknown kernel class");
+    bem::ClassStats s = bem::Profiler::get().read(cls);
+    if (launches) *launches = s.launches;
+    if (ms) *ms = s.ms;
+    if (bytes) *bytes = s.bytes;
+    if (work) *work = s.work;
     return BEM_OK;
   });
 }

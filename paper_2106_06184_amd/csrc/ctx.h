@@ -95,11 +95,20 @@ struct OpObj {
   // dense blocks
   std::vector<Dense> LA_int, Lphi_int, K_int, K_bg;  // per object (block-diagonal operators)
   Dense LA_bg, Lphi_bg;                              // all pairs (background coupling)
+  // nested solve and preconditioners
+  int inner_mode = BEM_INNER_GMRES;
+  bool precond = false;
+  std::vector<Dense> Minv;           // per object: inverse of M_eq (direct inner solve)
+  std::vector<Dense> SigP, SigEq;    // per object: inverses of the charge Schur complements
+  double2* pcW = nullptr;            // per edge: inverse of the 2x2 diagonal block of P (4 entries)
+  double2* lam_bg = nullptr;         // per triangle: diag L^phi_l
+  double2* lam_int = nullptr;        // per triangle: diag L^phi (object wavenumber)
+  double2* eq_d = nullptr;           // per edge: 1 / (mu_l diag L^A_l)
   // solver settings and work
   double inner_tol = 1e-12;
   int inner_restart = 200, inner_maxit = 4000;
   int last_inner_iters = 0, max_inner_iters = 0;
-  double fill_seconds = 0;
+  double fill_seconds = 0, fill_bytes = 0, kernel_evals = 0;
   std::unique_ptr<GmresWork> inner_ws, outer_ws;
   double2* work = nullptr;  // vector workspace
   int64_t work_len = 0;
@@ -122,16 +131,21 @@ struct GmresWork {
   int64_t n = 0, ldv = 0;
   int m = 0;
   double2 *V = nullptr, *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr, *y = nullptr, *h2 = nullptr;
+  double2 *z = nullptr, *z2 = nullptr;  // preconditioned-vector temporaries
   double2* nrm = nullptr;
   double* res = nullptr;
   KrylovScratch ks{};
+  const char* tag = nullptr;  // progress label (BEM_VERBOSE)
 };
 
 std::unique_ptr<GmresWork> make_gmres_work(DevArena& mem, int64_t n, int m);
 // Right-preconditioner-free restarted GMRES (CGS2 Arnoldi, complex Givens, float64) on `st`.
 // x holds the initial guess (zeroed when x_zero) and receives the solution.
+// M (optional) is a right preconditioner: GMRES runs on A M and returns x = M u.
 GmresResult gmres(GmresWork& w, double* pinned, const ApplyFn& A, const double2* b, double2* x, bool x_zero,
-                  double tol, int maxit, hipStream_t st);
+                  double tol, int maxit, hipStream_t st, const ApplyFn* M = nullptr);
+void apply_precond(OpObj& op, const double2* r, double2* x, bool fp32, hipStream_t st);
+void apply_precond_eq(OpObj& op, const double2* r, double2* x, bool fp32, hipStream_t st);
 
 // Operator construction and application.
 void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob);

@@ -1,0 +1,47 @@
+// Dense inversion, dense-matrix builders and block-preconditioner kernels (interface).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace bem {
+
+struct DenseScratch {
+  double2* P;  // 64 x 64
+  double2* R;  // 64 x n
+  double2* C;  // n x 64
+};
+
+// In-place inverse of the n x n complex matrix A (row-major, leading dimension ld) by blocked
+// Gauss-Jordan elimination without pivoting.  Asynchronous on st.
+void dense_invert(double2* A, int64_t n, int64_t ld, DenseScratch& ws, hipStream_t st);
+
+// Dense M_eq of one object (eq. AEFIEeqvdis) from its diagonal blocks of L^A_l and L^phi_l;
+// tp/tm are the object's edges' triangles in object-local numbering; mu = mu_l,
+// meps = -1/eps_l, k02 = k0^2.
+void build_meq(const double2* LA, int64_t lda, const double2* Lp, int64_t ldp, const int32_t* tp_local,
+               const int32_t* tm_local, int64_t ne, int64_t nt, double2 mu, double2 meps, double k02, double2* M,
+               int64_t ldm, hipStream_t st);
+
+// Dense S (nq x nq) = diag * I + G B for a sparse G (CSR over the nq kept charges, columns =
+// object-local triangles, the last one being the eliminated charge): (G B)[q][c] = G[q][c] -
+// G[q][last].
+void build_schur(const int64_t* ptr, const int32_t* idx, const double2* val, int64_t nq, int64_t last, double2 diag,
+                 double2* S, int64_t lds, hipStream_t st);
+
+// Block preconditioner of the final system (eq. pcext), per edge n with W = [[w11, w12],
+// [w21, w22]] the inverse of its 2x2 diagonal block:
+//   stage 1: t[n] = w11 r1[n] + w12 r2[n]
+//   stage 2: s_b = e_b[n] (lb[T+] v[T+] - lb[T-] v[T-]), s_i likewise with li and e_i,
+//            x1 = w11 (r1 - s_b) + w12 (r2 - s_i),  x2 = w21 (r1 - s_b) + w22 (r2 - s_i)
+void launch_pc_stage1(const double2* W, const double2* r1, const double2* r2, int64_t ne, double2* t, hipStream_t st);
+void launch_pc_stage2(const double2* W, const double2* r1, const double2* r2, const double2* v, const double2* lb,
+                      const double2* li, double2 e_b, const double2* e_i, const int32_t* tp, const int32_t* tm,
+                      int64_t ne, double2* x1, double2* x2, hipStream_t st);
+// Equivalent-configuration preconditioner: t = d r1 ; x1 = t + d e (lb[T+] v[T+] - lb[T-] v[T-])
+void launch_peq_stage1(const double2* d, const double2* r1, int64_t ne, double2* t, hipStream_t st);
+void launch_peq_stage2(const double2* d, const double2* t, const double2* v, const double2* lb, double2 e,
+                       const int32_t* tp, const int32_t* tm, int64_t ne, double2* x1, hipStream_t st);
+
+}  // namespace bem

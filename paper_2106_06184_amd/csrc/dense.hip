@@ -1,0 +1,348 @@
+// Dense complex float64 inversion on the device (blocked Gauss-Jordan without pivoting) and the
+// builders of the dense matrices it is applied to: the equivalent-configuration matrix M_eq of
+// eq. AEFIEeqvdis (direct inner solve, the paper's route for small objects) and the charge Schur
+// complements of the block preconditioners (eq. pcext for the final system, and its
+// equivalent-configuration counterpart for the nested iterative solve).
+//
+// Gauss-Jordan step on the diagonal block kb (width b <= 64):
+//   P = A_kb,kb^-1 ;  R = P A_kb,j (j outside kb) ;  C = A_i,kb (i outside kb)
+//   A_i,j -= C_i R_j ;  A_kb,j = R_j ;  A_i,kb = -C_i P ;  A_kb,kb = P
+// The update is a rank-b complex product over the whole matrix (64 x 64 output tiles per
+// workgroup, K staged through LDS in chunks of 16).  Without pivoting the elimination needs
+// non-singular leading blocks; for the matrices it is used on (near-field dominated BEM blocks
+// and their charge Schur complements) this holds and round-off growth stays small.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "dense.h"
+
+namespace bem {
+namespace dev {
+
+constexpr int NB = 64;
+
+__device__ __forceinline__ double2 cm(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cinv(double2 a) {
+  const double d = a.x * a.x + a.y * a.y;
+  return make_double2(a.x / d, -a.y / d);
+}
+
+// In-place inversion of the b x b diagonal block, copied to P (ld NB).
+__global__ void __launch_bounds__(256) k_gj_diag(double2* __restrict__ A, int64_t ld, int64_t k0, int b,
+                                                 double2* __restrict__ P) {
+  __shared__ double2 M[NB][NB];
+  for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
+    const int r = e / NB, c = e % NB;
+    M[r][c] = (r < b && c < b) ? A[(k0 + r) * ld + k0 + c] : make_double2(0, 0);
+  }
+  __syncthreads();
+  for (int p = 0; p < b; ++p) {
+    const double2 inv = cinv(M[p][p]);
+    __syncthreads();
+    // scale row p
+    for (int c = threadIdx.x; c < b; c += blockDim.x)
+      if (c != p) M[p][c] = cm(M[p][c], inv);
+    __syncthreads();
+    // eliminate column p from the other rows
+    for (int e = threadIdx.x; e < b * b; e += blockDim.x) {
+      const int r = e / b, c = e % b;
+      if (r != p && c != p) {
+        const double2 f = M[r][p], g = M[p][c];
+        M[r][c].x -= f.x * g.x - f.y * g.y;
+        M[r][c].y -= f.x * g.y + f.y * g.x;
+      }
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < b; r += blockDim.x)
+      if (r != p) {
+        const double2 f = M[r][p];
+        M[r][p] = make_double2(-(f.x * inv.x - f.y * inv.y), -(f.x * inv.y + f.y * inv.x));
+      }
+    if (threadIdx.x == 0) M[p][p] = inv;
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
+    const int r = e / NB, c = e % NB;
+    P[r * NB + c] = M[r][c];
+  }
+}
+
+// R[s][j] = sum_t P[s][t] A[k0+t][j] for all j (thread: one column, 16 values of s);
+// C[i][s] = A[i][k0+s] for all i (copied before the update overwrites them).
+__global__ void __launch_bounds__(256) k_gj_panels(const double2* __restrict__ A, int64_t ld, int64_t n, int64_t k0,
+                                                   int b, const double2* __restrict__ P, double2* __restrict__ R,
+                                                   double2* __restrict__ Cp) {
+  __shared__ double2 Ps[NB][NB];
+  for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) Ps[e / NB][e % NB] = P[e];
+  __syncthreads();
+  const int64_t j = int64_t(blockIdx.x) * 64 + (threadIdx.x & 63);
+  const int sg = threadIdx.x >> 6;  // s in [16 sg, 16 sg + 16)
+  if (j < n) {
+    double2 acc[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) acc[u] = make_double2(0, 0);
+    for (int t = 0; t < b; ++t) {
+      const double2 a = A[(k0 + t) * ld + j];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const double2 p = Ps[16 * sg + u][t];
+        acc[u].x += p.x * a.x - p.y * a.y;
+        acc[u].y += p.x * a.y + p.y * a.x;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      if (16 * sg + u < b) R[(16 * sg + u) * n + j] = acc[u];
+    // column panel: row j of the kb columns
+    for (int s = sg; s < b; s += 4) Cp[j * NB + s] = A[j * ld + k0 + s];
+  }
+}
+
+// A[i][j] -= sum_s C[i][s] R[s][j] for i, j outside [k0, k0+b)
+__global__ void __launch_bounds__(256) k_gj_update(double2* __restrict__ A, int64_t ld, int64_t n, int64_t k0, int b,
+                                                   const double2* __restrict__ R, const double2* __restrict__ Cp) {
+  __shared__ double2 Cs[64][17];
+  __shared__ double2 Rs[16][64];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int64_t i0 = int64_t(blockIdx.y) * 64, j0 = int64_t(blockIdx.x) * 64;
+  double2 acc[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[r][c] = make_double2(0, 0);
+  for (int s0 = 0; s0 < b; s0 += 16) {
+    // stage C (64 x 16) and R (16 x 64)
+    for (int e = threadIdx.x; e < 64 * 16; e += 256) {
+      const int r = e / 16, s = e % 16;
+      const int64_t gi = i0 + r;
+      Cs[r][s] = (gi < n && s0 + s < b) ? Cp[gi * NB + s0 + s] : make_double2(0, 0);
+      const int sr = e / 64, cc = e % 64;
+      const int64_t gj = j0 + cc;
+      Rs[sr][cc] = (gj < n && s0 + sr < b) ? R[(s0 + sr) * n + gj] : make_double2(0, 0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      double2 cv[4], rv[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) cv[r] = Cs[ty + 16 * r][s];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) rv[c] = Rs[s][tx + 16 * c];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          acc[r][c].x += cv[r].x * rv[c].x - cv[r].y * rv[c].y;
+          acc[r][c].y += cv[r].x * rv[c].y + cv[r].y * rv[c].x;
+        }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int64_t gi = i0 + ty + 16 * r;
+    if (gi >= n || (gi >= k0 && gi < k0 + b)) continue;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int64_t gj = j0 + tx + 16 * c;
+      if (gj >= n || (gj >= k0 && gj < k0 + b)) continue;
+      double2* a = A + gi * ld + gj;
+      *a = make_double2(a->x - acc[r][c].x, a->y - acc[r][c].y);
+    }
+  }
+}
+
+// A[k0+s][j] = R[s][j] (j outside kb); A[i][k0+s] = -sum_t C[i][t] P[t][s] (i outside kb);
+// A[kb][kb] = P
+// Thread (i, s): 4 rows i per block, 64 values of s.
+//   i outside kb:  A[k0+s][i] = R[s][i]  and  A[i][k0+s] = -sum_t C[i][t] P[t][s]
+//   i inside kb:   A[i][k0+s] = P[i-k0][s]
+__global__ void __launch_bounds__(256) k_gj_write(double2* __restrict__ A, int64_t ld, int64_t n, int64_t k0, int b,
+                                                  const double2* __restrict__ P, const double2* __restrict__ R,
+                                                  const double2* __restrict__ Cp) {
+  __shared__ double2 Ps[NB][NB];
+  for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) Ps[e / NB][e % NB] = P[e];
+  __syncthreads();
+  const int64_t i = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  const int s = threadIdx.x & 63;
+  if (i >= n || s >= b) return;
+  if (i >= k0 && i < k0 + b) {
+    A[i * ld + k0 + s] = Ps[i - k0][s];
+    return;
+  }
+  A[(k0 + s) * ld + i] = R[s * n + i];
+  double2 acc = make_double2(0, 0);
+  for (int t = 0; t < b; ++t) {
+    const double2 c = Cp[i * NB + t], p = Ps[t][s];
+    acc.x += c.x * p.x - c.y * p.y;
+    acc.y += c.x * p.y + c.y * p.x;
+  }
+  A[i * ld + k0 + s] = make_double2(-acc.x, -acc.y);
+}
+
+// ------------------------------------------------------------- builders
+
+// M_eq of one object (local indices): rows/cols [0, ne) edges, [ne, ne+nq) kept charges.
+//  M[m][n]      = mu_l L^A[m][n]
+//  M[m][ne+q]   = -eps_l^-1 ((L^phi B)[T+m][q] - (L^phi B)[T-m][q]),  (L^phi B)[t][q] = Lp[t][q] - Lp[t][last]
+//  M[ne+q][n]   = (F D)[q][n] = +1 if T+(n) = q, -1 if T-(n) = q
+//  M[ne+q][ne+q'] = -k0^2 delta
+__global__ void k_build_meq(const double2* __restrict__ LA, int64_t lda, const double2* __restrict__ Lp, int64_t ldp,
+                            const int32_t* __restrict__ tp, const int32_t* __restrict__ tm, int64_t ne, int64_t nt,
+                            double2 mu, double2 meps, double k02, double2* __restrict__ M, int64_t ldm) {
+  const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t r = blockIdx.y;
+  const int64_t nq = nt - 1, N = ne + nq;
+  if (c >= N) return;
+  double2 v = make_double2(0, 0);
+  if (r < ne) {
+    if (c < ne) {
+      v = cm(mu, LA[r * lda + c]);
+    } else {
+      const int64_t q = c - ne, last = nt - 1;
+      const double2 a = Lp[int64_t(tp[r]) * ldp + q], b = Lp[int64_t(tp[r]) * ldp + last];
+      const double2 d = Lp[int64_t(tm[r]) * ldp + q], e = Lp[int64_t(tm[r]) * ldp + last];
+      const double2 diff = make_double2((a.x - b.x) - (d.x - e.x), (a.y - b.y) - (d.y - e.y));
+      v = cm(meps, diff);
+    }
+  } else {
+    const int64_t q = r - ne;
+    if (c < ne) {
+      if (tp[c] == q) v.x += 1.0;
+      if (tm[c] == q) v.x -= 1.0;
+    } else if (c - ne == q) {
+      v.x = -k02;
+    }
+  }
+  M[r * ldm + c] = v;
+}
+
+// Dense charge Schur complement S = k0^2 s0 I + G_kept - g_last 1^T from a sparse G (CSR over
+// kept charges, columns = triangles of the object) - see dense.h.
+__global__ void k_build_schur(const int64_t* __restrict__ ptr, const int32_t* __restrict__ idx,
+                              const double2* __restrict__ val, int64_t nq, int64_t last, double2 diag,
+                              double2* __restrict__ S, int64_t lds) {
+  const int64_t q = blockIdx.x;
+  if (q >= nq) return;
+  double2 gl = make_double2(0, 0);
+  for (int64_t p = ptr[q]; p < ptr[q + 1]; ++p)
+    if (idx[p] == last) gl = val[p];
+  for (int64_t c = threadIdx.x; c < nq; c += blockDim.x)
+    S[q * lds + c] = make_double2((c == q ? diag.x : 0.0) - gl.x, (c == q ? diag.y : 0.0) - gl.y);
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int64_t p = ptr[q]; p < ptr[q + 1]; ++p)
+      if (idx[p] != last) {
+        double2* s = S + q * lds + idx[p];
+        *s = make_double2(s->x + val[p].x, s->y + val[p].y);
+      }
+}
+
+// ------------------------------------------------------------- preconditioners
+
+__global__ void k_pc_stage1(const double2* __restrict__ W, const double2* __restrict__ r1, const double2* __restrict__ r2,
+                            int64_t ne, double2* __restrict__ t) {
+  const int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (n >= ne) return;
+  const double2 a = cm(W[4 * n], r1[n]), b = cm(W[4 * n + 1], r2[n]);
+  t[n] = make_double2(a.x + b.x, a.y + b.y);
+}
+
+__global__ void k_pc_stage2(const double2* __restrict__ W, const double2* __restrict__ r1, const double2* __restrict__ r2,
+                            const double2* __restrict__ v, const double2* __restrict__ lb, const double2* __restrict__ li,
+                            double2 e_b, const double2* __restrict__ e_i, const int32_t* __restrict__ tp,
+                            const int32_t* __restrict__ tm, int64_t ne, double2* __restrict__ x1,
+                            double2* __restrict__ x2) {
+  const int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (n >= ne) return;
+  const int32_t p = tp[n], m = tm[n];
+  const double2 vp = v[p], vm = v[m];
+  const double2 db = make_double2(cm(lb[p], vp).x - cm(lb[m], vm).x, cm(lb[p], vp).y - cm(lb[m], vm).y);
+  const double2 di = make_double2(cm(li[p], vp).x - cm(li[m], vm).x, cm(li[p], vp).y - cm(li[m], vm).y);
+  const double2 sb = cm(e_b, db), si = cm(e_i[n], di);
+  const double2 a = make_double2(r1[n].x - sb.x, r1[n].y - sb.y);
+  const double2 b = make_double2(r2[n].x - si.x, r2[n].y - si.y);
+  const double2 u1 = cm(W[4 * n], a), u2 = cm(W[4 * n + 1], b), u3 = cm(W[4 * n + 2], a), u4 = cm(W[4 * n + 3], b);
+  x1[n] = make_double2(u1.x + u2.x, u1.y + u2.y);
+  x2[n] = make_double2(u3.x + u4.x, u3.y + u4.y);
+}
+
+__global__ void k_peq_stage1(const double2* __restrict__ d, const double2* __restrict__ r1, int64_t ne,
+                             double2* __restrict__ t) {
+  const int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (n >= ne) return;
+  t[n] = cm(d[n], r1[n]);
+}
+
+__global__ void k_peq_stage2(const double2* __restrict__ d, const double2* __restrict__ t, const double2* __restrict__ v,
+                             const double2* __restrict__ lb, double2 e, const int32_t* __restrict__ tp,
+                             const int32_t* __restrict__ tm, int64_t ne, double2* __restrict__ x1) {
+  const int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (n >= ne) return;
+  const int32_t p = tp[n], m = tm[n];
+  const double2 a = cm(lb[p], v[p]), b = cm(lb[m], v[m]);
+  const double2 s = cm(cm(d[n], e), make_double2(a.x - b.x, a.y - b.y));
+  x1[n] = make_double2(t[n].x + s.x, t[n].y + s.y);
+}
+
+}  // namespace dev
+
+void launch_pc_stage1(const double2* W, const double2* r1, const double2* r2, int64_t ne, double2* t, hipStream_t st) {
+  hipLaunchKernelGGL(dev::k_pc_stage1, dim3(unsigned((ne + 255) / 256)), dim3(256), 0, st, W, r1, r2, ne, t);
+  BEM_HIP(hipGetLastError());
+}
+
+void launch_pc_stage2(const double2* W, const double2* r1, const double2* r2, const double2* v, const double2* lb,
+                      const double2* li, double2 e_b, const double2* e_i, const int32_t* tp, const int32_t* tm,
+                      int64_t ne, double2* x1, double2* x2, hipStream_t st) {
+  hipLaunchKernelGGL(dev::k_pc_stage2, dim3(unsigned((ne + 255) / 256)), dim3(256), 0, st, W, r1, r2, v, lb, li, e_b,
+                     e_i, tp, tm, ne, x1, x2);
+  BEM_HIP(hipGetLastError());
+}
+
+void launch_peq_stage1(const double2* d, const double2* r1, int64_t ne, double2* t, hipStream_t st) {
+  hipLaunchKernelGGL(dev::k_peq_stage1, dim3(unsigned((ne + 255) / 256)), dim3(256), 0, st, d, r1, ne, t);
+  BEM_HIP(hipGetLastError());
+}
+
+void launch_peq_stage2(const double2* d, const double2* t, const double2* v, const double2* lb, double2 e,
+                       const int32_t* tp, const int32_t* tm, int64_t ne, double2* x1, hipStream_t st) {
+  hipLaunchKernelGGL(dev::k_peq_stage2, dim3(unsigned((ne + 255) / 256)), dim3(256), 0, st, d, t, v, lb, e, tp, tm, ne,
+                     x1);
+  BEM_HIP(hipGetLastError());
+}
+
+void dense_invert(double2* A, int64_t n, int64_t ld, DenseScratch& ws, hipStream_t st) {
+  if (n <= 0) return;
+  for (int64_t k0 = 0; k0 < n; k0 += dev::NB) {
+    const int b = int(std::min<int64_t>(dev::NB, n - k0));
+    hipLaunchKernelGGL(dev::k_gj_diag, dim3(1), dim3(256), 0, st, A, ld, k0, b, ws.P);
+    hipLaunchKernelGGL(dev::k_gj_panels, dim3(unsigned((n + 63) / 64)), dim3(256), 0, st, A, ld, n, k0, b, ws.P,
+                       ws.R, ws.C);
+    dim3 g(unsigned((n + 63) / 64), unsigned((n + 63) / 64));
+    hipLaunchKernelGGL(dev::k_gj_update, g, dim3(256), 0, st, A, ld, n, k0, b, ws.R, ws.C);
+    hipLaunchKernelGGL(dev::k_gj_write, dim3(unsigned((n + 3) / 4)), dim3(256), 0, st, A, ld, n, k0, b, ws.P, ws.R,
+                       ws.C);
+  }
+  BEM_HIP(hipGetLastError());
+}
+
+void build_meq(const double2* LA, int64_t lda, const double2* Lp, int64_t ldp, const int32_t* tp_local,
+               const int32_t* tm_local, int64_t ne, int64_t nt, double2 mu, double2 meps, double k02, double2* M,
+               int64_t ldm, hipStream_t st) {
+  const int64_t N = ne + nt - 1;
+  hipLaunchKernelGGL(dev::k_build_meq, dim3(unsigned((N + 255) / 256), unsigned(N)), dim3(256), 0, st, LA, lda, Lp, ldp,
+                     tp_local, tm_local, ne, nt, mu, meps, k02, M, ldm);
+  BEM_HIP(hipGetLastError());
+}
+
+void build_schur(const int64_t* ptr, const int32_t* idx, const double2* val, int64_t nq, int64_t last, double2 diag,
+                 double2* S, int64_t lds, hipStream_t st) {
+  hipLaunchKernelGGL(dev::k_build_schur, dim3(unsigned(nq)), dim3(256), 0, st, ptr, idx, val, nq, last, diag, S, lds);
+  BEM_HIP(hipGetLastError());
+}
+
+}  // namespace bem

@@ -21,6 +21,7 @@
 
 #include "devmath.h"
 #include "fill.h"
+#include "prof.h"
 
 namespace bem {
 namespace dev {
@@ -470,10 +471,15 @@ void launch_fill_L(const FillLArgs& a, const int32_t* near_t, const int32_t* nea
   if (a.ns <= 0 || a.nt_test <= 0) return;
   dim3 grid(unsigned((a.ns + 255) / 256), unsigned((a.nt_test + a.tchunk - 1) / a.tchunk));
   bool lossy = a.ki != 0.0;
-  if (lossy) hipLaunchKernelGGL(dev::k_fill_L_far<true>, grid, dim3(256), 0, st, a);
-  else hipLaunchKernelGGL(dev::k_fill_L_far<false>, grid, dim3(256), 0, st, a);
-  BEM_HIP(hipGetLastError());
+  {
+    const double pairs = double(a.ns) * a.nt_test;
+    ProfScope ps(st, KC_FILL_L, pairs * 10 * 16, pairs * 49);
+    if (lossy) hipLaunchKernelGGL(dev::k_fill_L_far<true>, grid, dim3(256), 0, st, a);
+    else hipLaunchKernelGGL(dev::k_fill_L_far<false>, grid, dim3(256), 0, st, a);
+    BEM_HIP(hipGetLastError());
+  }
   if (npairs > 0) {
+    ProfScope ps(st, KC_FILL_NEAR, double(npairs) * 10 * 16, double(npairs));
     dim3 g2(unsigned((npairs + 127) / 128));
     if (lossy) hipLaunchKernelGGL(dev::k_fill_L_near<true>, g2, dim3(128), 0, st, a, near_t, near_s, npairs);
     else hipLaunchKernelGGL(dev::k_fill_L_near<false>, g2, dim3(128), 0, st, a, near_t, near_s, npairs);
@@ -485,6 +491,7 @@ void launch_gather_LA(const double2* H, int64_t ldH, const int32_t* hp, const in
                       double2* out, int64_t ldo, hipStream_t st) {
   if (ne <= 0) return;
   dim3 grid(unsigned((ne + 255) / 256), unsigned(std::min<int64_t>(ne, 32768)));
+  ProfScope ps(st, KC_GATHER, double(ne) * ne * 5 * 16, double(ne) * ne);
   hipLaunchKernelGGL(dev::k_gather_LA, grid, dim3(256), 0, st, H, ldH, hp, hm, off, ne, out, ldo);
   BEM_HIP(hipGetLastError());
 }
@@ -495,13 +502,20 @@ void launch_fill_K(const FillKArgs& a, const int32_t* near_t, const int32_t* nea
   dim3 grid(unsigned((a.ncells + 127) / 128), unsigned((a.nt_test + a.tchunk - 1) / a.tchunk));
   bool lossy = a.ki != 0.0;
   dim3 g2(unsigned((npairs + 63) / 64));
-#define BEM_KLAUNCH(L, MV)                                                                          \
-  hipLaunchKernelGGL((dev::k_fill_K_far<L, MV>), grid, dim3(128), 0, st, a);                        \
-  BEM_HIP(hipGetLastError());                                                                       \
-  if (npairs > 0) {                                                                                 \
-    hipLaunchKernelGGL((dev::k_fill_K_near<L, MV>), g2, dim3(64), 0, st, a, near_t, near_c, npairs, \
-                       near_ptr, near_idx);                                                         \
-    BEM_HIP(hipGetLastError());                                                                     \
+  // every primal triangle of the object contributes 6 sub-triangles, 7 x 3 evaluations each
+  const double kwork = double(a.nt_test) * 6.0 * a.nt_test * 21.0;
+  const double kbytes = 3.0 * a.nt_test * a.ldK * 16.0;
+#define BEM_KLAUNCH(L, MV)                                                                            \
+  {                                                                                                   \
+    ProfScope ps(st, KC_FILL_K, kbytes, kwork);                                                       \
+    hipLaunchKernelGGL((dev::k_fill_K_far<L, MV>), grid, dim3(128), 0, st, a);                        \
+    BEM_HIP(hipGetLastError());                                                                       \
+  }                                                                                                   \
+  if (npairs > 0) {                                                                                   \
+    ProfScope ps(st, KC_FILL_NEAR, double(npairs) * 3 * MV * 16, double(npairs));                     \
+    hipLaunchKernelGGL((dev::k_fill_K_near<L, MV>), g2, dim3(64), 0, st, a, near_t, near_c, npairs,   \
+                       near_ptr, near_idx);                                                           \
+    BEM_HIP(hipGetLastError());                                                                       \
   }
   if (maxv == 8) {
     if (lossy) { BEM_KLAUNCH(true, 8) } else { BEM_KLAUNCH(false, 8) }
@@ -517,6 +531,7 @@ void launch_gather_K(const double2* Kc, int64_t ldK, const int32_t* hp, const in
                      const int32_t* cT, int64_t off, int64_t ne, double2* out, int64_t ldo, hipStream_t st) {
   if (ne <= 0) return;
   dim3 grid(unsigned((ne + 255) / 256), unsigned(std::min<int64_t>(ne, 32768)));
+  ProfScope ps(st, KC_GATHER, double(ne) * ne * 5 * 16, double(ne) * ne);
   hipLaunchKernelGGL(dev::k_gather_K, grid, dim3(256), 0, st, Kc, ldK, hp, hm, cS, cT, off, ne, out, ldo);
   BEM_HIP(hipGetLastError());
 }

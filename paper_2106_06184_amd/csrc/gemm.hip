@@ -1,0 +1,241 @@
+// Multi-excitation complex products on matrix cores: Y (+)= alpha A X with A complex float32
+// (interleaved re/im rows, the storage of the dense blocks), X and Y complex float64 column-
+// major with R columns.
+//
+// 4M real embedding: reading each complex row of A as 2K real numbers (re, im, re, im, ...),
+//   Re(A x) = sum_k' A'[k'] x_re'[k'],  x_re' = (Re x_0, -Im x_0, Re x_1, -Im x_1, ...)
+//   Im(A x) = sum_k' A'[k'] x_im'[k'],  x_im' = (Im x_0,  Re x_0, Im x_1,  Re x_1, ...)
+// so one real GEMM C (M x 2R) = A' (M x 2K) B (2K x 2R) with B's column 2r = x_re' and column
+// 2r+1 = x_im' of excitation r gives Re and Im of Y in adjacent columns.  8 real flops per
+// complex multiply-add, as the 4M method.
+//
+// Kernel: 128 x 128 output tile per 256-thread workgroup (2 x 2 waves of 64 x 64), K step 16,
+// double-buffered LDS (A stored k-major so that MFMA operand reads are conflict-free), float32
+// MFMA 32x32x2 with float32 accumulation.  Workgroup ids are remapped so that the column tiles
+// of one row tile run on the same XCD and share its L2 copy of the A rows.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "linalg.h"
+#include "prof.h"
+
+namespace bem {
+namespace dev {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+constexpr int BM = 128, BN = 128, BK = 16, PADA = 4, PADB = 4;
+
+__global__ void k_build_B(const double2* __restrict__ X, int64_t ldx, int64_t nc, int64_t R, float* __restrict__ Bm,
+                          int64_t ldb, int64_t K16) {
+  const int64_t col = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;  // 0 .. ldb-1
+  const int64_t kp = blockIdx.y;                                        // 0 .. K16-1
+  if (col >= ldb || kp >= K16) return;
+  float v = 0.f;
+  const int64_t k = kp >> 1, r = col >> 1;
+  if (k < nc && r < R) {
+    const double2 x = X[r * ldx + k];
+    const bool re_row = (kp & 1) == 0, re_col = (col & 1) == 0;
+    if (re_col) v = re_row ? float(x.x) : float(-x.y);
+    else v = re_row ? float(x.y) : float(x.x);
+  }
+  Bm[kp * ldb + col] = v;
+}
+
+template <bool ALIGNED>
+__global__ void __launch_bounds__(256) k_gemm_f32(const float* __restrict__ A, int64_t lda, const float* __restrict__ Bm,
+                                                  int64_t ldb, int64_t M, int64_t K, int64_t K16, int64_t ntn,
+                                                  double2* __restrict__ Y, int64_t ldy, int64_t R, double2 alpha,
+                                                  int accumulate) {
+  __shared__ float As[2][BK][BM + PADA];
+  __shared__ float Bs[2][BK][BN + PADB];
+  // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs; consecutive
+  // logical tiles (the column tiles of one row tile) are given to the same XCD.
+  const int64_t nwg = int64_t(gridDim.x);
+  const int64_t p = blockIdx.x;
+  int64_t logical = p;
+  if (nwg % 8 == 0) logical = (p % 8) * (nwg / 8) + p / 8;
+  const int64_t tm = logical / ntn, tn = logical % ntn;
+  const int64_t m0 = tm * BM, n0 = tn * BN;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wm = wave >> 1, wn = wave & 1;
+
+  // global-load coordinates
+  const int a_row = tid >> 1, a_k = (tid & 1) * 8;     // A: 128 rows x 16 k
+  const int b_k = tid >> 4, b_col = (tid & 15) * 8;    // B: 16 k x 128 cols
+  const int64_t gm = m0 + a_row;
+
+  floatx16 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
+
+  float ra[8], rb[8];
+  auto load_tile = [&](int64_t k0) {
+    const int64_t kk = k0 + a_k;
+    if (gm < M) {
+      const float* src = A + gm * lda + kk;
+      if (ALIGNED && kk + 8 <= K) {
+        const float4 u = *reinterpret_cast<const float4*>(src);
+        const float4 w = *reinterpret_cast<const float4*>(src + 4);
+        ra[0] = u.x; ra[1] = u.y; ra[2] = u.z; ra[3] = u.w;
+        ra[4] = w.x; ra[5] = w.y; ra[6] = w.z; ra[7] = w.w;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) ra[e] = (kk + e < K) ? src[e] : 0.f;
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) ra[e] = 0.f;
+    }
+    const float* bsrc = Bm + (k0 + b_k) * ldb + n0 + b_col;
+    const float4 u = *reinterpret_cast<const float4*>(bsrc);
+    const float4 w = *reinterpret_cast<const float4*>(bsrc + 4);
+    rb[0] = u.x; rb[1] = u.y; rb[2] = u.z; rb[3] = u.w;
+    rb[4] = w.x; rb[5] = w.y; rb[6] = w.z; rb[7] = w.w;
+  };
+  auto store_tile = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) As[buf][a_k + e][a_row] = ra[e];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) Bs[buf][b_k][b_col + e] = rb[e];
+  };
+
+  const int64_t nk = K16 / BK;
+  load_tile(0);
+  store_tile(0);
+  __syncthreads();
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    const int buf = int(kt & 1);
+    if (kt + 1 < nk) load_tile((kt + 1) * BK);
+#pragma unroll
+    for (int s = 0; s < BK / 2; ++s) {
+      const int kr = 2 * s + (lane >> 5);
+      float af[2], bf[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) af[i] = As[buf][kr][wm * 64 + i * 32 + (lane & 31)];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) bf[j] = Bs[buf][kr][wn * 64 + j * 32 + (lane & 31)];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[i], bf[j], acc[i][j], 0, 0, 0);
+    }
+    if (kt + 1 < nk) {
+      store_tile(buf ^ 1);
+    }
+    __syncthreads();
+  }
+
+  // epilogue: output column c = 2r (Re) or 2r+1 (Im); even lanes own the pair of an excitation
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const float mine = acc[i][j][v];
+        const float other = __shfl_xor(mine, 1, 64);
+        const int64_t row = m0 + wm * 64 + i * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
+        const int64_t col = n0 + wn * 64 + j * 32 + (lane & 31);
+        if ((lane & 1) == 0 && row < M && (col >> 1) < R) {
+          const double re = mine, im = other;
+          double yr = alpha.x * re - alpha.y * im, yi = alpha.x * im + alpha.y * re;
+          double2* y = Y + (col >> 1) * ldy + row;
+          if (accumulate) {
+            yr += y->x;
+            yi += y->y;
+          }
+          *y = make_double2(yr, yi);
+        }
+      }
+}
+
+// float64 storage: one wave per row, every lane keeps R/64 excitation sums in registers is not
+// practical for large R; instead loop over the columns of X in chunks of 4 (VALU).
+__global__ void __launch_bounds__(256) k_gemm_f64(const double2* __restrict__ A, int64_t lda, int64_t M, int64_t Kc,
+                                                  const double2* __restrict__ X, int64_t ldx, double2* __restrict__ Y,
+                                                  int64_t ldy, int64_t R, double2 alpha, int accumulate) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t row = int64_t(blockIdx.x) * 4 + wave;
+  if (row >= M) return;
+  const double2* a = A + row * lda;
+  for (int64_t r0 = 0; r0 < R; r0 += 4) {
+    double sr[4] = {0, 0, 0, 0}, si[4] = {0, 0, 0, 0};
+    for (int64_t k = lane; k < Kc; k += 64) {
+      const double2 av = a[k];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (r0 + q < R) {
+          const double2 x = X[(r0 + q) * ldx + k];
+          sr[q] += av.x * x.x - av.y * x.y;
+          si[q] += av.x * x.y + av.y * x.x;
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        sr[q] += __shfl_xor(sr[q], o, 64);
+        si[q] += __shfl_xor(si[q], o, 64);
+      }
+      if (lane == q && r0 + q < R) {
+        double yr = alpha.x * sr[q] - alpha.y * si[q], yi = alpha.x * si[q] + alpha.y * sr[q];
+        double2* y = Y + (r0 + q) * ldy + row;
+        if (accumulate) {
+          yr += y->x;
+          yi += y->y;
+        }
+        *y = make_double2(yr, yi);
+      }
+    }
+  }
+}
+
+}  // namespace dev
+
+size_t gemm_workspace_bytes(int64_t cols, int64_t nrhs) {
+  const int64_t K16 = (2 * cols + dev::BK - 1) / dev::BK * dev::BK;
+  const int64_t ldb = (2 * nrhs + dev::BN - 1) / dev::BN * dev::BN;
+  return size_t(K16) * ldb * sizeof(float);
+}
+
+void launch_gemm(const GemmDesc& d, void* ws, size_t ws_bytes, hipStream_t st) {
+  if (d.rows <= 0 || d.nrhs <= 0) return;
+  if (!d.fp32) {
+    ProfScope ps(st, KC_GEMV_F64, double(d.rows) * d.cols * 16.0, 8.0 * d.rows * d.cols * d.nrhs);
+    hipLaunchKernelGGL(dev::k_gemm_f64, dim3(unsigned((d.rows + 3) / 4)), dim3(256), 0, st,
+                       static_cast<const double2*>(d.A), d.lda, d.rows, d.cols, d.X, d.ldx, d.Y, d.ldy, d.nrhs,
+                       d.alpha, d.accumulate);
+    BEM_HIP(hipGetLastError());
+    return;
+  }
+  const int64_t K = 2 * d.cols;
+  const int64_t K16 = (K + dev::BK - 1) / dev::BK * dev::BK;
+  const int64_t ldb = (2 * d.nrhs + dev::BN - 1) / dev::BN * dev::BN;
+  if (size_t(K16) * ldb * sizeof(float) > ws_bytes) throw Error(BEM_E_INVALID, "GEMM workspace too small");
+  float* Bm = static_cast<float*>(ws);
+  hipLaunchKernelGGL(dev::k_build_B, dim3(unsigned((ldb + 255) / 256), unsigned(K16)), dim3(256), 0, st, d.X, d.ldx,
+                     d.cols, d.nrhs, Bm, ldb, K16);
+  BEM_HIP(hipGetLastError());
+  const int64_t ntm = (d.rows + dev::BM - 1) / dev::BM, ntn = ldb / dev::BN;
+  const float* A = static_cast<const float*>(d.A);
+  const int64_t lda = 2 * d.lda;
+  const bool aligned = ((reinterpret_cast<uintptr_t>(A) | uintptr_t(lda * 4)) & 15) == 0;
+  ProfScope ps(st, KC_GEMM_F32, double(d.rows) * d.cols * 8.0, 8.0 * double(d.rows) * d.cols * d.nrhs);
+  if (aligned)
+    hipLaunchKernelGGL(dev::k_gemm_f32<true>, dim3(unsigned(ntm * ntn)), dim3(256), 0, st, A, lda, Bm, ldb, d.rows, K,
+                       K16, ntn, d.Y, d.ldy, d.nrhs, d.alpha, d.accumulate);
+  else
+    hipLaunchKernelGGL(dev::k_gemm_f32<false>, dim3(unsigned(ntm * ntn)), dim3(256), 0, st, A, lda, Bm, ldb, d.rows,
+                       K, K16, ntn, d.Y, d.ldy, d.nrhs, d.alpha, d.accumulate);
+  BEM_HIP(hipGetLastError());
+}
+
+}  // namespace bem

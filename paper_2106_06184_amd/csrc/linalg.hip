@@ -10,6 +10,7 @@
 #include <algorithm>
 
 #include "linalg.h"
+#include "prof.h"
 
 namespace bem {
 namespace dev {
@@ -432,6 +433,10 @@ void launch_gemv_grouped(const GemvDesc* host_descs, int n, hipStream_t st) {
       tiles += (pack.d[i].rows + dev::kRowsPerBlock - 1) / dev::kRowsPerBlock;
     }
     if (tiles == 0) continue;
+    double bytes = 0;
+    for (int i = 0; i < pack.n; ++i)
+      bytes += double(pack.d[i].rows) * pack.d[i].cols * (pack.d[i].fp32 ? 8.0 : 16.0) * (pack.d[i].A2 ? 2 : 1);
+    ProfScope ps(st, pack.d[0].fp32 ? KC_GEMV_F32 : KC_GEMV_F64, bytes, bytes / (pack.d[0].fp32 ? 8.0 : 16.0));
     hipLaunchKernelGGL(dev::k_gemv_grouped, dim3(unsigned(tiles)), dim3(256), 0, st, pack);
     BEM_HIP(hipGetLastError());
   }

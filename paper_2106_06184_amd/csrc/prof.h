@@ -1,0 +1,69 @@
+// Opt-in per-kernel-class timing: HIP events recorded around launches on their own stream,
+// with the algorithmic bytes (or work units) of every launch.  Disabled by default; the events
+// are harvested at the library's own stream synchronisation points.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <mutex>
+#include <vector>
+
+namespace bem {
+
+enum KernelClass : int {
+  KC_GEMV_F64 = 0,   // dense complex products, float64 storage (bytes = matrix bytes read)
+  KC_GEMV_F32 = 1,   // dense complex products, float32 storage
+  KC_FILL_L = 2,     // far L^A/L^phi fill (work = Green's-function evaluations, bytes = written)
+  KC_FILL_K = 3,     // far K~ fill (work = gradient evaluations, bytes = written)
+  KC_FILL_NEAR = 4,  // near-pair singular corrections
+  KC_GATHER = 5,     // half-RWG / cell to edge gathers (bytes = read + written)
+  KC_GEMM_F32 = 6,   // multi-excitation products on matrix cores (work = real flops)
+  KC_COUNT = 7
+};
+
+struct ClassStats {
+  long long launches = 0;
+  double ms = 0, bytes = 0, work = 0;
+};
+
+class Profiler {
+ public:
+  static Profiler& get();
+  bool enabled() const { return on_; }
+  void enable(bool on);
+  // Record an event pair around a launch issued between begin() and end().
+  void begin(hipStream_t st);
+  void end(hipStream_t st, int cls, double bytes, double work);
+  void harvest(bool wait);
+  ClassStats read(int cls);
+
+ private:
+  struct Pending {
+    hipEvent_t a, b;
+    int cls;
+    double bytes, work;
+  };
+  hipEvent_t take();
+  std::mutex mu_;
+  bool on_ = false;
+  std::vector<hipEvent_t> pool_;
+  std::vector<Pending> pending_;
+  ClassStats stats_[KC_COUNT];
+};
+
+// RAII helper for a single launch.
+struct ProfScope {
+  hipStream_t st;
+  int cls;
+  double bytes, work;
+  bool on;
+  ProfScope(hipStream_t s, int c, double b, double w) : st(s), cls(c), bytes(b), work(w) {
+    on = Profiler::get().enabled();
+    if (on) Profiler::get().begin(st);
+  }
+  ~ProfScope() {
+    if (on) Profiler::get().end(st, cls, bytes, work);
+  }
+};
+
+}  // namespace bem

@@ -17,8 +17,11 @@
 #include <map>
 
 #include "ctx.h"
+#include "dense.h"
 
 namespace bem {
+
+void build_inner_and_precond(OpObj& op, const std::vector<double>& ixdiag, hipStream_t st);
 
 namespace {
 
@@ -90,6 +93,15 @@ void add_second(GemvDesc& d, const Dense& A, bool fp32, int64_t roff, int64_t co
 }
 
 }  // namespace
+
+// BEM_VERBOSE=1 prints one line per GMRES iteration (outer) and per nested solve to stderr.
+static bool verbose() {
+  static const bool v = [] {
+    const char* e = std::getenv("BEM_VERBOSE");
+    return e && *e && *e != '0';
+  }();
+  return v;
+}
 
 // ----------------------------------------------------------------- arena / ctx
 
@@ -226,6 +238,7 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
   op.eps_inv_edge = op.mem.upload(einv);
 
   // ---- Gram matrix I_x: int (n x f_m) . g_n dS, exact with the 3-point rule on every sub-triangle
+  std::vector<double> ixdiag(m.ne, 0.0);
   {
     std::vector<std::map<int32_t, double>> rows(m.ne);
     const int64_t nc = cdat.ncell;
@@ -273,6 +286,7 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
       for (auto& kv : rows[r]) {
         idx.push_back(kv.first);
         val.push_back(kv.second);
+        if (kv.first == r) ixdiag[r] = kv.second;
       }
       ptr[r + 1] = int64_t(idx.size());
     }
@@ -416,6 +430,13 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
   float ms = 0;
   BEM_HIP(hipEventElapsedTime(&ms, ev0, ev1));
   op.fill_seconds = ms * 1e-3;
+  op.fill_bytes = 16.0 * (double(m.ne) * m.ne + double(nt) * nt);
+  op.kernel_evals = 49.0 * double(nt) * nt;
+  for (int64_t o = 0; o < m.nobj; ++o) {
+    const double neo = double(m.obj_edge[o + 1] - m.obj_edge[o]), nto = double(m.obj_tri[o + 1] - m.obj_tri[o]);
+    op.fill_bytes += 16.0 * (3 * neo * neo + nto * nto);
+    op.kernel_evals += 49.0 * nto * nto + 2 * 126.0 * nto * nto;
+  }
   (void)hipEventDestroy(ev0);
   (void)hipEventDestroy(ev1);
   op.mem.release(H);
@@ -425,10 +446,160 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
                   (void*)d_cS, (void*)d_cT, (void*)d_near_ptr, (void*)d_near_idx})
     op.mem.release(p);
 
+  // ---- nested-solve mode and block preconditioners
+  int64_t max_neq = 0;
+  for (int64_t o = 0; o < m.nobj; ++o)
+    max_neq = std::max(max_neq, (m.obj_edge[o + 1] - m.obj_edge[o]) + (m.obj_tri[o + 1] - m.obj_tri[o]) - 1);
+  op.inner_mode = prob.inner_mode;
+  if (op.inner_mode == BEM_INNER_AUTO) op.inner_mode = max_neq <= 16384 ? BEM_INNER_DIRECT : BEM_INNER_GMRES;
+  if (op.inner_mode != BEM_INNER_DIRECT && op.inner_mode != BEM_INNER_GMRES)
+    throw Error(BEM_E_INVALID, "unknown inner_mode");
+  op.precond = prob.precond != 0;
+  build_inner_and_precond(op, ixdiag, st);
+
   // ---- work vectors and Krylov spaces
-  op.work_len = 4 * op.Neq + 6 * op.nt + 2 * op.ne + 2 * op.nq + 64;
+  op.work_len = 4 * op.Neq + 9 * op.nt + 4 * op.ne + 4 * op.nq + 64;
   op.work = op.mem.alloc<double2>(size_t(op.work_len));
-  op.inner_ws = make_gmres_work(op.mem, op.Neq, op.inner_restart);
+  if (op.inner_mode == BEM_INNER_GMRES) {
+    op.inner_ws = make_gmres_work(op.mem, op.Neq, op.inner_restart);
+    op.inner_ws->tag = nullptr;
+  }
+}
+
+// Direct inner solve (inverse of M_eq per object) and the block preconditioners: the per-edge
+// 2x2 inverses and the charge Schur complements of eq. pcext (final system) and of its
+// equivalent-configuration counterpart, both inverted on the device.
+void build_inner_and_precond(OpObj& op, const std::vector<double>& ixdiag, hipStream_t st) {
+  const Mesh& m = *op.m;
+  const bool f32 = op.precision == BEM_MIXED;
+  int64_t maxn = 0;
+  for (int64_t o = 0; o < m.nobj; ++o)
+    maxn = std::max(maxn, (m.obj_edge[o + 1] - m.obj_edge[o]) + (m.obj_tri[o + 1] - m.obj_tri[o]) - 1);
+  DenseScratch ds{};
+  std::vector<void*> tmp;
+  auto talloc = [&](size_t n) {
+    double2* p = op.mem.alloc<double2>(n);
+    tmp.push_back(p);
+    return p;
+  };
+  ds.P = talloc(64 * 64);
+  ds.R = talloc(size_t(64) * maxn);
+  ds.C = talloc(size_t(64) * maxn);
+  auto diag_of = [&](const Dense& A) {
+    std::vector<double2> d(A.rows);
+    BEM_HIP(hipMemcpy2D(d.data(), sizeof(double2), A.d64, (A.ld + 1) * sizeof(double2), sizeof(double2), A.rows,
+                        hipMemcpyDeviceToHost));
+    return d;
+  };
+  auto cdv = [](double2 v) { return cd(v.x, v.y); };
+  op.Minv.clear();
+  if (op.inner_mode == BEM_INNER_DIRECT) {
+    for (int64_t o = 0; o < m.nobj; ++o) {
+      const int64_t t0 = m.obj_tri[o], nto = m.obj_tri[o + 1] - t0;
+      const int64_t e0 = m.obj_edge[o], neo = m.obj_edge[o + 1] - e0;
+      const int64_t n = neo + nto - 1;
+      std::vector<int32_t> tpl(neo), tml(neo);
+      for (int64_t k = 0; k < neo; ++k) {
+        tpl[k] = int32_t(m.tp[e0 + k] - t0);
+        tml[k] = int32_t(m.tm[e0 + k] - t0);
+      }
+      int32_t* dtp = op.mem.upload(tpl);
+      int32_t* dtm = op.mem.upload(tml);
+      Dense M = alloc_dense(op.mem, n, n, f32);
+      build_meq(op.LA_bg.d64 + e0 * op.LA_bg.ld + e0, op.LA_bg.ld, op.Lphi_bg.d64 + t0 * op.Lphi_bg.ld + t0,
+                op.Lphi_bg.ld, dtp, dtm, neo, nto, c2(op.mu_bg), c2(-1.0 / op.eps_bg), op.k0 * op.k0, M.d64, M.ld, st);
+      dense_invert(M.d64, n, M.ld, ds, st);
+      to_f32(M, st);
+      BEM_HIP(hipStreamSynchronize(st));
+      op.mem.release(dtp);
+      op.mem.release(dtm);
+      op.Minv.push_back(M);
+    }
+  }
+  op.SigP.clear();
+  op.SigEq.clear();
+  if (!op.precond) {
+    for (void* p : tmp) op.mem.release(p);
+    return;
+  }
+  // diagonals of the dense blocks
+  std::vector<double2> dLAbg = diag_of(op.LA_bg), dLpbg = diag_of(op.Lphi_bg);
+  std::vector<double2> dLAint(m.ne), dKint(m.ne), dLpint(m.nt);
+  for (int64_t o = 0; o < m.nobj; ++o) {
+    auto a = diag_of(op.LA_int[o]), k = diag_of(op.K_int[o]), p = diag_of(op.Lphi_int[o]);
+    std::copy(a.begin(), a.end(), dLAint.begin() + m.obj_edge[o]);
+    std::copy(k.begin(), k.end(), dKint.begin() + m.obj_edge[o]);
+    std::copy(p.begin(), p.end(), dLpint.begin() + m.obj_tri[o]);
+  }
+  const cd inv_epsl = 1.0 / op.eps_bg;
+  // per-edge 2x2 diagonal block of P and its inverse
+  std::vector<double2> W(4 * m.ne), eqd(m.ne);
+  for (int64_t n = 0; n < m.ne; ++n) {
+    const int o = m.obj[m.tp[n]];
+    const cd l11 = op.mu_bg * cdv(dLAbg[n]), l12 = ixdiag[n];
+    const cd l21 = op.mur[o] * cdv(dLAint[n]), l22 = -(cdv(dKint[n]) + 0.5 * ixdiag[n]);
+    const cd det = l11 * l22 - l12 * l21;
+    W[4 * n] = c2(l22 / det);
+    W[4 * n + 1] = c2(-l12 / det);
+    W[4 * n + 2] = c2(-l21 / det);
+    W[4 * n + 3] = c2(l11 / det);
+    eqd[n] = c2(1.0 / (op.mu_bg * cdv(dLAbg[n])));
+  }
+  op.pcW = op.mem.upload(W);
+  op.eq_d = op.mem.upload(eqd);
+  op.lam_bg = op.mem.upload(dLpbg);
+  op.lam_int = op.mem.upload(dLpint);
+  // charge Schur complements, per object (local numbering)
+  for (int64_t o = 0; o < m.nobj; ++o) {
+    const int64_t t0 = m.obj_tri[o], nto = m.obj_tri[o + 1] - t0, nq = nto - 1;
+    const cd inv_epsc = 1.0 / op.epsc[o];
+    for (int which = 0; which < 2; ++which) {
+      if (which == 1 && op.inner_mode != BEM_INNER_GMRES) break;
+      // G[q][t] = sum over the edges n of triangle q: D[q][n] D[t][n] c_n(t), t in {T+(n), T-(n)}
+      std::vector<int64_t> ptr(nq + 1, 0);
+      std::vector<int32_t> idx;
+      std::vector<double2> val;
+      for (int64_t q = 0; q < nq; ++q) {
+        const int64_t tq = t0 + q;
+        std::map<int32_t, cd> row;
+        for (int i = 0; i < 3; ++i) {
+          const int32_t n = m.tri_edge[3 * tq + i];
+          const double s = m.tri_sign[3 * tq + i];
+          for (int side = 0; side < 2; ++side) {
+            const int32_t t = side == 0 ? m.tp[n] : m.tm[n];
+            const double dt = side == 0 ? 1.0 : -1.0;
+            cd c;
+            if (which == 0) {
+              c = cdv(W[4 * n]) * inv_epsl * cdv(dLpbg[t]) + cdv(W[4 * n + 1]) * inv_epsc * cdv(dLpint[t]);
+              c = -c;  // Sigma_P = k0^2 I - G B
+            } else {
+              c = cdv(eqd[n]) * inv_epsl * cdv(dLpbg[t]);  // Sigma_eq = G B - k0^2 I
+            }
+            row[int32_t(t - t0)] += s * dt * c;
+          }
+        }
+        for (auto& kv : row) {
+          idx.push_back(kv.first);
+          val.push_back(c2(kv.second));
+        }
+        ptr[q + 1] = int64_t(idx.size());
+      }
+      int64_t* dptr = op.mem.upload(ptr);
+      int32_t* didx = op.mem.upload(idx);
+      double2* dval = op.mem.upload(val);
+      Dense S = alloc_dense(op.mem, nq, nq, f32);
+      const double k02 = op.k0 * op.k0;
+      build_schur(dptr, didx, dval, nq, nto - 1, which == 0 ? c2(k02) : c2(-k02), S.d64, S.ld, st);
+      dense_invert(S.d64, nq, S.ld, ds, st);
+      to_f32(S, st);
+      BEM_HIP(hipStreamSynchronize(st));
+      op.mem.release(dptr);
+      op.mem.release(didx);
+      op.mem.release(dval);
+      (which == 0 ? op.SigP : op.SigEq).push_back(S);
+    }
+  }
+  for (void* p : tmp) op.mem.release(p);
 }
 
 // ----------------------------------------------------------------- products
@@ -437,6 +608,7 @@ namespace {
 // work vector layout
 struct WorkView {
   double2 *rin, *sol, *t1, *z1, *z2, *am, *xw, *mt, *mz;
+  double2 *pc_t, *pc_z, *pc_v, *eq_t, *eq_z, *eq_v;
 };
 WorkView views(OpObj& op) {
   double2* p = op.work;
@@ -450,8 +622,56 @@ WorkView views(OpObj& op) {
   v.xw = p; p += op.nq;
   v.mt = p; p += op.nt;
   v.mz = p; p += op.nt;
+  v.pc_t = p; p += op.ne;
+  v.pc_z = p; p += op.nq;
+  v.pc_v = p; p += op.nt;
+  v.eq_t = p; p += op.ne;
+  v.eq_z = p; p += op.nq;
+  v.eq_v = p; p += op.nt;
   return v;
 }
+}  // namespace
+
+// Block preconditioner of the final system (eq. pcext) applied to r = [r1; r2; r3]:
+//   x3 = Sigma_P^-1 (r3 - F D (W11 r1 + W12 r2)),  [x1; x2] = W ([r1; r2] - [S1; S2] x3)
+void apply_precond(OpObj& op, const double2* r, double2* x, bool fp32, hipStream_t st) {
+  WorkView wv = views(op);
+  const int64_t ne = op.ne;
+  const double2 *r1 = r, *r2 = r + ne, *r3 = r + 2 * ne;
+  double2 *x1 = x, *x2 = x + ne, *x3 = x + 2 * ne;
+  launch_pc_stage1(op.pcW, r1, r2, ne, wv.pc_t, st);
+  launch_FD(wv.pc_t, op.tri_edge, op.tri_sign, op.kept, op.nq, c2(-1.0), r3, c2(1.0), wv.pc_z, st);
+  std::vector<GemvDesc> ds;
+  for (int64_t o = 0; o < op.nobj; ++o) {
+    const int64_t q0 = op.obj_q[o], nq = op.obj_q[o + 1] - q0;
+    ds.push_back(desc(op.SigP[o], fp32, 0, 0, nq, nq, wv.pc_z + q0, x3 + q0, c2(1.0), 0));
+  }
+  launch_gemv_grouped(ds.data(), int(ds.size()), st);
+  launch_expand_charge(x3, wv.pc_v, op.obj_tri_d, op.nobj, c2(1.0), st);
+  launch_pc_stage2(op.pcW, r1, r2, wv.pc_v, op.lam_bg, op.lam_int, c2(1.0 / op.eps_bg), op.eps_inv_edge, op.tp,
+                   op.tm, ne, x1, x2, st);
+}
+
+// Equivalent-configuration counterpart for the nested GMRES (diagonal L blocks, exact charge
+// constraint): x2 = Sigma_eq^-1 (r2 - F D d r1), x1 = d (r1 + eps_l^-1 D^T diag(L^phi_l) B x2)
+void apply_precond_eq(OpObj& op, const double2* r, double2* x, bool fp32, hipStream_t st) {
+  WorkView wv = views(op);
+  const int64_t ne = op.ne;
+  const double2 *r1 = r, *r2 = r + ne;
+  double2 *x1 = x, *x2 = x + ne;
+  launch_peq_stage1(op.eq_d, r1, ne, wv.eq_t, st);
+  launch_FD(wv.eq_t, op.tri_edge, op.tri_sign, op.kept, op.nq, c2(-1.0), r2, c2(1.0), wv.eq_z, st);
+  std::vector<GemvDesc> ds;
+  for (int64_t o = 0; o < op.nobj; ++o) {
+    const int64_t q0 = op.obj_q[o], nq = op.obj_q[o + 1] - q0;
+    ds.push_back(desc(op.SigEq[o], fp32, 0, 0, nq, nq, wv.eq_z + q0, x2 + q0, c2(1.0), 0));
+  }
+  launch_gemv_grouped(ds.data(), int(ds.size()), st);
+  launch_expand_charge(x2, wv.eq_v, op.obj_tri_d, op.nobj, c2(1.0), st);
+  launch_peq_stage2(op.eq_d, wv.eq_t, wv.eq_v, op.lam_bg, c2(1.0 / op.eps_bg), op.tp, op.tm, ne, x1, st);
+}
+
+namespace {
 }  // namespace
 
 // Equivalent-configuration matrix (eq. AEFIEeqvdis), block-diagonal over objects:
@@ -503,11 +723,27 @@ void apply_final(OpObj& op, const double2* x, double2* y, bool fp32, double inne
   launch_spmv(op.ix_ptr, op.ix_idx, op.ix_val, ne, e, c2(-0.5), y2, 1, st);
   launch_DT(wv.z1, op.tp, op.tm, ne, c2(1.0), op.eps_inv_edge, y2, 1, st);
   // nested solve M_eq [u; w] = [r_in; 0]
-  launch_axpby(nq, c2(0.0), nullptr, c2(0.0), nullptr, wv.rin + ne, st);
-  ApplyFn meq = [&op, fp32, st](const double2* xi, double2* yi) { apply_meq(op, xi, yi, fp32, st); };
-  GmresResult gr = gmres(*op.inner_ws, op.pinned, meq, wv.rin, wv.sol, true, inner_tol, op.inner_maxit, st);
-  op.last_inner_iters = gr.iters;
-  op.max_inner_iters = std::max(op.max_inner_iters, gr.iters);
+  if (op.inner_mode == BEM_INNER_DIRECT) {
+    // [u_o; w_o] = M_eq,o^-1 [r_in,o; 0]: only the edge columns of the inverse are read
+    std::vector<GemvDesc> di;
+    for (int64_t o = 0; o < op.nobj; ++o) {
+      const int64_t e0 = op.obj_edge[o], neo = op.obj_edge[o + 1] - e0;
+      const int64_t q0 = op.obj_q[o], nqo = op.obj_q[o + 1] - q0;
+      di.push_back(desc(op.Minv[o], fp32, 0, 0, neo, neo, wv.rin + e0, wv.sol + e0, c2(1.0), 0));
+      di.push_back(desc(op.Minv[o], fp32, neo, 0, nqo, neo, wv.rin + e0, wv.sol + ne + q0, c2(1.0), 0));
+    }
+    launch_gemv_grouped(di.data(), int(di.size()), st);
+    op.last_inner_iters = 0;
+  } else {
+    launch_axpby(nq, c2(0.0), nullptr, c2(0.0), nullptr, wv.rin + ne, st);
+    ApplyFn meq = [&op, fp32, st](const double2* xi, double2* yi) { apply_meq(op, xi, yi, fp32, st); };
+    ApplyFn peq = [&op, fp32, st](const double2* xi, double2* yi) { apply_precond_eq(op, xi, yi, fp32, st); };
+    GmresResult gr = gmres(*op.inner_ws, op.pinned, meq, wv.rin, wv.sol, true, inner_tol, op.inner_maxit, st,
+                           op.precond ? &peq : nullptr);
+    op.last_inner_iters = gr.iters;
+    op.max_inner_iters = std::max(op.max_inner_iters, gr.iters);
+    if (verbose()) std::fprintf(stderr, "[bem] inner its %d res %.3e\n", gr.iters, gr.relres);
+  }
   const double2* u = wv.sol;
   const double2* w = wv.sol + ne;
   // a - u, x3 + w, B (x3 + w)
@@ -620,6 +856,8 @@ std::unique_ptr<GmresWork> make_gmres_work(DevArena& mem, int64_t n, int m) {
   w->g = mem.alloc<double2>(m + 2);
   w->y = mem.alloc<double2>(m + 1);
   w->h2 = mem.alloc<double2>(m + 2);
+  w->z = mem.alloc<double2>(size_t(w->ldv));
+  w->z2 = mem.alloc<double2>(size_t(w->ldv));
   w->nrm = mem.alloc<double2>(2);
   w->res = mem.alloc<double>(2);
   w->ks.partial = mem.alloc<double2>(1024);
@@ -634,7 +872,7 @@ static double read_scalar(double* pinned, const double* d, hipStream_t st) {
 }
 
 GmresResult gmres(GmresWork& w, double* ctx, const ApplyFn& A, const double2* b, double2* x, bool x_zero,
-                  double tol, int maxit, hipStream_t st) {
+                  double tol, int maxit, hipStream_t st, const ApplyFn* M) {
   GmresResult res;
   const int64_t n = w.n;
   const int64_t ldh = w.m + 2;
@@ -673,7 +911,12 @@ GmresResult gmres(GmresWork& w, double* ctx, const ApplyFn& A, const double2* b,
       double2* vj = w.V + int64_t(j) * w.ldv;
       double2* vn = w.V + int64_t(j + 1) * w.ldv;
       double2* Hcol = w.H + int64_t(j) * ldh;
-      A(vj, vn);
+      if (M) {
+        (*M)(vj, w.z);
+        A(w.z, vn);
+      } else {
+        A(vj, vn);
+      }
       // CGS2
       launch_mdot(w.V, w.ldv, j + 1, vn, n, Hcol, w.ks, st);
       launch_mupdate(w.V, w.ldv, j + 1, Hcol, -1.0, vn, n, st);
@@ -686,13 +929,23 @@ GmresResult gmres(GmresWork& w, double* ctx, const ApplyFn& A, const double2* b,
       const double r = read_scalar(ctx, w.res, st);
       if (!std::isfinite(r)) throw Error(BEM_E_NUMERIC, "non-finite Arnoldi residual");
       res.relres = r / bnorm;
+      if (verbose() && w.n > 0 && w.tag)
+        std::fprintf(stderr, "[bem] %s it %d res %.3e\n", w.tag, res.iters, res.relres);
       if (res.relres <= tol) {
         ++j;
         break;
       }
     }
     launch_backsolve(w.H, ldh, j, w.g, w.y, st);
-    launch_mupdate(w.V, w.ldv, j, w.y, +1.0, x, n, st);
+    if (M) {
+      // x += M (V y)
+      launch_axpby(n, c2(0.0), nullptr, c2(0.0), nullptr, w.z2, st);
+      launch_mupdate(w.V, w.ldv, j, w.y, +1.0, w.z2, n, st);
+      (*M)(w.z2, w.z);
+      launch_axpby(n, c2(1.0), x, c2(1.0), w.z, x, st);
+    } else {
+      launch_mupdate(w.V, w.ldv, j, w.y, +1.0, x, n, st);
+    }
     if (res.relres <= tol) {
       res.converged = true;
       break;
@@ -762,6 +1015,7 @@ int solve_op(OpObj& op, const bem_excitation* exc, int64_t nexc, const bem_solve
       BEM_HIP(hipMemcpyAsync(B + pw[i] * ne, Bpw + i * ne, sizeof(double2) * ne, hipMemcpyDeviceToDevice, st));
   }
   if (!op.outer_ws || op.outer_ws->m != opts.restart) op.outer_ws = make_gmres_work(op.mem, N, opts.restart);
+  op.outer_ws->tag = "outer";
   double2* bfull = tmp.alloc<double2>(N);
   double2* xs = tmp.alloc<double2>(N);
   double2* d = tmp.alloc<double2>(N);
@@ -776,11 +1030,14 @@ int solve_op(OpObj& op, const bem_excitation* exc, int64_t nexc, const bem_solve
     launch_axpby(N, c2(0.0), nullptr, c2(0.0), nullptr, bfull, st);
     BEM_HIP(hipMemcpyAsync(bfull, B + e * ne, sizeof(double2) * ne, hipMemcpyDeviceToDevice, st));
     ApplyFn A64 = [&op, inner, st](const double2* x, double2* y) { apply_final(op, x, y, false, inner, st); };
+    ApplyFn P64 = [&op, st](const double2* x, double2* y) { apply_precond(op, x, y, false, st); };
+    ApplyFn P32 = [&op, st](const double2* x, double2* y) { apply_precond(op, x, y, true, st); };
     double rel = 0;
     bool conv = false;
     int left = opts.maxit;
     if (op.precision == BEM_FP64) {
-      GmresResult g = gmres(*op.outer_ws, op.pinned,A64, bfull, xs, true, opts.tol, left, st);
+      GmresResult g = gmres(*op.outer_ws, op.pinned, A64, bfull, xs, true, opts.tol, left, st,
+                            op.precond ? &P64 : nullptr);
       inf.outer_iters += g.iters;
       inf.n_products += g.iters + 1;
       conv = g.converged;
@@ -795,7 +1052,7 @@ int solve_op(OpObj& op, const bem_excitation* exc, int64_t nexc, const bem_solve
       const int sweeps = opts.max_refine > 0 ? opts.max_refine : 5;
       for (int s = 0; s < sweeps && left > 0; ++s) {
         const double stol = std::max(opts.tol * 0.5, 1e-6);
-        GmresResult g = gmres(*op.outer_ws, op.pinned,A32, r, d, true, stol, left, st);
+        GmresResult g = gmres(*op.outer_ws, op.pinned, A32, r, d, true, stol, left, st, op.precond ? &P32 : nullptr);
         left -= g.iters;
         inf.outer_iters += g.iters;
         inf.n_products += g.iters + 1;

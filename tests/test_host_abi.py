@@ -1,0 +1,112 @@
+"""CPU tests of the C ABI and the library's host logic (no device compute).
+
+The library must load and export every function include/bem.h declares; a host-only
+context (device = -1) validates meshes and builds the topology, which is compared with the
+oracle's independently built one (edge table, T+/T-, near pairs) on several mesh families.
+"""
+from __future__ import annotations
+
+import re
+from pathlib import Path
+
+import numpy as np
+import pytest
+
+import meshgen
+import paper_2106_06184_amd as B
+from oracle import mesh as OM
+from oracle import operators as OO
+
+HEADER = Path(__file__).resolve().parent.parent / "include" / "bem.h"
+
+
+def test_library_exports_every_declared_symbol():
+    decl = set(re.findall(r"\b(bem_[a-z_0-9]+)\s*\(", HEADER.read_text()))
+    decl -= {"bem_ctx"}
+    assert decl, "no declarations parsed"
+    L = B.lib()
+    missing = [n for n in sorted(decl) if not hasattr(L, n)]
+    assert not missing, missing
+    assert set(B.SYMBOLS) == decl
+
+
+@pytest.fixture()
+def host_ctx():
+    c = B.bem_create(-1)
+    yield c
+    B.bem_destroy(c)
+
+
+MESHES = {
+    "ico2": lambda: meshgen.icosphere(2) + (None,),
+    "cube3": lambda: meshgen.cube(3) + (None,),
+    "ellipsoid_jitter": lambda: (lambda x, t: (meshgen.jitter(x, t, 0.02, 3), t, None))(
+        *meshgen.cubed_sphere(4, (1.0, 0.6, 0.4))),
+    "two_spheres": lambda: meshgen.merge([meshgen.icosphere(1), (meshgen.icosphere(1)[0] + [2.5, 0, 0],
+                                                                 meshgen.icosphere(1)[1])]),
+}
+
+
+@pytest.mark.parametrize("name", list(MESHES))
+def test_topology_matches_oracle(name, host_ctx):
+    xyz, tri, obj = MESHES[name]()
+    h = B.bem_mesh_load(host_ctx, xyz, tri, obj)
+    info = B.bem_mesh_info(host_ctx, h)
+    topo = OM.build_topology(xyz, tri, obj)
+    assert info["n_tri"] == len(tri) and info["n_edge"] == len(topo.edges)
+    assert info["n_obj"] == topo.n_obj
+    assert info["n_unknowns"] == 2 * len(topo.edges) + len(tri) - topo.n_obj
+    va, vb, tp, tm = B.bem_edge_table(host_ctx, h)
+    key = {(int(a), int(b)): i for i, (a, b) in enumerate(topo.edges)}
+    perm = np.array([key[(int(a), int(b))] for a, b in zip(va, vb)])
+    assert len(set(perm)) == len(perm)
+    assert np.array_equal(topo.tplus[perm], tp) and np.array_equal(topo.tminus[perm], tm)
+    ptr, idx = B.bem_near_pairs(host_ctx, h)
+    near = OO.near_pairs(topo)
+    lib_near = np.zeros_like(near)
+    for t in range(len(tri)):
+        lib_near[t, idx[ptr[t]:ptr[t + 1]]] = True
+    assert np.array_equal(lib_near, near)
+
+
+def test_invalid_meshes_rejected(host_ctx):
+    x, t = meshgen.icosphere(1)
+    cases = {
+        "open": (x, t[:-1]),
+        "flipped triangle": (x, np.concatenate([t[:1, [0, 2, 1]], t[1:]])),
+        "inward": (x, t[:, [0, 2, 1]]),
+        "degenerate": (np.concatenate([x, x[:1]]), np.concatenate([t, [[0, 0, 1]]])),
+    }
+    for lab, (xx, tt) in cases.items():
+        with pytest.raises(B.BemError) as e:
+            B.bem_mesh_load(host_ctx, xx, tt)
+        assert e.value.code == B.BEM_E_MESH, lab
+    bad = x.copy()
+    bad[3, 1] = np.nan
+    with pytest.raises(B.BemError) as e:
+        B.bem_mesh_load(host_ctx, bad, t)
+    assert e.value.code == B.BEM_E_NUMERIC
+    with pytest.raises(B.BemError) as e:
+        B.bem_mesh_load(host_ctx, x, t, obj=np.ones(len(t), np.int32))
+    assert e.value.code == B.BEM_E_MESH
+
+
+def test_host_context_refuses_device_work(host_ctx):
+    x, t = meshgen.icosphere(1)
+    h = B.bem_mesh_load(host_ctx, x, t)
+    with pytest.raises(B.BemError) as e:
+        B.bem_assemble(host_ctx, h, B.make_problem(1e8, [4.0], [1.0], [0.0]))
+    assert e.value.code == B.BEM_E_DEVICE
+    with pytest.raises(B.BemError) as e:
+        B.bem_release(host_ctx, 12345)
+    assert e.value.code == B.BEM_E_INVALID
+    B.bem_release(host_ctx, h)
+
+
+def test_last_error_is_per_call(host_ctx):
+    x, t = meshgen.icosphere(1)
+    with pytest.raises(B.BemError):
+        B.bem_mesh_load(host_ctx, x, t[:-1])
+    assert "open" in B.bem_last_error(host_ctx) or "edge" in B.bem_last_error(host_ctx)
+    B.bem_mesh_load(host_ctx, x, t)
+    assert B.bem_last_error(host_ctx) == ""
