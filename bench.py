@@ -94,6 +94,7 @@ def main() -> int:
     ap.add_argument("--inner", default="auto", choices=["auto", "gmres", "direct"])
     ap.add_argument("--no-precond", action="store_true")
     ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--restart", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -112,7 +113,7 @@ def main() -> int:
     precond = 0 if args.no_precond else 1
     ctx = B.bem_create(0)
     exc = B.plane_waves(w.khat, w.pol)
-    opts = B.solve_opts(tol=args.tol, restart=50, maxit=3000)
+    opts = B.solve_opts(tol=args.tol, restart=args.restart, maxit=3000)
 
     def step():
         mesh = B.bem_mesh_load(ctx, w.xyz, w.tri, w.obj)
@@ -144,10 +145,9 @@ def main() -> int:
             f"res {si.rel_residual:.2e}, fill {st['fill_seconds']*1e3:.1f} ms")
     torch.cuda.synchronize()
     total = time.perf_counter() - t_start
-    prof = {k: B.bem_profile_read(k) for k in range(7)}
+    prof = {k: B.bem_profile_read(k) for k in range(len(B.KC_NAMES))}
     B.bem_profile_enable(False)
-    names = {B.KC_GEMV_F64: "gemv_f64", B.KC_GEMV_F32: "gemv_f32", B.KC_FILL_L: "fill_L", B.KC_FILL_K: "fill_K",
-             B.KC_FILL_NEAR: "fill_near", B.KC_GATHER: "gather", B.KC_GEMM_F32: "gemm_f32_mfma"}
+    names = dict(enumerate(B.KC_NAMES))
     for k, p in prof.items():
         log(f"  {names[k]:14s} launches {p['launches']:7d}  {p['ms']:10.2f} ms  "
             f"{(p['bytes'] / p['ms'] / 1e6 if p['ms'] > 0 else 0):8.1f} GB/s")
@@ -162,6 +162,10 @@ def main() -> int:
         achieved = p["work"] / (p["ms"] * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": achieved, "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / FP32_MFMA_PEAK_TFLOPS, "traffic": None}
+    elif dom == B.KC_DENSE_INV:
+        achieved = p["work"] / (p["ms"] * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None}
     else:
         # fill: ~ 64 float64 vector operations per kernel evaluation (see the design notes)
         achieved = p["work"] * 64 / (p["ms"] * 1e-3) / 1e12
@@ -180,7 +184,7 @@ def main() -> int:
         "ms_per_step": 1e3 * total / args.steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32+f64" if prec == B.BEM_MIXED else "f64", "data": "synthetic",
         "config": {"workload": w.name, "n_tri": info["n_tri"], "n_unknowns": info["n_unknowns"],
-                   "excitations": 1, "tol": args.tol, "precision": args.precision,
+                   "excitations": 1, "tol": args.tol, "restart": args.restart, "precision": args.precision,
                    "inner": args.inner, "precond": bool(precond)},
         "p50_s": p50, "p99_s": p99,
         "fill_GBps": st["fill_bytes"] / st["fill_seconds"] / 1e9,

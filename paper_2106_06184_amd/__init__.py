@@ -26,7 +26,8 @@ SYMBOLS = ["bem_create", "bem_destroy", "bem_last_error", "bem_mesh_load", "bem_
            "bem_near_pairs", "bem_assemble", "bem_apply", "bem_block_export", "bem_set_inner_tol", "bem_solve",
            "bem_submit", "bem_poll", "bem_drain", "bem_release", "bem_memory_in_use", "bem_op_stats_get",
            "bem_profile_enable", "bem_profile_read"]
-KC_GEMV_F64, KC_GEMV_F32, KC_FILL_L, KC_FILL_K, KC_FILL_NEAR, KC_GATHER, KC_GEMM_F32 = range(7)
+KC_GEMV_F64, KC_GEMV_F32, KC_FILL_L, KC_FILL_K, KC_FILL_NEAR, KC_GATHER, KC_GEMM_F32, KC_DENSE_INV = range(8)
+KC_NAMES = ["gemv_f64", "gemv_f32", "fill_L", "fill_K", "fill_near", "gather", "gemm_f32_mfma", "dense_inv_update"]
 
 
 class bem_op_stats(C.Structure):

@@ -16,8 +16,18 @@
 #include <algorithm>
 
 #include "dense.h"
+#include "prof.h"
 
 namespace bem {
+
+// BEM_DENSE_VALU=1 selects the plain VALU rank-b update instead of the matrix-core one.
+static bool dense_use_mfma() {
+  static const bool v = [] {
+    const char* e = std::getenv("BEM_DENSE_VALU");
+    return !(e && *e && *e != '0');
+  }();
+  return v;
+}
 namespace dev {
 
 constexpr int NB = 64;
@@ -153,6 +163,84 @@ __global__ void __launch_bounds__(256) k_gj_update(double2* __restrict__ A, int6
       *a = make_double2(a->x - acc[r][c].x, a->y - acc[r][c].y);
     }
   }
+}
+
+// Same update on the float64 matrix cores.  Real embedding of the complex product: the rows of
+// C (interleaved re/im, 2b reals) times the 2b x 2n real matrix with 2x2 blocks
+// [[Re R, Im R], [-Im R, Re R]] give the interleaved rows of C R.  Workgroup tile 64 x 64
+// complex (64 x 128 reals), four waves of 32 x 64 reals, MFMA 16x16x4 (float64), K staged
+// through LDS 32 reals at a time (A k-major so that operand reads are conflict-free).
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(256) k_gj_update_mfma(double* __restrict__ A, int64_t ld, int64_t n, int64_t k0,
+                                                        int b, const double2* __restrict__ R,
+                                                        const double2* __restrict__ Cp) {
+  constexpr int KC = 32;  // reals of K per stage
+  __shared__ double As[KC][64 + 1];
+  __shared__ double Bs[KC][128 + 2];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int64_t i0 = int64_t(blockIdx.y) * 64;  // complex rows
+  const int64_t j0 = int64_t(blockIdx.x) * 64;  // complex columns
+  doublex4 acc[2][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[a][c] = doublex4{0, 0, 0, 0};
+  const int K = 2 * b;
+  for (int k0r = 0; k0r < K; k0r += KC) {
+    // stage A: 64 rows x 32 reals (16 complex of C)
+    for (int e = tid; e < 64 * (KC / 2); e += 256) {
+      const int r = e / (KC / 2), s = e % (KC / 2);
+      const int64_t gi = i0 + r;
+      const int sc = k0r / 2 + s;
+      double2 v = make_double2(0, 0);
+      if (gi < n && sc < b) v = Cp[gi * NB + sc];
+      As[2 * s][r] = v.x;
+      As[2 * s + 1][r] = v.y;
+    }
+    // stage B: 32 reals of K (16 complex s) x 128 reals (64 complex j)
+    for (int e = tid; e < (KC / 2) * 64; e += 256) {
+      const int s = e / 64, c = e % 64;
+      const int64_t gj = j0 + c;
+      const int sc = k0r / 2 + s;
+      double2 v = make_double2(0, 0);
+      if (gj < n && sc < b) v = R[int64_t(sc) * n + gj];
+      Bs[2 * s][2 * c] = v.x;
+      Bs[2 * s][2 * c + 1] = v.y;
+      Bs[2 * s + 1][2 * c] = -v.y;
+      Bs[2 * s + 1][2 * c + 1] = v.x;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += 4) {
+      const int kr = kk + (lane >> 4);
+      double af[2], bf[4];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) af[a] = As[kr][wm * 32 + a * 16 + (lane & 15)];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) bf[c] = Bs[kr][wn * 64 + c * 16 + (lane & 15)];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[c], acc[a][c], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // epilogue: lane holds rows 4*(lane/16)+v, column lane%16 of every 16x16 real tile
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t gi = i0 + wm * 32 + a * 16 + 4 * (lane >> 4) + v;
+        const int64_t rc = 2 * j0 + wn * 64 + c * 16 + (lane & 15);  // real column
+        const int64_t gj = rc >> 1;
+        if (gi >= n || gj >= n) continue;
+        if ((gi >= k0 && gi < k0 + b) || (gj >= k0 && gj < k0 + b)) continue;
+        A[gi * 2 * ld + rc] -= acc[a][c][v];
+      }
 }
 
 // A[k0+s][j] = R[s][j] (j outside kb); A[i][k0+s] = -sum_t C[i][t] P[t][s] (i outside kb);
@@ -323,7 +411,14 @@ void dense_invert(double2* A, int64_t n, int64_t ld, DenseScratch& ws, hipStream
     hipLaunchKernelGGL(dev::k_gj_panels, dim3(unsigned((n + 63) / 64)), dim3(256), 0, st, A, ld, n, k0, b, ws.P,
                        ws.R, ws.C);
     dim3 g(unsigned((n + 63) / 64), unsigned((n + 63) / 64));
-    hipLaunchKernelGGL(dev::k_gj_update, g, dim3(256), 0, st, A, ld, n, k0, b, ws.R, ws.C);
+    {
+      ProfScope ps(st, KC_DENSE_INV, 32.0 * double(n) * n, 8.0 * double(n) * n * b);
+      if (dense_use_mfma())
+        hipLaunchKernelGGL(dev::k_gj_update_mfma, g, dim3(256), 0, st, reinterpret_cast<double*>(A), ld, n, k0, b,
+                           ws.R, ws.C);
+      else
+        hipLaunchKernelGGL(dev::k_gj_update, g, dim3(256), 0, st, A, ld, n, k0, b, ws.R, ws.C);
+    }
     hipLaunchKernelGGL(dev::k_gj_write, dim3(unsigned((n + 3) / 4)), dim3(256), 0, st, A, ld, n, k0, b, ws.P, ws.R,
                        ws.C);
   }
