@@ -66,7 +66,9 @@ enum {
   BEM_BLOCK_LPHI_BG = 5,  /* L^(phi) at k_l, NT x NT, all pairs */
   BEM_BLOCK_K_BG = 6,     /* K~ at k_l, NE x NE, block-diagonal */
   BEM_BLOCK_IX = 7,       /* Gram matrix I_x (BC tested with n x RWG), NE x NE, sparse */
-  BEM_BLOCK_MEQ = 8       /* equivalent-configuration matrix of eq. AEFIEeqvdis, (NE+NQ)^2 */
+  BEM_BLOCK_MEQ = 8,      /* equivalent-configuration matrix of eq. AEFIEeqvdis, (NE+NQ)^2 */
+  BEM_BLOCK_MEQ_INV = 9   /* its device inverse (direct nested solve only), (NE+NQ)^2,
+                             block-diagonal; ordering [edges; kept charges] per object */
 };
 
 /* Context.  device >= 0 selects a HIP device; device = -1 gives a host-only

@@ -35,13 +35,18 @@ void build_schur(const int64_t* ptr, const int32_t* idx, const double2* val, int
 //   stage 1: t[n] = w11 r1[n] + w12 r2[n]
 //   stage 2: s_b = e_b[n] (lb[T+] v[T+] - lb[T-] v[T-]), s_i likewise with li and e_i,
 //            x1 = w11 (r1 - s_b) + w12 (r2 - s_i),  x2 = w21 (r1 - s_b) + w22 (r2 - s_i)
-void launch_pc_stage1(const double2* W, const double2* r1, const double2* r2, int64_t ne, double2* t, hipStream_t st);
+// (R columns: r-vectors r1, r2, x1, x2 with column stride ldr, temporaries t, v with ldt.)
+void launch_pc_stage1(const double2* W, const double2* r1, const double2* r2, int64_t ne, double2* t, hipStream_t st,
+                      int R = 1, int64_t ldr = 0, int64_t ldt = 0);
 void launch_pc_stage2(const double2* W, const double2* r1, const double2* r2, const double2* v, const double2* lb,
                       const double2* li, double2 e_b, const double2* e_i, const int32_t* tp, const int32_t* tm,
-                      int64_t ne, double2* x1, double2* x2, hipStream_t st);
+                      int64_t ne, double2* x1, double2* x2, hipStream_t st, int R = 1, int64_t ldr = 0,
+                      int64_t ldt = 0);
 // Equivalent-configuration preconditioner: t = d r1 ; x1 = t + d e (lb[T+] v[T+] - lb[T-] v[T-])
-void launch_peq_stage1(const double2* d, const double2* r1, int64_t ne, double2* t, hipStream_t st);
+void launch_peq_stage1(const double2* d, const double2* r1, int64_t ne, double2* t, hipStream_t st, int R = 1,
+                       int64_t ldr = 0, int64_t ldt = 0);
 void launch_peq_stage2(const double2* d, const double2* t, const double2* v, const double2* lb, double2 e,
-                       const int32_t* tp, const int32_t* tm, int64_t ne, double2* x1, hipStream_t st);
+                       const int32_t* tp, const int32_t* tm, int64_t ne, double2* x1, hipStream_t st, int R = 1,
+                       int64_t ldr = 0, int64_t ldt = 0);
 
 }  // namespace bem

@@ -20,13 +20,11 @@
 
 namespace bem {
 
-// BEM_DENSE_VALU=1 selects the plain VALU rank-b update instead of the matrix-core one.
+// BEM_DENSE_VALU=1 selects the plain VALU rank-b update instead of the matrix-core one (read
+// at every inversion).
 static bool dense_use_mfma() {
-  static const bool v = [] {
-    const char* e = std::getenv("BEM_DENSE_VALU");
-    return !(e && *e && *e != '0');
-  }();
-  return v;
+  const char* e = std::getenv("BEM_DENSE_VALU");
+  return !(e && *e && *e != '0');
 }
 namespace dev {
 
@@ -227,14 +225,14 @@ __global__ void __launch_bounds__(256) k_gj_update_mfma(double* __restrict__ A, 
     }
     __syncthreads();
   }
-  // epilogue: lane holds rows 4*(lane/16)+v, column lane%16 of every 16x16 real tile
+  // epilogue: item v of lane l is row (l/16) + 4 v, column l%16 of every 16x16 real tile
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int c = 0; c < 4; ++c)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int64_t gi = i0 + wm * 32 + a * 16 + 4 * (lane >> 4) + v;
+        const int64_t gi = i0 + wm * 32 + a * 16 + (lane >> 4) + 4 * v;
         const int64_t rc = 2 * j0 + wn * 64 + c * 16 + (lane & 15);  // real column
         const int64_t gj = rc >> 1;
         if (gi >= n || gj >= n) continue;
@@ -331,75 +329,86 @@ __global__ void k_build_schur(const int64_t* __restrict__ ptr, const int32_t* __
 
 // ------------------------------------------------------------- preconditioners
 
+// Column r of the R-column batch: r-vectors (r1, r2, x1, x2) start at + r * ldr, temporaries
+// (t, v) at + r * ldt.
 __global__ void k_pc_stage1(const double2* __restrict__ W, const double2* __restrict__ r1, const double2* __restrict__ r2,
-                            int64_t ne, double2* __restrict__ t) {
+                            int64_t ne, double2* __restrict__ t, int64_t ldr, int64_t ldt) {
   const int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (n >= ne) return;
-  const double2 a = cm(W[4 * n], r1[n]), b = cm(W[4 * n + 1], r2[n]);
-  t[n] = make_double2(a.x + b.x, a.y + b.y);
+  const int64_t cr = int64_t(blockIdx.y) * ldr, ct = int64_t(blockIdx.y) * ldt;
+  const double2 a = cm(W[4 * n], r1[cr + n]), b = cm(W[4 * n + 1], r2[cr + n]);
+  t[ct + n] = make_double2(a.x + b.x, a.y + b.y);
 }
 
 __global__ void k_pc_stage2(const double2* __restrict__ W, const double2* __restrict__ r1, const double2* __restrict__ r2,
                             const double2* __restrict__ v, const double2* __restrict__ lb, const double2* __restrict__ li,
                             double2 e_b, const double2* __restrict__ e_i, const int32_t* __restrict__ tp,
                             const int32_t* __restrict__ tm, int64_t ne, double2* __restrict__ x1,
-                            double2* __restrict__ x2) {
+                            double2* __restrict__ x2, int64_t ldr, int64_t ldt) {
   const int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (n >= ne) return;
+  const int64_t cr = int64_t(blockIdx.y) * ldr, ct = int64_t(blockIdx.y) * ldt;
   const int32_t p = tp[n], m = tm[n];
-  const double2 vp = v[p], vm = v[m];
+  const double2 vp = v[ct + p], vm = v[ct + m];
   const double2 db = make_double2(cm(lb[p], vp).x - cm(lb[m], vm).x, cm(lb[p], vp).y - cm(lb[m], vm).y);
   const double2 di = make_double2(cm(li[p], vp).x - cm(li[m], vm).x, cm(li[p], vp).y - cm(li[m], vm).y);
   const double2 sb = cm(e_b, db), si = cm(e_i[n], di);
-  const double2 a = make_double2(r1[n].x - sb.x, r1[n].y - sb.y);
-  const double2 b = make_double2(r2[n].x - si.x, r2[n].y - si.y);
+  const double2 a = make_double2(r1[cr + n].x - sb.x, r1[cr + n].y - sb.y);
+  const double2 b = make_double2(r2[cr + n].x - si.x, r2[cr + n].y - si.y);
   const double2 u1 = cm(W[4 * n], a), u2 = cm(W[4 * n + 1], b), u3 = cm(W[4 * n + 2], a), u4 = cm(W[4 * n + 3], b);
-  x1[n] = make_double2(u1.x + u2.x, u1.y + u2.y);
-  x2[n] = make_double2(u3.x + u4.x, u3.y + u4.y);
+  x1[cr + n] = make_double2(u1.x + u2.x, u1.y + u2.y);
+  x2[cr + n] = make_double2(u3.x + u4.x, u3.y + u4.y);
 }
 
 __global__ void k_peq_stage1(const double2* __restrict__ d, const double2* __restrict__ r1, int64_t ne,
-                             double2* __restrict__ t) {
+                             double2* __restrict__ t, int64_t ldr, int64_t ldt) {
   const int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (n >= ne) return;
-  t[n] = cm(d[n], r1[n]);
+  t[int64_t(blockIdx.y) * ldt + n] = cm(d[n], r1[int64_t(blockIdx.y) * ldr + n]);
 }
 
 __global__ void k_peq_stage2(const double2* __restrict__ d, const double2* __restrict__ t, const double2* __restrict__ v,
                              const double2* __restrict__ lb, double2 e, const int32_t* __restrict__ tp,
-                             const int32_t* __restrict__ tm, int64_t ne, double2* __restrict__ x1) {
+                             const int32_t* __restrict__ tm, int64_t ne, double2* __restrict__ x1, int64_t ldr,
+                             int64_t ldt) {
   const int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (n >= ne) return;
+  const int64_t cr = int64_t(blockIdx.y) * ldr, ct = int64_t(blockIdx.y) * ldt;
   const int32_t p = tp[n], m = tm[n];
-  const double2 a = cm(lb[p], v[p]), b = cm(lb[m], v[m]);
+  const double2 a = cm(lb[p], v[ct + p]), b = cm(lb[m], v[ct + m]);
   const double2 s = cm(cm(d[n], e), make_double2(a.x - b.x, a.y - b.y));
-  x1[n] = make_double2(t[n].x + s.x, t[n].y + s.y);
+  x1[cr + n] = make_double2(t[ct + n].x + s.x, t[ct + n].y + s.y);
 }
 
 }  // namespace dev
 
-void launch_pc_stage1(const double2* W, const double2* r1, const double2* r2, int64_t ne, double2* t, hipStream_t st) {
-  hipLaunchKernelGGL(dev::k_pc_stage1, dim3(unsigned((ne + 255) / 256)), dim3(256), 0, st, W, r1, r2, ne, t);
+void launch_pc_stage1(const double2* W, const double2* r1, const double2* r2, int64_t ne, double2* t, hipStream_t st,
+                      int R, int64_t ldr, int64_t ldt) {
+  hipLaunchKernelGGL(dev::k_pc_stage1, dim3(unsigned((ne + 255) / 256), unsigned(R)), dim3(256), 0, st, W, r1, r2, ne,
+                     t, ldr, ldt);
   BEM_HIP(hipGetLastError());
 }
 
 void launch_pc_stage2(const double2* W, const double2* r1, const double2* r2, const double2* v, const double2* lb,
                       const double2* li, double2 e_b, const double2* e_i, const int32_t* tp, const int32_t* tm,
-                      int64_t ne, double2* x1, double2* x2, hipStream_t st) {
-  hipLaunchKernelGGL(dev::k_pc_stage2, dim3(unsigned((ne + 255) / 256)), dim3(256), 0, st, W, r1, r2, v, lb, li, e_b,
-                     e_i, tp, tm, ne, x1, x2);
+                      int64_t ne, double2* x1, double2* x2, hipStream_t st, int R, int64_t ldr, int64_t ldt) {
+  hipLaunchKernelGGL(dev::k_pc_stage2, dim3(unsigned((ne + 255) / 256), unsigned(R)), dim3(256), 0, st, W, r1, r2, v,
+                     lb, li, e_b, e_i, tp, tm, ne, x1, x2, ldr, ldt);
   BEM_HIP(hipGetLastError());
 }
 
-void launch_peq_stage1(const double2* d, const double2* r1, int64_t ne, double2* t, hipStream_t st) {
-  hipLaunchKernelGGL(dev::k_peq_stage1, dim3(unsigned((ne + 255) / 256)), dim3(256), 0, st, d, r1, ne, t);
+void launch_peq_stage1(const double2* d, const double2* r1, int64_t ne, double2* t, hipStream_t st, int R,
+                       int64_t ldr, int64_t ldt) {
+  hipLaunchKernelGGL(dev::k_peq_stage1, dim3(unsigned((ne + 255) / 256), unsigned(R)), dim3(256), 0, st, d, r1, ne, t,
+                     ldr, ldt);
   BEM_HIP(hipGetLastError());
 }
 
 void launch_peq_stage2(const double2* d, const double2* t, const double2* v, const double2* lb, double2 e,
-                       const int32_t* tp, const int32_t* tm, int64_t ne, double2* x1, hipStream_t st) {
-  hipLaunchKernelGGL(dev::k_peq_stage2, dim3(unsigned((ne + 255) / 256)), dim3(256), 0, st, d, t, v, lb, e, tp, tm, ne,
-                     x1);
+                       const int32_t* tp, const int32_t* tm, int64_t ne, double2* x1, hipStream_t st, int R,
+                       int64_t ldr, int64_t ldt) {
+  hipLaunchKernelGGL(dev::k_peq_stage2, dim3(unsigned((ne + 255) / 256), unsigned(R)), dim3(256), 0, st, d, t, v, lb, e,
+                     tp, tm, ne, x1, ldr, ldt);
   BEM_HIP(hipGetLastError());
 }
 

@@ -21,6 +21,7 @@ struct GemvDesc {
   int accumulate;     // 0: y = ... ; 1: y += ...
   int fp32;           // storage of A (and A2)
   int64_t tile0;      // first row tile of this descriptor (filled by the launcher)
+  int64_t ldx, ldx2, ldy;  // column strides of x, x2, y for multi-column products
 };
 constexpr int kMaxGroup = 8;
 struct GemvPack {
@@ -47,24 +48,60 @@ struct GemmDesc {
   int fp32;
 };
 void launch_gemm(const GemmDesc& d, void* ws, size_t ws_bytes, hipStream_t st);
+// Runs the descriptors for R columns: R = 1 -> one grouped GEMV launch; R > 1 -> one matrix-core
+// GEMM per descriptor (float32 or float64 storage), using ws (gemm_workspace_bytes) for the
+// real-embedded right-hand sides.
+void launch_products(const std::vector<GemvDesc>& ds, int R, void* ws, size_t ws_bytes, hipStream_t st);
 
-// ---- sparse glue (float64 complex vectors)
+// ---- batched Krylov kernels (R independent Krylov spaces; vector i of column r at
+//      V + (i * R + r) * ldv; per-column Hessenberg at H + r * hs, column j at + j * ldh)
+struct BatchKrylov {
+  int R;
+  int64_t n, ldv, hs, ldh;
+  double2 *V, *H, *cs, *sn, *g, *y, *h2;  // cs/sn/y: stride m+1, g/h2: stride m+2
+  int m;
+  double* res;       // R
+  double* part;      // R * 128
+  int* jr;           // R (per-column Arnoldi length for the back-solve / update)
+};
+void launch_bmdot(const BatchKrylov& k, int j, const double2* W, int64_t ldw, double2* h, int64_t hstride,
+                  hipStream_t st);
+void launch_bmupdate(const BatchKrylov& k, int j, const int* jr, const double2* h, int64_t hstride, double sign,
+                     double2* W, int64_t ldw, hipStream_t st);
+void launch_bnorm(const BatchKrylov& k, const double2* W, int64_t ldw, double2* out, int64_t ostride, hipStream_t st);
+void launch_bscale_inv(const BatchKrylov& k, double2* W, int64_t ldw, const double2* nrm, int64_t nstride,
+                       hipStream_t st);
+void launch_bgivens(const BatchKrylov& k, int j, hipStream_t st);
+void launch_bbacksolve(const BatchKrylov& k, hipStream_t st);
+void launch_binit_g(const BatchKrylov& k, const double2* beta, int64_t bstride, hipStream_t st);
+// X[:, idx[c]] += U[:, c] for c < R (scatter of compacted columns)
+void launch_scatter_add(const double2* U, int64_t ldu, double2* X, int64_t ldx, const int* idx, int64_t n, int R,
+                        hipStream_t st);
+// U[:, c] = X[:, idx[c]]
+void launch_gather_cols(const double2* X, int64_t ldx, double2* U, int64_t ldu, const int* idx, int64_t n, int R,
+                        hipStream_t st);
+
+// ---- sparse glue (float64 complex vectors).  Every launcher processes R columns (grid.y),
+// column r of an argument starting at pointer + r * ld (ld unused when R = 1).
 // Charges: full[t] (per triangle) from reduced w (kept triangles); the last triangle of each
-// object gets minus the sum of the object's other charges.  kept_of[t] = index into w or -1.
+// object gets minus the sum of the object's other charges.
 void launch_expand_charge(const double2* w, double2* full, const int64_t* obj_tri, int64_t nobj,
-                          double2 scale, hipStream_t st);
+                          double2 scale, hipStream_t st, int R = 1, int64_t ldw = 0, int64_t ldf = 0);
 // y[n] (+)= s * sedge[n] * (z[T+(n)] - z[T-(n)])      (D^T z; sedge may be null)
 void launch_DT(const double2* z, const int32_t* tp, const int32_t* tm, int64_t ne, double2 s, const double2* sedge,
-               double2* y, int accumulate, hipStream_t st);
+               double2* y, int accumulate, hipStream_t st, int R = 1, int64_t ldz = 0, int64_t ldy = 0);
 // Reduced continuity rows: y[q] = s1 * (D u)[t(q)] + s2 * w[q] for kept triangles q (F D u + s2 w)
 void launch_FD(const double2* u, const int32_t* tri_edge, const int8_t* tri_sign, const int32_t* kept_tri,
-               int64_t nq, double2 s1, const double2* w, double2 s2, double2* y, hipStream_t st);
+               int64_t nq, double2 s1, const double2* w, double2 s2, double2* y, hipStream_t st, int R = 1,
+               int64_t ldu = 0, int64_t ldw = 0, int64_t ldy = 0);
 // y (+)= s * S x for a CSR real sparse matrix S
 void launch_spmv(const int64_t* ptr, const int32_t* idx, const double* val, int64_t rows, const double2* x,
-                 double2 s, double2* y, int accumulate, hipStream_t st);
-// z = a*x + b*y (elementwise, n)
+                 double2 s, double2* y, int accumulate, hipStream_t st, int R = 1, int64_t ldx = 0, int64_t ldy = 0);
+// z = a*x + b*y (elementwise, n; x or y may be null)
 void launch_axpby(int64_t n, double2 a, const double2* x, double2 b, const double2* y, double2* z,
-                  hipStream_t st);
+                  hipStream_t st, int R = 1, int64_t ldx = 0, int64_t ldy = 0, int64_t ldz = 0);
+// Workspace bytes of launch_gemm for a float32 block with `cols` complex columns and nrhs.
+size_t gemm_workspace_bytes(int64_t cols, int64_t nrhs);
 void launch_cast_f32(const double2* src, int64_t rows, int64_t cols, int64_t lds, float2* dst, int64_t ldd,
                      hipStream_t st);
 

@@ -182,8 +182,10 @@ __global__ void __launch_bounds__(256) k_gemv_grouped(GemvPack pack) {
 // ----------------------------------------------------------------- glue
 
 __global__ void k_expand_charge(const double2* __restrict__ w, double2* __restrict__ full,
-                                const int64_t* __restrict__ obj_tri, double2 scale) {
+                                const int64_t* __restrict__ obj_tri, double2 scale, int64_t ldw, int64_t ldf) {
   const int64_t o = blockIdx.x;
+  w += int64_t(blockIdx.y) * ldw;
+  full += int64_t(blockIdx.y) * ldf;
   const int64_t t0 = obj_tri[o], t1 = obj_tri[o + 1];
   // kept charges of object o are w[t0 - o .. t1 - o - 2]; the last triangle t1-1 is eliminated
   const int64_t q0 = t0 - o;
@@ -213,9 +215,12 @@ __global__ void k_expand_charge(const double2* __restrict__ w, double2* __restri
 }
 
 __global__ void k_DT(const double2* __restrict__ z, const int32_t* __restrict__ tp, const int32_t* __restrict__ tm,
-                     int64_t ne, double2 s, const double2* __restrict__ sedge, double2* __restrict__ y, int acc) {
+                     int64_t ne, double2 s, const double2* __restrict__ sedge, double2* __restrict__ y, int acc,
+                     int64_t ldz, int64_t ldy) {
   const int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (n >= ne) return;
+  z += int64_t(blockIdx.y) * ldz;
+  y += int64_t(blockIdx.y) * ldy;
   const double2 a = z[tp[n]], b = z[tm[n]];
   const double dr = a.x - b.x, di = a.y - b.y;
   double2 sc = s;
@@ -230,9 +235,13 @@ __global__ void k_DT(const double2* __restrict__ z, const int32_t* __restrict__ 
 
 __global__ void k_FD(const double2* __restrict__ u, const int32_t* __restrict__ tri_edge,
                      const int8_t* __restrict__ tri_sign, const int32_t* __restrict__ kept, int64_t nq, double2 s1,
-                     const double2* __restrict__ w, double2 s2, double2* __restrict__ y) {
+                     const double2* __restrict__ w, double2 s2, double2* __restrict__ y, int64_t ldu, int64_t ldw,
+                     int64_t ldy) {
   const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (q >= nq) return;
+  u += int64_t(blockIdx.y) * ldu;
+  if (w) w += int64_t(blockIdx.y) * ldw;
+  y += int64_t(blockIdx.y) * ldy;
   const int64_t t = kept[q];
   double dr = 0, di = 0;
 #pragma unroll
@@ -252,9 +261,12 @@ __global__ void k_FD(const double2* __restrict__ u, const int32_t* __restrict__ 
 }
 
 __global__ void k_spmv(const int64_t* __restrict__ ptr, const int32_t* __restrict__ idx, const double* __restrict__ val,
-                       int64_t rows, const double2* __restrict__ x, double2 s, double2* __restrict__ y, int acc) {
+                       int64_t rows, const double2* __restrict__ x, double2 s, double2* __restrict__ y, int acc,
+                       int64_t ldx, int64_t ldy) {
   const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (r >= rows) return;
+  x += int64_t(blockIdx.y) * ldx;
+  y += int64_t(blockIdx.y) * ldy;
   double ar = 0, ai = 0;
   for (int64_t p = ptr[r]; p < ptr[r + 1]; ++p) {
     const double2 v = x[idx[p]];
@@ -267,9 +279,12 @@ __global__ void k_spmv(const int64_t* __restrict__ ptr, const int32_t* __restric
 }
 
 __global__ void k_axpby(int64_t n, double2 a, const double2* __restrict__ x, double2 b, const double2* __restrict__ y,
-                        double2* __restrict__ z) {
+                        double2* __restrict__ z, int64_t ldx, int64_t ldy, int64_t ldz) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  if (x) x += int64_t(blockIdx.y) * ldx;
+  if (y) y += int64_t(blockIdx.y) * ldy;
+  z += int64_t(blockIdx.y) * ldz;
   const double2 u = x ? x[i] : make_double2(0, 0), v = y ? y[i] : make_double2(0, 0);
   z[i] = make_double2(a.x * u.x - a.y * u.y + b.x * v.x - b.y * v.y, a.x * u.y + a.y * u.x + b.x * v.y + b.y * v.x);
 }
@@ -443,34 +458,43 @@ void launch_gemv_grouped(const GemvDesc* host_descs, int n, hipStream_t st) {
 }
 
 void launch_expand_charge(const double2* w, double2* full, const int64_t* obj_tri, int64_t nobj, double2 scale,
-                          hipStream_t st) {
-  hipLaunchKernelGGL(dev::k_expand_charge, dim3(unsigned(nobj)), dim3(256), 0, st, w, full, obj_tri, scale);
+                          hipStream_t st, int R, int64_t ldw, int64_t ldf) {
+  if (R <= 0) return;
+  hipLaunchKernelGGL(dev::k_expand_charge, dim3(unsigned(nobj), unsigned(R)), dim3(256), 0, st, w, full, obj_tri,
+                     scale, ldw, ldf);
   BEM_HIP(hipGetLastError());
 }
 
 void launch_DT(const double2* z, const int32_t* tp, const int32_t* tm, int64_t ne, double2 s, const double2* sedge,
-               double2* y, int accumulate, hipStream_t st) {
-  hipLaunchKernelGGL(dev::k_DT, dim3(unsigned((ne + 255) / 256)), dim3(256), 0, st, z, tp, tm, ne, s, sedge, y,
-                     accumulate);
+               double2* y, int accumulate, hipStream_t st, int R, int64_t ldz, int64_t ldy) {
+  if (R <= 0) return;
+  hipLaunchKernelGGL(dev::k_DT, dim3(unsigned((ne + 255) / 256), unsigned(R)), dim3(256), 0, st, z, tp, tm, ne, s,
+                     sedge, y, accumulate, ldz, ldy);
   BEM_HIP(hipGetLastError());
 }
 
 void launch_FD(const double2* u, const int32_t* tri_edge, const int8_t* tri_sign, const int32_t* kept, int64_t nq,
-               double2 s1, const double2* w, double2 s2, double2* y, hipStream_t st) {
-  hipLaunchKernelGGL(dev::k_FD, dim3(unsigned((nq + 255) / 256)), dim3(256), 0, st, u, tri_edge, tri_sign, kept, nq,
-                     s1, w, s2, y);
+               double2 s1, const double2* w, double2 s2, double2* y, hipStream_t st, int R, int64_t ldu, int64_t ldw,
+               int64_t ldy) {
+  if (R <= 0) return;
+  hipLaunchKernelGGL(dev::k_FD, dim3(unsigned((nq + 255) / 256), unsigned(R)), dim3(256), 0, st, u, tri_edge,
+                     tri_sign, kept, nq, s1, w, s2, y, ldu, ldw, ldy);
   BEM_HIP(hipGetLastError());
 }
 
 void launch_spmv(const int64_t* ptr, const int32_t* idx, const double* val, int64_t rows, const double2* x,
-                 double2 s, double2* y, int accumulate, hipStream_t st) {
-  hipLaunchKernelGGL(dev::k_spmv, dim3(unsigned((rows + 255) / 256)), dim3(256), 0, st, ptr, idx, val, rows, x, s, y,
-                     accumulate);
+                 double2 s, double2* y, int accumulate, hipStream_t st, int R, int64_t ldx, int64_t ldy) {
+  if (R <= 0) return;
+  hipLaunchKernelGGL(dev::k_spmv, dim3(unsigned((rows + 255) / 256), unsigned(R)), dim3(256), 0, st, ptr, idx, val,
+                     rows, x, s, y, accumulate, ldx, ldy);
   BEM_HIP(hipGetLastError());
 }
 
-void launch_axpby(int64_t n, double2 a, const double2* x, double2 b, const double2* y, double2* z, hipStream_t st) {
-  hipLaunchKernelGGL(dev::k_axpby, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, n, a, x, b, y, z);
+void launch_axpby(int64_t n, double2 a, const double2* x, double2 b, const double2* y, double2* z, hipStream_t st,
+                  int R, int64_t ldx, int64_t ldy, int64_t ldz) {
+  if (R <= 0 || n <= 0) return;
+  hipLaunchKernelGGL(dev::k_axpby, dim3(unsigned((n + 255) / 256), unsigned(R)), dim3(256), 0, st, n, a, x, b, y, z,
+                     ldx, ldy, ldz);
   BEM_HIP(hipGetLastError());
 }
 

@@ -825,6 +825,25 @@ void export_block(OpObj& op, int block, bem_c64* host) {
     case BEM_BLOCK_LPHI_BG:
       copy_dense(op.Lphi_bg, 0, 0, op.nt);
       return;
+    case BEM_BLOCK_MEQ_INV: {
+      if (op.inner_mode != BEM_INNER_DIRECT) throw Error(BEM_E_INVALID, "no inverse: the nested solve is iterative");
+      std::memset(host, 0, sizeof(bem_c64) * op.Neq * op.Neq);
+      // object o occupies rows/columns: edges [e0, e0+ne_o) and charges ne + [q0, q0+nq_o)
+      for (int64_t o = 0; o < op.nobj; ++o) {
+        const Dense& A = op.Minv[o];
+        const int64_t e0 = op.obj_edge[o], neo = op.obj_edge[o + 1] - e0, q0 = op.obj_q[o];
+        std::vector<double2> row(A.cols);
+        for (int64_t r = 0; r < A.rows; ++r) {
+          BEM_HIP(hipMemcpy(row.data(), A.d64 + r * A.ld, sizeof(double2) * A.cols, hipMemcpyDeviceToHost));
+          const int64_t gr = r < neo ? e0 + r : op.ne + q0 + (r - neo);
+          for (int64_t c = 0; c < A.cols; ++c) {
+            const int64_t gc = c < neo ? e0 + c : op.ne + q0 + (c - neo);
+            host[gr * op.Neq + gc] = {row[c].x, row[c].y};
+          }
+        }
+      }
+      return;
+    }
     case BEM_BLOCK_IX: {
       std::vector<int64_t> ptr(op.ne + 1);
       BEM_HIP(hipMemcpy(ptr.data(), op.ix_ptr, sizeof(int64_t) * (op.ne + 1), hipMemcpyDeviceToHost));

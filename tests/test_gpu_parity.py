@@ -64,6 +64,32 @@ def case(name, ctx, inner=B.BEM_INNER_GMRES, precond=0, precision=B.BEM_FP64):
     return _cache[key]
 
 
+@pytest.mark.parametrize("backend", ["valu", "mfma"])
+def test_device_inverse_of_meq(backend, ctx, monkeypatch):
+    """The direct nested solve's device inverse times the oracle's M_eq is the identity (both
+    the VALU and the matrix-core rank-64 update of the Gauss-Jordan elimination)."""
+    monkeypatch.setenv("BEM_DENSE_VALU", "1" if backend == "valu" else "0")
+    level, k0a, eps, eps_bg = CASES["ico80_lossy"]
+    w = meshgen.sphere_workload(level, k0a, eps)
+    if "ico80_lossy" not in _oracle:
+        _oracle["ico80_lossy"] = S.assemble(w.xyz, w.tri, w.obj,
+                                            S.Problem(w.freq_hz, w.eps_r, w.mu_r, w.sigma, eps_bg=eps_bg))
+    ops = _oracle["ico80_lossy"]
+    mesh = B.bem_mesh_load(ctx, w.xyz, w.tri)
+    op = B.bem_assemble(ctx, mesh, B.make_problem(w.freq_hz, w.eps_r, w.mu_r, w.sigma, eps_bg=eps_bg,
+                                                  inner_mode=B.BEM_INNER_DIRECT, precond=0))
+    va, vb, _, _ = B.bem_edge_table(ctx, mesh)
+    perm = edge_perm(va, vb, ops.topo.edges)
+    ne, nt = len(ops.topo.edges), len(ops.topo.tri)
+    Meq, _, _ = S.equivalent_matrix_object(ops, 0)
+    P = meq_perm(perm, ne, nt - 1)
+    Minv = B.bem_block_export(ctx, op, B.BEM_BLOCK_MEQ_INV, len(Meq), len(Meq))
+    err = np.abs(Minv @ Meq[np.ix_(P, P)] - np.eye(len(Meq))).max()
+    print(f"{backend}: max |M_eq^-1 M_eq - I| = {err:.2e}")
+    B.bem_release(ctx, op)
+    assert err < 1e-10
+
+
 def oracle_blocks(ops):
     return {
         B.BEM_BLOCK_LA_INT: ops.LA_int, B.BEM_BLOCK_LPHI_INT: ops.Lphi_int, B.BEM_BLOCK_K_INT: ops.K_int,
