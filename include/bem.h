@@ -109,9 +109,14 @@ typedef struct { bem_c64 eps_r; double mu_r, sigma; } bem_material;
 
 /* How the equivalent-configuration system (eq. AEFIEeqvdis) is solved inside every product
  * (Sec. III): directly (its inverse is formed once per assembly; the paper's route for small
- * objects) or by nested GMRES (its route for large objects); AUTO picks direct while every
- * object's system has at most 16384 unknowns. */
-enum { BEM_INNER_AUTO = 0, BEM_INNER_GMRES = 1, BEM_INNER_DIRECT = 2 };
+ * objects) or by nested GMRES (its route for large objects).  DIRECT inverts the augmented
+ * (NE_o + NQ_o)^2 matrix of each object.  SCHUR uses that the right-hand side has no charge
+ * part: the second row gives w = k0^-2 F D u, and substituting it leaves
+ * S u = r with S = mu_l L^A_l - (eps_l k0^2)^-1 D^T L^phi_l D (NE_o x NE_o; exact because the
+ * charges of D u sum to zero on each object), so only S is inverted.  Its conditioning grows
+ * like (k_l h)^-2, h the longest edge, so AUTO takes SCHUR when |k_l| h >= 0.01 and
+ * NE_o <= 32768, else DIRECT while NE_o + NQ_o <= 16384, else GMRES. */
+enum { BEM_INNER_AUTO = 0, BEM_INNER_GMRES = 1, BEM_INNER_DIRECT = 2, BEM_INNER_SCHUR = 3 };
 
 typedef struct {
   double freq_hz;
@@ -223,9 +228,9 @@ int bem_op_stats_get(bem_ctx* ctx, bem_op_h op, bem_op_stats* out);
 /* Opt-in kernel timing (all contexts of the process).  When enabled, HIP events are recorded
  * on the launch stream around every fill, gather and dense-product launch, together with the
  * launch's algorithmic bytes and work.  Enabling clears the counters.  Classes: 0 float64
- * products, 1 float32 products, 2 L fill, 3 K~ fill, 4 near corrections, 5 gathers, 6 matrix-
- * core products, 7 rank-64 updates of the dense inversions.  bem_profile_read waits for the
- * recorded events. */
+ * products, 1 float32 products, 2 L fill, 3 K~ fill, 4 near corrections, 5 gathers, 6 float32
+ * matrix-core products (several excitations), 7 rank-64 updates of the dense inversions,
+ * 8 float64 matrix-core products.  bem_profile_read waits for the recorded events. */
 int bem_profile_enable(int on);
 int bem_profile_read(int kernel_class, int64_t* launches, double* ms, double* bytes, double* work);
 

@@ -26,8 +26,10 @@ SYMBOLS = ["bem_create", "bem_destroy", "bem_last_error", "bem_mesh_load", "bem_
            "bem_near_pairs", "bem_assemble", "bem_apply", "bem_block_export", "bem_set_inner_tol", "bem_solve",
            "bem_submit", "bem_poll", "bem_drain", "bem_release", "bem_memory_in_use", "bem_op_stats_get",
            "bem_profile_enable", "bem_profile_read"]
-KC_GEMV_F64, KC_GEMV_F32, KC_FILL_L, KC_FILL_K, KC_FILL_NEAR, KC_GATHER, KC_GEMM_F32, KC_DENSE_INV = range(8)
-KC_NAMES = ["gemv_f64", "gemv_f32", "fill_L", "fill_K", "fill_near", "gather", "gemm_f32_mfma", "dense_inv_update"]
+(KC_GEMV_F64, KC_GEMV_F32, KC_FILL_L, KC_FILL_K, KC_FILL_NEAR, KC_GATHER, KC_GEMM_F32, KC_DENSE_INV,
+ KC_GEMM_F64) = range(9)
+KC_NAMES = ["gemv_f64", "gemv_f32", "fill_L", "fill_K", "fill_near", "gather", "gemm_f32_mfma", "dense_inv_update",
+            "gemm_f64_mfma"]
 
 
 class bem_op_stats(C.Structure):
@@ -43,7 +45,7 @@ class bem_material(C.Structure):
     _fields_ = [("eps_r", c64), ("mu_r", C.c_double), ("sigma", C.c_double)]
 
 
-BEM_INNER_AUTO, BEM_INNER_GMRES, BEM_INNER_DIRECT = 0, 1, 2
+BEM_INNER_AUTO, BEM_INNER_GMRES, BEM_INNER_DIRECT, BEM_INNER_SCHUR = 0, 1, 2, 3
 
 
 class bem_problem(C.Structure):

@@ -1,4 +1,5 @@
 // C ABI of libbem: argument checks, handle tables, status codes and error messages.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -185,7 +186,9 @@ int bem_apply(bem_ctx* c, bem_op_h h, int block, const void* x, void* y, int64_t
     }
     const double2* xp = static_cast<const double2*>(x);
     double2* yp = static_cast<double2*>(y);
-    for (int64_t r = 0; r < nrhs; ++r) bem::apply_block(op, block, xp + r * cols, yp + r * rows, st);
+    // columns go through the matrix-core products in chunks of up to 256
+    for (int64_t r0 = 0; r0 < nrhs; r0 += 256)
+      bem::apply_block(op, block, xp + r0 * cols, yp + r0 * rows, std::min<int64_t>(256, nrhs - r0), st);
     return BEM_OK;
   });
 }

@@ -149,7 +149,9 @@ void apply_precond_eq(OpObj& op, const double2* r, double2* x, bool fp32, hipStr
 
 // Operator construction and application.
 void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob);
-void apply_block(OpObj& op, int block, const double2* x, double2* y, hipStream_t st);
+// y = A x for `block`, nrhs columns (leading dimensions = the block's size); nrhs > 1 runs the
+// dense products on matrix cores.
+void apply_block(OpObj& op, int block, const double2* x, double2* y, int64_t nrhs, hipStream_t st);
 void apply_meq(OpObj& op, const double2* x, double2* y, bool fp32, hipStream_t st);
 void apply_final(OpObj& op, const double2* x, double2* y, bool fp32, double inner_tol, hipStream_t st);
 void export_block(OpObj& op, int block, bem_c64* host);

@@ -24,6 +24,12 @@ void build_meq(const double2* LA, int64_t lda, const double2* Lp, int64_t ldp, c
                const int32_t* tm_local, int64_t ne, int64_t nt, double2 mu, double2 meps, double k02, double2* M,
                int64_t ldm, hipStream_t st);
 
+// Charge-eliminated M_eq of one object: S = mu L^A_l + c D^T L^phi_l D (ne x ne), with
+// c = -1/(eps_l k0^2).  Since the charges of D u sum to zero per object, M_eq [u; w] = [r; 0]
+// is equivalent to S u = r, w = k0^-2 F D u.
+void build_s(const double2* LA, int64_t lda, const double2* Lp, int64_t ldp, const int32_t* tp_local,
+             const int32_t* tm_local, int64_t ne, double2 mu, double2 c, double2* S, int64_t lds, hipStream_t st);
+
 // Dense S (nq x nq) = diag * I + G B for a sparse G (CSR over the nq kept charges, columns =
 // object-local triangles, the last one being the eliminated charge): (G B)[q][c] = G[q][c] -
 // G[q][last].

@@ -306,6 +306,24 @@ __global__ void k_build_meq(const double2* __restrict__ LA, int64_t lda, const d
   M[r * ldm + c] = v;
 }
 
+// Charge-eliminated equivalent-configuration matrix (eq. AEFIEeqvdis with w = k0^-2 F D u
+// substituted): S = mu L^A_l + c D^T L^phi_l D, c = -1/(eps_l k0^2), object-local T+/T-.
+__global__ void k_build_s(const double2* __restrict__ LA, int64_t lda, const double2* __restrict__ Lp, int64_t ldp,
+                          const int32_t* __restrict__ tp, const int32_t* __restrict__ tm, int64_t ne, double2 mu,
+                          double2 c, double2* __restrict__ S, int64_t lds) {
+  const int64_t col = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (col >= ne) return;
+  const int64_t cp = tp[col], cm_ = tm[col];
+  for (int64_t r = blockIdx.y; r < ne; r += gridDim.y) {
+    const double2* rp = Lp + int64_t(tp[r]) * ldp;
+    const double2* rm = Lp + int64_t(tm[r]) * ldp;
+    const double2 pp = rp[cp], pm = rp[cm_], mp = rm[cp], mm = rm[cm_];
+    const double2 d = make_double2((pp.x - pm.x) - (mp.x - mm.x), (pp.y - pm.y) - (mp.y - mm.y));
+    const double2 a = cm(mu, LA[r * lda + col]), b = cm(c, d);
+    S[r * lds + col] = make_double2(a.x + b.x, a.y + b.y);
+  }
+}
+
 // Dense charge Schur complement S = k0^2 s0 I + G_kept - g_last 1^T from a sparse G (CSR over
 // kept charges, columns = triangles of the object) - see dense.h.
 __global__ void k_build_schur(const int64_t* __restrict__ ptr, const int32_t* __restrict__ idx,
@@ -440,6 +458,14 @@ void build_meq(const double2* LA, int64_t lda, const double2* Lp, int64_t ldp, c
   const int64_t N = ne + nt - 1;
   hipLaunchKernelGGL(dev::k_build_meq, dim3(unsigned((N + 255) / 256), unsigned(N)), dim3(256), 0, st, LA, lda, Lp, ldp,
                      tp_local, tm_local, ne, nt, mu, meps, k02, M, ldm);
+  BEM_HIP(hipGetLastError());
+}
+
+void build_s(const double2* LA, int64_t lda, const double2* Lp, int64_t ldp, const int32_t* tp_local,
+             const int32_t* tm_local, int64_t ne, double2 mu, double2 c, double2* S, int64_t lds, hipStream_t st) {
+  if (ne <= 0) return;
+  hipLaunchKernelGGL(dev::k_build_s, dim3(unsigned((ne + 255) / 256), unsigned(std::min<int64_t>(ne, 32768))),
+                     dim3(256), 0, st, LA, lda, Lp, ldp, tp_local, tm_local, ne, mu, c, S, lds);
   BEM_HIP(hipGetLastError());
 }
 

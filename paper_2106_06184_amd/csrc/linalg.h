@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 #include "internal.h"
 
 namespace bem {
@@ -53,33 +55,38 @@ void launch_gemm(const GemmDesc& d, void* ws, size_t ws_bytes, hipStream_t st);
 // real-embedded right-hand sides.
 void launch_products(const std::vector<GemvDesc>& ds, int R, void* ws, size_t ws_bytes, hipStream_t st);
 
-// ---- batched Krylov kernels (R independent Krylov spaces; vector i of column r at
-//      V + (i * R + r) * ldv; per-column Hessenberg at H + r * hs, column j at + j * ldh)
-struct BatchKrylov {
-  int R;
-  int64_t n, ldv, hs, ldh;
-  double2 *V, *H, *cs, *sn, *g, *y, *h2;  // cs/sn/y: stride m+1, g/h2: stride m+2
-  int m;
-  double* res;       // R
-  double* part;      // R * 128
-  int* jr;           // R (per-column Arnoldi length for the back-solve / update)
-};
-void launch_bmdot(const BatchKrylov& k, int j, const double2* W, int64_t ldw, double2* h, int64_t hstride,
+// ---- batched Krylov kernels: R independent Krylov spaces that share their products.  Basis
+// vector i of column c at V + (i R + c) ldv (each step's R vectors form one n x R column-major
+// block); per-column small arrays at base + c * stride.  Reductions are deterministic (fixed
+// chunking and summation order).  `part` needs R (j1 max) bkry_chunks(n) complex entries.
+int bkry_chunks(int64_t n);
+// h[c hstride + i] = V_i,c^H w_c for i < j1
+void launch_bmdot(const double2* V, int64_t ldv, int R, int j1, const double2* W, int64_t ldw, int64_t n,
+                  double2* part, double2* h, int64_t hstride, hipStream_t st);
+// w_c += sign sum_{i < j_c} V_i,c h[c hstride + i], j_c = jr ? jr[c] : j1
+void launch_bmupdate(const double2* V, int64_t ldv, int R, int j1, const int* jr, const double2* h, int64_t hstride,
+                     double sign, double2* W, int64_t ldw, int64_t n, hipStream_t st);
+// out[c ostride] = (||w_c||_2, 0)
+void launch_bnorm(const double2* W, int64_t ldw, int R, int64_t n, double2* part, double2* out, int64_t ostride,
                   hipStream_t st);
-void launch_bmupdate(const BatchKrylov& k, int j, const int* jr, const double2* h, int64_t hstride, double sign,
-                     double2* W, int64_t ldw, hipStream_t st);
-void launch_bnorm(const BatchKrylov& k, const double2* W, int64_t ldw, double2* out, int64_t ostride, hipStream_t st);
-void launch_bscale_inv(const BatchKrylov& k, double2* W, int64_t ldw, const double2* nrm, int64_t nstride,
-                       hipStream_t st);
-void launch_bgivens(const BatchKrylov& k, int j, hipStream_t st);
-void launch_bbacksolve(const BatchKrylov& k, hipStream_t st);
-void launch_binit_g(const BatchKrylov& k, const double2* beta, int64_t bstride, hipStream_t st);
-// X[:, idx[c]] += U[:, c] for c < R (scatter of compacted columns)
-void launch_scatter_add(const double2* U, int64_t ldu, double2* X, int64_t ldx, const int* idx, int64_t n, int R,
-                        hipStream_t st);
+// w_c = w_c / nrm[c nstride] (0 when the norm is 0 or frozen[c] is set; frozen may be null)
+void launch_bscale_inv(double2* W, int64_t ldw, int R, int64_t n, const double2* nrm, int64_t nstride,
+                       const int* frozen, hipStream_t st);
+// Givens step j of every column: Hessenberg column j of column c at H + c hs + j ldh; cs, sn, y
+// with stride m+1, g and h2 with stride m+2; res[c] = |g_c[j+1]|.
+void launch_bgivens(double2* H, int64_t hs, int64_t ldh, int j, double2* cs, double2* sn, double2* g, double* res,
+                    const double2* h2, int m, int R, hipStream_t st);
+// y_c = R_c^{-1} g_c over the leading jr[c] x jr[c] block
+void launch_bbacksolve(const double2* H, int64_t hs, int64_t ldh, const int* jr, const double2* g, double2* y, int m,
+                       int R, hipStream_t st);
+// g_c = (beta[c bstride], 0, ..., 0)
+void launch_binit_g(double2* g, int m, const double2* beta, int64_t bstride, int R, hipStream_t st);
 // U[:, c] = X[:, idx[c]]
 void launch_gather_cols(const double2* X, int64_t ldx, double2* U, int64_t ldu, const int* idx, int64_t n, int R,
                         hipStream_t st);
+// X[:, idx[c]] (+)= U[:, c]
+void launch_scatter_cols(const double2* U, int64_t ldu, double2* X, int64_t ldx, const int* idx, int64_t n, int R,
+                         int accumulate, hipStream_t st);
 
 // ---- sparse glue (float64 complex vectors).  Every launcher processes R columns (grid.y),
 // column r of an argument starting at pointer + r * ld (ld unused when R = 1).

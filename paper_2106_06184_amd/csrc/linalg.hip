@@ -368,9 +368,8 @@ __global__ void k_scale_inv(const double2* __restrict__ w, int64_t n, const doub
 }
 
 // Hcol: entries 0..j (projections) and j+1 (norm of the new vector, real).
-__global__ void k_givens(double2* Hcol, int j, double2* cs, double2* sn, double2* g, double* res,
-                         const double2* h2) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__device__ void givens_step(double2* Hcol, int j, double2* cs, double2* sn, double2* g, double* res,
+                            const double2* h2) {
   if (h2)
     for (int i = 0; i <= j; ++i) Hcol[i] = make_double2(Hcol[i].x + h2[i].x, Hcol[i].y + h2[i].y);
   // apply previous rotations: [h_i; h_{i+1}] <- [c, s; -conj(s), c] [h_i; h_{i+1}]  (c real)
@@ -412,8 +411,14 @@ __global__ void k_givens(double2* Hcol, int j, double2* cs, double2* sn, double2
   *res = hypot(g[j + 1].x, g[j + 1].y);
 }
 
-__global__ void k_backsolve(const double2* H, int64_t ldh, int j, const double2* g, double2* y) {
+__global__ void k_givens(double2* Hcol, int j, double2* cs, double2* sn, double2* g, double* res,
+                         const double2* h2) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  givens_step(Hcol, j, cs, sn, g, res, h2);
+}
+
+// y = R^{-1} g for the leading j x j upper-triangular block of H (column-major, ldh)
+__device__ void backsolve(const double2* H, int64_t ldh, int j, const double2* g, double2* y) {
   for (int i = j - 1; i >= 0; --i) {
     double2 s = g[i];
     for (int k = i + 1; k < j; ++k) {
@@ -427,10 +432,199 @@ __global__ void k_backsolve(const double2* H, int64_t ldh, int j, const double2*
   }
 }
 
+__global__ void k_backsolve(const double2* H, int64_t ldh, int j, const double2* g, double2* y) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  backsolve(H, ldh, j, g, y);
+}
+
 __global__ void k_init_g(double2* g, int mmax, const double2* beta) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i > mmax) return;
   g[i] = i == 0 ? make_double2(beta->x, 0) : make_double2(0, 0);
+}
+
+// ---- batched Krylov: R independent spaces, vector i of column c at V + (i R + c) ldv
+
+constexpr int kChunk = 2048;  // vector elements per block of the batched reductions
+constexpr int kPer = kChunk / 256;
+
+// part[(c j1 + i) nch + ch] = sum over chunk ch of conj(V_i,c) w_c
+__global__ void __launch_bounds__(256) k_bmdot_part(const double2* __restrict__ V, int64_t ldv, int R, int j1,
+                                                    const double2* __restrict__ W, int64_t ldw, int64_t n, int nch,
+                                                    double2* __restrict__ part) {
+  const int ch = blockIdx.x, c = blockIdx.y;
+  const int64_t k0 = int64_t(ch) * kChunk + threadIdx.x;
+  const double2* w = W + int64_t(c) * ldw;
+  double2 wl[kPer];
+#pragma unroll
+  for (int s = 0; s < kPer; ++s) {
+    const int64_t k = k0 + 256 * s;
+    wl[s] = k < n ? w[k] : make_double2(0, 0);
+  }
+  __shared__ double2 red[4];
+  const int wv = threadIdx.x / kWave;
+  for (int i = 0; i < j1; ++i) {
+    const double2* v = V + (int64_t(i) * R + c) * ldv;
+    double ar = 0, ai = 0;
+#pragma unroll
+    for (int s = 0; s < kPer; ++s) {
+      const int64_t k = k0 + 256 * s;
+      if (k < n) {
+        const double2 a = v[k];
+        ar += a.x * wl[s].x + a.y * wl[s].y;
+        ai += a.x * wl[s].y - a.y * wl[s].x;
+      }
+    }
+    ar = wave_sum(ar);
+    ai = wave_sum(ai);
+    if (threadIdx.x % kWave == 0) red[wv] = make_double2(ar, ai);
+    __syncthreads();
+    if (threadIdx.x == 0)
+      part[(int64_t(c) * j1 + i) * nch + ch] =
+          make_double2(red[0].x + red[1].x + red[2].x + red[3].x, red[0].y + red[1].y + red[2].y + red[3].y);
+    __syncthreads();
+  }
+}
+
+// Same partial sums with one block per (chunk, basis vector, column): for few columns, where
+// the chunk-per-block form above leaves the GPU mostly idle.  Identical summation order.
+__global__ void __launch_bounds__(256) k_bmdot_part3(const double2* __restrict__ V, int64_t ldv, int R, int j1,
+                                                     const double2* __restrict__ W, int64_t ldw, int64_t n, int nch,
+                                                     double2* __restrict__ part) {
+  const int ch = blockIdx.x, i = blockIdx.y, c = blockIdx.z;
+  const int64_t k0 = int64_t(ch) * kChunk + threadIdx.x;
+  const double2* w = W + int64_t(c) * ldw;
+  const double2* v = V + (int64_t(i) * R + c) * ldv;
+  double ar = 0, ai = 0;
+#pragma unroll
+  for (int s = 0; s < kPer; ++s) {
+    const int64_t k = k0 + 256 * s;
+    const double2 wl = k < n ? w[k] : make_double2(0, 0);
+    if (k < n) {
+      const double2 a = v[k];
+      ar += a.x * wl.x + a.y * wl.y;
+      ai += a.x * wl.y - a.y * wl.x;
+    }
+  }
+  __shared__ double2 red[4];
+  ar = wave_sum(ar);
+  ai = wave_sum(ai);
+  if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = make_double2(ar, ai);
+  __syncthreads();
+  if (threadIdx.x == 0)
+    part[(int64_t(c) * j1 + i) * nch + ch] =
+        make_double2(red[0].x + red[1].x + red[2].x + red[3].x, red[0].y + red[1].y + red[2].y + red[3].y);
+}
+
+__global__ void k_bmdot_final(const double2* __restrict__ part, int nch, int j1, double2* __restrict__ h,
+                              int64_t hstride) {
+  const int c = blockIdx.x;
+  for (int i = threadIdx.x; i < j1; i += blockDim.x) {
+    const double2* p = part + (int64_t(c) * j1 + i) * nch;
+    double ar = 0, ai = 0;
+    for (int ch = 0; ch < nch; ++ch) {
+      ar += p[ch].x;
+      ai += p[ch].y;
+    }
+    h[int64_t(c) * hstride + i] = make_double2(ar, ai);
+  }
+}
+
+__global__ void k_bmupdate(const double2* __restrict__ V, int64_t ldv, int R, int j1, const int* __restrict__ jr,
+                           const double2* __restrict__ h, int64_t hstride, double sign, double2* __restrict__ W,
+                           int64_t ldw, int64_t n) {
+  const int c = blockIdx.y;
+  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int jc = jr ? jr[c] : j1;
+  const double2* hc = h + int64_t(c) * hstride;
+  double2* w = W + int64_t(c) * ldw;
+  double ar = w[k].x, ai = w[k].y;
+  for (int i = 0; i < jc; ++i) {
+    const double2 a = V[(int64_t(i) * R + c) * ldv + k], q = hc[i];
+    ar += sign * (a.x * q.x - a.y * q.y);
+    ai += sign * (a.x * q.y + a.y * q.x);
+  }
+  w[k] = make_double2(ar, ai);
+}
+
+__global__ void __launch_bounds__(256) k_bnorm_part(const double2* __restrict__ W, int64_t ldw, int64_t n, int nch,
+                                                    double* __restrict__ part) {
+  const int ch = blockIdx.x, c = blockIdx.y;
+  const double2* w = W + int64_t(c) * ldw;
+  double s = 0;
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int64_t k = int64_t(ch) * kChunk + threadIdx.x + 256 * q;
+    if (k < n) {
+      const double2 a = w[k];
+      s += a.x * a.x + a.y * a.y;
+    }
+  }
+  s = wave_sum(s);
+  __shared__ double sh[4];
+  if (threadIdx.x % kWave == 0) sh[threadIdx.x / kWave] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) part[int64_t(c) * nch + ch] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+__global__ void k_bnorm_final(const double* __restrict__ part, int nch, int R, double2* __restrict__ out,
+                              int64_t ostride) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= R) return;
+  double s = 0;
+  for (int ch = 0; ch < nch; ++ch) s += part[int64_t(c) * nch + ch];
+  out[int64_t(c) * ostride] = make_double2(sqrt(s), 0.0);
+}
+
+__global__ void k_bscale_inv(double2* __restrict__ W, int64_t ldw, int64_t n, const double2* __restrict__ nrm,
+                             int64_t nstride, const int* __restrict__ frozen) {
+  const int c = blockIdx.y;
+  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const double v = nrm[int64_t(c) * nstride].x;
+  const double s = (frozen && frozen[c]) ? 0.0 : (v > 0 ? 1.0 / v : 0.0);
+  double2* w = W + int64_t(c) * ldw;
+  w[k] = make_double2(w[k].x * s, w[k].y * s);
+}
+
+__global__ void k_bgivens(double2* H, int64_t hs, int64_t ldh, int j, double2* cs, double2* sn, double2* g,
+                          double* res, const double2* h2, int m, int R) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= R) return;
+  givens_step(H + int64_t(c) * hs + int64_t(j) * ldh, j, cs + int64_t(c) * (m + 1), sn + int64_t(c) * (m + 1),
+              g + int64_t(c) * (m + 2), res + c, h2 ? h2 + int64_t(c) * (m + 2) : nullptr);
+}
+
+__global__ void k_bbacksolve(const double2* H, int64_t hs, int64_t ldh, const int* jr, const double2* g, double2* y,
+                             int m, int R) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= R) return;
+  backsolve(H + int64_t(c) * hs, ldh, jr[c], g + int64_t(c) * (m + 2), y + int64_t(c) * (m + 1));
+}
+
+__global__ void k_binit_g(double2* g, int m, const double2* beta, int64_t bstride) {
+  const int c = blockIdx.x;
+  for (int i = threadIdx.x; i < m + 2; i += blockDim.x)
+    g[int64_t(c) * (m + 2) + i] = i == 0 ? make_double2(beta[int64_t(c) * bstride].x, 0) : make_double2(0, 0);
+}
+
+__global__ void k_gather_cols(const double2* __restrict__ X, int64_t ldx, double2* __restrict__ U, int64_t ldu,
+                              const int* __restrict__ idx, int64_t n) {
+  const int c = blockIdx.y;
+  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  U[int64_t(c) * ldu + k] = X[int64_t(idx[c]) * ldx + k];
+}
+
+__global__ void k_scatter_cols(const double2* __restrict__ U, int64_t ldu, double2* __restrict__ X, int64_t ldx,
+                               const int* __restrict__ idx, int64_t n, int accumulate) {
+  const int c = blockIdx.y;
+  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  double2* x = X + int64_t(idx[c]) * ldx + k;
+  const double2 u = U[int64_t(c) * ldu + k];
+  *x = accumulate ? make_double2(x->x + u.x, x->y + u.y) : u;
 }
 
 }  // namespace dev
@@ -546,6 +740,89 @@ void launch_backsolve(const double2* H, int64_t ldh, int j, double2* g, double2*
 
 void launch_init_g(double2* g, int mmax, const double2* beta, hipStream_t st) {
   hipLaunchKernelGGL(dev::k_init_g, dim3(unsigned((mmax + 1 + 255) / 256)), dim3(256), 0, st, g, mmax, beta);
+  BEM_HIP(hipGetLastError());
+}
+
+// ---- batched Krylov launchers
+
+int bkry_chunks(int64_t n) { return int((std::max<int64_t>(n, 1) + dev::kChunk - 1) / dev::kChunk); }
+
+void launch_bmdot(const double2* V, int64_t ldv, int R, int j1, const double2* W, int64_t ldw, int64_t n,
+                  double2* part, double2* h, int64_t hstride, hipStream_t st) {
+  if (R <= 0 || j1 <= 0) return;
+  const int nch = bkry_chunks(n);
+  if (int64_t(nch) * R >= 1024)
+    hipLaunchKernelGGL(dev::k_bmdot_part, dim3(unsigned(nch), unsigned(R)), dim3(256), 0, st, V, ldv, R, j1, W, ldw,
+                       n, nch, part);
+  else
+    hipLaunchKernelGGL(dev::k_bmdot_part3, dim3(unsigned(nch), unsigned(j1), unsigned(R)), dim3(256), 0, st, V, ldv,
+                       R, j1, W, ldw, n, nch, part);
+  BEM_HIP(hipGetLastError());
+  hipLaunchKernelGGL(dev::k_bmdot_final, dim3(unsigned(R)), dim3(64), 0, st, part, nch, j1, h, hstride);
+  BEM_HIP(hipGetLastError());
+}
+
+void launch_bmupdate(const double2* V, int64_t ldv, int R, int j1, const int* jr, const double2* h, int64_t hstride,
+                     double sign, double2* W, int64_t ldw, int64_t n, hipStream_t st) {
+  if (R <= 0 || n <= 0 || (j1 <= 0 && !jr)) return;
+  hipLaunchKernelGGL(dev::k_bmupdate, dim3(unsigned((n + 255) / 256), unsigned(R)), dim3(256), 0, st, V, ldv, R, j1,
+                     jr, h, hstride, sign, W, ldw, n);
+  BEM_HIP(hipGetLastError());
+}
+
+void launch_bnorm(const double2* W, int64_t ldw, int R, int64_t n, double2* part, double2* out, int64_t ostride,
+                  hipStream_t st) {
+  if (R <= 0) return;
+  const int nch = bkry_chunks(n);
+  double* p = reinterpret_cast<double*>(part);
+  hipLaunchKernelGGL(dev::k_bnorm_part, dim3(unsigned(nch), unsigned(R)), dim3(256), 0, st, W, ldw, n, nch, p);
+  BEM_HIP(hipGetLastError());
+  hipLaunchKernelGGL(dev::k_bnorm_final, dim3(unsigned((R + 63) / 64)), dim3(64), 0, st, p, nch, R, out, ostride);
+  BEM_HIP(hipGetLastError());
+}
+
+void launch_bscale_inv(double2* W, int64_t ldw, int R, int64_t n, const double2* nrm, int64_t nstride,
+                       const int* frozen, hipStream_t st) {
+  if (R <= 0 || n <= 0) return;
+  hipLaunchKernelGGL(dev::k_bscale_inv, dim3(unsigned((n + 255) / 256), unsigned(R)), dim3(256), 0, st, W, ldw, n,
+                     nrm, nstride, frozen);
+  BEM_HIP(hipGetLastError());
+}
+
+void launch_bgivens(double2* H, int64_t hs, int64_t ldh, int j, double2* cs, double2* sn, double2* g, double* res,
+                    const double2* h2, int m, int R, hipStream_t st) {
+  if (R <= 0) return;
+  hipLaunchKernelGGL(dev::k_bgivens, dim3(unsigned((R + 63) / 64)), dim3(64), 0, st, H, hs, ldh, j, cs, sn, g, res,
+                     h2, m, R);
+  BEM_HIP(hipGetLastError());
+}
+
+void launch_bbacksolve(const double2* H, int64_t hs, int64_t ldh, const int* jr, const double2* g, double2* y, int m,
+                       int R, hipStream_t st) {
+  if (R <= 0) return;
+  hipLaunchKernelGGL(dev::k_bbacksolve, dim3(unsigned((R + 63) / 64)), dim3(64), 0, st, H, hs, ldh, jr, g, y, m, R);
+  BEM_HIP(hipGetLastError());
+}
+
+void launch_binit_g(double2* g, int m, const double2* beta, int64_t bstride, int R, hipStream_t st) {
+  if (R <= 0) return;
+  hipLaunchKernelGGL(dev::k_binit_g, dim3(unsigned(R)), dim3(64), 0, st, g, m, beta, bstride);
+  BEM_HIP(hipGetLastError());
+}
+
+void launch_gather_cols(const double2* X, int64_t ldx, double2* U, int64_t ldu, const int* idx, int64_t n, int R,
+                        hipStream_t st) {
+  if (R <= 0 || n <= 0) return;
+  hipLaunchKernelGGL(dev::k_gather_cols, dim3(unsigned((n + 255) / 256), unsigned(R)), dim3(256), 0, st, X, ldx, U,
+                     ldu, idx, n);
+  BEM_HIP(hipGetLastError());
+}
+
+void launch_scatter_cols(const double2* U, int64_t ldu, double2* X, int64_t ldx, const int* idx, int64_t n, int R,
+                         int accumulate, hipStream_t st) {
+  if (R <= 0 || n <= 0) return;
+  hipLaunchKernelGGL(dev::k_scatter_cols, dim3(unsigned((n + 255) / 256), unsigned(R)), dim3(256), 0, st, U, ldu, X,
+                     ldx, idx, n, accumulate);
   BEM_HIP(hipGetLastError());
 }
 

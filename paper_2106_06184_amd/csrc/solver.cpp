@@ -29,6 +29,14 @@ inline double2 c2(double re, double im = 0.0) { return make_double2(re, im); }
 inline double2 c2(cd z) { return make_double2(z.real(), z.imag()); }
 inline int64_t pad64(int64_t n) { return (n + 63) / 64 * 64; }
 
+// Product work vectors: 15 fields per column, each padded to the equivalent-system size.
+constexpr int kWorkFields = 15;
+int64_t work_ld(const OpObj& op) { return pad64(op.Neq); }
+
+// Smallest |k_l| h_max for which the nested solve eliminates the charges (S of build_s): its
+// D^T L^phi D / k0^2 term grows like (k h)^-2 against the L^A term.
+constexpr double kSchurMinKh = 0.01;
+
 // Radon 7-point degree-5 rule (barycentric points, weights summing to 1) and the 3-point rule.
 struct Rules {
   double b7[7][3];
@@ -450,15 +458,25 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
   int64_t max_neq = 0;
   for (int64_t o = 0; o < m.nobj; ++o)
     max_neq = std::max(max_neq, (m.obj_edge[o + 1] - m.obj_edge[o]) + (m.obj_tri[o + 1] - m.obj_tri[o]) - 1);
+  int64_t max_ne = 0;
+  for (int64_t o = 0; o < m.nobj; ++o) max_ne = std::max(max_ne, m.obj_edge[o + 1] - m.obj_edge[o]);
+  const double hmax = *std::max_element(m.hmax.begin(), m.hmax.end());
   op.inner_mode = prob.inner_mode;
-  if (op.inner_mode == BEM_INNER_AUTO) op.inner_mode = max_neq <= 16384 ? BEM_INNER_DIRECT : BEM_INNER_GMRES;
-  if (op.inner_mode != BEM_INNER_DIRECT && op.inner_mode != BEM_INNER_GMRES)
+  if (op.inner_mode == BEM_INNER_AUTO) {
+    // charge elimination while the elements are not electrically tiny (its k0^-2 term sets the
+    // conditioning), the augmented inverse below that, nested GMRES for very large objects
+    const double kh = std::abs(op.kbg) * hmax;
+    if (kh >= kSchurMinKh && max_ne <= 32768) op.inner_mode = BEM_INNER_SCHUR;
+    else if (max_neq <= 16384) op.inner_mode = BEM_INNER_DIRECT;
+    else op.inner_mode = BEM_INNER_GMRES;
+  }
+  if (op.inner_mode != BEM_INNER_DIRECT && op.inner_mode != BEM_INNER_GMRES && op.inner_mode != BEM_INNER_SCHUR)
     throw Error(BEM_E_INVALID, "unknown inner_mode");
   op.precond = prob.precond != 0;
   build_inner_and_precond(op, ixdiag, st);
 
   // ---- work vectors and Krylov spaces
-  op.work_len = 4 * op.Neq + 9 * op.nt + 4 * op.ne + 4 * op.nq + 64;
+  op.work_len = int64_t(kWorkFields) * work_ld(op);
   op.work = op.mem.alloc<double2>(size_t(op.work_len));
   if (op.inner_mode == BEM_INNER_GMRES) {
     op.inner_ws = make_gmres_work(op.mem, op.Neq, op.inner_restart);
@@ -514,6 +532,28 @@ void build_inner_and_precond(OpObj& op, const std::vector<double>& ixdiag, hipSt
       op.mem.release(dtp);
       op.mem.release(dtm);
       op.Minv.push_back(M);
+    }
+  }
+  if (op.inner_mode == BEM_INNER_SCHUR) {
+    for (int64_t o = 0; o < m.nobj; ++o) {
+      const int64_t t0 = m.obj_tri[o];
+      const int64_t e0 = m.obj_edge[o], neo = m.obj_edge[o + 1] - e0;
+      std::vector<int32_t> tpl(neo), tml(neo);
+      for (int64_t k = 0; k < neo; ++k) {
+        tpl[k] = int32_t(m.tp[e0 + k] - t0);
+        tml[k] = int32_t(m.tm[e0 + k] - t0);
+      }
+      int32_t* dtp = op.mem.upload(tpl);
+      int32_t* dtm = op.mem.upload(tml);
+      Dense S = alloc_dense(op.mem, neo, neo, f32);
+      build_s(op.LA_bg.d64 + e0 * op.LA_bg.ld + e0, op.LA_bg.ld, op.Lphi_bg.d64 + t0 * op.Lphi_bg.ld + t0,
+              op.Lphi_bg.ld, dtp, dtm, neo, c2(op.mu_bg), c2(-1.0 / (op.eps_bg * op.k0 * op.k0)), S.d64, S.ld, st);
+      dense_invert(S.d64, neo, S.ld, ds, st);
+      to_f32(S, st);
+      BEM_HIP(hipStreamSynchronize(st));
+      op.mem.release(dtp);
+      op.mem.release(dtm);
+      op.Minv.push_back(S);
     }
   }
   op.SigP.clear();
@@ -605,99 +645,125 @@ void build_inner_and_precond(OpObj& op, const std::vector<double>& ixdiag, hipSt
 // ----------------------------------------------------------------- products
 
 namespace {
-// work vector layout
+// Work vectors of the products for R columns: column c of a field at field + c * ld.
 struct WorkView {
   double2 *rin, *sol, *t1, *z1, *z2, *am, *xw, *mt, *mz;
   double2 *pc_t, *pc_z, *pc_v, *eq_t, *eq_z, *eq_v;
+  int64_t ld = 0;
+  int R = 1;
+  void* gws = nullptr;  // matrix-core GEMM workspace (R > 1)
+  size_t gws_bytes = 0;
 };
-WorkView views(OpObj& op) {
-  double2* p = op.work;
+WorkView slice_work(double2* base, int64_t ld, int R) {
   WorkView v;
-  v.rin = p; p += op.Neq;
-  v.sol = p; p += op.Neq;
-  v.t1 = p; p += op.nt;
-  v.z1 = p; p += op.nt;
-  v.z2 = p; p += op.nt;
-  v.am = p; p += op.ne;
-  v.xw = p; p += op.nq;
-  v.mt = p; p += op.nt;
-  v.mz = p; p += op.nt;
-  v.pc_t = p; p += op.ne;
-  v.pc_z = p; p += op.nq;
-  v.pc_v = p; p += op.nt;
-  v.eq_t = p; p += op.ne;
-  v.eq_z = p; p += op.nq;
-  v.eq_v = p; p += op.nt;
+  double2** f[kWorkFields] = {&v.rin,  &v.sol,  &v.t1,   &v.z1,   &v.z2,   &v.am,   &v.xw,  &v.mt,
+                              &v.mz,   &v.pc_t, &v.pc_z, &v.pc_v, &v.eq_t, &v.eq_z, &v.eq_v};
+  for (int i = 0; i < kWorkFields; ++i) *f[i] = base + int64_t(i) * R * ld;
+  v.ld = ld;
+  v.R = R;
   return v;
 }
-}  // namespace
 
-// Block preconditioner of the final system (eq. pcext) applied to r = [r1; r2; r3]:
+// Column c of a batched view, as a one-column view.
+WorkView column_view(const WorkView& w, int c) {
+  WorkView v = w;
+  double2** f[kWorkFields] = {&v.rin,  &v.sol,  &v.t1,   &v.z1,   &v.z2,   &v.am,   &v.xw,  &v.mt,
+                              &v.mz,   &v.pc_t, &v.pc_z, &v.pc_v, &v.eq_t, &v.eq_z, &v.eq_v};
+  for (int i = 0; i < kWorkFields; ++i) *f[i] += int64_t(c) * w.ld;
+  v.R = 1;
+  return v;
+}
+
+WorkView views(OpObj& op) { return slice_work(op.work, work_ld(op), 1); }
+
+// Work of R-column products, owned by `mem`.
+WorkView batch_views(OpObj& op, DevArena& mem, int R) {
+  WorkView v = slice_work(mem.alloc<double2>(size_t(kWorkFields) * R * work_ld(op)), work_ld(op), R);
+  if (R > 1) {
+    v.gws_bytes = gemm_workspace_bytes(std::max(op.ne, op.nt), R);
+    v.gws = mem.alloc<char>(v.gws_bytes);
+  }
+  return v;
+}
+
+GemvDesc with_ld(GemvDesc d, int64_t ldx, int64_t ldy, int64_t ldx2 = 0) {
+  d.ldx = ldx;
+  d.ldy = ldy;
+  d.ldx2 = ldx2;
+  return d;
+}
+
+// Block preconditioner of the final system (eq. pcext) applied to the R columns of
+// r = [r1; r2; r3] (column stride ld; x likewise):
 //   x3 = Sigma_P^-1 (r3 - F D (W11 r1 + W12 r2)),  [x1; x2] = W ([r1; r2] - [S1; S2] x3)
-void apply_precond(OpObj& op, const double2* r, double2* x, bool fp32, hipStream_t st) {
-  WorkView wv = views(op);
-  const int64_t ne = op.ne;
+void precond_cols(OpObj& op, const WorkView& wv, const double2* r, double2* x, int64_t ld, bool fp32,
+                  hipStream_t st) {
+  const int R = wv.R;
+  const int64_t ne = op.ne, L = wv.ld;
   const double2 *r1 = r, *r2 = r + ne, *r3 = r + 2 * ne;
   double2 *x1 = x, *x2 = x + ne, *x3 = x + 2 * ne;
-  launch_pc_stage1(op.pcW, r1, r2, ne, wv.pc_t, st);
-  launch_FD(wv.pc_t, op.tri_edge, op.tri_sign, op.kept, op.nq, c2(-1.0), r3, c2(1.0), wv.pc_z, st);
+  launch_pc_stage1(op.pcW, r1, r2, ne, wv.pc_t, st, R, ld, L);
+  launch_FD(wv.pc_t, op.tri_edge, op.tri_sign, op.kept, op.nq, c2(-1.0), r3, c2(1.0), wv.pc_z, st, R, L, ld, L);
   std::vector<GemvDesc> ds;
   for (int64_t o = 0; o < op.nobj; ++o) {
     const int64_t q0 = op.obj_q[o], nq = op.obj_q[o + 1] - q0;
-    ds.push_back(desc(op.SigP[o], fp32, 0, 0, nq, nq, wv.pc_z + q0, x3 + q0, c2(1.0), 0));
+    ds.push_back(with_ld(desc(op.SigP[o], fp32, 0, 0, nq, nq, wv.pc_z + q0, x3 + q0, c2(1.0), 0), L, ld));
   }
-  launch_gemv_grouped(ds.data(), int(ds.size()), st);
-  launch_expand_charge(x3, wv.pc_v, op.obj_tri_d, op.nobj, c2(1.0), st);
+  launch_products(ds, R, wv.gws, wv.gws_bytes, st);
+  launch_expand_charge(x3, wv.pc_v, op.obj_tri_d, op.nobj, c2(1.0), st, R, ld, L);
   launch_pc_stage2(op.pcW, r1, r2, wv.pc_v, op.lam_bg, op.lam_int, c2(1.0 / op.eps_bg), op.eps_inv_edge, op.tp,
-                   op.tm, ne, x1, x2, st);
+                   op.tm, ne, x1, x2, st, R, ld, L);
 }
 
 // Equivalent-configuration counterpart for the nested GMRES (diagonal L blocks, exact charge
 // constraint): x2 = Sigma_eq^-1 (r2 - F D d r1), x1 = d (r1 + eps_l^-1 D^T diag(L^phi_l) B x2)
-void apply_precond_eq(OpObj& op, const double2* r, double2* x, bool fp32, hipStream_t st) {
-  WorkView wv = views(op);
-  const int64_t ne = op.ne;
+void precond_eq_cols(OpObj& op, const WorkView& wv, const double2* r, double2* x, int64_t ld, bool fp32,
+                     hipStream_t st) {
+  const int R = wv.R;
+  const int64_t ne = op.ne, L = wv.ld;
   const double2 *r1 = r, *r2 = r + ne;
   double2 *x1 = x, *x2 = x + ne;
-  launch_peq_stage1(op.eq_d, r1, ne, wv.eq_t, st);
-  launch_FD(wv.eq_t, op.tri_edge, op.tri_sign, op.kept, op.nq, c2(-1.0), r2, c2(1.0), wv.eq_z, st);
+  launch_peq_stage1(op.eq_d, r1, ne, wv.eq_t, st, R, ld, L);
+  launch_FD(wv.eq_t, op.tri_edge, op.tri_sign, op.kept, op.nq, c2(-1.0), r2, c2(1.0), wv.eq_z, st, R, L, ld, L);
   std::vector<GemvDesc> ds;
   for (int64_t o = 0; o < op.nobj; ++o) {
     const int64_t q0 = op.obj_q[o], nq = op.obj_q[o + 1] - q0;
-    ds.push_back(desc(op.SigEq[o], fp32, 0, 0, nq, nq, wv.eq_z + q0, x2 + q0, c2(1.0), 0));
+    ds.push_back(with_ld(desc(op.SigEq[o], fp32, 0, 0, nq, nq, wv.eq_z + q0, x2 + q0, c2(1.0), 0), L, ld));
   }
-  launch_gemv_grouped(ds.data(), int(ds.size()), st);
-  launch_expand_charge(x2, wv.eq_v, op.obj_tri_d, op.nobj, c2(1.0), st);
-  launch_peq_stage2(op.eq_d, wv.eq_t, wv.eq_v, op.lam_bg, c2(1.0 / op.eps_bg), op.tp, op.tm, ne, x1, st);
+  launch_products(ds, R, wv.gws, wv.gws_bytes, st);
+  launch_expand_charge(x2, wv.eq_v, op.obj_tri_d, op.nobj, c2(1.0), st, R, ld, L);
+  launch_peq_stage2(op.eq_d, wv.eq_t, wv.eq_v, op.lam_bg, c2(1.0 / op.eps_bg), op.tp, op.tm, ne, x1, st, R, ld, L);
 }
-
-namespace {
-}  // namespace
 
 // Equivalent-configuration matrix (eq. AEFIEeqvdis), block-diagonal over objects:
 //   y_u = mu_l L^A_l u - eps_l^-1 D^T L^phi_l B w ;  y_w = F D u - k0^2 w
-void apply_meq(OpObj& op, const double2* x, double2* y, bool fp32, hipStream_t st) {
-  WorkView wv = views(op);
+void meq_cols(OpObj& op, const WorkView& wv, const double2* x, int64_t ldx, double2* y, int64_t ldy, bool fp32,
+              hipStream_t st) {
+  const int R = wv.R;
+  const int64_t L = wv.ld;
   const double2* u = x;
   const double2* w = x + op.ne;
   double2* yu = y;
   double2* yw = y + op.ne;
-  launch_expand_charge(w, wv.mt, op.obj_tri_d, op.nobj, c2(1.0), st);
+  launch_expand_charge(w, wv.mt, op.obj_tri_d, op.nobj, c2(1.0), st, R, ldx, L);
   std::vector<GemvDesc> ds;
   for (int64_t o = 0; o < op.nobj; ++o) {
     const int64_t t0 = op.obj_tri[o], nto = op.obj_tri[o + 1] - t0;
     const int64_t e0 = op.obj_edge[o], neo = op.obj_edge[o + 1] - e0;
-    ds.push_back(desc(op.Lphi_bg, fp32, t0, t0, nto, nto, wv.mt + t0, wv.mz + t0, c2(1.0), 0));
-    ds.push_back(desc(op.LA_bg, fp32, e0, e0, neo, neo, u + e0, yu + e0, c2(op.mu_bg), 0));
+    ds.push_back(with_ld(desc(op.Lphi_bg, fp32, t0, t0, nto, nto, wv.mt + t0, wv.mz + t0, c2(1.0), 0), L, L));
+    ds.push_back(with_ld(desc(op.LA_bg, fp32, e0, e0, neo, neo, u + e0, yu + e0, c2(op.mu_bg), 0), ldx, ldy));
   }
-  launch_gemv_grouped(ds.data(), int(ds.size()), st);
-  launch_DT(wv.mz, op.tp, op.tm, op.ne, c2(-1.0 / op.eps_bg), nullptr, yu, 1, st);
-  launch_FD(u, op.tri_edge, op.tri_sign, op.kept, op.nq, c2(1.0), w, c2(-op.k0 * op.k0), yw, st);
+  launch_products(ds, R, wv.gws, wv.gws_bytes, st);
+  launch_DT(wv.mz, op.tp, op.tm, op.ne, c2(-1.0 / op.eps_bg), nullptr, yu, 1, st, R, L, ldy);
+  launch_FD(u, op.tri_edge, op.tri_sign, op.kept, op.nq, c2(1.0), w, c2(-op.k0 * op.k0), yw, st, R, ldx, ldx, ldy);
 }
 
-void apply_final(OpObj& op, const double2* x, double2* y, bool fp32, double inner_tol, hipStream_t st) {
-  WorkView wv = views(op);
-  const int64_t ne = op.ne, nq = op.nq;
+// Final system (eq. finalsystem) on R columns; the nested solve [u; w] = M_eq^-1 [r_in; 0]
+// runs for every column (directly, or by nested GMRES column by column).
+void final_cols(OpObj& op, const WorkView& wv, const double2* x, int64_t ldx, double2* y, int64_t ldy, bool fp32,
+                double inner_tol, hipStream_t st) {
+  const int R = wv.R;
+  const int64_t ne = op.ne, nq = op.nq, L = wv.ld;
   const double2* a = x;
   const double2* e = x + ne;
   const double2* x3 = x + 2 * ne;
@@ -705,23 +771,23 @@ void apply_final(OpObj& op, const double2* x, double2* y, bool fp32, double inne
   double2* y2 = y + ne;
   double2* y3 = y + 2 * ne;
   // B x3 for the interior charge term
-  launch_expand_charge(x3, wv.t1, op.obj_tri_d, op.nobj, c2(1.0), st);
+  launch_expand_charge(x3, wv.t1, op.obj_tri_d, op.nobj, c2(1.0), st, R, ldx, L);
   std::vector<GemvDesc> ds;
   for (int64_t o = 0; o < op.nobj; ++o) {
     const int64_t t0 = op.obj_tri[o], nto = op.obj_tri[o + 1] - t0;
     const int64_t e0 = op.obj_edge[o], neo = op.obj_edge[o + 1] - e0;
     // r_in = K~_l e ;  y2 = mu_r L^A a - K~ e ;  z1 = L^phi B x3
-    ds.push_back(desc(op.K_bg[o], fp32, 0, 0, neo, neo, e + e0, wv.rin + e0, c2(1.0), 0));
+    ds.push_back(with_ld(desc(op.K_bg[o], fp32, 0, 0, neo, neo, e + e0, wv.rin + e0, c2(1.0), 0), ldx, L));
     GemvDesc d2 = desc(op.LA_int[o], fp32, 0, 0, neo, neo, a + e0, y2 + e0, c2(op.mur[o]), 0);
     add_second(d2, op.K_int[o], fp32, 0, 0, e + e0, c2(-1.0));
-    ds.push_back(d2);
-    ds.push_back(desc(op.Lphi_int[o], fp32, 0, 0, nto, nto, wv.t1 + t0, wv.z1 + t0, c2(1.0), 0));
+    ds.push_back(with_ld(d2, ldx, ldy, ldx));
+    ds.push_back(with_ld(desc(op.Lphi_int[o], fp32, 0, 0, nto, nto, wv.t1 + t0, wv.z1 + t0, c2(1.0), 0), L, L));
   }
-  launch_gemv_grouped(ds.data(), int(ds.size()), st);
+  launch_products(ds, R, wv.gws, wv.gws_bytes, st);
   // r_in += I_x e / 2 ; y2 += -I_x e / 2 + eps_c^-1 D^T z1
-  launch_spmv(op.ix_ptr, op.ix_idx, op.ix_val, ne, e, c2(0.5), wv.rin, 1, st);
-  launch_spmv(op.ix_ptr, op.ix_idx, op.ix_val, ne, e, c2(-0.5), y2, 1, st);
-  launch_DT(wv.z1, op.tp, op.tm, ne, c2(1.0), op.eps_inv_edge, y2, 1, st);
+  launch_spmv(op.ix_ptr, op.ix_idx, op.ix_val, ne, e, c2(0.5), wv.rin, 1, st, R, ldx, L);
+  launch_spmv(op.ix_ptr, op.ix_idx, op.ix_val, ne, e, c2(-0.5), y2, 1, st, R, ldx, ldy);
+  launch_DT(wv.z1, op.tp, op.tm, ne, c2(1.0), op.eps_inv_edge, y2, 1, st, R, L, ldy);
   // nested solve M_eq [u; w] = [r_in; 0]
   if (op.inner_mode == BEM_INNER_DIRECT) {
     // [u_o; w_o] = M_eq,o^-1 [r_in,o; 0]: only the edge columns of the inverse are read
@@ -729,37 +795,76 @@ void apply_final(OpObj& op, const double2* x, double2* y, bool fp32, double inne
     for (int64_t o = 0; o < op.nobj; ++o) {
       const int64_t e0 = op.obj_edge[o], neo = op.obj_edge[o + 1] - e0;
       const int64_t q0 = op.obj_q[o], nqo = op.obj_q[o + 1] - q0;
-      di.push_back(desc(op.Minv[o], fp32, 0, 0, neo, neo, wv.rin + e0, wv.sol + e0, c2(1.0), 0));
-      di.push_back(desc(op.Minv[o], fp32, neo, 0, nqo, neo, wv.rin + e0, wv.sol + ne + q0, c2(1.0), 0));
+      di.push_back(with_ld(desc(op.Minv[o], fp32, 0, 0, neo, neo, wv.rin + e0, wv.sol + e0, c2(1.0), 0), L, L));
+      di.push_back(
+          with_ld(desc(op.Minv[o], fp32, neo, 0, nqo, neo, wv.rin + e0, wv.sol + ne + q0, c2(1.0), 0), L, L));
     }
-    launch_gemv_grouped(di.data(), int(di.size()), st);
+    launch_products(di, R, wv.gws, wv.gws_bytes, st);
+    op.last_inner_iters = 0;
+  } else if (op.inner_mode == BEM_INNER_SCHUR) {
+    // u = S^-1 r_in with the charges eliminated, then w = k0^-2 F D u
+    std::vector<GemvDesc> di;
+    for (int64_t o = 0; o < op.nobj; ++o) {
+      const int64_t e0 = op.obj_edge[o], neo = op.obj_edge[o + 1] - e0;
+      di.push_back(with_ld(desc(op.Minv[o], fp32, 0, 0, neo, neo, wv.rin + e0, wv.sol + e0, c2(1.0), 0), L, L));
+    }
+    launch_products(di, R, wv.gws, wv.gws_bytes, st);
+    launch_FD(wv.sol, op.tri_edge, op.tri_sign, op.kept, nq, c2(1.0 / (op.k0 * op.k0)), nullptr, c2(0.0),
+              wv.sol + ne, st, R, L, 0, L);
     op.last_inner_iters = 0;
   } else {
-    launch_axpby(nq, c2(0.0), nullptr, c2(0.0), nullptr, wv.rin + ne, st);
-    ApplyFn meq = [&op, fp32, st](const double2* xi, double2* yi) { apply_meq(op, xi, yi, fp32, st); };
-    ApplyFn peq = [&op, fp32, st](const double2* xi, double2* yi) { apply_precond_eq(op, xi, yi, fp32, st); };
-    GmresResult gr = gmres(*op.inner_ws, op.pinned, meq, wv.rin, wv.sol, true, inner_tol, op.inner_maxit, st,
-                           op.precond ? &peq : nullptr);
-    op.last_inner_iters = gr.iters;
-    op.max_inner_iters = std::max(op.max_inner_iters, gr.iters);
-    if (verbose()) std::fprintf(stderr, "[bem] inner its %d res %.3e\n", gr.iters, gr.relres);
+    launch_axpby(nq, c2(0.0), nullptr, c2(0.0), nullptr, wv.rin + ne, st, R, 0, 0, L);
+    for (int c = 0; c < R; ++c) {
+      const WorkView cv = column_view(wv, c);
+      ApplyFn meq = [&op, cv, fp32, st](const double2* xi, double2* yi) { meq_cols(op, cv, xi, 0, yi, 0, fp32, st); };
+      ApplyFn peq = [&op, cv, fp32, st](const double2* xi, double2* yi) {
+        precond_eq_cols(op, cv, xi, yi, 0, fp32, st);
+      };
+      GmresResult gr = gmres(*op.inner_ws, op.pinned, meq, cv.rin, cv.sol, true, inner_tol, op.inner_maxit, st,
+                             op.precond ? &peq : nullptr);
+      op.last_inner_iters = gr.iters;
+      op.max_inner_iters = std::max(op.max_inner_iters, gr.iters);
+      if (verbose()) std::fprintf(stderr, "[bem] inner its %d res %.3e\n", gr.iters, gr.relres);
+    }
   }
   const double2* u = wv.sol;
   const double2* w = wv.sol + ne;
   // a - u, x3 + w, B (x3 + w)
-  launch_axpby(ne, c2(1.0), a, c2(-1.0), u, wv.am, st);
-  launch_axpby(nq, c2(1.0), x3, c2(1.0), w, wv.xw, st);
-  launch_expand_charge(wv.xw, wv.t1, op.obj_tri_d, op.nobj, c2(1.0), st);
-  GemvDesc g2[2] = {desc(op.LA_bg, fp32, 0, 0, ne, ne, wv.am, y1, c2(op.mu_bg), 0),
-                    desc(op.Lphi_bg, fp32, 0, 0, op.nt, op.nt, wv.t1, wv.z2, c2(1.0), 0)};
-  launch_gemv_grouped(g2, 2, st);
+  launch_axpby(ne, c2(1.0), a, c2(-1.0), u, wv.am, st, R, ldx, L, L);
+  launch_axpby(nq, c2(1.0), x3, c2(1.0), w, wv.xw, st, R, ldx, L, L);
+  launch_expand_charge(wv.xw, wv.t1, op.obj_tri_d, op.nobj, c2(1.0), st, R, L, L);
+  std::vector<GemvDesc> g2 = {with_ld(desc(op.LA_bg, fp32, 0, 0, ne, ne, wv.am, y1, c2(op.mu_bg), 0), L, ldy),
+                              with_ld(desc(op.Lphi_bg, fp32, 0, 0, op.nt, op.nt, wv.t1, wv.z2, c2(1.0), 0), L, L)};
+  launch_products(g2, R, wv.gws, wv.gws_bytes, st);
   // y1 += eps_l^-1 D^T z2 + I_x e ;  y3 = F D (a - u) + k0^2 (x3 + w)
-  launch_DT(wv.z2, op.tp, op.tm, ne, c2(1.0 / op.eps_bg), nullptr, y1, 1, st);
-  launch_spmv(op.ix_ptr, op.ix_idx, op.ix_val, ne, e, c2(1.0), y1, 1, st);
-  launch_FD(wv.am, op.tri_edge, op.tri_sign, op.kept, nq, c2(1.0), wv.xw, c2(op.k0 * op.k0), y3, st);
+  launch_DT(wv.z2, op.tp, op.tm, ne, c2(1.0 / op.eps_bg), nullptr, y1, 1, st, R, L, ldy);
+  launch_spmv(op.ix_ptr, op.ix_idx, op.ix_val, ne, e, c2(1.0), y1, 1, st, R, ldx, ldy);
+  launch_FD(wv.am, op.tri_edge, op.tri_sign, op.kept, nq, c2(1.0), wv.xw, c2(op.k0 * op.k0), y3, st, R, L, L, ldy);
 }
 
-void apply_block(OpObj& op, int block, const double2* x, double2* y, hipStream_t st) {
+}  // namespace
+
+void apply_precond(OpObj& op, const double2* r, double2* x, bool fp32, hipStream_t st) {
+  precond_cols(op, views(op), r, x, 0, fp32, st);
+}
+
+void apply_precond_eq(OpObj& op, const double2* r, double2* x, bool fp32, hipStream_t st) {
+  precond_eq_cols(op, views(op), r, x, 0, fp32, st);
+}
+
+void apply_meq(OpObj& op, const double2* x, double2* y, bool fp32, hipStream_t st) {
+  meq_cols(op, views(op), x, 0, y, 0, fp32, st);
+}
+
+void apply_final(OpObj& op, const double2* x, double2* y, bool fp32, double inner_tol, hipStream_t st) {
+  final_cols(op, views(op), x, 0, y, 0, fp32, inner_tol, st);
+}
+
+void apply_block(OpObj& op, int block, const double2* x, double2* y, int64_t nrhs, hipStream_t st) {
+  if (nrhs <= 0) return;
+  const int R = int(nrhs);
+  DevArena tmp(op.ctx);
+  const WorkView wv = R == 1 ? views(op) : batch_views(op, tmp, R);
   std::vector<GemvDesc> ds;
   switch (block) {
     case BEM_BLOCK_LA_INT:
@@ -768,34 +873,36 @@ void apply_block(OpObj& op, int block, const double2* x, double2* y, hipStream_t
       for (int64_t o = 0; o < op.nobj; ++o) {
         const int64_t e0 = op.obj_edge[o], neo = op.obj_edge[o + 1] - e0;
         const Dense& A = block == BEM_BLOCK_LA_INT ? op.LA_int[o] : block == BEM_BLOCK_K_INT ? op.K_int[o] : op.K_bg[o];
-        ds.push_back(desc(A, false, 0, 0, neo, neo, x + e0, y + e0, c2(1.0), 0));
+        ds.push_back(with_ld(desc(A, false, 0, 0, neo, neo, x + e0, y + e0, c2(1.0), 0), op.ne, op.ne));
       }
       break;
     case BEM_BLOCK_LPHI_INT:
       for (int64_t o = 0; o < op.nobj; ++o) {
         const int64_t t0 = op.obj_tri[o], nto = op.obj_tri[o + 1] - t0;
-        ds.push_back(desc(op.Lphi_int[o], false, 0, 0, nto, nto, x + t0, y + t0, c2(1.0), 0));
+        ds.push_back(with_ld(desc(op.Lphi_int[o], false, 0, 0, nto, nto, x + t0, y + t0, c2(1.0), 0), op.nt, op.nt));
       }
       break;
     case BEM_BLOCK_LA_BG:
-      ds.push_back(desc(op.LA_bg, false, 0, 0, op.ne, op.ne, x, y, c2(1.0), 0));
+      ds.push_back(with_ld(desc(op.LA_bg, false, 0, 0, op.ne, op.ne, x, y, c2(1.0), 0), op.ne, op.ne));
       break;
     case BEM_BLOCK_LPHI_BG:
-      ds.push_back(desc(op.Lphi_bg, false, 0, 0, op.nt, op.nt, x, y, c2(1.0), 0));
+      ds.push_back(with_ld(desc(op.Lphi_bg, false, 0, 0, op.nt, op.nt, x, y, c2(1.0), 0), op.nt, op.nt));
       break;
     case BEM_BLOCK_IX:
-      launch_spmv(op.ix_ptr, op.ix_idx, op.ix_val, op.ne, x, c2(1.0), y, 0, st);
-      return;
+      launch_spmv(op.ix_ptr, op.ix_idx, op.ix_val, op.ne, x, c2(1.0), y, 0, st, R, op.ne, op.ne);
+      break;
     case BEM_BLOCK_MEQ:
-      apply_meq(op, x, y, false, st);
-      return;
+      meq_cols(op, wv, x, op.Neq, y, op.Neq, false, st);
+      break;
     case BEM_BLOCK_FINAL:
-      apply_final(op, x, y, false, op.inner_tol, st);
-      return;
+      final_cols(op, wv, x, op.N, y, op.N, false, op.inner_tol, st);
+      break;
     default:
       throw Error(BEM_E_INVALID, "unknown block");
   }
-  launch_gemv_grouped(ds.data(), int(ds.size()), st);
+  launch_products(ds, R, wv.gws, wv.gws_bytes, st);
+  // the batch work is freed on return: let the launches that read it finish first
+  if (R > 1) BEM_HIP(hipStreamSynchronize(st));
 }
 
 void export_block(OpObj& op, int block, bem_c64* host) {
@@ -826,7 +933,7 @@ void export_block(OpObj& op, int block, bem_c64* host) {
       copy_dense(op.Lphi_bg, 0, 0, op.nt);
       return;
     case BEM_BLOCK_MEQ_INV: {
-      if (op.inner_mode != BEM_INNER_DIRECT) throw Error(BEM_E_INVALID, "no inverse: the nested solve is iterative");
+      if (op.inner_mode != BEM_INNER_DIRECT) throw Error(BEM_E_INVALID, "M_eq^-1 is formed only by the augmented direct nested solve");
       std::memset(host, 0, sizeof(bem_c64) * op.Neq * op.Neq);
       // object o occupies rows/columns: edges [e0, e0+ne_o) and charges ne + [q0, q0+nq_o)
       for (int64_t o = 0; o < op.nobj; ++o) {
@@ -974,21 +1081,217 @@ GmresResult gmres(GmresWork& w, double* ctx, const ApplyFn& A, const double2* b,
   return res;
 }
 
+// ----------------------------------------------------------------- batched GMRES
+
+namespace {
+
+using BApplyFn = std::function<void(const double2* x, int64_t ldx, double2* y, int64_t ldy, int R)>;
+
+// Krylov state of R independent restarted GMRES runs that share their operator products:
+// basis vector i of column c at V + (i R + c) ldv, so every step's R vectors form one n x R
+// column-major block for the matrix-core products.
+struct BGmres {
+  int64_t n = 0, ldv = 0, hs = 0, ldh = 0;
+  int m = 0, Rmax = 0;
+  double2 *V = nullptr, *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr, *y = nullptr, *h2 = nullptr;
+  double2 *nrm = nullptr, *part = nullptr, *Z = nullptr, *U = nullptr, *T = nullptr;
+  double* res = nullptr;
+  int *d_frozen = nullptr, *d_jr = nullptr, *d_idx = nullptr;
+  // pinned host mirrors
+  double2* h_nrm = nullptr;
+  double* h_res = nullptr;
+  int *h_frozen = nullptr, *h_jr = nullptr, *h_idx = nullptr;
+  void* pin = nullptr;
+  BGmres(DevArena& mem, int64_t n_, int m_, int R) : n(n_), m(m_), Rmax(R) {
+    ldv = pad64(n);
+    ldh = m + 2;
+    hs = int64_t(m + 1) * ldh;
+    V = mem.alloc<double2>(size_t(m + 1) * R * ldv);
+    H = mem.alloc<double2>(size_t(R) * hs);
+    cs = mem.alloc<double2>(size_t(R) * (m + 1));
+    sn = mem.alloc<double2>(size_t(R) * (m + 1));
+    y = mem.alloc<double2>(size_t(R) * (m + 1));
+    g = mem.alloc<double2>(size_t(R) * (m + 2));
+    h2 = mem.alloc<double2>(size_t(R) * (m + 2));
+    nrm = mem.alloc<double2>(R);
+    part = mem.alloc<double2>(size_t(R) * (m + 1) * bkry_chunks(n));
+    Z = mem.alloc<double2>(size_t(R) * ldv);
+    U = mem.alloc<double2>(size_t(R) * ldv);
+    T = mem.alloc<double2>(size_t(R) * ldv);
+    res = mem.alloc<double>(R);
+    d_frozen = mem.alloc<int>(R);
+    d_jr = mem.alloc<int>(R);
+    d_idx = mem.alloc<int>(R);
+    const size_t pin_bytes = size_t(R) * (sizeof(double2) + sizeof(double) + 3 * sizeof(int)) + 64;
+    BEM_HIP(hipHostMalloc(&pin, pin_bytes, hipHostMallocDefault));
+    char* p = static_cast<char*>(pin);
+    h_nrm = reinterpret_cast<double2*>(p);
+    p += sizeof(double2) * R;
+    h_res = reinterpret_cast<double*>(p);
+    p += sizeof(double) * R;
+    h_frozen = reinterpret_cast<int*>(p);
+    h_jr = h_frozen + R;
+    h_idx = h_jr + R;
+  }
+  BGmres(const BGmres&) = delete;
+  ~BGmres() {
+    if (pin) (void)hipHostFree(pin);
+  }
+  void upload(int* d, const int* h, int R, hipStream_t st) {
+    BEM_HIP(hipMemcpyAsync(d, h, sizeof(int) * R, hipMemcpyHostToDevice, st));
+  }
+  // column norms of X (n x R, ldx) into h_nrm
+  void norms(const double2* X, int64_t ldx, int R, hipStream_t st) {
+    launch_bnorm(X, ldx, R, n, part, nrm, 1, st);
+    BEM_HIP(hipMemcpyAsync(h_nrm, nrm, sizeof(double2) * R, hipMemcpyDeviceToHost, st));
+    BEM_HIP(hipStreamSynchronize(st));
+  }
+};
+
+struct BResult {
+  std::vector<int> iters;        // Arnoldi steps taken by each column
+  std::vector<double> relres;    // estimated relative residual of each column
+  std::vector<char> converged;
+  int products = 0;              // batched operator products
+};
+
+// Restarted GMRES (CGS2 Arnoldi, complex Givens, float64) for the R0 columns of B (n x R0,
+// ldb) at once; X (ldx) is zeroed and receives the solutions.  Every Arnoldi step applies A
+// (and the right preconditioner M) to the block of the still-active columns in one call.
+// A column stops contributing basis vectors once its estimated residual reaches tol; at
+// every restart the unconverged columns are compacted.
+BResult gmres_batched(BGmres& w, const BApplyFn& A, const double2* B, int64_t ldb, double2* X, int64_t ldx, int R0,
+                      double tol, int maxit, hipStream_t st, const BApplyFn* M) {
+  BResult out;
+  out.iters.assign(R0, 0);
+  out.relres.assign(R0, 0.0);
+  out.converged.assign(R0, 0);
+  if (R0 > w.Rmax) throw Error(BEM_E_INVALID, "batch wider than its Krylov state");
+  const int64_t n = w.n, ldv = w.ldv;
+  const int m = w.m;
+  w.norms(B, ldb, R0, st);
+  std::vector<double> bn(R0);
+  std::vector<int> active;
+  for (int c = 0; c < R0; ++c) {
+    bn[c] = w.h_nrm[c].x;
+    if (!std::isfinite(bn[c])) throw Error(BEM_E_NUMERIC, "non-finite right-hand side");
+    if (bn[c] > 0) active.push_back(c);
+    else out.converged[c] = 1;
+  }
+  launch_axpby(n, c2(0.0), nullptr, c2(0.0), nullptr, X, st, R0, 0, 0, ldx);
+  int total = 0;  // batched Arnoldi steps
+  bool first = true;
+  while (!active.empty()) {
+    const int Rc = int(active.size());
+    for (int c = 0; c < Rc; ++c) w.h_idx[c] = active[c];
+    w.upload(w.d_idx, w.h_idx, Rc, st);
+    // residual block V_0 = B - A X over the active columns
+    double2* V0 = w.V;
+    launch_gather_cols(B, ldb, V0, ldv, w.d_idx, n, Rc, st);
+    if (!first) {
+      launch_gather_cols(X, ldx, w.U, ldv, w.d_idx, n, Rc, st);
+      A(w.U, ldv, w.T, ldv, Rc);
+      ++out.products;
+      launch_axpby(n, c2(1.0), V0, c2(-1.0), w.T, V0, st, Rc, ldv, ldv, ldv);
+    }
+    first = false;
+    w.norms(V0, ldv, Rc, st);
+    int live = 0;
+    for (int c = 0; c < Rc; ++c) {
+      const int col = active[c];
+      const double beta = w.h_nrm[c].x;
+      if (!std::isfinite(beta)) throw Error(BEM_E_NUMERIC, "non-finite residual in GMRES");
+      out.relres[col] = beta / bn[col];
+      w.h_frozen[c] = out.relres[col] <= tol ? 1 : 0;
+      w.h_jr[c] = 0;
+      if (w.h_frozen[c]) out.converged[col] = 1;
+      else ++live;
+    }
+    if (live == 0 || total >= maxit) break;
+    w.upload(w.d_frozen, w.h_frozen, Rc, st);
+    launch_bscale_inv(V0, ldv, Rc, n, w.nrm, 1, w.d_frozen, st);
+    launch_binit_g(w.g, m, w.nrm, 1, Rc, st);
+    int j = 0;
+    for (; j < m && total < maxit; ++j) {
+      double2* Vj = w.V + int64_t(j) * Rc * ldv;
+      double2* Vn = w.V + int64_t(j + 1) * Rc * ldv;
+      double2* Hj = w.H + int64_t(j) * w.ldh;
+      if (M) {
+        (*M)(Vj, ldv, w.Z, ldv, Rc);
+        A(w.Z, ldv, Vn, ldv, Rc);
+      } else {
+        A(Vj, ldv, Vn, ldv, Rc);
+      }
+      ++out.products;
+      launch_bmdot(w.V, ldv, Rc, j + 1, Vn, ldv, n, w.part, Hj, w.hs, st);
+      launch_bmupdate(w.V, ldv, Rc, j + 1, nullptr, Hj, w.hs, -1.0, Vn, ldv, n, st);
+      launch_bmdot(w.V, ldv, Rc, j + 1, Vn, ldv, n, w.part, w.h2, m + 2, st);
+      launch_bmupdate(w.V, ldv, Rc, j + 1, nullptr, w.h2, m + 2, -1.0, Vn, ldv, n, st);
+      launch_bnorm(Vn, ldv, Rc, n, w.part, Hj + j + 1, w.hs, st);
+      launch_bscale_inv(Vn, ldv, Rc, n, Hj + j + 1, w.hs, w.d_frozen, st);
+      launch_bgivens(w.H, w.hs, w.ldh, j, w.cs, w.sn, w.g, w.res, w.h2, m, Rc, st);
+      ++total;
+      BEM_HIP(hipMemcpyAsync(w.h_res, w.res, sizeof(double) * Rc, hipMemcpyDeviceToHost, st));
+      BEM_HIP(hipStreamSynchronize(st));
+      bool changed = false;
+      for (int c = 0; c < Rc; ++c) {
+        if (w.h_frozen[c]) continue;
+        const int col = active[c];
+        const double rr = w.h_res[c] / bn[col];
+        if (!std::isfinite(rr)) throw Error(BEM_E_NUMERIC, "non-finite Arnoldi residual");
+        ++out.iters[col];
+        out.relres[col] = rr;
+        if (rr <= tol) {
+          w.h_frozen[c] = 1;
+          w.h_jr[c] = j + 1;
+          out.converged[col] = 1;
+          --live;
+          changed = true;
+        }
+      }
+      if (verbose()) std::fprintf(stderr, "[bem] batched step %d: %d of %d columns active\n", total, live, Rc);
+      if (live == 0) {
+        ++j;
+        break;
+      }
+      if (changed) w.upload(w.d_frozen, w.h_frozen, Rc, st);
+    }
+    for (int c = 0; c < Rc; ++c)
+      if (!w.h_frozen[c]) w.h_jr[c] = j;
+    w.upload(w.d_jr, w.h_jr, Rc, st);
+    launch_bbacksolve(w.H, w.hs, w.ldh, w.d_jr, w.g, w.y, m, Rc, st);
+    // X[:, active] += M (V y)
+    launch_axpby(n, c2(0.0), nullptr, c2(0.0), nullptr, w.U, st, Rc, 0, 0, ldv);
+    launch_bmupdate(w.V, ldv, Rc, 0, w.d_jr, w.y, m + 1, +1.0, w.U, ldv, n, st);
+    if (M) {
+      (*M)(w.U, ldv, w.T, ldv, Rc);
+      launch_scatter_cols(w.T, ldv, X, ldx, w.d_idx, n, Rc, 1, st);
+    } else {
+      launch_scatter_cols(w.U, ldv, X, ldx, w.d_idx, n, Rc, 1, st);
+    }
+    BEM_HIP(hipStreamSynchronize(st));
+    std::vector<int> next;
+    for (int c = 0; c < Rc; ++c)
+      if (!out.converged[active[c]]) next.push_back(active[c]);
+    active.swap(next);
+    if (total >= maxit) break;
+  }
+  return out;
+}
+
+}  // namespace
+
 // ----------------------------------------------------------------- solve
 
-int solve_op(OpObj& op, const bem_excitation* exc, int64_t nexc, const bem_solve_opts& opts, bem_c64* Hout,
-             bem_c64* Eout, bem_c64* rhoout, bem_solve_info* info, hipStream_t st) {
-  auto tstart = std::chrono::steady_clock::now();
-  if (nexc <= 0 || !exc) throw Error(BEM_E_INVALID, "no excitation");
-  if (!(opts.tol > 0) || opts.restart <= 0 || opts.maxit <= 0) throw Error(BEM_E_INVALID, "invalid solve options");
-  const int64_t ne = op.ne, nq = op.nq, N = op.N;
-  DevArena tmp(op.ctx);
-  // right-hand sides
-  double2* B = tmp.alloc<double2>(size_t(ne) * nexc);
+namespace {
+
+// Right-hand sides (N_E x nexc, column-major) of eq. finalsystem's first block row.
+void build_rhs(OpObj& op, DevArena& tmp, const bem_excitation* exc, int64_t nexc, double2* B, hipStream_t st) {
+  const int64_t ne = op.ne;
   std::vector<double> khat;
   std::vector<double2> pol, amp;
   std::vector<int64_t> pw;  // plane-wave excitations
-  BEM_HIP(hipMemsetAsync(B, 0, sizeof(double2) * ne * nexc, st));
+  launch_axpby(ne * nexc, c2(0.0), nullptr, c2(0.0), nullptr, B, st);
   for (int64_t e = 0; e < nexc; ++e) {
     const bem_excitation& x = exc[e];
     if (x.kind == BEM_EXC_PLANE_WAVE) {
@@ -1011,7 +1314,10 @@ int solve_op(OpObj& op, const bem_excitation* exc, int64_t nexc, const bem_solve
       for (int64_t g = 0; g < x.n_gap; ++g) {
         int32_t a = x.gap_edges[2 * g], b = x.gap_edges[2 * g + 1];
         double s = 1.0;
-        if (a > b) { std::swap(a, b); s = -1.0; }
+        if (a > b) {
+          std::swap(a, b);
+          s = -1.0;
+        }
         auto it = eid.find({a, b});
         if (it == eid.end()) throw Error(BEM_E_INVALID, "gap edge is not a mesh edge");
         col[it->second] = c2(s * x.amp.re / kEta0, s * x.amp.im / kEta0);
@@ -1033,93 +1339,190 @@ int solve_op(OpObj& op, const bem_excitation* exc, int64_t nexc, const bem_solve
     for (size_t i = 0; i < pw.size(); ++i)
       BEM_HIP(hipMemcpyAsync(B + pw[i] * ne, Bpw + i * ne, sizeof(double2) * ne, hipMemcpyDeviceToDevice, st));
   }
-  if (!op.outer_ws || op.outer_ws->m != opts.restart) op.outer_ws = make_gmres_work(op.mem, N, opts.restart);
-  op.outer_ws->tag = "outer";
-  double2* bfull = tmp.alloc<double2>(N);
-  double2* xs = tmp.alloc<double2>(N);
-  double2* d = tmp.alloc<double2>(N);
-  double2* r = tmp.alloc<double2>(N);
-  double2* o1 = tmp.alloc<double2>(ne);
-  double2* o3 = tmp.alloc<double2>(op.nt);
+}
+
+// Outputs of R solutions xs (N x R, ldx): H = a / (j k0), E = eta0 e, rho = -B x3 / c0
+// (excitation e of the batch at column e of every output).
+void write_outputs(OpObj& op, DevArena& tmp, const double2* xs, int64_t ldx, int R, const bem_solve_opts& opts,
+                   bem_c64* Hout, bem_c64* Eout, bem_c64* rhoout, hipStream_t st) {
+  const int64_t ne = op.ne, nt = op.nt;
+  double2* o1 = tmp.alloc<double2>(size_t(ne) * R);
+  double2* o3 = tmp.alloc<double2>(size_t(nt) * R);
+  auto put = [&](bem_c64* dst, const double2* src, int64_t len) {
+    if (!dst) return;
+    BEM_HIP(hipMemcpyAsync(dst, src, sizeof(double2) * len * R,
+                           opts.out_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
+    BEM_HIP(hipStreamSynchronize(st));
+  };
+  launch_axpby(ne, c2(0.0, -1.0 / op.k0), xs, c2(0.0), nullptr, o1, st, R, ldx, 0, ne);
+  put(Hout, o1, ne);
+  launch_axpby(ne, c2(kEta0), xs + ne, c2(0.0), nullptr, o1, st, R, ldx, 0, ne);
+  put(Eout, o1, ne);
+  launch_expand_charge(xs + 2 * ne, o3, op.obj_tri_d, op.nobj, c2(-1.0 / kC0), st, R, ldx, nt);
+  put(rhoout, o3, nt);
+  tmp.release(o1);
+  tmp.release(o3);
+}
+
+// True float64 relative residuals ||b - A x|| / ||b|| of R columns.
+std::vector<double> true_residuals(BGmres& w, const BApplyFn& A64, const double2* b, const double2* x, int64_t ld,
+                                   int R, hipStream_t st) {
+  w.norms(b, ld, R, st);
+  std::vector<double> bn(R);
+  for (int c = 0; c < R; ++c) bn[c] = w.h_nrm[c].x;
+  A64(x, ld, w.T, w.ldv, R);
+  launch_axpby(w.n, c2(1.0), b, c2(-1.0), w.T, w.T, st, R, ld, w.ldv, w.ldv);
+  w.norms(w.T, w.ldv, R, st);
+  std::vector<double> rel(R);
+  for (int c = 0; c < R; ++c) rel[c] = bn[c] > 0 ? w.h_nrm[c].x / bn[c] : 0.0;
+  return rel;
+}
+
+constexpr int kMaxBatch = 256;
+
+}  // namespace
+
+int solve_op(OpObj& op, const bem_excitation* exc, int64_t nexc, const bem_solve_opts& opts, bem_c64* Hout,
+             bem_c64* Eout, bem_c64* rhoout, bem_solve_info* info, hipStream_t st) {
+  auto tstart = std::chrono::steady_clock::now();
+  if (nexc <= 0 || !exc) throw Error(BEM_E_INVALID, "no excitation");
+  if (!(opts.tol > 0) || opts.restart <= 0 || opts.maxit <= 0) throw Error(BEM_E_INVALID, "invalid solve options");
+  const int64_t ne = op.ne, nt = op.nt, N = op.N;
+  DevArena tmp(op.ctx);
+  double2* Bexc = tmp.alloc<double2>(size_t(ne) * nexc);
+  build_rhs(op, tmp, exc, nexc, Bexc, st);
   const double inner = opts.inner_tol > 0 ? opts.inner_tol : 0.1 * opts.tol;
+  const double inner32 = std::max(inner, 1e-7);
+  const double stol = std::max(opts.tol * 0.5, 1e-6);
+  const int sweeps = opts.max_refine > 0 ? opts.max_refine : 5;
   bem_solve_info inf{};
   int status = BEM_OK;
   op.max_inner_iters = 0;
-  for (int64_t e = 0; e < nexc; ++e) {
-    launch_axpby(N, c2(0.0), nullptr, c2(0.0), nullptr, bfull, st);
-    BEM_HIP(hipMemcpyAsync(bfull, B + e * ne, sizeof(double2) * ne, hipMemcpyDeviceToDevice, st));
-    ApplyFn A64 = [&op, inner, st](const double2* x, double2* y) { apply_final(op, x, y, false, inner, st); };
-    ApplyFn P64 = [&op, st](const double2* x, double2* y) { apply_precond(op, x, y, false, st); };
-    ApplyFn P32 = [&op, st](const double2* x, double2* y) { apply_precond(op, x, y, true, st); };
-    double rel = 0;
-    bool conv = false;
-    int left = opts.maxit;
+
+  // batch width: as many excitations as fit a quarter of the remaining budget
+  int Rb = int(std::min<int64_t>(nexc, kMaxBatch));
+  {
+    auto est = [&](int R) {
+      const double ldN = double(pad64(N)), m = opts.restart;
+      return 16.0 * R * (ldN * (m + 1 + 3 + 5) + double(kWorkFields) * work_ld(op)) +
+             double(gemm_workspace_bytes(std::max(ne, nt), R));
+    };
+    size_t avail;
+    {
+      std::lock_guard<std::mutex> g(op.ctx->mu);
+      avail = op.ctx->budget > op.ctx->used ? op.ctx->budget - op.ctx->used : 0;
+    }
+    while (Rb > 1 && est(Rb) > 0.5 * double(avail)) Rb = (Rb + 1) / 2;
+  }
+  const int64_t ldN = pad64(N);
+  BGmres bw(tmp, N, opts.restart, Rb);
+  WorkView wv = batch_views(op, tmp, Rb);
+  double2* bfull = tmp.alloc<double2>(size_t(Rb) * ldN);
+  double2* xs = tmp.alloc<double2>(size_t(Rb) * ldN);
+  double2* rr = tmp.alloc<double2>(size_t(Rb) * ldN);  // refinement residuals (compacted)
+  double2* dd = tmp.alloc<double2>(size_t(Rb) * ldN);  // refinement corrections (compacted)
+  int* ref_idx = tmp.alloc<int>(Rb);                     // refinement's active columns
+  auto with_R = [&wv](int R) {
+    WorkView v = wv;
+    v.R = R;
+    return v;
+  };
+  BApplyFn A64 = [&](const double2* x, int64_t ldx, double2* y, int64_t ldy, int R) {
+    final_cols(op, with_R(R), x, ldx, y, ldy, false, inner, st);
+  };
+  BApplyFn A32 = [&](const double2* x, int64_t ldx, double2* y, int64_t ldy, int R) {
+    final_cols(op, with_R(R), x, ldx, y, ldy, true, inner32, st);
+  };
+  BApplyFn P64 = [&](const double2* x, int64_t ldx, double2* y, int64_t ldy, int R) {
+    if (ldx != ldy) throw Error(BEM_E_INVALID, "preconditioner needs equal strides");
+    precond_cols(op, with_R(R), x, y, ldx, false, st);
+  };
+  BApplyFn P32 = [&](const double2* x, int64_t ldx, double2* y, int64_t ldy, int R) {
+    if (ldx != ldy) throw Error(BEM_E_INVALID, "preconditioner needs equal strides");
+    precond_cols(op, with_R(R), x, y, ldx, true, st);
+  };
+  const BApplyFn* Pm64 = op.precond ? &P64 : nullptr;
+  const BApplyFn* Pm32 = op.precond ? &P32 : nullptr;
+
+  for (int64_t e0 = 0; e0 < nexc; e0 += Rb) {
+    const int R = int(std::min<int64_t>(Rb, nexc - e0));
+    launch_axpby(N, c2(0.0), nullptr, c2(0.0), nullptr, bfull, st, R, 0, 0, ldN);
+    BEM_HIP(hipMemcpy2DAsync(bfull, sizeof(double2) * ldN, Bexc + e0 * ne, sizeof(double2) * ne,
+                             sizeof(double2) * ne, R, hipMemcpyDeviceToDevice, st));
+    std::vector<char> conv(R, 0);
     if (op.precision == BEM_FP64) {
-      GmresResult g = gmres(*op.outer_ws, op.pinned, A64, bfull, xs, true, opts.tol, left, st,
-                            op.precond ? &P64 : nullptr);
-      inf.outer_iters += g.iters;
-      inf.n_products += g.iters + 1;
-      conv = g.converged;
+      BResult g = gmres_batched(bw, A64, bfull, ldN, xs, ldN, R, opts.tol, opts.maxit, st, Pm64);
+      for (int c = 0; c < R; ++c) {
+        inf.outer_iters += g.iters[c];
+        conv[c] = g.converged[c];
+      }
+      inf.n_products += g.products;
+      std::vector<double> rel = true_residuals(bw, A64, bfull, xs, ldN, R, st);
+      ++inf.n_products;
+      for (int c = 0; c < R; ++c) inf.rel_residual = std::max(inf.rel_residual, rel[c]);
     } else {
-      // float32 products (and float32 nested solves), float64 Arnoldi; float64 residual refinement
-      const double inner32 = std::max(inner, 1e-7);
-      ApplyFn A32 = [&op, inner32, st](const double2* x, double2* y) { apply_final(op, x, y, true, inner32, st); };
-      launch_axpby(N, c2(0.0), nullptr, c2(0.0), nullptr, xs, st);
-      launch_axpby(N, c2(1.0), bfull, c2(0.0), nullptr, r, st);
-      launch_norm(bfull, N, op.outer_ws->nrm, op.outer_ws->ks, st);
-      const double bn = read_scalar(op.pinned,reinterpret_cast<const double*>(op.outer_ws->nrm), st);
-      const int sweeps = opts.max_refine > 0 ? opts.max_refine : 5;
-      for (int s = 0; s < sweeps && left > 0; ++s) {
-        const double stol = std::max(opts.tol * 0.5, 1e-6);
-        GmresResult g = gmres(*op.outer_ws, op.pinned, A32, r, d, true, stol, left, st, op.precond ? &P32 : nullptr);
-        left -= g.iters;
-        inf.outer_iters += g.iters;
-        inf.n_products += g.iters + 1;
-        launch_axpby(N, c2(1.0), xs, c2(1.0), d, xs, st);
-        A64(xs, r);
-        ++inf.refine_steps;
-        ++inf.n_products;
-        launch_axpby(N, c2(1.0), bfull, c2(-1.0), r, r, st);
-        launch_norm(r, N, op.outer_ws->nrm, op.outer_ws->ks, st);
-        const double rn = read_scalar(op.pinned,reinterpret_cast<const double*>(op.outer_ws->nrm), st);
-        rel = bn > 0 ? rn / bn : 0.0;
-        if (rel <= opts.tol) {
-          conv = true;
-          break;
+      // float32 products (and nested solves) inside GMRES with float64 Arnoldi, float64 residual
+      // refinement; converged columns leave the batch
+      launch_axpby(N, c2(0.0), nullptr, c2(0.0), nullptr, xs, st, R, 0, 0, ldN);
+      bw.norms(bfull, ldN, R, st);
+      std::vector<double> bn(R), rel(R, 1.0);
+      std::vector<int> active;
+      for (int c = 0; c < R; ++c) {
+        bn[c] = bw.h_nrm[c].x;
+        if (bn[c] > 0) active.push_back(c);
+        else {
+          conv[c] = 1;
+          rel[c] = 0.0;
         }
       }
+      int left = opts.maxit;
+      auto upload_active = [&]() {
+        BEM_HIP(hipStreamSynchronize(st));
+        BEM_HIP(hipMemcpy(ref_idx, active.data(), sizeof(int) * active.size(), hipMemcpyHostToDevice));
+      };
+      for (int s = 0; s < sweeps && left > 0 && !active.empty(); ++s) {
+        const int Rc = int(active.size());
+        const int* didx = ref_idx;
+        upload_active();
+        // compacted residual: r = b - A64 x (x = 0 on the first sweep)
+        launch_gather_cols(bfull, ldN, rr, ldN, didx, N, Rc, st);
+        if (s > 0) {
+          launch_gather_cols(xs, ldN, dd, ldN, didx, N, Rc, st);
+          A64(dd, ldN, bw.T, bw.ldv, Rc);
+          ++inf.n_products;
+          launch_axpby(N, c2(1.0), rr, c2(-1.0), bw.T, rr, st, Rc, ldN, bw.ldv, ldN);
+        }
+        BEM_HIP(hipStreamSynchronize(st));
+        BResult g = gmres_batched(bw, A32, rr, ldN, dd, ldN, Rc, stol, left, st, Pm32);
+        int most = 0;
+        for (int c = 0; c < Rc; ++c) {
+          inf.outer_iters += g.iters[c];
+          most = std::max(most, g.iters[c]);
+        }
+        left -= most;
+        inf.n_products += g.products;
+        ++inf.refine_steps;
+        // x += d ; float64 residual of the updated columns
+        launch_scatter_cols(dd, ldN, xs, ldN, didx, N, Rc, 1, st);
+        launch_gather_cols(xs, ldN, dd, ldN, didx, N, Rc, st);
+        launch_gather_cols(bfull, ldN, rr, ldN, didx, N, Rc, st);
+        std::vector<double> r = true_residuals(bw, A64, rr, dd, ldN, Rc, st);
+        ++inf.n_products;
+        std::vector<int> next;
+        for (int c = 0; c < Rc; ++c) {
+          rel[active[c]] = r[c];
+          if (r[c] <= opts.tol) conv[active[c]] = 1;
+          else next.push_back(active[c]);
+        }
+        active.swap(next);
+      }
+      for (int c = 0; c < R; ++c) inf.rel_residual = std::max(inf.rel_residual, rel[c]);
     }
-    // true float64 residual of the returned iterate
-    if (op.precision == BEM_FP64) {
-      A64(xs, r);
-      ++inf.n_products;
-      launch_axpby(N, c2(1.0), bfull, c2(-1.0), r, r, st);
-      launch_norm(r, N, op.outer_ws->nrm, op.outer_ws->ks, st);
-      const double rn = read_scalar(op.pinned,reinterpret_cast<const double*>(op.outer_ws->nrm), st);
-      launch_norm(bfull, N, op.outer_ws->nrm, op.outer_ws->ks, st);
-      const double bn = read_scalar(op.pinned,reinterpret_cast<const double*>(op.outer_ws->nrm), st);
-      rel = bn > 0 ? rn / bn : 0.0;
-    }
-    inf.rel_residual = std::max(inf.rel_residual, rel);
-    if (!conv) status = BEM_E_NOT_CONVERGED;
-    // outputs: H = a/(jk0), E = eta0 e, rho = -B x3 / c0
-    auto put = [&](bem_c64* dst, const double2* src, int64_t len) {
-      if (!dst) return;
-      bem_c64* p = dst + e * len;
-      BEM_HIP(hipMemcpyAsync(p, src, sizeof(double2) * len,
-                             opts.out_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
-    };
-    launch_axpby(ne, c2(0.0, -1.0 / op.k0), xs, c2(0.0), nullptr, o1, st);
-    put(Hout, o1, ne);
-    BEM_HIP(hipStreamSynchronize(st));
-    launch_axpby(ne, c2(kEta0), xs + ne, c2(0.0), nullptr, o1, st);
-    put(Eout, o1, ne);
-    BEM_HIP(hipStreamSynchronize(st));
-    launch_expand_charge(xs + 2 * ne, o3, op.obj_tri_d, op.nobj, c2(-1.0 / kC0), st);
-    put(rhoout, o3, op.nt);
-    BEM_HIP(hipStreamSynchronize(st));
+    for (int c = 0; c < R; ++c)
+      if (!conv[c]) status = BEM_E_NOT_CONVERGED;
+    write_outputs(op, tmp, xs, ldN, R, opts, Hout ? Hout + e0 * ne : nullptr, Eout ? Eout + e0 * ne : nullptr,
+                  rhoout ? rhoout + e0 * nt : nullptr, st);
   }
-  (void)nq;
   inf.inner_iters_max = op.max_inner_iters;
   inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - tstart).count();
   if (info) *info = inf;

@@ -118,8 +118,11 @@ def test_blocks_match_oracle(name, ctx):
         assert err < 1e-12 and emax < 1e-11, (block, err, emax)
 
 
+@pytest.mark.parametrize("nrhs", [2, 5])
 @pytest.mark.parametrize("name", list(CASES))
-def test_apply_matches_oracle(name, ctx, torch_mod):
+def test_apply_matches_oracle(name, nrhs, ctx, torch_mod):
+    """Every block times nrhs random columns: 2 columns run as grouped GEMVs, 5 as float64
+    matrix-core GEMMs (the nested solve of the final system by GMRES, column by column)."""
     torch = torch_mod
     w, ops, mesh, op, perm = case(name, ctx)
     ne, nt = len(ops.topo.edges), len(ops.topo.tri)
@@ -141,7 +144,6 @@ def test_apply_matches_oracle(name, ctx, torch_mod):
             ref_M = M[np.ix_(P, P)]
         else:
             ref_M = permute(block, M, perm)
-        nrhs = 2
         x = rng.standard_normal((nrhs, n)) + 1j * rng.standard_normal((nrhs, n))
         xd = torch.tensor(x, dtype=torch.complex128, device="cuda")
         yd = torch.zeros_like(xd)
@@ -155,7 +157,32 @@ def test_apply_matches_oracle(name, ctx, torch_mod):
         assert err < tol, (block, err)
 
 
-MODES = [(B.BEM_INNER_GMRES, 0), (B.BEM_INNER_GMRES, 1), (B.BEM_INNER_DIRECT, 0), (B.BEM_INNER_DIRECT, 1)]
+@pytest.mark.parametrize("inner", [B.BEM_INNER_DIRECT, B.BEM_INNER_SCHUR])
+@pytest.mark.parametrize("name", list(CASES))
+def test_apply_final_direct_modes(name, inner, ctx, torch_mod):
+    """The final system with the nested solve done by the augmented inverse or by the charge-
+    eliminated S^-1 (float64 GEMM over 5 columns, GEMV for 1) equals the oracle's matrix."""
+    torch = torch_mod
+    w, ops, mesh, op, perm = case(name, ctx, inner, 0)
+    ne, nt = len(ops.topo.edges), len(ops.topo.tri)
+    M = S.final_matrix(ops)
+    P = final_perm(perm, ne, nt - 1)
+    ref_M = M[np.ix_(P, P)]
+    rng = np.random.default_rng(11)
+    stream = torch.cuda.current_stream().cuda_stream
+    for nrhs in (1, 5):
+        x = rng.standard_normal((nrhs, len(M))) + 1j * rng.standard_normal((nrhs, len(M)))
+        xd = torch.tensor(x, dtype=torch.complex128, device="cuda")
+        yd = torch.zeros_like(xd)
+        B.bem_apply(ctx, op, B.BEM_BLOCK_FINAL, xd.data_ptr(), yd.data_ptr(), nrhs, stream)
+        torch.cuda.synchronize()
+        err = rel(yd.cpu().numpy(), x @ ref_M.T)
+        print(f"{name} inner {inner} nrhs {nrhs}: rel {err:.2e}")
+        assert err < 1e-11, (nrhs, err)
+
+
+MODES = [(B.BEM_INNER_GMRES, 0), (B.BEM_INNER_GMRES, 1), (B.BEM_INNER_DIRECT, 0), (B.BEM_INNER_DIRECT, 1),
+         (B.BEM_INNER_SCHUR, 0), (B.BEM_INNER_SCHUR, 1)]
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -180,11 +207,12 @@ def test_solve_fp64_matches_oracle(name, inner, precond, ctx):
         assert err < 1e-10, (lab, err)
 
 
+@pytest.mark.parametrize("inner", [B.BEM_INNER_DIRECT, B.BEM_INNER_SCHUR])
 @pytest.mark.parametrize("name", list(CASES))
-def test_solve_mixed_matches_oracle(name, ctx):
+def test_solve_mixed_matches_oracle(name, inner, ctx):
     """float32 products and nested solves, float64 Arnoldi and residual refinement: after
     refinement to a 1e-9 float64 residual the currents are within 1e-6 of the oracle."""
-    w, ops, mesh, op, perm = case(name, ctx, B.BEM_INNER_DIRECT, 1, B.BEM_MIXED)
+    w, ops, mesh, op, perm = case(name, ctx, inner, 1, B.BEM_MIXED)
     ne, nt = len(ops.topo.edges), len(ops.topo.tri)
     ref = S.solve_augmented(ops, S.rhs(ops, w.khat[0], w.pol[0]))
     rc, H, E, rho, info = B.bem_solve(ctx, op, B.plane_waves(w.khat, w.pol),
@@ -214,3 +242,36 @@ def test_dense_inverse_of_meq(ctx, torch_mod):
     B.bem_apply(ctx, op, B.BEM_BLOCK_MEQ, xd.data_ptr(), yd.data_ptr(), 1, torch.cuda.current_stream().cuda_stream)
     torch.cuda.synchronize()
     assert rel(yd.cpu().numpy(), Meq[np.ix_(P, P)] @ x) < 1e-12
+
+
+N_EXC = 6
+
+
+def _multi_reference(ops, n_exc, seed):
+    khat, pol = meshgen.plane_wave_draws(n_exc, seed)
+    b = np.stack([S.rhs(ops, khat[i], pol[i]) for i in range(n_exc)], axis=1)
+    return khat, pol, S.solve_augmented(ops, b)
+
+
+@pytest.mark.parametrize("precision", [B.BEM_FP64, B.BEM_MIXED])
+@pytest.mark.parametrize("name", list(CASES))
+def test_solve_many_excitations(name, precision, ctx):
+    """Several plane waves (random directions and polarisations) solved in one batch: every
+    Krylov step applies the final system to all unconverged columns with matrix-core GEMMs
+    (float64, or float32 with float64 refinement).  Each column matches the oracle's direct
+    solve: 1e-10 in float64, 1e-6 after refinement."""
+    w, ops, mesh, op, perm = case(name, ctx, B.BEM_INNER_SCHUR, 1, precision)
+    ne, nt = len(ops.topo.edges), len(ops.topo.tri)
+    khat, pol, refs = _multi_reference(ops, N_EXC, 5)
+    fp64 = precision == B.BEM_FP64
+    opts = B.solve_opts(tol=1e-13 if fp64 else 1e-9, restart=60, maxit=3000, max_refine=8)
+    rc, H, E, rho, info = B.bem_solve(ctx, op, B.plane_waves(khat, pol), opts, ne, nt)
+    print(f"{name} prec {precision}: outer {info.outer_iters} refine {info.refine_steps} "
+          f"products {info.n_products} res {info.rel_residual:.2e}")
+    assert rc == B.BEM_OK
+    tol = 1e-10 if fp64 else 1e-6
+    for c, ref in enumerate(refs):
+        for lab, got, want in (("H", H[:, c], ref.H(ops.k0)[perm]), ("E", E[:, c], ref.E()[perm]),
+                               ("rho", rho[:, c], ref.rho(ops.B))):
+            err = rel(got, want)
+            assert err < tol, (c, lab, err)
