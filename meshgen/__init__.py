@@ -229,6 +229,16 @@ def config_c2() -> Workload:
     return sphere_workload(4, 5.0, 2.5 - 0.1j, name="sphere5120_k0a5_eps2.5-0.1j")
 
 
+def config_c2_multi(n_exc: int = 256) -> Workload:
+    """The 5120-triangle sphere of config_c2 lit by `n_exc` random plane waves (many incidence
+    angles through one batched solve)."""
+    w = config_c2()
+    khat, pol = plane_wave_draws(n_exc, seed=21)
+    w.name = f"sphere5120_k0a5_eps2.5-0.1j_x{n_exc}"
+    w.khat, w.pol = khat, pol.astype(np.complex128)
+    return w
+
+
 def config_c3(n: int = 32, n_exc: int = 256) -> Workload:
     """Jittered ellipsoid 1.0/0.6/0.4 m (cubed sphere, 12 n^2 triangles), eps_r = 6,
     k0 a_max = 8, `n_exc` random plane waves."""

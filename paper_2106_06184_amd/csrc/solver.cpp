@@ -1234,6 +1234,7 @@ BResult gmres_batched(BGmres& w, const BApplyFn& A, const double2* B, int64_t ld
       BEM_HIP(hipMemcpyAsync(w.h_res, w.res, sizeof(double) * Rc, hipMemcpyDeviceToHost, st));
       BEM_HIP(hipStreamSynchronize(st));
       bool changed = false;
+      double worst = 0.0;
       for (int c = 0; c < Rc; ++c) {
         if (w.h_frozen[c]) continue;
         const int col = active[c];
@@ -1241,6 +1242,7 @@ BResult gmres_batched(BGmres& w, const BApplyFn& A, const double2* B, int64_t ld
         if (!std::isfinite(rr)) throw Error(BEM_E_NUMERIC, "non-finite Arnoldi residual");
         ++out.iters[col];
         out.relres[col] = rr;
+        worst = std::max(worst, rr);
         if (rr <= tol) {
           w.h_frozen[c] = 1;
           w.h_jr[c] = j + 1;
@@ -1249,7 +1251,9 @@ BResult gmres_batched(BGmres& w, const BApplyFn& A, const double2* B, int64_t ld
           changed = true;
         }
       }
-      if (verbose()) std::fprintf(stderr, "[bem] batched step %d: %d of %d columns active\n", total, live, Rc);
+      if (verbose())
+        std::fprintf(stderr, "[bem] batched step %d: %d of %d columns active, worst res %.3e\n", total, live, Rc,
+                     worst);
       if (live == 0) {
         ++j;
         break;
