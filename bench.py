@@ -85,6 +85,36 @@ def cpu_baseline(w, n_sample: int = 12) -> dict:
                       f"fill est {t_fill:.1f} s, LU est {t_lu:.1f} s"}
 
 
+def measured_traffic(kernel_class: str):
+    """HBM bytes per launch of a kernel class from the committed counter summary
+    (profiles/traffic.json), or None when the kernel source changed since it was measured."""
+    import hashlib
+    path = ROOT / "profiles" / "traffic.json"
+    if not path.exists():
+        return None
+    entry = json.loads(path.read_text()).get(kernel_class)
+    if not entry:
+        return None
+    src = ROOT / entry["source"]
+    if not src.exists() or hashlib.sha256(src.read_bytes()).hexdigest() != entry["source_sha256"]:
+        return None
+    return float(entry["hbm_bytes_per_launch"])
+
+
+def copy_calibration() -> int:
+    """A plain device copy of known size (256 MiB read + 256 MiB written per dispatch, 5
+    dispatches): the reference for scaling the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    n = 256 * 1024 * 1024 // 4
+    a = torch.ones(n, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print("copied 5 x 256 MiB", flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,7 +129,11 @@ def main() -> int:
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--restart", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run the plain copy used to calibrate the HBM byte counters")
     args = ap.parse_args()
+    if args.copy_calibration:
+        return copy_calibration()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU layout is a "
               f"design note, not a run.", file=sys.stderr)
@@ -179,6 +213,12 @@ def main() -> int:
         roof = {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None}
     roof.update({"kernel": names[dom], "avg_launch_ms": avg_ms, "launches": p["launches"]})
+    if roof["bound"] == "hbm":
+        # measured HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated on a plain
+        # copy) beside the algorithmic bytes per launch
+        roof["traffic"] = measured_traffic(names[dom])
+        roof["algorithmic_bytes_per_launch"] = p["bytes"] / max(p["launches"], 1)
+        roof["traffic_unit"] = "bytes/launch"
     gemv = prof[B.KC_GEMV_F32] if prec == B.BEM_MIXED else prof[B.KC_GEMV_F64]
     matvec_frac = (gemv["bytes"] / (gemv["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBPS) if gemv["ms"] > 0 else None
     lat_sorted = sorted(lat)

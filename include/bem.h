@@ -213,6 +213,10 @@ int bem_submit(bem_ctx* ctx, const bem_request* req, bem_ticket* out);
 int bem_poll(bem_ctx* ctx, bem_ticket ticket, bem_solve_info* info);
 /* Block until no submitted request is pending. */
 int bem_drain(bem_ctx* ctx);
+/* Serving counters since the first bem_submit: grouped launches issued by the product
+ * combiner, and the product requests they carried (> launches when requests shared a launch).
+ * Both outputs may be NULL. */
+int bem_serve_stats(bem_ctx* ctx, int64_t* combined_launches, int64_t* combined_products);
 
 /* Statistics of an assembled operator: device time of the whole fill (all wavenumbers, near
  * corrections and gathers), bytes of the float64 dense blocks written, Green's-function and

@@ -9,11 +9,13 @@ Loading fails loudly when the library has not been built (python -m paper_2106_0
 from __future__ import annotations
 
 import ctypes as C
+import os
 from pathlib import Path
 
 import numpy as np
 
-_LIB_PATH = Path(__file__).resolve().parent / "libbem.so"
+# BEM_LIB selects another build of the library (e.g. one made with other compiler flags).
+_LIB_PATH = Path(os.environ["BEM_LIB"]) if os.environ.get("BEM_LIB") else Path(__file__).resolve().parent / "libbem.so"
 
 BEM_OK, BEM_PENDING = 0, 1
 BEM_E_INVALID, BEM_E_MESH, BEM_E_NOMEM, BEM_E_NOT_CONVERGED, BEM_E_DEVICE, BEM_E_NUMERIC = -1, -2, -3, -4, -5, -6
@@ -25,7 +27,7 @@ BEM_EXC_PLANE_WAVE, BEM_EXC_DELTA_GAP = 0, 1
 SYMBOLS = ["bem_create", "bem_destroy", "bem_last_error", "bem_mesh_load", "bem_mesh_info", "bem_edge_table",
            "bem_near_pairs", "bem_assemble", "bem_apply", "bem_block_export", "bem_set_inner_tol", "bem_solve",
            "bem_submit", "bem_poll", "bem_drain", "bem_release", "bem_memory_in_use", "bem_op_stats_get",
-           "bem_profile_enable", "bem_profile_read"]
+           "bem_profile_enable", "bem_profile_read", "bem_serve_stats"]
 (KC_GEMV_F64, KC_GEMV_F32, KC_FILL_L, KC_FILL_K, KC_FILL_NEAR, KC_GATHER, KC_GEMM_F32, KC_DENSE_INV,
  KC_GEMM_F64) = range(9)
 KC_NAMES = ["gemv_f64", "gemv_f32", "fill_L", "fill_K", "fill_near", "gather", "gemm_f32_mfma", "dense_inv_update",
@@ -102,6 +104,7 @@ def lib() -> C.CDLL:
             "bem_solve": (C.c_int, [P, C.c_uint64, C.POINTER(bem_excitation), I64, C.POINTER(bem_solve_opts),
                                     C.POINTER(c64), C.POINTER(c64), C.POINTER(c64), C.POINTER(bem_solve_info)]),
             "bem_submit": (C.c_int, [P, C.POINTER(bem_request), C.POINTER(C.c_uint64)]),
+            "bem_serve_stats": (C.c_int, [P, C.POINTER(I64), C.POINTER(I64)]),
             "bem_poll": (C.c_int, [P, C.c_uint64, C.POINTER(bem_solve_info)]),
             "bem_drain": (C.c_int, [P]),
             "bem_release": (C.c_int, [P, C.c_uint64]),
@@ -252,7 +255,42 @@ def bem_solve(ctx, op: int, exc, opts: bem_solve_opts, n_edge: int, n_tri: int):
     return rc, H.T, E.T, rho.T, info
 
 
-def bem_submit(ctx, req: bem_request) -> int:
+class Request:
+    """A serving request with its own copies of the inputs and host output arrays (H, E: n_edge x
+    nexc; rho: n_tri x nexc, read after bem_poll returns a final status)."""
+
+    def __init__(self, xyz, tri, obj, prob: bem_problem, exc, opts: bem_solve_opts):
+        self.xyz = np.ascontiguousarray(xyz, np.float64)
+        self.tri = np.ascontiguousarray(tri, np.int32)
+        self.obj = None if obj is None else np.ascontiguousarray(obj, np.int32)
+        self.prob, self.exc, self.opts = prob, exc, opts
+        nt = len(self.tri)
+        ne = 3 * nt // 2
+        n = len(exc)
+        self._H = np.zeros((n, ne), np.complex128)
+        self._E = np.zeros((n, ne), np.complex128)
+        self._rho = np.zeros((n, nt), np.complex128)
+        self.c = bem_request(self.xyz.ctypes.data_as(C.POINTER(C.c_double)), len(self.xyz),
+                             _iptr(self.tri), nt, _iptr(self.obj) if self.obj is not None else None,
+                             prob, C.cast(exc, C.POINTER(bem_excitation)), n, opts,
+                             _cptr(self._H), _cptr(self._E), _cptr(self._rho))
+
+    @property
+    def H(self):
+        return self._H.T
+
+    @property
+    def E(self):
+        return self._E.T
+
+    @property
+    def rho(self):
+        return self._rho.T
+
+
+def bem_submit(ctx, req) -> int:
+    if isinstance(req, Request):
+        req = req.c
     t = C.c_uint64()
     _check(ctx, lib().bem_submit(ctx, C.byref(req), C.byref(t)))
     return t.value
@@ -268,6 +306,13 @@ def bem_poll(ctx, ticket: int):
 
 def bem_drain(ctx) -> None:
     _check(ctx, lib().bem_drain(ctx))
+
+
+def bem_serve_stats(ctx) -> tuple[int, int]:
+    """(grouped launches of the serving combiner, product requests they carried)."""
+    a, b = C.c_int64(), C.c_int64()
+    _check(ctx, lib().bem_serve_stats(ctx, C.byref(a), C.byref(b)))
+    return a.value, b.value
 
 
 def bem_release(ctx, handle: int) -> None:

@@ -80,7 +80,7 @@ int bem_create(int device, size_t hbm_budget_bytes, bem_ctx** out) {
       }
       BEM_HIP(hipSetDevice(device));
       BEM_HIP(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
-      BEM_HIP(hipHostMalloc(reinterpret_cast<void**>(&ctx->pinned), 64 * sizeof(double), hipHostMallocDefault));
+      BEM_HIP(hipHostMalloc(reinterpret_cast<void**>(&ctx->pinned), bem::kPinnedBytes, hipHostMallocDefault));
       size_t fr = 0, tot = 0;
       BEM_HIP(hipMemGetInfo(&fr, &tot));
       ctx->budget = hbm_budget_bytes ? hbm_budget_bytes : fr;
@@ -309,6 +309,17 @@ int bem_drain(bem_ctx* c) {
   return guarded([&]() -> int {
     bem::Ctx* ctx = C(c);
     if (ctx->server) ctx->server->drain();
+    return BEM_OK;
+  });
+}
+
+int bem_serve_stats(bem_ctx* c, int64_t* launches, int64_t* products) {
+  return guarded([&]() -> int {
+    bem::Ctx* ctx = C(c);
+    int64_t l = 0, p = 0;
+    if (ctx->server) ctx->server->combiner_stats(&l, &p);
+    if (launches) *launches = l;
+    if (products) *products = p;
     return BEM_OK;
   });
 }

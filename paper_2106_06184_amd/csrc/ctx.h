@@ -13,6 +13,11 @@ namespace bem {
 
 class Server;
 
+// Pinned host staging per stream owner (context or serving slot): the first 64 doubles hold
+// convergence scalars; the rest stages the per-column Krylov scalars and index lists.
+constexpr size_t kPinnedBytes = 64 * 1024;
+constexpr size_t kPinnedScalars = 64;
+
 struct Ctx {
   int device = -1;
   size_t budget = 0;
@@ -38,17 +43,26 @@ class DevArena {
   T* alloc(size_t n) {
     return static_cast<T*>(raw(sizeof(T) * (n ? n : 1)));
   }
+  // Copies v to a new device buffer, ordered on the arena's stream and complete on return (the
+  // kernels that read it may run on that stream, which does not synchronise with the null
+  // stream).
   template <class T>
   T* upload(const std::vector<T>& v) {
     T* p = alloc<T>(v.size());
-    if (!v.empty()) BEM_HIP(hipMemcpy(p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
+    if (!v.empty()) {
+      BEM_HIP(hipMemcpyAsync(p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, stream_));
+      BEM_HIP(hipStreamSynchronize(stream_));
+    }
     return p;
   }
+  void set_stream(hipStream_t st) { stream_ = st; }
+  hipStream_t stream() const { return stream_; }
   void release(void* p);
   size_t bytes() const { return total_; }
 
  private:
   Ctx* ctx_;
+  hipStream_t stream_ = nullptr;
   std::vector<std::pair<void*, size_t>> blocks_;
   size_t total_ = 0;
 };
@@ -66,6 +80,15 @@ struct Dense {
 };
 
 struct GmresWork;
+
+// Groups the small dense products of concurrently solving requests into shared launches.
+class ProductCombiner {
+ public:
+  virtual ~ProductCombiner() = default;
+  // Runs the descriptors after the work already enqueued on st and before the work enqueued on
+  // st after the call returns (possibly inside one grouped launch with other requests').
+  virtual void run(const std::vector<GemvDesc>& ds, hipStream_t st) = 0;
+};
 
 struct OpObj {
   Ctx* ctx;
@@ -112,6 +135,7 @@ struct OpObj {
   std::unique_ptr<GmresWork> inner_ws, outer_ws;
   double2* work = nullptr;  // vector workspace
   int64_t work_len = 0;
+  ProductCombiner* comb = nullptr;  // set by the serving loop
   hipStream_t stream = nullptr;  // stream of the operator's work
   double* pinned = nullptr;      // pinned host scalars for convergence checks
 
@@ -155,6 +179,8 @@ void apply_block(OpObj& op, int block, const double2* x, double2* y, int64_t nrh
 void apply_meq(OpObj& op, const double2* x, double2* y, bool fp32, hipStream_t st);
 void apply_final(OpObj& op, const double2* x, double2* y, bool fp32, double inner_tol, hipStream_t st);
 void export_block(OpObj& op, int block, bem_c64* host);
+// Upper bound of the device bytes of one request (assembly peak or solve peak), for admission.
+size_t estimate_request_bytes(int64_t nt, int64_t nobj, int precision, int restart, int64_t nexc);
 int solve_op(OpObj& op, const bem_excitation* exc, int64_t nexc, const bem_solve_opts& opts, bem_c64* H, bem_c64* E,
              bem_c64* rho, bem_solve_info* info, hipStream_t st);
 

@@ -71,7 +71,8 @@ struct RhsArgs {
 };
 void launch_rhs_planewave(const RhsArgs& a, int nexc, hipStream_t st);
 
-void fill_set_rules(const double w7[7], const double b3[3][3]);
+// Quadrature rules into constant memory (once per device; later calls return at once).
+void fill_set_rules(const double w7[7], const double b3[3][3], hipStream_t st);
 void launch_fill_L(const FillLArgs& a, const int32_t* near_t, const int32_t* near_s, int64_t npairs,
                    hipStream_t st);
 // Half-row indices hp/hm are global (3 T + i); `off` = 3 * first triangle of the block.

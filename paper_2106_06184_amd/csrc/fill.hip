@@ -19,6 +19,8 @@
 //    remainders; they overwrite the far-rule values.  K~ is zero for coplanar near pairs.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "devmath.h"
 #include "fill.h"
 #include "prof.h"
@@ -461,9 +463,18 @@ void launch_rhs_planewave(const RhsArgs& a, int nexc, hipStream_t st) {
   BEM_HIP(hipGetLastError());
 }
 
-void fill_set_rules(const double w7[7], const double b3[3][3]) {
-  BEM_HIP(hipMemcpyToSymbol(HIP_SYMBOL(dev::cW7), w7, sizeof(double) * 7));
-  BEM_HIP(hipMemcpyToSymbol(HIP_SYMBOL(dev::cB3), b3, sizeof(double) * 9));
+void fill_set_rules(const double w7[7], const double b3[3][3], hipStream_t st) {
+  // the rules never change: written once per device, complete before any fill reads them
+  static std::mutex mu;
+  static bool done[256] = {};
+  int dev = 0;
+  BEM_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> g(mu);
+  if (dev >= 0 && dev < 256 && done[dev]) return;
+  BEM_HIP(hipMemcpyToSymbolAsync(HIP_SYMBOL(dev::cW7), w7, sizeof(double) * 7, 0, hipMemcpyHostToDevice, st));
+  BEM_HIP(hipMemcpyToSymbolAsync(HIP_SYMBOL(dev::cB3), b3, sizeof(double) * 9, 0, hipMemcpyHostToDevice, st));
+  BEM_HIP(hipStreamSynchronize(st));
+  if (dev >= 0 && dev < 256) done[dev] = true;
 }
 
 void launch_fill_L(const FillLArgs& a, const int32_t* near_t, const int32_t* near_s, int64_t npairs,

@@ -25,11 +25,27 @@ struct GemvDesc {
   int64_t tile0;      // first row tile of this descriptor (filled by the launcher)
   int64_t ldx, ldx2, ldy;  // column strides of x, x2, y for multi-column products
 };
+// Device-side copy of a descriptor (what the kernel reads), passed by value in a pack that
+// stays under 1 KiB of kernel arguments.
+struct GemvDev {
+  const void* A;
+  const void* A2;
+  int64_t lda, lda2;
+  int64_t rows, cols;
+  const double2* x;
+  const double2* x2;
+  double2* y;
+  double ar, ai, a2r, a2i;  // alpha, alpha2 (8-byte aligned: keeps the pack dense)
+  int accumulate;
+  int fp32;
+  int64_t tile0;
+};
 constexpr int kMaxGroup = 8;
 struct GemvPack {
-  GemvDesc d[kMaxGroup];
   int n;
+  GemvDev d[kMaxGroup];
 };
+static_assert(sizeof(GemvPack) <= 1024, "grouped GEMV arguments must stay under 1 KiB");
 
 // Runs all descriptors (any number; kMaxGroup per launch) with their rows spread over the grid.
 // Descriptors travel as kernel arguments; the call is asynchronous on `st`.
@@ -109,6 +125,8 @@ void launch_axpby(int64_t n, double2 a, const double2* x, double2 b, const doubl
                   hipStream_t st, int R = 1, int64_t ldx = 0, int64_t ldy = 0, int64_t ldz = 0);
 // Workspace bytes of launch_gemm for a float32 block with `cols` complex columns and nrhs.
 size_t gemm_workspace_bytes(int64_t cols, int64_t nrhs);
+// out[i] = A[i][i], i < n (row-major, leading dimension ld)
+void launch_diag(const double2* A, int64_t ld, int64_t n, double2* out, hipStream_t st);
 void launch_cast_f32(const double2* src, int64_t rows, int64_t cols, int64_t lds, float2* dst, int64_t ldd,
                      hipStream_t st);
 

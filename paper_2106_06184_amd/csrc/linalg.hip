@@ -141,7 +141,7 @@ __global__ void __launch_bounds__(256) k_gemv_grouped(GemvPack pack) {
   const int64_t b = blockIdx.x;
   int di = 0;
   while (di + 1 < pack.n && pack.d[di + 1].tile0 <= b) ++di;
-  const GemvDesc& d = pack.d[di];
+  const GemvDev& d = pack.d[di];
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   const int64_t row0 = (b - d.tile0) * kRowsPerBlock + int64_t(wave) * kRPW;
   if (row0 >= d.rows) return;
@@ -151,22 +151,22 @@ __global__ void __launch_bounds__(256) k_gemv_grouped(GemvPack pack) {
   if (d.fp32) {
     const bool al1 = ((reinterpret_cast<uintptr_t>(d.A) | uintptr_t(d.lda * 8)) & 15) == 0;
     if (al1)
-      rows_f32<kRPW, true>(static_cast<const float2*>(d.A), d.lda, d.rows, d.cols, d.x, row0, lane, d.alpha, yr, yi);
+      rows_f32<kRPW, true>(static_cast<const float2*>(d.A), d.lda, d.rows, d.cols, d.x, row0, lane, make_double2(d.ar, d.ai), yr, yi);
     else
-      rows_f32<kRPW, false>(static_cast<const float2*>(d.A), d.lda, d.rows, d.cols, d.x, row0, lane, d.alpha, yr, yi);
+      rows_f32<kRPW, false>(static_cast<const float2*>(d.A), d.lda, d.rows, d.cols, d.x, row0, lane, make_double2(d.ar, d.ai), yr, yi);
     if (d.A2) {
       const bool al2 = ((reinterpret_cast<uintptr_t>(d.A2) | uintptr_t(d.lda2 * 8)) & 15) == 0;
       if (al2)
-        rows_f32<kRPW, true>(static_cast<const float2*>(d.A2), d.lda2, d.rows, d.cols, d.x2, row0, lane, d.alpha2,
+        rows_f32<kRPW, true>(static_cast<const float2*>(d.A2), d.lda2, d.rows, d.cols, d.x2, row0, lane, make_double2(d.a2r, d.a2i),
                              yr, yi);
       else
-        rows_f32<kRPW, false>(static_cast<const float2*>(d.A2), d.lda2, d.rows, d.cols, d.x2, row0, lane, d.alpha2,
+        rows_f32<kRPW, false>(static_cast<const float2*>(d.A2), d.lda2, d.rows, d.cols, d.x2, row0, lane, make_double2(d.a2r, d.a2i),
                               yr, yi);
     }
   } else {
-    rows_f64<kRPW>(static_cast<const double2*>(d.A), d.lda, d.rows, d.cols, d.x, row0, lane, d.alpha, yr, yi);
+    rows_f64<kRPW>(static_cast<const double2*>(d.A), d.lda, d.rows, d.cols, d.x, row0, lane, make_double2(d.ar, d.ai), yr, yi);
     if (d.A2)
-      rows_f64<kRPW>(static_cast<const double2*>(d.A2), d.lda2, d.rows, d.cols, d.x2, row0, lane, d.alpha2, yr, yi);
+      rows_f64<kRPW>(static_cast<const double2*>(d.A2), d.lda2, d.rows, d.cols, d.x2, row0, lane, make_double2(d.a2r, d.a2i), yr, yi);
   }
 #pragma unroll
   for (int r = 0; r < kRPW; ++r) {
@@ -287,6 +287,11 @@ __global__ void k_axpby(int64_t n, double2 a, const double2* __restrict__ x, dou
   z += int64_t(blockIdx.y) * ldz;
   const double2 u = x ? x[i] : make_double2(0, 0), v = y ? y[i] : make_double2(0, 0);
   z[i] = make_double2(a.x * u.x - a.y * u.y + b.x * v.x - b.y * v.y, a.x * u.y + a.y * u.x + b.x * v.y + b.y * v.x);
+}
+
+__global__ void k_diag(const double2* __restrict__ A, int64_t ld, int64_t n, double2* __restrict__ out) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = A[i * ld + i];
 }
 
 __global__ void k_cast_f32(const double2* __restrict__ src, int64_t rows, int64_t cols, int64_t lds,
@@ -637,8 +642,9 @@ void launch_gemv_grouped(const GemvDesc* host_descs, int n, hipStream_t st) {
     pack.n = std::min(kMaxGroup, n - base);
     int64_t tiles = 0;
     for (int i = 0; i < pack.n; ++i) {
-      pack.d[i] = host_descs[base + i];
-      pack.d[i].tile0 = tiles;
+      const GemvDesc& h = host_descs[base + i];
+      pack.d[i] = GemvDev{h.A,       h.A2,      h.lda,      h.lda2,     h.rows,       h.cols, h.x, h.x2, h.y,
+                          h.alpha.x, h.alpha.y, h.alpha2.x, h.alpha2.y, h.accumulate, h.fp32, tiles};
       tiles += (pack.d[i].rows + dev::kRowsPerBlock - 1) / dev::kRowsPerBlock;
     }
     if (tiles == 0) continue;
@@ -689,6 +695,12 @@ void launch_axpby(int64_t n, double2 a, const double2* x, double2 b, const doubl
   if (R <= 0 || n <= 0) return;
   hipLaunchKernelGGL(dev::k_axpby, dim3(unsigned((n + 255) / 256), unsigned(R)), dim3(256), 0, st, n, a, x, b, y, z,
                      ldx, ldy, ldz);
+  BEM_HIP(hipGetLastError());
+}
+
+void launch_diag(const double2* A, int64_t ld, int64_t n, double2* out, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(dev::k_diag, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, A, ld, n, out);
   BEM_HIP(hipGetLastError());
 }
 

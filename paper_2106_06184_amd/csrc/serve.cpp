@@ -25,16 +25,81 @@ struct Request {
   std::chrono::steady_clock::time_point t_submit;
 };
 
-size_t Server::estimate_bytes(int64_t nt, int64_t ne, int64_t nobj, int precision, int restart) {
-  const double per = precision == BEM_MIXED ? 24.0 : 16.0;  // float64 + optional float32 copy
-  const double dense = per * (4.0 * double(ne) * ne / std::max<int64_t>(nobj, 1) + double(ne) * ne +
-                              2.0 * double(nt) * nt);
-  const double scratch = 16.0 * 9.0 * double(nt) * nt;  // fill scratch (released after assembly)
-  const double krylov = 16.0 * (double(restart + 1) * (2 * ne + nt) + 201.0 * (ne + nt) + 12.0 * (ne + nt));
-  return size_t(dense + scratch + krylov + 64.0 * 1024 * 1024);
+// ---------------------------------------------------------------- combiner
+
+namespace {
+// Time a waiting product gives the other solving requests to join its launch.
+constexpr auto kCombineWindow = std::chrono::microseconds(100);
+thread_local hipEvent_t tl_ready = nullptr, tl_done = nullptr;
+}  // namespace
+
+Combiner::Combiner(int device) {
+  (void)device;
+  BEM_HIP(hipStreamCreateWithFlags(&stream_, hipStreamNonBlocking));
 }
 
-Server::Server(Ctx* ctx) : ctx_(ctx) {
+Combiner::~Combiner() {
+  if (stream_) (void)hipStreamDestroy(stream_);
+}
+
+void Combiner::join() {
+  std::lock_guard<std::mutex> g(mu_);
+  ++solving_;
+}
+
+void Combiner::leave() {
+  std::lock_guard<std::mutex> g(mu_);
+  --solving_;
+  cv_.notify_all();  // a waiter may now complete the group
+}
+
+void Combiner::launch_all() {
+  std::vector<GemvDesc> all;
+  for (Pending* p : pending_) {
+    BEM_HIP(hipStreamWaitEvent(stream_, p->ready, 0));
+    all.insert(all.end(), p->ds->begin(), p->ds->end());
+  }
+  launch_gemv_grouped(all.data(), int(all.size()), stream_);
+  for (Pending* p : pending_) {
+    BEM_HIP(hipEventRecord(p->done, stream_));
+    p->finished = true;
+  }
+  ++launches_;
+  served_ += (long long)pending_.size();
+  pending_.clear();
+  cv_.notify_all();
+}
+
+void Combiner::run(const std::vector<GemvDesc>& ds, hipStream_t st) {
+  if (!tl_ready) {
+    BEM_HIP(hipEventCreateWithFlags(&tl_ready, hipEventDisableTiming));
+    BEM_HIP(hipEventCreateWithFlags(&tl_done, hipEventDisableTiming));
+  }
+  BEM_HIP(hipEventRecord(tl_ready, st));
+  Pending me{&ds, tl_ready, tl_done, false};
+  {
+    std::unique_lock<std::mutex> lk(mu_);
+    pending_.push_back(&me);
+    const auto deadline = std::chrono::steady_clock::now() + kCombineWindow;
+    while (!me.finished) {
+      if (int(pending_.size()) >= solving_ || std::chrono::steady_clock::now() >= deadline) {
+        launch_all();
+        break;
+      }
+      cv_.wait_until(lk, deadline);
+    }
+  }
+  BEM_HIP(hipStreamWaitEvent(st, tl_done, 0));
+}
+
+// ---------------------------------------------------------------- server
+
+size_t Server::estimate_bytes(int64_t nt, int64_t ne, int64_t nobj, int precision, int restart) {
+  (void)ne;
+  return estimate_request_bytes(nt, nobj, precision, restart, 1);
+}
+
+Server::Server(Ctx* ctx) : ctx_(ctx), comb_(ctx->device) {
   for (int s = 0; s < kSlots; ++s) threads_.emplace_back(&Server::worker, this, s);
 }
 
@@ -70,7 +135,9 @@ bem_ticket Server::submit(const bem_request& r) {
   q->E = r.E;
   q->rho = r.rho;
   const int64_t ne = 3 * r.nt / 2;
-  q->bytes = estimate_bytes(r.nt, ne, r.prob.n_obj, r.prob.precision, r.opts.restart > 0 ? r.opts.restart : 50);
+  (void)ne;
+  q->bytes = estimate_request_bytes(r.nt, r.prob.n_obj, r.prob.precision, r.opts.restart > 0 ? r.opts.restart : 50,
+                                    r.nexc);
   if (q->bytes > ctx_->budget) throw Error(BEM_E_NOMEM, "request can never fit the device budget");
   q->t_submit = std::chrono::steady_clock::now();
   std::lock_guard<std::mutex> g(mu_);
@@ -104,7 +171,7 @@ void Server::worker(int) {
   hipStream_t st = nullptr;
   double* pinned = nullptr;
   if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return;
-  if (hipHostMalloc(reinterpret_cast<void**>(&pinned), 64 * sizeof(double), hipHostMallocDefault) != hipSuccess) return;
+  if (hipHostMalloc(reinterpret_cast<void**>(&pinned), kPinnedBytes, hipHostMallocDefault) != hipSuccess) return;
   while (true) {
     std::shared_ptr<Request> q;
     {
@@ -139,7 +206,15 @@ void Server::worker(int) {
       op.stream = st;
       op.pinned = pinned;
       assemble_op(op, *mo, q->prob);
+      // solve phase: small products go through the combiner
+      struct Joined {
+        Combiner& c;
+        explicit Joined(Combiner& cc) : c(cc) { c.join(); }
+        ~Joined() { c.leave(); }
+      } joined(comb_);
+      op.comb = &comb_;
       status = solve_op(op, q->exc.data(), int64_t(q->exc.size()), q->opts, q->H, q->E, q->rho, &info, st);
+      op.comb = nullptr;
       info.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - q->t_submit).count();
     } catch (const Error& e) {
       status = e.code;
@@ -161,6 +236,9 @@ void Server::worker(int) {
   }
   if (pinned) (void)hipHostFree(pinned);
   if (st) (void)hipStreamDestroy(st);
+  if (tl_ready) (void)hipEventDestroy(tl_ready);
+  if (tl_done) (void)hipEventDestroy(tl_done);
+  tl_ready = tl_done = nullptr;
 }
 
 }  // namespace bem

@@ -67,7 +67,7 @@ Dense alloc_dense(DevArena& mem, int64_t rows, int64_t cols, bool fp32) {
   d.cols = cols;
   d.ld = pad64(std::max<int64_t>(cols, 1));
   d.d64 = mem.alloc<double2>(size_t(rows) * d.ld);
-  BEM_HIP(hipMemset(d.d64, 0, sizeof(double2) * size_t(rows) * d.ld));
+  BEM_HIP(hipMemsetAsync(d.d64, 0, sizeof(double2) * size_t(rows) * d.ld, mem.stream()));
   if (fp32) d.d32 = mem.alloc<float2>(size_t(rows) * d.ld);
   return d;
 }
@@ -166,8 +166,9 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
   op.m = &m;
   op.cells = &cdat;
   hipStream_t st = op.stream;
+  op.mem.set_stream(st);
   const Rules& R = rules();
-  fill_set_rules(R.w7, R.b3);
+  fill_set_rules(R.w7, R.b3, st);
 
   // ---- problem constants (eq. epsrc; k = sqrt(eps_c mu_r) k0 with Im k <= 0)
   if (!(prob.freq_hz > 0) || !std::isfinite(prob.freq_hz)) throw Error(BEM_E_INVALID, "frequency must be positive");
@@ -379,6 +380,10 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
     scratch_elems = std::max(scratch_elems, 3 * nto * cdat.obj_ncol[o]);
   }
   double2* H = op.mem.alloc<double2>(size_t(scratch_elems));
+  // BEM_POISON=1 fills the fill scratch with NaN first, so that a read of an entry the fill
+  // kernels did not write shows up in the blocks (a check used by the tests)
+  if (const char* e = std::getenv("BEM_POISON"); e && *e == '1')
+    BEM_HIP(hipMemsetAsync(H, 0xFF, sizeof(double2) * size_t(scratch_elems), st));
 
   hipEvent_t ev0, ev1;
   BEM_HIP(hipEventCreate(&ev0));
@@ -503,10 +508,13 @@ void build_inner_and_precond(OpObj& op, const std::vector<double>& ixdiag, hipSt
   ds.P = talloc(64 * 64);
   ds.R = talloc(size_t(64) * maxn);
   ds.C = talloc(size_t(64) * maxn);
+  // diagonals through a gather kernel and a stream-ordered copy (complete on return)
+  double2* dbuf = talloc(size_t(std::max(m.ne, m.nt)));
   auto diag_of = [&](const Dense& A) {
     std::vector<double2> d(A.rows);
-    BEM_HIP(hipMemcpy2D(d.data(), sizeof(double2), A.d64, (A.ld + 1) * sizeof(double2), sizeof(double2), A.rows,
-                        hipMemcpyDeviceToHost));
+    launch_diag(A.d64, A.ld, A.rows, dbuf, st);
+    BEM_HIP(hipMemcpyAsync(d.data(), dbuf, sizeof(double2) * A.rows, hipMemcpyDeviceToHost, st));
+    BEM_HIP(hipStreamSynchronize(st));
     return d;
   };
   auto cdv = [](double2 v) { return cd(v.x, v.y); };
@@ -686,6 +694,33 @@ WorkView batch_views(OpObj& op, DevArena& mem, int R) {
   return v;
 }
 
+// Matrix bytes below which a one- or two-column product is handed to the serving loop's
+// combiner (it would not fill the GPU alone).
+constexpr double kCombineMaxBytes = 256.0 * 1024 * 1024;
+
+void products(OpObj& op, const std::vector<GemvDesc>& ds, const WorkView& wv, hipStream_t st) {
+  const int R = wv.R;
+  if (ds.empty()) return;
+  if (op.comb && R <= 2) {
+    double bytes = 0;
+    for (const GemvDesc& d : ds) bytes += double(d.rows) * d.cols * (d.fp32 ? 8.0 : 16.0) * (d.A2 ? 2 : 1);
+    if (bytes < kCombineMaxBytes) {
+      std::vector<GemvDesc> all;
+      for (int r = 0; r < R; ++r)
+        for (const GemvDesc& d : ds) {
+          GemvDesc c = d;
+          c.x = d.x + r * d.ldx;
+          if (d.x2) c.x2 = d.x2 + r * d.ldx2;
+          c.y = d.y + r * d.ldy;
+          all.push_back(c);
+        }
+      op.comb->run(all, st);
+      return;
+    }
+  }
+  launch_products(ds, R, wv.gws, wv.gws_bytes, st);
+}
+
 GemvDesc with_ld(GemvDesc d, int64_t ldx, int64_t ldy, int64_t ldx2 = 0) {
   d.ldx = ldx;
   d.ldy = ldy;
@@ -709,7 +744,7 @@ void precond_cols(OpObj& op, const WorkView& wv, const double2* r, double2* x, i
     const int64_t q0 = op.obj_q[o], nq = op.obj_q[o + 1] - q0;
     ds.push_back(with_ld(desc(op.SigP[o], fp32, 0, 0, nq, nq, wv.pc_z + q0, x3 + q0, c2(1.0), 0), L, ld));
   }
-  launch_products(ds, R, wv.gws, wv.gws_bytes, st);
+  products(op, ds, wv, st);
   launch_expand_charge(x3, wv.pc_v, op.obj_tri_d, op.nobj, c2(1.0), st, R, ld, L);
   launch_pc_stage2(op.pcW, r1, r2, wv.pc_v, op.lam_bg, op.lam_int, c2(1.0 / op.eps_bg), op.eps_inv_edge, op.tp,
                    op.tm, ne, x1, x2, st, R, ld, L);
@@ -730,7 +765,7 @@ void precond_eq_cols(OpObj& op, const WorkView& wv, const double2* r, double2* x
     const int64_t q0 = op.obj_q[o], nq = op.obj_q[o + 1] - q0;
     ds.push_back(with_ld(desc(op.SigEq[o], fp32, 0, 0, nq, nq, wv.eq_z + q0, x2 + q0, c2(1.0), 0), L, ld));
   }
-  launch_products(ds, R, wv.gws, wv.gws_bytes, st);
+  products(op, ds, wv, st);
   launch_expand_charge(x2, wv.eq_v, op.obj_tri_d, op.nobj, c2(1.0), st, R, ld, L);
   launch_peq_stage2(op.eq_d, wv.eq_t, wv.eq_v, op.lam_bg, c2(1.0 / op.eps_bg), op.tp, op.tm, ne, x1, st, R, ld, L);
 }
@@ -753,7 +788,7 @@ void meq_cols(OpObj& op, const WorkView& wv, const double2* x, int64_t ldx, doub
     ds.push_back(with_ld(desc(op.Lphi_bg, fp32, t0, t0, nto, nto, wv.mt + t0, wv.mz + t0, c2(1.0), 0), L, L));
     ds.push_back(with_ld(desc(op.LA_bg, fp32, e0, e0, neo, neo, u + e0, yu + e0, c2(op.mu_bg), 0), ldx, ldy));
   }
-  launch_products(ds, R, wv.gws, wv.gws_bytes, st);
+  products(op, ds, wv, st);
   launch_DT(wv.mz, op.tp, op.tm, op.ne, c2(-1.0 / op.eps_bg), nullptr, yu, 1, st, R, L, ldy);
   launch_FD(u, op.tri_edge, op.tri_sign, op.kept, op.nq, c2(1.0), w, c2(-op.k0 * op.k0), yw, st, R, ldx, ldx, ldy);
 }
@@ -783,7 +818,7 @@ void final_cols(OpObj& op, const WorkView& wv, const double2* x, int64_t ldx, do
     ds.push_back(with_ld(d2, ldx, ldy, ldx));
     ds.push_back(with_ld(desc(op.Lphi_int[o], fp32, 0, 0, nto, nto, wv.t1 + t0, wv.z1 + t0, c2(1.0), 0), L, L));
   }
-  launch_products(ds, R, wv.gws, wv.gws_bytes, st);
+  products(op, ds, wv, st);
   // r_in += I_x e / 2 ; y2 += -I_x e / 2 + eps_c^-1 D^T z1
   launch_spmv(op.ix_ptr, op.ix_idx, op.ix_val, ne, e, c2(0.5), wv.rin, 1, st, R, ldx, L);
   launch_spmv(op.ix_ptr, op.ix_idx, op.ix_val, ne, e, c2(-0.5), y2, 1, st, R, ldx, ldy);
@@ -799,7 +834,7 @@ void final_cols(OpObj& op, const WorkView& wv, const double2* x, int64_t ldx, do
       di.push_back(
           with_ld(desc(op.Minv[o], fp32, neo, 0, nqo, neo, wv.rin + e0, wv.sol + ne + q0, c2(1.0), 0), L, L));
     }
-    launch_products(di, R, wv.gws, wv.gws_bytes, st);
+    products(op, di, wv, st);
     op.last_inner_iters = 0;
   } else if (op.inner_mode == BEM_INNER_SCHUR) {
     // u = S^-1 r_in with the charges eliminated, then w = k0^-2 F D u
@@ -808,7 +843,7 @@ void final_cols(OpObj& op, const WorkView& wv, const double2* x, int64_t ldx, do
       const int64_t e0 = op.obj_edge[o], neo = op.obj_edge[o + 1] - e0;
       di.push_back(with_ld(desc(op.Minv[o], fp32, 0, 0, neo, neo, wv.rin + e0, wv.sol + e0, c2(1.0), 0), L, L));
     }
-    launch_products(di, R, wv.gws, wv.gws_bytes, st);
+    products(op, di, wv, st);
     launch_FD(wv.sol, op.tri_edge, op.tri_sign, op.kept, nq, c2(1.0 / (op.k0 * op.k0)), nullptr, c2(0.0),
               wv.sol + ne, st, R, L, 0, L);
     op.last_inner_iters = 0;
@@ -835,7 +870,7 @@ void final_cols(OpObj& op, const WorkView& wv, const double2* x, int64_t ldx, do
   launch_expand_charge(wv.xw, wv.t1, op.obj_tri_d, op.nobj, c2(1.0), st, R, L, L);
   std::vector<GemvDesc> g2 = {with_ld(desc(op.LA_bg, fp32, 0, 0, ne, ne, wv.am, y1, c2(op.mu_bg), 0), L, ldy),
                               with_ld(desc(op.Lphi_bg, fp32, 0, 0, op.nt, op.nt, wv.t1, wv.z2, c2(1.0), 0), L, L)};
-  launch_products(g2, R, wv.gws, wv.gws_bytes, st);
+  products(op, g2, wv, st);
   // y1 += eps_l^-1 D^T z2 + I_x e ;  y3 = F D (a - u) + k0^2 (x3 + w)
   launch_DT(wv.z2, op.tp, op.tm, ne, c2(1.0 / op.eps_bg), nullptr, y1, 1, st, R, L, ldy);
   launch_spmv(op.ix_ptr, op.ix_idx, op.ix_val, ne, e, c2(1.0), y1, 1, st, R, ldx, ldy);
@@ -864,6 +899,7 @@ void apply_block(OpObj& op, int block, const double2* x, double2* y, int64_t nrh
   if (nrhs <= 0) return;
   const int R = int(nrhs);
   DevArena tmp(op.ctx);
+  tmp.set_stream(st);
   const WorkView wv = R == 1 ? views(op) : batch_views(op, tmp, R);
   std::vector<GemvDesc> ds;
   switch (block) {
@@ -900,7 +936,7 @@ void apply_block(OpObj& op, int block, const double2* x, double2* y, int64_t nrh
     default:
       throw Error(BEM_E_INVALID, "unknown block");
   }
-  launch_products(ds, R, wv.gws, wv.gws_bytes, st);
+  products(op, ds, wv, st);
   // the batch work is freed on return: let the launches that read it finish first
   if (R > 1) BEM_HIP(hipStreamSynchronize(st));
 }
@@ -1100,9 +1136,13 @@ struct BGmres {
   // pinned host mirrors
   double2* h_nrm = nullptr;
   double* h_res = nullptr;
-  int *h_frozen = nullptr, *h_jr = nullptr, *h_idx = nullptr;
-  void* pin = nullptr;
-  BGmres(DevArena& mem, int64_t n_, int m_, int R) : n(n_), m(m_), Rmax(R) {
+  int *h_frozen = nullptr, *h_jr = nullptr, *h_idx = nullptr, *h_fz = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr};  // residuals of even / odd Arnoldi steps copied
+  // pin: pinned host staging of at least pinned_bytes(R) bytes, owned by the caller
+  static size_t pinned_bytes(int R) {
+    return size_t(R) * (sizeof(double2) + 2 * sizeof(double) + 5 * sizeof(int)) + 64;
+  }
+  BGmres(DevArena& mem, int64_t n_, int m_, int R, void* pin) : n(n_), m(m_), Rmax(R) {
     ldv = pad64(n);
     ldh = m + 2;
     hs = int64_t(m + 1) * ldh;
@@ -1122,21 +1162,22 @@ struct BGmres {
     d_frozen = mem.alloc<int>(R);
     d_jr = mem.alloc<int>(R);
     d_idx = mem.alloc<int>(R);
-    const size_t pin_bytes = size_t(R) * (sizeof(double2) + sizeof(double) + 3 * sizeof(int)) + 64;
-    BEM_HIP(hipHostMalloc(&pin, pin_bytes, hipHostMallocDefault));
     char* p = static_cast<char*>(pin);
     h_nrm = reinterpret_cast<double2*>(p);
     p += sizeof(double2) * R;
-    h_res = reinterpret_cast<double*>(p);
-    p += sizeof(double) * R;
+    h_res = reinterpret_cast<double*>(p);  // two slots of R
+    p += 2 * sizeof(double) * R;
     h_frozen = reinterpret_cast<int*>(p);
     h_jr = h_frozen + R;
     h_idx = h_jr + R;
+    h_fz = h_idx + R;  // two slots of R
+    for (auto& e : ev) BEM_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
+  ~BGmres() {
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
   }
   BGmres(const BGmres&) = delete;
-  ~BGmres() {
-    if (pin) (void)hipHostFree(pin);
-  }
   void upload(int* d, const int* h, int R, hipStream_t st) {
     BEM_HIP(hipMemcpyAsync(d, h, sizeof(int) * R, hipMemcpyHostToDevice, st));
   }
@@ -1211,7 +1252,39 @@ BResult gmres_batched(BGmres& w, const BApplyFn& A, const double2* B, int64_t ld
     w.upload(w.d_frozen, w.h_frozen, Rc, st);
     launch_bscale_inv(V0, ldv, Rc, n, w.nrm, 1, w.d_frozen, st);
     launch_binit_g(w.g, m, w.nrm, 1, Rc, st);
+    // Arnoldi steps.  The residual estimates of step j are examined while step j + 1 runs: the
+    // host waits for the copy of step j - 1 only after enqueuing step j, so the GPU never idles
+    // on the convergence check; a column converged at step j - 1 stops contributing vectors
+    // from step j + 1 on (its extra vectors are not used by the back-solve).
+    std::vector<char> frozen(Rc);
+    for (int c = 0; c < Rc; ++c) frozen[c] = char(w.h_frozen[c]);
     int j = 0;
+    auto examine = [&](int s) {
+      BEM_HIP(hipEventSynchronize(w.ev[s & 1]));
+      const double* hr = w.h_res + size_t(s & 1) * w.Rmax;
+      bool changed = false;
+      double worst = 0.0;
+      for (int c = 0; c < Rc; ++c) {
+        if (frozen[c]) continue;
+        const int col = active[c];
+        const double rr = hr[c] / bn[col];
+        if (!std::isfinite(rr)) throw Error(BEM_E_NUMERIC, "non-finite Arnoldi residual");
+        ++out.iters[col];
+        out.relres[col] = rr;
+        worst = std::max(worst, rr);
+        if (rr <= tol) {
+          frozen[c] = 1;
+          w.h_jr[c] = s + 1;
+          out.converged[col] = 1;
+          --live;
+          changed = true;
+        }
+      }
+      if (verbose())
+        std::fprintf(stderr, "[bem] batched step %d: %d of %d columns active, worst res %.3e\n", s + 1, live, Rc,
+                     worst);
+      return changed;
+    };
     for (; j < m && total < maxit; ++j) {
       double2* Vj = w.V + int64_t(j) * Rc * ldv;
       double2* Vn = w.V + int64_t(j + 1) * Rc * ldv;
@@ -1231,37 +1304,26 @@ BResult gmres_batched(BGmres& w, const BApplyFn& A, const double2* B, int64_t ld
       launch_bscale_inv(Vn, ldv, Rc, n, Hj + j + 1, w.hs, w.d_frozen, st);
       launch_bgivens(w.H, w.hs, w.ldh, j, w.cs, w.sn, w.g, w.res, w.h2, m, Rc, st);
       ++total;
-      BEM_HIP(hipMemcpyAsync(w.h_res, w.res, sizeof(double) * Rc, hipMemcpyDeviceToHost, st));
-      BEM_HIP(hipStreamSynchronize(st));
-      bool changed = false;
-      double worst = 0.0;
-      for (int c = 0; c < Rc; ++c) {
-        if (w.h_frozen[c]) continue;
-        const int col = active[c];
-        const double rr = w.h_res[c] / bn[col];
-        if (!std::isfinite(rr)) throw Error(BEM_E_NUMERIC, "non-finite Arnoldi residual");
-        ++out.iters[col];
-        out.relres[col] = rr;
-        worst = std::max(worst, rr);
-        if (rr <= tol) {
-          w.h_frozen[c] = 1;
-          w.h_jr[c] = j + 1;
-          out.converged[col] = 1;
-          --live;
-          changed = true;
+      BEM_HIP(hipMemcpyAsync(w.h_res + size_t(j & 1) * w.Rmax, w.res, sizeof(double) * Rc, hipMemcpyDeviceToHost,
+                             st));
+      BEM_HIP(hipEventRecord(w.ev[j & 1], st));
+      if (j >= 1) {
+        if (examine(j - 1)) {
+          // stage the new flags in this step's slot (the slot of step j - 2 is free: its copy
+          // was enqueued before the event just waited for)
+          int* fz = w.h_fz + size_t(j & 1) * w.Rmax;
+          for (int c = 0; c < Rc; ++c) fz[c] = frozen[c];
+          w.upload(w.d_frozen, fz, Rc, st);
+        }
+        if (live == 0) {
+          ++j;
+          break;
         }
       }
-      if (verbose())
-        std::fprintf(stderr, "[bem] batched step %d: %d of %d columns active, worst res %.3e\n", total, live, Rc,
-                     worst);
-      if (live == 0) {
-        ++j;
-        break;
-      }
-      if (changed) w.upload(w.d_frozen, w.h_frozen, Rc, st);
     }
+    if (live > 0 && j >= 1) examine(j - 1);  // the last step's estimates
     for (int c = 0; c < Rc; ++c)
-      if (!w.h_frozen[c]) w.h_jr[c] = j;
+      if (!frozen[c]) w.h_jr[c] = j;
     w.upload(w.d_jr, w.h_jr, Rc, st);
     launch_bbacksolve(w.H, w.hs, w.ldh, w.d_jr, w.g, w.y, m, Rc, st);
     // X[:, active] += M (V y)
@@ -1386,6 +1448,21 @@ constexpr int kMaxBatch = 256;
 
 }  // namespace
 
+size_t estimate_request_bytes(int64_t nt, int64_t nobj, int precision, int restart, int64_t nexc) {
+  const double ne = 1.5 * double(nt), no = double(std::max<int64_t>(nobj, 1));
+  const double nq = double(nt) - no, N = 2 * ne + nq, neq = ne + nq;
+  const double per = precision == BEM_MIXED ? 24.0 : 16.0;  // float64 + float32 copy
+  const double dense = per * ((3 * ne * ne + double(nt) * nt) / no + ne * ne + double(nt) * nt);
+  const double fill_scratch = 16.0 * 9.0 * double(nt) * nt;
+  const double inner = per * (neq * neq) / no + per * (nq * nq) / no;  // augmented inverse + Sigma_P^-1
+  const double R = double(std::min<int64_t>(std::max<int64_t>(nexc, 1), kMaxBatch));
+  const double ldN = double(pad64(int64_t(N)));
+  const double solve = 16.0 * R * (ldN * (restart + 1 + 3 + 4) + double(kWorkFields) * pad64(int64_t(neq))) +
+                       double(gemm_workspace_bytes(int64_t(std::max(ne, double(nt))), int64_t(R))) +
+                       16.0 * (ne * (nexc + 1) + 2 * 64.0 * neq);
+  return size_t(std::max(dense + fill_scratch, dense + inner + solve) + 64.0 * 1024 * 1024);
+}
+
 int solve_op(OpObj& op, const bem_excitation* exc, int64_t nexc, const bem_solve_opts& opts, bem_c64* Hout,
              bem_c64* Eout, bem_c64* rhoout, bem_solve_info* info, hipStream_t st) {
   auto tstart = std::chrono::steady_clock::now();
@@ -1393,6 +1470,7 @@ int solve_op(OpObj& op, const bem_excitation* exc, int64_t nexc, const bem_solve
   if (!(opts.tol > 0) || opts.restart <= 0 || opts.maxit <= 0) throw Error(BEM_E_INVALID, "invalid solve options");
   const int64_t ne = op.ne, nt = op.nt, N = op.N;
   DevArena tmp(op.ctx);
+  tmp.set_stream(st);
   double2* Bexc = tmp.alloc<double2>(size_t(ne) * nexc);
   build_rhs(op, tmp, exc, nexc, Bexc, st);
   const double inner = opts.inner_tol > 0 ? opts.inner_tol : 0.1 * opts.tol;
@@ -1419,7 +1497,8 @@ int solve_op(OpObj& op, const bem_excitation* exc, int64_t nexc, const bem_solve
     while (Rb > 1 && est(Rb) > 0.5 * double(avail)) Rb = (Rb + 1) / 2;
   }
   const int64_t ldN = pad64(N);
-  BGmres bw(tmp, N, opts.restart, Rb);
+  while (Rb > 1 && BGmres::pinned_bytes(Rb) > kPinnedBytes - kPinnedScalars * sizeof(double)) Rb = (Rb + 1) / 2;
+  BGmres bw(tmp, N, opts.restart, Rb, op.pinned + kPinnedScalars);
   WorkView wv = batch_views(op, tmp, Rb);
   double2* bfull = tmp.alloc<double2>(size_t(Rb) * ldN);
   double2* xs = tmp.alloc<double2>(size_t(Rb) * ldN);
@@ -1482,7 +1561,8 @@ int solve_op(OpObj& op, const bem_excitation* exc, int64_t nexc, const bem_solve
       int left = opts.maxit;
       auto upload_active = [&]() {
         BEM_HIP(hipStreamSynchronize(st));
-        BEM_HIP(hipMemcpy(ref_idx, active.data(), sizeof(int) * active.size(), hipMemcpyHostToDevice));
+        BEM_HIP(hipMemcpyAsync(ref_idx, active.data(), sizeof(int) * active.size(), hipMemcpyHostToDevice, st));
+        BEM_HIP(hipStreamSynchronize(st));
       };
       for (int s = 0; s < sweeps && left > 0 && !active.empty(); ++s) {
         const int Rc = int(active.size());
