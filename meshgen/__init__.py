@@ -264,3 +264,42 @@ def copper_bars(h_min: float = 0.05e-6, h_max: float = 1.0e-6, pitch: float = 3.
             x, t = _box_surface(xs, cs + iy * pitch, cs + iz * pitch)
             meshes.append((x, t))
     return merge(meshes)
+
+
+def serving_stream(n_req: int = 24, rate_hz: float = 6.0, seed: int = 5, n_min: int = 320, n_max: int = 3072,
+                   k0a_max: float = 3.0, eps_max: float = 6.0, exc_max: int = 16):
+    """A stream of scattering requests with Poisson arrivals (mean rate `rate_hz`).
+
+    Each request: a sphere (icosphere), an ellipsoid (cubed sphere, semi-axes 1/0.7/0.5) or a
+    cube, with a triangle count log-uniform in [n_min, n_max] (the nearest mesh of its kind),
+    eps_r ~ U[1.5, eps_max], k0 a ~ U[0.5, k0a_max] (a = largest half-size), and a
+    log-uniform number of random plane waves in [1, exc_max].  Returns a list of
+    (arrival time in s, Workload).
+    """
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for i in range(n_req):
+        t += float(rng.exponential(1.0 / rate_hz))
+        target = math.exp(rng.uniform(math.log(n_min), math.log(n_max)))
+        kind = int(rng.integers(3))
+        if kind == 0:
+            level = int(min(range(1, 6), key=lambda L: abs(20 * 4 ** L - target)))
+            xyz, tri = icosphere(level)
+            size, name = 1.0, f"sphere{len(tri)}"
+        else:
+            n = max(2, int(round(math.sqrt(target / 12.0))))
+            if kind == 1:
+                xyz, tri = cubed_sphere(n, (1.0, 0.7, 0.5))
+                size, name = 1.0, f"ellipsoid{len(tri)}"
+            else:
+                xyz, tri = cube(n, 2.0)
+                size, name = 1.0, f"cube{len(tri)}"
+        eps = float(rng.uniform(1.5, eps_max))
+        k0a = float(rng.uniform(0.5, k0a_max))
+        n_exc = int(round(math.exp(rng.uniform(0.0, math.log(exc_max)))))
+        khat, pol = plane_wave_draws(n_exc, seed=1000 + i)
+        w = Workload(f"{name}_k0a{k0a:.2f}_eps{eps:.2f}_x{n_exc}", xyz, tri, np.zeros(len(tri), np.int32),
+                     freq_from_k0(k0a / size), [eps], [1.0], [0.0], khat=khat, pol=pol.astype(np.complex128))
+        out.append((t, w))
+    return out

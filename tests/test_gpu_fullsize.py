@@ -1,0 +1,101 @@
+"""Full-size checks on the 5120-triangle sphere, in the configuration the benchmark times.
+
+The oracle cannot fill or solve this size in seconds, so the checks are (1) sampled rows of
+every dense block, which the oracle computes one test triangle at a time, and (2) a property
+that holds at any size: for a transparent object (object medium = background medium) the
+equivalent and original problems coincide and the BC coefficients of E satisfy I_x e = b
+(b the plane-wave right-hand side), with I_x and b from the oracle.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import meshgen
+import paper_2106_06184_amd as B
+from oracle import constants as OC
+from oracle import mesh as OM
+from oracle import operators as OO
+from tests.bemutil import edge_perm
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def c2():
+    w = meshgen.config_c2()
+    topo = OM.build_topology(w.xyz, w.tri, w.obj)
+    return w, topo
+
+
+def test_sampled_rows_match_oracle(c2):
+    """Rows of L^A, L^phi, K~ at the object and background wavenumbers for a seeded sample of
+    edges (both their triangles filled by the oracle) and triangles: 1e-12 relative per row."""
+    w, topo = c2
+    rng = np.random.default_rng(17)
+    ne, nt = len(topo.edges), len(topo.tri)
+    edges_o = rng.choice(ne, size=3, replace=False)               # oracle edge indices
+    tris = np.unique(np.concatenate([topo.tplus[edges_o], topo.tminus[edges_o], rng.choice(nt, 2)]))
+    bary = OM.buffa_christiansen(topo)
+    near = OO.near_pairs(topo)
+    bcd = OO.bc_on_subtriangles(bary)
+    k0 = OC.k0_of(w.freq_hz)
+    k_int = OC.wavenumber(k0, OC.eps_c(w.eps_r[0], w.sigma[0], w.freq_hz), w.mu_r[0])
+    k_bg = OC.wavenumber(k0, 1.0, 1.0)
+
+    ctx = B.bem_create(0)
+    mesh = B.bem_mesh_load(ctx, w.xyz, w.tri, w.obj)
+    op = B.bem_assemble(ctx, mesh, B.make_problem(w.freq_hz, w.eps_r, w.mu_r, w.sigma, precision=B.BEM_MIXED))
+    va, vb, _, _ = B.bem_edge_table(ctx, mesh)
+    perm = edge_perm(va, vb, topo.edges)                          # library edge -> oracle edge
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(ne)                                     # oracle edge -> library edge
+    rows_lib = inv[edges_o]
+
+    for k, (bla, blp, bk) in ((k_int, (B.BEM_BLOCK_LA_INT, B.BEM_BLOCK_LPHI_INT, B.BEM_BLOCK_K_INT)),
+                              (k_bg, (B.BEM_BLOCK_LA_BG, B.BEM_BLOCK_LPHI_BG, B.BEM_BLOCK_K_BG))):
+        LA, Lp = OO.fill_L(topo, k, near, test_subset=tris)
+        K = OO.fill_K(topo, bary, k, near, bcd, test_subset=tris)
+        for blk, ref_rows, lib_rows, n, cols in ((bla, LA[edges_o], rows_lib, ne, perm),
+                                                 (bk, K[edges_o], rows_lib, ne, perm),
+                                                 (blp, Lp[tris], tris, nt, np.arange(nt))):
+            G = B.bem_block_export(ctx, op, blk, n, n)
+            got = G[lib_rows][:, np.argsort(cols)] if blk != blp else G[lib_rows]
+            del G
+            for r in range(len(ref_rows)):
+                err = np.abs(got[r] - ref_rows[r]).max() / np.abs(ref_rows[r]).max()
+                assert err < 1e-12, (blk, r, err)
+            print(f"block {blk}: {len(ref_rows)} rows of {n} match to 1e-12")
+    B.bem_release(ctx, op)
+    B.bem_destroy(ctx)
+
+
+def test_transparent_object_identity_fullsize(c2):
+    """Object with the background's medium (eps_r = eps_l = 2 - 0.2j), solved as the benchmark
+    solves (mixed precision, automatic nested solve, block preconditioner, restart 100):
+    ||I_x e - b|| <= 1e-6 ||b|| with the oracle's I_x and b."""
+    w, topo = c2
+    eps = 2.0 - 0.2j
+    freq = meshgen.freq_from_k0(3.0)
+    ctx = B.bem_create(0)
+    mesh = B.bem_mesh_load(ctx, w.xyz, w.tri, w.obj)
+    op = B.bem_assemble(ctx, mesh, B.make_problem(freq, [eps], [1.0], [0.0], eps_bg=eps, precision=B.BEM_MIXED))
+    info = B.bem_mesh_info(ctx, mesh)
+    rc, H, E, rho, si = B.bem_solve(ctx, op, B.plane_waves(w.khat, w.pol),
+                                    B.solve_opts(tol=1e-9, restart=100, maxit=3000, max_refine=8),
+                                    info["n_edge"], info["n_tri"])
+    va, vb, _, _ = B.bem_edge_table(ctx, mesh)
+    B.bem_release(ctx, op)
+    B.bem_destroy(ctx)
+    assert rc == B.BEM_OK
+    perm = edge_perm(va, vb, topo.edges)
+    e = np.zeros(len(topo.edges), complex)
+    e[perm] = E[:, 0] / OC.ETA0
+    bary = OM.buffa_christiansen(topo)
+    Ix = OO.gram_Ix(topo, bary)
+    k0 = OC.k0_of(freq)
+    k_l = OC.wavenumber(k0, eps, 1.0)
+    b = OO.rhs_plane_wave(topo, k_l, w.khat[0], w.pol[0])
+    err = np.linalg.norm(Ix @ e - b) / np.linalg.norm(b)
+    print(f"outer {si.outer_iters}, residual {si.rel_residual:.2e}, ||I_x e - b|| / ||b|| = {err:.2e}")
+    assert err < 1e-6
