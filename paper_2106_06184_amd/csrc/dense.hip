@@ -38,74 +38,121 @@ __device__ __forceinline__ double2 cinv(double2 a) {
   return make_double2(a.x / d, -a.y / d);
 }
 
-// In-place inversion of the b x b diagonal block, copied to P (ld NB).
+// In-place inversion of the b x b diagonal block, copied to P (ld NB).  Thread t keeps the 4 x 4
+// sub-block (rows 4 (t / 16) + [0, 4), columns 4 (t % 16) + [0, 4)) of the block in registers;
+// at pivot p the owners of row p and of column p publish them in LDS (double-buffered by the
+// parity of p, so one barrier per pivot suffices) and every thread updates its 16 entries:
+//   M[p][p] <- 1/a,  M[p][c] <- M[p][c]/a,  M[r][p] <- -M[r][p]/a,
+//   M[r][c] <- M[r][c] - M[r][p] M[p][c]/a      (a = M[p][p] before the step).
+// Entries outside the b x b block are identity (so padded pivots are 1).
 __global__ void __launch_bounds__(256) k_gj_diag(double2* __restrict__ A, int64_t ld, int64_t k0, int b,
                                                  double2* __restrict__ P) {
-  __shared__ double2 M[NB][NB];
-  for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
-    const int r = e / NB, c = e % NB;
-    M[r][c] = (r < b && c < b) ? A[(k0 + r) * ld + k0 + c] : make_double2(0, 0);
-  }
-  __syncthreads();
-  for (int p = 0; p < b; ++p) {
-    const double2 inv = cinv(M[p][p]);
-    __syncthreads();
-    // scale row p
-    for (int c = threadIdx.x; c < b; c += blockDim.x)
-      if (c != p) M[p][c] = cm(M[p][c], inv);
-    __syncthreads();
-    // eliminate column p from the other rows
-    for (int e = threadIdx.x; e < b * b; e += blockDim.x) {
-      const int r = e / b, c = e % b;
-      if (r != p && c != p) {
-        const double2 f = M[r][p], g = M[p][c];
-        M[r][c].x -= f.x * g.x - f.y * g.y;
-        M[r][c].y -= f.x * g.y + f.y * g.x;
-      }
+  __shared__ double2 rowp[2][NB], colp[2][NB];
+  const int t = threadIdx.x;
+  const int r0 = 4 * (t >> 4), c0 = 4 * (t & 15);
+  double2 m[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int r = r0 + i, c = c0 + j;
+      m[i][j] = (r < b && c < b) ? A[(k0 + r) * ld + k0 + c] : make_double2(r == c ? 1.0 : 0.0, 0.0);
+    }
+  for (int p = 0; p < NB; ++p) {
+    const int buf = p & 1;
+    const int pl = p & 3;
+    // (register arrays are indexed with compile-time constants only, so they stay in VGPRs)
+    if ((p >> 2) == (r0 >> 2)) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (i == pl) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) rowp[buf][c0 + j] = m[i][j];
+        }
+    }
+    if ((p >> 2) == (c0 >> 2)) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (j == pl) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) colp[buf][r0 + i] = m[i][j];
+        }
     }
     __syncthreads();
-    for (int r = threadIdx.x; r < b; r += blockDim.x)
-      if (r != p) {
-        const double2 f = M[r][p];
-        M[r][p] = make_double2(-(f.x * inv.x - f.y * inv.y), -(f.x * inv.y + f.y * inv.x));
+    const double2 inv = cinv(rowp[buf][p]);
+    double2 g[4], cr[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) g[j] = cm(rowp[buf][c0 + j], inv);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) cr[i] = colp[buf][r0 + i];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        m[i][j].x -= cr[i].x * g[j].x - cr[i].y * g[j].y;
+        m[i][j].y -= cr[i].x * g[j].y + cr[i].y * g[j].x;
       }
-    if (threadIdx.x == 0) M[p][p] = inv;
-    __syncthreads();
+    // pivot row and column: M[p][c] = g[c], M[r][p] = -M[r][p] / a (old M[r][p] = colp), M[p][p] = 1/a
+    if ((p >> 2) == (c0 >> 2)) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (j == pl) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const double2 v = cm(cr[i], inv);
+            m[i][j] = make_double2(-v.x, -v.y);
+          }
+        }
+    }
+    if ((p >> 2) == (r0 >> 2)) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (i == pl) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) m[i][j] = (c0 + j == p) ? inv : g[j];
+        }
+    }
   }
-  for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
-    const int r = e / NB, c = e % NB;
-    P[r * NB + c] = M[r][c];
-  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) P[(r0 + i) * NB + c0 + j] = m[i][j];
 }
 
-// R[s][j] = sum_t P[s][t] A[k0+t][j] for all j (thread: one column, 16 values of s);
-// C[i][s] = A[i][k0+s] for all i (copied before the update overwrites them).
+// R[s][j] = sum_t P[s][t] A[k0+t][j] for all j (thread: one column, 8 values of s; 32 columns
+// per block so that even n = 2048 gives 64 blocks); C[i][s] = A[i][k0+s] for all i (copied
+// before the update overwrites them).
 __global__ void __launch_bounds__(256) k_gj_panels(const double2* __restrict__ A, int64_t ld, int64_t n, int64_t k0,
                                                    int b, const double2* __restrict__ P, double2* __restrict__ R,
                                                    double2* __restrict__ Cp) {
-  __shared__ double2 Ps[NB][NB];
+  __shared__ double2 Ps[NB][NB + 1];
   for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) Ps[e / NB][e % NB] = P[e];
   __syncthreads();
-  const int64_t j = int64_t(blockIdx.x) * 64 + (threadIdx.x & 63);
-  const int sg = threadIdx.x >> 6;  // s in [16 sg, 16 sg + 16)
+  const int64_t j = int64_t(blockIdx.x) * 32 + (threadIdx.x & 31);
+  const int sg = threadIdx.x >> 5;  // s in [8 sg, 8 sg + 8)
   if (j < n) {
-    double2 acc[16];
+    double2 acc[8];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) acc[u] = make_double2(0, 0);
+    for (int u = 0; u < 8; ++u) acc[u] = make_double2(0, 0);
     for (int t = 0; t < b; ++t) {
       const double2 a = A[(k0 + t) * ld + j];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const double2 p = Ps[16 * sg + u][t];
+      for (int u = 0; u < 8; ++u) {
+        const double2 p = Ps[8 * sg + u][t];
         acc[u].x += p.x * a.x - p.y * a.y;
         acc[u].y += p.x * a.y + p.y * a.x;
       }
     }
 #pragma unroll
-    for (int u = 0; u < 16; ++u)
-      if (16 * sg + u < b) R[(16 * sg + u) * n + j] = acc[u];
-    // column panel: row j of the kb columns
-    for (int s = sg; s < b; s += 4) Cp[j * NB + s] = A[j * ld + k0 + s];
+    for (int u = 0; u < 8; ++u)
+      if (8 * sg + u < b) R[(8 * sg + u) * n + j] = acc[u];
+  }
+  // column panel: rows i of the kb columns (coalesced along s)
+  for (int64_t e = int64_t(blockIdx.x) * 32 * NB + threadIdx.x; e < (int64_t(blockIdx.x) + 1) * 32 * NB;
+       e += blockDim.x) {
+    const int64_t i = e / NB;
+    const int s = int(e % NB);
+    if (i < n && s < b) Cp[i * NB + s] = A[i * ld + k0 + s];
   }
 }
 
@@ -170,46 +217,75 @@ __global__ void __launch_bounds__(256) k_gj_update(double2* __restrict__ A, int6
 // through LDS 32 reals at a time (A k-major so that operand reads are conflict-free).
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
-__global__ void __launch_bounds__(256) k_gj_update_mfma(double* __restrict__ A, int64_t ld, int64_t n, int64_t k0,
+__global__ void __launch_bounds__(256, 2) k_gj_update_mfma(double* __restrict__ A, int64_t ld, int64_t n, int64_t k0,
                                                         int b, const double2* __restrict__ R,
                                                         const double2* __restrict__ Cp) {
-  constexpr int KC = 32;  // reals of K per stage
+  constexpr int KC = 32;  // reals of K per stage (16 complex)
   __shared__ double As[KC][64 + 1];
   __shared__ double Bs[KC][128 + 2];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wm = wave >> 1, wn = wave & 1;
-  const int64_t i0 = int64_t(blockIdx.y) * 64;  // complex rows
-  const int64_t j0 = int64_t(blockIdx.x) * 64;  // complex columns
+  // XCD-aware order: the 8 XCDs take consecutive blocks round-robin; give each XCD a
+  // contiguous band of row tiles so that it re-reads the same column-panel rows from its L2
+  const unsigned nbx = gridDim.x, nby = gridDim.y, nb = nbx * nby;
+  unsigned lin = blockIdx.y * nbx + blockIdx.x;
+  if (nb % 8 == 0) lin = (lin % 8) * (nb / 8) + lin / 8;
+  const int64_t i0 = int64_t(lin / nbx) * 64;  // complex rows
+  const int64_t j0 = int64_t(lin % nbx) * 64;  // complex columns
+  // the rows and columns of the pivot block are overwritten afterwards, so the whole tile is
+  // updated; its old values are fetched first (they stream in while the product is formed)
+  double apre[2][4][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t gi = i0 + wm * 32 + a * 16 + (lane >> 4) + 4 * v;
+        const int64_t rc = 2 * j0 + wn * 64 + c * 16 + (lane & 15);
+        apre[a][c][v] = (gi < n && (rc >> 1) < n) ? A[gi * 2 * ld + rc] : 0.0;
+      }
   doublex4 acc[2][4];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[a][c] = doublex4{0, 0, 0, 0};
+  // staging: thread -> 4 consecutive complex of one row of C (row tid/4) and of one row of R
+  const int cr = tid >> 2, cs = (tid & 3) * 4;   // C: row, first s
+  const int rs = tid >> 4, rcol = (tid & 15) * 4;  // R: s, first column
+  double2 pc[4], pr[4];
+  auto fetch = [&](int s0) {
+    const int64_t gi = i0 + cr;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int sc = s0 + cs + e;
+      pc[e] = (gi < n && sc < b) ? Cp[gi * NB + sc] : make_double2(0, 0);
+    }
+    const int sr = s0 + rs;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t gj = j0 + rcol + e;
+      pr[e] = (gj < n && sr < b) ? R[int64_t(sr) * n + gj] : make_double2(0, 0);
+    }
+  };
+  auto stage = [&]() {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      As[2 * (cs + e)][cr] = pc[e].x;
+      As[2 * (cs + e) + 1][cr] = pc[e].y;
+      const int c2 = 2 * (rcol + e);
+      Bs[2 * rs][c2] = pr[e].x;
+      Bs[2 * rs][c2 + 1] = pr[e].y;
+      Bs[2 * rs + 1][c2] = -pr[e].y;
+      Bs[2 * rs + 1][c2 + 1] = pr[e].x;
+    }
+  };
   const int K = 2 * b;
+  fetch(0);
   for (int k0r = 0; k0r < K; k0r += KC) {
-    // stage A: 64 rows x 32 reals (16 complex of C)
-    for (int e = tid; e < 64 * (KC / 2); e += 256) {
-      const int r = e / (KC / 2), s = e % (KC / 2);
-      const int64_t gi = i0 + r;
-      const int sc = k0r / 2 + s;
-      double2 v = make_double2(0, 0);
-      if (gi < n && sc < b) v = Cp[gi * NB + sc];
-      As[2 * s][r] = v.x;
-      As[2 * s + 1][r] = v.y;
-    }
-    // stage B: 32 reals of K (16 complex s) x 128 reals (64 complex j)
-    for (int e = tid; e < (KC / 2) * 64; e += 256) {
-      const int s = e / 64, c = e % 64;
-      const int64_t gj = j0 + c;
-      const int sc = k0r / 2 + s;
-      double2 v = make_double2(0, 0);
-      if (gj < n && sc < b) v = R[int64_t(sc) * n + gj];
-      Bs[2 * s][2 * c] = v.x;
-      Bs[2 * s][2 * c + 1] = v.y;
-      Bs[2 * s + 1][2 * c] = -v.y;
-      Bs[2 * s + 1][2 * c + 1] = v.x;
-    }
+    stage();
     __syncthreads();
+    if (k0r + KC < K) fetch((k0r + KC) / 2);  // next chunk streams in during the MFMAs
 #pragma unroll
     for (int kk = 0; kk < KC; kk += 4) {
       const int kr = kk + (lane >> 4);
@@ -233,11 +309,8 @@ __global__ void __launch_bounds__(256) k_gj_update_mfma(double* __restrict__ A, 
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int64_t gi = i0 + wm * 32 + a * 16 + (lane >> 4) + 4 * v;
-        const int64_t rc = 2 * j0 + wn * 64 + c * 16 + (lane & 15);  // real column
-        const int64_t gj = rc >> 1;
-        if (gi >= n || gj >= n) continue;
-        if ((gi >= k0 && gi < k0 + b) || (gj >= k0 && gj < k0 + b)) continue;
-        A[gi * 2 * ld + rc] -= acc[a][c][v];
+        const int64_t rc = 2 * j0 + wn * 64 + c * 16 + (lane & 15);
+        if (gi < n && (rc >> 1) < n) A[gi * 2 * ld + rc] = apre[a][c][v] - acc[a][c][v];
       }
 }
 
@@ -435,7 +508,7 @@ void dense_invert(double2* A, int64_t n, int64_t ld, DenseScratch& ws, hipStream
   for (int64_t k0 = 0; k0 < n; k0 += dev::NB) {
     const int b = int(std::min<int64_t>(dev::NB, n - k0));
     hipLaunchKernelGGL(dev::k_gj_diag, dim3(1), dim3(256), 0, st, A, ld, k0, b, ws.P);
-    hipLaunchKernelGGL(dev::k_gj_panels, dim3(unsigned((n + 63) / 64)), dim3(256), 0, st, A, ld, n, k0, b, ws.P,
+    hipLaunchKernelGGL(dev::k_gj_panels, dim3(unsigned((n + 31) / 32)), dim3(256), 0, st, A, ld, n, k0, b, ws.P,
                        ws.R, ws.C);
     dim3 g(unsigned((n + 63) / 64), unsigned((n + 63) / 64));
     {

@@ -28,7 +28,10 @@ __device__ __forceinline__ float wave_sum(float v) {
   return v;
 }
 
-// Row sums of one matrix for RPW consecutive rows, float64 storage, float64 accumulation.
+typedef double dx2 __attribute__((ext_vector_type(2)));
+
+// Row sums of one matrix for RPW consecutive rows, float64 storage, float64 accumulation (the
+// matrix is streamed once per product: non-temporal loads keep x resident in L2).
 template <int RPW>
 __device__ __forceinline__ void rows_f64(const double2* __restrict__ A, int64_t lda, int64_t rows, int64_t cols,
                                          const double2* __restrict__ x, int64_t row0, int lane, double2 alpha,
@@ -45,8 +48,10 @@ __device__ __forceinline__ void rows_f64(const double2* __restrict__ A, int64_t 
     double2 a0[RPW], a1[RPW];
 #pragma unroll
     for (int r = 0; r < RPW; ++r) {
-      a0[r] = rowp[r][c];
-      a1[r] = rowp[r][c + kWave];
+      const dx2 u = __builtin_nontemporal_load(reinterpret_cast<const dx2*>(rowp[r] + c));
+      const dx2 w = __builtin_nontemporal_load(reinterpret_cast<const dx2*>(rowp[r] + c + kWave));
+      a0[r] = make_double2(u[0], u[1]);
+      a1[r] = make_double2(w[0], w[1]);
     }
 #pragma unroll
     for (int r = 0; r < RPW; ++r) {
@@ -71,8 +76,10 @@ __device__ __forceinline__ void rows_f64(const double2* __restrict__ A, int64_t 
   }
 }
 
+typedef float fx4 __attribute__((ext_vector_type(4)));
+
 // float32 storage and accumulation; each lane reads two consecutive complex entries per
-// 16-byte load (two 8-byte loads when the rows are not 16-byte aligned).
+// 16-byte non-temporal load (two 8-byte loads when the rows are not 16-byte aligned).
 template <int RPW, bool ALIGNED>
 __device__ __forceinline__ void rows_f32(const float2* __restrict__ A, int64_t lda, int64_t rows, int64_t cols,
                                          const double2* __restrict__ x, int64_t row0, int lane, double2 alpha,
@@ -93,8 +100,10 @@ __device__ __forceinline__ void rows_f32(const float2* __restrict__ A, int64_t l
 #pragma unroll
     for (int r = 0; r < RPW; ++r) {
       if (ALIGNED) {
-        a0[r] = *reinterpret_cast<const float4*>(rowp[r] + c);
-        a1[r] = *reinterpret_cast<const float4*>(rowp[r] + c + 2 * kWave);
+        const fx4 u = __builtin_nontemporal_load(reinterpret_cast<const fx4*>(rowp[r] + c));
+        const fx4 w = __builtin_nontemporal_load(reinterpret_cast<const fx4*>(rowp[r] + c + 2 * kWave));
+        a0[r] = make_float4(u[0], u[1], u[2], u[3]);
+        a1[r] = make_float4(w[0], w[1], w[2], w[3]);
       } else {
         const float2 p0 = rowp[r][c], p1 = rowp[r][c + 1];
         const float2 p2 = rowp[r][c + 2 * kWave], p3 = rowp[r][c + 2 * kWave + 1];
@@ -133,7 +142,7 @@ __device__ __forceinline__ void rows_f32(const float2* __restrict__ A, int64_t l
   }
 }
 
-constexpr int kRPW = 2;          // rows per wave
+constexpr int kRPW = 4;          // rows per wave
 constexpr int kWavesPerBlock = 4;
 constexpr int kRowsPerBlock = kRPW * kWavesPerBlock;
 
