@@ -127,6 +127,8 @@ def run_serve(args) -> int:
     import paper_2106_06184_amd as B
 
     stream = meshgen.serving_stream(args.serve_requests, rate_hz=args.serve_rate)
+    if args.restart <= 0:
+        args.restart = 200
     ctx = B.bem_create(0)
     opts = B.solve_opts(tol=args.tol, restart=args.restart, maxit=args.maxit, max_refine=8)
 
@@ -191,7 +193,9 @@ def main() -> int:
     ap.add_argument("--maxit", type=int, default=3000)
     ap.add_argument("--no-precond", action="store_true")
     ap.add_argument("--tol", type=float, default=1e-6)
-    ap.add_argument("--restart", type=int, default=100)
+    ap.add_argument("--restart", type=int, default=0,
+                    help="GMRES restart length (default: 300 for one excitation, 100 for batches, "
+                         "where the Gram-Schmidt cost grows with the batch)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=24)
     ap.add_argument("--serve-rate", type=float, default=6.0)
@@ -221,6 +225,8 @@ def main() -> int:
     khat, pol = (w.khat[:args.exc], w.pol[:args.exc]) if args.exc > 0 else (w.khat, w.pol)
     exc = B.plane_waves(khat, pol)
     n_exc = len(khat)
+    if args.restart <= 0:
+        args.restart = 300 if n_exc <= 8 else 100
     opts = B.solve_opts(tol=args.tol, restart=args.restart, maxit=args.maxit)
 
     def step():

@@ -239,6 +239,24 @@ def plane_waves(khat, pol, amp=1.0):
     return arr
 
 
+def delta_gaps(ports, volts=1.0):
+    """Voltage-gap excitations: ports is a list of (n_gap, 2) arrays of vertex pairs (a, b),
+    one array per excitation; the field across each listed edge drives the RWG of the directed
+    pair with `volts` (complex)."""
+    arr = (bem_excitation * len(ports))()
+    keep = []
+    for i, pairs in enumerate(ports):
+        pairs = np.ascontiguousarray(np.asarray(pairs, np.int32).reshape(-1, 2))
+        keep.append(pairs)
+        e = arr[i]
+        e.kind = BEM_EXC_DELTA_GAP
+        e.amp = c64(complex(volts).real, complex(volts).imag)
+        e.gap_edges = _iptr(pairs)
+        e.n_gap = len(pairs)
+    arr._keep = keep
+    return arr
+
+
 def solve_opts(tol=1e-8, restart=50, maxit=2000, inner_tol=0.0, max_refine=0, out_device=0):
     return bem_solve_opts(tol, restart, maxit, inner_tol, max_refine, out_device)
 

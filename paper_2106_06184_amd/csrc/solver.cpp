@@ -1476,7 +1476,7 @@ int solve_op(OpObj& op, const bem_excitation* exc, int64_t nexc, const bem_solve
   const double inner = opts.inner_tol > 0 ? opts.inner_tol : 0.1 * opts.tol;
   const double inner32 = std::max(inner, 1e-7);
   const double stol = std::max(opts.tol * 0.5, 1e-6);
-  const int sweeps = opts.max_refine > 0 ? opts.max_refine : 5;
+  const int sweeps = opts.max_refine > 0 ? opts.max_refine : (op.precision == BEM_MIXED ? 5 : 3);
   bem_solve_info inf{};
   int status = BEM_OK;
   op.max_inner_iters = 0;
@@ -1533,75 +1533,83 @@ int solve_op(OpObj& op, const bem_excitation* exc, int64_t nexc, const bem_solve
     BEM_HIP(hipMemcpy2DAsync(bfull, sizeof(double2) * ldN, Bexc + e0 * ne, sizeof(double2) * ne,
                              sizeof(double2) * ne, R, hipMemcpyDeviceToDevice, st));
     std::vector<char> conv(R, 0);
-    if (op.precision == BEM_FP64) {
-      BResult g = gmres_batched(bw, A64, bfull, ldN, xs, ldN, R, opts.tol, opts.maxit, st, Pm64);
-      for (int c = 0; c < R; ++c) {
-        inf.outer_iters += g.iters[c];
-        conv[c] = g.converged[c];
+    // One refinement loop for both precisions.  Every sweep solves A d = r for the active
+    // columns with GMRES (float32 products while in mixed precision, float64 otherwise), then
+    // x += d and the float64 residual r = b - A x is recomputed; a column leaves once
+    // ||r|| <= tol ||b||.  A float32 sweep that does not halve the residual of every active
+    // column switches the remaining sweeps to float64 products (float32 too inaccurate for
+    // this operator); in float64 precision the sweeps after the first correct the Arnoldi
+    // estimate drifting from the true residual.
+    launch_axpby(N, c2(0.0), nullptr, c2(0.0), nullptr, xs, st, R, 0, 0, ldN);
+    bw.norms(bfull, ldN, R, st);
+    std::vector<double> bn(R), rel(R, 1.0);
+    std::vector<int> active;
+    for (int c = 0; c < R; ++c) {
+      bn[c] = bw.h_nrm[c].x;
+      if (bn[c] > 0) active.push_back(c);
+      else {
+        conv[c] = 1;
+        rel[c] = 0.0;
       }
-      inf.n_products += g.products;
-      std::vector<double> rel = true_residuals(bw, A64, bfull, xs, ldN, R, st);
-      ++inf.n_products;
-      for (int c = 0; c < R; ++c) inf.rel_residual = std::max(inf.rel_residual, rel[c]);
-    } else {
-      // float32 products (and nested solves) inside GMRES with float64 Arnoldi, float64 residual
-      // refinement; converged columns leave the batch
-      launch_axpby(N, c2(0.0), nullptr, c2(0.0), nullptr, xs, st, R, 0, 0, ldN);
-      bw.norms(bfull, ldN, R, st);
-      std::vector<double> bn(R), rel(R, 1.0);
-      std::vector<int> active;
-      for (int c = 0; c < R; ++c) {
-        bn[c] = bw.h_nrm[c].x;
-        if (bn[c] > 0) active.push_back(c);
-        else {
-          conv[c] = 1;
-          rel[c] = 0.0;
-        }
-      }
-      int left = opts.maxit;
-      auto upload_active = [&]() {
-        BEM_HIP(hipStreamSynchronize(st));
-        BEM_HIP(hipMemcpyAsync(ref_idx, active.data(), sizeof(int) * active.size(), hipMemcpyHostToDevice, st));
-        BEM_HIP(hipStreamSynchronize(st));
-      };
-      for (int s = 0; s < sweeps && left > 0 && !active.empty(); ++s) {
-        const int Rc = int(active.size());
-        const int* didx = ref_idx;
-        upload_active();
-        // compacted residual: r = b - A64 x (x = 0 on the first sweep)
-        launch_gather_cols(bfull, ldN, rr, ldN, didx, N, Rc, st);
-        if (s > 0) {
-          launch_gather_cols(xs, ldN, dd, ldN, didx, N, Rc, st);
-          A64(dd, ldN, bw.T, bw.ldv, Rc);
-          ++inf.n_products;
-          launch_axpby(N, c2(1.0), rr, c2(-1.0), bw.T, rr, st, Rc, ldN, bw.ldv, ldN);
-        }
-        BEM_HIP(hipStreamSynchronize(st));
-        BResult g = gmres_batched(bw, A32, rr, ldN, dd, ldN, Rc, stol, left, st, Pm32);
-        int most = 0;
-        for (int c = 0; c < Rc; ++c) {
-          inf.outer_iters += g.iters[c];
-          most = std::max(most, g.iters[c]);
-        }
-        left -= most;
-        inf.n_products += g.products;
-        ++inf.refine_steps;
-        // x += d ; float64 residual of the updated columns
-        launch_scatter_cols(dd, ldN, xs, ldN, didx, N, Rc, 1, st);
-        launch_gather_cols(xs, ldN, dd, ldN, didx, N, Rc, st);
-        launch_gather_cols(bfull, ldN, rr, ldN, didx, N, Rc, st);
-        std::vector<double> r = true_residuals(bw, A64, rr, dd, ldN, Rc, st);
-        ++inf.n_products;
-        std::vector<int> next;
-        for (int c = 0; c < Rc; ++c) {
-          rel[active[c]] = r[c];
-          if (r[c] <= opts.tol) conv[active[c]] = 1;
-          else next.push_back(active[c]);
-        }
-        active.swap(next);
-      }
-      for (int c = 0; c < R; ++c) inf.rel_residual = std::max(inf.rel_residual, rel[c]);
     }
+    bool use32 = op.precision == BEM_MIXED;
+    int left = opts.maxit;
+    auto upload_active = [&]() {
+      BEM_HIP(hipStreamSynchronize(st));
+      BEM_HIP(hipMemcpyAsync(ref_idx, active.data(), sizeof(int) * active.size(), hipMemcpyHostToDevice, st));
+      BEM_HIP(hipStreamSynchronize(st));
+    };
+    for (int s = 0; s < sweeps && left > 0 && !active.empty(); ++s) {
+      const int Rc = int(active.size());
+      const int* didx = ref_idx;
+      upload_active();
+      // compacted residual: r = b - A64 x (x = 0 on the first sweep)
+      launch_gather_cols(bfull, ldN, rr, ldN, didx, N, Rc, st);
+      if (s > 0) {
+        launch_gather_cols(xs, ldN, dd, ldN, didx, N, Rc, st);
+        A64(dd, ldN, bw.T, bw.ldv, Rc);
+        ++inf.n_products;
+        launch_axpby(N, c2(1.0), rr, c2(-1.0), bw.T, rr, st, Rc, ldN, bw.ldv, ldN);
+      }
+      BEM_HIP(hipStreamSynchronize(st));
+      // GMRES target relative to ||r||: float32 sweeps reduce by stol; float64 sweeps aim at
+      // tol ||b|| directly (half of it, for margin)
+      double gtol = stol;
+      if (!use32) {
+        gtol = 1.0;
+        for (int c = 0; c < Rc; ++c) gtol = std::min(gtol, 0.5 * opts.tol / std::max(rel[active[c]], 1e-300));
+        gtol = std::max(gtol, 1e-15);
+      }
+      BResult g = gmres_batched(bw, use32 ? A32 : A64, rr, ldN, dd, ldN, Rc, gtol, left, st, use32 ? Pm32 : Pm64);
+      int most = 0;
+      for (int c = 0; c < Rc; ++c) {
+        inf.outer_iters += g.iters[c];
+        most = std::max(most, g.iters[c]);
+      }
+      left -= most;
+      inf.n_products += g.products;
+      if (s > 0 || use32) ++inf.refine_steps;
+      // x += d ; float64 residual of the updated columns
+      launch_scatter_cols(dd, ldN, xs, ldN, didx, N, Rc, 1, st);
+      launch_gather_cols(xs, ldN, dd, ldN, didx, N, Rc, st);
+      launch_gather_cols(bfull, ldN, rr, ldN, didx, N, Rc, st);
+      std::vector<double> r = true_residuals(bw, A64, rr, dd, ldN, Rc, st);
+      ++inf.n_products;
+      bool stalled = false;
+      std::vector<int> next;
+      for (int c = 0; c < Rc; ++c) {
+        if (r[c] > 0.5 * rel[active[c]]) stalled = true;
+        rel[active[c]] = r[c];
+        if (r[c] <= opts.tol) conv[active[c]] = 1;
+        else next.push_back(active[c]);
+      }
+      active.swap(next);
+      if (use32 && stalled && !active.empty()) {
+        use32 = false;
+        if (verbose()) std::fprintf(stderr, "[bem] float32 sweep stalled: float64 products from here on\n");
+      }
+    }
+    for (int c = 0; c < R; ++c) inf.rel_residual = std::max(inf.rel_residual, rel[c]);
     for (int c = 0; c < R; ++c)
       if (!conv[c]) status = BEM_E_NOT_CONVERGED;
     write_outputs(op, tmp, xs, ldN, R, opts, Hout ? Hout + e0 * ne : nullptr, Eout ? Eout + e0 * ne : nullptr,
