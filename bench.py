@@ -229,15 +229,24 @@ def main() -> int:
         args.restart = 300 if n_exc <= 8 else 100
     opts = B.solve_opts(tol=args.tol, restart=args.restart, maxit=args.maxit)
 
+    phases = {"mesh_load": 0.0, "assemble": 0.0, "solve": 0.0, "release": 0.0}
+
     def step():
+        t0 = time.perf_counter()
         mesh = B.bem_mesh_load(ctx, w.xyz, w.tri, w.obj)
         info = B.bem_mesh_info(ctx, mesh)
+        t1 = time.perf_counter()
         op = B.bem_assemble(ctx, mesh, B.make_problem(w.freq_hz, w.eps_r, w.mu_r, w.sigma, precision=prec,
                                                       inner_mode=inner, precond=precond))
+        t2 = time.perf_counter()
         rc, H, E, rho, si = B.bem_solve(ctx, op, exc, opts, info["n_edge"], info["n_tri"])
+        t3 = time.perf_counter()
         st = B.bem_op_stats_get(ctx, op)
         B.bem_release(ctx, op)
         B.bem_release(ctx, mesh)
+        t4 = time.perf_counter()
+        for k, dt in zip(phases, (t1 - t0, t2 - t1, t3 - t2, t4 - t3)):
+            phases[k] += dt
         if rc != B.BEM_OK or not (si.rel_residual <= args.tol):
             raise RuntimeError(f"solve failed: status {rc}, residual {si.rel_residual:.3e}")
         return info, si, st
@@ -259,6 +268,8 @@ def main() -> int:
             f"products {si.n_products}, res {si.rel_residual:.2e}, fill {st['fill_seconds']*1e3:.1f} ms")
     torch.cuda.synchronize()
     total = time.perf_counter() - t_start
+    log("  phases per step (host wall clock, includes warm-up): " +
+        ", ".join(f"{k} {1e3 * v / (args.steps + args.warmup):.1f} ms" for k, v in phases.items()))
     prof = {k: B.bem_profile_read(k) for k in range(len(B.KC_NAMES))}
     B.bem_profile_enable(False)
     names = dict(enumerate(B.KC_NAMES))

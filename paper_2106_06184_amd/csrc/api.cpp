@@ -62,6 +62,8 @@ Ctx::~Ctx() {
   meshes.clear();
   if (pinned) (void)hipHostFree(pinned);
   if (stream) (void)hipStreamDestroy(stream);
+  for (auto& kv : cache) (void)hipFree(kv.second);
+  cache.clear();
 }
 }  // namespace bem
 

@@ -28,7 +28,13 @@ struct Ctx {
   std::map<uint64_t, std::unique_ptr<struct OpObj>> ops;
   double* pinned = nullptr;  // small pinned host buffer for convergence scalars
   std::unique_ptr<Server> server;
-  std::mutex mu;             // guards `used` (the serving thread allocates too)
+  std::mutex mu;             // guards `used` and the block cache (the serving threads allocate too)
+  // Device blocks released by finished work, kept for reuse (hipMalloc / hipFree of the
+  // multi-GB dense blocks cost milliseconds and synchronise the device).  `used` counts
+  // blocks in use, `cached` the idle ones; both count against the budget, and idle blocks
+  // are freed when a new allocation would not fit otherwise.
+  std::multimap<size_t, void*> cache;
+  size_t cached = 0;
   ~Ctx();
 };
 

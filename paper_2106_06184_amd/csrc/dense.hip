@@ -222,7 +222,7 @@ __global__ void __launch_bounds__(256, 2) k_gj_update_mfma(double* __restrict__ 
                                                         const double2* __restrict__ Cp) {
   constexpr int KC = 32;  // reals of K per stage (16 complex)
   __shared__ double As[KC][64 + 1];
-  __shared__ double Bs[KC][128 + 2];
+  __shared__ __align__(16) double Bs[KC][128 + 2];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wm = wave >> 1, wn = wave & 1;
   // XCD-aware order: the 8 XCDs take consecutive blocks round-robin; give each XCD a
@@ -250,34 +250,28 @@ __global__ void __launch_bounds__(256, 2) k_gj_update_mfma(double* __restrict__ 
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[a][c] = doublex4{0, 0, 0, 0};
-  // staging: thread -> 4 consecutive complex of one row of C (row tid/4) and of one row of R
-  const int cr = tid >> 2, cs = (tid & 3) * 4;   // C: row, first s
-  const int rs = tid >> 4, rcol = (tid & 15) * 4;  // R: s, first column
+  // staging: thread -> one row of C (row tid % 64) and one column of R (column tid % 64), four
+  // consecutive s each (group tid / 64): the R loads are coalesced along columns, and both
+  // LDS stores are consecutive across lanes (R as 16-byte (re, im) / (-im, re) pairs)
+  const int sr = tid & 63, sg = (tid >> 6) * 4;
   double2 pc[4], pr[4];
   auto fetch = [&](int s0) {
-    const int64_t gi = i0 + cr;
+    const int64_t gi = i0 + sr, gj = j0 + sr;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const int sc = s0 + cs + e;
+      const int sc = s0 + sg + e;
       pc[e] = (gi < n && sc < b) ? Cp[gi * NB + sc] : make_double2(0, 0);
-    }
-    const int sr = s0 + rs;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int64_t gj = j0 + rcol + e;
-      pr[e] = (gj < n && sr < b) ? R[int64_t(sr) * n + gj] : make_double2(0, 0);
+      pr[e] = (gj < n && sc < b) ? R[int64_t(sc) * n + gj] : make_double2(0, 0);
     }
   };
   auto stage = [&]() {
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      As[2 * (cs + e)][cr] = pc[e].x;
-      As[2 * (cs + e) + 1][cr] = pc[e].y;
-      const int c2 = 2 * (rcol + e);
-      Bs[2 * rs][c2] = pr[e].x;
-      Bs[2 * rs][c2 + 1] = pr[e].y;
-      Bs[2 * rs + 1][c2] = -pr[e].y;
-      Bs[2 * rs + 1][c2 + 1] = pr[e].x;
+      const int k = 2 * (sg + e);
+      As[k][sr] = pc[e].x;
+      As[k + 1][sr] = pc[e].y;
+      *reinterpret_cast<double2*>(&Bs[k][2 * sr]) = pr[e];
+      *reinterpret_cast<double2*>(&Bs[k + 1][2 * sr]) = make_double2(-pr[e].y, pr[e].x);
     }
   };
   const int K = 2 * b;

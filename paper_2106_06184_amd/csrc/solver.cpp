@@ -113,21 +113,64 @@ static bool verbose() {
 
 // ----------------------------------------------------------------- arena / ctx
 
+namespace {
+// Allocation granule of the block cache: sizes are rounded up so that repeated assemblies of
+// similar problems find their blocks again.
+size_t granule(size_t bytes) {
+  const size_t g = bytes >= (size_t(64) << 20) ? (size_t(2) << 20) : (bytes >= (size_t(1) << 20) ? 65536 : 256);
+  return (bytes + g - 1) / g * g;
+}
+}  // namespace
+
 void* DevArena::raw(size_t bytes) {
+  bytes = granule(std::max<size_t>(bytes, 1));
+  std::vector<void*> evict;
+  void* p = nullptr;
   {
     std::lock_guard<std::mutex> g(ctx_->mu);
-    if (ctx_->used + bytes > ctx_->budget)
-      throw Error(BEM_E_NOMEM, "device memory budget exceeded (" + std::to_string(ctx_->used + bytes) + " > " +
-                                   std::to_string(ctx_->budget) + " bytes)");
+    // reuse an idle block of this size (at most 1/8 larger)
+    auto it = ctx_->cache.lower_bound(bytes);
+    if (it != ctx_->cache.end() && it->first <= bytes + bytes / 8) {
+      bytes = it->first;
+      p = it->second;
+      ctx_->cache.erase(it);
+      ctx_->cached -= bytes;
+    } else {
+      // make room: drop idle blocks (largest first) until the request fits the budget
+      while (ctx_->used + ctx_->cached + bytes > ctx_->budget && !ctx_->cache.empty()) {
+        auto last = std::prev(ctx_->cache.end());
+        evict.push_back(last->second);
+        ctx_->cached -= last->first;
+        ctx_->cache.erase(last);
+      }
+      if (ctx_->used + ctx_->cached + bytes > ctx_->budget)
+        throw Error(BEM_E_NOMEM, "device memory budget exceeded (" + std::to_string(ctx_->used + bytes) + " > " +
+                                     std::to_string(ctx_->budget) + " bytes)");
+    }
     ctx_->used += bytes;
   }
-  void* p = nullptr;
-  hipError_t e = hipMalloc(&p, bytes);
-  if (e != hipSuccess) {
-    std::lock_guard<std::mutex> g(ctx_->mu);
-    ctx_->used -= bytes;
-    (void)hipGetLastError();
-    throw Error(BEM_E_NOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+  for (void* q : evict) (void)hipFree(q);
+  if (!p) {
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      // the device may hold idle blocks of other contexts' sizes: drop ours and retry once
+      std::vector<void*> all;
+      {
+        std::lock_guard<std::mutex> g(ctx_->mu);
+        for (auto& kv : ctx_->cache) all.push_back(kv.second);
+        ctx_->cache.clear();
+        ctx_->cached = 0;
+      }
+      for (void* q : all) (void)hipFree(q);
+      e = hipMalloc(&p, bytes);
+      if (e != hipSuccess) {
+        std::lock_guard<std::mutex> g(ctx_->mu);
+        ctx_->used -= bytes;
+        (void)hipGetLastError();
+        throw Error(BEM_E_NOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+      }
+    }
   }
   blocks_.push_back({p, bytes});
   total_ += bytes;
@@ -137,9 +180,11 @@ void* DevArena::raw(size_t bytes) {
 void DevArena::release(void* p) {
   for (size_t i = 0; i < blocks_.size(); ++i) {
     if (blocks_[i].first == p) {
-      (void)hipFree(p);
+      if (stream_) (void)hipStreamSynchronize(stream_);  // the block is idle before it is reused
       std::lock_guard<std::mutex> g(ctx_->mu);
       ctx_->used -= blocks_[i].second;
+      ctx_->cached += blocks_[i].second;
+      ctx_->cache.emplace(blocks_[i].second, p);
       total_ -= blocks_[i].second;
       blocks_.erase(blocks_.begin() + long(i));
       return;
@@ -148,10 +193,13 @@ void DevArena::release(void* p) {
 }
 
 DevArena::~DevArena() {
+  if (blocks_.empty()) return;
+  if (stream_) (void)hipStreamSynchronize(stream_);
+  std::lock_guard<std::mutex> g(ctx_->mu);
   for (auto& b : blocks_) {
-    (void)hipFree(b.first);
-    std::lock_guard<std::mutex> g(ctx_->mu);
     ctx_->used -= b.second;
+    ctx_->cached += b.second;
+    ctx_->cache.emplace(b.second, b.first);
   }
 }
 
