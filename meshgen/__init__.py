@@ -158,6 +158,13 @@ def merge(meshes: list[tuple[np.ndarray, np.ndarray]]) -> tuple[np.ndarray, np.n
     return np.concatenate(xyzs), np.concatenate(tris).astype(np.int32), np.concatenate(objs)
 
 
+def sphere_row(level: int, count: int, gap: float, radius: float = 1.0):
+    """`count` icospheres of one radius along x with `gap` between neighbouring surfaces;
+    returns xyz, tri, per-triangle object id."""
+    x, t = icosphere(level, radius)
+    return merge([(x + np.array([i * (2 * radius + gap), 0.0, 0.0]), t) for i in range(count)])
+
+
 def jitter(xyz: np.ndarray, tri: np.ndarray, frac: float, seed: int) -> np.ndarray:
     """Move every vertex by an isotropic uniform offset in [-frac, frac] * mean edge length."""
     e = np.concatenate([tri[:, [0, 1]], tri[:, [1, 2]], tri[:, [2, 0]]])

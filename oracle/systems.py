@@ -24,6 +24,14 @@ unknowns [a; e; -q]:
 Readings: the middle block is -K (eliminating row (I) with x3 = -q gives -K;
 the printed +K does not follow from eq. AEFIEintdis), and C1 uses L^phi_m as in
 eq. AEFIEextdis (the printed L^phi_l differs from it by eps_l).
+
+eAEFIE counterpart (Sec. II-F): the same matrix with C1 and C2 replaced by the external
+double-layer operator of the background medium over every object pair, K~_m, and zero:
+  C1 = I_x/2 - K~_m,  C2 = 0   (same unknowns [a; e; -q], no equivalent problem)
+Reading: the comparison prints C1 = K~_m - I_x/2.  For one object on a homogeneous background
+the exact Y of eq. Yeqdef gives the proposed C1 = I_x - K_l = I_x/2 - K~_l and C2 = 0 in the
+sign convention of the unknowns above, i.e. the two formulations coincide; the printed sign
+belongs to the opposite sign of the E column that also prints +K in the middle block.
 """
 from __future__ import annotations
 
@@ -63,6 +71,7 @@ class Operators:
     LA_bg: np.ndarray       # full, background wavenumber
     Lphi_bg: np.ndarray
     K_bg: np.ndarray        # block-diagonal, background wavenumber
+    K_m: np.ndarray         # full (every object pair), background wavenumber
     k0: float
     k_int: list
     k_bg: complex
@@ -110,7 +119,7 @@ def assemble(xyz, tri, obj, prob: Problem) -> Operators:
         LA_bg, Lphi_bg = O.fill_L(topo, k_bg, near)
         Kb = O.fill_K(topo, bary, k_bg, near, bcdata)
     K_bg = np.where(same_e, Kb, 0.0)
-    return Operators(topo, bary, D, B, F, Ix, LA_int, Lphi_int, K_int, LA_bg, Lphi_bg, K_bg,
+    return Operators(topo, bary, D, B, F, Ix, LA_int, Lphi_int, K_int, LA_bg, Lphi_bg, K_bg, Kb,
                      k0, k_int, k_bg, epsc, list(prob.mu_r), complex(prob.eps_bg), float(prob.mu_bg))
 
 
@@ -252,6 +261,35 @@ def solve_final(ops: Operators, b, Y=None):
     x = sla.lu_solve(sla.lu_factor(A), rhs_full)
     a, e, x3 = x[:ne], x[ne:2 * ne], x[2 * ne:]
     return Solution(a, e, -x3, Y11 @ e, Y21 @ e)
+
+
+def final_matrix_eaefie(ops: Operators):
+    """The eAEFIE counterpart of eq. finalsystem (Sec. II-F; reading in the module docstring):
+    C1 = I_x/2 - K~_m with K~_m over every object pair at the background wavenumber, C2 = 0."""
+    D, B, F = ops.D, ops.B, ops.F
+    nq = B.shape[1]
+    ne = len(ops.topo.edges)
+    LAm = ops.mu_bg * ops.LA_bg
+    Lpm = (1 / ops.eps_bg) * ops.Lphi_bg
+    mu_e = _per_edge(ops, ops.mu_r)[:, None]
+    inv_eps_e = (1.0 / _per_edge(ops, ops.epsc))[:, None]
+    Kfull = ops.K_int + 0.5 * ops.Ix
+    return np.block([
+        [LAm, 0.5 * ops.Ix - ops.K_m, D.T @ Lpm @ B],
+        [mu_e * ops.LA_int, -Kfull, inv_eps_e * (D.T @ ops.Lphi_int @ B)],
+        [F @ D, np.zeros((nq, ne)), ops.k0 ** 2 * np.eye(nq)],
+    ])
+
+
+def solve_final_eaefie(ops: Operators, b):
+    """Solve the eAEFIE system by LU; returns (a, e, q) of the physical unknowns."""
+    ne = len(ops.topo.edges)
+    A = final_matrix_eaefie(ops)
+    b = np.asarray(b)
+    r = np.zeros((A.shape[0],) + b.shape[1:], complex)
+    r[:ne] = b
+    x = sla.lu_solve(sla.lu_factor(A), r)
+    return x[:ne], x[ne:2 * ne], -x[2 * ne:]
 
 
 def solve_reduced_single(ops: Operators, b):
