@@ -41,7 +41,7 @@ def log(*a):
 def workload(name: str):
     import meshgen
     return {"c1": meshgen.config_c1, "c2": meshgen.config_c2, "c2x256": meshgen.config_c2_multi,
-            "c3": meshgen.config_c3}[name]()
+            "c3": meshgen.config_c3, "spharr": meshgen.config_sphere_array}[name]()
 
 
 def cpu_baseline(w, n_sample: int = 12) -> dict:
@@ -189,6 +189,9 @@ def main() -> int:
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--inner", default="auto", choices=["auto", "gmres", "direct", "schur"])
+    ap.add_argument("--formulation", default="sldm", choices=["sldm", "eaefie"],
+                    help="sldm: the single-layer dual-mesh final system; eaefie: its comparison "
+                         "formulation with the external double-layer operator")
     ap.add_argument("--exc", type=int, default=0, help="use only the first N excitations of the workload")
     ap.add_argument("--maxit", type=int, default=3000)
     ap.add_argument("--no-precond", action="store_true")
@@ -221,6 +224,7 @@ def main() -> int:
     inner = {"auto": B.BEM_INNER_AUTO, "gmres": B.BEM_INNER_GMRES, "direct": B.BEM_INNER_DIRECT,
              "schur": B.BEM_INNER_SCHUR}[args.inner]
     precond = 0 if args.no_precond else 1
+    form = B.BEM_FORM_EAEFIE if args.formulation == "eaefie" else B.BEM_FORM_SLDM
     ctx = B.bem_create(0)
     khat, pol = (w.khat[:args.exc], w.pol[:args.exc]) if args.exc > 0 else (w.khat, w.pol)
     exc = B.plane_waves(khat, pol)
@@ -236,8 +240,9 @@ def main() -> int:
         mesh = B.bem_mesh_load(ctx, w.xyz, w.tri, w.obj)
         info = B.bem_mesh_info(ctx, mesh)
         t1 = time.perf_counter()
-        op = B.bem_assemble(ctx, mesh, B.make_problem(w.freq_hz, w.eps_r, w.mu_r, w.sigma, precision=prec,
-                                                      inner_mode=inner, precond=precond))
+        op = B.bem_assemble(ctx, mesh, B.make_problem(w.freq_hz, w.eps_r, w.mu_r, w.sigma, eps_bg=w.eps_bg,
+                                                      mu_bg=w.mu_bg, precision=prec, inner_mode=inner,
+                                                      precond=precond, formulation=form))
         t2 = time.perf_counter()
         rc, H, E, rho, si = B.bem_solve(ctx, op, exc, opts, info["n_edge"], info["n_tri"])
         t3 = time.perf_counter()
@@ -317,7 +322,7 @@ def main() -> int:
         "vs_baseline": None, "dtype": "f32+f64" if prec == B.BEM_MIXED else "f64", "data": "synthetic",
         "config": {"workload": w.name, "n_tri": info["n_tri"], "n_unknowns": info["n_unknowns"],
                    "excitations": n_exc, "tol": args.tol, "restart": args.restart, "precision": args.precision,
-                   "inner": args.inner, "precond": bool(precond)},
+                   "inner": args.inner, "precond": bool(precond), "formulation": args.formulation},
         "p50_s": p50, "p99_s": p99,
         "fill_GBps": st["fill_bytes"] / st["fill_seconds"] / 1e9,
         "fill_ms": st["fill_seconds"] * 1e3,

@@ -67,8 +67,9 @@ enum {
   BEM_BLOCK_K_BG = 6,     /* K~ at k_l, NE x NE, block-diagonal */
   BEM_BLOCK_IX = 7,       /* Gram matrix I_x (BC tested with n x RWG), NE x NE, sparse */
   BEM_BLOCK_MEQ = 8,      /* equivalent-configuration matrix of eq. AEFIEeqvdis, (NE+NQ)^2 */
-  BEM_BLOCK_MEQ_INV = 9   /* its device inverse (direct nested solve only), (NE+NQ)^2,
+  BEM_BLOCK_MEQ_INV = 9,  /* its device inverse (direct nested solve only), (NE+NQ)^2,
                              block-diagonal; ordering [edges; kept charges] per object */
+  BEM_BLOCK_K_M = 10      /* K~ at k_l over every object pair, NE x NE (eAEFIE formulation only) */
 };
 
 /* Context.  device >= 0 selects a HIP device; device = -1 gives a host-only
@@ -118,6 +119,16 @@ typedef struct { bem_c64 eps_r; double mu_r, sigma; } bem_material;
  * NE_o <= 32768, else DIRECT while NE_o + NQ_o <= 16384, else GMRES. */
 enum { BEM_INNER_AUTO = 0, BEM_INNER_GMRES = 1, BEM_INNER_DIRECT = 2, BEM_INNER_SCHUR = 3 };
 
+/* Formulation of the final system.  SLDM: eq. finalsystem, the external problem uses only
+ * single-layer operators and C1, C2 come from the equivalent configuration (eqs. C1, C2).
+ * EAEFIE: the comparison formulation of Sec. II-F on the same homogeneous background, with C1
+ * and C2 replaced by the external double-layer operator K~_m over every object pair and zero;
+ * in the sign convention of the unknowns [jk0 H; E / eta0; -c0 rho] used here C1 = I_x/2 - K~_m
+ * (the printed K~_m - I_x/2 goes with the printed sign of the middle block), so for a single
+ * object both give the same matrix.  No equivalent-configuration solve is made (inner_mode is
+ * ignored); K~_m (NE x NE) replaces the per-object K~_l blocks and nested-solve inverses. */
+enum { BEM_FORM_SLDM = 0, BEM_FORM_EAEFIE = 1 };
+
 typedef struct {
   double freq_hz;
   bem_c64 eps_bg;               /* background (homogeneous layer l) relative permittivity */
@@ -130,6 +141,7 @@ typedef struct {
   int precond;                  /* 1: block preconditioner of eq. pcext for the final system
                                    (and its equivalent-configuration counterpart for the nested
                                    GMRES), built at assembly; 0: none */
+  int formulation;              /* BEM_FORM_* (0: eq. finalsystem) */
 } bem_problem;
 
 /* Fill every dense block on the device: L^A, L^phi and K~ at the object

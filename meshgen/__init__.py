@@ -17,6 +17,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 C0 = 299_792_458.0  # speed of light in vacuum, m/s (exact by SI definition)
+EPS0 = 8.8541878128e-12  # vacuum permittivity, F/m (CODATA 2018)
 
 
 # ---------------------------------------------------------------- primitives
@@ -255,6 +256,22 @@ def config_c3(n: int = 32, n_exc: int = 256) -> Workload:
     return Workload(f"ellipsoid{len(tri)}_k0a8_eps6_x{n_exc}", xyz, tri,
                     np.zeros(len(tri), np.int32), freq_from_k0(8.0), [6.0], [1.0], [0.0],
                     khat=khat, pol=pol.astype(np.complex128))
+
+
+def config_sphere_array(n: int = 4, level: int = 2, pitch: float = 0.375) -> Workload:
+    """n x n array of dielectric spheres (eps_r = 12, diameter 250 mm, icosphere of 20 4^level
+    triangles each) at `pitch` in the x-y plane, centred on the origin, at 200 MHz in a
+    homogeneous background with the ground layer's eps_r = 3.47 and sigma = 1.725 mS/m (the
+    buried-array study of Sec. IV-B without its layer interfaces), lit by a plane wave along -z
+    (standing in for the dipole above the array)."""
+    f = 200e6
+    x, t = icosphere(level, 0.125)
+    meshes = [(x + np.array([(i - (n - 1) / 2) * pitch, (j - (n - 1) / 2) * pitch, 0.0]), t)
+              for i in range(n) for j in range(n)]
+    xyz, tri, obj = merge(meshes)
+    eps_bg = 3.47 - 1j * 1.725e-3 / (2 * math.pi * f * EPS0)
+    return Workload(f"spharr{n}x{n}_ico{len(t)}_eps12_200MHz", xyz, tri, obj, f, [12.0] * n * n, [1.0] * n * n,
+                    [0.0] * n * n, eps_bg=eps_bg)
 
 
 def copper_bars(h_min: float = 0.05e-6, h_max: float = 1.0e-6, pitch: float = 3.0e-6,

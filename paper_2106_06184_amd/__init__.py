@@ -21,7 +21,7 @@ BEM_OK, BEM_PENDING = 0, 1
 BEM_E_INVALID, BEM_E_MESH, BEM_E_NOMEM, BEM_E_NOT_CONVERGED, BEM_E_DEVICE, BEM_E_NUMERIC = -1, -2, -3, -4, -5, -6
 BEM_FP64, BEM_MIXED = 0, 2
 (BEM_BLOCK_FINAL, BEM_BLOCK_LA_INT, BEM_BLOCK_LPHI_INT, BEM_BLOCK_K_INT, BEM_BLOCK_LA_BG,
- BEM_BLOCK_LPHI_BG, BEM_BLOCK_K_BG, BEM_BLOCK_IX, BEM_BLOCK_MEQ, BEM_BLOCK_MEQ_INV) = range(10)
+ BEM_BLOCK_LPHI_BG, BEM_BLOCK_K_BG, BEM_BLOCK_IX, BEM_BLOCK_MEQ, BEM_BLOCK_MEQ_INV, BEM_BLOCK_K_M) = range(11)
 BEM_EXC_PLANE_WAVE, BEM_EXC_DELTA_GAP = 0, 1
 
 SYMBOLS = ["bem_create", "bem_destroy", "bem_last_error", "bem_mesh_load", "bem_mesh_info", "bem_edge_table",
@@ -48,12 +48,13 @@ class bem_material(C.Structure):
 
 
 BEM_INNER_AUTO, BEM_INNER_GMRES, BEM_INNER_DIRECT, BEM_INNER_SCHUR = 0, 1, 2, 3
+BEM_FORM_SLDM, BEM_FORM_EAEFIE = 0, 1
 
 
 class bem_problem(C.Structure):
     _fields_ = [("freq_hz", C.c_double), ("eps_bg", c64), ("mu_bg", C.c_double),
                 ("obj", C.POINTER(bem_material)), ("n_obj", C.c_int64), ("precision", C.c_int),
-                ("inner_mode", C.c_int), ("precond", C.c_int)]
+                ("inner_mode", C.c_int), ("precond", C.c_int), ("formulation", C.c_int)]
 
 
 class bem_excitation(C.Structure):
@@ -194,12 +195,13 @@ def bem_near_pairs(ctx, mesh: int):
 
 
 def make_problem(freq_hz, eps_r, mu_r, sigma, eps_bg=1.0, mu_bg=1.0, precision=BEM_FP64,
-                 inner_mode=BEM_INNER_AUTO, precond=1):
+                 inner_mode=BEM_INNER_AUTO, precond=1, formulation=BEM_FORM_SLDM):
     mats = (bem_material * len(eps_r))()
     for i, (e, m, s) in enumerate(zip(eps_r, mu_r, sigma)):
         mats[i] = bem_material(c64(complex(e).real, complex(e).imag), float(m), float(s))
     p = bem_problem(float(freq_hz), c64(complex(eps_bg).real, complex(eps_bg).imag), float(mu_bg),
-                    C.cast(mats, C.POINTER(bem_material)), len(eps_r), int(precision), int(inner_mode), int(precond))
+                    C.cast(mats, C.POINTER(bem_material)), len(eps_r), int(precision), int(inner_mode), int(precond),
+                    int(formulation))
     p._keep = mats
     return p
 

@@ -183,6 +183,7 @@ int bem_apply(bem_ctx* c, bem_op_h h, int block, const void* x, void* y, int64_t
       case BEM_BLOCK_K_INT:
       case BEM_BLOCK_LA_BG:
       case BEM_BLOCK_K_BG:
+      case BEM_BLOCK_K_M:
       case BEM_BLOCK_IX: rows = cols = op.ne; break;
       default: return fail(BEM_E_INVALID, "unknown block");
     }

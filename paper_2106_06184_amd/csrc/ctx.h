@@ -17,6 +17,7 @@ class Server;
 // convergence scalars; the rest stages the per-column Krylov scalars and index lists.
 constexpr size_t kPinnedBytes = 64 * 1024;
 constexpr size_t kPinnedScalars = 64;
+constexpr int kInnerNone = -1;  // operator without an equivalent-configuration solve
 
 struct Ctx {
   int device = -1;
@@ -124,8 +125,10 @@ struct OpObj {
   // dense blocks
   std::vector<Dense> LA_int, Lphi_int, K_int, K_bg;  // per object (block-diagonal operators)
   Dense LA_bg, Lphi_bg;                              // all pairs (background coupling)
+  int formulation = BEM_FORM_SLDM;
+  Dense Km;  // eAEFIE: K~ at k_l over all pairs (K_bg[o] are then views of its diagonal blocks)
   // nested solve and preconditioners
-  int inner_mode = BEM_INNER_GMRES;
+  int inner_mode = BEM_INNER_GMRES;  // kInnerNone for the eAEFIE (no equivalent configuration)
   bool precond = false;
   std::vector<Dense> Minv;           // per object: inverse of M_eq (direct inner solve)
   std::vector<Dense> SigP, SigEq;    // per object: inverses of the charge Schur complements
@@ -186,7 +189,8 @@ void apply_meq(OpObj& op, const double2* x, double2* y, bool fp32, hipStream_t s
 void apply_final(OpObj& op, const double2* x, double2* y, bool fp32, double inner_tol, hipStream_t st);
 void export_block(OpObj& op, int block, bem_c64* host);
 // Upper bound of the device bytes of one request (assembly peak or solve peak), for admission.
-size_t estimate_request_bytes(int64_t nt, int64_t nobj, int precision, int restart, int64_t nexc);
+size_t estimate_request_bytes(int64_t nt, int64_t nobj, int precision, int restart, int64_t nexc,
+                              int formulation = BEM_FORM_SLDM);
 int solve_op(OpObj& op, const bem_excitation* exc, int64_t nexc, const bem_solve_opts& opts, bem_c64* H, bem_c64* E,
              bem_c64* rho, bem_solve_info* info, hipStream_t st);
 

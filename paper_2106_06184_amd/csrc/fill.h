@@ -80,7 +80,9 @@ void launch_gather_LA(const double2* H, int64_t ldH, const int32_t* hp, const in
                       double2* out, int64_t ldo, hipStream_t st);
 void launch_fill_K(const FillKArgs& a, const int32_t* near_t, const int32_t* near_c, int64_t npairs,
                    const int64_t* near_ptr, const int32_t* near_idx, int maxv, hipStream_t st);
-void launch_gather_K(const double2* Kc, int64_t ldK, const int32_t* hp, const int32_t* hm, const int32_t* cS,
-                     const int32_t* cT, int64_t off, int64_t ne, double2* out, int64_t ldo, hipStream_t st);
+// Rows: the nrow test edges of hp/hm (half-rows 3 T + i - off of Kc); columns: the ncol source
+// edges whose BC functions sit in the cell-expanded columns cS/cT of Kc.
+void launch_gather_K(const double2* Kc, int64_t ldK, const int32_t* hp, const int32_t* hm, int64_t off, int64_t nrow,
+                     const int32_t* cS, const int32_t* cT, int64_t ncol, double2* out, int64_t ldo, hipStream_t st);
 
 }  // namespace bem

@@ -174,12 +174,13 @@ __global__ void __launch_bounds__(256) k_gather_LA(const double2* __restrict__ H
 // out[m][n] = sum_{a in {+,-}} s_a (Kc[row_a(m)][colS(n)] + Kc[row_a(m)][colT(n)])
 __global__ void __launch_bounds__(256) k_gather_K(const double2* __restrict__ Kc, int64_t ldK,
                                                   const int32_t* __restrict__ hp, const int32_t* __restrict__ hm,
-                                                  const int32_t* __restrict__ cS, const int32_t* __restrict__ cT,
-                                                  int64_t off, int64_t ne, double2* __restrict__ out, int64_t ldo) {
+                                                  int64_t off, int64_t nrow, const int32_t* __restrict__ cS,
+                                                  const int32_t* __restrict__ cT, int64_t ncol,
+                                                  double2* __restrict__ out, int64_t ldo) {
   const int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (n >= ne) return;
+  if (n >= ncol) return;
   const int32_t s = cS[n], u = cT[n];
-  for (int64_t m = blockIdx.y; m < ne; m += gridDim.y) {
+  for (int64_t m = blockIdx.y; m < nrow; m += gridDim.y) {
     const double2* rp = Kc + (int64_t(hp[m]) - off) * ldK;
     const double2* rm = Kc + (int64_t(hm[m]) - off) * ldK;
     double2 a = rp[s], b = rp[u], c = rm[s], d = rm[u];
@@ -538,12 +539,12 @@ void launch_fill_K(const FillKArgs& a, const int32_t* near_t, const int32_t* nea
 #undef BEM_KLAUNCH
 }
 
-void launch_gather_K(const double2* Kc, int64_t ldK, const int32_t* hp, const int32_t* hm, const int32_t* cS,
-                     const int32_t* cT, int64_t off, int64_t ne, double2* out, int64_t ldo, hipStream_t st) {
-  if (ne <= 0) return;
-  dim3 grid(unsigned((ne + 255) / 256), unsigned(std::min<int64_t>(ne, 32768)));
-  ProfScope ps(st, KC_GATHER, double(ne) * ne * 5 * 16, double(ne) * ne);
-  hipLaunchKernelGGL(dev::k_gather_K, grid, dim3(256), 0, st, Kc, ldK, hp, hm, cS, cT, off, ne, out, ldo);
+void launch_gather_K(const double2* Kc, int64_t ldK, const int32_t* hp, const int32_t* hm, int64_t off, int64_t nrow,
+                     const int32_t* cS, const int32_t* cT, int64_t ncol, double2* out, int64_t ldo, hipStream_t st) {
+  if (nrow <= 0 || ncol <= 0) return;
+  dim3 grid(unsigned((ncol + 255) / 256), unsigned(std::min<int64_t>(nrow, 32768)));
+  ProfScope ps(st, KC_GATHER, double(nrow) * ncol * 5 * 16, double(nrow) * ncol);
+  hipLaunchKernelGGL(dev::k_gather_K, grid, dim3(256), 0, st, Kc, ldK, hp, hm, off, nrow, cS, cT, ncol, out, ldo);
   BEM_HIP(hipGetLastError());
 }
 

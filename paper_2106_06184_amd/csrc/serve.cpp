@@ -137,7 +137,7 @@ bem_ticket Server::submit(const bem_request& r) {
   const int64_t ne = 3 * r.nt / 2;
   (void)ne;
   q->bytes = estimate_request_bytes(r.nt, r.prob.n_obj, r.prob.precision, r.opts.restart > 0 ? r.opts.restart : 50,
-                                    r.nexc);
+                                    r.nexc, r.prob.formulation);
   if (q->bytes > ctx_->budget) throw Error(BEM_E_NOMEM, "request can never fit the device budget");
   q->t_submit = std::chrono::steady_clock::now();
   std::lock_guard<std::mutex> g(mu_);

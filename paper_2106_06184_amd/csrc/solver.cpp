@@ -247,6 +247,10 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
   op.mu_bg = prob.mu_bg;
   if (std::abs(op.eps_bg) == 0 || !(op.mu_bg > 0)) throw Error(BEM_E_INVALID, "invalid background medium");
   op.kbg = wavenumber(op.eps_bg, op.mu_bg);
+  if (prob.formulation != BEM_FORM_SLDM && prob.formulation != BEM_FORM_EAEFIE)
+    throw Error(BEM_E_INVALID, "unknown formulation");
+  op.formulation = prob.formulation;
+  const bool eaefie = op.formulation == BEM_FORM_EAEFIE;
 
   op.ne = m.ne;
   op.nt = m.nt;
@@ -378,6 +382,14 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
         nc_t[m.obj[t]].push_back(int32_t(t));
         nc_c[m.obj[t]].push_back(nci[p]);
       }
+  // eAEFIE: near (triangle, cell) pairs of every test triangle with the cells of each object
+  std::vector<std::vector<int32_t>> ncm_t(eaefie ? m.nobj : 0), ncm_c(eaefie ? m.nobj : 0);
+  if (eaefie)
+    for (int64_t t = 0; t < nt; ++t)
+      for (int64_t p = ncp[t]; p < ncp[t + 1]; ++p) {
+        ncm_t[vobj[nci[p]]].push_back(int32_t(t));
+        ncm_c[vobj[nci[p]]].push_back(nci[p]);
+      }
 
   // ---- cell tables
   int32_t* d_cells = op.mem.upload(cdat.obj_cells);
@@ -416,16 +428,29 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
     op.LA_int.push_back(alloc_dense(op.mem, neo, neo, f32));
     op.Lphi_int.push_back(alloc_dense(op.mem, nto, nto, f32));
     op.K_int.push_back(alloc_dense(op.mem, neo, neo, f32));
-    op.K_bg.push_back(alloc_dense(op.mem, neo, neo, f32));
+    if (!eaefie) op.K_bg.push_back(alloc_dense(op.mem, neo, neo, f32));
   }
   op.LA_bg = alloc_dense(op.mem, m.ne, m.ne, f32);
   op.Lphi_bg = alloc_dense(op.mem, nt, nt, f32);
+  op.Km = Dense{};
+  if (eaefie) {
+    op.Km = alloc_dense(op.mem, m.ne, m.ne, f32);
+    for (int64_t o = 0; o < m.nobj; ++o) {
+      const int64_t e0 = m.obj_edge[o], neo = m.obj_edge[o + 1] - e0;
+      Dense v;
+      v.d64 = op.Km.d64 + e0 * op.Km.ld + e0;
+      v.d32 = op.Km.d32 ? op.Km.d32 + e0 * op.Km.ld + e0 : nullptr;
+      v.rows = v.cols = neo;
+      v.ld = op.Km.ld;
+      op.K_bg.push_back(v);
+    }
+  }
 
   // scratch for the half-RWG and cell-expanded matrices
   int64_t scratch_elems = 9 * nt * nt;
   for (int64_t o = 0; o < m.nobj; ++o) {
     const int64_t nto = m.obj_tri[o + 1] - m.obj_tri[o];
-    scratch_elems = std::max(scratch_elems, 3 * nto * cdat.obj_ncol[o]);
+    scratch_elems = std::max(scratch_elems, 3 * (eaefie ? nt : nto) * cdat.obj_ncol[o]);
   }
   double2* H = op.mem.alloc<double2>(size_t(scratch_elems));
   // BEM_POISON=1 fills the fill scratch with NaN first, so that a read of an entry the fill
@@ -458,13 +483,30 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
     int32_t* pct = up32(nc_t[o]);
     int32_t* pcc = up32(nc_c[o]);
     for (int which = 0; which < 2; ++which) {
+      // eAEFIE: K~ at k_l is filled below over every test triangle (K_bg[o] are views of it)
+      if (which == 1 && eaefie) break;
       const cd k = which == 0 ? op.kint[o] : op.kbg;
       Dense& dst = which == 0 ? op.K_int[o] : op.K_bg[o];
       FillKArgs ka{op.geo, nt, t0, nto, tchunk, k.real(), k.imag(), d_cells + cdat.obj_cell_ptr[o],
                    cdat.obj_cell_ptr[o + 1] - cdat.obj_cell_ptr[o], cdat.ncell, d_nval, d_vpos, d_col0, d_sub_m, d_sub_c,
                    d_sub_area, d_sub_parent, d_alpha, d_beta, H, cdat.obj_ncol[o]};
       launch_fill_K(ka, pct, pcc, int64_t(nc_t[o].size()), d_near_ptr, d_near_idx, cdat.maxv, st);
-      launch_gather_K(H, cdat.obj_ncol[o], d_hp + e0, d_hm + e0, d_cS + e0, d_cT + e0, 3 * t0, neo, dst.d64, dst.ld,
+      launch_gather_K(H, cdat.obj_ncol[o], d_hp + e0, d_hm + e0, 3 * t0, neo, d_cS + e0, d_cT + e0, neo, dst.d64,
+                      dst.ld, st);
+    }
+  }
+  if (eaefie) {
+    // K~_m (Sec. II-F): every test triangle against the BC cells of object o, at k_l; rows are
+    // all edges, columns the edges of object o
+    for (int64_t o = 0; o < m.nobj; ++o) {
+      const int64_t e0 = m.obj_edge[o], neo = m.obj_edge[o + 1] - e0;
+      int32_t* pct = up32(ncm_t[o]);
+      int32_t* pcc = up32(ncm_c[o]);
+      FillKArgs ka{op.geo, nt, 0, nt, tchunk, op.kbg.real(), op.kbg.imag(), d_cells + cdat.obj_cell_ptr[o],
+                   cdat.obj_cell_ptr[o + 1] - cdat.obj_cell_ptr[o], cdat.ncell, d_nval, d_vpos, d_col0, d_sub_m, d_sub_c,
+                   d_sub_area, d_sub_parent, d_alpha, d_beta, H, cdat.obj_ncol[o]};
+      launch_fill_K(ka, pct, pcc, int64_t(ncm_t[o].size()), d_near_ptr, d_near_idx, cdat.maxv, st);
+      launch_gather_K(H, cdat.obj_ncol[o], d_hp, d_hm, 0, m.ne, d_cS + e0, d_cT + e0, neo, op.Km.d64 + e0, op.Km.ld,
                       st);
     }
   }
@@ -481,8 +523,9 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
       to_f32(op.LA_int[o], st);
       to_f32(op.Lphi_int[o], st);
       to_f32(op.K_int[o], st);
-      to_f32(op.K_bg[o], st);
+      if (!eaefie) to_f32(op.K_bg[o], st);
     }
+    if (eaefie) to_f32(op.Km, st);
     to_f32(op.LA_bg, st);
     to_f32(op.Lphi_bg, st);
   }
@@ -495,8 +538,12 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
   op.kernel_evals = 49.0 * double(nt) * nt;
   for (int64_t o = 0; o < m.nobj; ++o) {
     const double neo = double(m.obj_edge[o + 1] - m.obj_edge[o]), nto = double(m.obj_tri[o + 1] - m.obj_tri[o]);
-    op.fill_bytes += 16.0 * (3 * neo * neo + nto * nto);
-    op.kernel_evals += 49.0 * nto * nto + 2 * 126.0 * nto * nto;
+    op.fill_bytes += 16.0 * ((eaefie ? 2 : 3) * neo * neo + nto * nto);
+    op.kernel_evals += 49.0 * nto * nto + (eaefie ? 1 : 2) * 126.0 * nto * nto;
+  }
+  if (eaefie) {
+    op.fill_bytes += 16.0 * double(m.ne) * m.ne;
+    op.kernel_evals += 126.0 * double(nt) * nt;
   }
   (void)hipEventDestroy(ev0);
   (void)hipEventDestroy(ev1);
@@ -514,7 +561,7 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
   int64_t max_ne = 0;
   for (int64_t o = 0; o < m.nobj; ++o) max_ne = std::max(max_ne, m.obj_edge[o + 1] - m.obj_edge[o]);
   const double hmax = *std::max_element(m.hmax.begin(), m.hmax.end());
-  op.inner_mode = prob.inner_mode;
+  op.inner_mode = eaefie ? kInnerNone : prob.inner_mode;
   if (op.inner_mode == BEM_INNER_AUTO) {
     // charge elimination while the elements are not electrically tiny (its k0^-2 term sets the
     // conditioning), the augmented inverse below that, nested GMRES for very large objects
@@ -523,7 +570,8 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
     else if (max_neq <= 16384) op.inner_mode = BEM_INNER_DIRECT;
     else op.inner_mode = BEM_INNER_GMRES;
   }
-  if (op.inner_mode != BEM_INNER_DIRECT && op.inner_mode != BEM_INNER_GMRES && op.inner_mode != BEM_INNER_SCHUR)
+  if (op.inner_mode != BEM_INNER_DIRECT && op.inner_mode != BEM_INNER_GMRES && op.inner_mode != BEM_INNER_SCHUR &&
+      !(eaefie && op.inner_mode == kInnerNone))
     throw Error(BEM_E_INVALID, "unknown inner_mode");
   op.precond = prob.precond != 0;
   build_inner_and_precond(op, ixdiag, st);
@@ -628,11 +676,15 @@ void build_inner_and_precond(OpObj& op, const std::vector<double>& ixdiag, hipSt
     std::copy(p.begin(), p.end(), dLpint.begin() + m.obj_tri[o]);
   }
   const cd inv_epsl = 1.0 / op.eps_bg;
+  // the (1,2) block: diag I_x (eq. pcext); for the eAEFIE the diagonal of its C1 = I_x/2 - K~_m
+  std::vector<double2> dKm;
+  if (op.formulation == BEM_FORM_EAEFIE) dKm = diag_of(op.Km);
   // per-edge 2x2 diagonal block of P and its inverse
   std::vector<double2> W(4 * m.ne), eqd(m.ne);
   for (int64_t n = 0; n < m.ne; ++n) {
     const int o = m.obj[m.tp[n]];
-    const cd l11 = op.mu_bg * cdv(dLAbg[n]), l12 = ixdiag[n];
+    const cd l11 = op.mu_bg * cdv(dLAbg[n]);
+    const cd l12 = dKm.empty() ? cd(ixdiag[n]) : 0.5 * ixdiag[n] - cdv(dKm[n]);
     const cd l21 = op.mur[o] * cdv(dLAint[n]), l22 = -(cdv(dKint[n]) + 0.5 * ixdiag[n]);
     const cd det = l11 * l22 - l12 * l21;
     W[4 * n] = c2(l22 / det);
@@ -841,6 +893,43 @@ void meq_cols(OpObj& op, const WorkView& wv, const double2* x, int64_t ldx, doub
   launch_FD(u, op.tri_edge, op.tri_sign, op.kept, op.nq, c2(1.0), w, c2(-op.k0 * op.k0), yw, st, R, ldx, ldx, ldy);
 }
 
+// eAEFIE counterpart of the final system (Sec. II-F) on R columns, no equivalent problem:
+//   y1 = L^A_m a + (I_x/2 - K~_m) e + D^T L^phi_m B x3
+//   y2 = mu_r L^A a - (K~ + I_x/2) e + eps_c^-1 D^T L^phi B x3      (as in eq. finalsystem)
+//   y3 = F D a + k0^2 x3
+void eaefie_cols(OpObj& op, const WorkView& wv, const double2* x, int64_t ldx, double2* y, int64_t ldy, bool fp32,
+                 hipStream_t st) {
+  const int R = wv.R;
+  const int64_t ne = op.ne, L = wv.ld;
+  const double2* a = x;
+  const double2* e = x + ne;
+  const double2* x3 = x + 2 * ne;
+  double2* y1 = y;
+  double2* y2 = y + ne;
+  double2* y3 = y + 2 * ne;
+  launch_expand_charge(x3, wv.t1, op.obj_tri_d, op.nobj, c2(1.0), st, R, ldx, L);
+  std::vector<GemvDesc> ds;
+  for (int64_t o = 0; o < op.nobj; ++o) {
+    const int64_t t0 = op.obj_tri[o], nto = op.obj_tri[o + 1] - t0;
+    const int64_t e0 = op.obj_edge[o], neo = op.obj_edge[o + 1] - e0;
+    GemvDesc d2 = desc(op.LA_int[o], fp32, 0, 0, neo, neo, a + e0, y2 + e0, c2(op.mur[o]), 0);
+    add_second(d2, op.K_int[o], fp32, 0, 0, e + e0, c2(-1.0));
+    ds.push_back(with_ld(d2, ldx, ldy, ldx));
+    ds.push_back(with_ld(desc(op.Lphi_int[o], fp32, 0, 0, nto, nto, wv.t1 + t0, wv.z1 + t0, c2(1.0), 0), L, L));
+  }
+  GemvDesc d1 = desc(op.LA_bg, fp32, 0, 0, ne, ne, a, y1, c2(op.mu_bg), 0);
+  add_second(d1, op.Km, fp32, 0, 0, e, c2(-1.0));
+  ds.push_back(with_ld(d1, ldx, ldy, ldx));
+  ds.push_back(with_ld(desc(op.Lphi_bg, fp32, 0, 0, op.nt, op.nt, wv.t1, wv.z2, c2(1.0), 0), L, L));
+  products(op, ds, wv, st);
+  launch_spmv(op.ix_ptr, op.ix_idx, op.ix_val, ne, e, c2(-0.5), y2, 1, st, R, ldx, ldy);
+  launch_DT(wv.z1, op.tp, op.tm, ne, c2(1.0), op.eps_inv_edge, y2, 1, st, R, L, ldy);
+  launch_spmv(op.ix_ptr, op.ix_idx, op.ix_val, ne, e, c2(0.5), y1, 1, st, R, ldx, ldy);
+  launch_DT(wv.z2, op.tp, op.tm, ne, c2(1.0 / op.eps_bg), nullptr, y1, 1, st, R, L, ldy);
+  launch_FD(a, op.tri_edge, op.tri_sign, op.kept, op.nq, c2(1.0), x3, c2(op.k0 * op.k0), y3, st, R, ldx, ldx, ldy);
+  op.last_inner_iters = 0;
+}
+
 // Final system (eq. finalsystem) on R columns; the nested solve [u; w] = M_eq^-1 [r_in; 0]
 // runs for every column (directly, or by nested GMRES column by column).
 void final_cols(OpObj& op, const WorkView& wv, const double2* x, int64_t ldx, double2* y, int64_t ldy, bool fp32,
@@ -853,6 +942,10 @@ void final_cols(OpObj& op, const WorkView& wv, const double2* x, int64_t ldx, do
   double2* y1 = y;
   double2* y2 = y + ne;
   double2* y3 = y + 2 * ne;
+  if (op.formulation == BEM_FORM_EAEFIE) {
+    eaefie_cols(op, wv, x, ldx, y, ldy, fp32, st);
+    return;
+  }
   // B x3 for the interior charge term
   launch_expand_charge(x3, wv.t1, op.obj_tri_d, op.nobj, c2(1.0), st, R, ldx, L);
   std::vector<GemvDesc> ds;
@@ -972,6 +1065,10 @@ void apply_block(OpObj& op, int block, const double2* x, double2* y, int64_t nrh
     case BEM_BLOCK_LPHI_BG:
       ds.push_back(with_ld(desc(op.Lphi_bg, false, 0, 0, op.nt, op.nt, x, y, c2(1.0), 0), op.nt, op.nt));
       break;
+    case BEM_BLOCK_K_M:
+      if (!op.Km.d64) throw Error(BEM_E_INVALID, "K~_m is formed only by the eAEFIE formulation");
+      ds.push_back(with_ld(desc(op.Km, false, 0, 0, op.ne, op.ne, x, y, c2(1.0), 0), op.ne, op.ne));
+      break;
     case BEM_BLOCK_IX:
       launch_spmv(op.ix_ptr, op.ix_idx, op.ix_val, op.ne, x, c2(1.0), y, 0, st, R, op.ne, op.ne);
       break;
@@ -1015,6 +1112,10 @@ void export_block(OpObj& op, int block, bem_c64* host) {
       return;
     case BEM_BLOCK_LPHI_BG:
       copy_dense(op.Lphi_bg, 0, 0, op.nt);
+      return;
+    case BEM_BLOCK_K_M:
+      if (!op.Km.d64) throw Error(BEM_E_INVALID, "K~_m is formed only by the eAEFIE formulation");
+      copy_dense(op.Km, 0, 0, op.ne);
       return;
     case BEM_BLOCK_MEQ_INV: {
       if (op.inner_mode != BEM_INNER_DIRECT) throw Error(BEM_E_INVALID, "M_eq^-1 is formed only by the augmented direct nested solve");
@@ -1496,13 +1597,17 @@ constexpr int kMaxBatch = 256;
 
 }  // namespace
 
-size_t estimate_request_bytes(int64_t nt, int64_t nobj, int precision, int restart, int64_t nexc) {
+size_t estimate_request_bytes(int64_t nt, int64_t nobj, int precision, int restart, int64_t nexc, int formulation) {
   const double ne = 1.5 * double(nt), no = double(std::max<int64_t>(nobj, 1));
   const double nq = double(nt) - no, N = 2 * ne + nq, neq = ne + nq;
   const double per = precision == BEM_MIXED ? 24.0 : 16.0;  // float64 + float32 copy
-  const double dense = per * ((3 * ne * ne + double(nt) * nt) / no + ne * ne + double(nt) * nt);
+  const bool eaefie = formulation == BEM_FORM_EAEFIE;
+  // per object L^A, K~ (and K~_l), L^phi; all pairs L^A_l, L^phi_l (and K~_m)
+  const double dense = per * (((eaefie ? 2 : 3) * ne * ne + double(nt) * nt) / no + (eaefie ? 2 : 1) * ne * ne +
+                               double(nt) * nt);
   const double fill_scratch = 16.0 * 9.0 * double(nt) * nt;
-  const double inner = per * (neq * neq) / no + per * (nq * nq) / no;  // augmented inverse + Sigma_P^-1
+  // augmented inverse (not for the eAEFIE) + Sigma_P^-1
+  const double inner = (eaefie ? 0.0 : per * (neq * neq) / no) + per * (nq * nq) / no;
   const double R = double(std::min<int64_t>(std::max<int64_t>(nexc, 1), kMaxBatch));
   const double ldN = double(pad64(int64_t(N)));
   const double solve = 16.0 * R * (ldN * (restart + 1 + 3 + 4) + double(kWorkFields) * pad64(int64_t(neq))) +
