@@ -105,6 +105,12 @@ int bem_edge_table(bem_ctx* ctx, bem_mesh_h mesh, int32_t* va, int32_t* vb, int3
  * closer than (2 - 2e-9) * max(longest edge of T, of T').  ptr: NT+1 int64, idx:
  * ptr[NT] int32 (call once with idx = NULL to size it).  Host buffers. */
 int bem_near_pairs(bem_ctx* ctx, bem_mesh_h mesh, int64_t* ptr, int32_t* idx);
+/* Repeated objects (Sec. II-F): proto[o] (host, n_obj int32) = the first object of which
+ * object o is a translated copy (its triangles, in order, are that object's moved by one
+ * translation, to 1e-12 of the coordinates, with a one-to-one vertex correspondence, and its
+ * edge table has the same local T+, T- and free vertices), or o itself.  Assembly shares the
+ * object-local blocks of such copies unless bem_problem.no_reuse is set. */
+int bem_mesh_copies(bem_ctx* ctx, bem_mesh_h mesh, int32_t* proto);
 
 typedef struct { bem_c64 eps_r; double mu_r, sigma; } bem_material;
 
@@ -142,6 +148,14 @@ typedef struct {
                                    (and its equivalent-configuration counterpart for the nested
                                    GMRES), built at assembly; 0: none */
   int formulation;              /* BEM_FORM_* (0: eq. finalsystem) */
+  int no_reuse;                 /* 0: an object that is a translated copy of an earlier one
+                                   (same triangles in the same order moved by one translation,
+                                   same edge table) shares that object's object-local blocks
+                                   and their inverses (Sec. II-F, repeated objects): K~_l and
+                                   the equivalent-configuration inverse for any material, and
+                                   L^A, L^phi, K~ and the preconditioner's charge Schur inverse
+                                   when the materials are equal too; 1: every object is filled
+                                   and inverted separately */
 } bem_problem;
 
 /* Fill every dense block on the device: L^A, L^phi and K~ at the object
@@ -232,12 +246,15 @@ int bem_serve_stats(bem_ctx* ctx, int64_t* combined_launches, int64_t* combined_
 
 /* Statistics of an assembled operator: device time of the whole fill (all wavenumbers, near
  * corrections and gathers), bytes of the float64 dense blocks written, Green's-function and
- * gradient evaluations of the quadrature, and device bytes held by the operator. */
+ * gradient evaluations of the quadrature, device bytes held by the operator, and the number of
+ * objects whose interior blocks (L^A, L^phi, K~ at the object wavenumber) were filled (the
+ * others share a translated copy's, see bem_problem.no_reuse). */
 typedef struct {
   double fill_seconds;
   double fill_bytes;
   double kernel_evals;
   double device_bytes;
+  double interiors_filled;
 } bem_op_stats;
 int bem_op_stats_get(bem_ctx* ctx, bem_op_h op, bem_op_stats* out);
 

@@ -25,7 +25,7 @@ BEM_FP64, BEM_MIXED = 0, 2
 BEM_EXC_PLANE_WAVE, BEM_EXC_DELTA_GAP = 0, 1
 
 SYMBOLS = ["bem_create", "bem_destroy", "bem_last_error", "bem_mesh_load", "bem_mesh_info", "bem_edge_table",
-           "bem_near_pairs", "bem_assemble", "bem_apply", "bem_block_export", "bem_set_inner_tol", "bem_solve",
+           "bem_near_pairs", "bem_mesh_copies", "bem_assemble", "bem_apply", "bem_block_export", "bem_set_inner_tol", "bem_solve",
            "bem_submit", "bem_poll", "bem_drain", "bem_release", "bem_memory_in_use", "bem_op_stats_get",
            "bem_profile_enable", "bem_profile_read", "bem_serve_stats"]
 (KC_GEMV_F64, KC_GEMV_F32, KC_FILL_L, KC_FILL_K, KC_FILL_NEAR, KC_GATHER, KC_GEMM_F32, KC_DENSE_INV,
@@ -36,7 +36,7 @@ KC_NAMES = ["gemv_f64", "gemv_f32", "fill_L", "fill_K", "fill_near", "gather", "
 
 class bem_op_stats(C.Structure):
     _fields_ = [("fill_seconds", C.c_double), ("fill_bytes", C.c_double), ("kernel_evals", C.c_double),
-                ("device_bytes", C.c_double)]
+                ("device_bytes", C.c_double), ("interiors_filled", C.c_double)]
 
 
 class c64(C.Structure):
@@ -54,7 +54,8 @@ BEM_FORM_SLDM, BEM_FORM_EAEFIE = 0, 1
 class bem_problem(C.Structure):
     _fields_ = [("freq_hz", C.c_double), ("eps_bg", c64), ("mu_bg", C.c_double),
                 ("obj", C.POINTER(bem_material)), ("n_obj", C.c_int64), ("precision", C.c_int),
-                ("inner_mode", C.c_int), ("precond", C.c_int), ("formulation", C.c_int)]
+                ("inner_mode", C.c_int), ("precond", C.c_int), ("formulation", C.c_int),
+                ("no_reuse", C.c_int)]
 
 
 class bem_excitation(C.Structure):
@@ -98,6 +99,7 @@ def lib() -> C.CDLL:
             "bem_mesh_info": (C.c_int, [P, C.c_uint64, C.POINTER(I64), C.POINTER(I64), C.POINTER(I64), C.POINTER(I64)]),
             "bem_edge_table": (C.c_int, [P, C.c_uint64, C.POINTER(I32), C.POINTER(I32), C.POINTER(I32), C.POINTER(I32)]),
             "bem_near_pairs": (C.c_int, [P, C.c_uint64, C.POINTER(I64), C.POINTER(I32)]),
+            "bem_mesh_copies": (C.c_int, [P, C.c_uint64, C.POINTER(I32)]),
             "bem_assemble": (C.c_int, [P, C.c_uint64, C.POINTER(bem_problem), C.POINTER(C.c_uint64)]),
             "bem_apply": (C.c_int, [P, C.c_uint64, C.c_int, P, P, I64, P]),
             "bem_block_export": (C.c_int, [P, C.c_uint64, C.c_int, C.POINTER(c64)]),
@@ -185,6 +187,13 @@ def bem_edge_table(ctx, mesh: int):
     return out  # va, vb, tplus, tminus
 
 
+def bem_mesh_copies(ctx, mesh: int) -> np.ndarray:
+    """proto[o]: the first object of which object o is a translated copy, or o."""
+    out = np.zeros(bem_mesh_info(ctx, mesh)["n_obj"], np.int32)
+    _check(ctx, lib().bem_mesh_copies(ctx, mesh, _iptr(out)))
+    return out
+
+
 def bem_near_pairs(ctx, mesh: int):
     nt = bem_mesh_info(ctx, mesh)["n_tri"]
     ptr = np.zeros(nt + 1, np.int64)
@@ -195,13 +204,13 @@ def bem_near_pairs(ctx, mesh: int):
 
 
 def make_problem(freq_hz, eps_r, mu_r, sigma, eps_bg=1.0, mu_bg=1.0, precision=BEM_FP64,
-                 inner_mode=BEM_INNER_AUTO, precond=1, formulation=BEM_FORM_SLDM):
+                 inner_mode=BEM_INNER_AUTO, precond=1, formulation=BEM_FORM_SLDM, reuse=True):
     mats = (bem_material * len(eps_r))()
     for i, (e, m, s) in enumerate(zip(eps_r, mu_r, sigma)):
         mats[i] = bem_material(c64(complex(e).real, complex(e).imag), float(m), float(s))
     p = bem_problem(float(freq_hz), c64(complex(eps_bg).real, complex(eps_bg).imag), float(mu_bg),
                     C.cast(mats, C.POINTER(bem_material)), len(eps_r), int(precision), int(inner_mode), int(precond),
-                    int(formulation))
+                    int(formulation), 0 if reuse else 1)
     p._keep = mats
     return p
 

@@ -151,6 +151,15 @@ int bem_near_pairs(bem_ctx* c, bem_mesh_h h, int64_t* ptr, int32_t* idx) {
   });
 }
 
+int bem_mesh_copies(bem_ctx* c, bem_mesh_h h, int32_t* proto) {
+  return guarded([&]() -> int {
+    const bem::Mesh& m = *mesh_of(C(c), h).mesh;
+    if (!proto) return fail(BEM_E_INVALID, "null proto");
+    std::memcpy(proto, m.geo_proto.data(), sizeof(int32_t) * m.geo_proto.size());
+    return BEM_OK;
+  });
+}
+
 int bem_assemble(bem_ctx* c, bem_mesh_h h, const bem_problem* prob, bem_op_h* out) {
   return guarded([&]() -> int {
     bem::Ctx* ctx = C(c);
@@ -263,6 +272,9 @@ int bem_op_stats_get(bem_ctx* c, bem_op_h h, bem_op_stats* out) {
     out->fill_bytes = op.fill_bytes;
     out->kernel_evals = op.kernel_evals;
     out->device_bytes = double(op.mem.bytes());
+    int64_t filled = 0;
+    for (int64_t o = 0; o < op.nobj; ++o) filled += op.mat_rep[o] == o ? 1 : 0;
+    out->interiors_filled = double(filled);
     return BEM_OK;
   });
 }

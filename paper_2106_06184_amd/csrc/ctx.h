@@ -126,6 +126,10 @@ struct OpObj {
   std::vector<Dense> LA_int, Lphi_int, K_int, K_bg;  // per object (block-diagonal operators)
   Dense LA_bg, Lphi_bg;                              // all pairs (background coupling)
   int formulation = BEM_FORM_SLDM;
+  // repeated objects: geo_rep[o] = the object whose background-wavenumber blocks o shares
+  // (a translated copy), mat_rep[o] = the object whose interior blocks it shares (a translated
+  // copy with the same material); o itself when it owns them
+  std::vector<int64_t> geo_rep, mat_rep;
   Dense Km;  // eAEFIE: K~ at k_l over all pairs (K_bg[o] are then views of its diagonal blocks)
   // nested solve and preconditioners
   int inner_mode = BEM_INNER_GMRES;  // kInnerNone for the eAEFIE (no equivalent configuration)

@@ -63,6 +63,8 @@ struct Mesh {
   // near pairs (CSR over test triangles, sorted source lists)
   std::vector<int64_t> near_ptr;
   std::vector<int32_t> near_idx;
+  // per object: the first object of which it is a translated copy (itself if none)
+  std::vector<int32_t> geo_proto;
 };
 
 // Validates and builds the topology; throws Error(BEM_E_MESH, ...) on invalid input.

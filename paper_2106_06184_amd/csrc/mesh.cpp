@@ -26,6 +26,52 @@ void fail(const std::string& m) { throw Error(BEM_E_MESH, m); }
 
 }  // namespace
 
+// Object o repeats an earlier object p when its triangles, in order, are p's triangles moved by
+// one translation with a one-to-one vertex correspondence, and its edges have the same local
+// table (T+, T-, free vertices).  Every object-local operator of o is then p's (Sec. II-F,
+// repeated objects): the integrands depend on differences of positions only.
+static bool translated_copy(const Mesh& m, int64_t p, int64_t o) {
+  const int64_t tp0 = m.obj_tri[p], to0 = m.obj_tri[o], nto = m.obj_tri[o + 1] - to0;
+  const int64_t ep0 = m.obj_edge[p], eo0 = m.obj_edge[o], neo = m.obj_edge[o + 1] - eo0;
+  if (m.obj_tri[p + 1] - tp0 != nto || m.obj_edge[p + 1] - ep0 != neo) return false;
+  for (int64_t k = 0; k < neo; ++k) {
+    if (m.tp[ep0 + k] - tp0 != m.tp[eo0 + k] - to0 || m.tm[ep0 + k] - tp0 != m.tm[eo0 + k] - to0 ||
+        m.ip[ep0 + k] != m.ip[eo0 + k] || m.im[ep0 + k] != m.im[eo0 + k])
+      return false;
+  }
+  const double* x = m.xyz.data();
+  const int32_t a0 = m.tri[3 * tp0], b0 = m.tri[3 * to0];
+  const double tr[3] = {x[3 * b0] - x[3 * a0], x[3 * b0 + 1] - x[3 * a0 + 1], x[3 * b0 + 2] - x[3 * a0 + 2]};
+  double ext = 0;
+  for (int64_t k = 0; k < nto; ++k) ext = std::max(ext, m.hmax[tp0 + k]);
+  const double tol = 1e-12 * (ext * double(nto) + std::fabs(tr[0]) + std::fabs(tr[1]) + std::fabs(tr[2]) +
+                              std::fabs(x[3 * a0]) + std::fabs(x[3 * a0 + 1]) + std::fabs(x[3 * a0 + 2]));
+  std::unordered_map<int32_t, int32_t> fwd, bwd;
+  for (int64_t k = 0; k < 3 * nto; ++k) {
+    const int32_t a = m.tri[3 * tp0 + k], b = m.tri[3 * to0 + k];
+    auto f = fwd.emplace(a, b);
+    auto g = bwd.emplace(b, a);
+    if (f.first->second != b || g.first->second != a) return false;
+    for (int c = 0; c < 3; ++c)
+      if (std::fabs(x[3 * b + c] - x[3 * a + c] - tr[c]) > tol) return false;
+  }
+  return true;
+}
+
+static void find_translated_copies(Mesh& m) {
+  m.geo_proto.assign(m.nobj, 0);
+  std::vector<int64_t> protos;
+  for (int64_t o = 0; o < m.nobj; ++o) {
+    m.geo_proto[o] = int32_t(o);
+    for (int64_t p : protos)
+      if (translated_copy(m, p, o)) {
+        m.geo_proto[o] = int32_t(p);
+        break;
+      }
+    if (m.geo_proto[o] == o) protos.push_back(o);
+  }
+}
+
 std::unique_ptr<Mesh> build_mesh(const double* xyz, int64_t nv, const int32_t* tri, int64_t nt,
                                  const int32_t* obj) {
   if (!xyz || !tri || nv <= 0 || nt <= 0) throw Error(BEM_E_INVALID, "empty mesh");
@@ -132,6 +178,7 @@ std::unique_ptr<Mesh> build_mesh(const double* xyz, int64_t nv, const int32_t* t
   m->obj_edge.assign(m->nobj + 1, 0);
   for (int64_t n = 0; n < m->ne; ++n) m->obj_edge[m->obj[m->tp[n]] + 1]++;
   for (int64_t o = 0; o < m->nobj; ++o) m->obj_edge[o + 1] += m->obj_edge[o];
+  find_translated_copies(*m);
 
   // outward orientation: positive enclosed volume per object
   for (int64_t o = 0; o < m->nobj; ++o) {

@@ -251,6 +251,17 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
     throw Error(BEM_E_INVALID, "unknown formulation");
   op.formulation = prob.formulation;
   const bool eaefie = op.formulation == BEM_FORM_EAEFIE;
+  op.geo_rep.assign(m.nobj, 0);
+  op.mat_rep.assign(m.nobj, 0);
+  for (int64_t o = 0; o < m.nobj; ++o) {
+    op.geo_rep[o] = prob.no_reuse ? o : m.geo_proto[o];
+    op.mat_rep[o] = o;
+    for (int64_t p = op.geo_rep[o]; p < o; ++p)
+      if (op.geo_rep[p] == op.geo_rep[o] && op.mat_rep[p] == p && op.epsc[p] == op.epsc[o] && op.mur[p] == op.mur[o]) {
+        op.mat_rep[o] = p;
+        break;
+      }
+  }
 
   op.ne = m.ne;
   op.nt = m.nt;
@@ -425,10 +436,11 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
   for (int64_t o = 0; o < m.nobj; ++o) {
     const int64_t neo = m.obj_edge[o + 1] - m.obj_edge[o];
     const int64_t nto = m.obj_tri[o + 1] - m.obj_tri[o];
-    op.LA_int.push_back(alloc_dense(op.mem, neo, neo, f32));
-    op.Lphi_int.push_back(alloc_dense(op.mem, nto, nto, f32));
-    op.K_int.push_back(alloc_dense(op.mem, neo, neo, f32));
-    if (!eaefie) op.K_bg.push_back(alloc_dense(op.mem, neo, neo, f32));
+    const int64_t mr = op.mat_rep[o], gr = op.geo_rep[o];
+    op.LA_int.push_back(mr == o ? alloc_dense(op.mem, neo, neo, f32) : op.LA_int[mr]);
+    op.Lphi_int.push_back(mr == o ? alloc_dense(op.mem, nto, nto, f32) : op.Lphi_int[mr]);
+    op.K_int.push_back(mr == o ? alloc_dense(op.mem, neo, neo, f32) : op.K_int[mr]);
+    if (!eaefie) op.K_bg.push_back(gr == o ? alloc_dense(op.mem, neo, neo, f32) : op.K_bg[gr]);
   }
   op.LA_bg = alloc_dense(op.mem, m.ne, m.ne, f32);
   op.Lphi_bg = alloc_dense(op.mem, nt, nt, f32);
@@ -472,19 +484,24 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
   for (int64_t o = 0; o < m.nobj; ++o) {
     const int64_t t0 = m.obj_tri[o], nto = m.obj_tri[o + 1] - t0;
     const int64_t e0 = m.obj_edge[o], neo = m.obj_edge[o + 1] - e0;
-    int32_t* pt = up32(no_t[o]);
-    int32_t* ps = up32(no_s[o]);
+    const bool own_int = op.mat_rep[o] == o, own_bg = op.geo_rep[o] == o && !eaefie;
+    if (!own_int && !own_bg) continue;  // a translated copy: every object-local block is shared
     // interior L^A, L^phi at k_int
-    FillLArgs la{op.geo, nt, t0, nto, t0, nto, tchunk, op.kint[o].real(), op.kint[o].imag(), H, 3 * nto,
-                 op.Lphi_int[o].d64, op.Lphi_int[o].ld};
-    launch_fill_L(la, pt, ps, int64_t(no_t[o].size()), st);
-    launch_gather_LA(H, 3 * nto, d_hp + e0, d_hm + e0, 3 * t0, neo, op.LA_int[o].d64, op.LA_int[o].ld, st);
+    if (own_int) {
+      int32_t* pt = up32(no_t[o]);
+      int32_t* ps = up32(no_s[o]);
+      FillLArgs la{op.geo, nt, t0, nto, t0, nto, tchunk, op.kint[o].real(), op.kint[o].imag(), H, 3 * nto,
+                   op.Lphi_int[o].d64, op.Lphi_int[o].ld};
+      launch_fill_L(la, pt, ps, int64_t(no_t[o].size()), st);
+      launch_gather_LA(H, 3 * nto, d_hp + e0, d_hm + e0, 3 * t0, neo, op.LA_int[o].d64, op.LA_int[o].ld, st);
+    }
     // K~ at k_int and at k_bg (object-local blocks)
     int32_t* pct = up32(nc_t[o]);
     int32_t* pcc = up32(nc_c[o]);
     for (int which = 0; which < 2; ++which) {
+      if (which == 0 && !own_int) continue;
       // eAEFIE: K~ at k_l is filled below over every test triangle (K_bg[o] are views of it)
-      if (which == 1 && eaefie) break;
+      if (which == 1 && !own_bg) break;
       const cd k = which == 0 ? op.kint[o] : op.kbg;
       Dense& dst = which == 0 ? op.K_int[o] : op.K_bg[o];
       FillKArgs ka{op.geo, nt, t0, nto, tchunk, k.real(), k.imag(), d_cells + cdat.obj_cell_ptr[o],
@@ -520,10 +537,12 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
   }
   if (f32) {
     for (int64_t o = 0; o < m.nobj; ++o) {
-      to_f32(op.LA_int[o], st);
-      to_f32(op.Lphi_int[o], st);
-      to_f32(op.K_int[o], st);
-      if (!eaefie) to_f32(op.K_bg[o], st);
+      if (op.mat_rep[o] == o) {
+        to_f32(op.LA_int[o], st);
+        to_f32(op.Lphi_int[o], st);
+        to_f32(op.K_int[o], st);
+      }
+      if (!eaefie && op.geo_rep[o] == o) to_f32(op.K_bg[o], st);
     }
     if (eaefie) to_f32(op.Km, st);
     to_f32(op.LA_bg, st);
@@ -538,8 +557,9 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
   op.kernel_evals = 49.0 * double(nt) * nt;
   for (int64_t o = 0; o < m.nobj; ++o) {
     const double neo = double(m.obj_edge[o + 1] - m.obj_edge[o]), nto = double(m.obj_tri[o + 1] - m.obj_tri[o]);
-    op.fill_bytes += 16.0 * ((eaefie ? 2 : 3) * neo * neo + nto * nto);
-    op.kernel_evals += 49.0 * nto * nto + (eaefie ? 1 : 2) * 126.0 * nto * nto;
+    const double n_int = op.mat_rep[o] == o ? 1 : 0, n_bg = (op.geo_rep[o] == o && !eaefie) ? 1 : 0;
+    op.fill_bytes += 16.0 * (n_int * (2 * neo * neo + nto * nto) + n_bg * neo * neo);
+    op.kernel_evals += n_int * (49.0 + 126.0) * nto * nto + n_bg * 126.0 * nto * nto;
   }
   if (eaefie) {
     op.fill_bytes += 16.0 * double(m.ne) * m.ne;
@@ -617,6 +637,11 @@ void build_inner_and_precond(OpObj& op, const std::vector<double>& ixdiag, hipSt
   op.Minv.clear();
   if (op.inner_mode == BEM_INNER_DIRECT) {
     for (int64_t o = 0; o < m.nobj; ++o) {
+      if (op.geo_rep[o] != o) {  // a translated copy shares the inverse
+        const Dense shared = op.Minv[op.geo_rep[o]];
+        op.Minv.push_back(shared);
+        continue;
+      }
       const int64_t t0 = m.obj_tri[o], nto = m.obj_tri[o + 1] - t0;
       const int64_t e0 = m.obj_edge[o], neo = m.obj_edge[o + 1] - e0;
       const int64_t n = neo + nto - 1;
@@ -640,6 +665,11 @@ void build_inner_and_precond(OpObj& op, const std::vector<double>& ixdiag, hipSt
   }
   if (op.inner_mode == BEM_INNER_SCHUR) {
     for (int64_t o = 0; o < m.nobj; ++o) {
+      if (op.geo_rep[o] != o) {
+        const Dense shared = op.Minv[op.geo_rep[o]];
+        op.Minv.push_back(shared);
+        continue;
+      }
       const int64_t t0 = m.obj_tri[o];
       const int64_t e0 = m.obj_edge[o], neo = m.obj_edge[o + 1] - e0;
       std::vector<int32_t> tpl(neo), tml(neo);
@@ -670,6 +700,14 @@ void build_inner_and_precond(OpObj& op, const std::vector<double>& ixdiag, hipSt
   std::vector<double2> dLAbg = diag_of(op.LA_bg), dLpbg = diag_of(op.Lphi_bg);
   std::vector<double2> dLAint(m.ne), dKint(m.ne), dLpint(m.nt);
   for (int64_t o = 0; o < m.nobj; ++o) {
+    const int64_t r = op.mat_rep[o];
+    if (r != o) {  // shared interior blocks: the same diagonals
+      const int64_t neo = m.obj_edge[o + 1] - m.obj_edge[o], nto = m.obj_tri[o + 1] - m.obj_tri[o];
+      std::copy_n(dLAint.begin() + m.obj_edge[r], neo, dLAint.begin() + m.obj_edge[o]);
+      std::copy_n(dKint.begin() + m.obj_edge[r], neo, dKint.begin() + m.obj_edge[o]);
+      std::copy_n(dLpint.begin() + m.obj_tri[r], nto, dLpint.begin() + m.obj_tri[o]);
+      continue;
+    }
     auto a = diag_of(op.LA_int[o]), k = diag_of(op.K_int[o]), p = diag_of(op.Lphi_int[o]);
     std::copy(a.begin(), a.end(), dLAint.begin() + m.obj_edge[o]);
     std::copy(k.begin(), k.end(), dKint.begin() + m.obj_edge[o]);
@@ -703,6 +741,14 @@ void build_inner_and_precond(OpObj& op, const std::vector<double>& ixdiag, hipSt
     const cd inv_epsc = 1.0 / op.epsc[o];
     for (int which = 0; which < 2; ++which) {
       if (which == 1 && op.inner_mode != BEM_INNER_GMRES) break;
+      // Sigma_P depends on the interior blocks, Sigma_eq on the background ones only
+      std::vector<Dense>& dst = which == 0 ? op.SigP : op.SigEq;
+      const int64_t rep = which == 0 ? op.mat_rep[o] : op.geo_rep[o];
+      if (rep != o) {
+        const Dense shared = dst[rep];
+        dst.push_back(shared);
+        continue;
+      }
       // G[q][t] = sum over the edges n of triangle q: D[q][n] D[t][n] c_n(t), t in {T+(n), T-(n)}
       std::vector<int64_t> ptr(nq + 1, 0);
       std::vector<int32_t> idx;

@@ -110,3 +110,26 @@ def test_last_error_is_per_call(host_ctx):
     assert "open" in B.bem_last_error(host_ctx) or "edge" in B.bem_last_error(host_ctx)
     B.bem_mesh_load(host_ctx, x, t)
     assert B.bem_last_error(host_ctx) == ""
+
+
+def test_translated_copies_detected(host_ctx):
+    """bem_mesh_copies: translated copies of an earlier object map to it; a jittered, rotated,
+    scaled or re-ordered copy, or a different shape, does not."""
+    sx, st = meshgen.icosphere(1)
+    cx, ct = meshgen.cube(2)
+    rot = np.array([[0.0, -1.0, 0.0], [1.0, 0.0, 0.0], [0.0, 0.0, 1.0]])
+    shift = np.array([3.0, 0.0, 0.0])
+    cases = {
+        "row": (meshgen.sphere_row(1, 3, 0.5), [0, 0, 0]),
+        "mixed": (meshgen.merge([(sx, st), (cx + shift, ct), (sx + 2 * shift, st), (cx - shift, ct)]), [0, 1, 0, 1]),
+        "jitter": (meshgen.merge([(sx, st), (meshgen.jitter(sx, st, 1e-3, 1) + shift, st)]), [0, 1]),
+        "rotated": (meshgen.merge([(sx + [0.3, 0.1, 0.0], st), (sx @ rot.T + shift, st)]), [0, 1]),
+        "scaled": (meshgen.merge([(sx, st), (1.01 * sx + shift, st)]), [0, 1]),
+        "reordered": (meshgen.merge([(sx, st), (sx + shift, np.roll(st, 1, axis=0))]), [0, 1]),
+        "bars": (meshgen.copper_bars(h_min=0.5e-6, h_max=2e-6, grid=2), [0, 0, 0, 0]),
+    }
+    for name, ((xyz, tri, obj), want) in cases.items():
+        h = B.bem_mesh_load(host_ctx, xyz, tri, obj)
+        got = B.bem_mesh_copies(host_ctx, h)
+        assert got.tolist() == want, (name, got)
+        B.bem_release(host_ctx, h)
