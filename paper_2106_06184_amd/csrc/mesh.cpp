@@ -392,15 +392,22 @@ CellData build_cells(const Mesh& m) {
 void near_cells(const Mesh& m, std::vector<int64_t>& ptr, std::vector<int32_t>& idx) {
   ptr.assign(m.nt + 1, 0);
   idx.clear();
+  idx.reserve(size_t(m.near_idx.size()));
   std::vector<int32_t> c;
+  std::vector<int64_t> stamp(m.nv, -1);  // last triangle that listed the vertex
   for (int64_t t = 0; t < m.nt; ++t) {
     c.clear();
     for (int64_t p = m.near_ptr[t]; p < m.near_ptr[t + 1]; ++p) {
       int32_t s = m.near_idx[p];
-      for (int i = 0; i < 3; ++i) c.push_back(m.tri[3 * s + i]);
+      for (int i = 0; i < 3; ++i) {
+        const int32_t v = m.tri[3 * s + i];
+        if (stamp[v] != t) {
+          stamp[v] = t;
+          c.push_back(v);
+        }
+      }
     }
     std::sort(c.begin(), c.end());
-    c.erase(std::unique(c.begin(), c.end()), c.end());
     idx.insert(idx.end(), c.begin(), c.end());
     ptr[t + 1] = int64_t(idx.size());
   }

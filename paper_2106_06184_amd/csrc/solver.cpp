@@ -111,6 +111,16 @@ static bool verbose() {
   return v;
 }
 
+// BEM_TIMING=1 prints the host wall time of each assembly phase (the stream is synchronised at
+// every mark, so the device work of a phase is inside it).
+static bool timing() {
+  static const bool v = [] {
+    const char* e = std::getenv("BEM_TIMING");
+    return e && *e && *e != '0';
+  }();
+  return v;
+}
+
 // ----------------------------------------------------------------- arena / ctx
 
 namespace {
@@ -208,12 +218,22 @@ OpObj::~OpObj() {}
 // ----------------------------------------------------------------- assembly
 
 void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
+  auto tmark = std::chrono::steady_clock::now();
   const Mesh& m = *mo.mesh;
   if (!mo.cells) mo.cells = std::make_unique<CellData>(build_cells(m));
   const CellData& cdat = *mo.cells;
   op.m = &m;
   op.cells = &cdat;
   hipStream_t st = op.stream;
+  auto mark = [&](const char* what) {
+    if (!timing()) return;
+    BEM_HIP(hipStreamSynchronize(st));
+    const auto now = std::chrono::steady_clock::now();
+    std::fprintf(stderr, "[bem] assemble %-22s %8.2f ms\n", what,
+                 std::chrono::duration<double, std::milli>(now - tmark).count());
+    tmark = now;
+  };
+  mark("cells");
   op.mem.set_stream(st);
   const Rules& R = rules();
   fill_set_rules(R.w7, R.b3, st);
@@ -309,10 +329,28 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
   for (int64_t n = 0; n < m.ne; ++n) einv[n] = c2(1.0 / op.epsc[m.obj[m.tp[n]]]);
   op.eps_inv_edge = op.mem.upload(einv);
 
+  mark("geometry+uploads");
   // ---- Gram matrix I_x: int (n x f_m) . g_n dS, exact with the 3-point rule on every sub-triangle
   std::vector<double> ixdiag(m.ne, 0.0);
   {
-    std::vector<std::map<int32_t, double>> rows(m.ne);
+    // rows collect (column, value) pairs in fixed-capacity slots: the columns of row m are the
+    // BC functions of the dual cells of the (at most four) vertices of T+(m) and T-(m)
+    const int cap = 4 * cdat.maxv + 4;
+    std::vector<int32_t> rcnt(m.ne, 0), rcol(size_t(m.ne) * cap);
+    std::vector<double> rval(size_t(m.ne) * cap);
+    auto add = [&](int32_t row, int32_t col, double v) {
+      int32_t* c = &rcol[size_t(row) * cap];
+      double* x = &rval[size_t(row) * cap];
+      int k = 0;
+      while (k < rcnt[row] && c[k] != col) ++k;
+      if (k == rcnt[row]) {
+        if (k == cap) throw Error(BEM_E_MESH, "I_x row wider than the dual-cell bound");
+        c[k] = col;
+        x[k] = 0.0;
+        ++rcnt[row];
+      }
+      x[k] += v;
+    };
     const int64_t nc = cdat.ncell;
     const int ns = 2 * cdat.maxv;
     for (int64_t v = 0; v < nc; ++v) {
@@ -329,6 +367,7 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
           const double As = cdat.sub_area[so];
           const double* be = &cdat.beta[((size_t(b) * ns + s) * nc + v) * 3];
           const double* nP = &m.normal[3 * P];
+          double acc[3] = {0.0, 0.0, 0.0};
           for (int j = 0; j < 3; ++j) {
             double rl[3], r[3], g[3];
             for (int k = 0; k < 3; ++k) {
@@ -337,7 +376,6 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
               g[k] = (al * rl[k] - be[k]) / (2 * As);
             }
             for (int i = 0; i < 3; ++i) {
-              const int32_t me = m.tri_edge[3 * P + i];
               const double sg = m.tri_sign[3 * P + i];
               const double* pi = &m.xyz[3 * m.tri[3 * P + i]];
               double f[3], nf[3];
@@ -345,17 +383,24 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
               nf[0] = nP[1] * f[2] - nP[2] * f[1];
               nf[1] = nP[2] * f[0] - nP[0] * f[2];
               nf[2] = nP[0] * f[1] - nP[1] * f[0];
-              rows[me][n] += As * (1.0 / 3.0) * (nf[0] * g[0] + nf[1] * g[1] + nf[2] * g[2]);
+              acc[i] += As * (1.0 / 3.0) * (nf[0] * g[0] + nf[1] * g[1] + nf[2] * g[2]);
             }
           }
+          for (int i = 0; i < 3; ++i) add(m.tri_edge[3 * P + i], n, acc[i]);
         }
       }
     }
     std::vector<int64_t> ptr(m.ne + 1, 0);
     std::vector<int32_t> idx;
     std::vector<double> val;
+    idx.reserve(size_t(m.ne) * 24);
+    val.reserve(size_t(m.ne) * 24);
+    std::vector<std::pair<int32_t, double>> row;
     for (int64_t r = 0; r < m.ne; ++r) {
-      for (auto& kv : rows[r]) {
+      row.clear();
+      for (int k = 0; k < rcnt[r]; ++k) row.emplace_back(rcol[size_t(r) * cap + k], rval[size_t(r) * cap + k]);
+      std::sort(row.begin(), row.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
+      for (auto& kv : row) {
         idx.push_back(kv.first);
         val.push_back(kv.second);
         if (kv.first == r) ixdiag[r] = kv.second;
@@ -367,6 +412,7 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
     op.ix_val = op.mem.upload(val);
   }
 
+  mark("I_x");
   // ---- near-pair lists (all pairs, and per object) for L, near cells per object for K~
   std::vector<int32_t> na_t, na_s;
   std::vector<std::vector<int32_t>> no_t(m.nobj), no_s(m.nobj);
@@ -402,6 +448,7 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
         ncm_c[vobj[nci[p]]].push_back(nci[p]);
       }
 
+  mark("near lists");
   // ---- cell tables
   int32_t* d_cells = op.mem.upload(cdat.obj_cells);
   int32_t* d_nval = op.mem.upload(cdat.nval);
@@ -427,6 +474,7 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
   int64_t* d_near_ptr = op.mem.upload(m.near_ptr);
   int32_t* d_near_idx = op.mem.upload(m.near_idx);
 
+  mark("cell tables");
   // ---- dense blocks
   const bool f32 = op.precision == BEM_MIXED;
   op.LA_int.clear();
@@ -574,6 +622,7 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
                   (void*)d_cS, (void*)d_cT, (void*)d_near_ptr, (void*)d_near_idx})
     op.mem.release(p);
 
+  mark("fill");
   // ---- nested-solve mode and block preconditioners
   int64_t max_neq = 0;
   for (int64_t o = 0; o < m.nobj; ++o)
@@ -596,6 +645,7 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
   op.precond = prob.precond != 0;
   build_inner_and_precond(op, ixdiag, st);
 
+  mark("inner+precond");
   // ---- work vectors and Krylov spaces
   op.work_len = int64_t(kWorkFields) * work_ld(op);
   op.work = op.mem.alloc<double2>(size_t(op.work_len));
@@ -603,6 +653,7 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
     op.inner_ws = make_gmres_work(op.mem, op.Neq, op.inner_restart);
     op.inner_ws->tag = nullptr;
   }
+  mark("work");
 }
 
 // Direct inner solve (inverse of M_eq per object) and the block preconditioners: the per-edge
@@ -610,6 +661,14 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
 // equivalent-configuration counterpart, both inverted on the device.
 void build_inner_and_precond(OpObj& op, const std::vector<double>& ixdiag, hipStream_t st) {
   const Mesh& m = *op.m;
+  auto tmark = std::chrono::steady_clock::now();
+  auto mark = [&](const char* what) {
+    if (!timing()) return;
+    BEM_HIP(hipStreamSynchronize(st));
+    const auto now = std::chrono::steady_clock::now();
+    std::fprintf(stderr, "[bem]   %-28s %8.2f ms\n", what, std::chrono::duration<double, std::milli>(now - tmark).count());
+    tmark = now;
+  };
   const bool f32 = op.precision == BEM_MIXED;
   int64_t maxn = 0;
   for (int64_t o = 0; o < m.nobj; ++o)
@@ -690,6 +749,7 @@ void build_inner_and_precond(OpObj& op, const std::vector<double>& ixdiag, hipSt
       op.Minv.push_back(S);
     }
   }
+  mark("nested inverses");
   op.SigP.clear();
   op.SigEq.clear();
   if (!op.precond) {
@@ -735,6 +795,7 @@ void build_inner_and_precond(OpObj& op, const std::vector<double>& ixdiag, hipSt
   op.eq_d = op.mem.upload(eqd);
   op.lam_bg = op.mem.upload(dLpbg);
   op.lam_int = op.mem.upload(dLpint);
+  mark("diagonals and 2x2 blocks");
   // charge Schur complements, per object (local numbering)
   for (int64_t o = 0; o < m.nobj; ++o) {
     const int64_t t0 = m.obj_tri[o], nto = m.obj_tri[o + 1] - t0, nq = nto - 1;
