@@ -225,13 +225,20 @@ __global__ void __launch_bounds__(256, 2) k_gj_update_mfma(double* __restrict__ 
   __shared__ __align__(16) double Bs[KC][128 + 2];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wm = wave >> 1, wn = wave & 1;
-  // XCD-aware order: the 8 XCDs take consecutive blocks round-robin; give each XCD a
-  // contiguous band of row tiles so that it re-reads the same column-panel rows from its L2
-  const unsigned nbx = gridDim.x, nby = gridDim.y, nb = nbx * nby;
-  unsigned lin = blockIdx.y * nbx + blockIdx.x;
-  if (nb % 8 == 0) lin = (lin % 8) * (nb / 8) + lin / 8;
-  const int64_t i0 = int64_t(lin / nbx) * 64;  // complex rows
-  const int64_t j0 = int64_t(lin % nbx) * 64;  // complex columns
+  // XCD-aware order: the 8 XCDs take consecutive blocks round-robin.  Each XCD gets a band of
+  // nby/8 row tiles and walks it column tile by column tile (rows fastest), so the band's
+  // rows of the column panel C and the few R columns in flight stay in its L2 and every panel
+  // entry is fetched from HBM about once per XCD
+  const unsigned nbx = gridDim.x, nby = gridDim.y;
+  const unsigned lin = blockIdx.y * nbx + blockIdx.x;
+  unsigned ti = lin / nbx, tj = lin % nbx;
+  if (nby % 8 == 0) {
+    const unsigned band = nby / 8, l = lin / 8;
+    ti = (lin % 8) * band + l % band;
+    tj = l / band;
+  }
+  const int64_t i0 = int64_t(ti) * 64;  // complex rows
+  const int64_t j0 = int64_t(tj) * 64;  // complex columns
   // the rows and columns of the pivot block are overwritten afterwards, so the whole tile is
   // updated; its old values are fetched first (they stream in while the product is formed)
   double apre[2][4][4];
