@@ -179,6 +179,20 @@ int bem_apply(bem_ctx* ctx, bem_op_h op, int block, const void* x, void* y, int6
 int bem_block_export(bem_ctx* ctx, bem_op_h op, int block, bem_c64* host_dst);
 int bem_set_inner_tol(bem_ctx* ctx, bem_op_h op, double tol);
 
+/* Far field of solutions (Sec. II-C: outside the objects the scattered field is the one the
+ * differential current J_delta = J - J_eq radiates in the background, J_eq being the current
+ * of the equivalent configuration, eq. AEFIEeqvdis, for the same E):
+ *   N(rhat) = int J_delta(r') exp(+j k_l rhat . r') dS'   (7-point rule on every triangle)
+ * for ndir unit directions rhat (host, 3 doubles each) and nexc solutions H, E as bem_solve
+ * returns them (host, column-major NE x nexc).  Outputs (host, either may be NULL): N, 3
+ * complex per (solution, direction), laid out [exc][dir][xyz]; rcs, the bistatic radar
+ * cross-section |k_l eta_l|^2 / (4 pi) |N_perp|^2 in m^2 per unit incident amplitude,
+ * [exc][dir].  The equivalent solve runs in float64 (nested GMRES to the operator's inner
+ * tolerance).  Not concurrently with bem_solve on the same operator.  BEM_E_INVALID for the
+ * eAEFIE formulation (no equivalent configuration) or non-unit directions. */
+int bem_far_field(bem_ctx* ctx, bem_op_h op, const bem_c64* H, const bem_c64* E, int64_t nexc,
+                  const double* rhat, int64_t ndir, bem_c64* N, double* rcs);
+
 enum { BEM_EXC_PLANE_WAVE = 0, BEM_EXC_DELTA_GAP = 1 };
 typedef struct {
   int kind;

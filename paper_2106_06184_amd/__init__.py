@@ -25,7 +25,7 @@ BEM_FP64, BEM_MIXED = 0, 2
 BEM_EXC_PLANE_WAVE, BEM_EXC_DELTA_GAP = 0, 1
 
 SYMBOLS = ["bem_create", "bem_destroy", "bem_last_error", "bem_mesh_load", "bem_mesh_info", "bem_edge_table",
-           "bem_near_pairs", "bem_mesh_copies", "bem_assemble", "bem_apply", "bem_block_export", "bem_set_inner_tol", "bem_solve",
+           "bem_near_pairs", "bem_mesh_copies", "bem_far_field", "bem_assemble", "bem_apply", "bem_block_export", "bem_set_inner_tol", "bem_solve",
            "bem_submit", "bem_poll", "bem_drain", "bem_release", "bem_memory_in_use", "bem_op_stats_get",
            "bem_profile_enable", "bem_profile_read", "bem_serve_stats"]
 (KC_GEMV_F64, KC_GEMV_F32, KC_FILL_L, KC_FILL_K, KC_FILL_NEAR, KC_GATHER, KC_GEMM_F32, KC_DENSE_INV,
@@ -100,6 +100,8 @@ def lib() -> C.CDLL:
             "bem_edge_table": (C.c_int, [P, C.c_uint64, C.POINTER(I32), C.POINTER(I32), C.POINTER(I32), C.POINTER(I32)]),
             "bem_near_pairs": (C.c_int, [P, C.c_uint64, C.POINTER(I64), C.POINTER(I32)]),
             "bem_mesh_copies": (C.c_int, [P, C.c_uint64, C.POINTER(I32)]),
+            "bem_far_field": (C.c_int, [P, C.c_uint64, C.POINTER(c64), C.POINTER(c64), C.c_int64,
+                                        C.POINTER(C.c_double), C.c_int64, C.POINTER(c64), C.POINTER(C.c_double)]),
             "bem_assemble": (C.c_int, [P, C.c_uint64, C.POINTER(bem_problem), C.POINTER(C.c_uint64)]),
             "bem_apply": (C.c_int, [P, C.c_uint64, C.c_int, P, P, I64, P]),
             "bem_block_export": (C.c_int, [P, C.c_uint64, C.c_int, C.POINTER(c64)]),
@@ -185,6 +187,21 @@ def bem_edge_table(ctx, mesh: int):
     out = [np.zeros(ne, np.int32) for _ in range(4)]
     _check(ctx, lib().bem_edge_table(ctx, mesh, *[_iptr(a) for a in out]))
     return out  # va, vb, tplus, tminus
+
+
+def bem_far_field(ctx, op: int, H, E, rhat):
+    """Far-field vector N[exc, dir, xyz] and bistatic RCS[exc, dir] (m^2 per unit amplitude) of
+    solutions H, E (NE x nexc) in the unit directions rhat (ndir x 3)."""
+    H = np.ascontiguousarray(np.asarray(H, np.complex128).reshape(H.shape[0], -1).T)
+    E = np.ascontiguousarray(np.asarray(E, np.complex128).reshape(E.shape[0], -1).T)
+    rhat = np.ascontiguousarray(np.atleast_2d(np.asarray(rhat, np.float64)))
+    nexc, ndir = H.shape[0], rhat.shape[0]
+    N = np.zeros((nexc, ndir, 3), np.complex128)
+    rcs = np.zeros((nexc, ndir), np.float64)
+    cp = lambda a: a.ctypes.data_as(C.POINTER(c64))
+    _check(ctx, lib().bem_far_field(ctx, op, cp(H), cp(E), nexc, rhat.ctypes.data_as(C.POINTER(C.c_double)), ndir,
+                                    cp(N), rcs.ctypes.data_as(C.POINTER(C.c_double))))
+    return N, rcs
 
 
 def bem_mesh_copies(ctx, mesh: int) -> np.ndarray:

@@ -151,6 +151,17 @@ int bem_near_pairs(bem_ctx* c, bem_mesh_h h, int64_t* ptr, int32_t* idx) {
   });
 }
 
+int bem_far_field(bem_ctx* c, bem_op_h h, const bem_c64* H, const bem_c64* E, int64_t nexc, const double* rhat,
+                  int64_t ndir, bem_c64* N, double* rcs) {
+  return guarded([&]() -> int {
+    bem::Ctx* ctx = C(c);
+    bem::OpObj& op = op_of(ctx, h);
+    need_device(c);
+    bem::far_field(op, H, E, nexc, rhat, ndir, N, rcs, op.stream);
+    return BEM_OK;
+  });
+}
+
 int bem_mesh_copies(bem_ctx* c, bem_mesh_h h, int32_t* proto) {
   return guarded([&]() -> int {
     const bem::Mesh& m = *mesh_of(C(c), h).mesh;

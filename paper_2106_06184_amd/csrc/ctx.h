@@ -192,6 +192,9 @@ void apply_block(OpObj& op, int block, const double2* x, double2* y, int64_t nrh
 void apply_meq(OpObj& op, const double2* x, double2* y, bool fp32, hipStream_t st);
 void apply_final(OpObj& op, const double2* x, double2* y, bool fp32, double inner_tol, hipStream_t st);
 void export_block(OpObj& op, int block, bem_c64* host);
+// Far field of nexc solutions (host H, E): N per (solution, direction) and the bistatic RCS.
+void far_field(OpObj& op, const bem_c64* H, const bem_c64* E, int64_t nexc, const double* rhat, int64_t ndir,
+               bem_c64* N, double* rcs, hipStream_t st);
 // Upper bound of the device bytes of one request (assembly peak or solve peak), for admission.
 size_t estimate_request_bytes(int64_t nt, int64_t nobj, int precision, int restart, int64_t nexc,
                               int formulation = BEM_FORM_SLDM);

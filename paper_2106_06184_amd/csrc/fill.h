@@ -71,6 +71,22 @@ struct RhsArgs {
 };
 void launch_rhs_planewave(const RhsArgs& a, int nexc, hipStream_t st);
 
+// N(rhat) = int J(r') exp(+j k rhat . r') dS' of RWG coefficients J (column c at J + c ldj),
+// 7-point rule per triangle; out[(c ndir + d) 3 + i], i = x, y, z.
+struct FarArgs {
+  const double* geo;
+  int64_t nt;
+  const int32_t* tri_edge;  // 3 nt
+  const int8_t* tri_sign;   // 3 nt
+  const double2* J;
+  int64_t ldj;
+  double kr, ki;            // background wavenumber
+  const double* rhat;       // 3 per direction
+  int64_t ndir;
+  double2* out;
+};
+void launch_far_field(const FarArgs& a, int ncol, hipStream_t st);
+
 // Quadrature rules into constant memory (once per device; later calls return at once).
 void fill_set_rules(const double w7[7], const double b3[3][3], hipStream_t st);
 void launch_fill_L(const FillLArgs& a, const int32_t* near_t, const int32_t* near_s, int64_t npairs,

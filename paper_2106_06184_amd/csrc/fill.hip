@@ -454,9 +454,69 @@ __global__ void k_rhs_planewave(RhsArgs a) {
   a.b[e * a.ldb + m] = make_double2(r.re, r.im);
 }
 
+// One block per (direction, column): threads stride over the triangles, then a fixed-order
+// tree reduction in LDS.
+__global__ void __launch_bounds__(256) k_far_field(FarArgs a) {
+  const int64_t d = blockIdx.x;
+  const int c = blockIdx.y;
+  const double* geo = a.geo;
+  const int64_t nt = a.nt;
+  const v3 rh = mk(a.rhat[3 * d], a.rhat[3 * d + 1], a.rhat[3 * d + 2]);
+  const double2* J = a.J + int64_t(c) * a.ldj;
+  cz nx = {0, 0}, ny = {0, 0}, nz = {0, 0};
+  for (int64_t t = threadIdx.x; t < nt; t += blockDim.x) {
+    const v3 ctr = G3(geo, nt, kGeoC, t);
+    cz w[3];
+    v3 p[3];
+    for (int i = 0; i < 3; ++i) {
+      const double2 j = J[a.tri_edge[3 * t + i]];
+      const double s = 0.5 * a.tri_sign[3 * t + i];
+      w[i] = {s * j.x, s * j.y};
+      p[i] = G3(geo, nt, kGeoP + 3 * i, t);
+    }
+    for (int k = 0; k < 7; ++k) {
+      const v3 dk = G3(geo, nt, kGeoQ + 3 * k, t);
+      const double ph = dot(rh, ctr + dk);
+      double sn, co;
+      sincos(a.kr * ph, &sn, &co);
+      const double ea = exp(-a.ki * ph);
+      const cz e = {cW7[k] * ea * co, cW7[k] * ea * sn};
+      for (int i = 0; i < 3; ++i) {
+        const v3 f = dk - p[i];
+        const cz we = cmul(w[i], e);
+        nx = cadd(nx, cscale(f.x, we));
+        ny = cadd(ny, cscale(f.y, we));
+        nz = cadd(nz, cscale(f.z, we));
+      }
+    }
+  }
+  __shared__ double red[6][256];
+  red[0][threadIdx.x] = nx.re; red[1][threadIdx.x] = nx.im;
+  red[2][threadIdx.x] = ny.re; red[3][threadIdx.x] = ny.im;
+  red[4][threadIdx.x] = nz.re; red[5][threadIdx.x] = nz.im;
+  __syncthreads();
+  for (int half = 128; half > 0; half >>= 1) {
+    if (threadIdx.x < half)
+      for (int q = 0; q < 6; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + half];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double2* o = a.out + (int64_t(c) * a.ndir + d) * 3;
+    o[0] = make_double2(red[0][0], red[1][0]);
+    o[1] = make_double2(red[2][0], red[3][0]);
+    o[2] = make_double2(red[4][0], red[5][0]);
+  }
+}
+
 }  // namespace dev
 
 // ------------------------------------------------------------------ launchers
+
+void launch_far_field(const FarArgs& a, int ncol, hipStream_t st) {
+  if (a.ndir <= 0 || ncol <= 0) return;
+  hipLaunchKernelGGL(dev::k_far_field, dim3(unsigned(a.ndir), unsigned(ncol)), dim3(256), 0, st, a);
+  BEM_HIP(hipGetLastError());
+}
 
 void launch_rhs_planewave(const RhsArgs& a, int nexc, hipStream_t st) {
   if (a.ne <= 0 || nexc <= 0) return;

@@ -1000,6 +1000,51 @@ void meq_cols(OpObj& op, const WorkView& wv, const double2* x, int64_t ldx, doub
   launch_FD(u, op.tri_edge, op.tri_sign, op.kept, op.nq, c2(1.0), w, c2(-op.k0 * op.k0), yw, st, R, ldx, ldx, ldy);
 }
 
+// Nested solve (eq. AEFIEeqvdis) of R columns: [u; w] = M_eq^-1 [r_in; 0] from wv.rin into wv.sol,
+// directly (augmented inverse or charge-eliminated S^-1) or by nested GMRES column by column.
+void nested_from_rin(OpObj& op, const WorkView& wv, bool fp32, double inner_tol, hipStream_t st) {
+  const int R = wv.R;
+  const int64_t ne = op.ne, nq = op.nq, L = wv.ld;
+  if (op.inner_mode == BEM_INNER_DIRECT) {
+    // [u_o; w_o] = M_eq,o^-1 [r_in,o; 0]: only the edge columns of the inverse are read
+    std::vector<GemvDesc> di;
+    for (int64_t o = 0; o < op.nobj; ++o) {
+      const int64_t e0 = op.obj_edge[o], neo = op.obj_edge[o + 1] - e0;
+      const int64_t q0 = op.obj_q[o], nqo = op.obj_q[o + 1] - q0;
+      di.push_back(with_ld(desc(op.Minv[o], fp32, 0, 0, neo, neo, wv.rin + e0, wv.sol + e0, c2(1.0), 0), L, L));
+      di.push_back(
+          with_ld(desc(op.Minv[o], fp32, neo, 0, nqo, neo, wv.rin + e0, wv.sol + ne + q0, c2(1.0), 0), L, L));
+    }
+    products(op, di, wv, st);
+    op.last_inner_iters = 0;
+  } else if (op.inner_mode == BEM_INNER_SCHUR) {
+    // u = S^-1 r_in with the charges eliminated, then w = k0^-2 F D u
+    std::vector<GemvDesc> di;
+    for (int64_t o = 0; o < op.nobj; ++o) {
+      const int64_t e0 = op.obj_edge[o], neo = op.obj_edge[o + 1] - e0;
+      di.push_back(with_ld(desc(op.Minv[o], fp32, 0, 0, neo, neo, wv.rin + e0, wv.sol + e0, c2(1.0), 0), L, L));
+    }
+    products(op, di, wv, st);
+    launch_FD(wv.sol, op.tri_edge, op.tri_sign, op.kept, nq, c2(1.0 / (op.k0 * op.k0)), nullptr, c2(0.0),
+              wv.sol + ne, st, R, L, 0, L);
+    op.last_inner_iters = 0;
+  } else {
+    launch_axpby(nq, c2(0.0), nullptr, c2(0.0), nullptr, wv.rin + ne, st, R, 0, 0, L);
+    for (int c = 0; c < R; ++c) {
+      const WorkView cv = column_view(wv, c);
+      ApplyFn meq = [&op, cv, fp32, st](const double2* xi, double2* yi) { meq_cols(op, cv, xi, 0, yi, 0, fp32, st); };
+      ApplyFn peq = [&op, cv, fp32, st](const double2* xi, double2* yi) {
+        precond_eq_cols(op, cv, xi, yi, 0, fp32, st);
+      };
+      GmresResult gr = gmres(*op.inner_ws, op.pinned, meq, cv.rin, cv.sol, true, inner_tol, op.inner_maxit, st,
+                             op.precond ? &peq : nullptr);
+      op.last_inner_iters = gr.iters;
+      op.max_inner_iters = std::max(op.max_inner_iters, gr.iters);
+      if (verbose()) std::fprintf(stderr, "[bem] inner its %d res %.3e\n", gr.iters, gr.relres);
+    }
+  }
+}
+
 // eAEFIE counterpart of the final system (Sec. II-F) on R columns, no equivalent problem:
 //   y1 = L^A_m a + (I_x/2 - K~_m) e + D^T L^phi_m B x3
 //   y2 = mu_r L^A a - (K~ + I_x/2) e + eps_c^-1 D^T L^phi B x3      (as in eq. finalsystem)
@@ -1071,45 +1116,7 @@ void final_cols(OpObj& op, const WorkView& wv, const double2* x, int64_t ldx, do
   launch_spmv(op.ix_ptr, op.ix_idx, op.ix_val, ne, e, c2(0.5), wv.rin, 1, st, R, ldx, L);
   launch_spmv(op.ix_ptr, op.ix_idx, op.ix_val, ne, e, c2(-0.5), y2, 1, st, R, ldx, ldy);
   launch_DT(wv.z1, op.tp, op.tm, ne, c2(1.0), op.eps_inv_edge, y2, 1, st, R, L, ldy);
-  // nested solve M_eq [u; w] = [r_in; 0]
-  if (op.inner_mode == BEM_INNER_DIRECT) {
-    // [u_o; w_o] = M_eq,o^-1 [r_in,o; 0]: only the edge columns of the inverse are read
-    std::vector<GemvDesc> di;
-    for (int64_t o = 0; o < op.nobj; ++o) {
-      const int64_t e0 = op.obj_edge[o], neo = op.obj_edge[o + 1] - e0;
-      const int64_t q0 = op.obj_q[o], nqo = op.obj_q[o + 1] - q0;
-      di.push_back(with_ld(desc(op.Minv[o], fp32, 0, 0, neo, neo, wv.rin + e0, wv.sol + e0, c2(1.0), 0), L, L));
-      di.push_back(
-          with_ld(desc(op.Minv[o], fp32, neo, 0, nqo, neo, wv.rin + e0, wv.sol + ne + q0, c2(1.0), 0), L, L));
-    }
-    products(op, di, wv, st);
-    op.last_inner_iters = 0;
-  } else if (op.inner_mode == BEM_INNER_SCHUR) {
-    // u = S^-1 r_in with the charges eliminated, then w = k0^-2 F D u
-    std::vector<GemvDesc> di;
-    for (int64_t o = 0; o < op.nobj; ++o) {
-      const int64_t e0 = op.obj_edge[o], neo = op.obj_edge[o + 1] - e0;
-      di.push_back(with_ld(desc(op.Minv[o], fp32, 0, 0, neo, neo, wv.rin + e0, wv.sol + e0, c2(1.0), 0), L, L));
-    }
-    products(op, di, wv, st);
-    launch_FD(wv.sol, op.tri_edge, op.tri_sign, op.kept, nq, c2(1.0 / (op.k0 * op.k0)), nullptr, c2(0.0),
-              wv.sol + ne, st, R, L, 0, L);
-    op.last_inner_iters = 0;
-  } else {
-    launch_axpby(nq, c2(0.0), nullptr, c2(0.0), nullptr, wv.rin + ne, st, R, 0, 0, L);
-    for (int c = 0; c < R; ++c) {
-      const WorkView cv = column_view(wv, c);
-      ApplyFn meq = [&op, cv, fp32, st](const double2* xi, double2* yi) { meq_cols(op, cv, xi, 0, yi, 0, fp32, st); };
-      ApplyFn peq = [&op, cv, fp32, st](const double2* xi, double2* yi) {
-        precond_eq_cols(op, cv, xi, yi, 0, fp32, st);
-      };
-      GmresResult gr = gmres(*op.inner_ws, op.pinned, meq, cv.rin, cv.sol, true, inner_tol, op.inner_maxit, st,
-                             op.precond ? &peq : nullptr);
-      op.last_inner_iters = gr.iters;
-      op.max_inner_iters = std::max(op.max_inner_iters, gr.iters);
-      if (verbose()) std::fprintf(stderr, "[bem] inner its %d res %.3e\n", gr.iters, gr.relres);
-    }
-  }
+  nested_from_rin(op, wv, fp32, inner_tol, st);
   const double2* u = wv.sol;
   const double2* w = wv.sol + ne;
   // a - u, x3 + w, B (x3 + w)
@@ -1191,6 +1198,68 @@ void apply_block(OpObj& op, int block, const double2* x, double2* y, int64_t nrh
   products(op, ds, wv, st);
   // the batch work is freed on return: let the launches that read it finish first
   if (R > 1) BEM_HIP(hipStreamSynchronize(st));
+}
+
+void far_field(OpObj& op, const bem_c64* H, const bem_c64* E, int64_t nexc, const double* rhat, int64_t ndir,
+               bem_c64* N, double* rcs, hipStream_t st) {
+  if (op.formulation != BEM_FORM_SLDM)
+    throw Error(BEM_E_INVALID, "the far field is radiated by the differential current of the proposed formulation");
+  if (nexc <= 0 || ndir <= 0 || !H || !E || !rhat) throw Error(BEM_E_INVALID, "invalid far-field arguments");
+  for (int64_t d = 0; d < ndir; ++d) {
+    const double n2 = rhat[3 * d] * rhat[3 * d] + rhat[3 * d + 1] * rhat[3 * d + 1] + rhat[3 * d + 2] * rhat[3 * d + 2];
+    if (!(std::fabs(n2 - 1.0) < 1e-9)) throw Error(BEM_E_INVALID, "directions must be unit vectors");
+  }
+  const int64_t ne = op.ne;
+  const cd eta_l = kEta0 * std::sqrt(op.mu_bg / op.eps_bg);
+  const double pref = std::norm(op.kbg * eta_l) / (4.0 * M_PI);
+  DevArena tmp(op.ctx);
+  tmp.set_stream(st);
+  double* d_rhat = tmp.alloc<double>(size_t(3 * ndir));
+  BEM_HIP(hipMemcpyAsync(d_rhat, rhat, sizeof(double) * 3 * ndir, hipMemcpyHostToDevice, st));
+  std::vector<double2> hN;
+  for (int64_t c0 = 0; c0 < nexc; c0 += 256) {
+    const int R = int(std::min<int64_t>(256, nexc - c0));
+    const WorkView wv = R == 1 ? views(op) : batch_views(op, tmp, R);
+    const int64_t L = wv.ld;
+    double2* e = tmp.alloc<double2>(size_t(L) * R);
+    double2* h = tmp.alloc<double2>(size_t(L) * R);
+    double2* out = tmp.alloc<double2>(size_t(3 * ndir) * R);
+    for (int c = 0; c < R; ++c) {
+      BEM_HIP(hipMemcpyAsync(e + c * L, E + (c0 + c) * ne, sizeof(double2) * ne, hipMemcpyHostToDevice, st));
+      BEM_HIP(hipMemcpyAsync(h + c * L, H + (c0 + c) * ne, sizeof(double2) * ne, hipMemcpyHostToDevice, st));
+    }
+    // e = E / eta0; r_in = (K~_l + I_x/2) e; [u; w] = M_eq^-1 [r_in; 0] (float64)
+    launch_axpby(ne, c2(1.0 / kEta0), e, c2(0.0), nullptr, e, st, R, L, 0, L);
+    std::vector<GemvDesc> ds;
+    for (int64_t o = 0; o < op.nobj; ++o) {
+      const int64_t e0 = op.obj_edge[o], neo = op.obj_edge[o + 1] - e0;
+      ds.push_back(with_ld(desc(op.K_bg[o], false, 0, 0, neo, neo, e + e0, wv.rin + e0, c2(1.0), 0), L, L));
+    }
+    products(op, ds, wv, st);
+    launch_spmv(op.ix_ptr, op.ix_idx, op.ix_val, ne, e, c2(0.5), wv.rin, 1, st, R, L, L);
+    nested_from_rin(op, wv, false, op.inner_tol, st);
+    // J_delta = H - H_eq = H - u / (j k0)
+    launch_axpby(ne, c2(1.0), h, c2(-cd(1.0) / cd(0.0, op.k0)), wv.sol, h, st, R, L, L, L);
+    FarArgs fa{op.geo, op.nt, op.tri_edge, op.tri_sign, h, L, op.kbg.real(), op.kbg.imag(), d_rhat, ndir, out};
+    launch_far_field(fa, R, st);
+    hN.resize(size_t(3 * ndir) * R);
+    BEM_HIP(hipMemcpyAsync(hN.data(), out, sizeof(double2) * hN.size(), hipMemcpyDeviceToHost, st));
+    BEM_HIP(hipStreamSynchronize(st));
+    for (int c = 0; c < R; ++c)
+      for (int64_t d = 0; d < ndir; ++d) {
+        const double2* v = &hN[(size_t(c) * ndir + d) * 3];
+        const cd n[3] = {cd(v[0].x, v[0].y), cd(v[1].x, v[1].y), cd(v[2].x, v[2].y)};
+        const double* r = rhat + 3 * d;
+        const cd nr = n[0] * r[0] + n[1] * r[1] + n[2] * r[2];
+        double s = 0;
+        for (int i = 0; i < 3; ++i) {
+          const cd perp = n[i] - nr * r[i];
+          s += std::norm(perp);
+          if (N) N[((c0 + c) * ndir + d) * 3 + i] = {n[i].real(), n[i].imag()};
+        }
+        if (rcs) rcs[(c0 + c) * ndir + d] = pref * s;
+      }
+  }
 }
 
 void export_block(OpObj& op, int block, bem_c64* host) {
