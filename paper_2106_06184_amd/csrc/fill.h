@@ -29,6 +29,7 @@ struct FillLArgs {
   int64_t ldH;
   double2* Lphi;        // rows T-t0, cols T'-s0
   int64_t ldP;
+  int sub;              // 1: some source triangle needs its rule subdivided (|Re k| h > 2)
 };
 
 struct FillKArgs {
@@ -51,7 +52,19 @@ struct FillKArgs {
   const double* beta;
   double2* Kc;            // rows 3*(T-t0)+i, cols = object-local (cell, BC) columns
   int64_t ldK;
+  int sub;                // 1: some source sub-triangle needs its rule subdivided
 };
+
+// Source-rule subdivision for highly conductive objects: a source piece of longest edge h is
+// split 4-to-1 L times, the least L with |Re k| h / 2^L <= kSubdivKh, at most kSubdivMax.
+constexpr double kSubdivKh = 2.0;
+constexpr int kSubdivMax = 4;
+inline int subdiv_level_host(double kr, double h) {
+  const double x = (kr < 0 ? -kr : kr) * h;
+  int L = 0;
+  while (L < kSubdivMax && x / double(1 << L) > kSubdivKh) ++L;
+  return L;
+}
 
 struct RhsArgs {
   const double* geo;
@@ -88,7 +101,7 @@ struct FarArgs {
 void launch_far_field(const FarArgs& a, int ncol, hipStream_t st);
 
 // Quadrature rules into constant memory (once per device; later calls return at once).
-void fill_set_rules(const double w7[7], const double b3[3][3], hipStream_t st);
+void fill_set_rules(const double w7[7], const double b7[7][3], const double b3[3][3], hipStream_t st);
 void launch_fill_L(const FillLArgs& a, const int32_t* near_t, const int32_t* near_s, int64_t npairs,
                    hipStream_t st);
 // Half-row indices hp/hm are global (3 T + i); `off` = 3 * first triangle of the block.

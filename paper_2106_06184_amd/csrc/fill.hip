@@ -30,7 +30,47 @@ namespace dev {
 
 // Q7 (Radon, degree 5) and Q3 (degree 2) weights; the points live in the geometry tables.
 __constant__ double cW7[7];
+__constant__ double cB7[7][3];
 __constant__ double cB3[3][3];
+
+// Level of the source-rule subdivision (same test as the host's subdiv_level_host).
+__device__ __forceinline__ int subdiv_level(double kr, double h) {
+  const double x = fabs(kr) * h;
+  int L = 0;
+  while (L < kSubdivMax && x / double(1 << L) > kSubdivKh) ++L;
+  return L;
+}
+
+// Barycentric corners of piece j of the level-L 4-to-1 split of a triangle (base-4 digits of
+// j from the first split on; children: (c0, m01, m20), (m01, c1, m12), (m20, m12, c2),
+// (m01, m12, m20)).  Row i = corner i.
+__device__ __forceinline__ void subdiv_corners(int L, int j, double c[3][3]) {
+  for (int i = 0; i < 3; ++i)
+    for (int m = 0; m < 3; ++m) c[i][m] = i == m ? 1.0 : 0.0;
+  for (int lev = L - 1; lev >= 0; --lev) {
+    const int d = (j >> (2 * lev)) & 3;
+    double m01[3], m12[3], m20[3];
+    for (int m = 0; m < 3; ++m) {
+      m01[m] = 0.5 * (c[0][m] + c[1][m]);
+      m12[m] = 0.5 * (c[1][m] + c[2][m]);
+      m20[m] = 0.5 * (c[2][m] + c[0][m]);
+    }
+    for (int m = 0; m < 3; ++m) {
+      const double a0 = c[0][m], a1 = c[1][m], a2 = c[2][m];
+      if (d == 0) { c[0][m] = a0;      c[1][m] = m01[m]; c[2][m] = m20[m]; }
+      else if (d == 1) { c[0][m] = m01[m]; c[1][m] = a1;      c[2][m] = m12[m]; }
+      else if (d == 2) { c[0][m] = m20[m]; c[1][m] = m12[m]; c[2][m] = a2; }
+      else { c[0][m] = m01[m]; c[1][m] = m12[m]; c[2][m] = m20[m]; }
+    }
+  }
+}
+
+// Point of barycentric coordinates (b . corners) on a triangle with vertex offsets P[3].
+__device__ __forceinline__ v3 subdiv_point(const double c[3][3], const double b[3], const v3 P[3]) {
+  double w[3];
+  for (int m = 0; m < 3; ++m) w[m] = b[0] * c[0][m] + b[1] * c[1][m] + b[2] * c[2][m];
+  return w[0] * P[0] + w[1] * P[1] + w[2] * P[2];
+}
 
 __device__ __forceinline__ double G(const double* geo, int64_t nt, int f, int64_t t) { return geo[f * nt + t]; }
 __device__ __forceinline__ v3 G3(const double* geo, int64_t nt, int f, int64_t t) {
@@ -38,7 +78,9 @@ __device__ __forceinline__ v3 G3(const double* geo, int64_t nt, int f, int64_t t
 }
 
 // ------------------------------------------------------------------ L far
-template <bool LOSSY>
+// SUB: the source rule is Q7 on each of the 4^L pieces of the source triangle's level-L split
+// (weights 1/4^L), L from |Re k| and the source's longest edge; otherwise plain Q7.
+template <bool LOSSY, bool SUB>
 __global__ void __launch_bounds__(256) k_fill_L_far(FillLArgs a) {
   const int64_t sl = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;  // local source index
   if (sl >= a.ns) return;
@@ -52,6 +94,9 @@ __global__ void __launch_bounds__(256) k_fill_L_far(FillLArgs a) {
   v3 pj[3];
 #pragma unroll
   for (int j = 0; j < 3; ++j) pj[j] = G3(geo, nt, kGeoP + 3 * j, s);
+  const int lev = SUB ? subdiv_level(a.kr, G(geo, nt, kGeoH, s)) : 0;
+  const int npiece = 1 << (2 * lev);
+  const double wpiece = 1.0 / double(npiece);
   const int64_t tbeg = int64_t(blockIdx.y) * a.tchunk;
   const int64_t tend = min(a.nt_test, tbeg + a.tchunk);
   for (int64_t tl = tbeg; tl < tend; ++tl) {
@@ -59,30 +104,37 @@ __global__ void __launch_bounds__(256) k_fill_L_far(FillLArgs a) {
     const v3 d = G3(geo, nt, kGeoC, t) - cs;  // centroid offset test - source
     cz I0 = {0, 0}, Idd = {0, 0};
     cv3 Id = cvzero(), Idp = cvzero();
-#pragma unroll
-    for (int k = 0; k < 7; ++k) {
-      const v3 dk = G3(geo, nt, kGeoQ + 3 * k, t);
-      const v3 base = d + dk;
-      cz s0 = {0, 0};
-      cv3 s1 = cvzero();
-#pragma unroll
-      for (int l = 0; l < 7; ++l) {
-        v3 r = base - dl[l];
-        double r2 = dot(r, r);
-        double inv = rsqrt(r2);
-        double R = r2 * inv;
-        cz g = green<LOSSY>(a.kr, a.ki, R, inv);
-        g = cscale(cW7[l], g);
-        s0 = cadd(s0, g);
-        cv_axpy(s1, g, dl[l]);
+    for (int jp = 0; jp < npiece; ++jp) {
+      if (SUB && lev > 0) {
+        double c[3][3];
+        subdiv_corners(lev, jp, c);
+        for (int l = 0; l < 7; ++l) dl[l] = subdiv_point(c, cB7[l], pj);
       }
-      const double wk = cW7[k];
-      s0 = cscale(wk, s0);
-      s1.x = cscale(wk, s1.x); s1.y = cscale(wk, s1.y); s1.z = cscale(wk, s1.z);
-      I0 = cadd(I0, s0);
-      cv_axpy(Id, s0, dk);
-      cv_add(Idp, s1);
-      Idd = cadd(Idd, cv_dot(dk, s1));
+#pragma unroll
+      for (int k = 0; k < 7; ++k) {
+        const v3 dk = G3(geo, nt, kGeoQ + 3 * k, t);
+        const v3 base = d + dk;
+        cz s0 = {0, 0};
+        cv3 s1 = cvzero();
+#pragma unroll
+        for (int l = 0; l < 7; ++l) {
+          v3 r = base - dl[l];
+          double r2 = dot(r, r);
+          double inv = rsqrt(r2);
+          double R = r2 * inv;
+          cz g = green<LOSSY>(a.kr, a.ki, R, inv);
+          g = cscale(SUB ? cW7[l] * wpiece : cW7[l], g);
+          s0 = cadd(s0, g);
+          cv_axpy(s1, g, dl[l]);
+        }
+        const double wk = cW7[k];
+        s0 = cscale(wk, s0);
+        s1.x = cscale(wk, s1.x); s1.y = cscale(wk, s1.y); s1.z = cscale(wk, s1.z);
+        I0 = cadd(I0, s0);
+        cv_axpy(Id, s0, dk);
+        cv_add(Idp, s1);
+        Idd = cadd(Idd, cv_dot(dk, s1));
+      }
     }
     // H_ij = 1/4 [Idd' - p'_j.Id - p_i.Id' + (p_i.p'_j) I0]
     double2* hrow = a.H + (3 * tl) * a.ldH + 3 * sl;
@@ -115,6 +167,11 @@ __global__ void __launch_bounds__(128) k_fill_L_near(FillLArgs a, const int32_t*
   v3 sv[3];
 #pragma unroll
   for (int j = 0; j < 3; ++j) sv[j] = (cs - ct) + G3(geo, nt, kGeoP + 3 * j, s);
+  // the remainder rule: Q7 on each piece of the source's level-L split (L = 0: plain Q7)
+  const int lev = a.sub ? subdiv_level(a.kr, G(geo, nt, kGeoH, s)) : 0;
+  const int npiece = 1 << (2 * lev);
+  v3 pj[3];
+  for (int j = 0; j < 3; ++j) pj[j] = G3(geo, nt, kGeoP + 3 * j, s);
   cz S0[7];
   cv3 S1[7];
   for (int k = 0; k < 7; ++k) {
@@ -123,13 +180,29 @@ __global__ void __launch_bounds__(128) k_fill_L_near(FillLArgs a, const int32_t*
     cz s0 = {kInv4Pi * si.i1, 0.0};
     cv3 s1 = cvzero();
     s1.x.re = kInv4Pi * si.iv.x; s1.y.re = kInv4Pi * si.iv.y; s1.z.re = kInv4Pi * si.iv.z;
-    for (int l = 0; l < 7; ++l) {
-      const v3 rl = (cs - ct) + G3(geo, nt, kGeoQ + 3 * l, s);
-      const v3 dd = rl - rk;
-      const double R = norm(dd);
-      cz gr = cscale(cW7[l] * As, green_rem(a.kr, a.ki, R));
-      s0 = cadd(s0, gr);
-      cv_axpy(s1, gr, dd);
+    if (lev == 0) {
+      for (int l = 0; l < 7; ++l) {
+        const v3 rl = (cs - ct) + G3(geo, nt, kGeoQ + 3 * l, s);
+        const v3 dd = rl - rk;
+        const double R = norm(dd);
+        cz gr = cscale(cW7[l] * As, green_rem(a.kr, a.ki, R));
+        s0 = cadd(s0, gr);
+        cv_axpy(s1, gr, dd);
+      }
+    } else {
+      const double wp = As / double(npiece);
+      for (int jp = 0; jp < npiece; ++jp) {
+        double c[3][3];
+        subdiv_corners(lev, jp, c);
+        for (int l = 0; l < 7; ++l) {
+          const v3 rl = (cs - ct) + subdiv_point(c, cB7[l], pj);
+          const v3 dd = rl - rk;
+          const double R = norm(dd);
+          cz gr = cscale(cW7[l] * wp, green_rem(a.kr, a.ki, R));
+          s0 = cadd(s0, gr);
+          cv_axpy(s1, gr, dd);
+        }
+      }
     }
     S0[k] = s0;
     S1[k] = s1;
@@ -195,7 +268,9 @@ __global__ void __launch_bounds__(256) k_gather_K(const double2* __restrict__ Kc
 //   m0_k = sum_j w_j g(R_kj),  m1_k = sum_j w_j g(R_kj) d'_j,  u_k = m1_k - Delta_k m0_k
 //   P = sum_k w_k d_k.(d x m1_k),  Q = sum_k w_k Delta_k x m1_k,
 //   R = sum_k w_k d_k x u_k,       S = sum_k w_k u_k
-template <bool LOSSY, int MAXV>
+// SUB: the inner rule of a sub-triangle is Q3 on each piece of its level-L split (L from |Re k|
+// and the sub-triangle's longest edge); otherwise plain Q3.
+template <bool LOSSY, int MAXV, bool SUB>
 __global__ void __launch_bounds__(128) k_fill_K_far(FillKArgs a) {
   const int64_t cl = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (cl >= a.ncells) return;
@@ -224,6 +299,9 @@ __global__ void __launch_bounds__(128) k_fill_K_far(FillKArgs a) {
       v3 dj[3];
 #pragma unroll
       for (int j = 0; j < 3; ++j) dj[j] = cB3[j][1] * sm + cB3[j][2] * sc;
+      const int lev = SUB ? subdiv_level(a.kr, fmax(fmax(norm(sm), norm(sc)), norm(sc - sm))) : 0;
+      const int npiece = 1 << (2 * lev);
+      const v3 sv3[3] = {mk(0, 0, 0), sm, sc};
       cz P = {0, 0};
       cv3 Q = cvzero(), Rm = cvzero(), S = cvzero();
 #pragma unroll
@@ -232,15 +310,22 @@ __global__ void __launch_bounds__(128) k_fill_K_far(FillKArgs a) {
         const v3 Dk = d + dk;
         cz m0 = {0, 0};
         cv3 m1 = cvzero();
+        for (int jp = 0; jp < npiece; ++jp) {
+          if (SUB && lev > 0) {
+            double c[3][3];
+            subdiv_corners(lev, jp, c);
+            for (int j = 0; j < 3; ++j) dj[j] = subdiv_point(c, cB3[j], sv3);
+          }
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-          v3 r = Dk - dj[j];
-          double r2 = dot(r, r);
-          double inv = rsqrt(r2);
-          double R = r2 * inv;
-          cz g = cscale(1.0 / 3.0, grad_green<LOSSY>(a.kr, a.ki, R, inv));
-          m0 = cadd(m0, g);
-          cv_axpy(m1, g, dj[j]);
+          for (int j = 0; j < 3; ++j) {
+            v3 r = Dk - dj[j];
+            double r2 = dot(r, r);
+            double inv = rsqrt(r2);
+            double R = r2 * inv;
+            cz g = cscale(1.0 / (3.0 * npiece), grad_green<LOSSY>(a.kr, a.ki, R, inv));
+            m0 = cadd(m0, g);
+            cv_axpy(m1, g, dj[j]);
+          }
         }
         const double wk = cW7[k];
         // u = m1 - Delta m0
@@ -329,6 +414,10 @@ __global__ void __launch_bounds__(64) k_fill_K_near(FillKArgs a, const int32_t* 
     }
     v3 dj[3];
     for (int j = 0; j < 3; ++j) dj[j] = cB3[j][1] * sm + cB3[j][2] * sc;
+    // inner rule: Q3 on each piece of the sub-triangle's level-L split (L = 0: plain Q3)
+    const int lev = a.sub ? subdiv_level(kr, fmax(fmax(norm(sm), norm(sc)), norm(sc - sm))) : 0;
+    const int npiece = 1 << (2 * lev);
+    const v3 sv3[3] = {mk(0, 0, 0), sm, sc};
     if (!is_near) {
       cz P = {0, 0};
       cv3 Q = cvzero(), Rm = cvzero(), S = cvzero();
@@ -337,13 +426,20 @@ __global__ void __launch_bounds__(64) k_fill_K_near(FillKArgs a, const int32_t* 
         const v3 Dk = d + dk;
         cz m0 = {0, 0};
         cv3 m1 = cvzero();
-        for (int j = 0; j < 3; ++j) {
-          v3 r = Dk - dj[j];
-          double r2 = dot(r, r);
-          double inv = rsqrt(r2);
-          cz g = cscale(1.0 / 3.0, grad_green<LOSSY>(kr, ki, r2 * inv, inv));
-          m0 = cadd(m0, g);
-          cv_axpy(m1, g, dj[j]);
+        for (int jp = 0; jp < npiece; ++jp) {
+          if (lev > 0) {
+            double c[3][3];
+            subdiv_corners(lev, jp, c);
+            for (int j = 0; j < 3; ++j) dj[j] = subdiv_point(c, cB3[j], sv3);
+          }
+          for (int j = 0; j < 3; ++j) {
+            v3 r = Dk - dj[j];
+            double r2 = dot(r, r);
+            double inv = rsqrt(r2);
+            cz g = cscale(1.0 / (3.0 * npiece), grad_green<LOSSY>(kr, ki, r2 * inv, inv));
+            m0 = cadd(m0, g);
+            cv_axpy(m1, g, dj[j]);
+          }
         }
         const double wk = cW7[k];
         cv3 u = m1;
@@ -387,11 +483,18 @@ __global__ void __launch_bounds__(64) k_fill_K_near(FillKArgs a, const int32_t* 
       vk.x.re = -kInv4Pi * si.j3.x; vk.y.re = -kInv4Pi * si.j3.y; vk.z.re = -kInv4Pi * si.j3.z;
       cz c8 = cscale(0.5 * kInv4Pi, k2);  // k^2/(8 pi)
       cv_axpy(vk, c8, si.iv);
-      for (int j = 0; j < 3; ++j) {
-        const v3 dd = Dk - dj[j];
-        const double R = norm(dd);
-        cz h = cscale(At / 3.0, grad_green_rem(kr, ki, R));
-        cv_axpy(vk, h, dd);
+      for (int jp = 0; jp < npiece; ++jp) {
+        if (lev > 0) {
+          double c[3][3];
+          subdiv_corners(lev, jp, c);
+          for (int j = 0; j < 3; ++j) dj[j] = subdiv_point(c, cB3[j], sv3);
+        }
+        for (int j = 0; j < 3; ++j) {
+          const v3 dd = Dk - dj[j];
+          const double R = norm(dd);
+          cz h = cscale(At / (3.0 * npiece), grad_green_rem(kr, ki, R));
+          cv_axpy(vk, h, dd);
+        }
       }
       const double wk = cW7[k] / (4.0 * At);
       for (int b = 0; b < MAXV; ++b) {
@@ -524,7 +627,7 @@ void launch_rhs_planewave(const RhsArgs& a, int nexc, hipStream_t st) {
   BEM_HIP(hipGetLastError());
 }
 
-void fill_set_rules(const double w7[7], const double b3[3][3], hipStream_t st) {
+void fill_set_rules(const double w7[7], const double b7[7][3], const double b3[3][3], hipStream_t st) {
   // the rules never change: written once per device, complete before any fill reads them
   static std::mutex mu;
   static bool done[256] = {};
@@ -533,6 +636,7 @@ void fill_set_rules(const double w7[7], const double b3[3][3], hipStream_t st) {
   std::lock_guard<std::mutex> g(mu);
   if (dev >= 0 && dev < 256 && done[dev]) return;
   BEM_HIP(hipMemcpyToSymbolAsync(HIP_SYMBOL(dev::cW7), w7, sizeof(double) * 7, 0, hipMemcpyHostToDevice, st));
+  BEM_HIP(hipMemcpyToSymbolAsync(HIP_SYMBOL(dev::cB7), b7, sizeof(double) * 21, 0, hipMemcpyHostToDevice, st));
   BEM_HIP(hipMemcpyToSymbolAsync(HIP_SYMBOL(dev::cB3), b3, sizeof(double) * 9, 0, hipMemcpyHostToDevice, st));
   BEM_HIP(hipStreamSynchronize(st));
   if (dev >= 0 && dev < 256) done[dev] = true;
@@ -546,8 +650,13 @@ void launch_fill_L(const FillLArgs& a, const int32_t* near_t, const int32_t* nea
   {
     const double pairs = double(a.ns) * a.nt_test;
     ProfScope ps(st, KC_FILL_L, pairs * 10 * 16, pairs * 49);
-    if (lossy) hipLaunchKernelGGL(dev::k_fill_L_far<true>, grid, dim3(256), 0, st, a);
-    else hipLaunchKernelGGL(dev::k_fill_L_far<false>, grid, dim3(256), 0, st, a);
+    if (a.sub) {
+      if (lossy) hipLaunchKernelGGL((dev::k_fill_L_far<true, true>), grid, dim3(256), 0, st, a);
+      else hipLaunchKernelGGL((dev::k_fill_L_far<false, true>), grid, dim3(256), 0, st, a);
+    } else {
+      if (lossy) hipLaunchKernelGGL((dev::k_fill_L_far<true, false>), grid, dim3(256), 0, st, a);
+      else hipLaunchKernelGGL((dev::k_fill_L_far<false, false>), grid, dim3(256), 0, st, a);
+    }
     BEM_HIP(hipGetLastError());
   }
   if (npairs > 0) {
@@ -580,7 +689,8 @@ void launch_fill_K(const FillKArgs& a, const int32_t* near_t, const int32_t* nea
 #define BEM_KLAUNCH(L, MV)                                                                            \
   {                                                                                                   \
     ProfScope ps(st, KC_FILL_K, kbytes, kwork);                                                       \
-    hipLaunchKernelGGL((dev::k_fill_K_far<L, MV>), grid, dim3(128), 0, st, a);                        \
+    if (a.sub) hipLaunchKernelGGL((dev::k_fill_K_far<L, MV, true>), grid, dim3(128), 0, st, a);      \
+    else hipLaunchKernelGGL((dev::k_fill_K_far<L, MV, false>), grid, dim3(128), 0, st, a);           \
     BEM_HIP(hipGetLastError());                                                                       \
   }                                                                                                   \
   if (npairs > 0) {                                                                                   \

@@ -236,7 +236,7 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
   mark("cells");
   op.mem.set_stream(st);
   const Rules& R = rules();
-  fill_set_rules(R.w7, R.b3, st);
+  fill_set_rules(R.w7, R.b7, R.b3, st);
 
   // ---- problem constants (eq. epsrc; k = sqrt(eps_c mu_r) k0 with Im k <= 0)
   if (!(prob.freq_hz > 0) || !std::isfinite(prob.freq_hz)) throw Error(BEM_E_INVALID, "frequency must be positive");
@@ -529,6 +529,13 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
     return p;
   };
   const int64_t tchunk = 8;
+  // source triangles [s0, s0 + ns) of which some need their rules subdivided at k (the
+  // barycentric sub-triangles are smaller than their parents, so this covers K~ as well)
+  auto needs_sub = [&](cd k, int64_t s0, int64_t ns) {
+    double h = 0;
+    for (int64_t t = s0; t < s0 + ns; ++t) h = std::max(h, m.hmax[t]);
+    return subdiv_level_host(k.real(), h) > 0 ? 1 : 0;
+  };
   for (int64_t o = 0; o < m.nobj; ++o) {
     const int64_t t0 = m.obj_tri[o], nto = m.obj_tri[o + 1] - t0;
     const int64_t e0 = m.obj_edge[o], neo = m.obj_edge[o + 1] - e0;
@@ -540,6 +547,7 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
       int32_t* ps = up32(no_s[o]);
       FillLArgs la{op.geo, nt, t0, nto, t0, nto, tchunk, op.kint[o].real(), op.kint[o].imag(), H, 3 * nto,
                    op.Lphi_int[o].d64, op.Lphi_int[o].ld};
+      la.sub = needs_sub(op.kint[o], t0, nto);
       launch_fill_L(la, pt, ps, int64_t(no_t[o].size()), st);
       launch_gather_LA(H, 3 * nto, d_hp + e0, d_hm + e0, 3 * t0, neo, op.LA_int[o].d64, op.LA_int[o].ld, st);
     }
@@ -555,6 +563,7 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
       FillKArgs ka{op.geo, nt, t0, nto, tchunk, k.real(), k.imag(), d_cells + cdat.obj_cell_ptr[o],
                    cdat.obj_cell_ptr[o + 1] - cdat.obj_cell_ptr[o], cdat.ncell, d_nval, d_vpos, d_col0, d_sub_m, d_sub_c,
                    d_sub_area, d_sub_parent, d_alpha, d_beta, H, cdat.obj_ncol[o]};
+      ka.sub = needs_sub(k, t0, nto);
       launch_fill_K(ka, pct, pcc, int64_t(nc_t[o].size()), d_near_ptr, d_near_idx, cdat.maxv, st);
       launch_gather_K(H, cdat.obj_ncol[o], d_hp + e0, d_hm + e0, 3 * t0, neo, d_cS + e0, d_cT + e0, neo, dst.d64,
                       dst.ld, st);
@@ -570,6 +579,7 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
       FillKArgs ka{op.geo, nt, 0, nt, tchunk, op.kbg.real(), op.kbg.imag(), d_cells + cdat.obj_cell_ptr[o],
                    cdat.obj_cell_ptr[o + 1] - cdat.obj_cell_ptr[o], cdat.ncell, d_nval, d_vpos, d_col0, d_sub_m, d_sub_c,
                    d_sub_area, d_sub_parent, d_alpha, d_beta, H, cdat.obj_ncol[o]};
+      ka.sub = needs_sub(op.kbg, m.obj_tri[o], m.obj_tri[o + 1] - m.obj_tri[o]);
       launch_fill_K(ka, pct, pcc, int64_t(ncm_t[o].size()), d_near_ptr, d_near_idx, cdat.maxv, st);
       launch_gather_K(H, cdat.obj_ncol[o], d_hp, d_hm, 0, m.ne, d_cS + e0, d_cT + e0, neo, op.Km.d64 + e0, op.Km.ld,
                       st);
@@ -580,6 +590,7 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
     int32_t* ps = up32(na_s);
     FillLArgs la{op.geo, nt, 0, nt, 0, nt, tchunk, op.kbg.real(), op.kbg.imag(), H, 3 * nt, op.Lphi_bg.d64,
                  op.Lphi_bg.ld};
+    la.sub = needs_sub(op.kbg, 0, nt);
     launch_fill_L(la, pt, ps, int64_t(na_t.size()), st);
     launch_gather_LA(H, 3 * nt, d_hp, d_hm, 0, m.ne, op.LA_bg.d64, op.LA_bg.ld, st);
   }
