@@ -41,7 +41,7 @@ def log(*a):
 def workload(name: str):
     import meshgen
     return {"c1": meshgen.config_c1, "c2": meshgen.config_c2, "c2x256": meshgen.config_c2_multi,
-            "c3": meshgen.config_c3, "spharr": meshgen.config_sphere_array}[name]()
+            "c3": meshgen.config_c3, "spharr": meshgen.config_sphere_array, "c4": meshgen.config_c4}[name]()
 
 
 def cpu_baseline(w, n_sample: int = 12) -> dict:
@@ -195,6 +195,8 @@ def main() -> int:
     ap.add_argument("--exc", type=int, default=0, help="use only the first N excitations of the workload")
     ap.add_argument("--maxit", type=int, default=3000)
     ap.add_argument("--no-precond", action="store_true")
+    ap.add_argument("--sweep-start", type=int, default=0,
+                    help="first frequency index of a swept workload (the conductor array)")
     ap.add_argument("--no-reuse", action="store_true",
                     help="fill and invert every object separately even when objects are translated copies")
     ap.add_argument("--tol", type=float, default=1e-6)
@@ -229,8 +231,12 @@ def main() -> int:
     form = B.BEM_FORM_EAEFIE if args.formulation == "eaefie" else B.BEM_FORM_SLDM
     ctx = B.bem_create(0)
     khat, pol = (w.khat[:args.exc], w.pol[:args.exc]) if args.exc > 0 else (w.khat, w.pol)
-    exc = B.plane_waves(khat, pol)
-    n_exc = len(khat)
+    port = getattr(w, "port", None)
+    exc = B.delta_gaps([port]) if port is not None else B.plane_waves(khat, pol)
+    n_exc = 1 if port is not None else len(khat)
+    # a frequency sweep (conductor array): step i solves the sweep's frequency i (cyclically)
+    freqs = list(getattr(w, "freqs", [w.freq_hz]))
+    nstep = [args.sweep_start]
     if args.restart <= 0:
         args.restart = 300 if n_exc <= 8 else 100
     opts = B.solve_opts(tol=args.tol, restart=args.restart, maxit=args.maxit)
@@ -238,11 +244,13 @@ def main() -> int:
     phases = {"mesh_load": 0.0, "assemble": 0.0, "solve": 0.0, "release": 0.0}
 
     def step():
+        freq = freqs[nstep[0] % len(freqs)]
+        nstep[0] += 1
         t0 = time.perf_counter()
         mesh = B.bem_mesh_load(ctx, w.xyz, w.tri, w.obj)
         info = B.bem_mesh_info(ctx, mesh)
         t1 = time.perf_counter()
-        op = B.bem_assemble(ctx, mesh, B.make_problem(w.freq_hz, w.eps_r, w.mu_r, w.sigma, eps_bg=w.eps_bg,
+        op = B.bem_assemble(ctx, mesh, B.make_problem(freq, w.eps_r, w.mu_r, w.sigma, eps_bg=w.eps_bg,
                                                       mu_bg=w.mu_bg, precision=prec, inner_mode=inner,
                                                       precond=precond, formulation=form, reuse=not args.no_reuse))
         t2 = time.perf_counter()
@@ -255,7 +263,7 @@ def main() -> int:
         for k, dt in zip(phases, (t1 - t0, t2 - t1, t3 - t2, t4 - t3)):
             phases[k] += dt
         if rc != B.BEM_OK or not (si.rel_residual <= args.tol):
-            raise RuntimeError(f"solve failed: status {rc}, residual {si.rel_residual:.3e}")
+            raise RuntimeError(f"solve failed at {freq:.4g} Hz: status {rc}, residual {si.rel_residual:.3e}")
         return info, si, st
 
     for i in range(args.warmup):
@@ -271,7 +279,8 @@ def main() -> int:
         info, si, st = step()
         torch.cuda.synchronize()
         lat.append(time.perf_counter() - t0)
-        log(f"step {i}: {lat[-1]:.3f} s, outer {si.outer_iters}, refine {si.refine_steps}, "
+        log(f"step {i} ({freqs[(nstep[0] - 1) % len(freqs)]:.4g} Hz): {lat[-1]:.3f} s, outer {si.outer_iters}, "
+            f"refine {si.refine_steps}, "
             f"products {si.n_products}, res {si.rel_residual:.2e}, fill {st['fill_seconds']*1e3:.1f} ms")
     torch.cuda.synchronize()
     total = time.perf_counter() - t_start
@@ -324,7 +333,7 @@ def main() -> int:
         "vs_baseline": None, "dtype": "f32+f64" if prec == B.BEM_MIXED else "f64", "data": "synthetic",
         "config": {"workload": w.name, "n_tri": info["n_tri"], "n_unknowns": info["n_unknowns"],
                    "excitations": n_exc, "tol": args.tol, "restart": args.restart, "precision": args.precision,
-                   "inner": args.inner, "precond": bool(precond), "formulation": args.formulation,
+                   "inner": args.inner, "precond": bool(precond), "formulation": args.formulation, "frequencies": len(freqs),
                    "reuse_repeated_objects": not args.no_reuse, "interiors_filled": int(st["interiors_filled"])},
         "p50_s": p50, "p99_s": p99,
         "fill_GBps": st["fill_bytes"] / st["fill_seconds"] / 1e9,

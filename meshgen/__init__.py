@@ -258,6 +258,29 @@ def config_c3(n: int = 32, n_exc: int = 256) -> Workload:
                     khat=khat, pol=pol.astype(np.complex128))
 
 
+def gap_ring(xyz: np.ndarray, tri: np.ndarray, obj: np.ndarray, o: int = 0, x0: float = 0.0) -> np.ndarray:
+    """Vertex pairs (a < b) of the edges of object o lying in the plane x = x0: the gap of a
+    voltage-gap port across a bar."""
+    t = tri[obj == o]
+    e = np.concatenate([t[:, [0, 1]], t[:, [1, 2]], t[:, [2, 0]]])
+    e = np.unique(np.sort(e, axis=1), axis=0)
+    on = (np.abs(xyz[e[:, 0], 0] - x0) < 1e-15) & (np.abs(xyz[e[:, 1], 0] - x0) < 1e-15)
+    return e[on].astype(np.int32)
+
+
+def config_c4(n_freq: int = 32) -> Workload:
+    """4 x 4 copper bars (10 x 1 x 1 um, sigma = 5.8e7 S/m, pitch 3 um) in eps_r = 4, graded
+    from 0.05 um at the edges and corners to 1 um (ratio 2, 22528 triangles); the sweep's
+    n_freq log-spaced frequencies 1-100 GHz are in `freqs` (freq_hz is the first); the port is
+    the ring x = 0 of the first bar (`gap_ring`)."""
+    xyz, tri, obj = copper_bars(h_min=0.05e-6, h_max=1.0e-6, ratio=2.0)
+    w = Workload(f"copper_bars4x4_{len(tri)}_1-100GHz", xyz, tri, obj, 1e9, [1.0] * 16, [1.0] * 16, [5.8e7] * 16,
+                 eps_bg=4.0)
+    w.freqs = np.logspace(9, 11, n_freq)
+    w.port = gap_ring(xyz, tri, obj, 0)
+    return w
+
+
 def config_sphere_array(n: int = 4, level: int = 2, pitch: float = 0.375) -> Workload:
     """n x n array of dielectric spheres (eps_r = 12, diameter 250 mm, icosphere of 20 4^level
     triangles each) at `pitch` in the x-y plane, centred on the origin, at 200 MHz in a

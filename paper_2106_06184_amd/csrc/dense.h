@@ -17,6 +17,15 @@ struct DenseScratch {
 // Gauss-Jordan elimination without pivoting.  Asynchronous on st.
 void dense_invert(double2* A, int64_t n, int64_t ld, DenseScratch& ws, hipStream_t st);
 
+// A[i][j] *= rs[i] cs[j] for i < nr, j < nc (device scale vectors, real).
+void scale_rows_cols(double2* A, int64_t ld, int64_t nr, int64_t nc, const double* rs, const double* cs,
+                     hipStream_t st);
+// out[j] = max over rows [r0, r1) of |A[i][c0 + j]|, j < nc; and out[i] = max over columns
+// [0, nc) of |A[r0 + i][j]|, i < nr (device outputs).
+void col_maxabs(const double2* A, int64_t ld, int64_t r0, int64_t r1, int64_t c0, int64_t nc, double* out,
+                hipStream_t st);
+void row_maxabs(const double2* A, int64_t ld, int64_t r0, int64_t nr, int64_t nc, double* out, hipStream_t st);
+
 // Dense M_eq of one object (eq. AEFIEeqvdis) from its diagonal blocks of L^A_l and L^phi_l;
 // tp/tm are the object's edges' triangles in object-local numbering; mu = mu_l,
 // meps = -1/eps_l, k02 = k0^2.

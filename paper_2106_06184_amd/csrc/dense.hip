@@ -526,6 +526,65 @@ void dense_invert(double2* A, int64_t n, int64_t ld, DenseScratch& ws, hipStream
   BEM_HIP(hipGetLastError());
 }
 
+namespace dev {
+__global__ void k_scale_rc(double2* __restrict__ A, int64_t ld, int64_t nr, int64_t nc, const double* __restrict__ rs,
+                           const double* __restrict__ cs) {
+  const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j >= nc) return;
+  const double c = cs[j];
+  for (int64_t i = blockIdx.y; i < nr; i += gridDim.y) {
+    const double s = rs[i] * c;
+    double2 v = A[i * ld + j];
+    A[i * ld + j] = make_double2(s * v.x, s * v.y);
+  }
+}
+__global__ void k_col_maxabs(const double2* __restrict__ A, int64_t ld, int64_t r0, int64_t r1, int64_t c0,
+                             int64_t nc, double* __restrict__ out) {
+  const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j >= nc) return;
+  double m = 0;
+  for (int64_t i = r0; i < r1; ++i) {
+    const double2 v = A[i * ld + c0 + j];
+    m = fmax(m, sqrt(v.x * v.x + v.y * v.y));
+  }
+  out[j] = m;
+}
+// one wave per row, fixed-order butterfly reduction
+__global__ void __launch_bounds__(256) k_row_maxabs(const double2* __restrict__ A, int64_t ld, int64_t r0, int64_t nr,
+                                                    int64_t nc, double* __restrict__ out) {
+  const int64_t i = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= nr) return;
+  const double2* row = A + (r0 + i) * ld;
+  double m = 0;
+  for (int64_t j = lane; j < nc; j += 64) m = fmax(m, sqrt(row[j].x * row[j].x + row[j].y * row[j].y));
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+  if (lane == 0) out[i] = m;
+}
+}  // namespace dev
+
+void scale_rows_cols(double2* A, int64_t ld, int64_t nr, int64_t nc, const double* rs, const double* cs,
+                     hipStream_t st) {
+  if (nr <= 0 || nc <= 0) return;
+  hipLaunchKernelGGL(dev::k_scale_rc, dim3(unsigned((nc + 255) / 256), unsigned(std::min<int64_t>(nr, 32768))),
+                     dim3(256), 0, st, A, ld, nr, nc, rs, cs);
+  BEM_HIP(hipGetLastError());
+}
+
+void col_maxabs(const double2* A, int64_t ld, int64_t r0, int64_t r1, int64_t c0, int64_t nc, double* out,
+                hipStream_t st) {
+  if (nc <= 0) return;
+  hipLaunchKernelGGL(dev::k_col_maxabs, dim3(unsigned((nc + 255) / 256)), dim3(256), 0, st, A, ld, r0, r1, c0, nc,
+                     out);
+  BEM_HIP(hipGetLastError());
+}
+
+void row_maxabs(const double2* A, int64_t ld, int64_t r0, int64_t nr, int64_t nc, double* out, hipStream_t st) {
+  if (nr <= 0) return;
+  hipLaunchKernelGGL(dev::k_row_maxabs, dim3(unsigned((nr + 3) / 4)), dim3(256), 0, st, A, ld, r0, nr, nc, out);
+  BEM_HIP(hipGetLastError());
+}
+
 void build_meq(const double2* LA, int64_t lda, const double2* Lp, int64_t ldp, const int32_t* tp_local,
                const int32_t* tm_local, int64_t ne, int64_t nt, double2 mu, double2 meps, double k02, double2* M,
                int64_t ldm, hipStream_t st) {

@@ -33,6 +33,10 @@ inline int64_t pad64(int64_t n) { return (n + 63) / 64 * 64; }
 constexpr int kWorkFields = 15;
 int64_t work_ld(const OpObj& op) { return pad64(op.Neq); }
 
+// Largest relative deviation of the float32 final-system product from the float64 one for which
+// a mixed-precision solve runs float32 sweeps.
+constexpr double kFp32ProbeTol = 1e-4;
+
 // Smallest |k_l| h_max for which the nested solve eliminates the charges (S of build_s): its
 // D^T L^phi D / k0^2 term grows like (k h)^-2 against the L^A term.
 constexpr double kSchurMinKh = 0.01;
@@ -695,7 +699,8 @@ void build_inner_and_precond(OpObj& op, const std::vector<double>& ixdiag, hipSt
   ds.R = talloc(size_t(64) * maxn);
   ds.C = talloc(size_t(64) * maxn);
   // diagonals through a gather kernel and a stream-ordered copy (complete on return)
-  double2* dbuf = talloc(size_t(std::max(m.ne, m.nt)));
+  const int64_t nbuf = std::max(std::max(m.ne, m.nt), maxn);
+  double2* dbuf = talloc(size_t(nbuf));
   auto diag_of = [&](const Dense& A) {
     std::vector<double2> d(A.rows);
     launch_diag(A.d64, A.ld, A.rows, dbuf, st);
@@ -704,6 +709,66 @@ void build_inner_and_precond(OpObj& op, const std::vector<double>& ixdiag, hipSt
     return d;
   };
   auto cdv = [](double2 v) { return cd(v.x, v.y); };
+  // Inversion of an equilibrated matrix: M' = diag(r) M diag(c) is inverted in place and turned
+  // back into M^-1 = diag(c) M'^-1 diag(r).  The scales change only the rounding: the blocks of
+  // M_eq differ by many orders of magnitude on graded meshes of small objects (|L^A| ~ h,
+  // |L^phi| ~ 1/h), and Gauss-Jordan without pivoting needs them balanced.
+  double* rdev = reinterpret_cast<double*>(talloc(size_t(nbuf)));
+  double* cdev = reinterpret_cast<double*>(talloc(size_t(nbuf)));
+  auto put = [&](double* d, const std::vector<double>& v) {
+    BEM_HIP(hipMemcpyAsync(d, v.data(), sizeof(double) * v.size(), hipMemcpyHostToDevice, st));
+    BEM_HIP(hipStreamSynchronize(st));
+  };
+  auto get = [&](const double* d, size_t n) {
+    std::vector<double> v(n);
+    BEM_HIP(hipMemcpyAsync(v.data(), d, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+    BEM_HIP(hipStreamSynchronize(st));
+    return v;
+  };
+  auto inv_scale = [](double x) { return x > 0 && std::isfinite(x) ? 1.0 / x : 1.0; };
+  auto invert_equilibrated = [&](Dense& M, int64_t n, const std::vector<double>& r, const std::vector<double>& c) {
+    put(rdev, r);
+    put(cdev, c);
+    scale_rows_cols(M.d64, M.ld, n, n, rdev, cdev, st);
+    dense_invert(M.d64, n, M.ld, ds, st);
+    scale_rows_cols(M.d64, M.ld, n, n, cdev, rdev, st);
+    BEM_HIP(hipStreamSynchronize(st));
+  };
+  // symmetric Jacobi scaling |diag|^-1/2 (S and the charge Schur complements)
+  auto invert_jacobi = [&](Dense& M, int64_t n) {
+    const std::vector<double2> d = diag_of(M);
+    std::vector<double> s(n);
+    for (int64_t i = 0; i < n; ++i) s[i] = inv_scale(std::sqrt(std::abs(cdv(d[i]))));
+    invert_equilibrated(M, n, s, s);
+  };
+  // M_eq: Jacobi on the edge block, then the charge columns and rows normalised by their
+  // largest entries (those of the coupling blocks)
+  auto invert_meq = [&](Dense& M, int64_t neo, int64_t n) {
+    const std::vector<double2> d = diag_of(M);
+    std::vector<double> r(n, 1.0), c(n, 1.0), one(n, 1.0);
+    for (int64_t i = 0; i < neo; ++i) r[i] = c[i] = inv_scale(std::sqrt(std::abs(cdv(d[i]))));
+    put(rdev, r);
+    scale_rows_cols(M.d64, M.ld, n, n, rdev, rdev, st);
+    col_maxabs(M.d64, M.ld, 0, neo, neo, n - neo, cdev, st);
+    std::vector<double> cq = get(cdev, size_t(n - neo));
+    std::vector<double> cs(one);
+    for (int64_t q = 0; q < n - neo; ++q) cs[neo + q] = c[neo + q] = inv_scale(cq[q]);
+    put(rdev, one);
+    put(cdev, cs);
+    scale_rows_cols(M.d64, M.ld, n, n, rdev, cdev, st);
+    row_maxabs(M.d64, M.ld, neo, n - neo, n, rdev, st);
+    std::vector<double> rq = get(rdev, size_t(n - neo));
+    std::vector<double> rs(one);
+    for (int64_t q = 0; q < n - neo; ++q) rs[neo + q] = r[neo + q] = inv_scale(rq[q]);
+    put(rdev, rs);
+    put(cdev, one);
+    scale_rows_cols(M.d64, M.ld, n, n, rdev, cdev, st);
+    dense_invert(M.d64, n, M.ld, ds, st);
+    put(rdev, r);
+    put(cdev, c);
+    scale_rows_cols(M.d64, M.ld, n, n, cdev, rdev, st);
+    BEM_HIP(hipStreamSynchronize(st));
+  };
   op.Minv.clear();
   if (op.inner_mode == BEM_INNER_DIRECT) {
     for (int64_t o = 0; o < m.nobj; ++o) {
@@ -725,7 +790,7 @@ void build_inner_and_precond(OpObj& op, const std::vector<double>& ixdiag, hipSt
       Dense M = alloc_dense(op.mem, n, n, f32);
       build_meq(op.LA_bg.d64 + e0 * op.LA_bg.ld + e0, op.LA_bg.ld, op.Lphi_bg.d64 + t0 * op.Lphi_bg.ld + t0,
                 op.Lphi_bg.ld, dtp, dtm, neo, nto, c2(op.mu_bg), c2(-1.0 / op.eps_bg), op.k0 * op.k0, M.d64, M.ld, st);
-      dense_invert(M.d64, n, M.ld, ds, st);
+      invert_meq(M, neo, n);
       to_f32(M, st);
       BEM_HIP(hipStreamSynchronize(st));
       op.mem.release(dtp);
@@ -752,7 +817,7 @@ void build_inner_and_precond(OpObj& op, const std::vector<double>& ixdiag, hipSt
       Dense S = alloc_dense(op.mem, neo, neo, f32);
       build_s(op.LA_bg.d64 + e0 * op.LA_bg.ld + e0, op.LA_bg.ld, op.Lphi_bg.d64 + t0 * op.Lphi_bg.ld + t0,
               op.Lphi_bg.ld, dtp, dtm, neo, c2(op.mu_bg), c2(-1.0 / (op.eps_bg * op.k0 * op.k0)), S.d64, S.ld, st);
-      dense_invert(S.d64, neo, S.ld, ds, st);
+      invert_jacobi(S, neo);
       to_f32(S, st);
       BEM_HIP(hipStreamSynchronize(st));
       op.mem.release(dtp);
@@ -856,7 +921,7 @@ void build_inner_and_precond(OpObj& op, const std::vector<double>& ixdiag, hipSt
       Dense S = alloc_dense(op.mem, nq, nq, f32);
       const double k02 = op.k0 * op.k0;
       build_schur(dptr, didx, dval, nq, nto - 1, which == 0 ? c2(k02) : c2(-k02), S.d64, S.ld, st);
-      dense_invert(S.d64, nq, S.ld, ds, st);
+      invert_jacobi(S, nq);
       to_f32(S, st);
       BEM_HIP(hipStreamSynchronize(st));
       op.mem.release(dptr);
@@ -1867,19 +1932,39 @@ int solve_op(OpObj& op, const bem_excitation* exc, int64_t nexc, const bem_solve
   const BApplyFn* Pm64 = op.precond ? &P64 : nullptr;
   const BApplyFn* Pm32 = op.precond ? &P32 : nullptr;
 
+  // Mixed precision pays only while the float32 products stay close to the float64 ones on
+  // vectors shaped like the solution: once per solve, z = P b (b the first excitation's
+  // right-hand side, P the preconditioner, an approximate inverse) is multiplied in both
+  // precisions, and float64 products are used throughout when ||A32 z - A64 z|| / ||A64 z||
+  // exceeds kFp32ProbeTol.  Random vectors do not show it: for small conductors at low
+  // frequency the equivalent current cancels the physical one to many digits, so float32
+  // products of solution-like vectors lose them all, and float32 sweeps make no progress.
+  bool fp32_ok = op.precision == BEM_MIXED;
+  bool probed = false;
   for (int64_t e0 = 0; e0 < nexc; e0 += Rb) {
     const int R = int(std::min<int64_t>(Rb, nexc - e0));
     launch_axpby(N, c2(0.0), nullptr, c2(0.0), nullptr, bfull, st, R, 0, 0, ldN);
     BEM_HIP(hipMemcpy2DAsync(bfull, sizeof(double2) * ldN, Bexc + e0 * ne, sizeof(double2) * ne,
                              sizeof(double2) * ne, R, hipMemcpyDeviceToDevice, st));
     std::vector<char> conv(R, 0);
+    if (fp32_ok && !probed) {
+      probed = true;
+      if (op.precond) P64(bfull, ldN, dd, ldN, 1);
+      else BEM_HIP(hipMemcpyAsync(dd, bfull, sizeof(double2) * N, hipMemcpyDeviceToDevice, st));
+      A64(dd, ldN, rr, ldN, 1);
+      const double dev = true_residuals(bw, A32, rr, dd, ldN, 1, st)[0];
+      inf.n_products += 2;
+      fp32_ok = dev <= kFp32ProbeTol;
+      if (verbose()) std::fprintf(stderr, "[bem] float32 product deviation %.3e%s\n", dev, fp32_ok ? "" : ": float64 products");
+    }
     // One refinement loop for both precisions.  Every sweep solves A d = r for the active
     // columns with GMRES (float32 products while in mixed precision, float64 otherwise), then
     // x += d and the float64 residual r = b - A x is recomputed; a column leaves once
     // ||r|| <= tol ||b||.  A float32 sweep that does not halve the residual of every active
-    // column switches the remaining sweeps to float64 products (float32 too inaccurate for
-    // this operator); in float64 precision the sweeps after the first correct the Arnoldi
-    // estimate drifting from the true residual.
+    // column, or that does not reach its target within three restart cycles, switches the
+    // remaining sweeps to float64 products (float32 too inaccurate for this operator); in
+    // float64 precision the sweeps after the first correct the Arnoldi estimate drifting from
+    // the true residual.
     launch_axpby(N, c2(0.0), nullptr, c2(0.0), nullptr, xs, st, R, 0, 0, ldN);
     bw.norms(bfull, ldN, R, st);
     std::vector<double> bn(R), rel(R, 1.0);
@@ -1892,7 +1977,7 @@ int solve_op(OpObj& op, const bem_excitation* exc, int64_t nexc, const bem_solve
         rel[c] = 0.0;
       }
     }
-    bool use32 = op.precision == BEM_MIXED;
+    bool use32 = fp32_ok;
     int left = opts.maxit;
     auto upload_active = [&]() {
       BEM_HIP(hipStreamSynchronize(st));
@@ -1920,7 +2005,12 @@ int solve_op(OpObj& op, const bem_excitation* exc, int64_t nexc, const bem_solve
         for (int c = 0; c < Rc; ++c) gtol = std::min(gtol, 0.5 * opts.tol / std::max(rel[active[c]], 1e-300));
         gtol = std::max(gtol, 1e-15);
       }
-      BResult g = gmres_batched(bw, use32 ? A32 : A64, rr, ldN, dd, ldN, Rc, gtol, left, st, use32 ? Pm32 : Pm64);
+      // a float32 sweep gets at most three restart cycles (600 steps at least): one that cannot
+      // reach its target in that budget works on products too inaccurate in float32
+      const int budget = use32 ? std::min(left, std::max(3 * opts.restart, 600)) : left;
+      BResult g = gmres_batched(bw, use32 ? A32 : A64, rr, ldN, dd, ldN, Rc, gtol, budget, st, use32 ? Pm32 : Pm64);
+      bool sweep_failed = false;
+      for (int c = 0; c < Rc; ++c) sweep_failed |= !g.converged[c];
       int most = 0;
       for (int c = 0; c < Rc; ++c) {
         inf.outer_iters += g.iters[c];
@@ -1944,7 +2034,7 @@ int solve_op(OpObj& op, const bem_excitation* exc, int64_t nexc, const bem_solve
         else next.push_back(active[c]);
       }
       active.swap(next);
-      if (use32 && stalled && !active.empty()) {
+      if (use32 && (stalled || sweep_failed) && !active.empty()) {
         use32 = false;
         if (verbose()) std::fprintf(stderr, "[bem] float32 sweep stalled: float64 products from here on\n");
       }
