@@ -99,3 +99,65 @@ def test_transparent_object_identity_fullsize(c2):
     err = np.linalg.norm(Ix @ e - b) / np.linalg.norm(b)
     print(f"outer {si.outer_iters}, residual {si.rel_residual:.2e}, ||I_x e - b|| / ||b|| = {err:.2e}")
     assert err < 1e-6
+
+
+def _c4_pair():
+    """Two neighbouring bars of the conductor-array workload (its graded 1408-triangle bar mesh,
+    0.05-1 um edges), with the array's port ring on the first."""
+    w = meshgen.config_c4()
+    sel = w.obj < 2
+    tri = w.tri[sel]
+    used = np.unique(tri)
+    remap = -np.ones(len(w.xyz), np.int64)
+    remap[used] = np.arange(len(used))
+    return w, w.xyz[used], remap[tri].astype(np.int32), w.obj[sel]
+
+
+@pytest.mark.parametrize("freq", [1e9, 1e11])
+def test_conductor_array_sampled_rows(freq):
+    """Bars of the conductor array at the ends of its sweep (at 100 GHz the source rules of the
+    copper interior are subdivided): sampled rows of the interior and background blocks against
+    the oracle, 1e-12 (L) and 1e-11 (K~, see the conductor-sphere tests)."""
+    w, xyz, tri, obj = _c4_pair()
+    topo = OM.build_topology(xyz, tri, obj)
+    rng = np.random.default_rng(23)
+    ne, nt = len(topo.edges), len(topo.tri)
+    edges_o = rng.choice(np.nonzero(topo.edge_obj == 0)[0], size=3, replace=False)
+    tris = np.unique(np.concatenate([topo.tplus[edges_o], topo.tminus[edges_o]]))
+    bary = OM.buffa_christiansen(topo)
+    near = OO.near_pairs(topo)
+    bcd = OO.bc_on_subtriangles(bary)
+    k0 = OC.k0_of(freq)
+    k_int = OC.wavenumber(k0, OC.eps_c(1.0, 5.8e7, freq), 1.0)
+    k_bg = OC.wavenumber(k0, 4.0, 1.0)
+    ctx = B.bem_create(0)
+    mesh = B.bem_mesh_load(ctx, xyz, tri, obj)
+    op = B.bem_assemble(ctx, mesh, B.make_problem(freq, [1.0, 1.0], [1.0, 1.0], [5.8e7, 5.8e7], eps_bg=4.0,
+                                                  precision=B.BEM_MIXED))
+    va, vb, _, _ = B.bem_edge_table(ctx, mesh)
+    perm = edge_perm(va, vb, topo.edges)
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(ne)
+    rows_lib = inv[edges_o]
+    same = (topo.edge_obj == 0)[None, :]
+    for k, (bla, blp, bk) in ((k_int, (B.BEM_BLOCK_LA_INT, B.BEM_BLOCK_LPHI_INT, B.BEM_BLOCK_K_INT)),
+                              (k_bg, (B.BEM_BLOCK_LA_BG, B.BEM_BLOCK_LPHI_BG, B.BEM_BLOCK_K_BG))):
+        LA, Lp = OO.fill_L(topo, k, near, test_subset=tris)
+        K = OO.fill_K(topo, bary, k, near, bcd, test_subset=tris)
+        interior = k is k_int
+        # interior blocks and the background K~ are block-diagonal: zero outside the object
+        for blk, ref_rows, tol, local in ((bla, LA[edges_o], 1e-12, interior), (bk, K[edges_o], 1e-11, True)):
+            G = B.bem_block_export(ctx, op, blk, ne, ne)
+            got = G[rows_lib][:, np.argsort(perm)]
+            want = np.where(same, ref_rows, 0.0) if local else ref_rows
+            for r in range(len(want)):
+                err = np.abs(got[r] - want[r]).max() / np.abs(want[r]).max()
+                assert err < tol, (freq, blk, r, err)
+        Gp = B.bem_block_export(ctx, op, blp, nt, nt)
+        for r, t in enumerate(tris):
+            ref = Lp[t] if not interior else np.where(topo.obj == topo.obj[t], Lp[t], 0.0)
+            err = np.abs(Gp[t] - ref).max() / np.abs(ref).max()
+            assert err < 1e-12, (freq, blp, t, err)
+        print(f"{freq:.0e} Hz k = {k:.3e}: rows of blocks {bla}, {bk}, {blp} match")
+    B.bem_release(ctx, op)
+    B.bem_destroy(ctx)
