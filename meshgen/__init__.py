@@ -65,6 +65,34 @@ def icosphere(level: int, radius: float = 1.0) -> tuple[np.ndarray, np.ndarray]:
     return xyz, _orient_outward(xyz, tri, np.zeros(3)).astype(np.int32)
 
 
+def bipyramid(n: int, radius: float = 1.0, height: float = 1.0, rings: int = 2) -> tuple[np.ndarray, np.ndarray]:
+    """Double cone over an n-gon with `rings` rings of n vertices between the equator and each
+    apex: the apexes have valence n (the largest vertex valence of the mesh)."""
+    verts = [np.array([0.0, 0.0, height]), np.array([0.0, 0.0, -height])]
+    levels = [height * (1 - (i + 1) / (rings + 1)) for i in range(rings)]
+    zs = levels + [0.0] + [-z for z in reversed(levels)]
+    ring_start = []
+    for r, z in enumerate(zs):
+        rad = radius * (1 - abs(z) / height)
+        ring_start.append(len(verts))
+        off = 0.5 * (r % 2)
+        for i in range(n):
+            a = 2 * math.pi * (i + off) / n
+            verts.append(np.array([rad * math.cos(a), rad * math.sin(a), z]))
+    tri = []
+    first, last = ring_start[0], ring_start[-1]
+    for i in range(n):
+        tri.append((0, first + i, first + (i + 1) % n))
+        tri.append((1, last + (i + 1) % n, last + i))
+    for r in range(len(zs) - 1):
+        a0, b0 = ring_start[r], ring_start[r + 1]
+        for i in range(n):
+            tri.append((a0 + i, b0 + i, b0 + (i + 1) % n))
+            tri.append((a0 + i, b0 + (i + 1) % n, a0 + (i + 1) % n))
+    xyz = np.array(verts)
+    return xyz, _orient_outward(xyz, np.array(tri, dtype=np.int32), np.zeros(3)).astype(np.int32)
+
+
 def _box_surface(xs: np.ndarray, ys: np.ndarray, zs: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
     """Structured surface mesh of the box spanned by the sorted node arrays xs, ys, zs.
 

@@ -131,6 +131,20 @@ def near_pairs(topo: Topology, factor: float = NEAR_FACTOR) -> np.ndarray:
     return near | share
 
 
+def near_rows(topo: Topology, rows, factor: float = NEAR_FACTOR) -> np.ndarray:
+    """The given rows of near_pairs (other rows False), for meshes whose full pair matrix is not
+    needed: shared vertex or centroid distance below factor * max(longest edges)."""
+    nt = len(topo.tri)
+    h = longest_edge(tri_vertices(topo))
+    c = topo.centroid
+    out = np.zeros((nt, nt), dtype=bool)
+    for t in np.atleast_1d(rows):
+        d = np.linalg.norm(c - c[t], axis=1)
+        share = np.isin(topo.tri, topo.tri[t]).any(axis=1)
+        out[t] = (d < factor * np.maximum(h, h[t])) | share
+    return out
+
+
 def coplanar(topo: Topology, t: int, others: np.ndarray) -> np.ndarray:
     n = topo.normal
     h = longest_edge(tri_vertices(topo))

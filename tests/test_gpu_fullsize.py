@@ -16,7 +16,7 @@ import paper_2106_06184_amd as B
 from oracle import constants as OC
 from oracle import mesh as OM
 from oracle import operators as OO
-from tests.bemutil import edge_perm
+from tests.bemutil import edge_perm, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -159,5 +159,53 @@ def test_conductor_array_sampled_rows(freq):
             err = np.abs(Gp[t] - ref).max() / np.abs(ref).max()
             assert err < 1e-12, (freq, blp, t, err)
         print(f"{freq:.0e} Hz k = {k:.3e}: rows of blocks {bla}, {bk}, {blp} match")
+    B.bem_release(ctx, op)
+    B.bem_destroy(ctx)
+
+
+def test_ellipsoid_full_size_rows_and_batched_product():
+    """The 12288-triangle jittered ellipsoid with 256 plane waves: sampled rows of L^A, K~ and
+    L^phi at the object wavenumber against the oracle (1e-12), and the 256-column product of
+    each dense block (float64 matrix-core GEMM) against the float64 product of the exported
+    block on the host (1e-12), a property that holds at any size."""
+    import torch
+    w = meshgen.config_c3()
+    topo = OM.build_topology(w.xyz, w.tri, w.obj)
+    rng = np.random.default_rng(29)
+    ne, nt = len(topo.edges), len(topo.tri)
+    edges_o = rng.choice(ne, size=2, replace=False)
+    tris = np.unique(np.concatenate([topo.tplus[edges_o], topo.tminus[edges_o]]))
+    k0 = OC.k0_of(w.freq_hz)
+    k_int = OC.wavenumber(k0, OC.eps_c(w.eps_r[0], w.sigma[0], w.freq_hz), w.mu_r[0])
+    ctx = B.bem_create(0)
+    mesh = B.bem_mesh_load(ctx, w.xyz, w.tri, w.obj)
+    op = B.bem_assemble(ctx, mesh, B.make_problem(w.freq_hz, w.eps_r, w.mu_r, w.sigma, precision=B.BEM_MIXED))
+    va, vb, _, _ = B.bem_edge_table(ctx, mesh)
+    perm = edge_perm(va, vb, topo.edges)
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(ne)
+    near = OO.near_rows(topo, tris)          # the sampled rows of the near-pair relation
+    bary = OM.buffa_christiansen(topo)
+    LA, Lp = OO.fill_L(topo, k_int, near, test_subset=tris)
+    K = OO.fill_K(topo, bary, k_int, near, OO.bc_on_subtriangles(bary), test_subset=tris)
+    for blk, ref in ((B.BEM_BLOCK_LA_INT, LA[edges_o]), (B.BEM_BLOCK_K_INT, K[edges_o])):
+        G = B.bem_block_export(ctx, op, blk, ne, ne)
+        got = G[inv[edges_o]][:, inv]
+        for r in range(len(ref)):
+            assert np.abs(got[r] - ref[r]).max() / np.abs(ref[r]).max() < 1e-12, (blk, r)
+        # 256-column product of the exported float64 block
+        X = rng.standard_normal((256, ne)) + 1j * rng.standard_normal((256, ne))
+        xd = torch.tensor(X, dtype=torch.complex128, device="cuda")
+        yd = torch.zeros_like(xd)
+        B.bem_apply(ctx, op, blk, xd.data_ptr(), yd.data_ptr(), 256, torch.cuda.current_stream().cuda_stream)
+        torch.cuda.synchronize()
+        rows = rng.choice(ne, size=64, replace=False)
+        err = rel(yd.cpu().numpy()[:, rows], X @ G[rows].T)
+        print(f"block {blk}: sampled rows match, 256-column product rel {err:.2e} (64 sampled rows)")
+        assert err < 1e-12
+        del G
+    Gp = B.bem_block_export(ctx, op, B.BEM_BLOCK_LPHI_INT, nt, nt)
+    for t in tris:
+        assert np.abs(Gp[t] - Lp[t]).max() / np.abs(Lp[t]).max() < 1e-12
     B.bem_release(ctx, op)
     B.bem_destroy(ctx)

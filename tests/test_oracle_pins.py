@@ -247,3 +247,13 @@ def test_gram_Ix_well_conditioned_under_refinement():
         assert np.all(np.diag(Ix) > 0)
         conds.append(np.linalg.cond(Ix))
     assert max(conds) < 10.0 and conds[2] < 1.5 * conds[0]
+
+
+def test_near_rows_equal_near_pairs():
+    xyz, tri = meshgen.cubed_sphere(4, (1.0, 0.6, 0.4))
+    topo = M.build_topology(meshgen.jitter(xyz, tri, 0.02, 3), tri)
+    full = O.near_pairs(topo)
+    rows = np.array([0, 17, 50, len(tri) - 1])
+    part = O.near_rows(topo, rows)
+    assert np.array_equal(part[rows], full[rows])
+    assert not np.delete(part, rows, axis=0).any()
