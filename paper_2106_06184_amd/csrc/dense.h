@@ -25,19 +25,24 @@ void scale_rows_cols(double2* A, int64_t ld, int64_t nr, int64_t nc, const doubl
 void col_maxabs(const double2* A, int64_t ld, int64_t r0, int64_t r1, int64_t c0, int64_t nc, double* out,
                 hipStream_t st);
 void row_maxabs(const double2* A, int64_t ld, int64_t r0, int64_t nr, int64_t nc, double* out, hipStream_t st);
+// Equilibration vectors on the device: v[i] = val (i < n); v[i] = |A_ii|^-1/2 for i in [i0, i1)
+// (1 where that is not finite); out1[i] = out2[i] = 1 / in[i] (1 where not finite), i < n.
+void fill_vec(double* v, int64_t n, double val, hipStream_t st);
+void jacobi_vec(const double2* A, int64_t ld, int64_t i0, int64_t i1, double* v, hipStream_t st);
+void recip_vec(const double* in, int64_t n, double* out1, double* out2, hipStream_t st);
 
 // Dense M_eq of one object (eq. AEFIEeqvdis) from its diagonal blocks of L^A_l and L^phi_l;
-// tp/tm are the object's edges' triangles in object-local numbering; mu = mu_l,
+// tp/tm are the object's edges' triangles (device), toff its first triangle; mu = mu_l,
 // meps = -1/eps_l, k02 = k0^2.
-void build_meq(const double2* LA, int64_t lda, const double2* Lp, int64_t ldp, const int32_t* tp_local,
-               const int32_t* tm_local, int64_t ne, int64_t nt, double2 mu, double2 meps, double k02, double2* M,
-               int64_t ldm, hipStream_t st);
+void build_meq(const double2* LA, int64_t lda, const double2* Lp, int64_t ldp, const int32_t* tp, const int32_t* tm,
+               int32_t toff, int64_t ne, int64_t nt, double2 mu, double2 meps, double k02, double2* M, int64_t ldm,
+               hipStream_t st);
 
 // Charge-eliminated M_eq of one object: S = mu L^A_l + c D^T L^phi_l D (ne x ne), with
 // c = -1/(eps_l k0^2).  Since the charges of D u sum to zero per object, M_eq [u; w] = [r; 0]
 // is equivalent to S u = r, w = k0^-2 F D u.
-void build_s(const double2* LA, int64_t lda, const double2* Lp, int64_t ldp, const int32_t* tp_local,
-             const int32_t* tm_local, int64_t ne, double2 mu, double2 c, double2* S, int64_t lds, hipStream_t st);
+void build_s(const double2* LA, int64_t lda, const double2* Lp, int64_t ldp, const int32_t* tp, const int32_t* tm,
+             int32_t toff, int64_t ne, double2 mu, double2 c, double2* S, int64_t lds, hipStream_t st);
 
 // Dense S (nq x nq) = diag * I + G B for a sparse G (CSR over the nq kept charges, columns =
 // object-local triangles, the last one being the eliminated charge): (G B)[q][c] = G[q][c] -

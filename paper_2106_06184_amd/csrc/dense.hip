@@ -351,8 +351,8 @@ __global__ void __launch_bounds__(256) k_gj_write(double2* __restrict__ A, int64
 //  M[ne+q][n]   = (F D)[q][n] = +1 if T+(n) = q, -1 if T-(n) = q
 //  M[ne+q][ne+q'] = -k0^2 delta
 __global__ void k_build_meq(const double2* __restrict__ LA, int64_t lda, const double2* __restrict__ Lp, int64_t ldp,
-                            const int32_t* __restrict__ tp, const int32_t* __restrict__ tm, int64_t ne, int64_t nt,
-                            double2 mu, double2 meps, double k02, double2* __restrict__ M, int64_t ldm) {
+                            const int32_t* __restrict__ tp, const int32_t* __restrict__ tm, int32_t toff, int64_t ne,
+                            int64_t nt, double2 mu, double2 meps, double k02, double2* __restrict__ M, int64_t ldm) {
   const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const int64_t r = blockIdx.y;
   const int64_t nq = nt - 1, N = ne + nq;
@@ -363,16 +363,17 @@ __global__ void k_build_meq(const double2* __restrict__ LA, int64_t lda, const d
       v = cm(mu, LA[r * lda + c]);
     } else {
       const int64_t q = c - ne, last = nt - 1;
-      const double2 a = Lp[int64_t(tp[r]) * ldp + q], b = Lp[int64_t(tp[r]) * ldp + last];
-      const double2 d = Lp[int64_t(tm[r]) * ldp + q], e = Lp[int64_t(tm[r]) * ldp + last];
+      const int64_t tpr = tp[r] - toff, tmr = tm[r] - toff;
+      const double2 a = Lp[tpr * ldp + q], b = Lp[tpr * ldp + last];
+      const double2 d = Lp[tmr * ldp + q], e = Lp[tmr * ldp + last];
       const double2 diff = make_double2((a.x - b.x) - (d.x - e.x), (a.y - b.y) - (d.y - e.y));
       v = cm(meps, diff);
     }
   } else {
     const int64_t q = r - ne;
     if (c < ne) {
-      if (tp[c] == q) v.x += 1.0;
-      if (tm[c] == q) v.x -= 1.0;
+      if (tp[c] - toff == q) v.x += 1.0;
+      if (tm[c] - toff == q) v.x -= 1.0;
     } else if (c - ne == q) {
       v.x = -k02;
     }
@@ -383,14 +384,14 @@ __global__ void k_build_meq(const double2* __restrict__ LA, int64_t lda, const d
 // Charge-eliminated equivalent-configuration matrix (eq. AEFIEeqvdis with w = k0^-2 F D u
 // substituted): S = mu L^A_l + c D^T L^phi_l D, c = -1/(eps_l k0^2), object-local T+/T-.
 __global__ void k_build_s(const double2* __restrict__ LA, int64_t lda, const double2* __restrict__ Lp, int64_t ldp,
-                          const int32_t* __restrict__ tp, const int32_t* __restrict__ tm, int64_t ne, double2 mu,
-                          double2 c, double2* __restrict__ S, int64_t lds) {
+                          const int32_t* __restrict__ tp, const int32_t* __restrict__ tm, int32_t toff, int64_t ne,
+                          double2 mu, double2 c, double2* __restrict__ S, int64_t lds) {
   const int64_t col = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (col >= ne) return;
-  const int64_t cp = tp[col], cm_ = tm[col];
+  const int64_t cp = tp[col] - toff, cm_ = tm[col] - toff;
   for (int64_t r = blockIdx.y; r < ne; r += gridDim.y) {
-    const double2* rp = Lp + int64_t(tp[r]) * ldp;
-    const double2* rm = Lp + int64_t(tm[r]) * ldp;
+    const double2* rp = Lp + int64_t(tp[r] - toff) * ldp;
+    const double2* rm = Lp + int64_t(tm[r] - toff) * ldp;
     const double2 pp = rp[cp], pm = rp[cm_], mp = rm[cp], mm = rm[cm_];
     const double2 d = make_double2((pp.x - pm.x) - (mp.x - mm.x), (pp.y - pm.y) - (mp.y - mm.y));
     const double2 a = cm(mu, LA[r * lda + col]), b = cm(c, d);
@@ -563,6 +564,46 @@ __global__ void __launch_bounds__(256) k_row_maxabs(const double2* __restrict__ 
 }
 }  // namespace dev
 
+namespace dev {
+__global__ void k_fill_vec(double* v, int64_t n, double val) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) v[i] = val;
+}
+__global__ void k_jacobi_vec(const double2* __restrict__ A, int64_t ld, int64_t i0, int64_t i1, double* v) {
+  const int64_t i = i0 + int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= i1) return;
+  const double2 d = A[i * ld + i];
+  const double s = 1.0 / sqrt(sqrt(d.x * d.x + d.y * d.y));
+  v[i] = isfinite(s) && s > 0 ? s : 1.0;
+}
+__global__ void k_recip_vec(const double* __restrict__ in, int64_t n, double* out1, double* out2) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double s = 1.0 / in[i];
+  const double r = isfinite(s) && s > 0 ? s : 1.0;
+  out1[i] = r;
+  out2[i] = r;
+}
+}  // namespace dev
+
+void fill_vec(double* v, int64_t n, double val, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(dev::k_fill_vec, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, v, n, val);
+  BEM_HIP(hipGetLastError());
+}
+
+void jacobi_vec(const double2* A, int64_t ld, int64_t i0, int64_t i1, double* v, hipStream_t st) {
+  if (i1 <= i0) return;
+  hipLaunchKernelGGL(dev::k_jacobi_vec, dim3(unsigned((i1 - i0 + 255) / 256)), dim3(256), 0, st, A, ld, i0, i1, v);
+  BEM_HIP(hipGetLastError());
+}
+
+void recip_vec(const double* in, int64_t n, double* out1, double* out2, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(dev::k_recip_vec, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, in, n, out1, out2);
+  BEM_HIP(hipGetLastError());
+}
+
 void scale_rows_cols(double2* A, int64_t ld, int64_t nr, int64_t nc, const double* rs, const double* cs,
                      hipStream_t st) {
   if (nr <= 0 || nc <= 0) return;
@@ -585,20 +626,20 @@ void row_maxabs(const double2* A, int64_t ld, int64_t r0, int64_t nr, int64_t nc
   BEM_HIP(hipGetLastError());
 }
 
-void build_meq(const double2* LA, int64_t lda, const double2* Lp, int64_t ldp, const int32_t* tp_local,
-               const int32_t* tm_local, int64_t ne, int64_t nt, double2 mu, double2 meps, double k02, double2* M,
-               int64_t ldm, hipStream_t st) {
+void build_meq(const double2* LA, int64_t lda, const double2* Lp, int64_t ldp, const int32_t* tp, const int32_t* tm,
+               int32_t toff, int64_t ne, int64_t nt, double2 mu, double2 meps, double k02, double2* M, int64_t ldm,
+               hipStream_t st) {
   const int64_t N = ne + nt - 1;
   hipLaunchKernelGGL(dev::k_build_meq, dim3(unsigned((N + 255) / 256), unsigned(N)), dim3(256), 0, st, LA, lda, Lp, ldp,
-                     tp_local, tm_local, ne, nt, mu, meps, k02, M, ldm);
+                     tp, tm, toff, ne, nt, mu, meps, k02, M, ldm);
   BEM_HIP(hipGetLastError());
 }
 
-void build_s(const double2* LA, int64_t lda, const double2* Lp, int64_t ldp, const int32_t* tp_local,
-             const int32_t* tm_local, int64_t ne, double2 mu, double2 c, double2* S, int64_t lds, hipStream_t st) {
+void build_s(const double2* LA, int64_t lda, const double2* Lp, int64_t ldp, const int32_t* tp, const int32_t* tm,
+             int32_t toff, int64_t ne, double2 mu, double2 c, double2* S, int64_t lds, hipStream_t st) {
   if (ne <= 0) return;
   hipLaunchKernelGGL(dev::k_build_s, dim3(unsigned((ne + 255) / 256), unsigned(std::min<int64_t>(ne, 32768))),
-                     dim3(256), 0, st, LA, lda, Lp, ldp, tp_local, tm_local, ne, mu, c, S, lds);
+                     dim3(256), 0, st, LA, lda, Lp, ldp, tp, tm, toff, ne, mu, c, S, lds);
   BEM_HIP(hipGetLastError());
 }
 

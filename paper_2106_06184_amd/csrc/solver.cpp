@@ -21,7 +21,8 @@
 
 namespace bem {
 
-void build_inner_and_precond(OpObj& op, const std::vector<double>& ixdiag, hipStream_t st);
+// part 1: nested-solve inverses; part 2: block preconditioners.
+void build_inner_and_precond(OpObj& op, const std::vector<double>& ixdiag, hipStream_t st, int part);
 
 namespace {
 
@@ -479,6 +480,25 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
   int32_t* d_near_idx = op.mem.upload(m.near_idx);
 
   mark("cell tables");
+  // ---- nested-solve mode
+  int64_t max_neq = 0;
+  for (int64_t o = 0; o < m.nobj; ++o)
+    max_neq = std::max(max_neq, (m.obj_edge[o + 1] - m.obj_edge[o]) + (m.obj_tri[o + 1] - m.obj_tri[o]) - 1);
+  int64_t max_ne = 0;
+  for (int64_t o = 0; o < m.nobj; ++o) max_ne = std::max(max_ne, m.obj_edge[o + 1] - m.obj_edge[o]);
+  const double hmax = *std::max_element(m.hmax.begin(), m.hmax.end());
+  op.inner_mode = eaefie ? kInnerNone : prob.inner_mode;
+  if (op.inner_mode == BEM_INNER_AUTO) {
+    // charge elimination while the elements are not electrically tiny (its k0^-2 term sets the
+    // conditioning), the augmented inverse below that, nested GMRES for very large objects
+    const double kh = std::abs(op.kbg) * hmax;
+    if (kh >= kSchurMinKh && max_ne <= 32768) op.inner_mode = BEM_INNER_SCHUR;
+    else if (max_neq <= 16384) op.inner_mode = BEM_INNER_DIRECT;
+    else op.inner_mode = BEM_INNER_GMRES;
+  }
+  if (op.inner_mode != BEM_INNER_DIRECT && op.inner_mode != BEM_INNER_GMRES && op.inner_mode != BEM_INNER_SCHUR &&
+      !(eaefie && op.inner_mode == kInnerNone))
+    throw Error(BEM_E_INVALID, "unknown inner_mode");
   // ---- dense blocks
   const bool f32 = op.precision == BEM_MIXED;
   op.LA_int.clear();
@@ -540,6 +560,16 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
     for (int64_t t = s0; t < s0 + ns; ++t) h = std::max(h, m.hmax[t]);
     return subdiv_level_host(k.real(), h) > 0 ? 1 : 0;
   };
+  // background L^A, L^phi (the coupling blocks; the nested-solve inverses are formed from them)
+  {
+    int32_t* pt = up32(na_t);
+    int32_t* ps = up32(na_s);
+    FillLArgs la{op.geo, nt, 0, nt, 0, nt, tchunk, op.kbg.real(), op.kbg.imag(), H, 3 * nt, op.Lphi_bg.d64,
+                 op.Lphi_bg.ld};
+    la.sub = needs_sub(op.kbg, 0, nt);
+    launch_fill_L(la, pt, ps, int64_t(na_t.size()), st);
+    launch_gather_LA(H, 3 * nt, d_hp, d_hm, 0, m.ne, op.LA_bg.d64, op.LA_bg.ld, st);
+  }
   for (int64_t o = 0; o < m.nobj; ++o) {
     const int64_t t0 = m.obj_tri[o], nto = m.obj_tri[o + 1] - t0;
     const int64_t e0 = m.obj_edge[o], neo = m.obj_edge[o + 1] - e0;
@@ -589,15 +619,6 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
                       st);
     }
   }
-  {
-    int32_t* pt = up32(na_t);
-    int32_t* ps = up32(na_s);
-    FillLArgs la{op.geo, nt, 0, nt, 0, nt, tchunk, op.kbg.real(), op.kbg.imag(), H, 3 * nt, op.Lphi_bg.d64,
-                 op.Lphi_bg.ld};
-    la.sub = needs_sub(op.kbg, 0, nt);
-    launch_fill_L(la, pt, ps, int64_t(na_t.size()), st);
-    launch_gather_LA(H, 3 * nt, d_hp, d_hm, 0, m.ne, op.LA_bg.d64, op.LA_bg.ld, st);
-  }
   if (f32) {
     for (int64_t o = 0; o < m.nobj; ++o) {
       if (op.mat_rep[o] == o) {
@@ -638,27 +659,9 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
     op.mem.release(p);
 
   mark("fill");
-  // ---- nested-solve mode and block preconditioners
-  int64_t max_neq = 0;
-  for (int64_t o = 0; o < m.nobj; ++o)
-    max_neq = std::max(max_neq, (m.obj_edge[o + 1] - m.obj_edge[o]) + (m.obj_tri[o + 1] - m.obj_tri[o]) - 1);
-  int64_t max_ne = 0;
-  for (int64_t o = 0; o < m.nobj; ++o) max_ne = std::max(max_ne, m.obj_edge[o + 1] - m.obj_edge[o]);
-  const double hmax = *std::max_element(m.hmax.begin(), m.hmax.end());
-  op.inner_mode = eaefie ? kInnerNone : prob.inner_mode;
-  if (op.inner_mode == BEM_INNER_AUTO) {
-    // charge elimination while the elements are not electrically tiny (its k0^-2 term sets the
-    // conditioning), the augmented inverse below that, nested GMRES for very large objects
-    const double kh = std::abs(op.kbg) * hmax;
-    if (kh >= kSchurMinKh && max_ne <= 32768) op.inner_mode = BEM_INNER_SCHUR;
-    else if (max_neq <= 16384) op.inner_mode = BEM_INNER_DIRECT;
-    else op.inner_mode = BEM_INNER_GMRES;
-  }
-  if (op.inner_mode != BEM_INNER_DIRECT && op.inner_mode != BEM_INNER_GMRES && op.inner_mode != BEM_INNER_SCHUR &&
-      !(eaefie && op.inner_mode == kInnerNone))
-    throw Error(BEM_E_INVALID, "unknown inner_mode");
   op.precond = prob.precond != 0;
-  build_inner_and_precond(op, ixdiag, st);
+  build_inner_and_precond(op, ixdiag, st, 1);
+  build_inner_and_precond(op, ixdiag, st, 2);
 
   mark("inner+precond");
   // ---- work vectors and Krylov spaces
@@ -674,7 +677,7 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
 // Direct inner solve (inverse of M_eq per object) and the block preconditioners: the per-edge
 // 2x2 inverses and the charge Schur complements of eq. pcext (final system) and of its
 // equivalent-configuration counterpart, both inverted on the device.
-void build_inner_and_precond(OpObj& op, const std::vector<double>& ixdiag, hipStream_t st) {
+void build_inner_and_precond(OpObj& op, const std::vector<double>& ixdiag, hipStream_t st, int part) {
   const Mesh& m = *op.m;
   auto tmark = std::chrono::steady_clock::now();
   auto mark = [&](const char* what) {
@@ -713,64 +716,41 @@ void build_inner_and_precond(OpObj& op, const std::vector<double>& ixdiag, hipSt
   // back into M^-1 = diag(c) M'^-1 diag(r).  The scales change only the rounding: the blocks of
   // M_eq differ by many orders of magnitude on graded meshes of small objects (|L^A| ~ h,
   // |L^phi| ~ 1/h), and Gauss-Jordan without pivoting needs them balanced.
+  // (on the device, without host round trips)
   double* rdev = reinterpret_cast<double*>(talloc(size_t(nbuf)));
   double* cdev = reinterpret_cast<double*>(talloc(size_t(nbuf)));
-  auto put = [&](double* d, const std::vector<double>& v) {
-    BEM_HIP(hipMemcpyAsync(d, v.data(), sizeof(double) * v.size(), hipMemcpyHostToDevice, st));
-    BEM_HIP(hipStreamSynchronize(st));
-  };
-  auto get = [&](const double* d, size_t n) {
-    std::vector<double> v(n);
-    BEM_HIP(hipMemcpyAsync(v.data(), d, sizeof(double) * n, hipMemcpyDeviceToHost, st));
-    BEM_HIP(hipStreamSynchronize(st));
-    return v;
-  };
-  auto inv_scale = [](double x) { return x > 0 && std::isfinite(x) ? 1.0 / x : 1.0; };
-  auto invert_equilibrated = [&](Dense& M, int64_t n, const std::vector<double>& r, const std::vector<double>& c) {
-    put(rdev, r);
-    put(cdev, c);
-    scale_rows_cols(M.d64, M.ld, n, n, rdev, cdev, st);
-    dense_invert(M.d64, n, M.ld, ds, st);
-    scale_rows_cols(M.d64, M.ld, n, n, cdev, rdev, st);
-    BEM_HIP(hipStreamSynchronize(st));
-  };
+  double* udev = reinterpret_cast<double*>(talloc(size_t(nbuf)));
+  double* odev = reinterpret_cast<double*>(talloc(size_t(nbuf)));
+  double* tdev = reinterpret_cast<double*>(talloc(size_t(nbuf)));
   // symmetric Jacobi scaling |diag|^-1/2 (S and the charge Schur complements)
   auto invert_jacobi = [&](Dense& M, int64_t n) {
-    const std::vector<double2> d = diag_of(M);
-    std::vector<double> s(n);
-    for (int64_t i = 0; i < n; ++i) s[i] = inv_scale(std::sqrt(std::abs(cdv(d[i]))));
-    invert_equilibrated(M, n, s, s);
+    jacobi_vec(M.d64, M.ld, 0, n, rdev, st);
+    scale_rows_cols(M.d64, M.ld, n, n, rdev, rdev, st);
+    dense_invert(M.d64, n, M.ld, ds, st);
+    scale_rows_cols(M.d64, M.ld, n, n, rdev, rdev, st);
   };
   // M_eq: Jacobi on the edge block, then the charge columns and rows normalised by their
-  // largest entries (those of the coupling blocks)
+  // largest entries (those of the coupling blocks).  r, c accumulate the total row and column
+  // scales; u holds the partial scale of one step, o is all ones.
   auto invert_meq = [&](Dense& M, int64_t neo, int64_t n) {
-    const std::vector<double2> d = diag_of(M);
-    std::vector<double> r(n, 1.0), c(n, 1.0), one(n, 1.0);
-    for (int64_t i = 0; i < neo; ++i) r[i] = c[i] = inv_scale(std::sqrt(std::abs(cdv(d[i]))));
-    put(rdev, r);
-    scale_rows_cols(M.d64, M.ld, n, n, rdev, rdev, st);
-    col_maxabs(M.d64, M.ld, 0, neo, neo, n - neo, cdev, st);
-    std::vector<double> cq = get(cdev, size_t(n - neo));
-    std::vector<double> cs(one);
-    for (int64_t q = 0; q < n - neo; ++q) cs[neo + q] = c[neo + q] = inv_scale(cq[q]);
-    put(rdev, one);
-    put(cdev, cs);
+    const int64_t nq = n - neo;
+    fill_vec(rdev, n, 1.0, st);
+    fill_vec(odev, n, 1.0, st);
+    jacobi_vec(M.d64, M.ld, 0, neo, rdev, st);
+    BEM_HIP(hipMemcpyAsync(cdev, rdev, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
     scale_rows_cols(M.d64, M.ld, n, n, rdev, cdev, st);
-    row_maxabs(M.d64, M.ld, neo, n - neo, n, rdev, st);
-    std::vector<double> rq = get(rdev, size_t(n - neo));
-    std::vector<double> rs(one);
-    for (int64_t q = 0; q < n - neo; ++q) rs[neo + q] = r[neo + q] = inv_scale(rq[q]);
-    put(rdev, rs);
-    put(cdev, one);
-    scale_rows_cols(M.d64, M.ld, n, n, rdev, cdev, st);
+    col_maxabs(M.d64, M.ld, 0, neo, neo, nq, tdev, st);
+    fill_vec(udev, neo, 1.0, st);
+    recip_vec(tdev, nq, cdev + neo, udev + neo, st);
+    scale_rows_cols(M.d64, M.ld, n, n, odev, udev, st);
+    row_maxabs(M.d64, M.ld, neo, nq, n, tdev, st);
+    recip_vec(tdev, nq, rdev + neo, udev + neo, st);
+    scale_rows_cols(M.d64, M.ld, n, n, udev, odev, st);
     dense_invert(M.d64, n, M.ld, ds, st);
-    put(rdev, r);
-    put(cdev, c);
     scale_rows_cols(M.d64, M.ld, n, n, cdev, rdev, st);
-    BEM_HIP(hipStreamSynchronize(st));
   };
-  op.Minv.clear();
-  if (op.inner_mode == BEM_INNER_DIRECT) {
+  if (part == 1) op.Minv.clear();
+  if (part == 1 && op.inner_mode == BEM_INNER_DIRECT) {
     for (int64_t o = 0; o < m.nobj; ++o) {
       if (op.geo_rep[o] != o) {  // a translated copy shares the inverse
         const Dense shared = op.Minv[op.geo_rep[o]];
@@ -780,25 +760,16 @@ void build_inner_and_precond(OpObj& op, const std::vector<double>& ixdiag, hipSt
       const int64_t t0 = m.obj_tri[o], nto = m.obj_tri[o + 1] - t0;
       const int64_t e0 = m.obj_edge[o], neo = m.obj_edge[o + 1] - e0;
       const int64_t n = neo + nto - 1;
-      std::vector<int32_t> tpl(neo), tml(neo);
-      for (int64_t k = 0; k < neo; ++k) {
-        tpl[k] = int32_t(m.tp[e0 + k] - t0);
-        tml[k] = int32_t(m.tm[e0 + k] - t0);
-      }
-      int32_t* dtp = op.mem.upload(tpl);
-      int32_t* dtm = op.mem.upload(tml);
       Dense M = alloc_dense(op.mem, n, n, f32);
       build_meq(op.LA_bg.d64 + e0 * op.LA_bg.ld + e0, op.LA_bg.ld, op.Lphi_bg.d64 + t0 * op.Lphi_bg.ld + t0,
-                op.Lphi_bg.ld, dtp, dtm, neo, nto, c2(op.mu_bg), c2(-1.0 / op.eps_bg), op.k0 * op.k0, M.d64, M.ld, st);
+                op.Lphi_bg.ld, op.tp + e0, op.tm + e0, int32_t(t0), neo, nto, c2(op.mu_bg), c2(-1.0 / op.eps_bg),
+                op.k0 * op.k0, M.d64, M.ld, st);
       invert_meq(M, neo, n);
       to_f32(M, st);
-      BEM_HIP(hipStreamSynchronize(st));
-      op.mem.release(dtp);
-      op.mem.release(dtm);
       op.Minv.push_back(M);
     }
   }
-  if (op.inner_mode == BEM_INNER_SCHUR) {
+  if (part == 1 && op.inner_mode == BEM_INNER_SCHUR) {
     for (int64_t o = 0; o < m.nobj; ++o) {
       if (op.geo_rep[o] != o) {
         const Dense shared = op.Minv[op.geo_rep[o]];
@@ -807,25 +778,20 @@ void build_inner_and_precond(OpObj& op, const std::vector<double>& ixdiag, hipSt
       }
       const int64_t t0 = m.obj_tri[o];
       const int64_t e0 = m.obj_edge[o], neo = m.obj_edge[o + 1] - e0;
-      std::vector<int32_t> tpl(neo), tml(neo);
-      for (int64_t k = 0; k < neo; ++k) {
-        tpl[k] = int32_t(m.tp[e0 + k] - t0);
-        tml[k] = int32_t(m.tm[e0 + k] - t0);
-      }
-      int32_t* dtp = op.mem.upload(tpl);
-      int32_t* dtm = op.mem.upload(tml);
       Dense S = alloc_dense(op.mem, neo, neo, f32);
       build_s(op.LA_bg.d64 + e0 * op.LA_bg.ld + e0, op.LA_bg.ld, op.Lphi_bg.d64 + t0 * op.Lphi_bg.ld + t0,
-              op.Lphi_bg.ld, dtp, dtm, neo, c2(op.mu_bg), c2(-1.0 / (op.eps_bg * op.k0 * op.k0)), S.d64, S.ld, st);
+              op.Lphi_bg.ld, op.tp + e0, op.tm + e0, int32_t(t0), neo, c2(op.mu_bg),
+              c2(-1.0 / (op.eps_bg * op.k0 * op.k0)), S.d64, S.ld, st);
       invert_jacobi(S, neo);
       to_f32(S, st);
-      BEM_HIP(hipStreamSynchronize(st));
-      op.mem.release(dtp);
-      op.mem.release(dtm);
       op.Minv.push_back(S);
     }
   }
   mark("nested inverses");
+  if (part == 1) {
+    for (void* p : tmp) op.mem.release(p);
+    return;
+  }
   op.SigP.clear();
   op.SigEq.clear();
   if (!op.precond) {
