@@ -1,10 +1,11 @@
 // Dense complex products, sparse glue and Krylov kernels (gfx950).
 //
 // The single-excitation products are HBM-bound (one complex MAC per matrix element read):
-// every wave owns RPW rows of one dense block, its 64 lanes stream the rows with 16-byte loads
-// (one float64 complex, or two float32 complex per load), the x chunk is loaded once per wave
-// and reused for all RPW rows, and the row sums are reduced with cross-lane shuffles.  Several
-// independent products (different matrices and vectors) share one launch.
+// every block owns 8 rows of one dense block and its 4 waves split the columns, the 64 lanes of
+// a wave streaming the rows with 16-byte loads (one float64 complex, or two float32 complex per
+// load); each x chunk is loaded once per wave and reused for the 8 rows, row sums are reduced
+// with cross-lane shuffles and then across the waves in a fixed order.  Several independent
+// products (different matrices and vectors) share one launch.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -16,6 +17,11 @@ namespace bem {
 namespace dev {
 
 constexpr int kWave = 64;
+// A block of the grouped GEMV owns kRowsPerBlock rows of one matrix; its kWavesPerBlock waves
+// split the columns (every wave reads all the rows over a quarter of the columns), so that the
+// grid has enough waves for the HBM latency and x is read once per block from L2.
+constexpr int kWavesPerBlock = 4;
+constexpr int kRowsPerBlock = 8;
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -34,38 +40,45 @@ typedef double dx2 __attribute__((ext_vector_type(2)));
 // matrix is streamed once per product: non-temporal loads keep x resident in L2).
 template <int RPW>
 __device__ __forceinline__ void rows_f64(const double2* __restrict__ A, int64_t lda, int64_t rows, int64_t cols,
-                                         const double2* __restrict__ x, int64_t row0, int lane, double2 alpha,
-                                         double* yr, double* yi) {
+                                         const double2* __restrict__ x, int64_t row0, int lane, int wv,
+                                         double2 alpha, double* yr, double* yi) {
   double ar[RPW], ai[RPW];
 #pragma unroll
   for (int r = 0; r < RPW; ++r) ar[r] = ai[r] = 0.0;
   const double2* rowp[RPW];
 #pragma unroll
   for (int r = 0; r < RPW; ++r) rowp[r] = A + min(row0 + r, rows - 1) * lda;
-  int64_t c = lane;
-  for (; c + kWave < cols; c += 2 * kWave) {
-    const double2 x0 = x[c], x1 = x[c + kWave];
-    double2 a0[RPW], a1[RPW];
+  // chunks of 2 kWave columns, dealt round-robin to the waves of the block
+  for (int64_t cs = int64_t(wv) * 2 * kWave; cs < cols; cs += int64_t(kWavesPerBlock) * 2 * kWave) {
+    const int64_t c = cs + lane;
+    if (cs + 2 * kWave <= cols) {
+      const double2 x0 = x[c], x1 = x[c + kWave];
+      double2 a0[RPW], a1[RPW];
 #pragma unroll
-    for (int r = 0; r < RPW; ++r) {
-      const dx2 u = __builtin_nontemporal_load(reinterpret_cast<const dx2*>(rowp[r] + c));
-      const dx2 w = __builtin_nontemporal_load(reinterpret_cast<const dx2*>(rowp[r] + c + kWave));
-      a0[r] = make_double2(u[0], u[1]);
-      a1[r] = make_double2(w[0], w[1]);
-    }
+      for (int r = 0; r < RPW; ++r) {
+        const dx2 u = __builtin_nontemporal_load(reinterpret_cast<const dx2*>(rowp[r] + c));
+        const dx2 w = __builtin_nontemporal_load(reinterpret_cast<const dx2*>(rowp[r] + c + kWave));
+        a0[r] = make_double2(u[0], u[1]);
+        a1[r] = make_double2(w[0], w[1]);
+      }
 #pragma unroll
-    for (int r = 0; r < RPW; ++r) {
-      ar[r] += a0[r].x * x0.x - a0[r].y * x0.y + a1[r].x * x1.x - a1[r].y * x1.y;
-      ai[r] += a0[r].x * x0.y + a0[r].y * x0.x + a1[r].x * x1.y + a1[r].y * x1.x;
-    }
-  }
-  for (; c < cols; c += kWave) {
-    const double2 x0 = x[c];
+      for (int r = 0; r < RPW; ++r) {
+        ar[r] += a0[r].x * x0.x - a0[r].y * x0.y + a1[r].x * x1.x - a1[r].y * x1.y;
+        ai[r] += a0[r].x * x0.y + a0[r].y * x0.x + a1[r].x * x1.y + a1[r].y * x1.x;
+      }
+    } else {
+      for (int h = 0; h < 2; ++h) {
+        const int64_t cc = c + h * kWave;
+        if (cc < cols) {
+          const double2 x0 = x[cc];
 #pragma unroll
-    for (int r = 0; r < RPW; ++r) {
-      const double2 a0 = rowp[r][c];
-      ar[r] += a0.x * x0.x - a0.y * x0.y;
-      ai[r] += a0.x * x0.y + a0.y * x0.x;
+          for (int r = 0; r < RPW; ++r) {
+            const double2 a0 = rowp[r][cc];
+            ar[r] += a0.x * x0.x - a0.y * x0.y;
+            ai[r] += a0.x * x0.y + a0.y * x0.x;
+          }
+        }
+      }
     }
   }
 #pragma unroll
@@ -79,57 +92,58 @@ __device__ __forceinline__ void rows_f64(const double2* __restrict__ A, int64_t 
 typedef float fx4 __attribute__((ext_vector_type(4)));
 
 // float32 storage and accumulation; each lane reads two consecutive complex entries per
-// 16-byte non-temporal load (two 8-byte loads when the rows are not 16-byte aligned).
+// 16-byte non-temporal load (two 8-byte loads when the rows are not 16-byte aligned); chunks of
+// 4 kWave columns are dealt round-robin to the waves of the block.
 template <int RPW, bool ALIGNED>
 __device__ __forceinline__ void rows_f32(const float2* __restrict__ A, int64_t lda, int64_t rows, int64_t cols,
-                                         const double2* __restrict__ x, int64_t row0, int lane, double2 alpha,
-                                         double* yr, double* yi) {
+                                         const double2* __restrict__ x, int64_t row0, int lane, int wv,
+                                         double2 alpha, double* yr, double* yi) {
   float ar[RPW], ai[RPW];
 #pragma unroll
   for (int r = 0; r < RPW; ++r) ar[r] = ai[r] = 0.0f;
   const float2* rowp[RPW];
 #pragma unroll
   for (int r = 0; r < RPW; ++r) rowp[r] = A + min(row0 + r, rows - 1) * lda;
-  int64_t c = 2 * lane;
-  const int64_t full = cols & ~int64_t(1);
-  for (; c + 2 * kWave < full; c += 4 * kWave) {
-    const double2 xa = x[c], xb = x[c + 1], xc = x[c + 2 * kWave], xd = x[c + 2 * kWave + 1];
-    const float x0r = float(xa.x), x0i = float(xa.y), x1r = float(xb.x), x1i = float(xb.y);
-    const float x2r = float(xc.x), x2i = float(xc.y), x3r = float(xd.x), x3i = float(xd.y);
-    float4 a0[RPW], a1[RPW];
+  for (int64_t cs = int64_t(wv) * 4 * kWave; cs < cols; cs += int64_t(kWavesPerBlock) * 4 * kWave) {
+    const int64_t c = cs + 2 * lane;
+    if (cs + 4 * kWave <= cols) {
+      const double2 xa = x[c], xb = x[c + 1], xc = x[c + 2 * kWave], xd = x[c + 2 * kWave + 1];
+      const float x0r = float(xa.x), x0i = float(xa.y), x1r = float(xb.x), x1i = float(xb.y);
+      const float x2r = float(xc.x), x2i = float(xc.y), x3r = float(xd.x), x3i = float(xd.y);
+      float4 a0[RPW], a1[RPW];
 #pragma unroll
-    for (int r = 0; r < RPW; ++r) {
-      if (ALIGNED) {
-        const fx4 u = __builtin_nontemporal_load(reinterpret_cast<const fx4*>(rowp[r] + c));
-        const fx4 w = __builtin_nontemporal_load(reinterpret_cast<const fx4*>(rowp[r] + c + 2 * kWave));
-        a0[r] = make_float4(u[0], u[1], u[2], u[3]);
-        a1[r] = make_float4(w[0], w[1], w[2], w[3]);
-      } else {
-        const float2 p0 = rowp[r][c], p1 = rowp[r][c + 1];
-        const float2 p2 = rowp[r][c + 2 * kWave], p3 = rowp[r][c + 2 * kWave + 1];
-        a0[r] = make_float4(p0.x, p0.y, p1.x, p1.y);
-        a1[r] = make_float4(p2.x, p2.y, p3.x, p3.y);
+      for (int r = 0; r < RPW; ++r) {
+        if (ALIGNED) {
+          const fx4 u = __builtin_nontemporal_load(reinterpret_cast<const fx4*>(rowp[r] + c));
+          const fx4 w = __builtin_nontemporal_load(reinterpret_cast<const fx4*>(rowp[r] + c + 2 * kWave));
+          a0[r] = make_float4(u[0], u[1], u[2], u[3]);
+          a1[r] = make_float4(w[0], w[1], w[2], w[3]);
+        } else {
+          const float2 p0 = rowp[r][c], p1 = rowp[r][c + 1];
+          const float2 p2 = rowp[r][c + 2 * kWave], p3 = rowp[r][c + 2 * kWave + 1];
+          a0[r] = make_float4(p0.x, p0.y, p1.x, p1.y);
+          a1[r] = make_float4(p2.x, p2.y, p3.x, p3.y);
+        }
       }
-    }
 #pragma unroll
-    for (int r = 0; r < RPW; ++r) {
-      ar[r] += a0[r].x * x0r - a0[r].y * x0i + a0[r].z * x1r - a0[r].w * x1i;
-      ai[r] += a0[r].x * x0i + a0[r].y * x0r + a0[r].z * x1i + a0[r].w * x1r;
-      ar[r] += a1[r].x * x2r - a1[r].y * x2i + a1[r].z * x3r - a1[r].w * x3i;
-      ai[r] += a1[r].x * x2i + a1[r].y * x2r + a1[r].z * x3i + a1[r].w * x3r;
-    }
-  }
-  for (; c < cols; c += 2 * kWave) {
+      for (int r = 0; r < RPW; ++r) {
+        ar[r] += a0[r].x * x0r - a0[r].y * x0i + a0[r].z * x1r - a0[r].w * x1i;
+        ai[r] += a0[r].x * x0i + a0[r].y * x0r + a0[r].z * x1i + a0[r].w * x1r;
+        ar[r] += a1[r].x * x2r - a1[r].y * x2i + a1[r].z * x3r - a1[r].w * x3i;
+        ai[r] += a1[r].x * x2i + a1[r].y * x2r + a1[r].z * x3i + a1[r].w * x3r;
+      }
+    } else {
+      for (int h = 0; h < 4; ++h) {
+        const int64_t cc = c + (h & 1) + (h >> 1) * 2 * kWave;
+        if (cc < cols) {
+          const double2 xv = x[cc];
+          const float xr = float(xv.x), xi = float(xv.y);
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      if (c + h < cols) {
-        const double2 xv = x[c + h];
-        const float xr = float(xv.x), xi = float(xv.y);
-#pragma unroll
-        for (int r = 0; r < RPW; ++r) {
-          const float2 a0 = rowp[r][c + h];
-          ar[r] += a0.x * xr - a0.y * xi;
-          ai[r] += a0.x * xi + a0.y * xr;
+          for (int r = 0; r < RPW; ++r) {
+            const float2 a0 = rowp[r][cc];
+            ar[r] += a0.x * xr - a0.y * xi;
+            ai[r] += a0.x * xi + a0.y * xr;
+          }
         }
       }
     }
@@ -142,9 +156,6 @@ __device__ __forceinline__ void rows_f32(const float2* __restrict__ A, int64_t l
   }
 }
 
-constexpr int kRPW = 4;          // rows per wave
-constexpr int kWavesPerBlock = 4;
-constexpr int kRowsPerBlock = kRPW * kWavesPerBlock;
 
 __global__ void __launch_bounds__(256) k_gemv_grouped(GemvPack pack) {
   const int64_t b = blockIdx.x;
@@ -152,39 +163,55 @@ __global__ void __launch_bounds__(256) k_gemv_grouped(GemvPack pack) {
   while (di + 1 < pack.n && pack.d[di + 1].tile0 <= b) ++di;
   const GemvDev& d = pack.d[di];
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  const int64_t row0 = (b - d.tile0) * kRowsPerBlock + int64_t(wave) * kRPW;
-  if (row0 >= d.rows) return;
-  double yr[kRPW], yi[kRPW];
+  const int64_t row0 = (b - d.tile0) * kRowsPerBlock;
+  constexpr int R = kRowsPerBlock;
+  double yr[R], yi[R];
 #pragma unroll
-  for (int r = 0; r < kRPW; ++r) yr[r] = yi[r] = 0.0;
+  for (int r = 0; r < R; ++r) yr[r] = yi[r] = 0.0;
   if (d.fp32) {
     const bool al1 = ((reinterpret_cast<uintptr_t>(d.A) | uintptr_t(d.lda * 8)) & 15) == 0;
     if (al1)
-      rows_f32<kRPW, true>(static_cast<const float2*>(d.A), d.lda, d.rows, d.cols, d.x, row0, lane, make_double2(d.ar, d.ai), yr, yi);
+      rows_f32<R, true>(static_cast<const float2*>(d.A), d.lda, d.rows, d.cols, d.x, row0, lane, wave,
+                        make_double2(d.ar, d.ai), yr, yi);
     else
-      rows_f32<kRPW, false>(static_cast<const float2*>(d.A), d.lda, d.rows, d.cols, d.x, row0, lane, make_double2(d.ar, d.ai), yr, yi);
+      rows_f32<R, false>(static_cast<const float2*>(d.A), d.lda, d.rows, d.cols, d.x, row0, lane, wave,
+                         make_double2(d.ar, d.ai), yr, yi);
     if (d.A2) {
       const bool al2 = ((reinterpret_cast<uintptr_t>(d.A2) | uintptr_t(d.lda2 * 8)) & 15) == 0;
       if (al2)
-        rows_f32<kRPW, true>(static_cast<const float2*>(d.A2), d.lda2, d.rows, d.cols, d.x2, row0, lane, make_double2(d.a2r, d.a2i),
-                             yr, yi);
+        rows_f32<R, true>(static_cast<const float2*>(d.A2), d.lda2, d.rows, d.cols, d.x2, row0, lane, wave,
+                          make_double2(d.a2r, d.a2i), yr, yi);
       else
-        rows_f32<kRPW, false>(static_cast<const float2*>(d.A2), d.lda2, d.rows, d.cols, d.x2, row0, lane, make_double2(d.a2r, d.a2i),
-                              yr, yi);
+        rows_f32<R, false>(static_cast<const float2*>(d.A2), d.lda2, d.rows, d.cols, d.x2, row0, lane, wave,
+                           make_double2(d.a2r, d.a2i), yr, yi);
     }
   } else {
-    rows_f64<kRPW>(static_cast<const double2*>(d.A), d.lda, d.rows, d.cols, d.x, row0, lane, make_double2(d.ar, d.ai), yr, yi);
+    rows_f64<R>(static_cast<const double2*>(d.A), d.lda, d.rows, d.cols, d.x, row0, lane, wave,
+                make_double2(d.ar, d.ai), yr, yi);
     if (d.A2)
-      rows_f64<kRPW>(static_cast<const double2*>(d.A2), d.lda2, d.rows, d.cols, d.x2, row0, lane, make_double2(d.a2r, d.a2i), yr, yi);
+      rows_f64<R>(static_cast<const double2*>(d.A2), d.lda2, d.rows, d.cols, d.x2, row0, lane, wave,
+                  make_double2(d.a2r, d.a2i), yr, yi);
   }
+  // the waves' partial row sums, added in wave order
+  __shared__ double red[kWavesPerBlock][R][2];
+  if (lane == 0) {
 #pragma unroll
-  for (int r = 0; r < kRPW; ++r) {
-    if (lane == r && row0 + r < d.rows) {
-      double2* y = d.y + row0 + r;
-      double vr = yr[r], vi = yi[r];
-      if (d.accumulate) { vr += y->x; vi += y->y; }
-      *y = make_double2(vr, vi);
+    for (int r = 0; r < R; ++r) {
+      red[wave][r][0] = yr[r];
+      red[wave][r][1] = yi[r];
     }
+  }
+  __syncthreads();
+  if (wave == 0 && lane < R && row0 + lane < d.rows) {
+    double vr = 0, vi = 0;
+#pragma unroll
+    for (int w = 0; w < kWavesPerBlock; ++w) {
+      vr += red[w][lane][0];
+      vi += red[w][lane][1];
+    }
+    double2* y = d.y + row0 + lane;
+    if (d.accumulate) { vr += y->x; vi += y->y; }
+    *y = make_double2(vr, vi);
   }
 }
 
