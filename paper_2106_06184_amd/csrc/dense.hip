@@ -20,11 +20,13 @@
 
 namespace bem {
 
-// BEM_DENSE_VALU=1 selects the plain VALU rank-b update instead of the matrix-core one (read
-// at every inversion).
-static bool dense_use_mfma() {
-  const char* e = std::getenv("BEM_DENSE_VALU");
-  return !(e && *e && *e != '0');
+// Rank-b update kernel (read at every inversion): BEM_DENSE_VALU=1 selects the plain VALU one,
+// BEM_DENSE_MFMA16=1 the float64 16x16x4 matrix-core one; the default is the 4x4x4 one.
+static int dense_update_kind() {
+  const char* v = std::getenv("BEM_DENSE_VALU");
+  if (v && *v && *v != '0') return 0;
+  const char* m = std::getenv("BEM_DENSE_MFMA16");
+  return (m && *m && *m != '0') ? 1 : 2;
 }
 namespace dev {
 
@@ -315,6 +317,100 @@ __global__ void __launch_bounds__(256, 2) k_gj_update_mfma(double* __restrict__ 
       }
 }
 
+// Same update with the float64 4x4x4 four-block matrix instruction (on gfx950 it runs at about
+// 1.45x the float64 16x16x4 one).  Lane l of one instruction supplies A_q[l % 4][l / 16] and
+// B_q[l / 16][l % 4] of block q = (l % 16) / 4 and receives D_q[l / 16][l % 4].  All four blocks
+// of an instruction share the rows (4 rows of the wave tile) and take four consecutive 4-column
+// groups, so a lane's A value serves the four column groups and its B value the eight row
+// groups: per 4 reals of K a wave issues 32 instructions on 8 A and 4 B values from LDS.
+// Output of instruction (bi, g), lane l: row 4 bi + l / 16, column 16 g + l % 16 of the wave tile
+// (32 x 64 reals).  Staging, tile order and the write-back are those of k_gj_update_mfma.
+__global__ void __launch_bounds__(256, 2) k_gj_update_mfma4(double* __restrict__ A, int64_t ld, int64_t n,
+                                                         int64_t k0, int b, const double2* __restrict__ R,
+                                                         const double2* __restrict__ Cp) {
+  constexpr int KC = 32;  // reals of K per stage (16 complex)
+  __shared__ double As[KC][64 + 1];
+  __shared__ __align__(16) double Bs[KC][128 + 2];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wm = wave >> 1, wn = wave & 1;
+  const unsigned nbx = gridDim.x, nby = gridDim.y;
+  const unsigned lin = blockIdx.y * nbx + blockIdx.x;
+  unsigned ti = lin / nbx, tj = lin % nbx;
+  if (nby % 8 == 0) {
+    const unsigned band = nby / 8, l = lin / 8;
+    ti = (lin % 8) * band + l % band;
+    tj = l / band;
+  }
+  const int64_t i0 = int64_t(ti) * 64;  // complex rows
+  const int64_t j0 = int64_t(tj) * 64;  // complex columns
+  const int sr = tid & 63, sg = (tid >> 6) * 4;
+  double2 pc[4], pr[4];
+  auto fetch = [&](int s0) {
+    const int64_t gi = i0 + sr, gj = j0 + sr;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int sc = s0 + sg + e;
+      pc[e] = (gi < n && sc < b) ? Cp[gi * NB + sc] : make_double2(0, 0);
+      pr[e] = (gj < n && sc < b) ? R[int64_t(sc) * n + gj] : make_double2(0, 0);
+    }
+  };
+  auto stage = [&]() {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int k = 2 * (sg + e);
+      As[k][sr] = pc[e].x;
+      As[k + 1][sr] = pc[e].y;
+      *reinterpret_cast<double2*>(&Bs[k][2 * sr]) = pr[e];
+      *reinterpret_cast<double2*>(&Bs[k + 1][2 * sr]) = make_double2(-pr[e].y, pr[e].x);
+    }
+  };
+  fetch(0);
+  // old values of the tile (rows and columns of the pivot block are overwritten afterwards)
+  const int orow = lane >> 4, ocol = lane & 15;
+  double apre[8][4];
+#pragma unroll
+  for (int bi = 0; bi < 8; ++bi)
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const int64_t gi = i0 + wm * 32 + 4 * bi + orow;
+      const int64_t rc = 2 * j0 + wn * 64 + 16 * g + ocol;
+      apre[bi][g] = (gi < n && (rc >> 1) < n) ? A[gi * 2 * ld + rc] : 0.0;
+    }
+  double acc[8][4];
+#pragma unroll
+  for (int bi = 0; bi < 8; ++bi)
+#pragma unroll
+    for (int g = 0; g < 4; ++g) acc[bi][g] = 0.0;
+  const int ai = lane & 3, ak = lane >> 4, bc = lane & 15;
+  const int K = 2 * b;
+  for (int k0r = 0; k0r < K; k0r += KC) {
+    stage();
+    __syncthreads();
+    if (k0r + KC < K) fetch((k0r + KC) / 2);  // next chunk streams in during the MFMAs
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += 4) {
+      double av[8], bv[4];
+#pragma unroll
+      for (int bi = 0; bi < 8; ++bi) av[bi] = As[kk + ak][wm * 32 + 4 * bi + ai];
+#pragma unroll
+      for (int g = 0; g < 4; ++g) bv[g] = Bs[kk + ak][wn * 64 + 16 * g + bc];
+#pragma unroll
+      for (int bi = 0; bi < 8; ++bi)
+#pragma unroll
+        for (int g = 0; g < 4; ++g) acc[bi][g] = __builtin_amdgcn_mfma_f64_4x4x4f64(av[bi], bv[g], acc[bi][g], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int bi = 0; bi < 8; ++bi)
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const int64_t gi = i0 + wm * 32 + 4 * bi + orow;
+      const int64_t rc = 2 * j0 + wn * 64 + 16 * g + ocol;
+      if (gi < n && (rc >> 1) < n) A[gi * 2 * ld + rc] = apre[bi][g] - acc[bi][g];
+    }
+}
+
 // A[k0+s][j] = R[s][j] (j outside kb); A[i][k0+s] = -sum_t C[i][t] P[t][s] (i outside kb);
 // A[kb][kb] = P
 // Thread (i, s): 4 rows i per block, 64 values of s.
@@ -515,7 +611,11 @@ void dense_invert(double2* A, int64_t n, int64_t ld, DenseScratch& ws, hipStream
     dim3 g(unsigned((n + 63) / 64), unsigned((n + 63) / 64));
     {
       ProfScope ps(st, KC_DENSE_INV, 32.0 * double(n) * n, 8.0 * double(n) * n * b);
-      if (dense_use_mfma())
+      const int kind = dense_update_kind();
+      if (kind == 2)
+        hipLaunchKernelGGL(dev::k_gj_update_mfma4, g, dim3(256), 0, st, reinterpret_cast<double*>(A), ld, n, k0, b,
+                           ws.R, ws.C);
+      else if (kind == 1)
         hipLaunchKernelGGL(dev::k_gj_update_mfma, g, dim3(256), 0, st, reinterpret_cast<double*>(A), ld, n, k0, b,
                            ws.R, ws.C);
       else

@@ -98,11 +98,13 @@ def case(name, ctx, inner=B.BEM_INNER_GMRES, precond=0, precision=B.BEM_FP64):
     return _cache[key]
 
 
-@pytest.mark.parametrize("backend", ["valu", "mfma"])
+@pytest.mark.parametrize("backend", ["valu", "mfma16", "mfma4"])
 def test_device_inverse_of_meq(backend, ctx, monkeypatch):
-    """The direct nested solve's device inverse times the oracle's M_eq is the identity (both
-    the VALU and the matrix-core rank-64 update of the Gauss-Jordan elimination)."""
+    """The direct nested solve's device inverse times the oracle's M_eq is the identity (the
+    VALU, the 16x16x4 and the 4x4x4 matrix-core rank-64 updates of the Gauss-Jordan
+    elimination)."""
     monkeypatch.setenv("BEM_DENSE_VALU", "1" if backend == "valu" else "0")
+    monkeypatch.setenv("BEM_DENSE_MFMA16", "1" if backend == "mfma16" else "0")
     w = CASES["ico80_lossy"]()
     if "ico80_lossy" not in _oracle:
         _oracle["ico80_lossy"] = S.assemble(w.xyz, w.tri, w.obj,
