@@ -22,6 +22,11 @@ namespace bem {
 
 // Rank-b update kernel (read at every inversion): BEM_DENSE_VALU=1 selects the plain VALU one,
 // BEM_DENSE_MFMA16=1 the float64 16x16x4 matrix-core one; the default is the 4x4x4 one.
+// BEM_DENSE_SINGLE=1 applies every panel by its own pass over the matrix (no panel pairing)
+static bool dense_pairing() {
+  const char* v = std::getenv("BEM_DENSE_SINGLE");
+  return !(v && *v && *v != '0');
+}
 static int dense_update_kind() {
   const char* v = std::getenv("BEM_DENSE_VALU");
   if (v && *v && *v != '0') return 0;
@@ -31,6 +36,7 @@ static int dense_update_kind() {
 namespace dev {
 
 constexpr int NB = 64;
+constexpr int LDC = 2 * NB;  // row stride of the column panels C (two panels side by side)
 
 __device__ __forceinline__ double2 cm(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -154,17 +160,52 @@ __global__ void __launch_bounds__(256) k_gj_panels(const double2* __restrict__ A
        e += blockDim.x) {
     const int64_t i = e / NB;
     const int s = int(e % NB);
-    if (i < n && s < b) Cp[i * NB + s] = A[i * ld + k0 + s];
+    if (i < n && s < b) Cp[i * LDC + s] = A[i * ld + k0 + s];
   }
 }
 
-// A[i][j] -= sum_s C[i][s] R[s][j] for i, j outside [k0, k0+b)
-__global__ void __launch_bounds__(256) k_gj_update(double2* __restrict__ A, int64_t ld, int64_t n, int64_t k0, int b,
-                                                   const double2* __restrict__ R, const double2* __restrict__ Cp) {
+// The 64 x 64 tile (ti, tj) of an update launch.  Mode 0 covers the matrix, gridDim.y x
+// gridDim.x tiles, in an XCD-aware order: the 8 XCDs take consecutive blocks round-robin; each
+// XCD gets a band of nby/8 row tiles and walks it column tile by column tile (rows fastest), so
+// the band's rows of the column panel C and the few R columns in flight stay in its L2 and
+// every panel entry is fetched from HBM about once per XCD.  Mode 1 is the column of tiles
+// tj = fix (one block per tile row), mode 2 the row of tiles ti = fix without its tile in
+// column fix.
+__device__ __forceinline__ void update_tile(int mode, int fix, unsigned& ti, unsigned& tj) {
+  if (mode == 1) {
+    ti = blockIdx.x;
+    tj = unsigned(fix);
+    return;
+  }
+  if (mode == 2) {
+    ti = unsigned(fix);
+    tj = blockIdx.x + (blockIdx.x >= unsigned(fix) ? 1u : 0u);
+    return;
+  }
+  const unsigned nbx = gridDim.x, nby = gridDim.y;
+  const unsigned lin = blockIdx.y * nbx + blockIdx.x;
+  ti = lin / nbx;
+  tj = lin % nbx;
+  if (nby % 8 == 0) {
+    const unsigned band = nby / 8, l = lin / 8;
+    ti = (lin % 8) * band + l % band;
+    tj = l / band;
+  }
+}
+
+// A[i][j] -= sum_s C[i][s] R[s][j] over the tiles of the launch (C: ld LDC, R: ld n).  Whole
+// tiles are updated: rows and columns of the pivot blocks are overwritten afterwards, and where
+// a tile holds an earlier pivot block's rows or columns, that panel's C rows and R columns there
+// are zero.
+__global__ void __launch_bounds__(256) k_gj_update(double2* __restrict__ A, int64_t ld, int64_t n, int mode, int fix,
+                                                   int b, const double2* __restrict__ R,
+                                                   const double2* __restrict__ Cp) {
   __shared__ double2 Cs[64][17];
   __shared__ double2 Rs[16][64];
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  const int64_t i0 = int64_t(blockIdx.y) * 64, j0 = int64_t(blockIdx.x) * 64;
+  unsigned ti, tj;
+  update_tile(mode, fix, ti, tj);
+  const int64_t i0 = int64_t(ti) * 64, j0 = int64_t(tj) * 64;
   double2 acc[4][4];
 #pragma unroll
   for (int r = 0; r < 4; ++r)
@@ -175,7 +216,7 @@ __global__ void __launch_bounds__(256) k_gj_update(double2* __restrict__ A, int6
     for (int e = threadIdx.x; e < 64 * 16; e += 256) {
       const int r = e / 16, s = e % 16;
       const int64_t gi = i0 + r;
-      Cs[r][s] = (gi < n && s0 + s < b) ? Cp[gi * NB + s0 + s] : make_double2(0, 0);
+      Cs[r][s] = (gi < n && s0 + s < b) ? Cp[gi * LDC + s0 + s] : make_double2(0, 0);
       const int sr = e / 64, cc = e % 64;
       const int64_t gj = j0 + cc;
       Rs[sr][cc] = (gj < n && s0 + sr < b) ? R[(s0 + sr) * n + gj] : make_double2(0, 0);
@@ -201,11 +242,11 @@ __global__ void __launch_bounds__(256) k_gj_update(double2* __restrict__ A, int6
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int64_t gi = i0 + ty + 16 * r;
-    if (gi >= n || (gi >= k0 && gi < k0 + b)) continue;
+    if (gi >= n) continue;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const int64_t gj = j0 + tx + 16 * c;
-      if (gj >= n || (gj >= k0 && gj < k0 + b)) continue;
+      if (gj >= n) continue;
       double2* a = A + gi * ld + gj;
       *a = make_double2(a->x - acc[r][c].x, a->y - acc[r][c].y);
     }
@@ -219,30 +260,20 @@ __global__ void __launch_bounds__(256) k_gj_update(double2* __restrict__ A, int6
 // through LDS 32 reals at a time (A k-major so that operand reads are conflict-free).
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
-__global__ void __launch_bounds__(256, 2) k_gj_update_mfma(double* __restrict__ A, int64_t ld, int64_t n, int64_t k0,
-                                                        int b, const double2* __restrict__ R,
+__global__ void __launch_bounds__(256, 2) k_gj_update_mfma(double* __restrict__ A, int64_t ld, int64_t n, int mode,
+                                                        int fix, int b, const double2* __restrict__ R,
                                                         const double2* __restrict__ Cp) {
   constexpr int KC = 32;  // reals of K per stage (16 complex)
   __shared__ double As[KC][64 + 1];
   __shared__ __align__(16) double Bs[KC][128 + 2];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wm = wave >> 1, wn = wave & 1;
-  // XCD-aware order: the 8 XCDs take consecutive blocks round-robin.  Each XCD gets a band of
-  // nby/8 row tiles and walks it column tile by column tile (rows fastest), so the band's
-  // rows of the column panel C and the few R columns in flight stay in its L2 and every panel
-  // entry is fetched from HBM about once per XCD
-  const unsigned nbx = gridDim.x, nby = gridDim.y;
-  const unsigned lin = blockIdx.y * nbx + blockIdx.x;
-  unsigned ti = lin / nbx, tj = lin % nbx;
-  if (nby % 8 == 0) {
-    const unsigned band = nby / 8, l = lin / 8;
-    ti = (lin % 8) * band + l % band;
-    tj = l / band;
-  }
+  unsigned ti, tj;
+  update_tile(mode, fix, ti, tj);
   const int64_t i0 = int64_t(ti) * 64;  // complex rows
   const int64_t j0 = int64_t(tj) * 64;  // complex columns
-  // the rows and columns of the pivot block are overwritten afterwards, so the whole tile is
-  // updated; its old values are fetched first (they stream in while the product is formed)
+  // the whole tile is updated (as in k_gj_update); its old values are fetched first (they
+  // stream in while the product is formed)
   double apre[2][4][4];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -269,7 +300,7 @@ __global__ void __launch_bounds__(256, 2) k_gj_update_mfma(double* __restrict__ 
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int sc = s0 + sg + e;
-      pc[e] = (gi < n && sc < b) ? Cp[gi * NB + sc] : make_double2(0, 0);
+      pc[e] = (gi < n && sc < b) ? Cp[gi * LDC + sc] : make_double2(0, 0);
       pr[e] = (gj < n && sc < b) ? R[int64_t(sc) * n + gj] : make_double2(0, 0);
     }
   };
@@ -326,21 +357,15 @@ __global__ void __launch_bounds__(256, 2) k_gj_update_mfma(double* __restrict__ 
 // Output of instruction (bi, g), lane l: row 4 bi + l / 16, column 16 g + l % 16 of the wave tile
 // (32 x 64 reals).  Staging, tile order and the write-back are those of k_gj_update_mfma.
 __global__ void __launch_bounds__(256, 2) k_gj_update_mfma4(double* __restrict__ A, int64_t ld, int64_t n,
-                                                         int64_t k0, int b, const double2* __restrict__ R,
+                                                         int mode, int fix, int b, const double2* __restrict__ R,
                                                          const double2* __restrict__ Cp) {
   constexpr int KC = 32;  // reals of K per stage (16 complex)
   __shared__ double As[KC][64 + 1];
   __shared__ __align__(16) double Bs[KC][128 + 2];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wm = wave >> 1, wn = wave & 1;
-  const unsigned nbx = gridDim.x, nby = gridDim.y;
-  const unsigned lin = blockIdx.y * nbx + blockIdx.x;
-  unsigned ti = lin / nbx, tj = lin % nbx;
-  if (nby % 8 == 0) {
-    const unsigned band = nby / 8, l = lin / 8;
-    ti = (lin % 8) * band + l % band;
-    tj = l / band;
-  }
+  unsigned ti, tj;
+  update_tile(mode, fix, ti, tj);
   const int64_t i0 = int64_t(ti) * 64;  // complex rows
   const int64_t j0 = int64_t(tj) * 64;  // complex columns
   const int sr = tid & 63, sg = (tid >> 6) * 4;
@@ -350,7 +375,7 @@ __global__ void __launch_bounds__(256, 2) k_gj_update_mfma4(double* __restrict__
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int sc = s0 + sg + e;
-      pc[e] = (gi < n && sc < b) ? Cp[gi * NB + sc] : make_double2(0, 0);
+      pc[e] = (gi < n && sc < b) ? Cp[gi * LDC + sc] : make_double2(0, 0);
       pr[e] = (gj < n && sc < b) ? R[int64_t(sc) * n + gj] : make_double2(0, 0);
     }
   };
@@ -416,9 +441,12 @@ __global__ void __launch_bounds__(256, 2) k_gj_update_mfma4(double* __restrict__
 // Thread (i, s): 4 rows i per block, 64 values of s.
 //   i outside kb:  A[k0+s][i] = R[s][i]  and  A[i][k0+s] = -sum_t C[i][t] P[t][s]
 //   i inside kb:   A[i][k0+s] = P[i-k0][s]
+//   and the panel entries of the pivot block's own rows and columns (R[s][i], C[i][s], i inside
+//   kb: read by no other thread) are zeroed, so that a later pass that applies this panel
+//   together with the next one leaves the rows and columns just written unchanged.
 __global__ void __launch_bounds__(256) k_gj_write(double2* __restrict__ A, int64_t ld, int64_t n, int64_t k0, int b,
-                                                  const double2* __restrict__ P, const double2* __restrict__ R,
-                                                  const double2* __restrict__ Cp) {
+                                                  const double2* __restrict__ P, double2* __restrict__ R,
+                                                  double2* __restrict__ Cp) {
   __shared__ double2 Ps[NB][NB];
   for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) Ps[e / NB][e % NB] = P[e];
   __syncthreads();
@@ -427,12 +455,14 @@ __global__ void __launch_bounds__(256) k_gj_write(double2* __restrict__ A, int64
   if (i >= n || s >= b) return;
   if (i >= k0 && i < k0 + b) {
     A[i * ld + k0 + s] = Ps[i - k0][s];
+    R[s * n + i] = make_double2(0, 0);
+    Cp[i * LDC + s] = make_double2(0, 0);
     return;
   }
   A[(k0 + s) * ld + i] = R[s * n + i];
   double2 acc = make_double2(0, 0);
   for (int t = 0; t < b; ++t) {
-    const double2 c = Cp[i * NB + t], p = Ps[t][s];
+    const double2 c = Cp[i * LDC + t], p = Ps[t][s];
     acc.x += c.x * p.x - c.y * p.y;
     acc.y += c.x * p.y + c.y * p.x;
   }
@@ -601,28 +631,60 @@ void launch_peq_stage2(const double2* d, const double2* t, const double2* v, con
   BEM_HIP(hipGetLastError());
 }
 
+// One update launch over the tiles of `mode` (see update_tile) with b panel columns.
+static void launch_update(int kind, double2* A, int64_t ld, int64_t n, int mode, int fix, int b, const double2* R,
+                          const double2* C, hipStream_t st) {
+  const unsigned nt = unsigned((n + 63) / 64);
+  const dim3 g = mode == 0 ? dim3(nt, nt) : dim3(mode == 1 ? nt : nt - 1);
+  if (g.x == 0) return;
+  const double ntile = double(g.x) * g.y, elems = ntile * 64.0 * 64.0;
+  ProfScope ps(st, KC_DENSE_INV, 32.0 * std::min(elems, mode == 0 ? double(n) * n : 64.0 * n),
+               8.0 * b * std::min(elems, mode == 0 ? double(n) * n : 64.0 * n));
+  double* Ad = reinterpret_cast<double*>(A);
+  if (kind == 2)
+    hipLaunchKernelGGL(dev::k_gj_update_mfma4, g, dim3(256), 0, st, Ad, ld, n, mode, fix, b, R, C);
+  else if (kind == 1)
+    hipLaunchKernelGGL(dev::k_gj_update_mfma, g, dim3(256), 0, st, Ad, ld, n, mode, fix, b, R, C);
+  else
+    hipLaunchKernelGGL(dev::k_gj_update, g, dim3(256), 0, st, A, ld, n, mode, fix, b, R, C);
+}
+
+// Blocked Gauss-Jordan, panels of NB.  Panels are taken in pairs (k0, k1 = k0 + NB) so that one
+// pass over the matrix applies both (a rank-2 NB update, half the matrix traffic per flop):
+// after panel k0's pivot rows and columns are written (which zeroes its C and R entries of
+// those rows and columns), only the row and column strips of block k1 are brought up to date
+// with panel k0; panel k1's pivot block and panels are taken from them; then every tile gets
+// A - C_k0 R_k0 - C_k1 R_k1 at once (the strips of block k1 are overwritten by its write).
+// Entry for entry this is the two single-panel steps.
 void dense_invert(double2* A, int64_t n, int64_t ld, DenseScratch& ws, hipStream_t st) {
   if (n <= 0) return;
-  for (int64_t k0 = 0; k0 < n; k0 += dev::NB) {
+  const int kind = dense_update_kind();
+  const bool pair = dense_pairing();
+  int64_t k0 = 0;
+  while (k0 < n) {
     const int b = int(std::min<int64_t>(dev::NB, n - k0));
+    const int64_t k1 = k0 + dev::NB;
+    const int b2 = (pair && k1 < n) ? int(std::min<int64_t>(dev::NB, n - k1)) : 0;
+    const unsigned gp = unsigned((n + 31) / 32), gw = unsigned((n + 3) / 4);
     hipLaunchKernelGGL(dev::k_gj_diag, dim3(1), dim3(256), 0, st, A, ld, k0, b, ws.P);
-    hipLaunchKernelGGL(dev::k_gj_panels, dim3(unsigned((n + 31) / 32)), dim3(256), 0, st, A, ld, n, k0, b, ws.P,
-                       ws.R, ws.C);
-    dim3 g(unsigned((n + 63) / 64), unsigned((n + 63) / 64));
-    {
-      ProfScope ps(st, KC_DENSE_INV, 32.0 * double(n) * n, 8.0 * double(n) * n * b);
-      const int kind = dense_update_kind();
-      if (kind == 2)
-        hipLaunchKernelGGL(dev::k_gj_update_mfma4, g, dim3(256), 0, st, reinterpret_cast<double*>(A), ld, n, k0, b,
-                           ws.R, ws.C);
-      else if (kind == 1)
-        hipLaunchKernelGGL(dev::k_gj_update_mfma, g, dim3(256), 0, st, reinterpret_cast<double*>(A), ld, n, k0, b,
-                           ws.R, ws.C);
-      else
-        hipLaunchKernelGGL(dev::k_gj_update, g, dim3(256), 0, st, A, ld, n, k0, b, ws.R, ws.C);
+    hipLaunchKernelGGL(dev::k_gj_panels, dim3(gp), dim3(256), 0, st, A, ld, n, k0, b, ws.P, ws.R, ws.C);
+    if (b2 == 0) {
+      launch_update(kind, A, ld, n, 0, 0, b, ws.R, ws.C, st);
+      hipLaunchKernelGGL(dev::k_gj_write, dim3(gw), dim3(256), 0, st, A, ld, n, k0, b, ws.P, ws.R, ws.C);
+      k0 += dev::NB;
+      continue;
     }
-    hipLaunchKernelGGL(dev::k_gj_write, dim3(unsigned((n + 3) / 4)), dim3(256), 0, st, A, ld, n, k0, b, ws.P, ws.R,
-                       ws.C);
+    hipLaunchKernelGGL(dev::k_gj_write, dim3(gw), dim3(256), 0, st, A, ld, n, k0, b, ws.P, ws.R, ws.C);
+    const int t1 = int(k1 / 64);
+    launch_update(kind, A, ld, n, 1, t1, b, ws.R, ws.C, st);
+    launch_update(kind, A, ld, n, 2, t1, b, ws.R, ws.C, st);
+    double2* R2 = ws.R + int64_t(dev::NB) * n;
+    double2* C2 = ws.C + dev::NB;
+    hipLaunchKernelGGL(dev::k_gj_diag, dim3(1), dim3(256), 0, st, A, ld, k1, b2, ws.P);
+    hipLaunchKernelGGL(dev::k_gj_panels, dim3(gp), dim3(256), 0, st, A, ld, n, k1, b2, ws.P, R2, C2);
+    launch_update(kind, A, ld, n, 0, 0, dev::NB + b2, ws.R, ws.C, st);
+    hipLaunchKernelGGL(dev::k_gj_write, dim3(gw), dim3(256), 0, st, A, ld, n, k1, b2, ws.P, R2, C2);
+    k0 += 2 * dev::NB;
   }
   BEM_HIP(hipGetLastError());
 }
