@@ -409,21 +409,48 @@ __global__ void k_scale_inv(const double2* __restrict__ w, int64_t n, const doub
 }
 
 // Hcol: entries 0..j (projections) and j+1 (norm of the new vector, real).
-__device__ void givens_step(double2* Hcol, int j, double2* cs, double2* sn, double2* g, double* res,
-                            const double2* h2) {
-  if (h2)
-    for (int i = 0; i <= j; ++i) Hcol[i] = make_double2(Hcol[i].x + h2[i].x, Hcol[i].y + h2[i].y);
-  // apply previous rotations: [h_i; h_{i+1}] <- [c, s; -conj(s), c] [h_i; h_{i+1}]  (c real)
-  for (int i = 0; i < j; ++i) {
-    const double c = cs[i].x;
-    const double2 s = sn[i];
-    const double2 a = Hcol[i], b = Hcol[i + 1];
-    const double2 na = make_double2(c * a.x + (s.x * b.x - s.y * b.y), c * a.y + (s.x * b.y + s.y * b.x));
-    const double2 nb = make_double2(-(s.x * a.x + s.y * a.y) + c * b.x, -(s.x * a.y - s.y * a.x) + c * b.y);
-    Hcol[i] = na;
-    Hcol[i + 1] = nb;
+// Column j of the Hessenberg matrix (h2, if given, is added to entries 0..j first) gets the j
+// earlier rotations and then the new rotation that zeroes entry j+1; g is rotated with it and
+// |g_{j+1}| is the residual norm.  Run by one wave: the rotations and the column are staged
+// through LDS in chunks with coalesced loads, so the serial recurrence of lane 0 (the rotated
+// entry carried in registers) reads only LDS.
+__device__ void givens_step(double2* __restrict__ Hcol, int j, const double2* __restrict__ cs_in,
+                            const double2* __restrict__ sn_in, double2* __restrict__ cs, double2* __restrict__ sn,
+                            double2* __restrict__ g, double* __restrict__ res, const double2* __restrict__ h2) {
+  constexpr int CH = 256;
+  __shared__ double2 sh[CH + 1], sc[CH], ss[CH];
+  const int t = threadIdx.x, nth = blockDim.x;
+  auto hload = [&](int i) {
+    double2 v = Hcol[i];
+    if (h2) v = make_double2(v.x + h2[i].x, v.y + h2[i].y);
+    return v;
+  };
+  double2 a = make_double2(0, 0);  // lane 0: entry i0 of the column, rotations before i0 applied
+  if (t == 0) a = hload(0);
+  for (int i0 = 0; i0 < j; i0 += CH) {
+    const int cnt = min(CH, j - i0);
+    for (int e = t; e < cnt; e += nth) {
+      sh[e + 1] = hload(i0 + e + 1);
+      sc[e] = cs_in[i0 + e];
+      ss[e] = sn_in[i0 + e];
+    }
+    __syncthreads();
+    if (t == 0) {
+      // [h_i; h_{i+1}] <- [c, s; -conj(s), c] [h_i; h_{i+1}]  (c real)
+#pragma unroll 8
+      for (int e = 0; e < cnt; ++e) {
+        const double c = sc[e].x;
+        const double2 sv = ss[e], b = sh[e + 1];
+        sh[e] = make_double2(c * a.x + (sv.x * b.x - sv.y * b.y), c * a.y + (sv.x * b.y + sv.y * b.x));
+        a = make_double2(-(sv.x * a.x + sv.y * a.y) + c * b.x, -(sv.x * a.y - sv.y * a.x) + c * b.y);
+      }
+    }
+    __syncthreads();
+    for (int e = t; e < cnt; e += nth) Hcol[i0 + e] = sh[e];
+    __syncthreads();
   }
-  const double2 a = Hcol[j], b = Hcol[j + 1];
+  if (t != 0) return;
+  const double2 b = Hcol[j + 1];
   const double na = hypot(a.x, a.y), nb = hypot(b.x, b.y);
   double c;
   double2 s;
@@ -434,11 +461,11 @@ __device__ void givens_step(double2* Hcol, int j, double2* cs, double2* sn, doub
     c = 0.0;
     s = make_double2(b.x / nb, -b.y / nb);  // s = conj(b)/|b|
   } else {
-    const double t = hypot(na, nb);
-    c = na / t;
+    const double t2 = hypot(na, nb);
+    c = na / t2;
     // s = (a/|a|) conj(b) / t
     const double2 ua = make_double2(a.x / na, a.y / na);
-    s = make_double2((ua.x * b.x + ua.y * b.y) / t, (ua.y * b.x - ua.x * b.y) / t);
+    s = make_double2((ua.x * b.x + ua.y * b.y) / t2, (ua.y * b.x - ua.x * b.y) / t2);
   }
   cs[j] = make_double2(c, 0);
   sn[j] = s;
@@ -452,10 +479,9 @@ __device__ void givens_step(double2* Hcol, int j, double2* cs, double2* sn, doub
   *res = hypot(g[j + 1].x, g[j + 1].y);
 }
 
-__global__ void k_givens(double2* Hcol, int j, double2* cs, double2* sn, double2* g, double* res,
-                         const double2* h2) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  givens_step(Hcol, j, cs, sn, g, res, h2);
+__global__ void __launch_bounds__(64) k_givens(double2* Hcol, int j, double2* cs, double2* sn, double2* g,
+                                               double* res, const double2* h2) {
+  givens_step(Hcol, j, cs, sn, cs, sn, g, res, h2);
 }
 
 // y = R^{-1} g for the leading j x j upper-triangular block of H (column-major, ldh)
@@ -571,22 +597,35 @@ __global__ void k_bmdot_final(const double2* __restrict__ part, int nch, int j1,
   }
 }
 
-__global__ void k_bmupdate(const double2* __restrict__ V, int64_t ldv, int R, int j1, const int* __restrict__ jr,
-                           const double2* __restrict__ h, int64_t hstride, double sign, double2* __restrict__ W,
-                           int64_t ldw, int64_t n) {
-  const int c = blockIdx.y;
-  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (k >= n) return;
+// w_c += sign sum_{i < j_c} V_i,c h_i,c.  A block owns 64 consecutive elements (one per lane);
+// its four waves take the basis vectors i = wave, wave + 4, ... and their partial sums are
+// added in LDS in a fixed order, then to w: one column alone still gives n / 64 blocks.
+__global__ void __launch_bounds__(256) k_bmupdate(const double2* __restrict__ V, int64_t ldv, int R, int j1,
+                                                  const int* __restrict__ jr, const double2* __restrict__ h,
+                                                  int64_t hstride, double sign, double2* __restrict__ W,
+                                                  int64_t ldw, int64_t n) {
+  const int c = blockIdx.y, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t k = int64_t(blockIdx.x) * 64 + lane;
   const int jc = jr ? jr[c] : j1;
   const double2* hc = h + int64_t(c) * hstride;
-  double2* w = W + int64_t(c) * ldw;
-  double ar = w[k].x, ai = w[k].y;
-  for (int i = 0; i < jc; ++i) {
-    const double2 a = V[(int64_t(i) * R + c) * ldv + k], q = hc[i];
-    ar += sign * (a.x * q.x - a.y * q.y);
-    ai += sign * (a.x * q.y + a.y * q.x);
+  double ar = 0, ai = 0;
+  if (k < n) {
+#pragma unroll 4
+    for (int i = wv; i < jc; i += 4) {
+      const double2 a = V[(int64_t(i) * R + c) * ldv + k], q = hc[i];
+      ar += a.x * q.x - a.y * q.y;
+      ai += a.x * q.y + a.y * q.x;
+    }
   }
-  w[k] = make_double2(ar, ai);
+  __shared__ double2 red[4][64];
+  red[wv][lane] = make_double2(ar, ai);
+  __syncthreads();
+  if (wv == 0 && k < n) {
+    const double sr = ((red[0][lane].x + red[1][lane].x) + red[2][lane].x) + red[3][lane].x;
+    const double si = ((red[0][lane].y + red[1][lane].y) + red[2][lane].y) + red[3][lane].y;
+    double2* w = W + int64_t(c) * ldw;
+    w[k] = make_double2(w[k].x + sign * sr, w[k].y + sign * si);
+  }
 }
 
 __global__ void __launch_bounds__(256) k_bnorm_part(const double2* __restrict__ W, int64_t ldw, int64_t n, int nch,
@@ -629,12 +668,14 @@ __global__ void k_bscale_inv(double2* __restrict__ W, int64_t ldw, int64_t n, co
   w[k] = make_double2(w[k].x * s, w[k].y * s);
 }
 
-__global__ void k_bgivens(double2* H, int64_t hs, int64_t ldh, int j, double2* cs, double2* sn, double2* g,
-                          double* res, const double2* h2, int m, int R) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= R) return;
-  givens_step(H + int64_t(c) * hs + int64_t(j) * ldh, j, cs + int64_t(c) * (m + 1), sn + int64_t(c) * (m + 1),
-              g + int64_t(c) * (m + 2), res + c, h2 ? h2 + int64_t(c) * (m + 2) : nullptr);
+// one wave per column c
+__global__ void __launch_bounds__(64) k_bgivens(double2* H, int64_t hs, int64_t ldh, int j, double2* cs, double2* sn,
+                                                double2* g, double* res, const double2* h2, int m, int R) {
+  const int c = blockIdx.x;
+  double2* csc = cs + int64_t(c) * (m + 1);
+  double2* snc = sn + int64_t(c) * (m + 1);
+  givens_step(H + int64_t(c) * hs + int64_t(j) * ldh, j, csc, snc, csc, snc, g + int64_t(c) * (m + 2), res + c,
+              h2 ? h2 + int64_t(c) * (m + 2) : nullptr);
 }
 
 __global__ void k_bbacksolve(const double2* H, int64_t hs, int64_t ldh, const int* jr, const double2* g, double2* y,
@@ -813,7 +854,7 @@ void launch_bmdot(const double2* V, int64_t ldv, int R, int j1, const double2* W
 void launch_bmupdate(const double2* V, int64_t ldv, int R, int j1, const int* jr, const double2* h, int64_t hstride,
                      double sign, double2* W, int64_t ldw, int64_t n, hipStream_t st) {
   if (R <= 0 || n <= 0 || (j1 <= 0 && !jr)) return;
-  hipLaunchKernelGGL(dev::k_bmupdate, dim3(unsigned((n + 255) / 256), unsigned(R)), dim3(256), 0, st, V, ldv, R, j1,
+  hipLaunchKernelGGL(dev::k_bmupdate, dim3(unsigned((n + 63) / 64), unsigned(R)), dim3(256), 0, st, V, ldv, R, j1,
                      jr, h, hstride, sign, W, ldw, n);
   BEM_HIP(hipGetLastError());
 }
@@ -840,8 +881,7 @@ void launch_bscale_inv(double2* W, int64_t ldw, int R, int64_t n, const double2*
 void launch_bgivens(double2* H, int64_t hs, int64_t ldh, int j, double2* cs, double2* sn, double2* g, double* res,
                     const double2* h2, int m, int R, hipStream_t st) {
   if (R <= 0) return;
-  hipLaunchKernelGGL(dev::k_bgivens, dim3(unsigned((R + 63) / 64)), dim3(64), 0, st, H, hs, ldh, j, cs, sn, g, res,
-                     h2, m, R);
+  hipLaunchKernelGGL(dev::k_bgivens, dim3(unsigned(R)), dim3(64), 0, st, H, hs, ldh, j, cs, sn, g, res, h2, m, R);
   BEM_HIP(hipGetLastError());
 }
 
