@@ -9,8 +9,8 @@ namespace bem {
 
 struct DenseScratch {
   double2* P;  // 64 x 64
-  double2* R;  // 128 x n (two row panels)
-  double2* C;  // n x 128 (two column panels side by side)
+  double2* R;  // 256 x n (four row panels)
+  double2* C;  // n x 256 (four column panels side by side)
 };
 
 // In-place inverse of the n x n complex matrix A (row-major, leading dimension ld) by blocked

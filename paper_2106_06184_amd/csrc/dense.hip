@@ -22,10 +22,11 @@ namespace bem {
 
 // Rank-b update kernel (read at every inversion): BEM_DENSE_VALU=1 selects the plain VALU one,
 // BEM_DENSE_MFMA16=1 the float64 16x16x4 matrix-core one; the default is the 4x4x4 one.
-// BEM_DENSE_SINGLE=1 applies every panel by its own pass over the matrix (no panel pairing)
-static bool dense_pairing() {
-  const char* v = std::getenv("BEM_DENSE_SINGLE");
-  return !(v && *v && *v != '0');
+// Panels per pass over the matrix: 4, or BEM_DENSE_GROUP = 1, 2 or 4
+static int dense_group() {
+  const char* v = std::getenv("BEM_DENSE_GROUP");
+  const int g = (v && *v) ? std::atoi(v) : 4;
+  return (g == 1 || g == 2) ? g : 4;
 }
 static int dense_update_kind() {
   const char* v = std::getenv("BEM_DENSE_VALU");
@@ -36,7 +37,8 @@ static int dense_update_kind() {
 namespace dev {
 
 constexpr int NB = 64;
-constexpr int LDC = 2 * NB;  // row stride of the column panels C (two panels side by side)
+constexpr int GMAX = 4;         // most panels applied by one pass
+constexpr int LDC = GMAX * NB;  // row stride of the column panels C (panels side by side)
 
 __device__ __forceinline__ double2 cm(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -441,12 +443,13 @@ __global__ void __launch_bounds__(256, 2) k_gj_update_mfma4(double* __restrict__
 // Thread (i, s): 4 rows i per block, 64 values of s.
 //   i outside kb:  A[k0+s][i] = R[s][i]  and  A[i][k0+s] = -sum_t C[i][t] P[t][s]
 //   i inside kb:   A[i][k0+s] = P[i-k0][s]
-//   and the panel entries of the pivot block's own rows and columns (R[s][i], C[i][s], i inside
-//   kb: read by no other thread) are zeroed, so that a later pass that applies this panel
-//   together with the next one leaves the rows and columns just written unchanged.
+// Panel m of the group: R and Cp are the group's panel bases (panel q at R + q NB n and
+// Cp + q NB).  The entries of panels 0..m in the pivot block's own rows and columns (R[q][s][i],
+// C[i][q][s], i inside kb: read by no other thread) are zeroed, so that the group's pass, which
+// applies all its panels at once, leaves the rows and columns just written as they are.
 __global__ void __launch_bounds__(256) k_gj_write(double2* __restrict__ A, int64_t ld, int64_t n, int64_t k0, int b,
                                                   const double2* __restrict__ P, double2* __restrict__ R,
-                                                  double2* __restrict__ Cp) {
+                                                  double2* __restrict__ Cp, int m) {
   __shared__ double2 Ps[NB][NB];
   for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) Ps[e / NB][e % NB] = P[e];
   __syncthreads();
@@ -455,10 +458,14 @@ __global__ void __launch_bounds__(256) k_gj_write(double2* __restrict__ A, int64
   if (i >= n || s >= b) return;
   if (i >= k0 && i < k0 + b) {
     A[i * ld + k0 + s] = Ps[i - k0][s];
-    R[s * n + i] = make_double2(0, 0);
-    Cp[i * LDC + s] = make_double2(0, 0);
+    for (int q = 0; q <= m; ++q) {
+      R[int64_t(q * NB + s) * n + i] = make_double2(0, 0);
+      Cp[i * LDC + q * NB + s] = make_double2(0, 0);
+    }
     return;
   }
+  R += int64_t(m) * NB * n;
+  Cp += m * NB;
   A[(k0 + s) * ld + i] = R[s * n + i];
   double2 acc = make_double2(0, 0);
   for (int t = 0; t < b; ++t) {
@@ -649,42 +656,40 @@ static void launch_update(int kind, double2* A, int64_t ld, int64_t n, int mode,
     hipLaunchKernelGGL(dev::k_gj_update, g, dim3(256), 0, st, A, ld, n, mode, fix, b, R, C);
 }
 
-// Blocked Gauss-Jordan, panels of NB.  Panels are taken in pairs (k0, k1 = k0 + NB) so that one
-// pass over the matrix applies both (a rank-2 NB update, half the matrix traffic per flop):
-// after panel k0's pivot rows and columns are written (which zeroes its C and R entries of
-// those rows and columns), only the row and column strips of block k1 are brought up to date
-// with panel k0; panel k1's pivot block and panels are taken from them; then every tile gets
-// A - C_k0 R_k0 - C_k1 R_k1 at once (the strips of block k1 are overwritten by its write).
-// Entry for entry this is the two single-panel steps.
+// Blocked Gauss-Jordan, panels of NB, applied in groups of G panels so that one pass over the
+// matrix applies a whole group (rank G NB: 1/G of the matrix traffic per flop).  Within a group,
+// before panel m's pivot block and panels are taken, only the row and column strips of its
+// block are brought up to date with panels 0..m-1; panels before the last write their pivot
+// rows and columns at once (zeroing the group's panel entries there).  The pass then gives
+// every tile A - sum_q C_q R_q, and the last panel's rows and columns are written over it.
+// Entry for entry this is G single-panel steps.
 void dense_invert(double2* A, int64_t n, int64_t ld, DenseScratch& ws, hipStream_t st) {
   if (n <= 0) return;
   const int kind = dense_update_kind();
-  const bool pair = dense_pairing();
-  int64_t k0 = 0;
-  while (k0 < n) {
-    const int b = int(std::min<int64_t>(dev::NB, n - k0));
-    const int64_t k1 = k0 + dev::NB;
-    const int b2 = (pair && k1 < n) ? int(std::min<int64_t>(dev::NB, n - k1)) : 0;
-    const unsigned gp = unsigned((n + 31) / 32), gw = unsigned((n + 3) / 4);
-    hipLaunchKernelGGL(dev::k_gj_diag, dim3(1), dim3(256), 0, st, A, ld, k0, b, ws.P);
-    hipLaunchKernelGGL(dev::k_gj_panels, dim3(gp), dim3(256), 0, st, A, ld, n, k0, b, ws.P, ws.R, ws.C);
-    if (b2 == 0) {
-      launch_update(kind, A, ld, n, 0, 0, b, ws.R, ws.C, st);
-      hipLaunchKernelGGL(dev::k_gj_write, dim3(gw), dim3(256), 0, st, A, ld, n, k0, b, ws.P, ws.R, ws.C);
-      k0 += dev::NB;
-      continue;
+  const int G = dense_group();
+  const unsigned gp = unsigned((n + 31) / 32), gw = unsigned((n + 3) / 4);
+  for (int64_t k0 = 0; k0 < n;) {
+    const int npan = int(std::min<int64_t>(G, (n - k0 + dev::NB - 1) / dev::NB));
+    int blast = 0;
+    for (int mp = 0; mp < npan; ++mp) {
+      const int64_t km = k0 + int64_t(mp) * dev::NB;
+      const int bm = int(std::min<int64_t>(dev::NB, n - km));
+      if (mp > 0) {
+        launch_update(kind, A, ld, n, 1, int(km / 64), mp * dev::NB, ws.R, ws.C, st);
+        launch_update(kind, A, ld, n, 2, int(km / 64), mp * dev::NB, ws.R, ws.C, st);
+      }
+      double2* Rm = ws.R + int64_t(mp) * dev::NB * n;
+      double2* Cm = ws.C + mp * dev::NB;
+      hipLaunchKernelGGL(dev::k_gj_diag, dim3(1), dim3(256), 0, st, A, ld, km, bm, ws.P);
+      hipLaunchKernelGGL(dev::k_gj_panels, dim3(gp), dim3(256), 0, st, A, ld, n, km, bm, ws.P, Rm, Cm);
+      if (mp + 1 < npan)
+        hipLaunchKernelGGL(dev::k_gj_write, dim3(gw), dim3(256), 0, st, A, ld, n, km, bm, ws.P, ws.R, ws.C, mp);
+      blast = bm;
     }
-    hipLaunchKernelGGL(dev::k_gj_write, dim3(gw), dim3(256), 0, st, A, ld, n, k0, b, ws.P, ws.R, ws.C);
-    const int t1 = int(k1 / 64);
-    launch_update(kind, A, ld, n, 1, t1, b, ws.R, ws.C, st);
-    launch_update(kind, A, ld, n, 2, t1, b, ws.R, ws.C, st);
-    double2* R2 = ws.R + int64_t(dev::NB) * n;
-    double2* C2 = ws.C + dev::NB;
-    hipLaunchKernelGGL(dev::k_gj_diag, dim3(1), dim3(256), 0, st, A, ld, k1, b2, ws.P);
-    hipLaunchKernelGGL(dev::k_gj_panels, dim3(gp), dim3(256), 0, st, A, ld, n, k1, b2, ws.P, R2, C2);
-    launch_update(kind, A, ld, n, 0, 0, dev::NB + b2, ws.R, ws.C, st);
-    hipLaunchKernelGGL(dev::k_gj_write, dim3(gw), dim3(256), 0, st, A, ld, n, k1, b2, ws.P, R2, C2);
-    k0 += 2 * dev::NB;
+    launch_update(kind, A, ld, n, 0, 0, (npan - 1) * dev::NB + blast, ws.R, ws.C, st);
+    const int64_t kl = k0 + int64_t(npan - 1) * dev::NB;
+    hipLaunchKernelGGL(dev::k_gj_write, dim3(gw), dim3(256), 0, st, A, ld, n, kl, blast, ws.P, ws.R, ws.C, npan - 1);
+    k0 += int64_t(npan) * dev::NB;
   }
   BEM_HIP(hipGetLastError());
 }

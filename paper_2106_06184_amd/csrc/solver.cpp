@@ -699,8 +699,8 @@ void build_inner_and_precond(OpObj& op, const std::vector<double>& ixdiag, hipSt
     return p;
   };
   ds.P = talloc(64 * 64);
-  ds.R = talloc(size_t(128) * maxn);  // two panels (Gauss-Jordan applies them in pairs)
-  ds.C = talloc(size_t(128) * maxn);
+  ds.R = talloc(size_t(256) * maxn);  // four panels (Gauss-Jordan applies them in groups)
+  ds.C = talloc(size_t(256) * maxn);
   // diagonals through a gather kernel and a stream-ordered copy (complete on return)
   const int64_t nbuf = std::max(std::max(m.ne, m.nt), maxn);
   double2* dbuf = talloc(size_t(nbuf));

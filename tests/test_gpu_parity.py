@@ -98,15 +98,15 @@ def case(name, ctx, inner=B.BEM_INNER_GMRES, precond=0, precision=B.BEM_FP64):
     return _cache[key]
 
 
-@pytest.mark.parametrize("backend", ["valu", "mfma16", "mfma4", "mfma4-single"])
+@pytest.mark.parametrize("backend", ["valu", "mfma16", "mfma4", "mfma4-g2", "mfma4-g1"])
 def test_device_inverse_of_meq(backend, ctx, monkeypatch):
     """The direct nested solve's device inverse times the oracle's M_eq is the identity (the
     VALU, the 16x16x4 and the 4x4x4 matrix-core updates of the Gauss-Jordan elimination, with
-    panels applied in pairs, and the 4x4x4 one panel at a time).  M_eq has 199 rows: two
-    panel pairs, the second with a 7-row panel."""
+    panels applied in groups of four, and the 4x4x4 one in pairs and one panel at a time).
+    M_eq has 199 rows: one group of four panels, the last with 7 rows."""
     monkeypatch.setenv("BEM_DENSE_VALU", "1" if backend == "valu" else "0")
     monkeypatch.setenv("BEM_DENSE_MFMA16", "1" if backend == "mfma16" else "0")
-    monkeypatch.setenv("BEM_DENSE_SINGLE", "1" if backend == "mfma4-single" else "0")
+    monkeypatch.setenv("BEM_DENSE_GROUP", backend[-1] if backend.endswith(("g1", "g2")) else "4")
     w = CASES["ico80_lossy"]()
     if "ico80_lossy" not in _oracle:
         _oracle["ico80_lossy"] = S.assemble(w.xyz, w.tri, w.obj,
