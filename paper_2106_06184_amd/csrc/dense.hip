@@ -144,6 +144,7 @@ __global__ void __launch_bounds__(256) k_gj_panels(const double2* __restrict__ A
     double2 acc[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) acc[u] = make_double2(0, 0);
+#pragma unroll 4
     for (int t = 0; t < b; ++t) {
       const double2 a = A[(k0 + t) * ld + j];
 #pragma unroll
@@ -439,41 +440,56 @@ __global__ void __launch_bounds__(256, 2) k_gj_update_mfma4(double* __restrict__
 }
 
 // A[k0+s][j] = R[s][j] (j outside kb); A[i][k0+s] = -sum_t C[i][t] P[t][s] (i outside kb);
-// A[kb][kb] = P
-// Thread (i, s): 4 rows i per block, 64 values of s.
-//   i outside kb:  A[k0+s][i] = R[s][i]  and  A[i][k0+s] = -sum_t C[i][t] P[t][s]
-//   i inside kb:   A[i][k0+s] = P[i-k0][s]
+// A[kb][kb] = P.  A block takes 16 consecutive indices r: rows i = r of the pivot columns (a wave
+// per row, lanes along s, C rows staged in LDS) and columns j = r of the pivot rows (16
+// consecutive j per s, so the row-block copy moves 256-byte segments).
 // Panel m of the group: R and Cp are the group's panel bases (panel q at R + q NB n and
 // Cp + q NB).  The entries of panels 0..m in the pivot block's own rows and columns (R[q][s][i],
-// C[i][q][s], i inside kb: read by no other thread) are zeroed, so that the group's pass, which
-// applies all its panels at once, leaves the rows and columns just written as they are.
+// C[i][q][s], i inside kb: read by no thread of the launch) are zeroed, so that the group's
+// pass, which applies all its panels at once, leaves the rows and columns just written as they
+// are.
 __global__ void __launch_bounds__(256) k_gj_write(double2* __restrict__ A, int64_t ld, int64_t n, int64_t k0, int b,
                                                   const double2* __restrict__ P, double2* __restrict__ R,
                                                   double2* __restrict__ Cp, int m) {
   __shared__ double2 Ps[NB][NB];
+  __shared__ double2 Cs[16][NB];
+  const int64_t r0 = int64_t(blockIdx.x) * 16;
+  const double2* Rm = R + int64_t(m) * NB * n;
+  const double2* Cm = Cp + m * NB;
   for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) Ps[e / NB][e % NB] = P[e];
+  for (int e = threadIdx.x; e < 16 * NB; e += blockDim.x) {
+    const int64_t i = r0 + e / NB;
+    const int t = e % NB;
+    const bool out = i < n && t < b && !(i >= k0 && i < k0 + b);
+    Cs[e / NB][t] = out ? Cm[i * LDC + t] : make_double2(0, 0);
+  }
   __syncthreads();
-  const int64_t i = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
-  const int s = threadIdx.x & 63;
-  if (i >= n || s >= b) return;
-  if (i >= k0 && i < k0 + b) {
-    A[i * ld + k0 + s] = Ps[i - k0][s];
-    for (int q = 0; q <= m; ++q) {
-      R[int64_t(q * NB + s) * n + i] = make_double2(0, 0);
-      Cp[i * LDC + q * NB + s] = make_double2(0, 0);
+  const int s = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int r = w; r < 16; r += 4) {
+    const int64_t i = r0 + r;
+    if (i >= n || s >= b) continue;
+    if (i >= k0 && i < k0 + b) {
+      A[i * ld + k0 + s] = Ps[i - k0][s];
+      for (int q = 0; q <= m; ++q) {
+        R[int64_t(q * NB + s) * n + i] = make_double2(0, 0);
+        Cp[i * LDC + q * NB + s] = make_double2(0, 0);
+      }
+      continue;
     }
-    return;
+    double2 acc = make_double2(0, 0);
+    for (int t = 0; t < b; ++t) {
+      const double2 c = Cs[r][t], p = Ps[t][s];
+      acc.x += c.x * p.x - c.y * p.y;
+      acc.y += c.x * p.y + c.y * p.x;
+    }
+    A[i * ld + k0 + s] = make_double2(-acc.x, -acc.y);
   }
-  R += int64_t(m) * NB * n;
-  Cp += m * NB;
-  A[(k0 + s) * ld + i] = R[s * n + i];
-  double2 acc = make_double2(0, 0);
-  for (int t = 0; t < b; ++t) {
-    const double2 c = Cp[i * LDC + t], p = Ps[t][s];
-    acc.x += c.x * p.x - c.y * p.y;
-    acc.y += c.x * p.y + c.y * p.x;
+  for (int e = threadIdx.x; e < 16 * NB; e += blockDim.x) {
+    const int64_t j = r0 + e % 16;
+    const int ss = e / 16;
+    if (j >= n || ss >= b || (j >= k0 && j < k0 + b)) continue;
+    A[(k0 + ss) * ld + j] = Rm[int64_t(ss) * n + j];
   }
-  A[i * ld + k0 + s] = make_double2(-acc.x, -acc.y);
 }
 
 // ------------------------------------------------------------- builders
@@ -667,7 +683,7 @@ void dense_invert(double2* A, int64_t n, int64_t ld, DenseScratch& ws, hipStream
   if (n <= 0) return;
   const int kind = dense_update_kind();
   const int G = dense_group();
-  const unsigned gp = unsigned((n + 31) / 32), gw = unsigned((n + 3) / 4);
+  const unsigned gp = unsigned((n + 31) / 32), gw = unsigned((n + 15) / 16);
   for (int64_t k0 = 0; k0 < n;) {
     const int npan = int(std::min<int64_t>(G, (n - k0 + dev::NB - 1) / dev::NB));
     int blast = 0;
