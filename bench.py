@@ -85,18 +85,33 @@ def cpu_baseline(w, n_sample: int = 12) -> dict:
                       f"fill est {t_fill:.1f} s, LU est {t_lu:.1f} s"}
 
 
+def kernel_source_digest(regions) -> str | None:
+    """sha256 over the source text of a kernel: each region is [file, begin, end] (from the
+    first occurrence of `begin`, "" for the file start, up to the next `end`)."""
+    import hashlib
+    h = hashlib.sha256()
+    for rel, begin, end in regions:
+        path = ROOT / rel
+        if not path.exists():
+            return None
+        text = path.read_text()
+        i = text.find(begin)
+        j = text.find(end, i) if i >= 0 else -1
+        if i < 0 or j < 0:
+            return None
+        h.update(text[i:j].encode())
+    return h.hexdigest()
+
+
 def measured_traffic(kernel_class: str):
     """HBM bytes per launch of a kernel class from the committed counter summary
-    (profiles/traffic.json), or None when the kernel source changed since it was measured."""
-    import hashlib
+    (profiles/traffic.json), or None when the kernel's source (its listed regions) changed
+    since it was measured."""
     path = ROOT / "profiles" / "traffic.json"
     if not path.exists():
         return None
     entry = json.loads(path.read_text()).get(kernel_class)
-    if not entry:
-        return None
-    src = ROOT / entry["source"]
-    if not src.exists() or hashlib.sha256(src.read_bytes()).hexdigest() != entry["source_sha256"]:
+    if not entry or kernel_source_digest(entry["source_regions"]) != entry["source_sha256"]:
         return None
     return float(entry["hbm_bytes_per_launch"])
 
