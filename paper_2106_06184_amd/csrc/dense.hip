@@ -48,85 +48,89 @@ __device__ __forceinline__ double2 cinv(double2 a) {
   return make_double2(a.x / d, -a.y / d);
 }
 
-// In-place inversion of the b x b diagonal block, copied to P (ld NB).  Thread t keeps the 4 x 4
-// sub-block (rows 4 (t / 16) + [0, 4), columns 4 (t % 16) + [0, 4)) of the block in registers;
-// at pivot p the owners of row p and of column p publish them in LDS (double-buffered by the
-// parity of p, so one barrier per pivot suffices) and every thread updates its 16 entries:
+// In-place inversion of the b x b diagonal block, copied to P (ld NB).  Thread t keeps the
+// S x S sub-block (rows S (t / (NB/S)) + [0, S), columns S (t % (NB/S)) + [0, S)) of the block in
+// registers; at pivot p the owners of row p and of column p publish them in LDS (double-buffered
+// by the parity of p, so one barrier per pivot suffices) and every thread updates its entries:
 //   M[p][p] <- 1/a,  M[p][c] <- M[p][c]/a,  M[r][p] <- -M[r][p]/a,
 //   M[r][c] <- M[r][c] - M[r][p] M[p][c]/a      (a = M[p][p] before the step).
-// Entries outside the b x b block are identity (so padded pivots are 1).
-__global__ void __launch_bounds__(256) k_gj_diag(double2* __restrict__ A, int64_t ld, int64_t k0, int b,
-                                                 double2* __restrict__ P) {
+// Entries outside the b x b block are identity (so padded pivots are 1).  The pivots form a
+// serial chain, so the sub-blocks are small (S = 2: 1024 threads) to keep each step short.
+constexpr int kDiagS = 2;
+constexpr int kDiagThreads = (NB / kDiagS) * (NB / kDiagS);
+__global__ void __launch_bounds__(kDiagThreads) k_gj_diag(double2* __restrict__ A, int64_t ld, int64_t k0, int b,
+                                                          double2* __restrict__ P) {
+  constexpr int S = kDiagS, W = NB / S;
   __shared__ double2 rowp[2][NB], colp[2][NB];
   const int t = threadIdx.x;
-  const int r0 = 4 * (t >> 4), c0 = 4 * (t & 15);
-  double2 m[4][4];
+  const int r0 = S * (t / W), c0 = S * (t % W);
+  double2 m[S][S];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < S; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < S; ++j) {
       const int r = r0 + i, c = c0 + j;
       m[i][j] = (r < b && c < b) ? A[(k0 + r) * ld + k0 + c] : make_double2(r == c ? 1.0 : 0.0, 0.0);
     }
   for (int p = 0; p < NB; ++p) {
     const int buf = p & 1;
-    const int pl = p & 3;
+    const int pl = p % S;
     // (register arrays are indexed with compile-time constants only, so they stay in VGPRs)
-    if ((p >> 2) == (r0 >> 2)) {
+    if (p / S == r0 / S) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < S; ++i)
         if (i == pl) {
 #pragma unroll
-          for (int j = 0; j < 4; ++j) rowp[buf][c0 + j] = m[i][j];
+          for (int j = 0; j < S; ++j) rowp[buf][c0 + j] = m[i][j];
         }
     }
-    if ((p >> 2) == (c0 >> 2)) {
+    if (p / S == c0 / S) {
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
+      for (int j = 0; j < S; ++j)
         if (j == pl) {
 #pragma unroll
-          for (int i = 0; i < 4; ++i) colp[buf][r0 + i] = m[i][j];
+          for (int i = 0; i < S; ++i) colp[buf][r0 + i] = m[i][j];
         }
     }
     __syncthreads();
     const double2 inv = cinv(rowp[buf][p]);
-    double2 g[4], cr[4];
+    double2 g[S], cr[S];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) g[j] = cm(rowp[buf][c0 + j], inv);
+    for (int j = 0; j < S; ++j) g[j] = cm(rowp[buf][c0 + j], inv);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) cr[i] = colp[buf][r0 + i];
+    for (int i = 0; i < S; ++i) cr[i] = colp[buf][r0 + i];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < S; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < S; ++j) {
         m[i][j].x -= cr[i].x * g[j].x - cr[i].y * g[j].y;
         m[i][j].y -= cr[i].x * g[j].y + cr[i].y * g[j].x;
       }
     // pivot row and column: M[p][c] = g[c], M[r][p] = -M[r][p] / a (old M[r][p] = colp), M[p][p] = 1/a
-    if ((p >> 2) == (c0 >> 2)) {
+    if (p / S == c0 / S) {
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
+      for (int j = 0; j < S; ++j)
         if (j == pl) {
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
+          for (int i = 0; i < S; ++i) {
             const double2 v = cm(cr[i], inv);
             m[i][j] = make_double2(-v.x, -v.y);
           }
         }
     }
-    if ((p >> 2) == (r0 >> 2)) {
+    if (p / S == r0 / S) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < S; ++i)
         if (i == pl) {
 #pragma unroll
-          for (int j = 0; j < 4; ++j) m[i][j] = (c0 + j == p) ? inv : g[j];
+          for (int j = 0; j < S; ++j) m[i][j] = (c0 + j == p) ? inv : g[j];
         }
     }
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < S; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) P[(r0 + i) * NB + c0 + j] = m[i][j];
+    for (int j = 0; j < S; ++j) P[(r0 + i) * NB + c0 + j] = m[i][j];
 }
 
 // R[s][j] = sum_t P[s][t] A[k0+t][j] for all j (thread: one column, 8 values of s; 32 columns
@@ -696,7 +700,7 @@ void dense_invert(double2* A, int64_t n, int64_t ld, DenseScratch& ws, hipStream
       }
       double2* Rm = ws.R + int64_t(mp) * dev::NB * n;
       double2* Cm = ws.C + mp * dev::NB;
-      hipLaunchKernelGGL(dev::k_gj_diag, dim3(1), dim3(256), 0, st, A, ld, km, bm, ws.P);
+      hipLaunchKernelGGL(dev::k_gj_diag, dim3(1), dim3(dev::kDiagThreads), 0, st, A, ld, km, bm, ws.P);
       hipLaunchKernelGGL(dev::k_gj_panels, dim3(gp), dim3(256), 0, st, A, ld, n, km, bm, ws.P, Rm, Cm);
       if (mp + 1 < npan)
         hipLaunchKernelGGL(dev::k_gj_write, dim3(gw), dim3(256), 0, st, A, ld, n, km, bm, ws.P, ws.R, ws.C, mp);
