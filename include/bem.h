@@ -276,7 +276,7 @@ int bem_op_stats_get(bem_ctx* ctx, bem_op_h op, bem_op_stats* out);
  * on the launch stream around every fill, gather and dense-product launch, together with the
  * launch's algorithmic bytes and work.  Enabling clears the counters.  Classes: 0 float64
  * products, 1 float32 products, 2 L fill, 3 K~ fill, 4 near corrections, 5 gathers, 6 float32
- * matrix-core products (several excitations), 7 rank-64 updates of the dense inversions,
+ * matrix-core products (several excitations), 7 Gauss-Jordan panel updates of the dense inversions,
  * 8 float64 matrix-core products.  bem_profile_read waits for the recorded events. */
 int bem_profile_enable(int on);
 int bem_profile_read(int kernel_class, int64_t* launches, double* ms, double* bytes, double* work);

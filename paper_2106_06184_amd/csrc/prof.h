@@ -18,7 +18,7 @@ enum KernelClass : int {
   KC_FILL_NEAR = 4,  // near-pair singular corrections
   KC_GATHER = 5,     // half-RWG / cell to edge gathers (bytes = read + written)
   KC_GEMM_F32 = 6,   // multi-excitation products on matrix cores (work = real flops)
-  KC_DENSE_INV = 7,  // rank-64 updates of the dense inversions (work = real flops)
+  KC_DENSE_INV = 7,  // Gauss-Jordan panel updates of the dense inversions (work = real flops)
   KC_GEMM_F64 = 8,   // multi-excitation products, float64 matrix cores (work = real flops)
   KC_COUNT = 9
 };
