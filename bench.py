@@ -146,9 +146,10 @@ def run_serve(args) -> int:
         args.restart = 200
     ctx = B.bem_create(0)
     opts = B.solve_opts(tol=args.tol, restart=args.restart, maxit=args.maxit, max_refine=8)
+    prec = B.BEM_MIXED if args.precision == "mixed" else B.BEM_FP64
 
     def request(w):
-        prob = B.make_problem(w.freq_hz, w.eps_r, w.mu_r, w.sigma, precision=B.BEM_MIXED)
+        prob = B.make_problem(w.freq_hz, w.eps_r, w.mu_r, w.sigma, precision=prec)
         return B.Request(w.xyz, w.tri, w.obj, prob, B.plane_waves(w.khat, w.pol), opts)
 
     # warm-up: one small request alone (kernel loading, allocator)
@@ -184,10 +185,10 @@ def run_serve(args) -> int:
         "metric": "serving: completed requests/s with p50/p99 latency at 1e-6 relative residual",
         "value": ok / wall, "unit": "requests/s", "n_gpus": 1, "steps": len(reqs), "warmup": 1,
         "ms_per_step": 1e3 * wall / len(reqs), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "vs_baseline": None, "dtype": "f32+f64" if args.precision == "mixed" else "f64", "data": "synthetic",
         "config": {"workload": f"serving stream: {len(reqs)} requests, Poisson {args.serve_rate}/s, spheres/"
                                "ellipsoids/cubes 300-3072 triangles, eps_r 1.5-6, k0a 0.5-3, 1-16 plane waves",
-                   "tol": args.tol, "restart": args.restart, "precision": "mixed"},
+                   "tol": args.tol, "restart": args.restart, "precision": args.precision},
         "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
         "excitation_solves_per_s": n_exc / wall, "converged": ok,
         "combined_launches": launches, "combined_products": products,

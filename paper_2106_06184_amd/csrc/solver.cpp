@@ -1846,7 +1846,9 @@ int solve_op(OpObj& op, const bem_excitation* exc, int64_t nexc, const bem_solve
   build_rhs(op, tmp, exc, nexc, Bexc, st);
   const double inner = opts.inner_tol > 0 ? opts.inner_tol : 0.1 * opts.tol;
   const double inner32 = std::max(inner, 1e-7);
-  const double stol = std::max(opts.tol * 0.5, 1e-6);
+  // a float32 sweep is not asked for more than 1e-6 of its right-hand side: float32 products
+  // do not carry the true residual further
+  constexpr double kFp32SweepFloor = 1e-6;
   const int sweeps = opts.max_refine > 0 ? opts.max_refine : (op.precision == BEM_MIXED ? 5 : 3);
   bem_solve_info inf{};
   int status = BEM_OK;
@@ -1963,14 +1965,13 @@ int solve_op(OpObj& op, const bem_excitation* exc, int64_t nexc, const bem_solve
         launch_axpby(N, c2(1.0), rr, c2(-1.0), bw.T, rr, st, Rc, ldN, bw.ldv, ldN);
       }
       BEM_HIP(hipStreamSynchronize(st));
-      // GMRES target relative to ||r||: float32 sweeps reduce by stol; float64 sweeps aim at
-      // tol ||b|| directly (half of it, for margin)
-      double gtol = stol;
-      if (!use32) {
-        gtol = 1.0;
-        for (int c = 0; c < Rc; ++c) gtol = std::min(gtol, 0.5 * opts.tol / std::max(rel[active[c]], 1e-300));
-        gtol = std::max(gtol, 1e-15);
-      }
+      // GMRES target relative to ||r||: every sweep aims at what the tolerance still needs,
+      // tol ||b|| (half of it, for margin).  Float32 sweeps stop at their floor (the first one
+      // usually ends there) and reduce by at least 4x (so a sweep that does not halve the
+      // true residual has met float32's limit); float64 sweeps have no such floor.
+      double gtol = use32 ? 0.25 : 1.0;
+      for (int c = 0; c < Rc; ++c) gtol = std::min(gtol, 0.5 * opts.tol / std::max(rel[active[c]], 1e-300));
+      gtol = std::max(gtol, use32 ? kFp32SweepFloor : 1e-15);
       // a float32 sweep gets at most three restart cycles (600 steps at least): one that cannot
       // reach its target in that budget works on products too inaccurate in float32
       const int budget = use32 ? std::min(left, std::max(3 * opts.restart, 600)) : left;

@@ -101,6 +101,34 @@ def test_transparent_object_identity_fullsize(c2):
     assert err < 1e-6
 
 
+def test_mixed_precision_currents_fullsize(c2):
+    """The benchmark's problem solved with float64 products to a 1e-10 residual and with
+    float32 products plus float64 refinement: refined to a 1e-9 residual, the mixed currents
+    (H, E, rho) are within 1e-6 of the float64 ones; the deviation of the benchmark's own
+    stopping point (1e-6) is printed beside it."""
+    w, _ = c2
+    ctx = B.bem_create(0)
+    mesh = B.bem_mesh_load(ctx, w.xyz, w.tri, w.obj)
+    info = B.bem_mesh_info(ctx, mesh)
+    exc = B.plane_waves(w.khat, w.pol)
+    sol = {}
+    for name, prec, tol in (("fp64", B.BEM_FP64, 1e-10), ("mixed", B.BEM_MIXED, 1e-9),
+                            ("mixed_bench", B.BEM_MIXED, 1e-6)):
+        op = B.bem_assemble(ctx, mesh, B.make_problem(w.freq_hz, w.eps_r, w.mu_r, w.sigma, precision=prec))
+        rc, H, E, rho, si = B.bem_solve(ctx, op, exc, B.solve_opts(tol=tol, restart=300, maxit=4000, max_refine=8),
+                                        info["n_edge"], info["n_tri"])
+        B.bem_release(ctx, op)
+        assert rc == B.BEM_OK and si.rel_residual <= tol, (name, rc, si.rel_residual)
+        print(f"{name}: outer {si.outer_iters}, residual {si.rel_residual:.2e}")
+        sol[name] = (H[:, 0], E[:, 0], rho[:, 0])
+    B.bem_destroy(ctx)
+    for name in ("mixed", "mixed_bench"):
+        errs = [rel(got, want) for got, want in zip(sol[name], sol["fp64"])]
+        print(f"{name} vs fp64: H {errs[0]:.2e}, E {errs[1]:.2e}, rho {errs[2]:.2e}")
+        if name == "mixed":
+            assert max(errs) < 1e-6, errs
+
+
 def _c4_pair():
     """Two neighbouring bars of the conductor-array workload (its graded 1408-triangle bar mesh,
     0.05-1 um edges), with the array's port ring on the first."""
