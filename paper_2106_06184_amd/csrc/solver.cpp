@@ -1568,8 +1568,15 @@ struct BResult {
 // (and the right preconditioner M) to the block of the still-active columns in one call.
 // A column stops contributing basis vectors once its estimated residual reaches tol; at
 // every restart the unconverged columns are compacted.
+// Relaxed products (A_lo, M_lo: the float32 operator and preconditioner): once the largest
+// estimated relative residual of the active columns is at most `relax`, the Arnoldi steps use
+// them in place of A and M.  The error a cruder product adds to the solution is scaled by the
+// basis coefficients of its step, which shrink with the residual, so early steps get accurate
+// products and late ones cheap products (relaxation in inexact Krylov methods: Bouras and
+// Fraysse 2005, Simoncini and Szyld 2003).  Restart residuals and the solution update use A, M.
 BResult gmres_batched(BGmres& w, const BApplyFn& A, const double2* B, int64_t ldb, double2* X, int64_t ldx, int R0,
-                      double tol, int maxit, hipStream_t st, const BApplyFn* M) {
+                      double tol, int maxit, hipStream_t st, const BApplyFn* M, const BApplyFn* A_lo = nullptr,
+                      const BApplyFn* M_lo = nullptr, double relax = 0.0) {
   BResult out;
   out.iters.assign(R0, 0);
   out.relres.assign(R0, 0.0);
@@ -1605,11 +1612,13 @@ BResult gmres_batched(BGmres& w, const BApplyFn& A, const double2* B, int64_t ld
     first = false;
     w.norms(V0, ldv, Rc, st);
     int live = 0;
+    double worst_est = 0.0;  // largest estimated relative residual of the active columns
     for (int c = 0; c < Rc; ++c) {
       const int col = active[c];
       const double beta = w.h_nrm[c].x;
       if (!std::isfinite(beta)) throw Error(BEM_E_NUMERIC, "non-finite residual in GMRES");
       out.relres[col] = beta / bn[col];
+      if (out.relres[col] > tol) worst_est = std::max(worst_est, out.relres[col]);
       w.h_frozen[c] = out.relres[col] <= tol ? 1 : 0;
       w.h_jr[c] = 0;
       if (w.h_frozen[c]) out.converged[col] = 1;
@@ -1650,17 +1659,25 @@ BResult gmres_batched(BGmres& w, const BApplyFn& A, const double2* B, int64_t ld
       if (verbose())
         std::fprintf(stderr, "[bem] batched step %d: %d of %d columns active, worst res %.3e\n", s + 1, live, Rc,
                      worst);
+      worst_est = worst;
       return changed;
     };
+    bool lo = false;
     for (; j < m && total < maxit; ++j) {
       double2* Vj = w.V + int64_t(j) * Rc * ldv;
       double2* Vn = w.V + int64_t(j + 1) * Rc * ldv;
       double2* Hj = w.H + int64_t(j) * w.ldh;
-      if (M) {
-        (*M)(Vj, ldv, w.Z, ldv, Rc);
-        A(w.Z, ldv, Vn, ldv, Rc);
+      if (A_lo && !lo && worst_est <= relax) {
+        lo = true;
+        if (verbose()) std::fprintf(stderr, "[bem] relaxed products from step %d (residual %.3e)\n", j, worst_est);
+      }
+      const BApplyFn& Aj = lo ? *A_lo : A;
+      const BApplyFn* Mj = lo ? M_lo : M;
+      if (Mj) {
+        (*Mj)(Vj, ldv, w.Z, ldv, Rc);
+        Aj(w.Z, ldv, Vn, ldv, Rc);
       } else {
-        A(Vj, ldv, Vn, ldv, Rc);
+        Aj(Vj, ldv, Vn, ldv, Rc);
       }
       ++out.products;
       launch_bmdot(w.V, ldv, Rc, j + 1, Vn, ldv, n, w.part, Hj, w.hs, st);
@@ -1846,9 +1863,12 @@ int solve_op(OpObj& op, const bem_excitation* exc, int64_t nexc, const bem_solve
   build_rhs(op, tmp, exc, nexc, Bexc, st);
   const double inner = opts.inner_tol > 0 ? opts.inner_tol : 0.1 * opts.tol;
   const double inner32 = std::max(inner, 1e-7);
-  // a float32 sweep is not asked for more than 1e-6 of its right-hand side: float32 products
-  // do not carry the true residual further
-  constexpr double kFp32SweepFloor = 1e-6;
+  // Mixed precision: a sweep runs float64 products until the estimated residual is sqrt(tol)
+  // of ||b||, then float32 products (relaxed products of gmres_batched).  With float32 products
+  // from the first step the true residual stalls near the float32 operator's error times the
+  // solution's size (1.4e-4 on the 5120-triangle sphere, against 1e-6 estimated), and every
+  // refinement sweep restarts the Krylov space; scaled by sqrt(tol) that error is below tol.
+  const double relax_global = std::sqrt(opts.tol);
   const int sweeps = opts.max_refine > 0 ? opts.max_refine : (op.precision == BEM_MIXED ? 5 : 3);
   bem_solve_info inf{};
   int status = BEM_OK;
@@ -1926,13 +1946,13 @@ int solve_op(OpObj& op, const bem_excitation* exc, int64_t nexc, const bem_solve
       if (verbose()) std::fprintf(stderr, "[bem] float32 product deviation %.3e%s\n", dev, fp32_ok ? "" : ": float64 products");
     }
     // One refinement loop for both precisions.  Every sweep solves A d = r for the active
-    // columns with GMRES (float32 products while in mixed precision, float64 otherwise), then
-    // x += d and the float64 residual r = b - A x is recomputed; a column leaves once
-    // ||r|| <= tol ||b||.  A float32 sweep that does not halve the residual of every active
-    // column, or that does not reach its target within three restart cycles, switches the
-    // remaining sweeps to float64 products (float32 too inaccurate for this operator); in
-    // float64 precision the sweeps after the first correct the Arnoldi estimate drifting from
-    // the true residual.
+    // columns with GMRES (in mixed precision float64 products until the residual is small,
+    // float32 products after; float64 products otherwise), then x += d and the float64
+    // residual r = b - A x is recomputed; a column leaves once ||r|| <= tol ||b||.  A mixed
+    // sweep that does not halve the residual of every active column, or that does not reach
+    // its target within three restart cycles, switches the remaining sweeps to float64
+    // products (float32 too inaccurate for this operator); the sweeps after the first correct
+    // the Arnoldi estimate drifting from the true residual.
     launch_axpby(N, c2(0.0), nullptr, c2(0.0), nullptr, xs, st, R, 0, 0, ldN);
     bw.norms(bfull, ldN, R, st);
     std::vector<double> bn(R), rel(R, 1.0);
@@ -1966,16 +1986,21 @@ int solve_op(OpObj& op, const bem_excitation* exc, int64_t nexc, const bem_solve
       }
       BEM_HIP(hipStreamSynchronize(st));
       // GMRES target relative to ||r||: every sweep aims at what the tolerance still needs,
-      // tol ||b|| (half of it, for margin).  Float32 sweeps stop at their floor (the first one
-      // usually ends there) and reduce by at least 4x (so a sweep that does not halve the
-      // true residual has met float32's limit); float64 sweeps have no such floor.
-      double gtol = use32 ? 0.25 : 1.0;
-      for (int c = 0; c < Rc; ++c) gtol = std::min(gtol, 0.5 * opts.tol / std::max(rel[active[c]], 1e-300));
-      gtol = std::max(gtol, use32 ? kFp32SweepFloor : 1e-15);
+      // tol ||b|| (half of it, for margin); a mixed sweep reduces by at least 4x (so one that
+      // does not halve the true residual has met float32's limit).  Its switch to float32
+      // products is relative to ||r|| too.
+      double gtol = use32 ? 0.25 : 1.0, rmax = 0.0;
+      for (int c = 0; c < Rc; ++c) {
+        gtol = std::min(gtol, 0.5 * opts.tol / std::max(rel[active[c]], 1e-300));
+        rmax = std::max(rmax, rel[active[c]]);
+      }
+      gtol = std::max(gtol, 1e-15);
+      const double relax = relax_global / std::max(rmax, 1e-300);
       // a float32 sweep gets at most three restart cycles (600 steps at least): one that cannot
       // reach its target in that budget works on products too inaccurate in float32
       const int budget = use32 ? std::min(left, std::max(3 * opts.restart, 600)) : left;
-      BResult g = gmres_batched(bw, use32 ? A32 : A64, rr, ldN, dd, ldN, Rc, gtol, budget, st, use32 ? Pm32 : Pm64);
+      BResult g = use32 ? gmres_batched(bw, A64, rr, ldN, dd, ldN, Rc, gtol, budget, st, Pm64, &A32, Pm32, relax)
+                        : gmres_batched(bw, A64, rr, ldN, dd, ldN, Rc, gtol, budget, st, Pm64);
       bool sweep_failed = false;
       for (int c = 0; c < Rc; ++c) sweep_failed |= !g.converged[c];
       int most = 0;
@@ -1992,6 +2017,9 @@ int solve_op(OpObj& op, const bem_excitation* exc, int64_t nexc, const bem_solve
       launch_gather_cols(bfull, ldN, rr, ldN, didx, N, Rc, st);
       std::vector<double> r = true_residuals(bw, A64, rr, dd, ldN, Rc, st);
       ++inf.n_products;
+      if (verbose())
+        std::fprintf(stderr, "[bem] sweep %d %s: target %.2e, %d steps, true residual %.3e\n", s,
+                     use32 ? "mixed" : "float64", gtol, most, *std::max_element(r.begin(), r.end()));
       bool stalled = false;
       std::vector<int> next;
       for (int c = 0; c < Rc; ++c) {
