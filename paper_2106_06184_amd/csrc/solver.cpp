@@ -1568,12 +1568,16 @@ struct BResult {
 // (and the right preconditioner M) to the block of the still-active columns in one call.
 // A column stops contributing basis vectors once its estimated residual reaches tol; at
 // every restart the unconverged columns are compacted.
-// Relaxed products (A_lo, M_lo: the float32 operator and preconditioner): once the largest
+// Relaxed products (A_lo, M_lo: a cheaper operator and preconditioner): once the largest
 // estimated relative residual of the active columns is at most `relax`, the Arnoldi steps use
-// them in place of A and M.  The error a cruder product adds to the solution is scaled by the
-// basis coefficients of its step, which shrink with the residual, so early steps get accurate
-// products and late ones cheap products (relaxation in inexact Krylov methods: Bouras and
-// Fraysse 2005, Simoncini and Szyld 2003).  Restart residuals and the solution update use A, M.
+// them in place of A and M (M_lo must equal M unless the steps and the solution update agree
+// on it: the update applies M to V y).  The error a cruder product adds to the solution is
+// scaled by the basis coefficients of its step, which shrink with the residual, so early steps
+// get accurate products and late ones cheap products (relaxation in inexact Krylov methods:
+// Bouras and Fraysse 2005, Simoncini and Szyld 2003).  Only the first cycle relaxes: a
+// restarted cycle works on the slowly converging components, whose large coefficients take the
+// cruder products' error whole (float32 cycles after a restart made no true progress on the
+// 5120-triangle sphere).  Restart residuals and the solution update use A and M.
 BResult gmres_batched(BGmres& w, const BApplyFn& A, const double2* B, int64_t ldb, double2* X, int64_t ldx, int R0,
                       double tol, int maxit, hipStream_t st, const BApplyFn* M, const BApplyFn* A_lo = nullptr,
                       const BApplyFn* M_lo = nullptr, double relax = 0.0) {
@@ -1595,7 +1599,7 @@ BResult gmres_batched(BGmres& w, const BApplyFn& A, const double2* B, int64_t ld
   }
   launch_axpby(n, c2(0.0), nullptr, c2(0.0), nullptr, X, st, R0, 0, 0, ldx);
   int total = 0;  // batched Arnoldi steps
-  bool first = true;
+  bool first = true, first_cycle = true;
   while (!active.empty()) {
     const int Rc = int(active.size());
     for (int c = 0; c < Rc; ++c) w.h_idx[c] = active[c];
@@ -1667,7 +1671,7 @@ BResult gmres_batched(BGmres& w, const BApplyFn& A, const double2* B, int64_t ld
       double2* Vj = w.V + int64_t(j) * Rc * ldv;
       double2* Vn = w.V + int64_t(j + 1) * Rc * ldv;
       double2* Hj = w.H + int64_t(j) * w.ldh;
-      if (A_lo && !lo && worst_est <= relax) {
+      if (A_lo && first_cycle && !lo && worst_est <= relax) {
         lo = true;
         if (verbose()) std::fprintf(stderr, "[bem] relaxed products from step %d (residual %.3e)\n", j, worst_est);
       }
@@ -1724,6 +1728,7 @@ BResult gmres_batched(BGmres& w, const BApplyFn& A, const double2* B, int64_t ld
     for (int c = 0; c < Rc; ++c)
       if (!out.converged[active[c]]) next.push_back(active[c]);
     active.swap(next);
+    first_cycle = false;
     if (total >= maxit) break;
   }
   return out;
@@ -1913,12 +1918,7 @@ int solve_op(OpObj& op, const bem_excitation* exc, int64_t nexc, const bem_solve
     if (ldx != ldy) throw Error(BEM_E_INVALID, "preconditioner needs equal strides");
     precond_cols(op, with_R(R), x, y, ldx, false, st);
   };
-  BApplyFn P32 = [&](const double2* x, int64_t ldx, double2* y, int64_t ldy, int R) {
-    if (ldx != ldy) throw Error(BEM_E_INVALID, "preconditioner needs equal strides");
-    precond_cols(op, with_R(R), x, y, ldx, true, st);
-  };
   const BApplyFn* Pm64 = op.precond ? &P64 : nullptr;
-  const BApplyFn* Pm32 = op.precond ? &P32 : nullptr;
 
   // Mixed precision pays only while the float32 products stay close to the float64 ones on
   // vectors shaped like the solution: once per solve, z = P b (b the first excitation's
@@ -1999,7 +1999,9 @@ int solve_op(OpObj& op, const bem_excitation* exc, int64_t nexc, const bem_solve
       // a float32 sweep gets at most three restart cycles (600 steps at least): one that cannot
       // reach its target in that budget works on products too inaccurate in float32
       const int budget = use32 ? std::min(left, std::max(3 * opts.restart, 600)) : left;
-      BResult g = use32 ? gmres_batched(bw, A64, rr, ldN, dd, ldN, Rc, gtol, budget, st, Pm64, &A32, Pm32, relax)
+      // (the preconditioner stays float64: the solution update applies it to V y, so the steps
+      // must have applied the same one)
+      BResult g = use32 ? gmres_batched(bw, A64, rr, ldN, dd, ldN, Rc, gtol, budget, st, Pm64, &A32, Pm64, relax)
                         : gmres_batched(bw, A64, rr, ldN, dd, ldN, Rc, gtol, budget, st, Pm64);
       bool sweep_failed = false;
       for (int c = 0; c < Rc; ++c) sweep_failed |= !g.converged[c];
