@@ -369,18 +369,22 @@ __global__ void __launch_bounds__(128) k_fill_K_far(FillKArgs a) {
 }
 
 // ------------------------------------------------------------------ K near
-// Thread per near (T, cell) pair: recompute the whole cell with the far moments for far
-// sub-triangles and, for sub-triangles whose primal triangle is near T and not coplanar with
+// 2 MAXV lanes per near (T, cell) pair, one per sub-triangle of the cell (so a small mesh still
+// fills the GPU): recompute the whole cell with the far moments for far sub-triangles and, for sub-triangles whose primal triangle is near T and not coplanar with
 // it, with the extracted inner integral v_k = int_t g_k (r_k - r') dS':
 //   v_k = -J/(4 pi) + k^2/(8 pi) Iv + sum_j w_j A_t h(R_kj) (r_k - r'_j)
 // and the contribution 1/(4 A_t) sum_k w_k (r_k - p_i) . [v_k x (alpha (r_k - v) - beta)].
+// The lanes' contributions are added by a butterfly over the pair's lanes (fixed order).
 template <bool LOSSY, int MAXV>
 __global__ void __launch_bounds__(64) k_fill_K_near(FillKArgs a, const int32_t* __restrict__ pt,
                                                     const int32_t* __restrict__ pc, int64_t npairs,
                                                     const int64_t* __restrict__ near_ptr,
                                                     const int32_t* __restrict__ near_idx) {
-  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (p >= npairs) return;
+  constexpr int LANES = 2 * MAXV;  // divides 64: a pair's lanes share a wave
+  const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t p = gid / LANES;
+  const int sidx = int(gid % LANES);
+  if (p >= npairs) return;  // whole lane groups leave together
   const int64_t t = pt[p];
   const int32_t v = pc[p];
   const int64_t nc = a.ncell_total;
@@ -397,7 +401,7 @@ __global__ void __launch_bounds__(64) k_fill_K_near(FillKArgs a, const int32_t* 
   cz acc[MAXV][3];
   for (int b = 0; b < MAXV; ++b)
     for (int i = 0; i < 3; ++i) acc[b][i] = {0, 0};
-  for (int sidx = 0; sidx < 2 * nval; ++sidx) {
+  if (sidx < 2 * nval) do {
     const size_t so = size_t(sidx) * nc + v;
     const v3 sm = mk(a.sub_m[3 * so], a.sub_m[3 * so + 1], a.sub_m[3 * so + 2]);
     const v3 sc = mk(a.sub_c[3 * so], a.sub_c[3 * so + 1], a.sub_c[3 * so + 2]);
@@ -466,12 +470,12 @@ __global__ void __launch_bounds__(64) k_fill_K_near(FillKArgs a, const int32_t* 
           }
         }
       }
-      continue;
+      break;
     }
     // near: zero when coplanar with the test triangle
     const v3 nP = G3(geo, nt, kGeoN, par);
     const v3 cP = G3(geo, nt, kGeoC, par);
-    if (fabs(dot(nP, nT)) > 1.0 - 1e-12 && fabs(dot(cP - ct, nT)) < 1e-10 * hT) continue;
+    if (fabs(dot(nP, nT)) > 1.0 - 1e-12 && fabs(dot(cP - ct, nT)) < 1e-10 * hT) break;
     // sub-triangle vertices relative to v: (0, m, c) (the closed forms do not depend on the
     // vertex order)
     const v3 A0 = mk(0, 0, 0), A1 = sm, A2 = sc;
@@ -515,7 +519,14 @@ __global__ void __launch_bounds__(64) k_fill_K_near(FillKArgs a, const int32_t* 
         }
       }
     }
-  }
+  } while (false);
+  for (int b = 0; b < MAXV; ++b)
+    for (int i = 0; i < 3; ++i)
+      for (int off = 1; off < LANES; off <<= 1) {
+        acc[b][i].re += __shfl_xor(acc[b][i].re, off);
+        acc[b][i].im += __shfl_xor(acc[b][i].im, off);
+      }
+  if (sidx != 0) return;
   double2* out = a.Kc + (3 * (t - a.t0)) * a.ldK + a.col0[v];
   for (int b = 0; b < MAXV; ++b)
     if (b < nval)
@@ -682,7 +693,7 @@ void launch_fill_K(const FillKArgs& a, const int32_t* near_t, const int32_t* nea
   if (a.ncells <= 0 || a.nt_test <= 0) return;
   dim3 grid(unsigned((a.ncells + 127) / 128), unsigned((a.nt_test + a.tchunk - 1) / a.tchunk));
   bool lossy = a.ki != 0.0;
-  dim3 g2(unsigned((npairs + 63) / 64));
+  dim3 g2(unsigned((npairs * 2 * maxv + 63) / 64));
   // every primal triangle of the object contributes 6 sub-triangles, 7 x 3 evaluations each
   const double kwork = double(a.nt_test) * 6.0 * a.nt_test * 21.0;
   const double kbytes = 3.0 * a.nt_test * a.ldK * 16.0;

@@ -552,7 +552,13 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
     tmp_dev.push_back(p);
     return p;
   };
-  const int64_t tchunk = 8;
+  // test triangles per block of a far-fill launch: 8 (the per-source set-up is shared by 8
+  // rows), fewer while that leaves under 2048 blocks (small meshes: one CU per block row
+  // would leave most of the GPU idle).  Each entry is computed the same way in any chunking.
+  auto tchunk_for = [](int64_t nsrc, int64_t per_block, int64_t ntest) {
+    const int64_t bx = (nsrc + per_block - 1) / per_block;
+    return std::max<int64_t>(1, std::min<int64_t>(8, bx * ntest / 2048));
+  };
   // source triangles [s0, s0 + ns) of which some need their rules subdivided at k (the
   // barycentric sub-triangles are smaller than their parents, so this covers K~ as well)
   auto needs_sub = [&](cd k, int64_t s0, int64_t ns) {
@@ -564,7 +570,8 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
   {
     int32_t* pt = up32(na_t);
     int32_t* ps = up32(na_s);
-    FillLArgs la{op.geo, nt, 0, nt, 0, nt, tchunk, op.kbg.real(), op.kbg.imag(), H, 3 * nt, op.Lphi_bg.d64,
+    FillLArgs la{op.geo, nt, 0, nt, 0, nt, tchunk_for(nt, 256, nt), op.kbg.real(), op.kbg.imag(), H, 3 * nt,
+                 op.Lphi_bg.d64,
                  op.Lphi_bg.ld};
     la.sub = needs_sub(op.kbg, 0, nt);
     launch_fill_L(la, pt, ps, int64_t(na_t.size()), st);
@@ -579,7 +586,8 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
     if (own_int) {
       int32_t* pt = up32(no_t[o]);
       int32_t* ps = up32(no_s[o]);
-      FillLArgs la{op.geo, nt, t0, nto, t0, nto, tchunk, op.kint[o].real(), op.kint[o].imag(), H, 3 * nto,
+      FillLArgs la{op.geo, nt, t0, nto, t0, nto, tchunk_for(nto, 256, nto), op.kint[o].real(), op.kint[o].imag(), H,
+                   3 * nto,
                    op.Lphi_int[o].d64, op.Lphi_int[o].ld};
       la.sub = needs_sub(op.kint[o], t0, nto);
       launch_fill_L(la, pt, ps, int64_t(no_t[o].size()), st);
@@ -594,8 +602,9 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
       if (which == 1 && !own_bg) break;
       const cd k = which == 0 ? op.kint[o] : op.kbg;
       Dense& dst = which == 0 ? op.K_int[o] : op.K_bg[o];
-      FillKArgs ka{op.geo, nt, t0, nto, tchunk, k.real(), k.imag(), d_cells + cdat.obj_cell_ptr[o],
-                   cdat.obj_cell_ptr[o + 1] - cdat.obj_cell_ptr[o], cdat.ncell, d_nval, d_vpos, d_col0, d_sub_m, d_sub_c,
+      const int64_t ncell_o = cdat.obj_cell_ptr[o + 1] - cdat.obj_cell_ptr[o];
+      FillKArgs ka{op.geo, nt, t0, nto, tchunk_for(ncell_o, 128, nto), k.real(), k.imag(),
+                   d_cells + cdat.obj_cell_ptr[o], ncell_o, cdat.ncell, d_nval, d_vpos, d_col0, d_sub_m, d_sub_c,
                    d_sub_area, d_sub_parent, d_alpha, d_beta, H, cdat.obj_ncol[o]};
       ka.sub = needs_sub(k, t0, nto);
       launch_fill_K(ka, pct, pcc, int64_t(nc_t[o].size()), d_near_ptr, d_near_idx, cdat.maxv, st);
@@ -610,8 +619,9 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
       const int64_t e0 = m.obj_edge[o], neo = m.obj_edge[o + 1] - e0;
       int32_t* pct = up32(ncm_t[o]);
       int32_t* pcc = up32(ncm_c[o]);
-      FillKArgs ka{op.geo, nt, 0, nt, tchunk, op.kbg.real(), op.kbg.imag(), d_cells + cdat.obj_cell_ptr[o],
-                   cdat.obj_cell_ptr[o + 1] - cdat.obj_cell_ptr[o], cdat.ncell, d_nval, d_vpos, d_col0, d_sub_m, d_sub_c,
+      const int64_t ncell_o = cdat.obj_cell_ptr[o + 1] - cdat.obj_cell_ptr[o];
+      FillKArgs ka{op.geo, nt, 0, nt, tchunk_for(ncell_o, 128, nt), op.kbg.real(), op.kbg.imag(),
+                   d_cells + cdat.obj_cell_ptr[o], ncell_o, cdat.ncell, d_nval, d_vpos, d_col0, d_sub_m, d_sub_c,
                    d_sub_area, d_sub_parent, d_alpha, d_beta, H, cdat.obj_ncol[o]};
       ka.sub = needs_sub(op.kbg, m.obj_tri[o], m.obj_tri[o + 1] - m.obj_tri[o]);
       launch_fill_K(ka, pct, pcc, int64_t(ncm_t[o].size()), d_near_ptr, d_near_idx, cdat.maxv, st);
