@@ -173,9 +173,10 @@ __global__ void __launch_bounds__(256) k_gj_panels(const double2* __restrict__ A
 
 // The 64 x 64 tile (ti, tj) of an update launch.  Mode 0 covers the matrix, gridDim.y x
 // gridDim.x tiles, in an XCD-aware order: the 8 XCDs take consecutive blocks round-robin; each
-// XCD gets a band of nby/8 row tiles and walks it column tile by column tile (rows fastest), so
-// the band's rows of the column panel C and the few R columns in flight stay in its L2 and
-// every panel entry is fetched from HBM about once per XCD.  Mode 1 is the column of tiles
+// XCD gets a band of nby/8 row tiles, cut into balanced sub-bands of at most 10 row tiles, and
+// walks one sub-band after the other column tile by column tile (rows fastest), so the
+// sub-band's rows of the column panels C (at most 10 x 64 rows x 4 panels x 1 KiB = 2.5 MB) and
+// the few R columns in flight stay in its L2 (4 MB).  Mode 1 is the column of tiles
 // tj = fix (one block per tile row), mode 2 the row of tiles ti = fix without its tile in
 // column fix.
 __device__ __forceinline__ void update_tile(int mode, int fix, unsigned& ti, unsigned& tj) {
@@ -195,8 +196,12 @@ __device__ __forceinline__ void update_tile(int mode, int fix, unsigned& ti, uns
   tj = lin % nbx;
   if (nby % 8 == 0) {
     const unsigned band = nby / 8, l = lin / 8;
-    ti = (lin % 8) * band + l % band;
-    tj = l / band;
+    const unsigned nsb = (band + 9) / 10, sb = (band + nsb - 1) / nsb;  // sub-bands, their height
+    const unsigned sub = l / (sb * nbx);                                 // full sub-bands before
+    const unsigned h = min(sb, band - sub * sb);                         // this sub-band's height
+    const unsigned r = l - sub * sb * nbx;
+    ti = (lin % 8) * band + sub * sb + r % h;
+    tj = r / h;
   }
 }
 
@@ -406,7 +411,9 @@ __global__ void __launch_bounds__(256, 2) k_gj_update_mfma4(double* __restrict__
     for (int g = 0; g < 4; ++g) {
       const int64_t gi = i0 + wm * 32 + 4 * bi + orow;
       const int64_t rc = 2 * j0 + wn * 64 + 16 * g + ocol;
-      apre[bi][g] = (gi < n && (rc >> 1) < n) ? A[gi * 2 * ld + rc] : 0.0;
+      // (the tile is read once and written once per pass: non-temporal, so that the panels
+      // keep the L2)
+      apre[bi][g] = (gi < n && (rc >> 1) < n) ? __builtin_nontemporal_load(&A[gi * 2 * ld + rc]) : 0.0;
     }
   double acc[8][4];
 #pragma unroll
@@ -439,7 +446,7 @@ __global__ void __launch_bounds__(256, 2) k_gj_update_mfma4(double* __restrict__
     for (int g = 0; g < 4; ++g) {
       const int64_t gi = i0 + wm * 32 + 4 * bi + orow;
       const int64_t rc = 2 * j0 + wn * 64 + 16 * g + ocol;
-      if (gi < n && (rc >> 1) < n) A[gi * 2 * ld + rc] = apre[bi][g] - acc[bi][g];
+      if (gi < n && (rc >> 1) < n) __builtin_nontemporal_store(apre[bi][g] - acc[bi][g], &A[gi * 2 * ld + rc]);
     }
 }
 
