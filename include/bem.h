@@ -141,8 +141,11 @@ typedef struct {
   double mu_bg;
   const bem_material* obj;      /* n_obj materials, host */
   int64_t n_obj;
-  int precision;                /* BEM_FP64, or BEM_MIXED: float32 copies of the dense blocks
-                                   for the Krylov products, float64 residual refinement */
+  int precision;                /* BEM_FP64, or BEM_MIXED: float32 copies of the dense blocks;
+                                   each refinement sweep runs float64 products until GMRES's
+                                   residual estimate is sqrt(tol), float32 products after (first
+                                   restart cycle only), float64 residual refinement; float64
+                                   products throughout when a float32 probe deviates > 1e-4 */
   int inner_mode;               /* BEM_INNER_* */
   int precond;                  /* 1: block preconditioner of eq. pcext for the final system
                                    (and its equivalent-configuration counterpart for the nested

@@ -105,15 +105,17 @@ def test_mixed_precision_currents_fullsize(c2):
     """The benchmark's problem solved with float64 products to a 1e-10 residual and with
     float32 products plus float64 refinement: refined to a 1e-9 residual, the mixed currents
     (H, E, rho) are within 1e-6 of the float64 ones; the deviation of the benchmark's own
-    stopping point (1e-6) is printed beside it."""
+    stopping point (1e-6) is printed beside it, and at that tolerance the mixed solve needs
+    at most 15% more outer iterations than the float64 one."""
     w, _ = c2
     ctx = B.bem_create(0)
     mesh = B.bem_mesh_load(ctx, w.xyz, w.tri, w.obj)
     info = B.bem_mesh_info(ctx, mesh)
     exc = B.plane_waves(w.khat, w.pol)
     sol = {}
+    its = {}
     for name, prec, tol in (("fp64", B.BEM_FP64, 1e-10), ("mixed", B.BEM_MIXED, 1e-9),
-                            ("mixed_bench", B.BEM_MIXED, 1e-6)):
+                            ("mixed_bench", B.BEM_MIXED, 1e-6), ("fp64_bench", B.BEM_FP64, 1e-6)):
         op = B.bem_assemble(ctx, mesh, B.make_problem(w.freq_hz, w.eps_r, w.mu_r, w.sigma, precision=prec))
         rc, H, E, rho, si = B.bem_solve(ctx, op, exc, B.solve_opts(tol=tol, restart=300, maxit=4000, max_refine=8),
                                         info["n_edge"], info["n_tri"])
@@ -121,7 +123,11 @@ def test_mixed_precision_currents_fullsize(c2):
         assert rc == B.BEM_OK and si.rel_residual <= tol, (name, rc, si.rel_residual)
         print(f"{name}: outer {si.outer_iters}, residual {si.rel_residual:.2e}")
         sol[name] = (H[:, 0], E[:, 0], rho[:, 0])
+        its[name] = si.outer_iters
     B.bem_destroy(ctx)
+    # relaxed products keep the float64 iteration count (float32 from the first step took
+    # 284 iterations against 129 here)
+    assert its["mixed_bench"] <= 1.15 * its["fp64_bench"] + 5, its
     for name in ("mixed", "mixed_bench"):
         errs = [rel(got, want) for got, want in zip(sol[name], sol["fp64"])]
         print(f"{name} vs fp64: H {errs[0]:.2e}, E {errs[1]:.2e}, rho {errs[2]:.2e}")
