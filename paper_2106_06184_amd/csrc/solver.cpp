@@ -336,8 +336,9 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
 
   mark("geometry+uploads");
   // ---- Gram matrix I_x: int (n x f_m) . g_n dS, exact with the 3-point rule on every sub-triangle
+  // (host work, run while the fill kernels are on the GPU: called once they are enqueued)
   std::vector<double> ixdiag(m.ne, 0.0);
-  {
+  auto build_ix = [&]() {
     // rows collect (column, value) pairs in fixed-capacity slots: the columns of row m are the
     // BC functions of the dual cells of the (at most four) vertices of T+(m) and T-(m)
     const int cap = 4 * cdat.maxv + 4;
@@ -415,9 +416,8 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
     op.ix_ptr = op.mem.upload(ptr);
     op.ix_idx = op.mem.upload(idx);
     op.ix_val = op.mem.upload(val);
-  }
+  };
 
-  mark("I_x");
   // ---- near-pair lists (all pairs, and per object) for L, near cells per object for K~
   std::vector<int32_t> na_t, na_s;
   std::vector<std::vector<int32_t>> no_t(m.nobj), no_s(m.nobj);
@@ -643,6 +643,7 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
     to_f32(op.Lphi_bg, st);
   }
   BEM_HIP(hipEventRecord(ev1, st));
+  build_ix();
   BEM_HIP(hipStreamSynchronize(st));
   float ms = 0;
   BEM_HIP(hipEventElapsedTime(&ms, ev0, ev1));
@@ -668,7 +669,7 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
                   (void*)d_cS, (void*)d_cT, (void*)d_near_ptr, (void*)d_near_idx})
     op.mem.release(p);
 
-  mark("fill");
+  mark("fill (and I_x on the host)");
   op.precond = prob.precond != 0;
   build_inner_and_precond(op, ixdiag, st, 1);
   build_inner_and_precond(op, ixdiag, st, 2);
