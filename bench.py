@@ -222,7 +222,7 @@ def main() -> int:
                          "where the Gram-Schmidt cost grows with the batch)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=24)
-    ap.add_argument("--serve-rate", type=float, default=6.0)
+    ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the plain copy used to calibrate the HBM byte counters")
     args = ap.parse_args()
