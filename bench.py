@@ -87,8 +87,9 @@ def cpu_baseline(w, n_sample: int = 12) -> dict:
 
 
 def kernel_source_digest(regions) -> str | None:
-    """sha256 over the source text of a kernel: each region is [file, begin, end] (from the
-    first occurrence of `begin`, "" for the file start, up to the next `end`)."""
+    """sha256 over the code of a kernel: each region is [file, begin, end] (from the first
+    occurrence of `begin`, "" for the file start, up to the next `end`); // comments, trailing
+    blanks and empty lines are left out, so that only a change of the code itself counts."""
     import hashlib
     h = hashlib.sha256()
     for rel, begin, end in regions:
@@ -100,7 +101,10 @@ def kernel_source_digest(regions) -> str | None:
         j = text.find(end, i) if i >= 0 else -1
         if i < 0 or j < 0:
             return None
-        h.update(text[i:j].encode())
+        for line in text[i:j].splitlines():
+            code = line.split("//", 1)[0].rstrip()
+            if code:
+                h.update((code + "\n").encode())
     return h.hexdigest()
 
 

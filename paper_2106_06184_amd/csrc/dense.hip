@@ -360,9 +360,10 @@ __global__ void __launch_bounds__(256, 2) k_gj_update_mfma(double* __restrict__ 
       }
 }
 
-// Same update with the float64 4x4x4 four-block matrix instruction (on gfx950 it runs at about
-// 1.45x the float64 16x16x4 one).  Lane l of one instruction supplies A_q[l % 4][l / 16] and
-// B_q[l / 16][l % 4] of block q = (l % 16) / 4 and receives D_q[l / 16][l % 4].  All four blocks
+// Same update with the float64 4x4x4 four-block matrix instruction (alone, on gfx950, it runs
+// at about 1.45x the float64 16x16x4 one; in this kernel the gain is a few percent).  Lane l
+// of one instruction supplies A_q[l % 4][l / 16] and B_q[l / 16][l % 4] of block
+// q = (l % 16) / 4 and receives D_q[l / 16][l % 4].  All four blocks
 // of an instruction share the rows (4 rows of the wave tile) and take four consecutive 4-column
 // groups, so a lane's A value serves the four column groups and its B value the eight row
 // groups: per 4 reals of K a wave issues 32 instructions on 8 A and 4 B values from LDS.

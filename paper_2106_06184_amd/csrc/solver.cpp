@@ -35,7 +35,7 @@ constexpr int kWorkFields = 15;
 int64_t work_ld(const OpObj& op) { return pad64(op.Neq); }
 
 // Largest relative deviation of the float32 final-system product from the float64 one for which
-// a mixed-precision solve runs float32 sweeps.
+// a mixed-precision solve uses float32 products (in the late steps of its sweeps).
 constexpr double kFp32ProbeTol = 1e-4;
 
 // Smallest |k_l| h_max for which the nested solve eliminates the charges (S of build_s): its
@@ -1937,7 +1937,7 @@ int solve_op(OpObj& op, const bem_excitation* exc, int64_t nexc, const bem_solve
   // precisions, and float64 products are used throughout when ||A32 z - A64 z|| / ||A64 z||
   // exceeds kFp32ProbeTol.  Random vectors do not show it: for small conductors at low
   // frequency the equivalent current cancels the physical one to many digits, so float32
-  // products of solution-like vectors lose them all, and float32 sweeps make no progress.
+  // products of solution-like vectors lose them all, and float32 steps make no progress.
   bool fp32_ok = op.precision == BEM_MIXED;
   bool probed = false;
   for (int64_t e0 = 0; e0 < nexc; e0 += Rb) {
@@ -2007,7 +2007,7 @@ int solve_op(OpObj& op, const bem_excitation* exc, int64_t nexc, const bem_solve
       }
       gtol = std::max(gtol, 1e-15);
       const double relax = relax_global / std::max(rmax, 1e-300);
-      // a float32 sweep gets at most three restart cycles (600 steps at least): one that cannot
+      // a mixed sweep gets at most three restart cycles (600 steps at least): one that cannot
       // reach its target in that budget works on products too inaccurate in float32
       const int budget = use32 ? std::min(left, std::max(3 * opts.restart, 600)) : left;
       // (the preconditioner stays float64: the solution update applies it to V y, so the steps
@@ -2044,7 +2044,7 @@ int solve_op(OpObj& op, const bem_excitation* exc, int64_t nexc, const bem_solve
       active.swap(next);
       if (use32 && (stalled || sweep_failed) && !active.empty()) {
         use32 = false;
-        if (verbose()) std::fprintf(stderr, "[bem] float32 sweep stalled: float64 products from here on\n");
+        if (verbose()) std::fprintf(stderr, "[bem] mixed sweep stalled: float64 products from here on\n");
       }
     }
     for (int c = 0; c < R; ++c) inf.rel_residual = std::max(inf.rel_residual, rel[c]);
