@@ -8,6 +8,7 @@
 // dual edge, every sub-triangle of the source cell emitting 1/(2N), of the sink cell absorbing
 // 1/(2N)).
 #include <algorithm>
+#include <thread>
 #include <array>
 #include <cmath>
 #include <unordered_map>
@@ -261,33 +262,52 @@ std::unique_ptr<Mesh> build_mesh(const double* xyz, int64_t nv, const int32_t* t
   std::unordered_map<int64_t, std::vector<int32_t>> grid;
   for (int64_t t = 0; t < nt; ++t)
     grid[(gidx(t, 0) * gdim[1] + gidx(t, 1)) * gdim[2] + gidx(t, 2)].push_back(int32_t(t));
+  // (triangle ranges on several host threads: graded meshes have hundreds of near pairs per
+  // triangle; each range's lists are concatenated in order, so the result does not depend on
+  // the thread count)
   m->near_ptr.assign(nt + 1, 0);
-  std::vector<int32_t> cand;
-  for (int64_t t = 0; t < nt; ++t) {
-    cand.clear();
-    int64_t g0 = gidx(t, 0), g1 = gidx(t, 1), g2 = gidx(t, 2);
-    for (int64_t a = std::max<int64_t>(0, g0 - 1); a <= std::min(gdim[0] - 1, g0 + 1); ++a)
-      for (int64_t b = std::max<int64_t>(0, g1 - 1); b <= std::min(gdim[1] - 1, g1 + 1); ++b)
-        for (int64_t c = std::max<int64_t>(0, g2 - 1); c <= std::min(gdim[2] - 1, g2 + 1); ++c) {
-          auto it = grid.find((a * gdim[1] + b) * gdim[2] + c);
-          if (it == grid.end()) continue;
-          for (int32_t s : it->second) {
-            double dx = m->centroid[3 * t] - m->centroid[3 * s];
-            double dy = m->centroid[3 * t + 1] - m->centroid[3 * s + 1];
-            double dz = m->centroid[3 * t + 2] - m->centroid[3 * s + 2];
-            double d = std::sqrt(dx * dx + dy * dy + dz * dz);
-            if (d < kNearFactor * std::max(m->hmax[t], m->hmax[s])) cand.push_back(s);
+  const int nthr = int(std::max<int64_t>(1, std::min<int64_t>({int64_t(std::thread::hardware_concurrency()), 16,
+                                                               nt / 2048 + 1})));
+  std::vector<std::vector<int32_t>> part_idx(nthr);
+  auto near_range = [&](int w) {
+    const int64_t ta = nt * w / nthr, tb = nt * (w + 1) / nthr;
+    std::vector<int32_t> cand;
+    std::vector<int32_t>& out = part_idx[w];
+    for (int64_t t = ta; t < tb; ++t) {
+      cand.clear();
+      int64_t g0 = gidx(t, 0), g1 = gidx(t, 1), g2 = gidx(t, 2);
+      for (int64_t a = std::max<int64_t>(0, g0 - 1); a <= std::min(gdim[0] - 1, g0 + 1); ++a)
+        for (int64_t b = std::max<int64_t>(0, g1 - 1); b <= std::min(gdim[1] - 1, g1 + 1); ++b)
+          for (int64_t c = std::max<int64_t>(0, g2 - 1); c <= std::min(gdim[2] - 1, g2 + 1); ++c) {
+            auto it = grid.find((a * gdim[1] + b) * gdim[2] + c);
+            if (it == grid.end()) continue;
+            for (int32_t s : it->second) {
+              double dx = m->centroid[3 * t] - m->centroid[3 * s];
+              double dy = m->centroid[3 * t + 1] - m->centroid[3 * s + 1];
+              double dz = m->centroid[3 * t + 2] - m->centroid[3 * s + 2];
+              double d = std::sqrt(dx * dx + dy * dy + dz * dz);
+              if (d < kNearFactor * std::max(m->hmax[t], m->hmax[s])) cand.push_back(s);
+            }
           }
-        }
-    for (int i = 0; i < 3; ++i) {
-      int32_t v = m->tri[3 * t + i];
-      for (int64_t p = m->vptr[v]; p < m->vptr[v + 1]; ++p) cand.push_back(m->vtri[p]);
+      for (int i = 0; i < 3; ++i) {
+        int32_t v = m->tri[3 * t + i];
+        for (int64_t p = m->vptr[v]; p < m->vptr[v + 1]; ++p) cand.push_back(m->vtri[p]);
+      }
+      std::sort(cand.begin(), cand.end());
+      cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+      out.insert(out.end(), cand.begin(), cand.end());
+      m->near_ptr[t + 1] = int64_t(cand.size());
     }
-    std::sort(cand.begin(), cand.end());
-    cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
-    m->near_idx.insert(m->near_idx.end(), cand.begin(), cand.end());
-    m->near_ptr[t + 1] = int64_t(m->near_idx.size());
+  };
+  {
+    std::vector<std::thread> pool;
+    for (int w = 1; w < nthr; ++w) pool.emplace_back(near_range, w);
+    near_range(0);
+    for (auto& th : pool) th.join();
   }
+  for (int64_t t = 0; t < nt; ++t) m->near_ptr[t + 1] += m->near_ptr[t];
+  m->near_idx.reserve(size_t(m->near_ptr[nt]));
+  for (auto& p : part_idx) m->near_idx.insert(m->near_idx.end(), p.begin(), p.end());
   return m;
 }
 
