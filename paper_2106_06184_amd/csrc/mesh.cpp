@@ -410,27 +410,42 @@ CellData build_cells(const Mesh& m) {
 }
 
 void near_cells(const Mesh& m, std::vector<int64_t>& ptr, std::vector<int32_t>& idx) {
+  // triangle ranges on several host threads, concatenated in order (as the near pairs)
   ptr.assign(m.nt + 1, 0);
   idx.clear();
-  idx.reserve(size_t(m.near_idx.size()));
-  std::vector<int32_t> c;
-  std::vector<int64_t> stamp(m.nv, -1);  // last triangle that listed the vertex
-  for (int64_t t = 0; t < m.nt; ++t) {
-    c.clear();
-    for (int64_t p = m.near_ptr[t]; p < m.near_ptr[t + 1]; ++p) {
-      int32_t s = m.near_idx[p];
-      for (int i = 0; i < 3; ++i) {
-        const int32_t v = m.tri[3 * s + i];
-        if (stamp[v] != t) {
-          stamp[v] = t;
-          c.push_back(v);
+  const int nthr = int(std::max<int64_t>(1, std::min<int64_t>({int64_t(std::thread::hardware_concurrency()), 16,
+                                                               m.nt / 2048 + 1})));
+  std::vector<std::vector<int32_t>> part(nthr);
+  auto range = [&](int w) {
+    const int64_t ta = m.nt * w / nthr, tb = m.nt * (w + 1) / nthr;
+    std::vector<int32_t> c;
+    std::vector<int64_t> stamp(m.nv, -1);  // last triangle that listed the vertex
+    for (int64_t t = ta; t < tb; ++t) {
+      c.clear();
+      for (int64_t p = m.near_ptr[t]; p < m.near_ptr[t + 1]; ++p) {
+        int32_t s = m.near_idx[p];
+        for (int i = 0; i < 3; ++i) {
+          const int32_t v = m.tri[3 * s + i];
+          if (stamp[v] != t) {
+            stamp[v] = t;
+            c.push_back(v);
+          }
         }
       }
+      std::sort(c.begin(), c.end());
+      part[w].insert(part[w].end(), c.begin(), c.end());
+      ptr[t + 1] = int64_t(c.size());
     }
-    std::sort(c.begin(), c.end());
-    idx.insert(idx.end(), c.begin(), c.end());
-    ptr[t + 1] = int64_t(idx.size());
+  };
+  {
+    std::vector<std::thread> pool;
+    for (int w = 1; w < nthr; ++w) pool.emplace_back(range, w);
+    range(0);
+    for (auto& th : pool) th.join();
   }
+  for (int64_t t = 0; t < m.nt; ++t) ptr[t + 1] += ptr[t];
+  idx.reserve(size_t(ptr[m.nt]));
+  for (auto& q : part) idx.insert(idx.end(), q.begin(), q.end());
 }
 
 }  // namespace bem

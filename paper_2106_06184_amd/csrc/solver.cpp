@@ -421,6 +421,12 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
   // ---- near-pair lists (all pairs, and per object) for L, near cells per object for K~
   std::vector<int32_t> na_t, na_s;
   std::vector<std::vector<int32_t>> no_t(m.nobj), no_s(m.nobj);
+  na_t.reserve(m.near_idx.size());
+  na_s.reserve(m.near_idx.size());
+  if (m.nobj == 1) {
+    no_t[0].reserve(m.near_idx.size());
+    no_s[0].reserve(m.near_idx.size());
+  }
   for (int64_t t = 0; t < nt; ++t)
     for (int64_t p = m.near_ptr[t]; p < m.near_ptr[t + 1]; ++p) {
       const int32_t s = m.near_idx[p];
@@ -438,6 +444,10 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
   for (int64_t t = 0; t < nt; ++t)
     for (int i = 0; i < 3; ++i) vobj[m.tri[3 * t + i]] = m.obj[t];
   std::vector<std::vector<int32_t>> nc_t(m.nobj), nc_c(m.nobj);
+  if (m.nobj == 1) {
+    nc_t[0].reserve(nci.size());
+    nc_c[0].reserve(nci.size());
+  }
   for (int64_t t = 0; t < nt; ++t)
     for (int64_t p = ncp[t]; p < ncp[t + 1]; ++p)
       if (vobj[nci[p]] == m.obj[t]) {
