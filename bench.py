@@ -222,8 +222,7 @@ def main() -> int:
                     help="fill and invert every object separately even when objects are translated copies")
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--restart", type=int, default=0,
-                    help="GMRES restart length (default: 300 for one excitation, 100 for batches, "
-                         "where the Gram-Schmidt cost grows with the batch)")
+                    help="GMRES restart length (default 300; 200 when serving)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=24)
     ap.add_argument("--serve-rate", type=float, default=20.0)
@@ -259,7 +258,7 @@ def main() -> int:
     freqs = list(getattr(w, "freqs", [w.freq_hz]))
     nstep = [args.sweep_start]
     if args.restart <= 0:
-        args.restart = 300 if n_exc <= 8 else 100
+        args.restart = 300
     opts = B.solve_opts(tol=args.tol, restart=args.restart, maxit=args.maxit)
 
     phases = {"mesh_load": 0.0, "assemble": 0.0, "solve": 0.0, "release": 0.0}
