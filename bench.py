@@ -10,7 +10,8 @@ eps_r = 2.5 - 0.1j), x-polarised plane wave along -z - seeded synthetic input.
 Reported beside the throughput:
   roofline      the dominant kernel class over the timed region, measured with HIP events on
                 its launch stream (library profiler): achieved algorithmic GB/s vs 8 TB/s HBM
-                for the dense products, or Green's-function evaluations/s for the fill;
+                for the GEMV, TFLOP/s vs the matrix peak for the Gauss-Jordan update and the
+                GEMMs, with the measured HBM bytes per launch (rocprofv3 counters) beside it;
   fill_GBps     bytes of the float64 dense blocks written / device fill time;
   cpu_baseline  the float64 CPU oracle on a bounded sample of the same workload (a subset of
                 test triangles of every fill, and a dense LU of a smaller matrix), scaled to
