@@ -165,7 +165,9 @@ typedef struct {
  * wavenumbers (interior, eq. AEFIEintdis) and at the background wavenumber
  * (eqs. AEFIEeqvdis and AEFIEextdis), the sparse D, F, B and I_x, and, with
  * BEM_MIXED, their float32 copies.  Runs synchronously on the context's
- * stream.  BEM_E_NOMEM if the blocks exceed the HBM budget. */
+ * stream.  BEM_E_NOMEM if the blocks exceed the HBM budget; BEM_E_NUMERIC if a
+ * dense inversion of the nested solve or of the preconditioner breaks down (see
+ * bem_op_stats). */
 int bem_assemble(bem_ctx* ctx, bem_mesh_h mesh, const bem_problem* prob, bem_op_h* out);
 
 /* y = A x for `block` (see above), nrhs columns.  x, y: device pointers, column-
@@ -176,6 +178,20 @@ int bem_assemble(bem_ctx* ctx, bem_mesh_h mesh, const bem_problem* prob, bem_op_
  * solve (eq. AEFIEeqvdis) done by GMRES to the relative tolerance set by
  * bem_set_inner_tol (default 1e-12). */
 int bem_apply(bem_ctx* ctx, bem_op_h op, int block, const void* x, void* y, int64_t nrhs, void* stream);
+/* In-place inverse of a dense complex matrix on the device by the library's blocked
+ * Gauss-Jordan elimination without pivoting: the routine that forms the direct nested-solve
+ * inverses (M_eq^-1 of eq. AEFIEeqvdis, or its charge-eliminated S^-1) and the inverses of the
+ * preconditioner's charge Schur complements (eq. pcext; Sec. III).  A: device pointer, n x n
+ * row-major complex float64 (bem_c64 layout), leading dimension ld >= n elements; the caller
+ * owns it and should equilibrate it (no scaling is done here).  stream: a hipStream_t or NULL
+ * for the context's stream; the call waits for it.  The library allocates a workspace of about
+ * 8 KiB per row for the call.  health (host, 2 doubles, may be NULL): the smallest pivot relative
+ * to the largest entry of its 64 x 64 diagonal block, and the relative error
+ * |A^-1 (A x) - x| / |x| of a fixed probe vector x.  BEM_E_NUMERIC when a pivot ratio is below
+ * 1e-12, the probe error above 1e-6, or either is NaN: elimination without pivoting has broken
+ * down and A holds no usable inverse.  BEM_E_INVALID for n < 0, ld < n or a null A. */
+int bem_dense_invert(bem_ctx* ctx, void* A, int64_t n, int64_t ld, void* stream, double* health);
+
 /* Copy a dense block (blocks 1..7) into a host buffer, row-major complex
  * float64, rows x cols as documented above (block-diagonal blocks include
  * their zero off-diagonal parts). */
@@ -263,15 +279,22 @@ int bem_serve_stats(bem_ctx* ctx, int64_t* combined_launches, int64_t* combined_
 
 /* Statistics of an assembled operator: device time of the whole fill (all wavenumbers, near
  * corrections and gathers), bytes of the float64 dense blocks written, Green's-function and
- * gradient evaluations of the quadrature, device bytes held by the operator, and the number of
+ * gradient evaluations of the quadrature, device bytes held by the operator, the number of
  * objects whose interior blocks (L^A, L^phi, K~ at the object wavenumber) were filled (the
- * others share a translated copy's, see bem_problem.no_reuse). */
+ * others share a translated copy's, see bem_problem.no_reuse), and the worst health of the
+ * operator's dense inversions (nested-solve inverses and the preconditioner's charge Schur
+ * complements; blocked Gauss-Jordan without pivoting): the smallest pivot relative to the
+ * largest entry of its 64 x 64 diagonal block (+inf when nothing was inverted) and the largest
+ * relative error |A^-1 (A x) - x| / |x| of a fixed probe vector x.  bem_assemble fails with
+ * BEM_E_NUMERIC when a pivot ratio is below 1e-12 or a probe error above 1e-6. */
 typedef struct {
   double fill_seconds;
   double fill_bytes;
   double kernel_evals;
   double device_bytes;
   double interiors_filled;
+  double inverse_min_pivot_ratio;
+  double inverse_probe_error;
 } bem_op_stats;
 int bem_op_stats_get(bem_ctx* ctx, bem_op_h op, bem_op_stats* out);
 

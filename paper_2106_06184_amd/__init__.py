@@ -25,7 +25,8 @@ BEM_FP64, BEM_MIXED = 0, 2
 BEM_EXC_PLANE_WAVE, BEM_EXC_DELTA_GAP = 0, 1
 
 SYMBOLS = ["bem_create", "bem_destroy", "bem_last_error", "bem_mesh_load", "bem_mesh_info", "bem_edge_table",
-           "bem_near_pairs", "bem_mesh_copies", "bem_far_field", "bem_assemble", "bem_apply", "bem_block_export", "bem_set_inner_tol", "bem_solve",
+           "bem_near_pairs", "bem_mesh_copies", "bem_far_field", "bem_assemble", "bem_apply", "bem_dense_invert",
+           "bem_block_export", "bem_set_inner_tol", "bem_solve",
            "bem_submit", "bem_poll", "bem_drain", "bem_release", "bem_memory_in_use", "bem_op_stats_get",
            "bem_profile_enable", "bem_profile_read", "bem_serve_stats"]
 (KC_GEMV_F64, KC_GEMV_F32, KC_FILL_L, KC_FILL_K, KC_FILL_NEAR, KC_GATHER, KC_GEMM_F32, KC_DENSE_INV,
@@ -36,7 +37,8 @@ KC_NAMES = ["gemv_f64", "gemv_f32", "fill_L", "fill_K", "fill_near", "gather", "
 
 class bem_op_stats(C.Structure):
     _fields_ = [("fill_seconds", C.c_double), ("fill_bytes", C.c_double), ("kernel_evals", C.c_double),
-                ("device_bytes", C.c_double), ("interiors_filled", C.c_double)]
+                ("device_bytes", C.c_double), ("interiors_filled", C.c_double),
+                ("inverse_min_pivot_ratio", C.c_double), ("inverse_probe_error", C.c_double)]
 
 
 class c64(C.Structure):
@@ -104,6 +106,7 @@ def lib() -> C.CDLL:
                                         C.POINTER(C.c_double), C.c_int64, C.POINTER(c64), C.POINTER(C.c_double)]),
             "bem_assemble": (C.c_int, [P, C.c_uint64, C.POINTER(bem_problem), C.POINTER(C.c_uint64)]),
             "bem_apply": (C.c_int, [P, C.c_uint64, C.c_int, P, P, I64, P]),
+            "bem_dense_invert": (C.c_int, [P, P, I64, I64, P, C.POINTER(D)]),
             "bem_block_export": (C.c_int, [P, C.c_uint64, C.c_int, C.POINTER(c64)]),
             "bem_set_inner_tol": (C.c_int, [P, C.c_uint64, D]),
             "bem_solve": (C.c_int, [P, C.c_uint64, C.POINTER(bem_excitation), I64, C.POINTER(bem_solve_opts),
@@ -241,6 +244,17 @@ def bem_assemble(ctx, mesh: int, prob: bem_problem) -> int:
 def bem_apply(ctx, op: int, block: int, x_ptr: int, y_ptr: int, nrhs: int = 1, stream: int | None = None) -> None:
     _check(ctx, lib().bem_apply(ctx, op, block, C.c_void_p(x_ptr), C.c_void_p(y_ptr), nrhs,
                                 C.c_void_p(stream) if stream else None))
+
+
+def bem_dense_invert(ctx, a_ptr: int, n: int, ld: int, stream=None):
+    """In-place device inverse of the n x n complex matrix at a_ptr (row-major, leading dimension
+    ld).  Returns (status, (min_pivot_ratio, probe_error)); raises on errors other than
+    BEM_E_NUMERIC (the breakdown status, returned so that callers can inspect the health)."""
+    h = np.zeros(2, np.float64)
+    rc = lib().bem_dense_invert(ctx, C.c_void_p(a_ptr), int(n), int(ld), C.c_void_p(stream) if stream else None,
+                                h.ctypes.data_as(C.POINTER(C.c_double)))
+    _check(ctx, rc, allow=(BEM_OK, BEM_E_NUMERIC))
+    return rc, (float(h[0]), float(h[1]))
 
 
 def bem_block_export(ctx, op: int, block: int, rows: int, cols: int) -> np.ndarray:

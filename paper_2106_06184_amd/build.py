@@ -18,15 +18,11 @@ ARCH = os.environ.get("BEM_OFFLOAD_ARCH", "gfx950")
 # Packed float32 instructions are disabled for all device code.
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-result"]
-# The quadrature fill kernels are built at -O1: with this compiler their -O2/-O3 builds give
-# run-to-run differences in the last bit of the K~ entries on gfx950 (measured: repeated fills of
-# one mesh differ in thousands of entries), while -O1 is bitwise reproducible at the same speed.
-OPT = {"fill.hip": "-O1"}
 
 
 def _compile(src: Path) -> Path:
     obj = BUILD / (src.name + ".o")
-    cmd = [HIPCC, OPT.get(src.name, "-O3"), *COMMON, *DEVICE_FLAGS, "-c", str(src), "-o", str(obj)]
+    cmd = [HIPCC, "-O3", *COMMON, *DEVICE_FLAGS, "-c", str(src), "-o", str(obj)]
     if src.suffix == ".hip":
         cmd.insert(1, "-xhip")
     r = subprocess.run(cmd, capture_output=True, text=True)

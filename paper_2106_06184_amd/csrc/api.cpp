@@ -1,9 +1,11 @@
 // C ABI of libbem: argument checks, handle tables, status codes and error messages.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 
 #include "ctx.h"
+#include "dense.h"
 #include "prof.h"
 #include "serve.h"
 
@@ -216,6 +218,32 @@ int bem_apply(bem_ctx* c, bem_op_h h, int block, const void* x, void* y, int64_t
   });
 }
 
+int bem_dense_invert(bem_ctx* c, void* A, int64_t n, int64_t ld, void* stream, double* health) {
+  return guarded([&]() -> int {
+    bem::Ctx* ctx = C(c);
+    need_device(c);
+    if (!A || n < 0 || ld < n) return fail(BEM_E_INVALID, "invalid matrix");
+    if (n == 0) return BEM_OK;
+    hipStream_t st = stream ? static_cast<hipStream_t>(stream) : ctx->stream;
+    bem::DevArena mem(ctx);
+    mem.set_stream(st);
+    bem::DenseScratch ws = bem::dense_scratch_at(mem.alloc<double2>(bem::dense_scratch_elems(n)), n);
+    bem::dense_invert(static_cast<double2*>(A), n, ld, ws, st);
+    const bem::DenseHealth h = bem::dense_health(ws, st);
+    if (health) {
+      health[0] = h.min_pivot_ratio;
+      health[1] = h.probe_error;
+    }
+    if (!bem::dense_health_ok(h)) {
+      char msg[160];
+      std::snprintf(msg, sizeof msg, "elimination without pivoting broke down: smallest pivot ratio %.3e, probe error %.3e",
+                    h.min_pivot_ratio, h.probe_error);
+      return fail(BEM_E_NUMERIC, msg);
+    }
+    return BEM_OK;
+  });
+}
+
 int bem_block_export(bem_ctx* c, bem_op_h h, int block, bem_c64* host_dst) {
   return guarded([&]() -> int {
     bem::Ctx* ctx = C(c);
@@ -286,6 +314,8 @@ int bem_op_stats_get(bem_ctx* c, bem_op_h h, bem_op_stats* out) {
     int64_t filled = 0;
     for (int64_t o = 0; o < op.nobj; ++o) filled += op.mat_rep[o] == o ? 1 : 0;
     out->interiors_filled = double(filled);
+    out->inverse_min_pivot_ratio = op.inv_min_pivot;
+    out->inverse_probe_error = op.inv_probe_err;
     return BEM_OK;
   });
 }

@@ -145,6 +145,7 @@ struct OpObj {
   int inner_restart = 200, inner_maxit = 4000;
   int last_inner_iters = 0, max_inner_iters = 0;
   double fill_seconds = 0, fill_bytes = 0, kernel_evals = 0;
+  double inv_min_pivot = HUGE_VAL, inv_probe_err = 0;  // worst health of the dense inversions
   std::unique_ptr<GmresWork> inner_ws, outer_ws;
   double2* work = nullptr;  // vector workspace
   int64_t work_len = 0;

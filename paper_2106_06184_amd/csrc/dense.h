@@ -8,14 +8,46 @@
 namespace bem {
 
 struct DenseScratch {
-  double2* P;  // 64 x 64
-  double2* R;  // 256 x n (four row panels)
-  double2* C;  // n x 256 (four column panels side by side)
+  double2* P;        // 64 x 64
+  double2* R;        // 256 x n (four row panels)
+  double2* C;        // n x 256 (four column panels side by side)
+  double2* probe_y;  // n
+  double* probe_d;   // n
+  double* health;    // 2: smallest pivot ratio, probe error
 };
 
+// Device workspace of dense_invert for matrices up to n rows, in elements of double2
+// (P, R, C, probe_y, then probe_d and health reinterpreted as doubles).
+inline size_t dense_scratch_elems(int64_t n) { return size_t(64 * 64) + size_t(513) * size_t(n) + size_t(n) + 2; }
+inline DenseScratch dense_scratch_at(double2* base, int64_t n) {
+  DenseScratch ws;
+  ws.P = base;
+  ws.R = ws.P + 64 * 64;
+  ws.C = ws.R + size_t(256) * n;
+  ws.probe_y = ws.C + size_t(256) * n;
+  ws.probe_d = reinterpret_cast<double*>(ws.probe_y + n);
+  ws.health = ws.probe_d + n;
+  return ws;
+}
+
 // In-place inverse of the n x n complex matrix A (row-major, leading dimension ld) by blocked
-// Gauss-Jordan elimination without pivoting.  Asynchronous on st.
+// Gauss-Jordan elimination without pivoting.  Asynchronous on st.  Breakdown is watched, not
+// avoided: the smallest pivot relative to its diagonal block and the relative error
+// |A^-1 (A x) - x| / |x| of a fixed probe vector x end in ws.health (read by dense_health).
 void dense_invert(double2* A, int64_t n, int64_t ld, DenseScratch& ws, hipStream_t st);
+
+// Health of the last dense_invert with this workspace (synchronises st).  An inversion is
+// accepted when every pivot is at least kMinPivotRatio times the largest entry of its diagonal
+// block and the probe error is at most kMaxProbeError (NaN fails both): below that the
+// elimination without pivoting has broken down, and its inverse is not used.
+struct DenseHealth {
+  double min_pivot_ratio;
+  double probe_error;
+};
+constexpr double kMinPivotRatio = 1e-12;
+constexpr double kMaxProbeError = 1e-6;
+DenseHealth dense_health(const DenseScratch& ws, hipStream_t st);
+bool dense_health_ok(const DenseHealth& h);
 
 // A[i][j] *= rs[i] cs[j] for i < nr, j < nc (device scale vectors, real).
 void scale_rows_cols(double2* A, int64_t ld, int64_t nr, int64_t nc, const double* rs, const double* cs,

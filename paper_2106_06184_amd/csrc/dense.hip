@@ -20,20 +20,6 @@
 
 namespace bem {
 
-// Rank-b update kernel (read at every inversion): BEM_DENSE_VALU=1 selects the plain VALU one,
-// BEM_DENSE_MFMA16=1 the float64 16x16x4 matrix-core one; the default is the 4x4x4 one.
-// Panels per pass over the matrix: 4, or BEM_DENSE_GROUP = 1, 2 or 4
-static int dense_group() {
-  const char* v = std::getenv("BEM_DENSE_GROUP");
-  const int g = (v && *v) ? std::atoi(v) : 4;
-  return (g == 1 || g == 2) ? g : 4;
-}
-static int dense_update_kind() {
-  const char* v = std::getenv("BEM_DENSE_VALU");
-  if (v && *v && *v != '0') return 0;
-  const char* m = std::getenv("BEM_DENSE_MFMA16");
-  return (m && *m && *m != '0') ? 1 : 2;
-}
 namespace dev {
 
 constexpr int NB = 64;
@@ -58,20 +44,35 @@ __device__ __forceinline__ double2 cinv(double2 a) {
 // serial chain, so the sub-blocks are small (S = 2: 1024 threads) to keep each step short.
 constexpr int kDiagS = 2;
 constexpr int kDiagThreads = (NB / kDiagS) * (NB / kDiagS);
+//
+// Breakdown watch (no pivoting is done): the smallest |pivot| of the block relative to the
+// largest |entry| of the block as it arrives is folded into health[0] (a running minimum over
+// the launches of one inversion, NaN once any ratio is not finite).  Launches of one inversion
+// run in stream order, so thread 0 updates it without atomics.
 __global__ void __launch_bounds__(kDiagThreads) k_gj_diag(double2* __restrict__ A, int64_t ld, int64_t k0, int b,
-                                                          double2* __restrict__ P) {
+                                                          double2* __restrict__ P, double* __restrict__ health) {
   constexpr int S = kDiagS, W = NB / S;
   __shared__ double2 rowp[2][NB], colp[2][NB];
+  __shared__ double red[kDiagThreads / 64];
   const int t = threadIdx.x;
   const int r0 = S * (t / W), c0 = S * (t % W);
   double2 m[S][S];
+  double amax = 0.0;
 #pragma unroll
   for (int i = 0; i < S; ++i)
 #pragma unroll
     for (int j = 0; j < S; ++j) {
       const int r = r0 + i, c = c0 + j;
       m[i][j] = (r < b && c < b) ? A[(k0 + r) * ld + k0 + c] : make_double2(r == c ? 1.0 : 0.0, 0.0);
+      if (r < b && c < b) amax = fmax(amax, sqrt(m[i][j].x * m[i][j].x + m[i][j].y * m[i][j].y));
     }
+  for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off));
+  if ((t & 63) == 0) red[t >> 6] = amax;
+  __syncthreads();
+  double bmax = red[0];
+  for (int w = 1; w < kDiagThreads / 64; ++w) bmax = fmax(bmax, red[w]);
+  double min_ratio = HUGE_VAL;
+  bool bad = false;
   for (int p = 0; p < NB; ++p) {
     const int buf = p & 1;
     const int pl = p % S;
@@ -93,6 +94,12 @@ __global__ void __launch_bounds__(kDiagThreads) k_gj_diag(double2* __restrict__ 
         }
     }
     __syncthreads();
+    if (t == 0 && p < b) {
+      const double2 a = rowp[buf][p];
+      const double ratio = sqrt(a.x * a.x + a.y * a.y) / bmax;
+      if (!isfinite(ratio)) bad = true;
+      else min_ratio = fmin(min_ratio, ratio);
+    }
     const double2 inv = cinv(rowp[buf][p]);
     double2 g[S], cr[S];
 #pragma unroll
@@ -131,6 +138,70 @@ __global__ void __launch_bounds__(kDiagThreads) k_gj_diag(double2* __restrict__ 
   for (int i = 0; i < S; ++i)
 #pragma unroll
     for (int j = 0; j < S; ++j) P[(r0 + i) * NB + c0 + j] = m[i][j];
+  if (t == 0) {
+    const double h = health[0];
+    health[0] = (bad || isnan(h)) ? __builtin_nan("") : fmin(h, min_ratio);
+  }
+}
+
+// Probe of an inversion: x_j = (1 + (j mod 7) / 7) e^{0.7 j i} (a fixed, full vector).  Before the
+// inversion y = A x; after it z = A^-1 y and d_i = |z_i - x_i|^2.  One wave per row, lanes along
+// the row, a fixed-order butterfly.  health[0] is reset to +inf before the inversion.
+__device__ __forceinline__ double2 probe_x(int64_t j) {
+  double s, c;
+  sincos(0.7 * double(j), &s, &c);
+  const double a = 1.0 + double(j % 7) / 7.0;
+  return make_double2(a * c, a * s);
+}
+__global__ void __launch_bounds__(256) k_probe_mv(const double2* __restrict__ A, int64_t ld, int64_t n,
+                                                  double2* __restrict__ y, double* __restrict__ d, int after,
+                                                  double* __restrict__ health) {
+  const int64_t i = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i == 0 && threadIdx.x == 0 && !after) health[0] = HUGE_VAL;
+  if (i >= n) return;
+  const double2* row = A + i * ld;
+  double sr = 0.0, si = 0.0;
+  for (int64_t j = lane; j < n; j += 64) {
+    const double2 a = row[j];
+    const double2 v = after ? y[j] : probe_x(j);
+    sr += a.x * v.x - a.y * v.y;
+    si += a.x * v.y + a.y * v.x;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    sr += __shfl_xor(sr, off);
+    si += __shfl_xor(si, off);
+  }
+  if (lane != 0) return;
+  if (!after) {
+    y[i] = make_double2(sr, si);
+  } else {
+    const double2 x = probe_x(i);
+    d[i] = (sr - x.x) * (sr - x.x) + (si - x.y) * (si - x.y);
+  }
+}
+// health[1] = sqrt(sum d / sum |x|^2), one block, fixed order.  The probe's y is read by the
+// rows of the second product while they write d, so d has its own storage.
+__global__ void __launch_bounds__(256) k_probe_reduce(const double* __restrict__ d, int64_t n,
+                                                      double* __restrict__ health) {
+  __shared__ double num[256], den[256];
+  double a = 0.0, b = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) {
+    const double2 x = probe_x(i);
+    a += d[i];
+    b += x.x * x.x + x.y * x.y;
+  }
+  num[threadIdx.x] = a;
+  den[threadIdx.x] = b;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) {
+      num[threadIdx.x] += num[threadIdx.x + h];
+      den[threadIdx.x] += den[threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) health[1] = sqrt(num[0] / den[0]);
 }
 
 // R[s][j] = sum_t P[s][t] A[k0+t][j] for all j (thread: one column, 8 values of s; 32 columns
@@ -205,170 +276,22 @@ __device__ __forceinline__ void update_tile(int mode, int fix, unsigned& ti, uns
   }
 }
 
-// A[i][j] -= sum_s C[i][s] R[s][j] over the tiles of the launch (C: ld LDC, R: ld n).  Whole
-// tiles are updated: rows and columns of the pivot blocks are overwritten afterwards, and where
-// a tile holds an earlier pivot block's rows or columns, that panel's C rows and R columns there
-// are zero.
-__global__ void __launch_bounds__(256) k_gj_update(double2* __restrict__ A, int64_t ld, int64_t n, int mode, int fix,
-                                                   int b, const double2* __restrict__ R,
-                                                   const double2* __restrict__ Cp) {
-  __shared__ double2 Cs[64][17];
-  __shared__ double2 Rs[16][64];
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  unsigned ti, tj;
-  update_tile(mode, fix, ti, tj);
-  const int64_t i0 = int64_t(ti) * 64, j0 = int64_t(tj) * 64;
-  double2 acc[4][4];
-#pragma unroll
-  for (int r = 0; r < 4; ++r)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) acc[r][c] = make_double2(0, 0);
-  for (int s0 = 0; s0 < b; s0 += 16) {
-    // stage C (64 x 16) and R (16 x 64)
-    for (int e = threadIdx.x; e < 64 * 16; e += 256) {
-      const int r = e / 16, s = e % 16;
-      const int64_t gi = i0 + r;
-      Cs[r][s] = (gi < n && s0 + s < b) ? Cp[gi * LDC + s0 + s] : make_double2(0, 0);
-      const int sr = e / 64, cc = e % 64;
-      const int64_t gj = j0 + cc;
-      Rs[sr][cc] = (gj < n && s0 + sr < b) ? R[(s0 + sr) * n + gj] : make_double2(0, 0);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int s = 0; s < 16; ++s) {
-      double2 cv[4], rv[4];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) cv[r] = Cs[ty + 16 * r][s];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) rv[c] = Rs[s][tx + 16 * c];
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          acc[r][c].x += cv[r].x * rv[c].x - cv[r].y * rv[c].y;
-          acc[r][c].y += cv[r].x * rv[c].y + cv[r].y * rv[c].x;
-        }
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int64_t gi = i0 + ty + 16 * r;
-    if (gi >= n) continue;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int64_t gj = j0 + tx + 16 * c;
-      if (gj >= n) continue;
-      double2* a = A + gi * ld + gj;
-      *a = make_double2(a->x - acc[r][c].x, a->y - acc[r][c].y);
-    }
-  }
-}
-
-// Same update on the float64 matrix cores.  Real embedding of the complex product: the rows of
-// C (interleaved re/im, 2b reals) times the 2b x 2n real matrix with 2x2 blocks
+// A[i][j] -= sum_s C[i][s] R[s][j] over the tiles of the launch (C: ld LDC, R: ld n) on the
+// float64 matrix cores.  Whole tiles are updated: rows and columns of the pivot blocks are
+// overwritten afterwards, and where a tile holds an earlier pivot block's rows or columns, that
+// panel's C rows and R columns there are zero.  Real embedding of the complex product: the rows
+// of C (interleaved re/im, 2b reals) times the 2b x 2n real matrix with 2x2 blocks
 // [[Re R, Im R], [-Im R, Re R]] give the interleaved rows of C R.  Workgroup tile 64 x 64
-// complex (64 x 128 reals), four waves of 32 x 64 reals, MFMA 16x16x4 (float64), K staged
-// through LDS 32 reals at a time (A k-major so that operand reads are conflict-free).
-typedef double doublex4 __attribute__((ext_vector_type(4)));
-
-__global__ void __launch_bounds__(256, 2) k_gj_update_mfma(double* __restrict__ A, int64_t ld, int64_t n, int mode,
-                                                        int fix, int b, const double2* __restrict__ R,
-                                                        const double2* __restrict__ Cp) {
-  constexpr int KC = 32;  // reals of K per stage (16 complex)
-  __shared__ double As[KC][64 + 1];
-  __shared__ __align__(16) double Bs[KC][128 + 2];
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int wm = wave >> 1, wn = wave & 1;
-  unsigned ti, tj;
-  update_tile(mode, fix, ti, tj);
-  const int64_t i0 = int64_t(ti) * 64;  // complex rows
-  const int64_t j0 = int64_t(tj) * 64;  // complex columns
-  // the whole tile is updated (as in k_gj_update); its old values are fetched first (they
-  // stream in while the product is formed)
-  double apre[2][4][4];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int c = 0; c < 4; ++c)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t gi = i0 + wm * 32 + a * 16 + (lane >> 4) + 4 * v;
-        const int64_t rc = 2 * j0 + wn * 64 + c * 16 + (lane & 15);
-        apre[a][c][v] = (gi < n && (rc >> 1) < n) ? A[gi * 2 * ld + rc] : 0.0;
-      }
-  doublex4 acc[2][4];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) acc[a][c] = doublex4{0, 0, 0, 0};
-  // staging: thread -> one row of C (row tid % 64) and one column of R (column tid % 64), four
-  // consecutive s each (group tid / 64): the R loads are coalesced along columns, and both
-  // LDS stores are consecutive across lanes (R as 16-byte (re, im) / (-im, re) pairs)
-  const int sr = tid & 63, sg = (tid >> 6) * 4;
-  double2 pc[4], pr[4];
-  auto fetch = [&](int s0) {
-    const int64_t gi = i0 + sr, gj = j0 + sr;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int sc = s0 + sg + e;
-      pc[e] = (gi < n && sc < b) ? Cp[gi * LDC + sc] : make_double2(0, 0);
-      pr[e] = (gj < n && sc < b) ? R[int64_t(sc) * n + gj] : make_double2(0, 0);
-    }
-  };
-  auto stage = [&]() {
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int k = 2 * (sg + e);
-      As[k][sr] = pc[e].x;
-      As[k + 1][sr] = pc[e].y;
-      *reinterpret_cast<double2*>(&Bs[k][2 * sr]) = pr[e];
-      *reinterpret_cast<double2*>(&Bs[k + 1][2 * sr]) = make_double2(-pr[e].y, pr[e].x);
-    }
-  };
-  const int K = 2 * b;
-  fetch(0);
-  for (int k0r = 0; k0r < K; k0r += KC) {
-    stage();
-    __syncthreads();
-    if (k0r + KC < K) fetch((k0r + KC) / 2);  // next chunk streams in during the MFMAs
-#pragma unroll
-    for (int kk = 0; kk < KC; kk += 4) {
-      const int kr = kk + (lane >> 4);
-      double af[2], bf[4];
-#pragma unroll
-      for (int a = 0; a < 2; ++a) af[a] = As[kr][wm * 32 + a * 16 + (lane & 15)];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) bf[c] = Bs[kr][wn * 64 + c * 16 + (lane & 15)];
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) acc[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[c], acc[a][c], 0, 0, 0);
-    }
-    __syncthreads();
-  }
-  // epilogue: item v of lane l is row (l/16) + 4 v, column l%16 of every 16x16 real tile
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int c = 0; c < 4; ++c)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t gi = i0 + wm * 32 + a * 16 + (lane >> 4) + 4 * v;
-        const int64_t rc = 2 * j0 + wn * 64 + c * 16 + (lane & 15);
-        if (gi < n && (rc >> 1) < n) A[gi * 2 * ld + rc] = apre[a][c][v] - acc[a][c][v];
-      }
-}
-
-// Same update with the float64 4x4x4 four-block matrix instruction (alone, on gfx950, it runs
-// at about 1.45x the float64 16x16x4 one; in this kernel the gain is a few percent).  Lane l
+// complex (64 x 128 reals), four waves of 32 x 64 reals, K staged through LDS 32 reals at a
+// time (A k-major so that operand reads are conflict-free).  The float64 4x4x4 four-block
+// instruction (alone, on gfx950, about 1.45x the float64 16x16x4 one).  Lane l
 // of one instruction supplies A_q[l % 4][l / 16] and B_q[l / 16][l % 4] of block
 // q = (l % 16) / 4 and receives D_q[l / 16][l % 4].  All four blocks
 // of an instruction share the rows (4 rows of the wave tile) and take four consecutive 4-column
 // groups, so a lane's A value serves the four column groups and its B value the eight row
 // groups: per 4 reals of K a wave issues 32 instructions on 8 A and 4 B values from LDS.
 // Output of instruction (bi, g), lane l: row 4 bi + l / 16, column 16 g + l % 16 of the wave tile
-// (32 x 64 reals).  Staging, tile order and the write-back are those of k_gj_update_mfma.
+// (32 x 64 reals).
 __global__ void __launch_bounds__(256, 2) k_gj_update_mfma4(double* __restrict__ A, int64_t ld, int64_t n,
                                                          int mode, int fix, int b, const double2* __restrict__ R,
                                                          const double2* __restrict__ Cp) {
@@ -667,7 +590,7 @@ void launch_peq_stage2(const double2* d, const double2* t, const double2* v, con
 }
 
 // One update launch over the tiles of `mode` (see update_tile) with b panel columns.
-static void launch_update(int kind, double2* A, int64_t ld, int64_t n, int mode, int fix, int b, const double2* R,
+static void launch_update(double2* A, int64_t ld, int64_t n, int mode, int fix, int b, const double2* R,
                           const double2* C, hipStream_t st) {
   const unsigned nt = unsigned((n + 63) / 64);
   const dim3 g = mode == 0 ? dim3(nt, nt) : dim3(mode == 1 ? nt : nt - 1);
@@ -675,13 +598,8 @@ static void launch_update(int kind, double2* A, int64_t ld, int64_t n, int mode,
   const double ntile = double(g.x) * g.y, elems = ntile * 64.0 * 64.0;
   ProfScope ps(st, KC_DENSE_INV, 32.0 * std::min(elems, mode == 0 ? double(n) * n : 64.0 * n),
                8.0 * b * std::min(elems, mode == 0 ? double(n) * n : 64.0 * n));
-  double* Ad = reinterpret_cast<double*>(A);
-  if (kind == 2)
-    hipLaunchKernelGGL(dev::k_gj_update_mfma4, g, dim3(256), 0, st, Ad, ld, n, mode, fix, b, R, C);
-  else if (kind == 1)
-    hipLaunchKernelGGL(dev::k_gj_update_mfma, g, dim3(256), 0, st, Ad, ld, n, mode, fix, b, R, C);
-  else
-    hipLaunchKernelGGL(dev::k_gj_update, g, dim3(256), 0, st, A, ld, n, mode, fix, b, R, C);
+  hipLaunchKernelGGL(dev::k_gj_update_mfma4, g, dim3(256), 0, st, reinterpret_cast<double*>(A), ld, n, mode, fix, b,
+                     R, C);
 }
 
 // Blocked Gauss-Jordan, panels of NB, applied in groups of G panels so that one pass over the
@@ -693,9 +611,9 @@ static void launch_update(int kind, double2* A, int64_t ld, int64_t n, int mode,
 // Entry for entry this is G single-panel steps.
 void dense_invert(double2* A, int64_t n, int64_t ld, DenseScratch& ws, hipStream_t st) {
   if (n <= 0) return;
-  const int kind = dense_update_kind();
-  const int G = dense_group();
-  const unsigned gp = unsigned((n + 31) / 32), gw = unsigned((n + 15) / 16);
+  constexpr int G = dev::GMAX;
+  const unsigned gp = unsigned((n + 31) / 32), gw = unsigned((n + 15) / 16), gr = unsigned((n + 3) / 4);
+  hipLaunchKernelGGL(dev::k_probe_mv, dim3(gr), dim3(256), 0, st, A, ld, n, ws.probe_y, ws.probe_d, 0, ws.health);
   for (int64_t k0 = 0; k0 < n;) {
     const int npan = int(std::min<int64_t>(G, (n - k0 + dev::NB - 1) / dev::NB));
     int blast = 0;
@@ -703,23 +621,36 @@ void dense_invert(double2* A, int64_t n, int64_t ld, DenseScratch& ws, hipStream
       const int64_t km = k0 + int64_t(mp) * dev::NB;
       const int bm = int(std::min<int64_t>(dev::NB, n - km));
       if (mp > 0) {
-        launch_update(kind, A, ld, n, 1, int(km / 64), mp * dev::NB, ws.R, ws.C, st);
-        launch_update(kind, A, ld, n, 2, int(km / 64), mp * dev::NB, ws.R, ws.C, st);
+        launch_update(A, ld, n, 1, int(km / 64), mp * dev::NB, ws.R, ws.C, st);
+        launch_update(A, ld, n, 2, int(km / 64), mp * dev::NB, ws.R, ws.C, st);
       }
       double2* Rm = ws.R + int64_t(mp) * dev::NB * n;
       double2* Cm = ws.C + mp * dev::NB;
-      hipLaunchKernelGGL(dev::k_gj_diag, dim3(1), dim3(dev::kDiagThreads), 0, st, A, ld, km, bm, ws.P);
+      hipLaunchKernelGGL(dev::k_gj_diag, dim3(1), dim3(dev::kDiagThreads), 0, st, A, ld, km, bm, ws.P, ws.health);
       hipLaunchKernelGGL(dev::k_gj_panels, dim3(gp), dim3(256), 0, st, A, ld, n, km, bm, ws.P, Rm, Cm);
       if (mp + 1 < npan)
         hipLaunchKernelGGL(dev::k_gj_write, dim3(gw), dim3(256), 0, st, A, ld, n, km, bm, ws.P, ws.R, ws.C, mp);
       blast = bm;
     }
-    launch_update(kind, A, ld, n, 0, 0, (npan - 1) * dev::NB + blast, ws.R, ws.C, st);
+    launch_update(A, ld, n, 0, 0, (npan - 1) * dev::NB + blast, ws.R, ws.C, st);
     const int64_t kl = k0 + int64_t(npan - 1) * dev::NB;
     hipLaunchKernelGGL(dev::k_gj_write, dim3(gw), dim3(256), 0, st, A, ld, n, kl, blast, ws.P, ws.R, ws.C, npan - 1);
     k0 += int64_t(npan) * dev::NB;
   }
+  hipLaunchKernelGGL(dev::k_probe_mv, dim3(gr), dim3(256), 0, st, A, ld, n, ws.probe_y, ws.probe_d, 1, ws.health);
+  hipLaunchKernelGGL(dev::k_probe_reduce, dim3(1), dim3(256), 0, st, ws.probe_d, n, ws.health);
   BEM_HIP(hipGetLastError());
+}
+
+DenseHealth dense_health(const DenseScratch& ws, hipStream_t st) {
+  double h[2] = {0.0, 0.0};
+  BEM_HIP(hipMemcpyAsync(h, ws.health, sizeof(h), hipMemcpyDeviceToHost, st));
+  BEM_HIP(hipStreamSynchronize(st));
+  return DenseHealth{h[0], h[1]};
+}
+
+bool dense_health_ok(const DenseHealth& h) {
+  return h.min_pivot_ratio >= kMinPivotRatio && h.probe_error <= kMaxProbeError;
 }
 
 namespace dev {

@@ -158,11 +158,8 @@ __global__ void __launch_bounds__(256) k_gemm_f32(const float* __restrict__ A, i
       }
 }
 
-// ---- float64: the same real embedding on float64 matrix cores (MFMA 4x4x4, or 16x16x4).  Tile 64 x 128
-// per 256-thread workgroup (2 x 2 waves of 32 x 64 = 2 x 4 blocks of 16 x 16), K step 16.
-// MFMA f64 16x16x4 operand layout: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16];
-// result item v of lane l is row l / 16 + 4 v, column l % 16.
-typedef double doublex4 __attribute__((ext_vector_type(4)));
+// ---- float64: the same real embedding on the float64 4x4x4 four-block matrix instruction.  Tile
+// 64 x 128 per 256-thread workgroup (2 x 2 waves of 32 x 64 reals), K step 16.
 constexpr int DM = 64, DN = 128, DK = 16, DPAD = 2;
 
 __global__ void k_build_B64(const double2* __restrict__ X, int64_t ldx, int64_t nc, int64_t R,
@@ -182,12 +179,11 @@ __global__ void k_build_B64(const double2* __restrict__ X, int64_t ldx, int64_t 
   }
 }
 
-// FOUR selects the float64 4x4x4 four-block instruction (faster on gfx950): lane l supplies
-// A_q[l % 4][l / 16] and B_q[l / 16][l % 4] of block q = (l % 16) / 4; all four blocks share the
-// rows, so per 4 k a wave issues 8 x 4 instructions for its 32 x 64 tile, and the result of
-// instruction (i, j) on lane l is row 4 i + l / 16, column 16 j + l % 16 (columns as in the
-// 16x16x4 layout, so the epilogue's re/im pairing is the same).
-template <bool ALIGNED, bool FOUR>
+// Lane l of an instruction supplies A_q[l % 4][l / 16] and B_q[l / 16][l % 4] of block
+// q = (l % 16) / 4; all four blocks share the rows, so per 4 k a wave issues 8 x 4 instructions
+// for its 32 x 64 tile, and the result of instruction (i, j) on lane l is row 4 i + l / 16,
+// column 16 j + l % 16 (even columns real, odd imaginary parts).
+template <bool ALIGNED>
 __global__ void __launch_bounds__(256) k_gemm_f64(const double* __restrict__ A, int64_t lda,
                                                   const double* __restrict__ Bm, int64_t ldb, int64_t M, int64_t K,
                                                   int64_t K16, int64_t ntn, double2* __restrict__ Y, int64_t ldy,
@@ -208,14 +204,7 @@ __global__ void __launch_bounds__(256) k_gemm_f64(const double* __restrict__ A, 
   const int b_k = tid >> 4, b_col = (tid & 15) * 8;  // B: 16 k x 128 columns, 8 per thread
   const int64_t gm = m0 + a_row;
 
-  doublex4 acc[2][4];
   double acc4[8][4];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) acc[i][j][v] = 0.0;
 #pragma unroll
   for (int i = 0; i < 8; ++i)
 #pragma unroll
@@ -263,27 +252,15 @@ __global__ void __launch_bounds__(256) k_gemm_f64(const double* __restrict__ A, 
 #pragma unroll
     for (int s = 0; s < DK / 4; ++s) {
       const int kr = 4 * s + (lane >> 4);
-      if (FOUR) {
-        double av[8], bv[4];
+      double av[8], bv[4];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) av[i] = As[buf][kr][wm * 32 + 4 * i + (lane & 3)];
+      for (int i = 0; i < 8; ++i) av[i] = As[buf][kr][wm * 32 + 4 * i + (lane & 3)];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) bv[j] = Bs[buf][kr][wn * 64 + j * 16 + (lane & 15)];
+      for (int j = 0; j < 4; ++j) bv[j] = Bs[buf][kr][wn * 64 + j * 16 + (lane & 15)];
 #pragma unroll
-        for (int i = 0; i < 8; ++i)
+      for (int i = 0; i < 8; ++i)
 #pragma unroll
-          for (int j = 0; j < 4; ++j) acc4[i][j] = __builtin_amdgcn_mfma_f64_4x4x4f64(av[i], bv[j], acc4[i][j], 0, 0, 0);
-      } else {
-        double af[2], bf[4];
-#pragma unroll
-        for (int i = 0; i < 2; ++i) af[i] = As[buf][kr][wm * 32 + i * 16 + (lane & 15)];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) bf[j] = Bs[buf][kr][wn * 64 + j * 16 + (lane & 15)];
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
-      }
+        for (int j = 0; j < 4; ++j) acc4[i][j] = __builtin_amdgcn_mfma_f64_4x4x4f64(av[i], bv[j], acc4[i][j], 0, 0, 0);
     }
     if (kt + 1 < nk) store_tile(buf ^ 1);
     __syncthreads();
@@ -293,11 +270,9 @@ __global__ void __launch_bounds__(256) k_gemm_f64(const double* __restrict__ A, 
   for (int i = 0; i < 8; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      // item (i, j) of the tile: 16x16x4 item v = i % 4 of block (i / 4, j), or 4x4x4 group i
-      const double mine = FOUR ? acc4[i][j] : acc[i / 4][j][i % 4];
+      const double mine = acc4[i][j];
       const double other = __shfl_xor(mine, 1, 64);
-      const int64_t row = FOUR ? m0 + wm * 32 + 4 * i + (lane >> 4)
-                               : m0 + wm * 32 + (i / 4) * 16 + (lane >> 4) + 4 * (i % 4);
+      const int64_t row = m0 + wm * 32 + 4 * i + (lane >> 4);
       const int64_t col = n0 + wn * 64 + j * 16 + (lane & 15);
       if ((lane & 1) == 0 && row < M && (col >> 1) < R) {
         double yr = alpha.x * mine - alpha.y * other, yi = alpha.x * other + alpha.y * mine;
@@ -336,24 +311,13 @@ void launch_gemm(const GemmDesc& d, void* ws, size_t ws_bytes, hipStream_t st) {
     const double* A = static_cast<const double*>(d.A);
     const bool aligned = ((reinterpret_cast<uintptr_t>(A) | uintptr_t(lda * 8)) & 15) == 0;
     ProfScope ps(st, KC_GEMM_F64, double(d.rows) * d.cols * 16.0, 8.0 * double(d.rows) * d.cols * d.nrhs);
-    // BEM_GEMM_MFMA16=1: the float64 16x16x4 instruction instead of 4x4x4
-    static const bool m16 = [] {
-      const char* v = std::getenv("BEM_GEMM_MFMA16");
-      return v && *v && *v != '0';
-    }();
     const dim3 g(unsigned(ntm * ntn));
-    if (aligned && !m16)
-      hipLaunchKernelGGL((dev::k_gemm_f64<true, true>), g, dim3(256), 0, st, A, lda, Bm, ldb, d.rows, K, K16, ntn,
-                         d.Y, d.ldy, d.nrhs, d.alpha, d.accumulate);
-    else if (!m16)
-      hipLaunchKernelGGL((dev::k_gemm_f64<false, true>), g, dim3(256), 0, st, A, lda, Bm, ldb, d.rows, K, K16, ntn,
-                         d.Y, d.ldy, d.nrhs, d.alpha, d.accumulate);
-    else if (aligned)
-      hipLaunchKernelGGL((dev::k_gemm_f64<true, false>), g, dim3(256), 0, st, A, lda, Bm, ldb, d.rows, K, K16, ntn,
-                         d.Y, d.ldy, d.nrhs, d.alpha, d.accumulate);
+    if (aligned)
+      hipLaunchKernelGGL((dev::k_gemm_f64<true>), g, dim3(256), 0, st, A, lda, Bm, ldb, d.rows, K, K16, ntn, d.Y,
+                         d.ldy, d.nrhs, d.alpha, d.accumulate);
     else
-      hipLaunchKernelGGL((dev::k_gemm_f64<false, false>), g, dim3(256), 0, st, A, lda, Bm, ldb, d.rows, K, K16, ntn,
-                         d.Y, d.ldy, d.nrhs, d.alpha, d.accumulate);
+      hipLaunchKernelGGL((dev::k_gemm_f64<false>), g, dim3(256), 0, st, A, lda, Bm, ldb, d.rows, K, K16, ntn, d.Y,
+                         d.ldy, d.nrhs, d.alpha, d.accumulate);
     BEM_HIP(hipGetLastError());
     return;
   }

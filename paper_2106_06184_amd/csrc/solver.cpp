@@ -712,16 +712,27 @@ void build_inner_and_precond(OpObj& op, const std::vector<double>& ixdiag, hipSt
   int64_t maxn = 0;
   for (int64_t o = 0; o < m.nobj; ++o)
     maxn = std::max(maxn, (m.obj_edge[o + 1] - m.obj_edge[o]) + (m.obj_tri[o + 1] - m.obj_tri[o]) - 1);
-  DenseScratch ds{};
   std::vector<void*> tmp;
   auto talloc = [&](size_t n) {
     double2* p = op.mem.alloc<double2>(n);
     tmp.push_back(p);
     return p;
   };
-  ds.P = talloc(64 * 64);
-  ds.R = talloc(size_t(256) * maxn);  // four panels (Gauss-Jordan applies them in groups)
-  ds.C = talloc(size_t(256) * maxn);
+  DenseScratch ds = dense_scratch_at(talloc(dense_scratch_elems(maxn)), maxn);
+  // every inverse is checked (pivots, probe vector); a broken-down elimination fails the assembly
+  auto checked = [&](const char* what, int64_t o) {
+    const DenseHealth h = dense_health(ds, st);
+    op.inv_min_pivot = std::min(op.inv_min_pivot, std::isnan(h.min_pivot_ratio) ? 0.0 : h.min_pivot_ratio);
+    op.inv_probe_err = std::max(op.inv_probe_err, std::isnan(h.probe_error) ? HUGE_VAL : h.probe_error);
+    if (!dense_health_ok(h)) {
+      char msg[256];
+      std::snprintf(msg, sizeof msg,
+                    "inversion of %s of object %lld broke down (no pivoting): smallest pivot ratio %.3e, "
+                    "probe error %.3e",
+                    what, (long long)o, h.min_pivot_ratio, h.probe_error);
+      throw Error(BEM_E_NUMERIC, msg);
+    }
+  };
   // diagonals through a gather kernel and a stream-ordered copy (complete on return)
   const int64_t nbuf = std::max(std::max(m.ne, m.nt), maxn);
   double2* dbuf = talloc(size_t(nbuf));
@@ -744,16 +755,17 @@ void build_inner_and_precond(OpObj& op, const std::vector<double>& ixdiag, hipSt
   double* odev = reinterpret_cast<double*>(talloc(size_t(nbuf)));
   double* tdev = reinterpret_cast<double*>(talloc(size_t(nbuf)));
   // symmetric Jacobi scaling |diag|^-1/2 (S and the charge Schur complements)
-  auto invert_jacobi = [&](Dense& M, int64_t n) {
+  auto invert_jacobi = [&](Dense& M, int64_t n, const char* what, int64_t o) {
     jacobi_vec(M.d64, M.ld, 0, n, rdev, st);
     scale_rows_cols(M.d64, M.ld, n, n, rdev, rdev, st);
     dense_invert(M.d64, n, M.ld, ds, st);
+    checked(what, o);
     scale_rows_cols(M.d64, M.ld, n, n, rdev, rdev, st);
   };
   // M_eq: Jacobi on the edge block, then the charge columns and rows normalised by their
   // largest entries (those of the coupling blocks).  r, c accumulate the total row and column
   // scales; u holds the partial scale of one step, o is all ones.
-  auto invert_meq = [&](Dense& M, int64_t neo, int64_t n) {
+  auto invert_meq = [&](Dense& M, int64_t neo, int64_t n, int64_t o) {
     const int64_t nq = n - neo;
     fill_vec(rdev, n, 1.0, st);
     fill_vec(odev, n, 1.0, st);
@@ -768,6 +780,7 @@ void build_inner_and_precond(OpObj& op, const std::vector<double>& ixdiag, hipSt
     recip_vec(tdev, nq, rdev + neo, udev + neo, st);
     scale_rows_cols(M.d64, M.ld, n, n, udev, odev, st);
     dense_invert(M.d64, n, M.ld, ds, st);
+    checked("M_eq", o);
     scale_rows_cols(M.d64, M.ld, n, n, cdev, rdev, st);
   };
   if (part == 1) op.Minv.clear();
@@ -785,7 +798,7 @@ void build_inner_and_precond(OpObj& op, const std::vector<double>& ixdiag, hipSt
       build_meq(op.LA_bg.d64 + e0 * op.LA_bg.ld + e0, op.LA_bg.ld, op.Lphi_bg.d64 + t0 * op.Lphi_bg.ld + t0,
                 op.Lphi_bg.ld, op.tp + e0, op.tm + e0, int32_t(t0), neo, nto, c2(op.mu_bg), c2(-1.0 / op.eps_bg),
                 op.k0 * op.k0, M.d64, M.ld, st);
-      invert_meq(M, neo, n);
+      invert_meq(M, neo, n, o);
       to_f32(M, st);
       op.Minv.push_back(M);
     }
@@ -803,7 +816,7 @@ void build_inner_and_precond(OpObj& op, const std::vector<double>& ixdiag, hipSt
       build_s(op.LA_bg.d64 + e0 * op.LA_bg.ld + e0, op.LA_bg.ld, op.Lphi_bg.d64 + t0 * op.Lphi_bg.ld + t0,
               op.Lphi_bg.ld, op.tp + e0, op.tm + e0, int32_t(t0), neo, c2(op.mu_bg),
               c2(-1.0 / (op.eps_bg * op.k0 * op.k0)), S.d64, S.ld, st);
-      invert_jacobi(S, neo);
+      invert_jacobi(S, neo, "S", o);
       to_f32(S, st);
       op.Minv.push_back(S);
     }
@@ -908,7 +921,7 @@ void build_inner_and_precond(OpObj& op, const std::vector<double>& ixdiag, hipSt
       Dense S = alloc_dense(op.mem, nq, nq, f32);
       const double k02 = op.k0 * op.k0;
       build_schur(dptr, didx, dval, nq, nto - 1, which == 0 ? c2(k02) : c2(-k02), S.d64, S.ld, st);
-      invert_jacobi(S, nq);
+      invert_jacobi(S, nq, which == 0 ? "the charge Schur complement" : "the equivalent charge Schur complement", o);
       to_f32(S, st);
       BEM_HIP(hipStreamSynchronize(st));
       op.mem.release(dptr);

@@ -98,15 +98,11 @@ def case(name, ctx, inner=B.BEM_INNER_GMRES, precond=0, precision=B.BEM_FP64):
     return _cache[key]
 
 
-@pytest.mark.parametrize("backend", ["valu", "mfma16", "mfma4", "mfma4-g2", "mfma4-g1"])
-def test_device_inverse_of_meq(backend, ctx, monkeypatch):
-    """The direct nested solve's device inverse times the oracle's M_eq is the identity (the
-    VALU, the 16x16x4 and the 4x4x4 matrix-core updates of the Gauss-Jordan elimination, with
-    panels applied in groups of four, and the 4x4x4 one in pairs and one panel at a time).
-    M_eq has 199 rows: one group of four panels, the last with 7 rows."""
-    monkeypatch.setenv("BEM_DENSE_VALU", "1" if backend == "valu" else "0")
-    monkeypatch.setenv("BEM_DENSE_MFMA16", "1" if backend == "mfma16" else "0")
-    monkeypatch.setenv("BEM_DENSE_GROUP", backend[-1] if backend.endswith(("g1", "g2")) else "4")
+def test_device_inverse_of_meq(ctx):
+    """The direct nested solve's device inverse times the oracle's M_eq is the identity (blocked
+    Gauss-Jordan, panels applied in groups of four by the float64 4x4x4 matrix-core update).
+    M_eq has 199 rows: one group of four panels, the last with 7 rows.  The assembly's own
+    inversion health is reported in the operator statistics."""
     w = CASES["ico80_lossy"]()
     if "ico80_lossy" not in _oracle:
         _oracle["ico80_lossy"] = S.assemble(w.xyz, w.tri, w.obj,
@@ -122,9 +118,12 @@ def test_device_inverse_of_meq(backend, ctx, monkeypatch):
     P = meq_perm(perm, ne, nt - 1)
     Minv = B.bem_block_export(ctx, op, B.BEM_BLOCK_MEQ_INV, len(Meq), len(Meq))
     err = np.abs(Minv @ Meq[np.ix_(P, P)] - np.eye(len(Meq))).max()
-    print(f"{backend}: max |M_eq^-1 M_eq - I| = {err:.2e}")
+    st = B.bem_op_stats_get(ctx, op)
+    print(f"max |M_eq^-1 M_eq - I| = {err:.2e}; pivot ratio {st['inverse_min_pivot_ratio']:.2e}, "
+          f"probe error {st['inverse_probe_error']:.2e}")
     B.bem_release(ctx, op)
     assert err < 1e-10
+    assert st["inverse_min_pivot_ratio"] > 1e-6 and st["inverse_probe_error"] < 1e-12
 
 
 def full_meq(ops):

@@ -37,3 +37,30 @@ def test_repeated_fill_and_solve_are_bitwise_identical():
         for got, want in zip(r[1:], runs[0][1:]):
             assert np.array_equal(got, want)
     B.bem_destroy(ctx)
+
+
+def test_sphere5120_fill_is_bitwise_reproducible():
+    """The -O3 quadrature fill at full size (the 5120-triangle sphere of the solve benchmark,
+    k0 a = 5, eps_r = 2.5 - 0.1j): three assemblies give bitwise identical K~ (interior and
+    background), L^A and L^phi blocks."""
+    w = meshgen.config_c2()
+    ctx = B.bem_create(0)
+    try:
+        mesh = B.bem_mesh_load(ctx, w.xyz, w.tri)
+        info = B.bem_mesh_info(ctx, mesh)
+        ne, nt = info["n_edge"], info["n_tri"]
+        blocks = [(B.BEM_BLOCK_K_INT, ne), (B.BEM_BLOCK_K_BG, ne), (B.BEM_BLOCK_LA_INT, ne),
+                  (B.BEM_BLOCK_LPHI_BG, nt)]
+        first = None
+        for _ in range(3):
+            op = B.bem_assemble(ctx, mesh, B.make_problem(w.freq_hz, w.eps_r, w.mu_r, w.sigma))
+            mats = [B.bem_block_export(ctx, op, b, n, n) for b, n in blocks]
+            B.bem_release(ctx, op)
+            if first is None:
+                first = mats
+                continue
+            for (b, _), got, want in zip(blocks, mats, first):
+                diff = int((got != want).sum())
+                assert diff == 0, (b, diff)
+    finally:
+        B.bem_destroy(ctx)
