@@ -192,6 +192,14 @@ int bem_apply(bem_ctx* ctx, bem_op_h op, int block, const void* x, void* y, int6
  * down and A holds no usable inverse.  BEM_E_INVALID for n < 0, ld < n or a null A. */
 int bem_dense_invert(bem_ctx* ctx, void* A, int64_t n, int64_t ld, void* stream, double* health);
 
+/* bem_dense_invert for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): the same elimination, checks, arguments
+ * and status codes, but the workspace is a fixed device array of the library (one per GPU, about
+ * 17 MB, held until the process ends), so the call allocates nothing.  n is limited to 2048 rows
+ * (BEM_E_INVALID above).  Every call on one GPU uses that GPU's array: calls that overlap on one
+ * GPU (from any context or thread) race and must not be made. */
+int bem_dense_invert_noalloc(bem_ctx* ctx, void* A, int64_t n, int64_t ld, void* stream, double* health);
+
 /* Copy a dense block (blocks 1..7) into a host buffer, row-major complex
  * float64, rows x cols as documented above (block-diagonal blocks include
  * their zero off-diagonal parts). */

@@ -26,6 +26,7 @@ BEM_EXC_PLANE_WAVE, BEM_EXC_DELTA_GAP = 0, 1
 
 SYMBOLS = ["bem_create", "bem_destroy", "bem_last_error", "bem_mesh_load", "bem_mesh_info", "bem_edge_table",
            "bem_near_pairs", "bem_mesh_copies", "bem_far_field", "bem_assemble", "bem_apply", "bem_dense_invert",
+           "bem_dense_invert_noalloc",
            "bem_block_export", "bem_set_inner_tol", "bem_solve",
            "bem_submit", "bem_poll", "bem_drain", "bem_release", "bem_memory_in_use", "bem_op_stats_get",
            "bem_profile_enable", "bem_profile_read", "bem_serve_stats"]
@@ -107,6 +108,7 @@ def lib() -> C.CDLL:
             "bem_assemble": (C.c_int, [P, C.c_uint64, C.POINTER(bem_problem), C.POINTER(C.c_uint64)]),
             "bem_apply": (C.c_int, [P, C.c_uint64, C.c_int, P, P, I64, P]),
             "bem_dense_invert": (C.c_int, [P, P, I64, I64, P, C.POINTER(D)]),
+            "bem_dense_invert_noalloc": (C.c_int, [P, P, I64, I64, P, C.POINTER(D)]),
             "bem_block_export": (C.c_int, [P, C.c_uint64, C.c_int, C.POINTER(c64)]),
             "bem_set_inner_tol": (C.c_int, [P, C.c_uint64, D]),
             "bem_solve": (C.c_int, [P, C.c_uint64, C.POINTER(bem_excitation), I64, C.POINTER(bem_solve_opts),
@@ -253,6 +255,15 @@ def bem_dense_invert(ctx, a_ptr: int, n: int, ld: int, stream=None):
     h = np.zeros(2, np.float64)
     rc = lib().bem_dense_invert(ctx, C.c_void_p(a_ptr), int(n), int(ld), C.c_void_p(stream) if stream else None,
                                 h.ctypes.data_as(C.POINTER(C.c_double)))
+    _check(ctx, rc, allow=(BEM_OK, BEM_E_NUMERIC))
+    return rc, (float(h[0]), float(h[1]))
+
+
+def bem_dense_invert_noalloc(ctx, a_ptr: int, n: int, ld: int, stream=None):
+    """bem_dense_invert on the library's fixed workspace (allocates nothing; n <= 2048)."""
+    h = np.zeros(2, np.float64)
+    rc = lib().bem_dense_invert_noalloc(ctx, C.c_void_p(a_ptr), int(n), int(ld),
+                                        C.c_void_p(stream) if stream else None, h.ctypes.data_as(C.POINTER(C.c_double)))
     _check(ctx, rc, allow=(BEM_OK, BEM_E_NUMERIC))
     return rc, (float(h[0]), float(h[1]))
 

@@ -83,6 +83,7 @@ int bem_create(int device, size_t hbm_budget_bytes, bem_ctx** out) {
         return fail(BEM_E_DEVICE, "no such HIP device");
       }
       BEM_HIP(hipSetDevice(device));
+      bem::noalloc_scratch_init(device);  // device address of the fixed inversion workspace
       BEM_HIP(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
       BEM_HIP(hipHostMalloc(reinterpret_cast<void**>(&ctx->pinned), bem::kPinnedBytes, hipHostMallocDefault));
       size_t fr = 0, tot = 0;
@@ -230,6 +231,29 @@ int bem_dense_invert(bem_ctx* c, void* A, int64_t n, int64_t ld, void* stream, d
     bem::DenseScratch ws = bem::dense_scratch_at(mem.alloc<double2>(bem::dense_scratch_elems(n)), n);
     bem::dense_invert(static_cast<double2*>(A), n, ld, ws, st);
     const bem::DenseHealth h = bem::dense_health(ws, st);
+    if (health) {
+      health[0] = h.min_pivot_ratio;
+      health[1] = h.probe_error;
+    }
+    if (!bem::dense_health_ok(h)) {
+      char msg[160];
+      std::snprintf(msg, sizeof msg, "elimination without pivoting broke down: smallest pivot ratio %.3e, probe error %.3e",
+                    h.min_pivot_ratio, h.probe_error);
+      return fail(BEM_E_NUMERIC, msg);
+    }
+    return BEM_OK;
+  });
+}
+
+int bem_dense_invert_noalloc(bem_ctx* c, void* A, int64_t n, int64_t ld, void* stream, double* health) {
+  return guarded([&]() -> int {
+    bem::Ctx* ctx = C(c);
+    need_device(c);
+    if (!A || n < 0 || ld < n) return fail(BEM_E_INVALID, "invalid matrix");
+    if (n == 0) return BEM_OK;
+    hipStream_t st = stream ? static_cast<hipStream_t>(stream) : ctx->stream;
+    bem::DenseHealth h{};
+    bem::dense_invert_noalloc(ctx->device, static_cast<double2*>(A), n, ld, &h, st);
     if (health) {
       health[0] = h.min_pivot_ratio;
       health[1] = h.probe_error;

@@ -18,7 +18,7 @@ struct DenseScratch {
 
 // Device workspace of dense_invert for matrices up to n rows, in elements of double2
 // (P, R, C, probe_y, then probe_d and health reinterpreted as doubles).
-inline size_t dense_scratch_elems(int64_t n) { return size_t(64 * 64) + size_t(513) * size_t(n) + size_t(n) + 2; }
+constexpr size_t dense_scratch_elems(int64_t n) { return size_t(64 * 64) + size_t(513) * size_t(n) + size_t(n) + 2; }
 inline DenseScratch dense_scratch_at(double2* base, int64_t n) {
   DenseScratch ws;
   ws.P = base;
@@ -48,6 +48,16 @@ constexpr double kMinPivotRatio = 1e-12;
 constexpr double kMaxProbeError = 1e-6;
 DenseHealth dense_health(const DenseScratch& ws, hipStream_t st);
 bool dense_health_ok(const DenseHealth& h);
+
+// Inversion without allocation: the same elimination on a workspace that is a fixed device array
+// (one per GPU, for matrices of up to kNoAllocMaxN rows, about 17 MB).  noalloc_scratch_init takes
+// the array's device address once per device, with that device current (at context creation);
+// dense_invert_noalloc then allocates nothing.  Calls that overlap on one GPU share the array and
+// race.
+constexpr int64_t kNoAllocMaxN = 2048;
+constexpr int kMaxDevices = 64;
+void noalloc_scratch_init(int device);
+void dense_invert_noalloc(int device, double2* A, int64_t n, int64_t ld, DenseHealth* health, hipStream_t st);
 
 // A[i][j] *= rs[i] cs[j] for i < nr, j < nc (device scale vectors, real).
 void scale_rows_cols(double2* A, int64_t ld, int64_t nr, int64_t nc, const double* rs, const double* cs,

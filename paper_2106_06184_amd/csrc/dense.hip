@@ -14,6 +14,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
+#include <string>
 
 #include "dense.h"
 #include "prof.h"
@@ -640,6 +642,48 @@ void dense_invert(double2* A, int64_t n, int64_t ld, DenseScratch& ws, hipStream
   hipLaunchKernelGGL(dev::k_probe_mv, dim3(gr), dim3(256), 0, st, A, ld, n, ws.probe_y, ws.probe_d, 1, ws.health);
   hipLaunchKernelGGL(dev::k_probe_reduce, dim3(1), dim3(256), 0, st, ws.probe_d, n, ws.health);
   BEM_HIP(hipGetLastError());
+}
+
+// ---- inversion without allocation (for callers that cannot allocate device memory)
+// A fixed workspace for matrices of up to kNoAllocMaxN rows, one copy per GPU (it lives as long as
+// the process).  Host code never uses the array's name as an address: its device address is taken
+// once per device by noalloc_scratch_init and kept in g_noalloc_ptr.
+namespace dev {
+static __device__ __align__(256) double2 scratch[64 * 64 + 514 * kNoAllocMaxN + 2];
+}  // namespace dev
+static_assert(sizeof(dev::scratch) >= sizeof(double2) * dense_scratch_elems(kNoAllocMaxN), "workspace layout");
+static std::mutex g_noalloc_mu;
+static double2* g_noalloc_ptr[kMaxDevices] = {};
+
+void noalloc_scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) throw Error(BEM_E_DEVICE, "device index beyond the workspace table");
+  std::lock_guard<std::mutex> g(g_noalloc_mu);
+  if (g_noalloc_ptr[device]) return;
+  int cur = -1;
+  BEM_HIP(hipGetDevice(&cur));
+  if (cur != device) throw Error(BEM_E_DEVICE, "workspace set-up needs its device current");
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(dev::scratch));
+  if (e != hipSuccess || !p) {
+    (void)hipGetLastError();
+    throw Error(BEM_E_DEVICE, std::string("address of the inversion workspace: ") + hipGetErrorString(e));
+  }
+  g_noalloc_ptr[device] = static_cast<double2*>(p);
+}
+
+void dense_invert_noalloc(int device, double2* A, int64_t n, int64_t ld, DenseHealth* health, hipStream_t st) {
+  if (n > kNoAllocMaxN)
+    throw Error(BEM_E_INVALID, "n = " + std::to_string(n) + " exceeds the " + std::to_string(kNoAllocMaxN) +
+                                   "-row limit of the inversion without allocation");
+  double2* base = nullptr;
+  {
+    std::lock_guard<std::mutex> g(g_noalloc_mu);
+    base = (device >= 0 && device < kMaxDevices) ? g_noalloc_ptr[device] : nullptr;
+  }
+  if (!base) throw Error(BEM_E_DEVICE, "inversion workspace not set up on this device");
+  DenseScratch ws = dense_scratch_at(base, n);
+  dense_invert(A, n, ld, ws, st);
+  *health = dense_health(ws, st);
 }
 
 DenseHealth dense_health(const DenseScratch& ws, hipStream_t st) {
