@@ -136,36 +136,133 @@ def copy_calibration() -> int:
     return 0
 
 
-def run_serve(args) -> int:
-    """Serving stream (bem_submit / bem_poll): requests of different meshes, frequencies,
-    materials and excitation counts arrive by a Poisson process and are admitted by the HBM
-    budget; reports completed requests/s over the run and p50/p99 request latency (submit to
-    result)."""
+def _oracle_assemble_parallel(w, procs: int):
+    """The oracle's four dense fills split by test triangle over `procs` host processes (rows
+    summed in a fixed chunk order), then its Operators record - the same arithmetic as
+    oracle.systems.assemble, on every host core."""
+    import multiprocessing as mp
+
     import numpy as np
+
+    from oracle import constants as OC
+    from oracle import mesh as OM
+    from oracle import operators as OO
+    from oracle import systems as OS
+
+    topo = OM.build_topology(w.xyz, w.tri, w.obj)
+    bary = OM.buffa_christiansen(topo)
+    bcd = OO.bc_on_subtriangles(bary)
+    near = OO.near_pairs(topo)
+    _ORACLE_SHARED.update(topo=topo, bary=bary, bcd=bcd, near=near)
+    nt, ne = len(topo.tri), len(topo.edges)
+    k0 = OC.k0_of(w.freq_hz)
+    epsc = OC.eps_c(w.eps_r[0], w.sigma[0], w.freq_hz)
+    k_int = OC.wavenumber(k0, epsc, w.mu_r[0])
+    k_bg = OC.wavenumber(k0, w.eps_bg, w.mu_bg)
+    chunks = [list(range(i, nt, 4 * procs)) for i in range(4 * procs)]
+    mats = {}
+    with mp.get_context("fork").Pool(procs, initializer=_oracle_worker_init) as pool:
+        for name, k in (("int", k_int), ("bg", k_bg)):
+            LA, Lp, K = np.zeros((ne, ne), complex), np.zeros((nt, nt), complex), np.zeros((ne, ne), complex)
+            for er, la, tr, lp, kk in pool.imap(_oracle_rows, [(k, c) for c in chunks]):
+                LA[er] += la
+                Lp[tr] += lp
+                K[er] += kk
+            mats[name] = (LA, Lp, K)
+    Ix = OO.gram_Ix(topo, bary, bcd)
+    D = OM.incidence_D(topo).toarray()
+    Bm, F, _ = OM.charge_maps(topo)
+    return OS.Operators(topo, bary, D, Bm.toarray(), F.toarray(), Ix, *mats["int"], *mats["bg"], mats["bg"][2], k0,
+                        [k_int], k_bg, [epsc], list(w.mu_r), complex(w.eps_bg), float(w.mu_bg))
+
+
+_ORACLE_SHARED: dict = {}
+
+
+def _oracle_worker_init():
+    from threadpoolctl import threadpool_limits
+    threadpool_limits(1)
+
+
+def _oracle_rows(args):
+    import numpy as np
+
+    from oracle import operators as OO
+    k, subset = args
+    g = _ORACLE_SHARED
+    LA, Lp = OO.fill_L(g["topo"], k, g["near"], test_subset=subset)
+    K = OO.fill_K(g["topo"], g["bary"], k, g["near"], g["bcd"], test_subset=subset)
+    er = np.unique(g["topo"].tri_edges[subset].ravel())
+    return er, LA[er], np.asarray(subset), Lp[subset], K[er]
+
+
+def serve_cpu_baseline(requests, budget_s: float = 20.0) -> dict:
+    """The oracle solving whole requests of the stream, smallest first, until `budget_s` of host
+    wall time is spent (at least one): fills on every host core, the augmented system (eqs.
+    AEFIEintdis, AEFIEeqvdis, AEFIEextdis) by LAPACK LU for all the request's plane waves."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    from oracle import systems as OS
+
+    procs = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    done, t_total, names = 0, 0.0, []
+    for w in sorted(requests, key=lambda w: (len(w.tri), len(w.khat))):
+        t0 = time.perf_counter()
+        ops = _oracle_assemble_parallel(w, procs)
+        b = np.stack([OS.rhs(ops, w.khat[i], w.pol[i]) for i in range(len(w.khat))], axis=1)
+        OS.solve_augmented(ops, b)
+        t_total += time.perf_counter() - t0
+        done += 1
+        names.append(f"{w.name} ({len(w.tri)} triangles)")
+        if t_total >= budget_s:
+            break
+    blas = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    cpu = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
+    return {"value": done / t_total, "unit": "solves/s", "cores": int(procs), "kind": "oracle",
+            "sample": f"{done} whole request(s) of the timed stream, smallest first, timed end to end "
+                      f"(fill on {procs} processes, augmented LU with {blas} BLAS threads): " + "; ".join(names),
+            "seconds": t_total, "host_cpu": cpu, "nproc": os.cpu_count()}
+
+
+def _dense_bytes(nt: int) -> float:
+    """float64 bytes of the dense blocks one single-object request fills: L^A, L^phi at the
+    background wavenumber, L^A, L^phi, K~ at the object's, K~ at the background's."""
+    ne = 1.5 * nt
+    return 16.0 * (4 * ne * ne + 2.0 * nt * nt)
+
+
+def _serve_once(B, stream, prec, args):
+    """Submit the stream's requests at their arrival times on a fresh context, poll until all are
+    final.  Returns the per-request records, the wall time from the first arrival to the last
+    completion, and the combiner counters."""
     import torch
 
-    import meshgen
-    import paper_2106_06184_amd as B
-
-    stream = meshgen.serving_stream(args.serve_requests, rate_hz=args.serve_rate)
-    if args.restart <= 0:
-        args.restart = 200
     ctx = B.bem_create(0)
     opts = B.solve_opts(tol=args.tol, restart=args.restart, maxit=args.maxit, max_refine=8)
-    prec = B.BEM_MIXED if args.precision == "mixed" else B.BEM_FP64
 
     def request(w):
-        prob = B.make_problem(w.freq_hz, w.eps_r, w.mu_r, w.sigma, precision=prec)
-        return B.Request(w.xyz, w.tri, w.obj, prob, B.plane_waves(w.khat, w.pol), opts)
+        p = B.make_problem(w.freq_hz, w.eps_r, w.mu_r, w.sigma, precision=prec)
+        return B.Request(w.xyz, w.tri, w.obj, p, B.plane_waves(w.khat, w.pol), opts)
 
-    # warm-up: one small request alone (kernel loading, allocator)
-    r0 = request(stream[0][1])
-    t = B.bem_submit(ctx, r0)
+    warm, timed = stream[:args.warmup], stream[args.warmup:]
+    # warm-up requests, all at once, untimed (kernel loading, allocator, host threads)
+    held = [request(w) for _, w in warm]  # the outputs must outlive the requests
+    tickets = [B.bem_submit(ctx, r) for r in held]
     B.bem_drain(ctx)
-    B.bem_poll(ctx, t)
+    for t in tickets:
+        try:
+            B.bem_poll(ctx, t)
+        except B.BemError as e:
+            log(f"  warm-up request failed: {e}")
     torch.cuda.synchronize()
-    reqs = [(at, request(w), w) for at, w in stream]
-    pending, lat, status, n_exc = {}, [], [], 0
+    reqs = [(at - timed[0][0], request(w), w) for at, w in timed]
+    pending, recs = {}, []
     t0 = time.perf_counter()
     i = 0
     while i < len(reqs) or pending:
@@ -174,41 +271,154 @@ def run_serve(args) -> int:
             pending[B.bem_submit(ctx, reqs[i][1])] = reqs[i]
             i += 1
         for tk in list(pending):
-            rc, info = B.bem_poll(ctx, tk)
+            try:
+                rc, info = B.bem_poll(ctx, tk)
+            except B.BemError as e:
+                rc, info = e.args[0], None
             if rc != B.BEM_PENDING:
                 _, r, w = pending.pop(tk)
-                lat.append(info.seconds)
-                status.append(rc)
-                n_exc += len(w.khat)
-                log(f"  {w.name:36s} status {rc:2d} latency {info.seconds:.3f} s outer {info.outer_iters} "
-                    f"res {info.rel_residual:.1e}")
-        time.sleep(0.001)
+                recs.append({"name": w.name, "nt": len(w.tri), "nexc": len(w.khat), "status": int(rc) if isinstance(rc, int) else -99,
+                             "latency": info.seconds if info else float("nan"),
+                             "outer": info.outer_iters if info else -1,
+                             "res": info.rel_residual if info else float("nan")})
+                log(f"  {w.name:36s} status {recs[-1]['status']:3d} latency {recs[-1]['latency']:7.3f} s "
+                    f"outer {recs[-1]['outer']:5d} res {recs[-1]['res']:.1e}")
+        time.sleep(0.0005)
     wall = time.perf_counter() - t0
-    launches, products = B.bem_serve_stats(ctx)
+    comb = B.bem_serve_stats(ctx)
     B.bem_destroy(ctx)
-    ok = sum(1 for s_ in status if s_ == B.BEM_OK)
+    return recs, wall, comb
+
+
+def _profiled_pass(B, timed, args):
+    """The timed requests once more, one after another (mesh load, mixed-precision assembly,
+    solve), with HIP events recorded around every launch on its stream: per-class device time,
+    algorithmic bytes and work of each kernel class without the overlap of concurrent requests."""
+    ctx = B.bem_create(0)
+    opts = B.solve_opts(tol=args.tol, restart=args.restart, maxit=args.maxit, max_refine=8)
+    B.bem_profile_enable(True)
+    for w in timed:
+        mesh = B.bem_mesh_load(ctx, w.xyz, w.tri, w.obj)
+        info = B.bem_mesh_info(ctx, mesh)
+        op = B.bem_assemble(ctx, mesh, B.make_problem(w.freq_hz, w.eps_r, w.mu_r, w.sigma, precision=B.BEM_MIXED))
+        rc, _, _, _, si = B.bem_solve(ctx, op, B.plane_waves(w.khat, w.pol), opts, info["n_edge"], info["n_tri"])
+        B.bem_release(ctx, op)
+        B.bem_release(ctx, mesh)
+        log(f"  profiled {w.name:36s} status {rc} outer {si.outer_iters}")
+    prof = {k: B.bem_profile_read(k) for k in range(len(B.KC_NAMES))}
+    B.bem_profile_enable(False)
+    B.bem_destroy(ctx)
+    return prof
+
+
+def _roofline(B, prof) -> dict:
+    names = dict(enumerate(B.KC_NAMES))
+    dom = max(prof, key=lambda k: prof[k]["ms"])
+    p = prof[dom]
+    avg_ms = p["ms"] / max(p["launches"], 1)
+    if dom in (B.KC_GEMV_F64, B.KC_GEMV_F32, B.KC_GATHER):
+        achieved = p["bytes"] / (p["ms"] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBPS}
+    elif dom == B.KC_GEMM_F32:
+        achieved = p["work"] / (p["ms"] * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": achieved, "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP32_MFMA_PEAK_TFLOPS}
+    elif dom in (B.KC_DENSE_INV, B.KC_GEMM_F64):
+        achieved = p["work"] / (p["ms"] * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": achieved, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP64_MFMA_PEAK_TFLOPS}
+    else:
+        # fill: ~ 64 float64 vector operations per kernel evaluation (see the design notes)
+        achieved = p["work"] * 64 / (p["ms"] * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP64_VECTOR_PEAK_TFLOPS}
+    roof.update({"kernel": names[dom], "avg_launch_ms": avg_ms, "launches": p["launches"],
+                 "traffic": measured_traffic(names[dom]),
+                 "algorithmic_bytes_per_launch": p["bytes"] / max(p["launches"], 1), "traffic_unit": "bytes/launch"})
+    return roof
+
+
+def run_serve(args) -> int:
+    """Serving mix (bem_submit / bem_poll): W warm-up requests, then a timed Poisson stream of K
+    requests (one bench step = one request: mesh load, fill, nested-solve inverses, batched
+    GMRES to the residual tolerance for all its plane waves), admitted by the HBM budget and
+    overlapping on the device.  value = completed requests per second of wall time from the
+    first timed arrival to the last completion; p50/p99 = request latency (submit to result).
+    The same stream is served in mixed precision (the headline) and in float64."""
+    import numpy as np
+
+    import meshgen
+    import paper_2106_06184_amd as B
+
+    if args.restart <= 0:
+        args.restart = 200
+    stream = meshgen.mixed_stream(args.warmup + args.steps, rate_hz=args.serve_rate, seed=args.serve_seed)
+    timed = [w for _, w in stream[args.warmup:]]
+    runs = {}
+    for prec_name in ("mixed", "fp64"):
+        prec = B.BEM_MIXED if prec_name == "mixed" else B.BEM_FP64
+        log(f"serving {len(timed)} requests ({prec_name}) after {args.warmup} warm-up requests ...")
+        recs, wall, comb = _serve_once(B, stream, prec, args)
+        ok = [r for r in recs if r["status"] == B.BEM_OK]
+        lat = [r["latency"] for r in recs]
+        runs[prec_name] = {"value": len(ok) / wall, "wall_s": wall, "converged": len(ok), "requests": len(recs),
+                           "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+                           "excitation_solves_per_s": sum(r["nexc"] for r in ok) / wall,
+                           "combined_launches": comb[0], "combined_products": comb[1],
+                           "failed": [(r["name"], r["status"]) for r in recs if r["status"] != B.BEM_OK]}
+        log(f"  {prec_name}: {runs[prec_name]['value']:.3f} requests/s, p50 {runs[prec_name]['p50_s']:.2f} s, "
+            f"p99 {runs[prec_name]['p99_s']:.2f} s, {len(ok)}/{len(recs)} converged")
+    m, d = runs["mixed"], runs["fp64"]
+    log("profiled pass over the timed requests (one at a time) ...")
+    prof = _profiled_pass(B, timed, args)
+    names = dict(enumerate(B.KC_NAMES))
+    for k, p in prof.items():
+        log(f"  {names[k]:16s} launches {p['launches']:7d}  {p['ms']:10.2f} ms  "
+            f"{(p['bytes'] / p['ms'] / 1e6 if p['ms'] > 0 else 0):8.1f} GB/s  "
+            f"{(p['work'] / p['ms'] / 1e9 if p['ms'] > 0 else 0):8.2f} Twork/s")
+    fill_ms = sum(prof[k]["ms"] for k in (B.KC_FILL_L, B.KC_FILL_K, B.KC_FILL_NEAR, B.KC_GATHER))
+    gemv_b = prof[B.KC_GEMV_F32]["bytes"] + prof[B.KC_GEMV_F64]["bytes"]
+    gemv_ms = prof[B.KC_GEMV_F32]["ms"] + prof[B.KC_GEMV_F64]["ms"]
     out = {
-        "metric": "serving: completed requests/s with p50/p99 latency at 1e-6 relative residual",
-        "value": ok / wall, "unit": "requests/s", "n_gpus": 1, "steps": len(reqs), "warmup": 1,
-        "ms_per_step": 1e3 * wall / len(reqs), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32+f64" if args.precision == "mixed" else "f64", "data": "synthetic",
-        "config": {"workload": f"serving stream: {len(reqs)} requests, Poisson {args.serve_rate}/s, spheres/"
-                               "ellipsoids/cubes 300-3072 triangles, eps_r 1.5-6, k0a 0.5-3, 1-16 plane waves",
-                   "tol": args.tol, "restart": args.restart, "precision": args.precision},
-        "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
-        "excitation_solves_per_s": n_exc / wall, "converged": ok,
-        "combined_launches": launches, "combined_products": products,
+        "metric": "solves/s + p50/p99 latency at 1e-6 relative residual (serving mix)",
+        "value": m["value"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * m["wall_s"] / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "serving mix: Poisson arrivals of spheres, 1.0/0.6/0.4 ellipsoids and cubes "
+                               "(cube-topology meshes of 12 n^2 triangles, T log-uniform in [320, 20000]), "
+                               "eps_r ~ U[1.5, 10], k0 a ~ U[0.5, 10] redrawn below 10 mean edges per interior "
+                               "wavelength, 1-64 random plane waves each; one step = one request",
+                   "rate_per_s": args.serve_rate, "seed": args.serve_seed, "tol": args.tol,
+                   "restart": args.restart, "precision": "mixed", "admission": "HBM budget, 4 slots",
+                   "triangles": [len(w.tri) for w in timed], "plane_waves": [len(w.khat) for w in timed]},
+        "p50_s": m["p50_s"], "p99_s": m["p99_s"],
+        "excitation_solves_per_s": m["excitation_solves_per_s"],
+        "converged": m["converged"],
+        "fp64": {k: d[k] for k in ("value", "p50_s", "p99_s", "excitation_solves_per_s", "converged", "wall_s")},
+        "mixed_over_fp64": m["value"] / d["value"] if d["value"] > 0 else None,
+        "fill_GBps": sum(_dense_bytes(len(w.tri)) for w in timed) / (fill_ms * 1e-3) / 1e9 if fill_ms > 0 else None,
+        "matvec_frac_hbm": (gemv_b / (gemv_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS) if gemv_ms > 0 else None,
+        "combined_launches": m["combined_launches"], "combined_products": m["combined_products"],
+        "roofline": _roofline(B, prof),
     }
+    if m["failed"] or d["failed"]:
+        out["failed"] = {"mixed": m["failed"], "fp64": d["failed"]}
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on whole requests of the stream ...")
+        out["cpu_baseline"] = serve_cpu_baseline(timed)
     print(json.dumps(out), flush=True)
-    return 0 if ok == len(reqs) else 1
+    return 0 if not m["failed"] else 1
 
 
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=4)
+    ap.add_argument("--workload", default="serve",
+                    help="serve (default: the serving mix), or one problem solved per step: c1, c2, "
+                         "c2x256, c3, spharr, c4")
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--inner", default="auto", choices=["auto", "gmres", "direct", "schur"])
     ap.add_argument("--formulation", default="sldm", choices=["sldm", "eaefie"],
@@ -225,19 +435,20 @@ def main() -> int:
     ap.add_argument("--restart", type=int, default=0,
                     help="GMRES restart length (default 300; 200 when serving)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=24)
-    ap.add_argument("--serve-rate", type=float, default=20.0)
+    ap.add_argument("--serve-rate", type=float, default=2.0,
+                    help="mean Poisson arrival rate of the serving mix, requests/s")
+    ap.add_argument("--serve-seed", type=int, default=5)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the plain copy used to calibrate the HBM byte counters")
     args = ap.parse_args()
     if args.copy_calibration:
         return copy_calibration()
-    if args.workload == "serve":
-        return run_serve(args)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU layout is a "
               f"design note, not a run.", file=sys.stderr)
         return 2
+    if args.workload == "serve":
+        return run_serve(args)
 
     import numpy as np
     import torch

@@ -65,6 +65,23 @@ def icosphere(level: int, radius: float = 1.0) -> tuple[np.ndarray, np.ndarray]:
     return xyz, _orient_outward(xyz, tri, np.zeros(3)).astype(np.int32)
 
 
+def tetrahedron(radius: float = 1.0) -> tuple[np.ndarray, np.ndarray]:
+    """Regular tetrahedron inscribed in a sphere of the given radius (4 triangles)."""
+    v = np.array([(1, 1, 1), (1, -1, -1), (-1, 1, -1), (-1, -1, 1)], dtype=np.float64) / math.sqrt(3.0)
+    tri = np.array([(0, 1, 2), (0, 3, 1), (0, 2, 3), (1, 3, 2)], dtype=np.int32)
+    xyz = v * radius
+    return xyz, _orient_outward(xyz, tri, np.zeros(3)).astype(np.int32)
+
+
+def octahedron(radius: float = 1.0) -> tuple[np.ndarray, np.ndarray]:
+    """Regular octahedron inscribed in a sphere of the given radius (8 triangles)."""
+    v = np.array([(1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)], dtype=np.float64)
+    tri = np.array([(0, 2, 4), (2, 1, 4), (1, 3, 4), (3, 0, 4), (2, 0, 5), (1, 2, 5), (3, 1, 5), (0, 3, 5)],
+                   dtype=np.int32)
+    xyz = v * radius
+    return xyz, _orient_outward(xyz, tri, np.zeros(3)).astype(np.int32)
+
+
 def bipyramid(n: int, radius: float = 1.0, height: float = 1.0, rings: int = 2) -> tuple[np.ndarray, np.ndarray]:
     """Double cone over an n-gon with `rings` rings of n vertices between the equator and each
     apex: the apexes have valence n (the largest vertex valence of the mesh)."""
@@ -339,6 +356,56 @@ def copper_bars(h_min: float = 0.05e-6, h_max: float = 1.0e-6, pitch: float = 3.
             x, t = _box_surface(xs, cs + iy * pitch, cs + iz * pitch)
             meshes.append((x, t))
     return merge(meshes)
+
+
+def mean_edge(xyz: np.ndarray, tri: np.ndarray) -> float:
+    e = np.concatenate([tri[:, [0, 1]], tri[:, [1, 2]], tri[:, [2, 0]]])
+    e = np.unique(np.sort(e, axis=1), axis=0)
+    return float(np.linalg.norm(xyz[e[:, 0]] - xyz[e[:, 1]], axis=1).mean())
+
+
+def mixed_stream(n_req: int, rate_hz: float, seed: int = 5, t_min: int = 320, t_max: int = 20000,
+                 eps_range=(1.5, 10.0), k0a_range=(0.5, 10.0), exc_max: int = 64, min_edges_per_wl: float = 10.0):
+    """The serving mix: Poisson arrivals (mean rate `rate_hz`) of scattering requests.
+
+    Each request: shape uniform over {sphere, ellipsoid with semi-axes 1.0/0.6/0.4 m, cube of
+    circumradius 1 m}, every one an n x n-per-face cube-topology mesh of 12 n^2 triangles
+    (sphere and ellipsoid: cubed sphere; cube: structured box), n = round(sqrt(T / 12)) with T
+    log-uniform in [t_min, t_max]; eps_r ~ U(eps_range), k0 a ~ U(k0a_range) with a the
+    circumradius (1 m); R ~ U{1..exc_max} random plane waves.  A draw of (eps_r, k0 a) that leaves
+    fewer than `min_edges_per_wl` mean edges per interior wavelength 2 pi / (k0 sqrt(eps_r)) on
+    the drawn mesh is redrawn (the mesh draw is kept, so T keeps its stated distribution).
+    Returns a list of (arrival time in s, Workload).
+    """
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for i in range(n_req):
+        t += float(rng.exponential(1.0 / rate_hz))
+        target = math.exp(rng.uniform(math.log(t_min), math.log(t_max)))
+        n = max(2, int(round(math.sqrt(target / 12.0))))
+        kind = int(rng.integers(3))
+        if kind == 0:
+            xyz, tri = cubed_sphere(n, (1.0, 1.0, 1.0))
+            name = f"sphere{len(tri)}"
+        elif kind == 1:
+            xyz, tri = cubed_sphere(n, (1.0, 0.6, 0.4))
+            name = f"ellipsoid{len(tri)}"
+        else:
+            xyz, tri = cube(n, 2.0 / math.sqrt(3.0))
+            name = f"cube{len(tri)}"
+        h = mean_edge(xyz, tri)
+        while True:
+            eps = float(rng.uniform(*eps_range))
+            k0a = float(rng.uniform(*k0a_range))
+            if 2 * math.pi / (k0a * math.sqrt(eps)) / h >= min_edges_per_wl:
+                break
+        n_exc = int(rng.integers(1, exc_max + 1))
+        khat, pol = plane_wave_draws(n_exc, seed=1000 + i)
+        w = Workload(f"{name}_k0a{k0a:.2f}_eps{eps:.2f}_x{n_exc}", xyz, tri, np.zeros(len(tri), np.int32),
+                     freq_from_k0(k0a), [eps], [1.0], [0.0], khat=khat, pol=pol.astype(np.complex128))
+        out.append((t, w))
+    return out
 
 
 def serving_stream(n_req: int = 24, rate_hz: float = 6.0, seed: int = 5, n_min: int = 320, n_max: int = 3072,

@@ -23,4 +23,8 @@ Modules
   systems     augmented, reduced and final (explicit-Y) systems, LU solves,
               far-field / RCS of the differential current
   mie         Mie series for a homogeneous dielectric sphere
+  brute       whole Galerkin entries of L^A, L^phi, K~ by brute force (singularity-
+              cancelling maps of each triangle pair onto the 4-cube, tensor
+              Gauss-Legendre): no extraction, no closed forms, no rule set Q; it pins
+              the near-pair fill of `operators`
 """

@@ -602,6 +602,7 @@ static void launch_update(double2* A, int64_t ld, int64_t n, int mode, int fix, 
                8.0 * b * std::min(elems, mode == 0 ? double(n) * n : 64.0 * n));
   hipLaunchKernelGGL(dev::k_gj_update_mfma4, g, dim3(256), 0, st, reinterpret_cast<double*>(A), ld, n, mode, fix, b,
                      R, C);
+  BEM_HIP(hipGetLastError());  // before the profiler's scope ends (it clears event-query status)
 }
 
 // Blocked Gauss-Jordan, panels of NB, applied in groups of G panels so that one pass over the

@@ -54,50 +54,55 @@ void Profiler::end(hipStream_t st, int cls, double bytes, double work) {
     b = take();
   }
   (void)hipEventRecord(b, st);
-  std::lock_guard<std::mutex> g(mu_);
-  pending_.push_back({a, b, cls, bytes, work});
-  if (pending_.size() > 4096) {
-    // keep the pool bounded: harvest what has completed
-    std::vector<Pending> keep;
-    for (auto& p : pending_) {
-      if (hipEventQuery(p.b) == hipSuccess) {
-        float ms = 0;
-        if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
-          auto& s = stats_[p.cls];
-          s.launches++;
-          s.ms += ms;
-          s.bytes += p.bytes;
-          s.work += p.work;
-        }
-        pool_.push_back(p.a);
-        pool_.push_back(p.b);
-      } else {
-        keep.push_back(p);
-      }
+  Pending oldest{};
+  bool wait_oldest = false;
+  {
+    std::lock_guard<std::mutex> g(mu_);
+    pending_.push_back({a, b, cls, bytes, work});
+    // harvest the oldest pairs that have completed (a few per launch, oldest first: O(1) per
+    // launch however deep the device queues of the streams are)
+    for (int n = 0; n < 8 && !pending_.empty(); ++n) {
+      const Pending& p = pending_.front();
+      if (hipEventQuery(p.b) != hipSuccess) break;
+      account(p);
+      pending_.pop_front();
     }
-    pending_.swap(keep);
+    (void)hipGetLastError();
+    // bound the events in flight: beyond kMaxOutstanding the calling thread waits for the oldest
+    // pair (outside the lock), so timing never holds an unbounded number of device signals
+    if (pending_.size() > kMaxOutstanding) {
+      oldest = pending_.front();
+      pending_.pop_front();
+      wait_oldest = true;
+    }
   }
+  if (wait_oldest) {
+    (void)hipEventSynchronize(oldest.b);
+    std::lock_guard<std::mutex> g(mu_);
+    account(oldest);
+  }
+}
+
+void Profiler::account(const Pending& p) {
+  float ms = 0;
+  if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+    auto& s = stats_[p.cls];
+    s.launches++;
+    s.ms += ms;
+    s.bytes += p.bytes;
+    s.work += p.work;
+  }
+  pool_.push_back(p.a);
+  pool_.push_back(p.b);
 }
 
 void Profiler::harvest(bool wait) {
   std::lock_guard<std::mutex> g(mu_);
-  std::vector<Pending> keep;
+  std::deque<Pending> keep;
   for (auto& p : pending_) {
     if (wait) (void)hipEventSynchronize(p.b);
-    if (hipEventQuery(p.b) == hipSuccess) {
-      float ms = 0;
-      if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
-        auto& s = stats_[p.cls];
-        s.launches++;
-        s.ms += ms;
-        s.bytes += p.bytes;
-        s.work += p.work;
-      }
-      pool_.push_back(p.a);
-      pool_.push_back(p.b);
-    } else {
-      keep.push_back(p);
-    }
+    if (hipEventQuery(p.b) == hipSuccess) account(p);
+    else keep.push_back(p);
   }
   pending_.swap(keep);
   (void)hipGetLastError();

@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <deque>
 #include <mutex>
 #include <vector>
 
@@ -46,10 +47,12 @@ class Profiler {
     double bytes, work;
   };
   hipEvent_t take();
+  void account(const Pending& p);  // with mu_ held
+  static constexpr size_t kMaxOutstanding = 1024;
   std::mutex mu_;
   bool on_ = false;
   std::vector<hipEvent_t> pool_;
-  std::vector<Pending> pending_;
+  std::deque<Pending> pending_;
   ClassStats stats_[KC_COUNT];
 };
 

@@ -99,8 +99,29 @@ size_t Server::estimate_bytes(int64_t nt, int64_t ne, int64_t nobj, int precisio
   return estimate_request_bytes(nt, nobj, precision, restart, 1);
 }
 
+// Every slot's stream and pinned staging are made here, on the caller's thread, so that a
+// failure reaches the caller (bem_submit) instead of leaving a slot silently dead.
 Server::Server(Ctx* ctx) : ctx_(ctx), comb_(ctx->device) {
+  slot_stream_.assign(kSlots, nullptr);
+  slot_pinned_.assign(kSlots, nullptr);
+  for (int s = 0; s < kSlots; ++s) {
+    hipError_t e = hipStreamCreateWithFlags(&slot_stream_[s], hipStreamNonBlocking);
+    if (e == hipSuccess)
+      e = hipHostMalloc(reinterpret_cast<void**>(&slot_pinned_[s]), kPinnedBytes, hipHostMallocDefault);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      release_slots();
+      throw Error(BEM_E_DEVICE, std::string("serving slot set-up failed: ") + hipGetErrorString(e));
+    }
+  }
   for (int s = 0; s < kSlots; ++s) threads_.emplace_back(&Server::worker, this, s);
+}
+
+void Server::release_slots() {
+  for (auto& p : slot_pinned_)
+    if (p) (void)hipHostFree(p), p = nullptr;
+  for (auto& st : slot_stream_)
+    if (st) (void)hipStreamDestroy(st), st = nullptr;
 }
 
 Server::~Server() {
@@ -110,6 +131,7 @@ Server::~Server() {
   }
   cv_.notify_all();
   for (auto& t : threads_) t.join();
+  release_slots();
 }
 
 bem_ticket Server::submit(const bem_request& r) {
@@ -166,12 +188,10 @@ void Server::drain() {
   done_cv_.wait(lk, [&] { return queue_.empty() && active_ == 0; });
 }
 
-void Server::worker(int) {
-  (void)hipSetDevice(ctx_->device);
-  hipStream_t st = nullptr;
-  double* pinned = nullptr;
-  if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return;
-  if (hipHostMalloc(reinterpret_cast<void**>(&pinned), kPinnedBytes, hipHostMallocDefault) != hipSuccess) return;
+void Server::worker(int slot) {
+  hipStream_t st = slot_stream_[slot];
+  double* pinned = slot_pinned_[slot];
+  const bool device_ok = hipSetDevice(ctx_->device) == hipSuccess;
   while (true) {
     std::shared_ptr<Request> q;
     {
@@ -199,6 +219,7 @@ void Server::worker(int) {
     std::string msg;
     bem_solve_info info{};
     try {
+      if (!device_ok) throw Error(BEM_E_DEVICE, "serving slot could not select the device");
       auto mo = std::make_unique<MeshObj>();
       mo->mesh = build_mesh(q->xyz.data(), int64_t(q->xyz.size() / 3), q->tri.data(), int64_t(q->tri.size() / 3),
                             q->obj.empty() ? nullptr : q->obj.data());
@@ -234,8 +255,6 @@ void Server::worker(int) {
     cv_.notify_all();
     done_cv_.notify_all();
   }
-  if (pinned) (void)hipHostFree(pinned);
-  if (st) (void)hipStreamDestroy(st);
   if (tl_ready) (void)hipEventDestroy(tl_ready);
   if (tl_done) (void)hipEventDestroy(tl_done);
   tl_ready = tl_done = nullptr;

@@ -68,7 +68,10 @@ class Server {
 
  private:
   void worker(int slot);
+  void release_slots();
   Ctx* ctx_;
+  std::vector<hipStream_t> slot_stream_;
+  std::vector<double*> slot_pinned_;
   Combiner comb_;
   std::mutex mu_;
   std::condition_variable cv_, done_cv_;
