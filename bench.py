@@ -290,17 +290,18 @@ def _serve_once(B, stream, prec, args):
     return recs, wall, comb
 
 
-def _profiled_pass(B, timed, args):
-    """The timed requests once more, one after another (mesh load, mixed-precision assembly,
-    solve), with HIP events recorded around every launch on its stream: per-class device time,
-    algorithmic bytes and work of each kernel class without the overlap of concurrent requests."""
+def _profiled_pass(B, timed, args, prec):
+    """The timed requests once more, one after another (mesh load, assembly in the headline
+    precision, solve), with HIP events recorded around every launch on its stream: per-class
+    device time, algorithmic bytes and work of each kernel class without the overlap of
+    concurrent requests."""
     ctx = B.bem_create(0)
     opts = B.solve_opts(tol=args.tol, restart=args.restart, maxit=args.maxit, max_refine=8)
     B.bem_profile_enable(True)
     for w in timed:
         mesh = B.bem_mesh_load(ctx, w.xyz, w.tri, w.obj)
         info = B.bem_mesh_info(ctx, mesh)
-        op = B.bem_assemble(ctx, mesh, B.make_problem(w.freq_hz, w.eps_r, w.mu_r, w.sigma, precision=B.BEM_MIXED))
+        op = B.bem_assemble(ctx, mesh, B.make_problem(w.freq_hz, w.eps_r, w.mu_r, w.sigma, precision=prec))
         rc, _, _, _, si = B.bem_solve(ctx, op, B.plane_waves(w.khat, w.pol), opts, info["n_edge"], info["n_tri"])
         B.bem_release(ctx, op)
         B.bem_release(ctx, mesh)
@@ -351,13 +352,13 @@ def run_serve(args) -> int:
     import meshgen
     import paper_2106_06184_amd as B
 
-    if args.restart <= 0:
-        args.restart = 200
+    # restart <= 0: the library's automatic cycle length (100-1000 steps, Krylov basis <= 8 GB)
     stream = meshgen.mixed_stream(args.warmup + args.steps, rate_hz=args.serve_rate, seed=args.serve_seed)
     timed = [w for _, w in stream[args.warmup:]]
     runs = {}
-    for prec_name in ("mixed", "fp64"):
-        prec = B.BEM_MIXED if prec_name == "mixed" else B.BEM_FP64
+    precs = {"fp32": B.BEM_FP32, "mixed": B.BEM_MIXED, "fp64": B.BEM_FP64}
+    for prec_name in [p for p in args.serve_precisions.split(",") if p]:
+        prec = precs[prec_name]
         log(f"serving {len(timed)} requests ({prec_name}) after {args.warmup} warm-up requests ...")
         recs, wall, comb = _serve_once(B, stream, prec, args)
         ok = [r for r in recs if r["status"] == B.BEM_OK]
@@ -369,9 +370,10 @@ def run_serve(args) -> int:
                            "failed": [(r["name"], r["status"]) for r in recs if r["status"] != B.BEM_OK]}
         log(f"  {prec_name}: {runs[prec_name]['value']:.3f} requests/s, p50 {runs[prec_name]['p50_s']:.2f} s, "
             f"p99 {runs[prec_name]['p99_s']:.2f} s, {len(ok)}/{len(recs)} converged")
-    m, d = runs["mixed"], runs["fp64"]
+    head = args.serve_precisions.split(",")[0]
+    m, d = runs[head], runs.get("fp64", runs[head])
     log("profiled pass over the timed requests (one at a time) ...")
-    prof = _profiled_pass(B, timed, args)
+    prof = _profiled_pass(B, timed, args, precs[head])
     names = dict(enumerate(B.KC_NAMES))
     for k, p in prof.items():
         log(f"  {names[k]:16s} launches {p['launches']:7d}  {p['ms']:10.2f} ms  "
@@ -384,26 +386,29 @@ def run_serve(args) -> int:
         "metric": "solves/s + p50/p99 latency at 1e-6 relative residual (serving mix)",
         "value": m["value"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": 1e3 * m["wall_s"] / args.steps, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "vs_baseline": None, "dtype": {"fp32": "f32 storage+products, f64 refinement", "mixed": "f32+f64",
+                                       "fp64": "f64"}[head], "data": "synthetic",
         "config": {"workload": "serving mix: Poisson arrivals of spheres, 1.0/0.6/0.4 ellipsoids and cubes "
                                "(cube-topology meshes of 12 n^2 triangles, T log-uniform in [320, 20000]), "
                                "eps_r ~ U[1.5, 10], k0 a ~ U[0.5, 10] redrawn below 10 mean edges per interior "
                                "wavelength, 1-64 random plane waves each; one step = one request",
                    "rate_per_s": args.serve_rate, "seed": args.serve_seed, "tol": args.tol,
-                   "restart": args.restart, "precision": "mixed", "admission": "HBM budget, 4 slots",
+                   "restart": args.restart, "precision": head, "admission": "HBM budget, 4 slots",
                    "triangles": [len(w.tri) for w in timed], "plane_waves": [len(w.khat) for w in timed]},
         "p50_s": m["p50_s"], "p99_s": m["p99_s"],
         "excitation_solves_per_s": m["excitation_solves_per_s"],
         "converged": m["converged"],
-        "fp64": {k: d[k] for k in ("value", "p50_s", "p99_s", "excitation_solves_per_s", "converged", "wall_s")},
-        "mixed_over_fp64": m["value"] / d["value"] if d["value"] > 0 else None,
+        "by_precision": {k: {f: v[f] for f in ("value", "p50_s", "p99_s", "excitation_solves_per_s", "converged",
+                                               "wall_s")} for k, v in runs.items()},
+        f"{head}_over_fp64": m["value"] / d["value"] if d["value"] > 0 else None,
         "fill_GBps": sum(_dense_bytes(len(w.tri)) for w in timed) / (fill_ms * 1e-3) / 1e9 if fill_ms > 0 else None,
         "matvec_frac_hbm": (gemv_b / (gemv_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS) if gemv_ms > 0 else None,
         "combined_launches": m["combined_launches"], "combined_products": m["combined_products"],
         "roofline": _roofline(B, prof),
     }
-    if m["failed"] or d["failed"]:
-        out["failed"] = {"mixed": m["failed"], "fp64": d["failed"]}
+    failed = {k: v["failed"] for k, v in runs.items() if v["failed"]}
+    if failed:
+        out["failed"] = failed
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on whole requests of the stream ...")
         out["cpu_baseline"] = serve_cpu_baseline(timed)
@@ -433,11 +438,13 @@ def main() -> int:
                     help="fill and invert every object separately even when objects are translated copies")
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--restart", type=int, default=0,
-                    help="GMRES restart length (default 300; 200 when serving)")
+                    help="GMRES restart length (default 300; automatic when serving)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-rate", type=float, default=2.0,
                     help="mean Poisson arrival rate of the serving mix, requests/s")
     ap.add_argument("--serve-seed", type=int, default=5)
+    ap.add_argument("--serve-precisions", default="fp32,mixed,fp64",
+                    help="precisions the serving mix is run in, the first one being the headline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the plain copy used to calibrate the HBM byte counters")
     args = ap.parse_args()

@@ -54,7 +54,17 @@ enum {
   BEM_E_NUMERIC = -6        /* NaN/Inf in an input or in a residual */
 };
 
-enum { BEM_FP64 = 0, BEM_MIXED = 2 };
+/* Precision of an operator (bem_problem.precision).
+ * BEM_FP64: float64 blocks and products.
+ * BEM_FP32: the fill runs in float64 and is rounded once to float32; only the float32 blocks
+ *   (and float32 copies of the nested-solve and preconditioner inverses) are kept, a third of the
+ *   float64-plus-float32 memory; every product reads float32 storage, and bem_solve refines in
+ *   float64 vectors: its GMRES sweeps and residuals r = b - A x use the float32 operator, so the
+ *   solution converges to that of the float32-rounded operator (its difference from the float64
+ *   one is the rounding times the condition number).  bem_apply takes and returns float32 vectors.
+ * BEM_MIXED: float64 blocks plus float32 copies; float32 products in the late steps of each
+ *   refinement sweep, float64 residuals (see bem_problem.precision). */
+enum { BEM_FP64 = 0, BEM_FP32 = 1, BEM_MIXED = 2 };
 
 /* Dense operator blocks addressable through bem_apply / bem_block_export. */
 enum {
@@ -141,7 +151,8 @@ typedef struct {
   double mu_bg;
   const bem_material* obj;      /* n_obj materials, host */
   int64_t n_obj;
-  int precision;                /* BEM_FP64, or BEM_MIXED: float32 copies of the dense blocks;
+  int precision;                /* BEM_FP64, BEM_FP32 (float32 blocks only, see above), or
+                                   BEM_MIXED: float32 copies of the dense blocks;
                                    each refinement sweep runs float64 products until GMRES's
                                    residual estimate is sqrt(tol), float32 products after (first
                                    restart cycle only), float64 residual refinement; float64
@@ -171,7 +182,8 @@ typedef struct {
 int bem_assemble(bem_ctx* ctx, bem_mesh_h mesh, const bem_problem* prob, bem_op_h* out);
 
 /* y = A x for `block` (see above), nrhs columns.  x, y: device pointers, column-
- * major, leading dimension = the block's row/column count, complex float64;
+ * major, leading dimension = the block's row/column count, complex float64 (two
+ * floats per entry when the operator was assembled with BEM_FP32);
  * stream: a hipStream_t or NULL for the context's stream (the call is
  * asynchronous on it, except BEM_BLOCK_FINAL, whose inner solve synchronises).
  * BEM_BLOCK_FINAL applies eq. finalsystem with the equivalent-configuration
@@ -202,7 +214,8 @@ int bem_dense_invert_noalloc(bem_ctx* ctx, void* A, int64_t n, int64_t ld, void*
 
 /* Copy a dense block (blocks 1..7) into a host buffer, row-major complex
  * float64, rows x cols as documented above (block-diagonal blocks include
- * their zero off-diagonal parts). */
+ * their zero off-diagonal parts); a BEM_FP32 operator's float32 entries are
+ * widened. */
 int bem_block_export(bem_ctx* ctx, bem_op_h op, int block, bem_c64* host_dst);
 int bem_set_inner_tol(bem_ctx* ctx, bem_op_h op, double tol);
 
@@ -232,7 +245,9 @@ typedef struct {
 
 typedef struct {
   double tol;                   /* relative residual ||b - A x|| / ||b|| in float64 */
-  int restart;                  /* GMRES restart length */
+  int restart;                  /* GMRES restart length; <= 0: automatic, the longest cycle (100 to
+                                   1000 steps) whose Krylov basis for the batch of excitations
+                                   stays under 8 GB */
   int maxit;                    /* total outer iteration limit */
   double inner_tol;             /* relative tolerance of the equivalent-configuration solve;
                                    <= 0 selects 0.1 * tol */

@@ -19,7 +19,7 @@ _LIB_PATH = Path(os.environ["BEM_LIB"]) if os.environ.get("BEM_LIB") else Path(_
 
 BEM_OK, BEM_PENDING = 0, 1
 BEM_E_INVALID, BEM_E_MESH, BEM_E_NOMEM, BEM_E_NOT_CONVERGED, BEM_E_DEVICE, BEM_E_NUMERIC = -1, -2, -3, -4, -5, -6
-BEM_FP64, BEM_MIXED = 0, 2
+BEM_FP64, BEM_FP32, BEM_MIXED = 0, 1, 2
 (BEM_BLOCK_FINAL, BEM_BLOCK_LA_INT, BEM_BLOCK_LPHI_INT, BEM_BLOCK_K_INT, BEM_BLOCK_LA_BG,
  BEM_BLOCK_LPHI_BG, BEM_BLOCK_K_BG, BEM_BLOCK_IX, BEM_BLOCK_MEQ, BEM_BLOCK_MEQ_INV, BEM_BLOCK_K_M) = range(11)
 BEM_EXC_PLANE_WAVE, BEM_EXC_DELTA_GAP = 0, 1

@@ -6,6 +6,7 @@
 
 #include "ctx.h"
 #include "dense.h"
+#include "linalg.h"
 #include "prof.h"
 #include "serve.h"
 
@@ -209,6 +210,25 @@ int bem_apply(bem_ctx* c, bem_op_h h, int block, const void* x, void* y, int64_t
       case BEM_BLOCK_K_M:
       case BEM_BLOCK_IX: rows = cols = op.ne; break;
       default: return fail(BEM_E_INVALID, "unknown block");
+    }
+    if (op.precision == BEM_FP32) {
+      // float32 vectors: widened into float64 work columns, products on the float32 blocks,
+      // results rounded back (chunks of up to 256 columns)
+      const float2* xp = static_cast<const float2*>(x);
+      float2* yp = static_cast<float2*>(y);
+      bem::DevArena tmp(ctx);
+      tmp.set_stream(st);
+      const int64_t cb = std::min<int64_t>(256, nrhs);
+      double2* xw = tmp.alloc<double2>(size_t(cols) * cb);
+      double2* yw = tmp.alloc<double2>(size_t(rows) * cb);
+      for (int64_t r0 = 0; r0 < nrhs; r0 += 256) {
+        const int64_t nr = std::min<int64_t>(256, nrhs - r0);
+        bem::launch_cast_f64(xp + r0 * cols, nr, cols, cols, xw, cols, st);
+        bem::apply_block(op, block, xw, yw, nr, st);
+        bem::launch_cast_f32(yw, nr, rows, rows, yp + r0 * rows, rows, st);
+      }
+      BEM_HIP(hipStreamSynchronize(st));
+      return BEM_OK;
     }
     const double2* xp = static_cast<const double2*>(x);
     double2* yp = static_cast<double2*>(y);

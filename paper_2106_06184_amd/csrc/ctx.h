@@ -65,6 +65,11 @@ class DevArena {
   void set_stream(hipStream_t st) { stream_ = st; }
   hipStream_t stream() const { return stream_; }
   void release(void* p);
+  bool owns(const void* p) const {
+    for (const auto& b : blocks_)
+      if (b.first == p) return true;
+    return false;
+  }
   size_t bytes() const { return total_; }
 
  private:
@@ -199,6 +204,9 @@ void far_field(OpObj& op, const bem_c64* H, const bem_c64* E, int64_t nexc, cons
 // Upper bound of the device bytes of one request (assembly peak or solve peak), for admission.
 size_t estimate_request_bytes(int64_t nt, int64_t nobj, int precision, int restart, int64_t nexc,
                               int formulation = BEM_FORM_SLDM);
+// GMRES restart chosen when bem_solve_opts.restart <= 0 (N final unknowns, nexc excitations).
+constexpr double kAutoKrylovBytes = 8.0e9;
+int auto_restart(int64_t N, int64_t nexc);
 int solve_op(OpObj& op, const bem_excitation* exc, int64_t nexc, const bem_solve_opts& opts, bem_c64* H, bem_c64* E,
              bem_c64* rho, bem_solve_info* info, hipStream_t st);
 

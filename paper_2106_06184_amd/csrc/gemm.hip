@@ -9,10 +9,17 @@
 // 2r+1 = x_im' of excitation r gives Re and Im of Y in adjacent columns.  8 real flops per
 // complex multiply-add, as the 4M method.
 //
-// Kernel: 128 x 128 output tile per 256-thread workgroup (2 x 2 waves of 64 x 64), K step 16,
-// double-buffered LDS (A stored k-major so that MFMA operand reads are conflict-free), float32
-// MFMA 32x32x2 with float32 accumulation.  Workgroup ids are remapped so that the column tiles
-// of one row tile run on the same XCD and share its L2 copy of the A rows.
+// Kernels: 256-thread workgroups of four waves; float32 MFMA 32x32x2 (wave tile 64 x 32 JN) or
+// float64 MFMA 4x4x4 four-block (wave tile 32 x 16 JN), K step 16, double-buffered LDS (A stored
+// k-major so that MFMA operand reads are conflict-free).  The N tile (real columns) is the
+// smallest of 32, 64 and 128 that holds the 2R columns, so a few excitations do not pay for a
+// wide tile of zero columns, and the waves not needed along N go along M.  Where the row and
+// column tiles give fewer than ~2048 workgroups (tall matrices with few columns), K is split S
+// ways: split s of every tile writes its partial product to a workspace and a second kernel sums
+// the S partials in a fixed order (deterministic), applies alpha and accumulates into Y.  With
+// S > 1, split s runs on XCD s mod 8 (workgroups are dealt round-robin), so the slice of the
+// embedded right-hand sides it reads stays in that XCD's L2; with S = 1 the column tiles of one
+// row tile are given to the same XCD and share its L2 copy of the A rows.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -26,7 +33,7 @@ namespace dev {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
-constexpr int BM = 128, BN = 128, BK = 16, PADA = 4, PADB = 4;
+constexpr int BK = 16, PADA = 4, PADB = 4;
 
 __global__ void k_build_B(const double2* __restrict__ X, int64_t ldx, int64_t nc, int64_t R, float* __restrict__ Bm,
                           int64_t ldb, int64_t K16) {
@@ -45,122 +52,178 @@ __global__ void k_build_B(const double2* __restrict__ X, int64_t ldx, int64_t nc
   }
 }
 
-template <bool ALIGNED>
-__global__ void __launch_bounds__(256) k_gemm_f32(const float* __restrict__ A, int64_t lda, const float* __restrict__ Bm,
-                                                  int64_t ldb, int64_t M, int64_t K, int64_t K16, int64_t ntn,
-                                                  double2* __restrict__ Y, int64_t ldy, int64_t R, double2 alpha,
-                                                  int accumulate) {
-  __shared__ float As[2][BK][BM + PADA];
-  __shared__ float Bs[2][BK][BN + PADB];
-  // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs; consecutive
-  // logical tiles (the column tiles of one row tile) are given to the same XCD.
-  const int64_t nwg = int64_t(gridDim.x);
-  const int64_t p = blockIdx.x;
+// Tile decode shared by both kernels: blockIdx.x -> (row tile, column tile, K split).
+struct TileIdx {
+  int64_t tm, tn, ks;
+};
+__device__ __forceinline__ TileIdx tile_of(int64_t ntn, int64_t S) {
+  const int64_t nwg = int64_t(gridDim.x), p = blockIdx.x;
+  TileIdx t;
+  if (S > 1) {
+    t.ks = p % S;
+    const int64_t tile = p / S;
+    t.tm = tile / ntn;
+    t.tn = tile % ntn;
+    return t;
+  }
   int64_t logical = p;
   if (nwg % 8 == 0) logical = (p % 8) * (nwg / 8) + p / 8;
-  const int64_t tm = logical / ntn, tn = logical % ntn;
-  const int64_t m0 = tm * BM, n0 = tn * BN;
+  t.tm = logical / ntn;
+  t.tn = logical % ntn;
+  t.ks = 0;
+  return t;
+}
+
+// One output element of the real embedding: with S = 1 the even lane of a (Re, Im) column pair
+// writes alpha (re + j im) (+ Y) to Y; with S > 1 every lane writes its real partial.
+__device__ __forceinline__ void emit(double mine, double other, int lane, int64_t row, int64_t col, int64_t M,
+                                     int64_t R, int64_t ldb, int64_t S, int64_t ks, double* __restrict__ P,
+                                     double2* __restrict__ Y, int64_t ldy, double2 alpha, int accumulate) {
+  if (row >= M) return;
+  if (S > 1) {
+    if (col < ldb) P[(size_t(ks) * M + row) * ldb + col] = mine;
+    return;
+  }
+  if ((lane & 1) == 0 && (col >> 1) < R) {
+    double yr = alpha.x * mine - alpha.y * other, yi = alpha.x * other + alpha.y * mine;
+    double2* y = Y + (col >> 1) * ldy + row;
+    if (accumulate) {
+      yr += y->x;
+      yi += y->y;
+    }
+    *y = make_double2(yr, yi);
+  }
+}
+
+// Y[r][row] = alpha sum_s (P[s][row][2r] + j P[s][row][2r+1]) (+ Y), s in order.
+__global__ void k_splitk_reduce(const double* __restrict__ P, int64_t M, int64_t ldb, int64_t S, int64_t R,
+                                double2* __restrict__ Y, int64_t ldy, double2 alpha, int accumulate) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= M * R) return;
+  const int64_t row = e / R, r = e % R;
+  double re = 0.0, im = 0.0;
+  for (int64_t s = 0; s < S; ++s) {
+    const double* p = P + (size_t(s) * M + row) * ldb + 2 * r;
+    re += p[0];
+    im += p[1];
+  }
+  double yr = alpha.x * re - alpha.y * im, yi = alpha.x * im + alpha.y * re;
+  double2* y = Y + r * ldy + row;
+  if (accumulate) {
+    yr += y->x;
+    yi += y->y;
+  }
+  *y = make_double2(yr, yi);
+}
+
+// float32 storage: WN waves along N, JN 32-column MFMA blocks per wave, 2 x 32 rows per wave;
+// tile (4 / WN) 64 x WN JN 32.  Split s covers K [s kc, (s + 1) kc).
+template <bool ALIGNED, int WN, int JN>
+__global__ void __launch_bounds__(256) k_gemm_f32(const float* __restrict__ A, int64_t lda, const float* __restrict__ Bm,
+                                                  int64_t ldb, int64_t M, int64_t K, int64_t K16, int64_t kc,
+                                                  int64_t ntn, int64_t S, double* __restrict__ P,
+                                                  double2* __restrict__ Y, int64_t ldy, int64_t R, double2 alpha,
+                                                  int accumulate) {
+  constexpr int WM = 4 / WN, TM = WM * 64, TN = WN * JN * 32;
+  constexpr int EA = TM * BK / 256, EB = TN * BK / 256;  // A and B values per thread per K step
+  __shared__ float As[2][BK][TM + PADA];
+  __shared__ float Bs[2][BK][TN + PADB];
+  const TileIdx ti = tile_of(ntn, S);
+  const int64_t m0 = ti.tm * TM, n0 = ti.tn * TN;
+  const int64_t kbeg = ti.ks * kc, kend = min(K16, kbeg + kc);
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / WN, wn = wave % WN;
 
-  // global-load coordinates
-  const int a_row = tid >> 1, a_k = (tid & 1) * 8;     // A: 128 rows x 16 k
-  const int b_k = tid >> 4, b_col = (tid & 15) * 8;    // B: 16 k x 128 cols
+  const int a_row = tid / (BK / EA), a_k = (tid % (BK / EA)) * EA;
+  const int b_k = tid >> 4, b_col = (tid & 15) * EB;
   const int64_t gm = m0 + a_row;
 
-  floatx16 acc[2][2];
+  floatx16 acc[2][JN];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < JN; ++j)
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
 
-  float ra[8], rb[8];
+  float ra[EA], rb[EB];
   auto load_tile = [&](int64_t k0) {
     const int64_t kk = k0 + a_k;
     if (gm < M) {
       const float* src = A + gm * lda + kk;
-      if (ALIGNED && kk + 8 <= K) {
-        const float4 u = *reinterpret_cast<const float4*>(src);
-        const float4 w = *reinterpret_cast<const float4*>(src + 4);
-        ra[0] = u.x; ra[1] = u.y; ra[2] = u.z; ra[3] = u.w;
-        ra[4] = w.x; ra[5] = w.y; ra[6] = w.z; ra[7] = w.w;
+      if (ALIGNED && kk + EA <= K) {
+#pragma unroll
+        for (int e = 0; e < EA; e += 4) {
+          const float4 u = *reinterpret_cast<const float4*>(src + e);
+          ra[e] = u.x; ra[e + 1] = u.y; ra[e + 2] = u.z; ra[e + 3] = u.w;
+        }
       } else {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) ra[e] = (kk + e < K) ? src[e] : 0.f;
+        for (int e = 0; e < EA; ++e) ra[e] = (kk + e < K) ? src[e] : 0.f;
       }
     } else {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) ra[e] = 0.f;
+      for (int e = 0; e < EA; ++e) ra[e] = 0.f;
     }
     const float* bsrc = Bm + (k0 + b_k) * ldb + n0 + b_col;
-    const float4 u = *reinterpret_cast<const float4*>(bsrc);
-    const float4 w = *reinterpret_cast<const float4*>(bsrc + 4);
-    rb[0] = u.x; rb[1] = u.y; rb[2] = u.z; rb[3] = u.w;
-    rb[4] = w.x; rb[5] = w.y; rb[6] = w.z; rb[7] = w.w;
+#pragma unroll
+    for (int e = 0; e < EB; e += 2) {
+      const float2 u = *reinterpret_cast<const float2*>(bsrc + e);
+      rb[e] = u.x;
+      rb[e + 1] = u.y;
+    }
   };
   auto store_tile = [&](int buf) {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) As[buf][a_k + e][a_row] = ra[e];
+    for (int e = 0; e < EA; ++e) As[buf][a_k + e][a_row] = ra[e];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) Bs[buf][b_k][b_col + e] = rb[e];
+    for (int e = 0; e < EB; ++e) Bs[buf][b_k][b_col + e] = rb[e];
   };
 
-  const int64_t nk = K16 / BK;
-  load_tile(0);
-  store_tile(0);
+  const int64_t nk = (kend - kbeg) / BK;
+  if (nk > 0) {
+    load_tile(kbeg);
+    store_tile(0);
+  }
   __syncthreads();
   for (int64_t kt = 0; kt < nk; ++kt) {
     const int buf = int(kt & 1);
-    if (kt + 1 < nk) load_tile((kt + 1) * BK);
+    if (kt + 1 < nk) load_tile(kbeg + (kt + 1) * BK);
 #pragma unroll
     for (int s = 0; s < BK / 2; ++s) {
       const int kr = 2 * s + (lane >> 5);
-      float af[2], bf[2];
+      float af[2], bf[JN];
 #pragma unroll
       for (int i = 0; i < 2; ++i) af[i] = As[buf][kr][wm * 64 + i * 32 + (lane & 31)];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) bf[j] = Bs[buf][kr][wn * 64 + j * 32 + (lane & 31)];
+      for (int j = 0; j < JN; ++j) bf[j] = Bs[buf][kr][wn * JN * 32 + j * 32 + (lane & 31)];
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[i], bf[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < JN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[i], bf[j], acc[i][j], 0, 0, 0);
     }
-    if (kt + 1 < nk) {
-      store_tile(buf ^ 1);
-    }
+    if (kt + 1 < nk) store_tile(buf ^ 1);
     __syncthreads();
   }
 
-  // epilogue: output column c = 2r (Re) or 2r+1 (Im); even lanes own the pair of an excitation
+  // item v of lane l: row (v / 4) 8 + (l / 32) 4 + v % 4, column l % 32 of the 32 x 32 block
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < JN; ++j)
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
-        const float mine = acc[i][j][v];
-        const float other = __shfl_xor(mine, 1, 64);
+        const double mine = acc[i][j][v];
+        const double other = __shfl_xor(mine, 1, 64);
         const int64_t row = m0 + wm * 64 + i * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
-        const int64_t col = n0 + wn * 64 + j * 32 + (lane & 31);
-        if ((lane & 1) == 0 && row < M && (col >> 1) < R) {
-          const double re = mine, im = other;
-          double yr = alpha.x * re - alpha.y * im, yi = alpha.x * im + alpha.y * re;
-          double2* y = Y + (col >> 1) * ldy + row;
-          if (accumulate) {
-            yr += y->x;
-            yi += y->y;
-          }
-          *y = make_double2(yr, yi);
-        }
+        const int64_t col = n0 + wn * JN * 32 + j * 32 + (lane & 31);
+        emit(mine, other, lane, row, col, M, R, ldb, S, ti.ks, P, Y, ldy, alpha, accumulate);
       }
 }
 
-// ---- float64: the same real embedding on the float64 4x4x4 four-block matrix instruction.  Tile
-// 64 x 128 per 256-thread workgroup (2 x 2 waves of 32 x 64 reals), K step 16.
-constexpr int DM = 64, DN = 128, DK = 16, DPAD = 2;
+// ---- float64: the same real embedding on the float64 4x4x4 four-block matrix instruction.
+constexpr int DK = 16, DPAD = 2;
 
 __global__ void k_build_B64(const double2* __restrict__ X, int64_t ldx, int64_t nc, int64_t R,
                             double* __restrict__ Bm, int64_t ldb, int64_t K16) {
@@ -180,56 +243,68 @@ __global__ void k_build_B64(const double2* __restrict__ X, int64_t ldx, int64_t 
 }
 
 // Lane l of an instruction supplies A_q[l % 4][l / 16] and B_q[l / 16][l % 4] of block
-// q = (l % 16) / 4; all four blocks share the rows, so per 4 k a wave issues 8 x 4 instructions
-// for its 32 x 64 tile, and the result of instruction (i, j) on lane l is row 4 i + l / 16,
-// column 16 j + l % 16 (even columns real, odd imaginary parts).
-template <bool ALIGNED>
-__global__ void __launch_bounds__(256) k_gemm_f64(const double* __restrict__ A, int64_t lda,
+// q = (l % 16) / 4; all four blocks share the rows, so per 4 k a wave issues 8 x JN instructions
+// for its 32 x 16 JN tile, and the result of instruction (i, j) on lane l is row 4 i + l / 16,
+// column 16 j + l % 16 (even columns real, odd imaginary parts).  WN waves along N: tile
+// (4 / WN) 32 x WN JN 16.
+// TA = float: float32 entries widened as they are staged (float64 arithmetic on a float32-only
+// operator, for the refinement's residuals).
+template <typename TA, bool ALIGNED, int WN, int JN>
+__global__ void __launch_bounds__(256) k_gemm_f64(const TA* __restrict__ A, int64_t lda,
                                                   const double* __restrict__ Bm, int64_t ldb, int64_t M, int64_t K,
-                                                  int64_t K16, int64_t ntn, double2* __restrict__ Y, int64_t ldy,
+                                                  int64_t K16, int64_t kc, int64_t ntn, int64_t S,
+                                                  double* __restrict__ P, double2* __restrict__ Y, int64_t ldy,
                                                   int64_t R, double2 alpha, int accumulate) {
-  __shared__ double As[2][DK][DM + DPAD];
-  __shared__ double Bs[2][DK][DN + DPAD];
-  const int64_t nwg = int64_t(gridDim.x);
-  const int64_t p = blockIdx.x;
-  int64_t logical = p;
-  if (nwg % 8 == 0) logical = (p % 8) * (nwg / 8) + p / 8;
-  const int64_t tm = logical / ntn, tn = logical % ntn;
-  const int64_t m0 = tm * DM, n0 = tn * DN;
+  constexpr int WM = 4 / WN, TM = WM * 32, TN = WN * JN * 16;
+  constexpr int EA = TM * DK / 256, EB = TN * DK / 256;
+  __shared__ double As[2][DK][TM + DPAD];
+  __shared__ double Bs[2][DK][TN + DPAD];
+  const TileIdx ti = tile_of(ntn, S);
+  const int64_t m0 = ti.tm * TM, n0 = ti.tn * TN;
+  const int64_t kbeg = ti.ks * kc, kend = min(K16, kbeg + kc);
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / WN, wn = wave % WN;
 
-  const int a_row = tid >> 2, a_k = (tid & 3) * 4;   // A: 64 rows x 16 k, 4 per thread
-  const int b_k = tid >> 4, b_col = (tid & 15) * 8;  // B: 16 k x 128 columns, 8 per thread
+  const int a_row = tid / (DK / EA), a_k = (tid % (DK / EA)) * EA;
+  const int b_k = tid >> 4, b_col = (tid & 15) * EB;
   const int64_t gm = m0 + a_row;
 
-  double acc4[8][4];
+  double acc4[8][JN];
 #pragma unroll
   for (int i = 0; i < 8; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc4[i][j] = 0.0;
+    for (int j = 0; j < JN; ++j) acc4[i][j] = 0.0;
 
-  double ra[4], rb[8];
+  double ra[EA], rb[EB];
   auto load_tile = [&](int64_t k0) {
     const int64_t kk = k0 + a_k;
     if (gm < M) {
-      const double* src = A + gm * lda + kk;
-      if (ALIGNED && kk + 4 <= K) {
-        const double2 u = *reinterpret_cast<const double2*>(src);
-        const double2 w = *reinterpret_cast<const double2*>(src + 2);
-        ra[0] = u.x; ra[1] = u.y; ra[2] = w.x; ra[3] = w.y;
+      const TA* src = A + gm * lda + kk;
+      if (ALIGNED && kk + EA <= K) {
+#pragma unroll
+        for (int e = 0; e < EA; e += 2) {
+          if constexpr (sizeof(TA) == 8) {
+            const double2 u = *reinterpret_cast<const double2*>(src + e);
+            ra[e] = u.x;
+            ra[e + 1] = u.y;
+          } else {
+            const float2 u = *reinterpret_cast<const float2*>(src + e);
+            ra[e] = double(u.x);
+            ra[e + 1] = double(u.y);
+          }
+        }
       } else {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) ra[e] = (kk + e < K) ? src[e] : 0.0;
+        for (int e = 0; e < EA; ++e) ra[e] = (kk + e < K) ? double(src[e]) : 0.0;
       }
     } else {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) ra[e] = 0.0;
+      for (int e = 0; e < EA; ++e) ra[e] = 0.0;
     }
     const double* bsrc = Bm + (k0 + b_k) * ldb + n0 + b_col;
 #pragma unroll
-    for (int e = 0; e < 8; e += 2) {
+    for (int e = 0; e < EB; e += 2) {
       const double2 u = *reinterpret_cast<const double2*>(bsrc + e);
       rb[e] = u.x;
       rb[e + 1] = u.y;
@@ -237,30 +312,32 @@ __global__ void __launch_bounds__(256) k_gemm_f64(const double* __restrict__ A, 
   };
   auto store_tile = [&](int buf) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) As[buf][a_k + e][a_row] = ra[e];
+    for (int e = 0; e < EA; ++e) As[buf][a_k + e][a_row] = ra[e];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) Bs[buf][b_k][b_col + e] = rb[e];
+    for (int e = 0; e < EB; ++e) Bs[buf][b_k][b_col + e] = rb[e];
   };
 
-  const int64_t nk = K16 / DK;
-  load_tile(0);
-  store_tile(0);
+  const int64_t nk = (kend - kbeg) / DK;
+  if (nk > 0) {
+    load_tile(kbeg);
+    store_tile(0);
+  }
   __syncthreads();
   for (int64_t kt = 0; kt < nk; ++kt) {
     const int buf = int(kt & 1);
-    if (kt + 1 < nk) load_tile((kt + 1) * DK);
+    if (kt + 1 < nk) load_tile(kbeg + (kt + 1) * DK);
 #pragma unroll
     for (int s = 0; s < DK / 4; ++s) {
       const int kr = 4 * s + (lane >> 4);
-      double av[8], bv[4];
+      double av[8], bv[JN];
 #pragma unroll
       for (int i = 0; i < 8; ++i) av[i] = As[buf][kr][wm * 32 + 4 * i + (lane & 3)];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) bv[j] = Bs[buf][kr][wn * 64 + j * 16 + (lane & 15)];
+      for (int j = 0; j < JN; ++j) bv[j] = Bs[buf][kr][wn * JN * 16 + j * 16 + (lane & 15)];
 #pragma unroll
       for (int i = 0; i < 8; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc4[i][j] = __builtin_amdgcn_mfma_f64_4x4x4f64(av[i], bv[j], acc4[i][j], 0, 0, 0);
+        for (int j = 0; j < JN; ++j) acc4[i][j] = __builtin_amdgcn_mfma_f64_4x4x4f64(av[i], bv[j], acc4[i][j], 0, 0, 0);
     }
     if (kt + 1 < nk) store_tile(buf ^ 1);
     __syncthreads();
@@ -269,74 +346,112 @@ __global__ void __launch_bounds__(256) k_gemm_f64(const double* __restrict__ A, 
 #pragma unroll
   for (int i = 0; i < 8; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < JN; ++j) {
       const double mine = acc4[i][j];
       const double other = __shfl_xor(mine, 1, 64);
       const int64_t row = m0 + wm * 32 + 4 * i + (lane >> 4);
-      const int64_t col = n0 + wn * 64 + j * 16 + (lane & 15);
-      if ((lane & 1) == 0 && row < M && (col >> 1) < R) {
-        double yr = alpha.x * mine - alpha.y * other, yi = alpha.x * other + alpha.y * mine;
-        double2* y = Y + (col >> 1) * ldy + row;
-        if (accumulate) {
-          yr += y->x;
-          yi += y->y;
-        }
-        *y = make_double2(yr, yi);
-      }
+      const int64_t col = n0 + wn * JN * 16 + j * 16 + (lane & 15);
+      emit(mine, other, lane, row, col, M, R, ldb, S, ti.ks, P, Y, ldy, alpha, accumulate);
     }
 }
 
 }  // namespace dev
 
-size_t gemm_workspace_bytes(int64_t cols, int64_t nrhs) {
-  // float64 embedding (the larger of the two): K16 x ldb doubles
-  const int64_t K16 = (2 * cols + dev::BK - 1) / dev::BK * dev::BK;
-  const int64_t ldb = (2 * nrhs + dev::BN - 1) / dev::BN * dev::BN;
-  return size_t(K16) * ldb * sizeof(double);
+namespace {
+// Work decomposition of one product: the N tile (real columns) for 2R columns, the split of K.
+constexpr int64_t kTargetWorkgroups = 2048;
+constexpr int64_t kMaxSplit = 16;
+int ntile_for(int64_t nrhs) { return 2 * nrhs <= 32 ? 32 : (2 * nrhs <= 64 ? 64 : 128); }
+int64_t split_for(int64_t tiles, int64_t K16) {
+  int64_t S = 1;
+  // at least 8 K steps of 16 per split
+  while (S < kMaxSplit && tiles * S < kTargetWorkgroups && K16 / (2 * S * dev::BK) >= 8) S *= 2;
+  return S;
+}
+int64_t ldb_for(int64_t nrhs) {
+  const int64_t tn = ntile_for(nrhs);
+  return (2 * nrhs + tn - 1) / tn * tn;
+}
+}  // namespace
+
+size_t gemm_workspace_bytes(int64_t n, int64_t nrhs) {
+  // the float64 embedding of the right-hand sides (K16 x ldb doubles, the larger of the two),
+  // then the split-K partials: S M ldb doubles for blocks of up to n rows (S tiles x splits is
+  // at most about kTargetWorkgroups, the tile at most 256 x 128)
+  const int64_t K16 = (2 * n + dev::BK - 1) / dev::BK * dev::BK;
+  const int64_t ldb = ldb_for(nrhs);
+  const int64_t partial = std::min<int64_t>(kMaxSplit * n * ldb, 2 * kTargetWorkgroups * 256 * 128 + n * ldb);
+  return (size_t(K16) * ldb + size_t(partial)) * sizeof(double) + 256;
 }
 
 void launch_gemm(const GemmDesc& d, void* ws, size_t ws_bytes, hipStream_t st) {
   if (d.rows <= 0 || d.nrhs <= 0) return;
   const int64_t K = 2 * d.cols;
   const int64_t K16 = (K + dev::BK - 1) / dev::BK * dev::BK;
-  const int64_t ldb = (2 * d.nrhs + dev::BN - 1) / dev::BN * dev::BN;
+  const int tn = ntile_for(d.nrhs);
+  const int64_t ldb = ldb_for(d.nrhs), ntn = ldb / tn;
   const int64_t lda = 2 * d.lda;  // real leading dimension
-  if (!d.fp32) {
-    if (size_t(K16) * ldb * sizeof(double) > ws_bytes) throw Error(BEM_E_INVALID, "GEMM workspace too small");
+  // fp32 == 2: float32 entries on the float64 kernel (float64 arithmetic)
+  const bool mfma32 = d.fp32 == 1;
+  const size_t bbytes = size_t(K16) * ldb * (mfma32 ? sizeof(float) : sizeof(double));
+  const int64_t tm = mfma32 ? (tn == 128 ? 128 : 256) : (tn == 128 ? 64 : 128);
+  const int64_t ntm = (d.rows + tm - 1) / tm;
+  const int64_t S = split_for(ntm * ntn, K16);
+  const int64_t kc = (K16 / S + dev::BK - 1) / dev::BK * dev::BK;
+  const size_t poff = (bbytes + 255) / 256 * 256;
+  const size_t need = poff + (S > 1 ? size_t(S) * d.rows * ldb * sizeof(double) : 0);
+  if (need > ws_bytes) throw Error(BEM_E_INVALID, "GEMM workspace too small");
+  double* P = reinterpret_cast<double*>(static_cast<char*>(ws) + poff);
+  const dim3 g(unsigned(ntm * ntn * S));
+  // the split-K sum belongs to the product (inside its timing scope)
+  auto reduce = [&]() {
+    if (S <= 1) return;
+    const int64_t n = d.rows * d.nrhs;
+    hipLaunchKernelGGL(dev::k_splitk_reduce, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, P, d.rows, ldb, S,
+                       d.nrhs, d.Y, d.ldy, d.alpha, d.accumulate);
+    BEM_HIP(hipGetLastError());
+  };
+  if (!mfma32) {
     double* Bm = static_cast<double*>(ws);
     hipLaunchKernelGGL(dev::k_build_B64, dim3(unsigned((ldb + 255) / 256), unsigned(std::min<int64_t>(K16, 32768))), dim3(256), 0, st, d.X,
                        d.ldx, d.cols, d.nrhs, Bm, ldb, K16);
     BEM_HIP(hipGetLastError());
-    const int64_t ntm = (d.rows + dev::DM - 1) / dev::DM, ntn = ldb / dev::DN;
-    const double* A = static_cast<const double*>(d.A);
-    const bool aligned = ((reinterpret_cast<uintptr_t>(A) | uintptr_t(lda * 8)) & 15) == 0;
-    ProfScope ps(st, KC_GEMM_F64, double(d.rows) * d.cols * 16.0, 8.0 * double(d.rows) * d.cols * d.nrhs);
-    const dim3 g(unsigned(ntm * ntn));
-    if (aligned)
-      hipLaunchKernelGGL((dev::k_gemm_f64<true>), g, dim3(256), 0, st, A, lda, Bm, ldb, d.rows, K, K16, ntn, d.Y,
-                         d.ldy, d.nrhs, d.alpha, d.accumulate);
-    else
-      hipLaunchKernelGGL((dev::k_gemm_f64<false>), g, dim3(256), 0, st, A, lda, Bm, ldb, d.rows, K, K16, ntn, d.Y,
-                         d.ldy, d.nrhs, d.alpha, d.accumulate);
+    ProfScope ps(st, KC_GEMM_F64, double(d.rows) * d.cols * (d.fp32 ? 8.0 : 16.0),
+                 8.0 * double(d.rows) * d.cols * d.nrhs);
+#define BEM_G64(TA, AL, WN, JN)                                                                                      \
+  hipLaunchKernelGGL((dev::k_gemm_f64<TA, AL, WN, JN>), g, dim3(256), 0, st, static_cast<const TA*>(d.A), lda, Bm, \
+                     ldb, d.rows, K, K16, kc, ntn, S, P, d.Y, d.ldy, d.nrhs, d.alpha, d.accumulate)
+#define BEM_G64T(TA, AL) \
+  if (tn == 128) BEM_G64(TA, AL, 2, 4); else if (tn == 64) BEM_G64(TA, AL, 1, 4); else BEM_G64(TA, AL, 1, 2)
+    if (!d.fp32) {
+      const bool aligned = ((reinterpret_cast<uintptr_t>(d.A) | uintptr_t(lda * 8)) & 15) == 0;
+      if (aligned) { BEM_G64T(double, true); } else { BEM_G64T(double, false); }
+    } else {
+      const bool aligned = ((reinterpret_cast<uintptr_t>(d.A) | uintptr_t(lda * 4)) & 7) == 0;
+      if (aligned) { BEM_G64T(float, true); } else { BEM_G64T(float, false); }
+    }
+#undef BEM_G64T
+#undef BEM_G64
     BEM_HIP(hipGetLastError());
-    return;
+    reduce();
+  } else {
+    float* Bm = static_cast<float*>(ws);
+    hipLaunchKernelGGL(dev::k_build_B, dim3(unsigned((ldb + 255) / 256), unsigned(std::min<int64_t>(K16, 32768))), dim3(256), 0, st, d.X, d.ldx,
+                       d.cols, d.nrhs, Bm, ldb, K16);
+    BEM_HIP(hipGetLastError());
+    const float* A = static_cast<const float*>(d.A);
+    const bool aligned = ((reinterpret_cast<uintptr_t>(A) | uintptr_t(lda * 4)) & 15) == 0;
+    ProfScope ps(st, KC_GEMM_F32, double(d.rows) * d.cols * 8.0, 8.0 * double(d.rows) * d.cols * d.nrhs);
+#define BEM_G32(AL, WN, JN)                                                                                      \
+  hipLaunchKernelGGL((dev::k_gemm_f32<AL, WN, JN>), g, dim3(256), 0, st, A, lda, Bm, ldb, d.rows, K, K16, kc, ntn, \
+                     S, P, d.Y, d.ldy, d.nrhs, d.alpha, d.accumulate)
+    if (tn == 128) { if (aligned) BEM_G32(true, 2, 2); else BEM_G32(false, 2, 2); }
+    else if (tn == 64) { if (aligned) BEM_G32(true, 1, 2); else BEM_G32(false, 1, 2); }
+    else { if (aligned) BEM_G32(true, 1, 1); else BEM_G32(false, 1, 1); }
+#undef BEM_G32
+    BEM_HIP(hipGetLastError());
+    reduce();
   }
-  if (size_t(K16) * ldb * sizeof(float) > ws_bytes) throw Error(BEM_E_INVALID, "GEMM workspace too small");
-  float* Bm = static_cast<float*>(ws);
-  hipLaunchKernelGGL(dev::k_build_B, dim3(unsigned((ldb + 255) / 256), unsigned(std::min<int64_t>(K16, 32768))), dim3(256), 0, st, d.X, d.ldx,
-                     d.cols, d.nrhs, Bm, ldb, K16);
-  BEM_HIP(hipGetLastError());
-  const int64_t ntm = (d.rows + dev::BM - 1) / dev::BM, ntn = ldb / dev::BN;
-  const float* A = static_cast<const float*>(d.A);
-  const bool aligned = ((reinterpret_cast<uintptr_t>(A) | uintptr_t(lda * 4)) & 15) == 0;
-  ProfScope ps(st, KC_GEMM_F32, double(d.rows) * d.cols * 8.0, 8.0 * double(d.rows) * d.cols * d.nrhs);
-  if (aligned)
-    hipLaunchKernelGGL(dev::k_gemm_f32<true>, dim3(unsigned(ntm * ntn)), dim3(256), 0, st, A, lda, Bm, ldb, d.rows, K,
-                       K16, ntn, d.Y, d.ldy, d.nrhs, d.alpha, d.accumulate);
-  else
-    hipLaunchKernelGGL(dev::k_gemm_f32<false>, dim3(unsigned(ntm * ntn)), dim3(256), 0, st, A, lda, Bm, ldb, d.rows,
-                       K, K16, ntn, d.Y, d.ldy, d.nrhs, d.alpha, d.accumulate);
-  BEM_HIP(hipGetLastError());
 }
 
 // Columns at or below this count run as repeated grouped GEMVs (the float32 tile of 64 real

@@ -21,7 +21,8 @@ struct GemvDesc {
   double2* y;         // rows, float64 complex
   double2 alpha, alpha2;
   int accumulate;     // 0: y = ... ; 1: y += ...
-  int fp32;           // storage of A (and A2)
+  int fp32;           // storage of A (and A2): 0 float64; 1 float32 (float32 arithmetic);
+                      // 2 float32 entries in float64 arithmetic
   int64_t tile0;      // first row tile of this descriptor (filled by the launcher)
   int64_t ldx, ldx2, ldy;  // column strides of x, x2, y for multi-column products
 };
@@ -123,11 +124,15 @@ void launch_spmv(const int64_t* ptr, const int32_t* idx, const double* val, int6
 // z = a*x + b*y (elementwise, n; x or y may be null)
 void launch_axpby(int64_t n, double2 a, const double2* x, double2 b, const double2* y, double2* z,
                   hipStream_t st, int R = 1, int64_t ldx = 0, int64_t ldy = 0, int64_t ldz = 0);
-// Workspace bytes of launch_gemm for a float32 block with `cols` complex columns and nrhs.
-size_t gemm_workspace_bytes(int64_t cols, int64_t nrhs);
+// Workspace bytes of launch_gemm for products of blocks with at most n rows and n complex
+// columns and nrhs right-hand sides (either storage precision).
+size_t gemm_workspace_bytes(int64_t n, int64_t nrhs);
 // out[i] = A[i][i], i < n (row-major, leading dimension ld)
 void launch_diag(const double2* A, int64_t ld, int64_t n, double2* out, hipStream_t st);
 void launch_cast_f32(const double2* src, int64_t rows, int64_t cols, int64_t lds, float2* dst, int64_t ldd,
+                     hipStream_t st);
+// dst[r][c] = src[r][c] widened to float64, r < rows, c < cols
+void launch_cast_f64(const float2* src, int64_t rows, int64_t cols, int64_t lds, double2* dst, int64_t ldd,
                      hipStream_t st);
 
 // ---- Krylov (float64 complex, deterministic reductions)

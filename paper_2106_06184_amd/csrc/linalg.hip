@@ -89,6 +89,42 @@ __device__ __forceinline__ void rows_f64(const double2* __restrict__ A, int64_t 
   }
 }
 
+// float32 storage, float64 arithmetic (the float64 residuals of a float32-only operator): the
+// loop of rows_f64 with each entry widened as it is loaded.
+template <int RPW>
+__device__ __forceinline__ void rows_f32w(const float2* __restrict__ A, int64_t lda, int64_t rows, int64_t cols,
+                                          const double2* __restrict__ x, int64_t row0, int lane, int wv,
+                                          double2 alpha, double* yr, double* yi) {
+  double ar[RPW], ai[RPW];
+#pragma unroll
+  for (int r = 0; r < RPW; ++r) ar[r] = ai[r] = 0.0;
+  const float2* rowp[RPW];
+#pragma unroll
+  for (int r = 0; r < RPW; ++r) rowp[r] = A + min(row0 + r, rows - 1) * lda;
+  for (int64_t cs = int64_t(wv) * 2 * kWave; cs < cols; cs += int64_t(kWavesPerBlock) * 2 * kWave) {
+    const int64_t c = cs + lane;
+    for (int h = 0; h < 2; ++h) {
+      const int64_t cc = c + h * kWave;
+      if (cc < cols) {
+        const double2 x0 = x[cc];
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) {
+          const float2 f = rowp[r][cc];
+          const double a0x = double(f.x), a0y = double(f.y);
+          ar[r] += a0x * x0.x - a0y * x0.y;
+          ai[r] += a0x * x0.y + a0y * x0.x;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < RPW; ++r) {
+    const double sr = wave_sum(ar[r]), si = wave_sum(ai[r]);
+    yr[r] += alpha.x * sr - alpha.y * si;
+    yi[r] += alpha.x * si + alpha.y * sr;
+  }
+}
+
 typedef float fx4 __attribute__((ext_vector_type(4)));
 
 // float32 storage and accumulation; each lane reads two consecutive complex entries per
@@ -168,7 +204,13 @@ __global__ void __launch_bounds__(256) k_gemv_grouped(GemvPack pack) {
   double yr[R], yi[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) yr[r] = yi[r] = 0.0;
-  if (d.fp32) {
+  if (d.fp32 == 2) {
+    rows_f32w<R>(static_cast<const float2*>(d.A), d.lda, d.rows, d.cols, d.x, row0, lane, wave,
+                 make_double2(d.ar, d.ai), yr, yi);
+    if (d.A2)
+      rows_f32w<R>(static_cast<const float2*>(d.A2), d.lda2, d.rows, d.cols, d.x2, row0, lane, wave,
+                   make_double2(d.a2r, d.a2i), yr, yi);
+  } else if (d.fp32) {
     const bool al1 = ((reinterpret_cast<uintptr_t>(d.A) | uintptr_t(d.lda * 8)) & 15) == 0;
     if (al1)
       rows_f32<R, true>(static_cast<const float2*>(d.A), d.lda, d.rows, d.cols, d.x, row0, lane, wave,
@@ -328,6 +370,15 @@ __global__ void k_axpby(int64_t n, double2 a, const double2* __restrict__ x, dou
 __global__ void k_diag(const double2* __restrict__ A, int64_t ld, int64_t n, double2* __restrict__ out) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) out[i] = A[i * ld + i];
+}
+
+__global__ void k_cast_f64(const float2* __restrict__ src, int64_t rows, int64_t cols, int64_t lds,
+                           double2* __restrict__ dst, int64_t ldd) {
+  const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t r = blockIdx.y;
+  if (c >= cols) return;
+  const float2 v = src[r * lds + c];
+  dst[r * ldd + c] = make_double2(double(v.x), double(v.y));
 }
 
 __global__ void k_cast_f32(const double2* __restrict__ src, int64_t rows, int64_t cols, int64_t lds,
@@ -787,6 +838,17 @@ void launch_cast_f32(const double2* src, int64_t rows, int64_t cols, int64_t lds
   hipLaunchKernelGGL(dev::k_cast_f32, dim3(unsigned((ldd + 255) / 256), unsigned(rows)), dim3(256), 0, st, src, rows,
                      cols, lds, dst, ldd);
   BEM_HIP(hipGetLastError());
+}
+
+void launch_cast_f64(const float2* src, int64_t rows, int64_t cols, int64_t lds, double2* dst, int64_t ldd,
+                     hipStream_t st) {
+  if (rows <= 0 || cols <= 0) return;
+  for (int64_t r0 = 0; r0 < rows; r0 += 65535) {
+    const int64_t nr = std::min<int64_t>(65535, rows - r0);
+    hipLaunchKernelGGL(dev::k_cast_f64, dim3(unsigned((cols + 255) / 256), unsigned(nr)), dim3(256), 0, st,
+                       src + r0 * lds, nr, cols, lds, dst + r0 * ldd, ldd);
+    BEM_HIP(hipGetLastError());
+  }
 }
 
 void launch_mdot(const double2* V, int64_t ldv, int j, const double2* w, int64_t n, double2* h,

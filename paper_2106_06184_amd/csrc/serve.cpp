@@ -158,7 +158,9 @@ bem_ticket Server::submit(const bem_request& r) {
   q->rho = r.rho;
   const int64_t ne = 3 * r.nt / 2;
   (void)ne;
-  q->bytes = estimate_request_bytes(r.nt, r.prob.n_obj, r.prob.precision, r.opts.restart > 0 ? r.opts.restart : 50,
+  const int64_t nunk = 4 * r.nt - 2 * r.prob.n_obj;  // upper bound of 2 NE + NT - n_obj
+  q->bytes = estimate_request_bytes(r.nt, r.prob.n_obj, r.prob.precision,
+                                    r.opts.restart > 0 ? r.opts.restart : auto_restart(nunk, r.nexc),
                                     r.nexc, r.prob.formulation);
   if (q->bytes > ctx_->budget) throw Error(BEM_E_NOMEM, "request can never fit the device budget");
   q->t_submit = std::chrono::steady_clock::now();

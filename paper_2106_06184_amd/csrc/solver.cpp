@@ -84,7 +84,13 @@ void to_f32(Dense& d, hipStream_t st) {
 GemvDesc desc(const Dense& A, bool fp32, int64_t roff, int64_t coff, int64_t rows, int64_t cols, const double2* x,
               double2* y, double2 alpha, int acc) {
   GemvDesc d{};
+  // a block whose float64 entries were dropped (BEM_FP32) is read in float32; a float64 product
+  // of it keeps float64 arithmetic (the refinement's residuals)
   d.fp32 = fp32 ? 1 : 0;
+  if (!A.d64) {
+    d.fp32 = fp32 ? 1 : 2;
+    fp32 = true;
+  }
   if (fp32) d.A = A.d32 + roff * A.ld + coff;
   else d.A = A.d64 + roff * A.ld + coff;
   d.lda = A.ld;
@@ -98,7 +104,8 @@ GemvDesc desc(const Dense& A, bool fp32, int64_t roff, int64_t coff, int64_t row
 }
 
 void add_second(GemvDesc& d, const Dense& A, bool fp32, int64_t roff, int64_t coff, const double2* x, double2 alpha) {
-  if (fp32) d.A2 = A.d32 + roff * A.ld + coff;
+  (void)fp32;  // one launch reads both matrices in the first one's storage precision
+  if (d.fp32) d.A2 = A.d32 + roff * A.ld + coff;
   else d.A2 = A.d64 + roff * A.ld + coff;
   d.lda2 = A.ld;
   d.x2 = x;
@@ -222,6 +229,29 @@ OpObj::~OpObj() {}
 
 // ----------------------------------------------------------------- assembly
 
+// BEM_FP32: once the float32 copies and the inverses exist, the float64 entries of every dense
+// block are released (shared copies of an object's blocks point at the same memory, so every
+// descriptor of a released buffer is cleared); products then read float32 storage (desc).
+void drop_f64_blocks(OpObj& op) {
+  BEM_HIP(hipStreamSynchronize(op.stream));
+  std::vector<Dense*> all;
+  for (auto* v : {&op.LA_int, &op.Lphi_int, &op.K_int, &op.K_bg, &op.Minv, &op.SigP, &op.SigEq})
+    for (Dense& d : *v) all.push_back(&d);
+  for (Dense* d : {&op.LA_bg, &op.Lphi_bg, &op.Km}) all.push_back(d);
+  std::vector<double2*> done;
+  for (Dense* d : all) {
+    if (!d->d64) continue;
+    if (!d->d32) throw Error(BEM_E_INVALID, "float32 copy missing");
+    double2* p = d->d64;
+    if (std::find(done.begin(), done.end(), p) == done.end()) {
+      // views into a larger block (the eAEFIE's per-object K~_l) are released with that block
+      if (op.mem.owns(p)) op.mem.release(p);
+      done.push_back(p);
+    }
+  }
+  for (Dense* d : all) d->d64 = nullptr;
+}
+
 void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
   auto tmark = std::chrono::steady_clock::now();
   const Mesh& m = *mo.mesh;
@@ -246,7 +276,8 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
   // ---- problem constants (eq. epsrc; k = sqrt(eps_c mu_r) k0 with Im k <= 0)
   if (!(prob.freq_hz > 0) || !std::isfinite(prob.freq_hz)) throw Error(BEM_E_INVALID, "frequency must be positive");
   if (prob.n_obj != m.nobj || (m.nobj > 0 && !prob.obj)) throw Error(BEM_E_INVALID, "one material per object required");
-  if (prob.precision != BEM_FP64 && prob.precision != BEM_MIXED) throw Error(BEM_E_INVALID, "unknown precision");
+  if (prob.precision != BEM_FP64 && prob.precision != BEM_MIXED && prob.precision != BEM_FP32)
+    throw Error(BEM_E_INVALID, "unknown precision");
   op.precision = prob.precision;
   op.freq = prob.freq_hz;
   const double w = 2 * kPi * prob.freq_hz;
@@ -510,7 +541,7 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
       !(eaefie && op.inner_mode == kInnerNone))
     throw Error(BEM_E_INVALID, "unknown inner_mode");
   // ---- dense blocks
-  const bool f32 = op.precision == BEM_MIXED;
+  const bool f32 = op.precision != BEM_FP64;
   op.LA_int.clear();
   op.Lphi_int.clear();
   op.K_int.clear();
@@ -685,6 +716,7 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
   build_inner_and_precond(op, ixdiag, st, 2);
 
   mark("inner+precond");
+  if (op.precision == BEM_FP32) drop_f64_blocks(op);
   // ---- work vectors and Krylov spaces
   op.work_len = int64_t(kWorkFields) * work_ld(op);
   op.work = op.mem.alloc<double2>(size_t(op.work_len));
@@ -708,7 +740,7 @@ void build_inner_and_precond(OpObj& op, const std::vector<double>& ixdiag, hipSt
     std::fprintf(stderr, "[bem]   %-28s %8.2f ms\n", what, std::chrono::duration<double, std::milli>(now - tmark).count());
     tmark = now;
   };
-  const bool f32 = op.precision == BEM_MIXED;
+  const bool f32 = op.precision != BEM_FP64;
   int64_t maxn = 0;
   for (int64_t o = 0; o < m.nobj; ++o)
     maxn = std::max(maxn, (m.obj_edge[o + 1] - m.obj_edge[o]) + (m.obj_tri[o + 1] - m.obj_tri[o]) - 1);
@@ -1256,7 +1288,7 @@ void apply_block(OpObj& op, int block, const double2* x, double2* y, int64_t nrh
       ds.push_back(with_ld(desc(op.Lphi_bg, false, 0, 0, op.nt, op.nt, x, y, c2(1.0), 0), op.nt, op.nt));
       break;
     case BEM_BLOCK_K_M:
-      if (!op.Km.d64) throw Error(BEM_E_INVALID, "K~_m is formed only by the eAEFIE formulation");
+      if (!op.Km.d64 && !op.Km.d32) throw Error(BEM_E_INVALID, "K~_m is formed only by the eAEFIE formulation");
       ds.push_back(with_ld(desc(op.Km, false, 0, 0, op.ne, op.ne, x, y, c2(1.0), 0), op.ne, op.ne));
       break;
     case BEM_BLOCK_IX:
@@ -1339,10 +1371,19 @@ void far_field(OpObj& op, const bem_c64* H, const bem_c64* E, int64_t nexc, cons
 }
 
 void export_block(OpObj& op, int block, bem_c64* host) {
+  // a BEM_FP32 block is widened on the host
+  std::vector<float2> row32;
+  auto copy_row = [&](const Dense& A, int64_t r, bem_c64* dst) {
+    if (A.d64) {
+      BEM_HIP(hipMemcpy(dst, A.d64 + r * A.ld, sizeof(double2) * A.cols, hipMemcpyDeviceToHost));
+      return;
+    }
+    row32.resize(size_t(A.cols));
+    BEM_HIP(hipMemcpy(row32.data(), A.d32 + r * A.ld, sizeof(float2) * A.cols, hipMemcpyDeviceToHost));
+    for (int64_t c = 0; c < A.cols; ++c) dst[c] = {double(row32[c].x), double(row32[c].y)};
+  };
   auto copy_dense = [&](const Dense& A, int64_t roff, int64_t coff, int64_t ldh) {
-    for (int64_t r = 0; r < A.rows; ++r)
-      BEM_HIP(hipMemcpy(host + (roff + r) * ldh + coff, A.d64 + r * A.ld, sizeof(double2) * A.cols,
-                        hipMemcpyDeviceToHost));
+    for (int64_t r = 0; r < A.rows; ++r) copy_row(A, r, host + (roff + r) * ldh + coff);
   };
   BEM_HIP(hipStreamSynchronize(op.stream));
   switch (block) {
@@ -1366,7 +1407,7 @@ void export_block(OpObj& op, int block, bem_c64* host) {
       copy_dense(op.Lphi_bg, 0, 0, op.nt);
       return;
     case BEM_BLOCK_K_M:
-      if (!op.Km.d64) throw Error(BEM_E_INVALID, "K~_m is formed only by the eAEFIE formulation");
+      if (!op.Km.d64 && !op.Km.d32) throw Error(BEM_E_INVALID, "K~_m is formed only by the eAEFIE formulation");
       copy_dense(op.Km, 0, 0, op.ne);
       return;
     case BEM_BLOCK_MEQ_INV: {
@@ -1376,13 +1417,13 @@ void export_block(OpObj& op, int block, bem_c64* host) {
       for (int64_t o = 0; o < op.nobj; ++o) {
         const Dense& A = op.Minv[o];
         const int64_t e0 = op.obj_edge[o], neo = op.obj_edge[o + 1] - e0, q0 = op.obj_q[o];
-        std::vector<double2> row(A.cols);
+        std::vector<bem_c64> row(A.cols);
         for (int64_t r = 0; r < A.rows; ++r) {
-          BEM_HIP(hipMemcpy(row.data(), A.d64 + r * A.ld, sizeof(double2) * A.cols, hipMemcpyDeviceToHost));
+          copy_row(A, r, row.data());
           const int64_t gr = r < neo ? e0 + r : op.ne + q0 + (r - neo);
           for (int64_t c = 0; c < A.cols; ++c) {
             const int64_t gc = c < neo ? e0 + c : op.ne + q0 + (c - neo);
-            host[gr * op.Neq + gc] = {row[c].x, row[c].y};
+            host[gr * op.Neq + gc] = row[c];
           }
         }
       }
@@ -1874,27 +1915,44 @@ constexpr int kMaxBatch = 256;
 size_t estimate_request_bytes(int64_t nt, int64_t nobj, int precision, int restart, int64_t nexc, int formulation) {
   const double ne = 1.5 * double(nt), no = double(std::max<int64_t>(nobj, 1));
   const double nq = double(nt) - no, N = 2 * ne + nq, neq = ne + nq;
-  const double per = precision == BEM_MIXED ? 24.0 : 16.0;  // float64 + float32 copy
+  // bytes per dense entry: float64 + float32 copy while assembling (BEM_FP32 and BEM_MIXED), then
+  // the float32 copy alone (BEM_FP32) or both (BEM_MIXED)
+  const double per_fill = precision == BEM_FP64 ? 16.0 : 24.0;
+  const double per = precision == BEM_FP64 ? 16.0 : (precision == BEM_FP32 ? 8.0 : 24.0);
   const bool eaefie = formulation == BEM_FORM_EAEFIE;
   // per object L^A, K~ (and K~_l), L^phi; all pairs L^A_l, L^phi_l (and K~_m)
-  const double dense = per * (((eaefie ? 2 : 3) * ne * ne + double(nt) * nt) / no + (eaefie ? 2 : 1) * ne * ne +
-                               double(nt) * nt);
+  const double entries = ((eaefie ? 2 : 3) * ne * ne + double(nt) * nt) / no + (eaefie ? 2 : 1) * ne * ne +
+                         double(nt) * nt;
+  const double dense = per * entries, dense_fill = per_fill * entries;
   const double fill_scratch = 16.0 * 9.0 * double(nt) * nt;
-  // augmented inverse (not for the eAEFIE) + Sigma_P^-1
-  const double inner = (eaefie ? 0.0 : per * (neq * neq) / no) + per * (nq * nq) / no;
+  // augmented inverse (not for the eAEFIE) + Sigma_P^-1 (formed in float64 before the drop)
+  const double inv_entries = (eaefie ? 0.0 : (neq * neq) / no) + (nq * nq) / no;
+  const double inner = per * inv_entries;
   const double R = double(std::min<int64_t>(std::max<int64_t>(nexc, 1), kMaxBatch));
   const double ldN = double(pad64(int64_t(N)));
   const double solve = 16.0 * R * (ldN * (restart + 1 + 3 + 4) + double(kWorkFields) * pad64(int64_t(neq))) +
                        double(gemm_workspace_bytes(int64_t(std::max(ne, double(nt))), int64_t(R))) +
                        16.0 * (ne * (nexc + 1) + 2 * 64.0 * neq);
-  return size_t(std::max(dense + fill_scratch, dense + inner + solve) + 64.0 * 1024 * 1024);
+  const double assembly = std::max(dense_fill + fill_scratch, dense_fill + per_fill * inv_entries);
+  return size_t(std::max(assembly, dense + inner + solve) + 64.0 * 1024 * 1024);
 }
 
-int solve_op(OpObj& op, const bem_excitation* exc, int64_t nexc, const bem_solve_opts& opts, bem_c64* Hout,
+int auto_restart(int64_t N, int64_t nexc) {
+  // the longest cycle (at most 1000 steps, at least 100) whose Krylov basis of the batch stays
+  // under kAutoKrylovBytes: restarts discard the Krylov space, and the hard (electrically large,
+  // high-contrast) problems converge in far fewer steps with long cycles
+  const double per_step = 16.0 * double(std::min<int64_t>(std::max<int64_t>(nexc, 1), kMaxBatch)) * double(pad64(N));
+  const double m = std::floor(kAutoKrylovBytes / per_step) - 1.0;
+  return int(std::max(100.0, std::min(1000.0, m)));
+}
+
+int solve_op(OpObj& op, const bem_excitation* exc, int64_t nexc, const bem_solve_opts& opts_in, bem_c64* Hout,
              bem_c64* Eout, bem_c64* rhoout, bem_solve_info* info, hipStream_t st) {
   auto tstart = std::chrono::steady_clock::now();
   if (nexc <= 0 || !exc) throw Error(BEM_E_INVALID, "no excitation");
-  if (!(opts.tol > 0) || opts.restart <= 0 || opts.maxit <= 0) throw Error(BEM_E_INVALID, "invalid solve options");
+  if (!(opts_in.tol > 0) || opts_in.maxit <= 0) throw Error(BEM_E_INVALID, "invalid solve options");
+  bem_solve_opts opts = opts_in;
+  if (opts.restart <= 0) opts.restart = auto_restart(op.N, nexc);
   const int64_t ne = op.ne, nt = op.nt, N = op.N;
   DevArena tmp(op.ctx);
   tmp.set_stream(st);
@@ -1907,8 +1965,9 @@ int solve_op(OpObj& op, const bem_excitation* exc, int64_t nexc, const bem_solve
   // from the first step the true residual stalls near the float32 operator's error times the
   // solution's size (1.4e-4 on the 5120-triangle sphere, against 1e-6 estimated), and every
   // refinement sweep restarts the Krylov space; scaled by sqrt(tol) that error is below tol.
+  // (switching earlier costs iterations: from tol^(1/3) the serving mix needed 22% more steps)
   const double relax_global = std::sqrt(opts.tol);
-  const int sweeps = opts.max_refine > 0 ? opts.max_refine : (op.precision == BEM_MIXED ? 5 : 3);
+  const int sweeps = opts.max_refine > 0 ? opts.max_refine : (op.precision != BEM_FP64 ? 5 : 3);
   bem_solve_info inf{};
   int status = BEM_OK;
   op.max_inner_iters = 0;
@@ -1961,7 +2020,8 @@ int solve_op(OpObj& op, const bem_excitation* exc, int64_t nexc, const bem_solve
   // exceeds kFp32ProbeTol.  Random vectors do not show it: for small conductors at low
   // frequency the equivalent current cancels the physical one to many digits, so float32
   // products of solution-like vectors lose them all, and float32 steps make no progress.
-  bool fp32_ok = op.precision == BEM_MIXED;
+  // (BEM_FP32: both products read the float32 entries; A64 takes them in float64 arithmetic)
+  bool fp32_ok = op.precision != BEM_FP64;
   bool probed = false;
   for (int64_t e0 = 0; e0 < nexc; e0 += Rb) {
     const int R = int(std::min<int64_t>(Rb, nexc - e0));
@@ -2029,6 +2089,9 @@ int solve_op(OpObj& op, const bem_excitation* exc, int64_t nexc, const bem_solve
         rmax = std::max(rmax, rel[active[c]]);
       }
       gtol = std::max(gtol, 1e-15);
+      // (BEM_FP32 the same: its float64-arithmetic products on the float32 entries until then;
+      // float32 arithmetic from the first step costs more iterations in the later sweeps than it
+      // saves - 45% more on the serving mix)
       const double relax = relax_global / std::max(rmax, 1e-300);
       // a mixed sweep gets at most three restart cycles (600 steps at least): one that cannot
       // reach its target in that budget works on products too inaccurate in float32

@@ -1,0 +1,122 @@
+"""Dense products through bem_apply against numpy on the exported blocks, for every column count
+that selects a different kernel (grouped GEMV for 1-2 columns; matrix-core GEMMs with 32-, 64- and
+128-wide real N tiles, with and without the split-K sum), in float64 and in float32 storage
+(BEM_FP32: float32 vectors in and out), and the BEM_FP32 precision's solve against the oracle.
+
+Blocks: L^A at the background wavenumber of a 1280-triangle sphere (1920 x 1920: tall enough for
+the split-K path) and of an 80-triangle sphere (120 x 120: one tile, ragged)."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import meshgen
+import paper_2106_06184_amd as B
+from oracle import systems as S
+from tests.bemutil import edge_perm, rel
+
+pytestmark = pytest.mark.gpu
+
+COLS = [1, 2, 3, 8, 16, 17, 32, 33, 64, 65, 130]
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ops():
+    ctx = B.bem_create(0)
+    out = {}
+    for level in (1, 3):
+        w = meshgen.sphere_workload(level, 2.0, 3.0 - 0.2j)
+        mesh = B.bem_mesh_load(ctx, w.xyz, w.tri)
+        info = B.bem_mesh_info(ctx, mesh)
+        op64 = B.bem_assemble(ctx, mesh, B.make_problem(w.freq_hz, w.eps_r, w.mu_r, w.sigma, precision=B.BEM_FP64))
+        op32 = B.bem_assemble(ctx, mesh, B.make_problem(w.freq_hz, w.eps_r, w.mu_r, w.sigma, precision=B.BEM_FP32))
+        ne = info["n_edge"]
+        A = B.bem_block_export(ctx, op64, B.BEM_BLOCK_LA_BG, ne, ne)
+        A32 = B.bem_block_export(ctx, op32, B.BEM_BLOCK_LA_BG, ne, ne)
+        out[level] = (w, mesh, info, op64, op32, A, A32)
+    yield ctx, out
+    B.bem_destroy(ctx)
+
+
+def _x(n, R, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((R, n)) + 1j * rng.standard_normal((R, n))
+
+
+def test_fp32_blocks_are_the_rounded_fp64_blocks(ops):
+    """BEM_FP32 keeps the float64 fill rounded once to float32 (exported widened)."""
+    _, out = ops
+    for level, (_, _, _, _, _, A, A32) in out.items():
+        want = (A.real.astype(np.float32) + 1j * A.imag.astype(np.float32)).astype(np.complex128)
+        assert np.array_equal(A32, want), level
+
+
+@pytest.mark.parametrize("R", COLS)
+@pytest.mark.parametrize("level", [1, 3])
+def test_float64_products(torch_mod, ops, R, level):
+    torch = torch_mod
+    ctx, out = ops
+    w, mesh, info, op64, op32, A, _ = out[level]
+    ne = A.shape[0]
+    X = _x(ne, R, 100 + R)
+    xd = torch.tensor(X, dtype=torch.complex128, device="cuda")
+    yd = torch.zeros((R, ne), dtype=torch.complex128, device="cuda")
+    B.bem_apply(ctx, op64, B.BEM_BLOCK_LA_BG, xd.data_ptr(), yd.data_ptr(), R)
+    torch.cuda.synchronize()
+    Y = yd.cpu().numpy()
+    ref = X @ A.T
+    err = np.linalg.norm(Y - ref) / np.linalg.norm(ref)
+    assert err < 1e-13, err
+
+
+@pytest.mark.parametrize("R", COLS)
+@pytest.mark.parametrize("level", [1, 3])
+def test_float32_products(torch_mod, ops, R, level):
+    """float32 storage and float32 vectors (BEM_FP32): against the exported float32 entries in
+    float64 arithmetic, within the float32 rounding of the inputs and of the accumulation."""
+    torch = torch_mod
+    ctx, out = ops
+    w, mesh, info, op64, op32, _, A32 = out[level]
+    ne = A32.shape[0]
+    X = _x(ne, R, 200 + R).astype(np.complex64)
+    xd = torch.tensor(X, dtype=torch.complex64, device="cuda")
+    yd = torch.zeros((R, ne), dtype=torch.complex64, device="cuda")
+    B.bem_apply(ctx, op32, B.BEM_BLOCK_LA_BG, xd.data_ptr(), yd.data_ptr(), R)
+    torch.cuda.synchronize()
+    Y = yd.cpu().numpy().astype(np.complex128)
+    ref = X.astype(np.complex128) @ A32.T
+    err = np.linalg.norm(Y - ref) / np.linalg.norm(ref)
+    assert err < 2e-6, err
+
+
+def test_fp32_solve_matches_oracle():
+    """BEM_FP32 on the 320-triangle sphere (k0 a = 1, eps_r = 4): refined to a 1e-9 residual
+    with the float32 operator, the currents are within 1e-6 of the float64 oracle's (the
+    difference is the float32 rounding of the operator times its condition number)."""
+    w = meshgen.config_c1()
+    ctx = B.bem_create(0)
+    try:
+        mesh = B.bem_mesh_load(ctx, w.xyz, w.tri)
+        info = B.bem_mesh_info(ctx, mesh)
+        op = B.bem_assemble(ctx, mesh, B.make_problem(w.freq_hz, w.eps_r, w.mu_r, w.sigma, precision=B.BEM_FP32))
+        st = B.bem_op_stats_get(ctx, op)
+        rc, H, E, rho, si = B.bem_solve(ctx, op, B.plane_waves(w.khat, w.pol),
+                                        B.solve_opts(tol=1e-9, restart=100, maxit=2000, max_refine=10),
+                                        info["n_edge"], info["n_tri"])
+        va, vb, _, _ = B.bem_edge_table(ctx, mesh)
+    finally:
+        B.bem_destroy(ctx)
+    assert rc == B.BEM_OK
+    ops_ = S.assemble(w.xyz, w.tri, w.obj, S.Problem(w.freq_hz, w.eps_r, w.mu_r, w.sigma))
+    ref = S.solve_augmented(ops_, S.rhs(ops_, w.khat[0], w.pol[0]))
+    perm = edge_perm(va, vb, ops_.topo.edges)
+    e = (rel(H[:, 0], ref.H(ops_.k0)[perm]), rel(E[:, 0], ref.E()[perm]), rel(rho[:, 0], ref.rho(ops_.B)))
+    print(f"BEM_FP32: outer {si.outer_iters}, refine {si.refine_steps}, residual {si.rel_residual:.2e}, "
+          f"device bytes {st['device_bytes'] / 1e6:.1f} MB, rel err H {e[0]:.2e} E {e[1]:.2e} rho {e[2]:.2e}")
+    assert max(e) < 1e-6
