@@ -322,8 +322,9 @@ typedef struct {
 int bem_op_stats_get(bem_ctx* ctx, bem_op_h op, bem_op_stats* out);
 
 /* Opt-in kernel timing (all contexts of the process).  When enabled, HIP events are recorded
- * on the launch stream around every fill, gather and dense-product launch, together with the
- * launch's algorithmic bytes and work.  Enabling clears the counters.  Classes: 0 float64
+ * on the launch stream around every fill, gather and dense-product launch made by a caller's
+ * thread (the serving loop's requests are not timed: they overlap on the device), together
+ * with the launch's algorithmic bytes and work.  Enabling clears the counters.  Classes: 0 float64
  * products, 1 float32 products, 2 L fill, 3 K~ fill, 4 near corrections, 5 gathers, 6 float32
  * matrix-core products (several excitations), 7 Gauss-Jordan panel updates of the dense inversions,
  * 8 float64 matrix-core products.  bem_profile_read waits for the recorded events. */

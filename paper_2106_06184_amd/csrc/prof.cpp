@@ -9,7 +9,12 @@ namespace bem {
 namespace {
 // begin/end pairs are matched per calling thread (launches from different threads interleave)
 thread_local std::vector<hipEvent_t> t_open;
+thread_local bool t_opted_out = false;
 }  // namespace
+
+void Profiler::opt_out_this_thread() { t_opted_out = true; }
+
+bool Profiler::enabled() const { return on_ && !t_opted_out; }
 
 Profiler& Profiler::get() {
   static Profiler p;

@@ -32,7 +32,11 @@ struct ClassStats {
 class Profiler {
  public:
   static Profiler& get();
-  bool enabled() const { return on_; }
+  // Launches from threads that opted out (the serving loop's workers) are not timed: requests
+  // that overlap on the device would time each other, and a timing event waited for on one
+  // worker can depend on launches another worker has still to make.
+  static void opt_out_this_thread();
+  bool enabled() const;
   void enable(bool on);
   // Record an event pair around a launch issued between begin() and end().
   void begin(hipStream_t st);

@@ -1,6 +1,8 @@
 // Serving loop (see serve.h).
 #include "serve.h"
 
+#include "prof.h"
+
 #include <chrono>
 
 namespace bem {
@@ -191,6 +193,7 @@ void Server::drain() {
 }
 
 void Server::worker(int slot) {
+  Profiler::opt_out_this_thread();
   hipStream_t st = slot_stream_[slot];
   double* pinned = slot_pinned_[slot];
   const bool device_ok = hipSetDevice(ctx_->device) == hipSuccess;

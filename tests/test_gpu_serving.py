@@ -91,5 +91,4 @@ def test_results_same_alone_and_in_the_mix():
             worst = max(worst, float(np.abs(got - want).max() / np.abs(want).max()))
         print(f"{specs[i][0]}: latency {sec:.3f} s, max rel diff vs alone {worst:.1e}")
         assert worst <= 1e-12, (specs[i][0], worst)
-    assert products >= launches
     B.bem_destroy(ctx)

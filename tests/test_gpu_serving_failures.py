@@ -1,0 +1,238 @@
+"""Failure paths and guarantees of the solve and serving calls (SURVEY-style: admission refusal,
+iteration limit with the best iterate, non-finite input, a failing request among healthy ones),
+the serving loop's results against the oracle, real sharing of grouped launches by concurrent
+requests, and the opt-in kernel timer left on while serving.  Every failure is forced from the
+host side (a budget, an iteration limit, a NaN input); no kernel is made to fault."""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+import pytest
+
+import meshgen
+import paper_2106_06184_amd as B
+from oracle import systems as S
+from tests.bemutil import edge_perm, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _wait(ctx, tickets, limit=120.0):
+    done = {}
+    t_end = time.time() + limit
+    while len(done) < len(tickets):
+        assert time.time() < t_end, "serving did not finish"
+        for t in tickets:
+            if t in done:
+                continue
+            try:
+                rc, info = B.bem_poll(ctx, t)
+            except B.BemError as e:
+                rc, info = int(str(e).split()[2].rstrip(":")), None
+            if rc != B.BEM_PENDING:
+                done[t] = (rc, info)
+        time.sleep(0.005)
+    return done
+
+
+def _sphere(level, k0, eps, prec=B.BEM_FP64):
+    xyz, tri = meshgen.icosphere(level)
+    prob = B.make_problem(meshgen.freq_from_k0(k0), [eps], [1.0], [0.0], precision=prec)
+    return xyz, tri, prob
+
+
+def test_admission_refuses_a_request_beyond_the_budget():
+    """A 256 MB budget: a 5120-triangle request (GBs of dense blocks) can never be admitted and
+    bem_submit says so (BEM_E_NOMEM); a 80-triangle request still runs on the same context."""
+    ctx = B.bem_create(0, 256 * 1024 * 1024)
+    try:
+        xyz, tri, prob = _sphere(4, 1.0, 2.0)
+        big = B.Request(xyz, tri, None, prob, B.plane_waves([[0, 0, -1.0]], [[1.0, 0, 0]]),
+                        B.solve_opts(tol=1e-8, restart=50))
+        with pytest.raises(B.BemError) as ei:
+            B.bem_submit(ctx, big)
+        assert "status -3" in str(ei.value)
+        xyz, tri, prob = _sphere(1, 1.0, 2.0)
+        small = B.Request(xyz, tri, None, prob, B.plane_waves([[0, 0, -1.0]], [[1.0, 0, 0]]),
+                          B.solve_opts(tol=1e-8, restart=50))
+        t = B.bem_submit(ctx, small)
+        done = _wait(ctx, [t])
+        assert done[t][0] == B.BEM_OK
+    finally:
+        B.bem_destroy(ctx)
+
+
+def test_iteration_limit_returns_the_best_iterate():
+    """maxit = 2 on a problem that needs tens of steps: BEM_E_NOT_CONVERGED, the residual of the
+    written iterate is reported (below 1: two steps reduce it) and the currents are written."""
+    ctx = B.bem_create(0)
+    try:
+        xyz, tri, prob = _sphere(2, 1.0, 4.0)
+        mesh = B.bem_mesh_load(ctx, xyz, tri)
+        info = B.bem_mesh_info(ctx, mesh)
+        op = B.bem_assemble(ctx, mesh, prob)
+        rc, H, E, rho, si = B.bem_solve(ctx, op, B.plane_waves([[0, 0, -1.0]], [[1.0, 0, 0]]),
+                                        B.solve_opts(tol=1e-10, restart=50, maxit=2), info["n_edge"], info["n_tri"])
+    finally:
+        B.bem_destroy(ctx)
+    assert rc == B.BEM_E_NOT_CONVERGED
+    assert 1e-10 < si.rel_residual < 1.0
+    assert np.abs(H).max() > 0 and np.abs(E).max() > 0
+    print(f"after {si.outer_iters} steps: residual {si.rel_residual:.3e}")
+
+
+def test_nonfinite_excitation_is_refused():
+    ctx = B.bem_create(0)
+    try:
+        xyz, tri, prob = _sphere(1, 1.0, 2.0)
+        mesh = B.bem_mesh_load(ctx, xyz, tri)
+        info = B.bem_mesh_info(ctx, mesh)
+        op = B.bem_assemble(ctx, mesh, prob)
+        with pytest.raises(B.BemError) as ei:
+            B.bem_solve(ctx, op, B.plane_waves([[0, 0, -1.0]], [[np.nan, 0, 0]]), B.solve_opts(tol=1e-8),
+                        info["n_edge"], info["n_tri"])
+        assert "status -6" in str(ei.value)
+        # the context and operator stay usable
+        rc, H, _, _, _ = B.bem_solve(ctx, op, B.plane_waves([[0, 0, -1.0]], [[1.0, 0, 0]]), B.solve_opts(tol=1e-8),
+                                     info["n_edge"], info["n_tri"])
+        assert rc == B.BEM_OK and np.isfinite(H).all()
+    finally:
+        B.bem_destroy(ctx)
+
+
+def _solo(level, k0, eps, khat, pol, opts):
+    ctx = B.bem_create(0)
+    try:
+        xyz, tri, prob = _sphere(level, k0, eps)
+        mesh = B.bem_mesh_load(ctx, xyz, tri)
+        info = B.bem_mesh_info(ctx, mesh)
+        op = B.bem_assemble(ctx, mesh, prob)
+        rc, H, E, rho, _ = B.bem_solve(ctx, op, B.plane_waves(khat, pol), opts, info["n_edge"], info["n_tri"])
+        assert rc == B.BEM_OK
+        return H, E, rho
+    finally:
+        B.bem_destroy(ctx)
+
+
+def test_failing_request_leaves_the_others_intact():
+    """Four requests in flight, one of them with a NaN polarisation: that one ends with
+    BEM_E_NUMERIC, the three others converge to exactly what they give alone."""
+    opts = B.solve_opts(tol=1e-9, restart=60, maxit=2000)
+    specs = [(2, 1.0, 4.0, 11), (1, 0.7, 2.5, 12), (2, 1.5, 3.0 - 0.1j, 13), (1, 1.0, 2.0, 14)]
+    ctx = B.bem_create(0)
+    try:
+        reqs, tickets = [], []
+        for i, (level, k0, eps, seed) in enumerate(specs):
+            xyz, tri, prob = _sphere(level, k0, eps)
+            khat, pol = meshgen.plane_wave_draws(2, seed)
+            pol = pol.astype(np.complex128)
+            if i == 2:
+                pol[1, 0] = np.nan
+            r = B.Request(xyz, tri, None, prob, B.plane_waves(khat, pol), opts)
+            reqs.append((r, khat, pol))
+            tickets.append(B.bem_submit(ctx, r))
+        done = _wait(ctx, tickets)
+    finally:
+        B.bem_destroy(ctx)
+    for i, ((r, khat, pol), t) in enumerate(zip(reqs, tickets)):
+        rc = done[t][0]
+        if i == 2:
+            assert rc == B.BEM_E_NUMERIC, rc
+            continue
+        assert rc == B.BEM_OK, (i, rc)
+        level, k0, eps, _ = specs[i]
+        for got, want in zip((r.H, r.E, r.rho), _solo(level, k0, eps, khat, pol, opts)):
+            assert np.array_equal(got, want), i
+
+
+def test_concurrent_requests_share_grouped_launches():
+    """Eight one-column requests of the same 320-triangle sphere at once: four solve at a time,
+    so their small products wait for each other and go out together (more products than
+    launches), and each result is bitwise its solo result."""
+    opts = B.solve_opts(tol=1e-8, restart=60, maxit=2000)
+    khat, pol = meshgen.plane_wave_draws(8, 21)
+    pol = pol.astype(np.complex128)
+    ctx = B.bem_create(0)
+    try:
+        reqs, tickets = [], []
+        for i in range(8):
+            xyz, tri, prob = _sphere(2, 1.2, 3.0)
+            r = B.Request(xyz, tri, None, prob, B.plane_waves(khat[i:i + 1], pol[i:i + 1]), opts)
+            reqs.append(r)
+            tickets.append(B.bem_submit(ctx, r))
+        done = _wait(ctx, tickets)
+        launches, products = B.bem_serve_stats(ctx)
+    finally:
+        B.bem_destroy(ctx)
+    print(f"combiner: {launches} grouped launches carried {products} products")
+    assert products > launches > 0
+    for i, (r, t) in enumerate(zip(reqs, tickets)):
+        assert done[t][0] == B.BEM_OK
+        want = _solo(2, 1.2, 3.0, khat[i:i + 1], pol[i:i + 1], opts)
+        for got, w in zip((r.H, r.E, r.rho), want):
+            assert np.array_equal(got, w), i
+
+
+def test_served_currents_match_the_oracle():
+    """Two small requests served together (80- and 320-triangle spheres, two plane waves each) to
+    a 1e-12 residual: H, E, rho within 1e-9 of the oracle's augmented LU solution."""
+    opts = B.solve_opts(tol=1e-12, restart=100, maxit=3000)
+    cases = [(1, 0.8, 2.5 - 0.2j, 31), (2, 1.0, 4.0, 32)]
+    ctx = B.bem_create(0)
+    try:
+        reqs, tickets = [], []
+        for level, k0, eps, seed in cases:
+            xyz, tri, prob = _sphere(level, k0, eps)
+            khat, pol = meshgen.plane_wave_draws(2, seed)
+            r = B.Request(xyz, tri, None, prob, B.plane_waves(khat, pol), opts)
+            reqs.append((r, xyz, tri, khat, pol))
+            tickets.append(B.bem_submit(ctx, r))
+        done = _wait(ctx, tickets)
+        # the library's edge order, from a host-only context
+        hctx = B.bem_create(-1)
+        perms = []
+        for (_, xyz, tri, _, _) in reqs:
+            va, vb, _, _ = B.bem_edge_table(hctx, B.bem_mesh_load(hctx, xyz, tri))
+            perms.append((va, vb))
+        B.bem_destroy(hctx)
+    finally:
+        B.bem_destroy(ctx)
+    for (r, xyz, tri, khat, pol), t, (level, k0, eps, _), (va, vb) in zip(reqs, tickets, cases, perms):
+        assert done[t][0] == B.BEM_OK
+        ops = S.assemble(xyz, tri, np.zeros(len(tri), np.int32),
+                         S.Problem(meshgen.freq_from_k0(k0), [eps], [1.0], [0.0]))
+        perm = edge_perm(va, vb, ops.topo.edges)
+        for c in range(2):
+            ref = S.solve_augmented(ops, S.rhs(ops, khat[c], pol[c]))
+            e = max(rel(r.H[:, c], ref.H(ops.k0)[perm]), rel(r.E[:, c], ref.E()[perm]),
+                    rel(r.rho[:, c], ref.rho(ops.B)))
+            print(f"{len(tri)} triangles, wave {c}: rel err vs oracle {e:.2e}")
+            assert e < 1e-9
+
+
+def test_serving_with_the_kernel_timer_on():
+    """The kernel timer left on while requests are served: the requests complete (the serving
+    workers do not time their launches) and a solve on the caller's thread is still timed."""
+    opts = B.solve_opts(tol=1e-8, restart=60, maxit=2000)
+    B.bem_profile_enable(True)
+    ctx = B.bem_create(0)
+    try:
+        reqs, tickets = [], []
+        for i, level in enumerate((2, 1, 2, 2)):
+            xyz, tri, prob = _sphere(level, 1.0, 3.0)
+            khat, pol = meshgen.plane_wave_draws(3, 40 + i)
+            r = B.Request(xyz, tri, None, prob, B.plane_waves(khat, pol), opts)
+            reqs.append(r)
+            tickets.append(B.bem_submit(ctx, r))
+        done = _wait(ctx, tickets, limit=60.0)
+        assert all(v[0] == B.BEM_OK for v in done.values())
+        served = sum(B.bem_profile_read(k)["launches"] for k in range(len(B.KC_NAMES)))
+        assert served == 0
+        xyz, tri, prob = _sphere(1, 1.0, 3.0)
+        mesh = B.bem_mesh_load(ctx, xyz, tri)
+        op = B.bem_assemble(ctx, mesh, prob)
+        assert B.bem_profile_read(B.KC_FILL_L)["launches"] > 0
+    finally:
+        B.bem_profile_enable(False)
+        B.bem_destroy(ctx)
