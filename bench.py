@@ -355,8 +355,14 @@ def run_serve(args) -> int:
     # restart <= 0: the library's automatic cycle length (100-1000 steps, Krylov basis <= 8 GB)
     stream = meshgen.mixed_stream(args.warmup + args.steps, rate_hz=args.serve_rate, seed=args.serve_seed)
     timed = [w for _, w in stream[args.warmup:]]
-    runs = {}
     precs = {"fp32": B.BEM_FP32, "mixed": B.BEM_MIXED, "fp64": B.BEM_FP64}
+    if args.serve_profile_only:
+        # only the sequential profiled pass (one host thread: for kernel traces and counters)
+        prof = _profiled_pass(B, timed, args, precs[args.serve_precisions.split(",")[0]])
+        print(json.dumps({"roofline": _roofline(B, prof),
+                          "classes": {B.KC_NAMES[k]: v for k, v in prof.items()}}), flush=True)
+        return 0
+    runs = {}
     for prec_name in [p for p in args.serve_precisions.split(",") if p]:
         prec = precs[prec_name]
         log(f"serving {len(timed)} requests ({prec_name}) after {args.warmup} warm-up requests ...")
@@ -443,6 +449,9 @@ def main() -> int:
     ap.add_argument("--serve-rate", type=float, default=2.0,
                     help="mean Poisson arrival rate of the serving mix, requests/s")
     ap.add_argument("--serve-seed", type=int, default=5)
+    ap.add_argument("--serve-profile-only", action="store_true",
+                    help="run only the sequential profiled pass over the timed requests (one host thread; "
+                         "for rocprofv3 kernel traces and counters of the roofline's launches)")
     ap.add_argument("--serve-precisions", default="fp32,mixed,fp64",
                     help="precisions the serving mix is run in, the first one being the headline")
     ap.add_argument("--copy-calibration", action="store_true",
