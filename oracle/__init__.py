@@ -22,7 +22,10 @@ Modules
               plane-wave right-hand side
   systems     augmented, reduced and final (explicit-Y) systems, LU solves,
               far-field / RCS of the differential current
-  mie         Mie series for a homogeneous dielectric sphere
+  mie         Mie series for a homogeneous dielectric sphere (far-field amplitudes and
+              the scattered near field)
+  nearfield   E and H at exterior points radiated by the differential current and
+              charge (mixed potentials, singularity extraction near the surface)
   brute       whole Galerkin entries of L^A, L^phi, K~ by brute force (singularity-
               cancelling maps of each triangle pair onto the 4-cube, tensor
               Gauss-Legendre): no extraction, no closed forms, no rule set Q; it pins

@@ -80,3 +80,52 @@ def bistatic_rcs(eps_r: complex, radius: float, k_bg: float, theta_obs, phi_obs)
     theta_obs = np.atleast_1d(theta_obs)
     S1, S2 = amplitudes(m, x, math.pi - theta_obs)
     return 4 * math.pi / k_bg ** 2 * (np.abs(S2) ** 2 * np.cos(phi_obs) ** 2 + np.abs(S1) ** 2 * np.sin(phi_obs) ** 2)
+
+
+def near_field(eps_r: complex, radius: float, k_bg: float, points, eta: float = 376.730313668):
+    """Scattered E, H (npts, 3) outside the sphere for the plane wave E = x e^{+j k z} (travelling
+    along -z, unit amplitude), in this code base's e^{+j omega t} convention.
+
+    Bohren & Huffman's series (e^{-i omega t}, incidence along +z, x-polarised):
+      E_s = sum_n E_n (i a_n N_e1n - b_n M_o1n),  H_s = (1/eta) sum_n E_n (i b_n N_o1n + a_n M_e1n),
+      E_n = i^n (2n + 1)/(n (n + 1)), radial function h_n^(1)(k r).
+    The textbook frame is this one turned by pi about x (x' = x, y' = -y, z' = -z), and the
+    e^{+j omega t} phasor is the complex conjugate of the e^{-i omega t} one (with m taken as
+    sqrt(conj(eps_r)), as in bistatic_rcs)."""
+    m = np.sqrt(np.conj(complex(eps_r)))
+    a, b = coefficients(m, k_bg * radius)
+    nmax = len(a)
+    n = np.arange(1, nmax + 1)
+    P = np.atleast_2d(np.asarray(points, dtype=np.float64))
+    Pp = P * np.array([1.0, -1.0, -1.0])
+    r = np.linalg.norm(Pp, axis=1)
+    th = np.arccos(np.clip(Pp[:, 2] / r, -1.0, 1.0))
+    ph = np.arctan2(Pp[:, 1], Pp[:, 0])
+    rho = k_bg * r
+    pi_n, tau_n = angular(nmax, th)                                     # (nmax, npts)
+    jn = special.spherical_jn(n[:, None], rho[None, :])
+    yn = special.spherical_yn(n[:, None], rho[None, :])
+    djn = special.spherical_jn(n[:, None], rho[None, :], derivative=True)
+    dyn = special.spherical_yn(n[:, None], rho[None, :], derivative=True)
+    z = jn + 1j * yn                                                    # h_n^(1)
+    dz = (z + rho[None, :] * (djn + 1j * dyn)) / rho[None, :]           # (rho h_n)' / rho
+    En = (1j ** n * (2 * n + 1) / (n * (n + 1)))[:, None]
+    cp, sp, st = np.cos(ph)[None, :], np.sin(ph)[None, :], np.sin(th)[None, :]
+    nn1 = (n * (n + 1))[:, None]
+    # N_e1n, M_o1n, N_o1n, M_e1n as (r, theta, phi) components
+    Ne = (cp * nn1 * st * pi_n * z / rho[None, :], cp * tau_n * dz, -sp * pi_n * dz)
+    Mo = (0.0, cp * pi_n * z, -sp * tau_n * z)
+    No = (sp * nn1 * st * pi_n * z / rho[None, :], sp * tau_n * dz, cp * pi_n * dz)
+    Me = (0.0, -sp * pi_n * z, -cp * tau_n * z)
+    Es = [np.sum(En * (1j * a[:, None] * Ne[c] - b[:, None] * Mo[c]), axis=0) for c in range(3)]
+    Hs = [np.sum(En * (1j * b[:, None] * No[c] + a[:, None] * Me[c]), axis=0) / eta for c in range(3)]
+
+    def cart(f):
+        th_, ph_ = th, ph
+        rh = np.stack([np.sin(th_) * np.cos(ph_), np.sin(th_) * np.sin(ph_), np.cos(th_)], 1)
+        thh = np.stack([np.cos(th_) * np.cos(ph_), np.cos(th_) * np.sin(ph_), -np.sin(th_)], 1)
+        phh = np.stack([-np.sin(ph_), np.cos(ph_), np.zeros_like(ph_)], 1)
+        v = f[0][:, None] * rh + f[1][:, None] * thh + f[2][:, None] * phh
+        return np.conj(v) * np.array([1.0, -1.0, -1.0])
+
+    return cart(Es), cart(Hs)
