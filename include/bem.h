@@ -243,6 +243,26 @@ typedef struct {
   int64_t n_gap;
 } bem_excitation;
 
+/* Near field of solutions at exterior points (Sec. II-C, eqs. diffsources and diffsourcesdis;
+ * the probe-line observable of Sec. IV-D): outside the objects the scattered field is the one
+ * that the differential current J_delta = J - J_eq and charge rho_delta = rho - rho_eq radiate
+ * in the background (k_l, eps_l, mu_l), J_eq and rho_eq being those of the equivalent
+ * configuration (eq. AEFIEeqvdis, same E; solved in float64 to the operator's inner tolerance):
+ *   E = -j omega mu A - grad Phi,  H = curl A,  A = int G J_delta dS',  Phi = (1/eps) int G rho_delta dS'
+ * per triangle by the 7-point rule on the fill's source split; for a point within two longest
+ * edges of a triangle's centroid the static parts of G and grad G in closed form and the
+ * bounded remainders on at least 16 pieces.  Inputs (host): H, E (NE x nexc) and rho
+ * (NT x nexc) as bem_solve returns them, column-major; npts points, 3 doubles each, which must
+ * lie outside every object and off the surface (inside an object the sum is not that
+ * object's field; on the surface it is singular).  exc: NULL for the scattered field only, or
+ * the nexc plane waves of the solve to add the incident field (E0 pol e^{-j k_l khat . r},
+ * H = khat x E / eta_l): the total field.  Outputs (host, either may be NULL): E_out, H_out,
+ * 3 complex per (solution, point), laid out [exc][point][xyz], in V/m and A/m.  npts = 0
+ * returns at once.  Not concurrently with bem_solve on the same operator.  BEM_E_INVALID for
+ * the eAEFIE formulation, a delta-gap excitation with exc given, or a non-finite point. */
+int bem_near_field(bem_ctx* ctx, bem_op_h op, const bem_c64* H, const bem_c64* E, const bem_c64* rho, int64_t nexc,
+                   const bem_excitation* exc, const double* points, int64_t npts, bem_c64* E_out, bem_c64* H_out);
+
 typedef struct {
   double tol;                   /* relative residual ||b - A x|| / ||b|| in float64 */
   int restart;                  /* GMRES restart length; <= 0: automatic, the longest cycle (100 to

@@ -25,7 +25,7 @@ BEM_FP64, BEM_FP32, BEM_MIXED = 0, 1, 2
 BEM_EXC_PLANE_WAVE, BEM_EXC_DELTA_GAP = 0, 1
 
 SYMBOLS = ["bem_create", "bem_destroy", "bem_last_error", "bem_mesh_load", "bem_mesh_info", "bem_edge_table",
-           "bem_near_pairs", "bem_mesh_copies", "bem_far_field", "bem_assemble", "bem_apply", "bem_dense_invert",
+           "bem_near_pairs", "bem_mesh_copies", "bem_far_field", "bem_near_field", "bem_assemble", "bem_apply", "bem_dense_invert",
            "bem_dense_invert_noalloc",
            "bem_block_export", "bem_set_inner_tol", "bem_solve",
            "bem_submit", "bem_poll", "bem_drain", "bem_release", "bem_memory_in_use", "bem_op_stats_get",
@@ -105,6 +105,9 @@ def lib() -> C.CDLL:
             "bem_mesh_copies": (C.c_int, [P, C.c_uint64, C.POINTER(I32)]),
             "bem_far_field": (C.c_int, [P, C.c_uint64, C.POINTER(c64), C.POINTER(c64), C.c_int64,
                                         C.POINTER(C.c_double), C.c_int64, C.POINTER(c64), C.POINTER(C.c_double)]),
+            "bem_near_field": (C.c_int, [P, C.c_uint64, C.POINTER(c64), C.POINTER(c64), C.POINTER(c64), C.c_int64,
+                                         C.POINTER(bem_excitation), C.POINTER(C.c_double), C.c_int64,
+                                         C.POINTER(c64), C.POINTER(c64)]),
             "bem_assemble": (C.c_int, [P, C.c_uint64, C.POINTER(bem_problem), C.POINTER(C.c_uint64)]),
             "bem_apply": (C.c_int, [P, C.c_uint64, C.c_int, P, P, I64, P]),
             "bem_dense_invert": (C.c_int, [P, P, I64, I64, P, C.POINTER(D)]),
@@ -207,6 +210,23 @@ def bem_far_field(ctx, op: int, H, E, rhat):
     _check(ctx, lib().bem_far_field(ctx, op, cp(H), cp(E), nexc, rhat.ctypes.data_as(C.POINTER(C.c_double)), ndir,
                                     cp(N), rcs.ctypes.data_as(C.POINTER(C.c_double))))
     return N, rcs
+
+
+def bem_near_field(ctx, op: int, H, E, rho, points, exc=None):
+    """Near field E[exc, point, xyz], H[exc, point, xyz] (V/m, A/m) of solutions H, E (NE x nexc)
+    and rho (NT x nexc) at exterior points (npts x 3): the scattered field, or the total field
+    when `exc` holds the solve's plane waves."""
+    H = np.ascontiguousarray(np.asarray(H, np.complex128).reshape(H.shape[0], -1).T)
+    E = np.ascontiguousarray(np.asarray(E, np.complex128).reshape(E.shape[0], -1).T)
+    rho = np.ascontiguousarray(np.asarray(rho, np.complex128).reshape(rho.shape[0], -1).T)
+    pts = np.ascontiguousarray(np.asarray(points, np.float64).reshape(-1, 3))
+    nexc, npts = H.shape[0], pts.shape[0]
+    Eo = np.zeros((nexc, npts, 3), np.complex128)
+    Ho = np.zeros((nexc, npts, 3), np.complex128)
+    cp = lambda a: a.ctypes.data_as(C.POINTER(c64))
+    _check(ctx, lib().bem_near_field(ctx, op, cp(H), cp(E), cp(rho), nexc, exc,
+                                     pts.ctypes.data_as(C.POINTER(C.c_double)), npts, cp(Eo), cp(Ho)))
+    return Eo, Ho
 
 
 def bem_mesh_copies(ctx, mesh: int) -> np.ndarray:

@@ -166,6 +166,17 @@ int bem_far_field(bem_ctx* c, bem_op_h h, const bem_c64* H, const bem_c64* E, in
   });
 }
 
+int bem_near_field(bem_ctx* c, bem_op_h h, const bem_c64* H, const bem_c64* E, const bem_c64* rho, int64_t nexc,
+                   const bem_excitation* exc, const double* points, int64_t npts, bem_c64* E_out, bem_c64* H_out) {
+  return guarded([&]() -> int {
+    bem::Ctx* ctx = C(c);
+    bem::OpObj& op = op_of(ctx, h);
+    need_device(c);
+    bem::near_field(op, H, E, rho, nexc, exc, points, npts, E_out, H_out, op.stream);
+    return BEM_OK;
+  });
+}
+
 int bem_mesh_copies(bem_ctx* c, bem_mesh_h h, int32_t* proto) {
   return guarded([&]() -> int {
     const bem::Mesh& m = *mesh_of(C(c), h).mesh;

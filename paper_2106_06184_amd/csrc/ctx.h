@@ -201,6 +201,9 @@ void export_block(OpObj& op, int block, bem_c64* host);
 // Far field of nexc solutions (host H, E): N per (solution, direction) and the bistatic RCS.
 void far_field(OpObj& op, const bem_c64* H, const bem_c64* E, int64_t nexc, const double* rhat, int64_t ndir,
                bem_c64* N, double* rcs, hipStream_t st);
+void near_field(OpObj& op, const bem_c64* H, const bem_c64* E, const bem_c64* rho, int64_t nexc,
+                const bem_excitation* exc, const double* pts, int64_t npts, bem_c64* Eout, bem_c64* Hout,
+                hipStream_t st);
 // Upper bound of the device bytes of one request (assembly peak or solve peak), for admission.
 size_t estimate_request_bytes(int64_t nt, int64_t nobj, int precision, int restart, int64_t nexc,
                               int formulation = BEM_FORM_SLDM);

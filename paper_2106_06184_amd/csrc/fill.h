@@ -100,6 +100,42 @@ struct FarArgs {
 };
 void launch_far_field(const FarArgs& a, int ncol, hipStream_t st);
 
+// Near field at exterior points of the sources J (RWG coefficients, column c at J + c ldj) and
+// rho (area-normalised pulse coefficients, rho + c ldr) radiating in the background:
+//   E = -j omega mu A - grad Phi,  H = curl A,  A = int G J,  Phi = (1/eps) int G rho.
+// Triangle t's part is formed from its moments I0 = int G, I1 = int G (r' - r),
+// Ig = int grad_r G (7-point rule on the 4^L pieces of the fill's source split; for a point
+// closer than kNearFactor longest edges to the centroid the static parts in closed form and
+// the remainders on at least the kNearFieldLevel split).  Blocks: (point, group of
+// kNearFieldCols columns, triangle range); the range sums go to `part` and a second kernel adds
+// them in range order (and the incident plane wave of column c when `inc` is set), writing
+// E[(c npts + p) 3 + i] and H likewise.
+constexpr int kNearFieldCols = 4;
+constexpr int kNearFieldLevel = 2;
+struct NearArgs {
+  const double* geo;
+  int64_t nt;
+  const int32_t* tri_edge;  // 3 nt
+  const int8_t* tri_sign;   // 3 nt
+  const double2* J;
+  int64_t ldj;
+  const double2* rho;
+  int64_t ldr;
+  int ncol;
+  double kr, ki;            // background wavenumber
+  double2 jwmu;             // j omega mu0 mu_l
+  double2 inv_eps;          // 1 / (eps0 eps_l)
+  double2 inv_eta;          // 1 / eta_l
+  const double* pts;        // 3 per point
+  int64_t npts;
+  const double* inc;        // null, or 11 per column: khat (3), Re pol (3), Im pol (3), Re E0, Im E0
+  int nsplit;               // triangle ranges
+  double2* part;            // nsplit x ncol x npts x 6
+  double2* E;               // ncol x npts x 3
+  double2* H;
+};
+void launch_near_field(const NearArgs& a, hipStream_t st);
+
 // Quadrature rules into constant memory (once per device; later calls return at once).
 void fill_set_rules(const double w7[7], const double b7[7][3], const double b3[3][3], hipStream_t st);
 void launch_fill_L(const FillLArgs& a, const int32_t* near_t, const int32_t* near_s, int64_t npairs,

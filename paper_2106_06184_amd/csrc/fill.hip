@@ -622,6 +622,170 @@ __global__ void __launch_bounds__(256) k_far_field(FarArgs a) {
   }
 }
 
+// One block per (point, column group, triangle range): each thread forms the three moments of
+// its triangles once and applies them to every column of the group; fixed-order LDS tree per
+// column, so the result does not depend on scheduling.
+__global__ void __launch_bounds__(256) k_near_field(NearArgs a) {
+  const int64_t p = blockIdx.x;
+  const int c0 = int(blockIdx.y) * kNearFieldCols;
+  const int nc = min(kNearFieldCols, a.ncol - c0);
+  const int64_t per = (a.nt + a.nsplit - 1) / a.nsplit;
+  const int64_t tb = int64_t(blockIdx.z) * per;
+  const int64_t te = min(a.nt, tb + per);
+  const double* geo = a.geo;
+  const int64_t nt = a.nt;
+  const v3 r = mk(a.pts[3 * p], a.pts[3 * p + 1], a.pts[3 * p + 2]);
+  const cz k = {a.kr, a.ki};
+  const cz k2over8pi = cscale(1.0 / (8.0 * kPi), cmul(k, k));
+  const cz jwmu = {a.jwmu.x, a.jwmu.y}, inv_eps = {a.inv_eps.x, a.inv_eps.y};
+  cz acc[kNearFieldCols][6];
+#pragma unroll
+  for (int cl = 0; cl < kNearFieldCols; ++cl)
+#pragma unroll
+    for (int m = 0; m < 6; ++m) acc[cl][m] = {0.0, 0.0};
+  for (int64_t t = tb + threadIdx.x; t < te; t += blockDim.x) {
+    const v3 rr = r - G3(geo, nt, kGeoC, t);  // the point relative to the centroid
+    const double h = G(geo, nt, kGeoH, t), area = G(geo, nt, kGeoA, t);
+    v3 P[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) P[i] = G3(geo, nt, kGeoP + 3 * i, t);
+    const bool near = norm(rr) < kNearFactor * h;
+    int L = subdiv_level(a.kr, h);
+    if (near && L < kNearFieldLevel) L = kNearFieldLevel;
+    const int npiece = 1 << (2 * L);
+    const double wp = area / double(npiece);
+    cz I0 = {0.0, 0.0};
+    cv3 I1 = cvzero(), Ig = cvzero();
+    for (int jp = 0; jp < npiece; ++jp) {
+      double cc[3][3];
+      if (L > 0) subdiv_corners(L, jp, cc);
+      for (int q = 0; q < 7; ++q) {
+        const v3 x = L > 0 ? subdiv_point(cc, cB7[q], P) : G3(geo, nt, kGeoQ + 3 * q, t);
+        const v3 d = x - rr;  // r' - r
+        const double R2 = dot(d, d);
+        const double inv = 1.0 / sqrt(R2);
+        const double R = R2 * inv;
+        cz g, gg;
+        if (near) {
+          g = green_rem(a.kr, a.ki, R);
+          gg = grad_green_rem(a.kr, a.ki, R);
+        } else {
+          g = green<true>(a.kr, a.ki, R, inv);
+          gg = grad_green<true>(a.kr, a.ki, R, inv);
+        }
+        const double w = cW7[q] * wp;
+        g = cscale(w, g);
+        gg = cscale(-w, gg);
+        I0 = cadd(I0, g);
+        cv_axpy(I1, g, d);
+        cv_axpy(Ig, gg, d);
+      }
+    }
+    if (near) {
+      // grad G = [g_rem - 1/(4 pi R^3) - k^2/(8 pi R)] (r - r')
+      const StaticInts si = static_ints(rr, P[0], P[1], P[2], true);
+      I0.re += kInv4Pi * si.i1;
+      cv_axpy(I1, cz{kInv4Pi, 0.0}, si.iv);
+      cv_axpy(Ig, cz{-kInv4Pi, 0.0}, si.j3);
+      cv_axpy(Ig, k2over8pi, si.iv);
+    }
+    const double half_inv_area = 0.5 / area;
+#pragma unroll
+    for (int cl = 0; cl < kNearFieldCols; ++cl) {
+      if (cl >= nc) continue;
+      const int64_t c = c0 + cl;
+      // J on t = (C r' - P)/(2 A): C = sum s_i J_i, P = sum s_i J_i v_i;  W = C r - P
+      cz Cs = {0.0, 0.0};
+      cv3 Q = cvzero();
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const double2 j = a.J[c * a.ldj + a.tri_edge[3 * t + i]];
+        const cz js = cscale(double(a.tri_sign[3 * t + i]), cz{j.x, j.y});
+        Cs = cadd(Cs, js);
+        cv_axpy(Q, js, P[i]);
+      }
+      cv3 W;
+      W.x = csub(cscale(rr.x, Cs), Q.x);
+      W.y = csub(cscale(rr.y, Cs), Q.y);
+      W.z = csub(cscale(rr.z, Cs), Q.z);
+      const double2 rho = a.rho[c * a.ldr + t];
+      const cz qs = cscale(1.0 / area, cmul(inv_eps, cz{rho.x, rho.y}));
+      // E += -j omega mu (C I1 + W I0)/(2A) - (rho / (eps A)) Ig;  H += Ig x W / (2A)
+      const cz Ac[3] = {cscale(half_inv_area, cadd(cmul(Cs, I1.x), cmul(W.x, I0))),
+                        cscale(half_inv_area, cadd(cmul(Cs, I1.y), cmul(W.y, I0))),
+                        cscale(half_inv_area, cadd(cmul(Cs, I1.z), cmul(W.z, I0)))};
+      const cz Igc[3] = {Ig.x, Ig.y, Ig.z};
+      const cz Wc[3] = {W.x, W.y, W.z};
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        acc[cl][m] = csub(acc[cl][m], cadd(cmul(jwmu, Ac[m]), cmul(qs, Igc[m])));
+        const int m1 = (m + 1) % 3, m2 = (m + 2) % 3;
+        const cz hx = csub(cmul(Igc[m1], Wc[m2]), cmul(Igc[m2], Wc[m1]));
+        acc[cl][3 + m] = cadd(acc[cl][3 + m], cscale(half_inv_area, hx));
+      }
+    }
+  }
+  __shared__ double red[12][256];
+#pragma unroll
+  for (int cl = 0; cl < kNearFieldCols; ++cl) {
+    if (cl >= nc) break;  // nc is the same for the whole block
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+      red[2 * m][threadIdx.x] = acc[cl][m].re;
+      red[2 * m + 1][threadIdx.x] = acc[cl][m].im;
+    }
+    __syncthreads();
+    for (int half = 128; half > 0; half >>= 1) {
+      if (threadIdx.x < half)
+        for (int q = 0; q < 12; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + half];
+      __syncthreads();
+    }
+    if (threadIdx.x < 6) {
+      const int m = threadIdx.x;
+      a.part[((int64_t(blockIdx.z) * a.ncol + c0 + cl) * a.npts + p) * 6 + m] =
+          make_double2(red[2 * m][0], red[2 * m + 1][0]);
+    }
+    __syncthreads();
+  }
+}
+
+// Sum of the triangle ranges in order, plus the incident plane wave when given:
+// E_inc = E0 pol e^{-j k khat . r},  H_inc = khat x E_inc / eta.
+__global__ void k_near_field_finish(NearArgs a) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;  // c npts + p
+  if (i >= int64_t(a.ncol) * a.npts) return;
+  const int64_t c = i / a.npts, p = i - c * a.npts;
+  cz f[6];
+  for (int m = 0; m < 6; ++m) f[m] = {0.0, 0.0};
+  for (int s = 0; s < a.nsplit; ++s)
+    for (int m = 0; m < 6; ++m) {
+      const double2 v = a.part[((int64_t(s) * a.ncol + c) * a.npts + p) * 6 + m];
+      f[m] = cadd(f[m], cz{v.x, v.y});
+    }
+  if (a.inc) {
+    const double* w = a.inc + 11 * c;
+    const double ph = w[0] * a.pts[3 * p] + w[1] * a.pts[3 * p + 1] + w[2] * a.pts[3 * p + 2];
+    // e^{-j k ph} with k = kr + j ki: e^{ki ph} (cos(kr ph) - j sin(kr ph))
+    double sn, cs;
+    sincos(a.kr * ph, &sn, &cs);
+    const double ea = exp(a.ki * ph);
+    const cz e0 = cmul(cz{w[9], w[10]}, cz{ea * cs, -ea * sn});
+    cz Ei[3];
+    for (int m = 0; m < 3; ++m) Ei[m] = cmul(e0, cz{w[3 + m], w[6 + m]});
+    const cz ie = {a.inv_eta.x, a.inv_eta.y};
+    for (int m = 0; m < 3; ++m) {
+      const int m1 = (m + 1) % 3, m2 = (m + 2) % 3;
+      f[m] = cadd(f[m], Ei[m]);
+      const cz hx = csub(cscale(w[m1], Ei[m2]), cscale(w[m2], Ei[m1]));
+      f[3 + m] = cadd(f[3 + m], cmul(ie, hx));
+    }
+  }
+  for (int m = 0; m < 3; ++m) {
+    a.E[i * 3 + m] = make_double2(f[m].re, f[m].im);
+    a.H[i * 3 + m] = make_double2(f[3 + m].re, f[3 + m].im);
+  }
+}
+
 }  // namespace dev
 
 // ------------------------------------------------------------------ launchers
@@ -629,6 +793,19 @@ __global__ void __launch_bounds__(256) k_far_field(FarArgs a) {
 void launch_far_field(const FarArgs& a, int ncol, hipStream_t st) {
   if (a.ndir <= 0 || ncol <= 0) return;
   hipLaunchKernelGGL(dev::k_far_field, dim3(unsigned(a.ndir), unsigned(ncol)), dim3(256), 0, st, a);
+  BEM_HIP(hipGetLastError());
+}
+
+void launch_near_field(const NearArgs& a, hipStream_t st) {
+  if (a.npts <= 0 || a.ncol <= 0 || a.nt <= 0) return;
+  const int64_t groups = (a.ncol + kNearFieldCols - 1) / kNearFieldCols;
+  if (a.npts > 0x7fffffffLL || groups > 65535 || a.nsplit < 1 || a.nsplit > 65535)
+    throw Error(BEM_E_INVALID, "near field: launch shape out of range");
+  hipLaunchKernelGGL(dev::k_near_field, dim3(unsigned(a.npts), unsigned(groups), unsigned(a.nsplit)), dim3(256), 0,
+                     st, a);
+  BEM_HIP(hipGetLastError());
+  const int64_t n = int64_t(a.ncol) * a.npts;
+  hipLaunchKernelGGL(dev::k_near_field_finish, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, a);
   BEM_HIP(hipGetLastError());
 }
 

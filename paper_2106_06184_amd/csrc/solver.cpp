@@ -1308,6 +1308,26 @@ void apply_block(OpObj& op, int block, const double2* x, double2* y, int64_t nrh
   if (R > 1) BEM_HIP(hipStreamSynchronize(st));
 }
 
+namespace {
+// The equivalent configuration of a solution (eq. AEFIEeqvdis, same E): e = E / eta0 in place,
+// r_in = (K~_l + I_x/2) e, [u; w] = M_eq^-1 [r_in; 0] in float64 into wv.sol, and the
+// differential current J_delta = H - u / (j k0) in place of h (eq. diffsourcesdis).
+void equivalent_solve(OpObj& op, const WorkView& wv, double2* e, double2* h, hipStream_t st) {
+  const int R = wv.R;
+  const int64_t ne = op.ne, L = wv.ld;
+  launch_axpby(ne, c2(1.0 / kEta0), e, c2(0.0), nullptr, e, st, R, L, 0, L);
+  std::vector<GemvDesc> ds;
+  for (int64_t o = 0; o < op.nobj; ++o) {
+    const int64_t e0 = op.obj_edge[o], neo = op.obj_edge[o + 1] - e0;
+    ds.push_back(with_ld(desc(op.K_bg[o], false, 0, 0, neo, neo, e + e0, wv.rin + e0, c2(1.0), 0), L, L));
+  }
+  products(op, ds, wv, st);
+  launch_spmv(op.ix_ptr, op.ix_idx, op.ix_val, ne, e, c2(0.5), wv.rin, 1, st, R, L, L);
+  nested_from_rin(op, wv, false, op.inner_tol, st);
+  launch_axpby(ne, c2(1.0), h, c2(-cd(1.0) / cd(0.0, op.k0)), wv.sol, h, st, R, L, L, L);
+}
+}  // namespace
+
 void far_field(OpObj& op, const bem_c64* H, const bem_c64* E, int64_t nexc, const double* rhat, int64_t ndir,
                bem_c64* N, double* rcs, hipStream_t st) {
   if (op.formulation != BEM_FORM_SLDM)
@@ -1336,18 +1356,7 @@ void far_field(OpObj& op, const bem_c64* H, const bem_c64* E, int64_t nexc, cons
       BEM_HIP(hipMemcpyAsync(e + c * L, E + (c0 + c) * ne, sizeof(double2) * ne, hipMemcpyHostToDevice, st));
       BEM_HIP(hipMemcpyAsync(h + c * L, H + (c0 + c) * ne, sizeof(double2) * ne, hipMemcpyHostToDevice, st));
     }
-    // e = E / eta0; r_in = (K~_l + I_x/2) e; [u; w] = M_eq^-1 [r_in; 0] (float64)
-    launch_axpby(ne, c2(1.0 / kEta0), e, c2(0.0), nullptr, e, st, R, L, 0, L);
-    std::vector<GemvDesc> ds;
-    for (int64_t o = 0; o < op.nobj; ++o) {
-      const int64_t e0 = op.obj_edge[o], neo = op.obj_edge[o + 1] - e0;
-      ds.push_back(with_ld(desc(op.K_bg[o], false, 0, 0, neo, neo, e + e0, wv.rin + e0, c2(1.0), 0), L, L));
-    }
-    products(op, ds, wv, st);
-    launch_spmv(op.ix_ptr, op.ix_idx, op.ix_val, ne, e, c2(0.5), wv.rin, 1, st, R, L, L);
-    nested_from_rin(op, wv, false, op.inner_tol, st);
-    // J_delta = H - H_eq = H - u / (j k0)
-    launch_axpby(ne, c2(1.0), h, c2(-cd(1.0) / cd(0.0, op.k0)), wv.sol, h, st, R, L, L, L);
+    equivalent_solve(op, wv, e, h, st);
     FarArgs fa{op.geo, op.nt, op.tri_edge, op.tri_sign, h, L, op.kbg.real(), op.kbg.imag(), d_rhat, ndir, out};
     launch_far_field(fa, R, st);
     hN.resize(size_t(3 * ndir) * R);
@@ -1367,6 +1376,83 @@ void far_field(OpObj& op, const bem_c64* H, const bem_c64* E, int64_t nexc, cons
         }
         if (rcs) rcs[(c0 + c) * ndir + d] = pref * s;
       }
+  }
+}
+
+void near_field(OpObj& op, const bem_c64* H, const bem_c64* E, const bem_c64* rho, int64_t nexc,
+                const bem_excitation* exc, const double* pts, int64_t npts, bem_c64* Eout, bem_c64* Hout,
+                hipStream_t st) {
+  if (op.formulation != BEM_FORM_SLDM)
+    throw Error(BEM_E_INVALID, "the near field is radiated by the differential sources of the proposed formulation");
+  if (nexc <= 0 || npts < 0 || !H || !E || !rho || (npts > 0 && !pts))
+    throw Error(BEM_E_INVALID, "invalid near-field arguments");
+  if (npts == 0) return;
+  for (int64_t i = 0; i < 3 * npts; ++i)
+    if (!std::isfinite(pts[i])) throw Error(BEM_E_INVALID, "non-finite observation point");
+  std::vector<double> inc;
+  if (exc) {
+    inc.resize(size_t(11 * nexc));
+    for (int64_t c = 0; c < nexc; ++c) {
+      const bem_excitation& x = exc[c];
+      if (x.kind != BEM_EXC_PLANE_WAVE)
+        throw Error(BEM_E_INVALID, "the incident field is defined for plane waves only");
+      double* w = &inc[size_t(11 * c)];
+      for (int i = 0; i < 3; ++i) {
+        w[i] = x.khat[i];
+        w[3 + i] = x.pol[i].re;
+        w[6 + i] = x.pol[i].im;
+      }
+      w[9] = x.amp.re;
+      w[10] = x.amp.im;
+    }
+  }
+  const int64_t ne = op.ne, nt = op.nt;
+  const cd eps_l = kEps0 * op.eps_bg;
+  const cd jwmu(0.0, op.k0 * kC0 * kMu0 * op.mu_bg);
+  const cd inv_eps = 1.0 / eps_l;
+  const cd inv_eta = 1.0 / (kEta0 * std::sqrt(op.mu_bg / op.eps_bg));
+  DevArena tmp(op.ctx);
+  tmp.set_stream(st);
+  double* d_pts = tmp.alloc<double>(size_t(3 * npts));
+  BEM_HIP(hipMemcpyAsync(d_pts, pts, sizeof(double) * 3 * npts, hipMemcpyHostToDevice, st));
+  double* d_inc = nullptr;
+  if (exc) {
+    d_inc = tmp.alloc<double>(inc.size());
+    BEM_HIP(hipMemcpyAsync(d_inc, inc.data(), sizeof(double) * inc.size(), hipMemcpyHostToDevice, st));
+  }
+  // triangle ranges: about 2048 blocks in all, each range at least 512 triangles
+  for (int64_t c0 = 0; c0 < nexc; c0 += 256) {
+    const int R = int(std::min<int64_t>(256, nexc - c0));
+    const WorkView wv = R == 1 ? views(op) : batch_views(op, tmp, R);
+    const int64_t L = wv.ld;
+    double2* e = tmp.alloc<double2>(size_t(L) * R);
+    double2* h = tmp.alloc<double2>(size_t(L) * R);
+    double2* q = tmp.alloc<double2>(size_t(nt) * R);
+    for (int c = 0; c < R; ++c) {
+      BEM_HIP(hipMemcpyAsync(e + c * L, E + (c0 + c) * ne, sizeof(double2) * ne, hipMemcpyHostToDevice, st));
+      BEM_HIP(hipMemcpyAsync(h + c * L, H + (c0 + c) * ne, sizeof(double2) * ne, hipMemcpyHostToDevice, st));
+      BEM_HIP(hipMemcpyAsync(q + c * nt, rho + (c0 + c) * nt, sizeof(double2) * nt, hipMemcpyHostToDevice, st));
+    }
+    equivalent_solve(op, wv, e, h, st);
+    // rho_delta = rho - rho_eq, rho_eq = B w / c0 (w: the reduced charges of the equivalent solve)
+    double2* qeq = tmp.alloc<double2>(size_t(nt) * R);
+    launch_expand_charge(wv.sol + ne, qeq, op.obj_tri_d, op.nobj, c2(1.0 / kC0), st, R, L, nt);
+    launch_axpby(nt, c2(1.0), q, c2(-1.0), qeq, q, st, R, nt, nt, nt);
+    const int64_t groups = (R + kNearFieldCols - 1) / kNearFieldCols;
+    const int64_t want = (2048 + npts * groups - 1) / (npts * groups);
+    const int nsplit = int(std::max<int64_t>(1, std::min<int64_t>({want, (nt + 511) / 512, 64})));
+    double2* part = tmp.alloc<double2>(size_t(nsplit) * R * npts * 6);
+    double2* dE = tmp.alloc<double2>(size_t(R) * npts * 3);
+    double2* dH = tmp.alloc<double2>(size_t(R) * npts * 3);
+    NearArgs na{op.geo, nt, op.tri_edge, op.tri_sign, h, L, q, nt, R, op.kbg.real(), op.kbg.imag(),
+                c2(jwmu), c2(inv_eps), c2(inv_eta), d_pts, npts, d_inc ? d_inc + 11 * c0 : nullptr, nsplit,
+                part, dE, dH};
+    launch_near_field(na, st);
+    if (Eout)
+      BEM_HIP(hipMemcpyAsync(Eout + c0 * npts * 3, dE, sizeof(double2) * R * npts * 3, hipMemcpyDeviceToHost, st));
+    if (Hout)
+      BEM_HIP(hipMemcpyAsync(Hout + c0 * npts * 3, dH, sizeof(double2) * R * npts * 3, hipMemcpyDeviceToHost, st));
+    BEM_HIP(hipStreamSynchronize(st));
   }
 }
 
