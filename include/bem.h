@@ -282,6 +282,9 @@ typedef struct {
   int n_products;               /* applications of the final system */
   double rel_residual;          /* final float64 relative residual (worst excitation) */
   double seconds;
+  int graph_steps;              /* Arnoldi steps whose product was replayed from a captured HIP
+                                   graph (small operators without a nested GMRES; BEM_GRAPH=0
+                                   in the environment turns the capture off) */
 } bem_solve_info;
 
 /* Solve eq. finalsystem for nexc excitations (right-hand side of eq.

@@ -27,6 +27,7 @@
 
 #include "linalg.h"
 #include "prof.h"
+#include "tune.h"
 
 namespace bem {
 namespace dev {
@@ -52,11 +53,13 @@ __global__ void k_build_B(const double2* __restrict__ X, int64_t ldx, int64_t nc
   }
 }
 
-// Tile decode shared by both kernels: blockIdx.x -> (row tile, column tile, K split).
+// Tile decode shared by both kernels: blockIdx.x -> (row tile, column tile, K split).  xcd = 1
+// deals consecutive tiles to one XCD (workgroups go round-robin over the 8 XCDs), xcd = 0 keeps
+// the launch order; either way every tile is computed the same.
 struct TileIdx {
   int64_t tm, tn, ks;
 };
-__device__ __forceinline__ TileIdx tile_of(int64_t ntn, int64_t S) {
+__device__ __forceinline__ TileIdx tile_of(int64_t ntn, int64_t S, int xcd) {
   const int64_t nwg = int64_t(gridDim.x), p = blockIdx.x;
   TileIdx t;
   if (S > 1) {
@@ -67,7 +70,7 @@ __device__ __forceinline__ TileIdx tile_of(int64_t ntn, int64_t S) {
     return t;
   }
   int64_t logical = p;
-  if (nwg % 8 == 0) logical = (p % 8) * (nwg / 8) + p / 8;
+  if (xcd && nwg % 8 == 0) logical = (p % 8) * (nwg / 8) + p / 8;
   t.tm = logical / ntn;
   t.tn = logical % ntn;
   t.ks = 0;
@@ -123,12 +126,12 @@ __global__ void __launch_bounds__(256) k_gemm_f32(const float* __restrict__ A, i
                                                   int64_t ldb, int64_t M, int64_t K, int64_t K16, int64_t kc,
                                                   int64_t ntn, int64_t S, double* __restrict__ P,
                                                   double2* __restrict__ Y, int64_t ldy, int64_t R, double2 alpha,
-                                                  int accumulate) {
+                                                  int accumulate, int xcd) {
   constexpr int WM = 4 / WN, TM = WM * 64, TN = WN * JN * 32;
   constexpr int EA = TM * BK / 256, EB = TN * BK / 256;  // A and B values per thread per K step
   __shared__ float As[2][BK][TM + PADA];
   __shared__ float Bs[2][BK][TN + PADB];
-  const TileIdx ti = tile_of(ntn, S);
+  const TileIdx ti = tile_of(ntn, S, xcd);
   const int64_t m0 = ti.tm * TM, n0 = ti.tn * TN;
   const int64_t kbeg = ti.ks * kc, kend = min(K16, kbeg + kc);
   const int tid = threadIdx.x;
@@ -254,12 +257,12 @@ __global__ void __launch_bounds__(256) k_gemm_f64(const TA* __restrict__ A, int6
                                                   const double* __restrict__ Bm, int64_t ldb, int64_t M, int64_t K,
                                                   int64_t K16, int64_t kc, int64_t ntn, int64_t S,
                                                   double* __restrict__ P, double2* __restrict__ Y, int64_t ldy,
-                                                  int64_t R, double2 alpha, int accumulate) {
+                                                  int64_t R, double2 alpha, int accumulate, int xcd) {
   constexpr int WM = 4 / WN, TM = WM * 32, TN = WN * JN * 16;
   constexpr int EA = TM * DK / 256, EB = TN * DK / 256;
   __shared__ double As[2][DK][TM + DPAD];
   __shared__ double Bs[2][DK][TN + DPAD];
-  const TileIdx ti = tile_of(ntn, S);
+  const TileIdx ti = tile_of(ntn, S, xcd);
   const int64_t m0 = ti.tm * TM, n0 = ti.tn * TN;
   const int64_t kbeg = ti.ks * kc, kend = min(K16, kbeg + kc);
   const int tid = threadIdx.x;
@@ -303,11 +306,17 @@ __global__ void __launch_bounds__(256) k_gemm_f64(const TA* __restrict__ A, int6
       for (int e = 0; e < EA; ++e) ra[e] = 0.0;
     }
     const double* bsrc = Bm + (k0 + b_k) * ldb + n0 + b_col;
+    if constexpr (EB % 2 == 0) {
 #pragma unroll
-    for (int e = 0; e < EB; e += 2) {
-      const double2 u = *reinterpret_cast<const double2*>(bsrc + e);
-      rb[e] = u.x;
-      rb[e + 1] = u.y;
+      for (int e = 0; e < EB; e += 2) {
+        const double2 u = *reinterpret_cast<const double2*>(bsrc + e);
+        rb[e] = u.x;
+        rb[e + 1] = u.y;
+      }
+    } else {
+      // odd counts (16- and 48-column tiles) start at odd columns: single loads
+#pragma unroll
+      for (int e = 0; e < EB; ++e) rb[e] = bsrc[e];
     }
   };
   auto store_tile = [&](int buf) {
@@ -358,19 +367,125 @@ __global__ void __launch_bounds__(256) k_gemm_f64(const TA* __restrict__ A, int6
 }  // namespace dev
 
 namespace {
-// Work decomposition of one product: the N tile (real columns) for 2R columns, the split of K.
+// Work decomposition of one product.  The N tile (real columns) is the smallest one of the path
+// that holds the 2R columns (float64: multiples of 16 up to 128 except 80 and 112; float32:
+// 32, 64, 96, 128).  Each N tile has one or two variants (waves along N x MFMA blocks per
+// wave, so different row tiles); the first is canonical and its row tile alone sets the K
+// split, so all variants sum the same partial products in the same order and agree bitwise.
 constexpr int64_t kTargetWorkgroups = 2048;
 constexpr int64_t kMaxSplit = 16;
-int ntile_for(int64_t nrhs) { return 2 * nrhs <= 32 ? 32 : (2 * nrhs <= 64 ? 64 : 128); }
+int ntile_f64(int64_t nrhs) {
+  const int64_t c = 2 * nrhs;
+  for (int t : {16, 32, 48, 64, 96})
+    if (c <= t) return t;
+  return 128;
+}
+int ntile_f32(int64_t nrhs) {
+  const int64_t c = 2 * nrhs;
+  for (int t : {32, 64, 96})
+    if (c <= t) return t;
+  return 128;
+}
+int64_t ldb_of(int64_t nrhs, int tn) { return (2 * nrhs + tn - 1) / tn * tn; }
+// the larger leading dimension of the two paths (workspace sizing)
+int64_t ldb_for(int64_t nrhs) { return ldb_of(nrhs, ntile_f32(nrhs)); }
 int64_t split_for(int64_t tiles, int64_t K16) {
   int64_t S = 1;
   // at least 8 K steps of 16 per split
   while (S < kMaxSplit && tiles * S < kTargetWorkgroups && K16 / (2 * S * dev::BK) >= 8) S *= 2;
   return S;
 }
-int64_t ldb_for(int64_t nrhs) {
-  const int64_t tn = ntile_for(nrhs);
-  return (2 * nrhs + tn - 1) / tn * tn;
+struct Var {
+  int wn, jn;
+};
+// variants per N tile, canonical first
+std::vector<Var> vars_f64(int tn) {
+  switch (tn) {
+    case 16: return {{1, 1}};
+    case 32: return {{1, 2}, {2, 1}};
+    case 48: return {{1, 3}};
+    case 64: return {{1, 4}, {2, 2}};
+    case 96: return {{2, 3}};
+    default: return {{2, 4}, {4, 2}};
+  }
+}
+std::vector<Var> vars_f32(int tn) {
+  switch (tn) {
+    case 32: return {{1, 1}};
+    case 64: return {{1, 2}, {2, 1}};
+    case 96: return {{1, 3}};
+    default: return {{2, 2}, {1, 4}};
+  }
+}
+
+struct GemmLaunch {
+  dim3 g;
+  int64_t lda, ldb, K, K16, kc, ntn, S;
+  double* P;
+  int xcd;
+};
+
+template <typename TA, bool AL>
+void launch_f64_variant(const Var& v, const GemmLaunch& l, const GemmDesc& d, const double* Bm, hipStream_t st) {
+  const TA* A = static_cast<const TA*>(d.A);
+#define BEM_G64(WN, JN)                                                                                              \
+  hipLaunchKernelGGL((dev::k_gemm_f64<TA, AL, WN, JN>), l.g, dim3(256), 0, st, A, l.lda, Bm, l.ldb, d.rows, l.K,  \
+                     l.K16, l.kc, l.ntn, l.S, l.P, d.Y, d.ldy, d.nrhs, d.alpha, d.accumulate, l.xcd)
+  const int code = v.wn * 10 + v.jn;
+  if constexpr (AL) {
+    switch (code) {
+      case 11: BEM_G64(1, 1); break;
+      case 12: BEM_G64(1, 2); break;
+      case 21: BEM_G64(2, 1); break;
+      case 13: BEM_G64(1, 3); break;
+      case 14: BEM_G64(1, 4); break;
+      case 22: BEM_G64(2, 2); break;
+      case 23: BEM_G64(2, 3); break;
+      case 24: BEM_G64(2, 4); break;
+      case 42: BEM_G64(4, 2); break;
+      default: throw Error(BEM_E_INVALID, "no such float64 GEMM variant");
+    }
+  } else {
+    switch (code) {  // unaligned operands: canonical variants only
+      case 11: BEM_G64(1, 1); break;
+      case 12: BEM_G64(1, 2); break;
+      case 13: BEM_G64(1, 3); break;
+      case 14: BEM_G64(1, 4); break;
+      case 23: BEM_G64(2, 3); break;
+      case 24: BEM_G64(2, 4); break;
+      default: throw Error(BEM_E_INVALID, "no such float64 GEMM variant");
+    }
+  }
+#undef BEM_G64
+}
+
+template <bool AL>
+void launch_f32_variant(const Var& v, const GemmLaunch& l, const GemmDesc& d, const float* Bm, hipStream_t st) {
+  const float* A = static_cast<const float*>(d.A);
+#define BEM_G32(WN, JN)                                                                                        \
+  hipLaunchKernelGGL((dev::k_gemm_f32<AL, WN, JN>), l.g, dim3(256), 0, st, A, l.lda, Bm, l.ldb, d.rows, l.K, \
+                     l.K16, l.kc, l.ntn, l.S, l.P, d.Y, d.ldy, d.nrhs, d.alpha, d.accumulate, l.xcd)
+  const int code = v.wn * 10 + v.jn;
+  if constexpr (AL) {
+    switch (code) {
+      case 11: BEM_G32(1, 1); break;
+      case 12: BEM_G32(1, 2); break;
+      case 21: BEM_G32(2, 1); break;
+      case 13: BEM_G32(1, 3); break;
+      case 22: BEM_G32(2, 2); break;
+      case 14: BEM_G32(1, 4); break;
+      default: throw Error(BEM_E_INVALID, "no such float32 GEMM variant");
+    }
+  } else {
+    switch (code) {
+      case 11: BEM_G32(1, 1); break;
+      case 12: BEM_G32(1, 2); break;
+      case 13: BEM_G32(1, 3); break;
+      case 22: BEM_G32(2, 2); break;
+      default: throw Error(BEM_E_INVALID, "no such float32 GEMM variant");
+    }
+  }
+#undef BEM_G32
 }
 }  // namespace
 
@@ -386,70 +501,82 @@ size_t gemm_workspace_bytes(int64_t n, int64_t nrhs) {
 
 void launch_gemm(const GemmDesc& d, void* ws, size_t ws_bytes, hipStream_t st) {
   if (d.rows <= 0 || d.nrhs <= 0) return;
-  const int64_t K = 2 * d.cols;
-  const int64_t K16 = (K + dev::BK - 1) / dev::BK * dev::BK;
-  const int tn = ntile_for(d.nrhs);
-  const int64_t ldb = ldb_for(d.nrhs), ntn = ldb / tn;
-  const int64_t lda = 2 * d.lda;  // real leading dimension
   // fp32 == 2: float32 entries on the float64 kernel (float64 arithmetic)
   const bool mfma32 = d.fp32 == 1;
-  const size_t bbytes = size_t(K16) * ldb * (mfma32 ? sizeof(float) : sizeof(double));
-  const int64_t tm = mfma32 ? (tn == 128 ? 128 : 256) : (tn == 128 ? 64 : 128);
-  const int64_t ntm = (d.rows + tm - 1) / tm;
-  const int64_t S = split_for(ntm * ntn, K16);
-  const int64_t kc = (K16 / S + dev::BK - 1) / dev::BK * dev::BK;
+  const int tn = mfma32 ? ntile_f32(d.nrhs) : ntile_f64(d.nrhs);
+  GemmLaunch l;
+  l.K = 2 * d.cols;
+  l.K16 = (l.K + dev::BK - 1) / dev::BK * dev::BK;
+  l.ldb = ldb_of(d.nrhs, tn);
+  l.ntn = l.ldb / tn;
+  l.lda = 2 * d.lda;  // real leading dimension
+  const size_t esz = mfma32 ? sizeof(float) : (d.fp32 ? sizeof(float) : sizeof(double));
+  const bool aligned = mfma32 ? ((reinterpret_cast<uintptr_t>(d.A) | uintptr_t(l.lda * 4)) & 15) == 0
+                              : ((reinterpret_cast<uintptr_t>(d.A) | uintptr_t(l.lda * esz)) & (2 * esz - 1)) == 0;
+  std::vector<Var> vars = mfma32 ? vars_f32(tn) : vars_f64(tn);
+  if (!aligned) vars.resize(1);
+  auto tm_of = [&](const Var& v) -> int64_t { return (4 / v.wn) * (mfma32 ? 64 : 32); };
+  const int64_t ntm0 = (d.rows + tm_of(vars[0]) - 1) / tm_of(vars[0]);
+  l.S = split_for(ntm0 * l.ntn, l.K16);
+  l.kc = (l.K16 / l.S + dev::BK - 1) / dev::BK * dev::BK;
+  const size_t bbytes = size_t(l.K16) * l.ldb * (mfma32 ? sizeof(float) : sizeof(double));
   const size_t poff = (bbytes + 255) / 256 * 256;
-  const size_t need = poff + (S > 1 ? size_t(S) * d.rows * ldb * sizeof(double) : 0);
+  const size_t need = poff + (l.S > 1 ? size_t(l.S) * d.rows * l.ldb * sizeof(double) : 0);
   if (need > ws_bytes) throw Error(BEM_E_INVALID, "GEMM workspace too small");
-  double* P = reinterpret_cast<double*>(static_cast<char*>(ws) + poff);
-  const dim3 g(unsigned(ntm * ntn * S));
+  l.P = reinterpret_cast<double*>(static_cast<char*>(ws) + poff);
+  // candidates: the variants, and with S = 1 the tile-to-XCD mapping on and off
+  const int nx = l.S == 1 ? 2 : 1;
+  const int ncand = int(vars.size()) * nx;
+  const uint64_t key = tune_key(mfma32 ? 1 : (d.fp32 ? 2 : 3),
+                                {tn, l.S, aligned ? 1 : 0, log2_bucket(d.rows), log2_bucket(l.K16)});
   // the split-K sum belongs to the product (inside its timing scope)
   auto reduce = [&]() {
-    if (S <= 1) return;
+    if (l.S <= 1) return;
     const int64_t n = d.rows * d.nrhs;
-    hipLaunchKernelGGL(dev::k_splitk_reduce, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, P, d.rows, ldb, S,
-                       d.nrhs, d.Y, d.ldy, d.alpha, d.accumulate);
+    hipLaunchKernelGGL(dev::k_splitk_reduce, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, l.P, d.rows, l.ldb,
+                       l.S, d.nrhs, d.Y, d.ldy, d.alpha, d.accumulate);
     BEM_HIP(hipGetLastError());
+  };
+  auto shape = [&](int cand) {
+    const Var& v = vars[cand / nx];
+    l.xcd = (cand % nx) == 0 ? 1 : 0;
+    const int64_t ntm = (d.rows + tm_of(v) - 1) / tm_of(v);
+    l.g = dim3(unsigned(ntm * l.ntn * l.S));
+    return v;
   };
   if (!mfma32) {
     double* Bm = static_cast<double*>(ws);
-    hipLaunchKernelGGL(dev::k_build_B64, dim3(unsigned((ldb + 255) / 256), unsigned(std::min<int64_t>(K16, 32768))), dim3(256), 0, st, d.X,
-                       d.ldx, d.cols, d.nrhs, Bm, ldb, K16);
+    hipLaunchKernelGGL(dev::k_build_B64, dim3(unsigned((l.ldb + 255) / 256), unsigned(std::min<int64_t>(l.K16, 32768))),
+                       dim3(256), 0, st, d.X, d.ldx, d.cols, d.nrhs, Bm, l.ldb, l.K16);
     BEM_HIP(hipGetLastError());
     ProfScope ps(st, KC_GEMM_F64, double(d.rows) * d.cols * (d.fp32 ? 8.0 : 16.0),
                  8.0 * double(d.rows) * d.cols * d.nrhs);
-#define BEM_G64(TA, AL, WN, JN)                                                                                      \
-  hipLaunchKernelGGL((dev::k_gemm_f64<TA, AL, WN, JN>), g, dim3(256), 0, st, static_cast<const TA*>(d.A), lda, Bm, \
-                     ldb, d.rows, K, K16, kc, ntn, S, P, d.Y, d.ldy, d.nrhs, d.alpha, d.accumulate)
-#define BEM_G64T(TA, AL) \
-  if (tn == 128) BEM_G64(TA, AL, 2, 4); else if (tn == 64) BEM_G64(TA, AL, 1, 4); else BEM_G64(TA, AL, 1, 2)
-    if (!d.fp32) {
-      const bool aligned = ((reinterpret_cast<uintptr_t>(d.A) | uintptr_t(lda * 8)) & 15) == 0;
-      if (aligned) { BEM_G64T(double, true); } else { BEM_G64T(double, false); }
-    } else {
-      const bool aligned = ((reinterpret_cast<uintptr_t>(d.A) | uintptr_t(lda * 4)) & 7) == 0;
-      if (aligned) { BEM_G64T(float, true); } else { BEM_G64T(float, false); }
+    {
+      TuneScope ts(key, ncand, st);
+      const Var v = shape(ts.variant());
+      if (!d.fp32) {
+        if (aligned) launch_f64_variant<double, true>(v, l, d, Bm, st);
+        else launch_f64_variant<double, false>(v, l, d, Bm, st);
+      } else {
+        if (aligned) launch_f64_variant<float, true>(v, l, d, Bm, st);
+        else launch_f64_variant<float, false>(v, l, d, Bm, st);
+      }
+      BEM_HIP(hipGetLastError());
     }
-#undef BEM_G64T
-#undef BEM_G64
-    BEM_HIP(hipGetLastError());
     reduce();
   } else {
     float* Bm = static_cast<float*>(ws);
-    hipLaunchKernelGGL(dev::k_build_B, dim3(unsigned((ldb + 255) / 256), unsigned(std::min<int64_t>(K16, 32768))), dim3(256), 0, st, d.X, d.ldx,
-                       d.cols, d.nrhs, Bm, ldb, K16);
+    hipLaunchKernelGGL(dev::k_build_B, dim3(unsigned((l.ldb + 255) / 256), unsigned(std::min<int64_t>(l.K16, 32768))),
+                       dim3(256), 0, st, d.X, d.ldx, d.cols, d.nrhs, Bm, l.ldb, l.K16);
     BEM_HIP(hipGetLastError());
-    const float* A = static_cast<const float*>(d.A);
-    const bool aligned = ((reinterpret_cast<uintptr_t>(A) | uintptr_t(lda * 4)) & 15) == 0;
     ProfScope ps(st, KC_GEMM_F32, double(d.rows) * d.cols * 8.0, 8.0 * double(d.rows) * d.cols * d.nrhs);
-#define BEM_G32(AL, WN, JN)                                                                                      \
-  hipLaunchKernelGGL((dev::k_gemm_f32<AL, WN, JN>), g, dim3(256), 0, st, A, lda, Bm, ldb, d.rows, K, K16, kc, ntn, \
-                     S, P, d.Y, d.ldy, d.nrhs, d.alpha, d.accumulate)
-    if (tn == 128) { if (aligned) BEM_G32(true, 2, 2); else BEM_G32(false, 2, 2); }
-    else if (tn == 64) { if (aligned) BEM_G32(true, 1, 2); else BEM_G32(false, 1, 2); }
-    else { if (aligned) BEM_G32(true, 1, 1); else BEM_G32(false, 1, 1); }
-#undef BEM_G32
-    BEM_HIP(hipGetLastError());
+    {
+      TuneScope ts(key, ncand, st);
+      const Var v = shape(ts.variant());
+      if (aligned) launch_f32_variant<true>(v, l, d, Bm, st);
+      else launch_f32_variant<false>(v, l, d, Bm, st);
+      BEM_HIP(hipGetLastError());
+    }
     reduce();
   }
 }

@@ -12,16 +12,17 @@
 
 #include "linalg.h"
 #include "prof.h"
+#include "tune.h"
 
 namespace bem {
 namespace dev {
 
 constexpr int kWave = 64;
-// A block of the grouped GEMV owns kRowsPerBlock rows of one matrix; its kWavesPerBlock waves
-// split the columns (every wave reads all the rows over a quarter of the columns), so that the
-// grid has enough waves for the HBM latency and x is read once per block from L2.
+// A block of the grouped GEMV owns RPB rows of one matrix (4, 8 or 16, chosen per problem class
+// by the launch tuner: every row is summed the same way whatever RPB is); its kWavesPerBlock
+// waves split the columns (every wave reads all the rows over a quarter of the columns), so that
+// the grid has enough waves for the HBM latency and x is read once per block from L2.
 constexpr int kWavesPerBlock = 4;
-constexpr int kRowsPerBlock = 8;
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -193,14 +194,15 @@ __device__ __forceinline__ void rows_f32(const float2* __restrict__ A, int64_t l
 }
 
 
+template <int RPB>
 __global__ void __launch_bounds__(256) k_gemv_grouped(GemvPack pack) {
   const int64_t b = blockIdx.x;
   int di = 0;
   while (di + 1 < pack.n && pack.d[di + 1].tile0 <= b) ++di;
   const GemvDev& d = pack.d[di];
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  const int64_t row0 = (b - d.tile0) * kRowsPerBlock;
-  constexpr int R = kRowsPerBlock;
+  const int64_t row0 = (b - d.tile0) * RPB;
+  constexpr int R = RPB;
   double yr[R], yi[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) yr[r] = yi[r] = 0.0;
@@ -765,22 +767,33 @@ __global__ void k_scatter_cols(const double2* __restrict__ U, int64_t ldu, doubl
 // ----------------------------------------------------------------- launchers
 
 void launch_gemv_grouped(const GemvDesc* host_descs, int n, hipStream_t st) {
+  static const int kRpb[3] = {8, 4, 16};  // candidates, canonical first
   for (int base = 0; base < n; base += kMaxGroup) {
     GemvPack pack{};
     pack.n = std::min(kMaxGroup, n - base);
-    int64_t tiles = 0;
+    int64_t rows = 0, cols = 0;
     for (int i = 0; i < pack.n; ++i) {
       const GemvDesc& h = host_descs[base + i];
       pack.d[i] = GemvDev{h.A,       h.A2,      h.lda,      h.lda2,     h.rows,       h.cols, h.x, h.x2, h.y,
-                          h.alpha.x, h.alpha.y, h.alpha2.x, h.alpha2.y, h.accumulate, h.fp32, tiles};
-      tiles += (pack.d[i].rows + dev::kRowsPerBlock - 1) / dev::kRowsPerBlock;
+                          h.alpha.x, h.alpha.y, h.alpha2.x, h.alpha2.y, h.accumulate, h.fp32, 0};
+      rows += h.rows;
+      cols = std::max(cols, h.cols);
     }
-    if (tiles == 0) continue;
+    if (rows == 0) continue;
     double bytes = 0;
     for (int i = 0; i < pack.n; ++i)
       bytes += double(pack.d[i].rows) * pack.d[i].cols * (pack.d[i].fp32 ? 8.0 : 16.0) * (pack.d[i].A2 ? 2 : 1);
     ProfScope ps(st, pack.d[0].fp32 ? KC_GEMV_F32 : KC_GEMV_F64, bytes, bytes / (pack.d[0].fp32 ? 8.0 : 16.0));
-    hipLaunchKernelGGL(dev::k_gemv_grouped, dim3(unsigned(tiles)), dim3(256), 0, st, pack);
+    TuneScope ts(tune_key(8, {pack.d[0].fp32, pack.n, log2_bucket(rows), log2_bucket(cols)}), 3, st);
+    const int rpb = kRpb[ts.variant()];
+    int64_t tiles = 0;
+    for (int i = 0; i < pack.n; ++i) {
+      pack.d[i].tile0 = tiles;
+      tiles += (pack.d[i].rows + rpb - 1) / rpb;
+    }
+    if (rpb == 4) hipLaunchKernelGGL(dev::k_gemv_grouped<4>, dim3(unsigned(tiles)), dim3(256), 0, st, pack);
+    else if (rpb == 16) hipLaunchKernelGGL(dev::k_gemv_grouped<16>, dim3(unsigned(tiles)), dim3(256), 0, st, pack);
+    else hipLaunchKernelGGL(dev::k_gemv_grouped<8>, dim3(unsigned(tiles)), dim3(256), 0, st, pack);
     BEM_HIP(hipGetLastError());
   }
 }

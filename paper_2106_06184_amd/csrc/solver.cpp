@@ -13,11 +13,13 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 
 #include "ctx.h"
 #include "dense.h"
+#include "prof.h"
 
 namespace bem {
 
@@ -1722,6 +1724,7 @@ struct BResult {
   std::vector<double> relres;    // estimated relative residual of each column
   std::vector<char> converged;
   int products = 0;              // batched operator products
+  int graph_steps = 0;           // Arnoldi steps replayed from a captured graph
 };
 
 // Restarted GMRES (CGS2 Arnoldi, complex Givens, float64) for the R0 columns of B (n x R0,
@@ -1739,9 +1742,69 @@ struct BResult {
 // restarted cycle works on the slowly converging components, whose large coefficients take the
 // cruder products' error whole (float32 cycles after a restart made no true progress on the
 // 5120-triangle sphere).  Restart residuals and the solution update use A and M.
+// Captured step products: the launch chain of one Arnoldi step's product A (M x), recorded once
+// per (column count, precision) into a HIP graph on fixed buffers (w.U in, w.Z between, w.T
+// out) and replayed between two device copies.  For small operators the chain (20-30 launches
+// of a few microseconds each) is bound by launch overhead; the replay submits it at once.  The
+// same kernels run with the same arguments, so results are bitwise those of direct launches.
+struct StepGraphs {
+  struct Entry {
+    int R;
+    bool lo;
+    hipGraph_t g;
+    hipGraphExec_t e;
+  };
+  std::vector<Entry> v;
+  bool failed = false;
+  StepGraphs() = default;
+  StepGraphs(const StepGraphs&) = delete;
+  ~StepGraphs() {
+    for (auto& c : v) {
+      if (c.e) (void)hipGraphExecDestroy(c.e);
+      if (c.g) (void)hipGraphDestroy(c.g);
+    }
+  }
+  // the replayable chain for R columns, captured on first use; null if capture is not possible
+  hipGraphExec_t get(int R, bool lo, const std::function<void()>& chain, hipStream_t st) {
+    for (auto& c : v)
+      if (c.R == R && c.lo == lo) return c.e;
+    if (failed) return nullptr;
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      (void)hipGetLastError();
+      failed = true;
+      return nullptr;
+    }
+    try {
+      chain();
+    } catch (...) {
+      (void)hipStreamEndCapture(st, &g);
+      if (g) (void)hipGraphDestroy(g);
+      (void)hipGetLastError();
+      throw;
+    }
+    if (hipStreamEndCapture(st, &g) != hipSuccess || !g) {
+      (void)hipGetLastError();
+      failed = true;
+      return nullptr;
+    }
+    hipGraphExec_t e = nullptr;
+    if (hipGraphInstantiate(&e, g, nullptr, nullptr, 0) != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipGraphDestroy(g);
+      failed = true;
+      return nullptr;
+    }
+    v.push_back({R, lo, g, e});
+    if (verbose()) std::fprintf(stderr, "[bem] captured the step product for %d columns%s\n", R, lo ? " (relaxed)" : "");
+    return e;
+  }
+};
+
 BResult gmres_batched(BGmres& w, const BApplyFn& A, const double2* B, int64_t ldb, double2* X, int64_t ldx, int R0,
                       double tol, int maxit, hipStream_t st, const BApplyFn* M, const BApplyFn* A_lo = nullptr,
-                      const BApplyFn* M_lo = nullptr, double relax = 0.0) {
+                      const BApplyFn* M_lo = nullptr, double relax = 0.0, bool graphs = false) {
+  StepGraphs sg;
   BResult out;
   out.iters.assign(R0, 0);
   out.relres.assign(R0, 0.0);
@@ -1838,7 +1901,23 @@ BResult gmres_batched(BGmres& w, const BApplyFn& A, const double2* B, int64_t ld
       }
       const BApplyFn& Aj = lo ? *A_lo : A;
       const BApplyFn* Mj = lo ? M_lo : M;
-      if (Mj) {
+      hipGraphExec_t ge = nullptr;
+      if (graphs)
+        ge = sg.get(Rc, lo, [&]() {
+          if (Mj) {
+            (*Mj)(w.U, ldv, w.Z, ldv, Rc);
+            Aj(w.Z, ldv, w.T, ldv, Rc);
+          } else {
+            Aj(w.U, ldv, w.T, ldv, Rc);
+          }
+        }, st);
+      if (ge) {
+        // (U and T are free during the Arnoldi steps: they serve the restart and the update)
+        BEM_HIP(hipMemcpyAsync(w.U, Vj, sizeof(double2) * Rc * ldv, hipMemcpyDeviceToDevice, st));
+        BEM_HIP(hipGraphLaunch(ge, st));
+        BEM_HIP(hipMemcpyAsync(Vn, w.T, sizeof(double2) * Rc * ldv, hipMemcpyDeviceToDevice, st));
+        ++out.graph_steps;
+      } else if (Mj) {
         (*Mj)(Vj, ldv, w.Z, ldv, Rc);
         Aj(w.Z, ldv, Vn, ldv, Rc);
       } else {
@@ -1995,6 +2074,8 @@ std::vector<double> true_residuals(BGmres& w, const BApplyFn& A64, const double2
 }
 
 constexpr int kMaxBatch = 256;
+// largest system (unknowns) whose step products are replayed from captured graphs
+constexpr int64_t kGraphMaxN = 65536;
 
 }  // namespace
 
@@ -2109,6 +2190,12 @@ int solve_op(OpObj& op, const bem_excitation* exc, int64_t nexc, const bem_solve
   // (BEM_FP32: both products read the float32 entries; A64 takes them in float64 arithmetic)
   bool fp32_ok = op.precision != BEM_FP64;
   bool probed = false;
+  // Arnoldi step products replayed from captured graphs: where the chain has no host step (no
+  // nested GMRES, no serving combiner, no kernel timer) and the operator is small enough for
+  // launch overhead to matter.  BEM_GRAPH=0 turns it off.
+  const char* genv = std::getenv("BEM_GRAPH");
+  const bool graphs = !(genv && std::strcmp(genv, "0") == 0) && !op.comb && !Profiler::get().enabled() &&
+                      (op.formulation == BEM_FORM_EAEFIE || op.inner_mode != BEM_INNER_GMRES) && N <= kGraphMaxN;
   for (int64_t e0 = 0; e0 < nexc; e0 += Rb) {
     const int R = int(std::min<int64_t>(Rb, nexc - e0));
     launch_axpby(N, c2(0.0), nullptr, c2(0.0), nullptr, bfull, st, R, 0, 0, ldN);
@@ -2184,8 +2271,10 @@ int solve_op(OpObj& op, const bem_excitation* exc, int64_t nexc, const bem_solve
       const int budget = use32 ? std::min(left, std::max(3 * opts.restart, 600)) : left;
       // (the preconditioner stays float64: the solution update applies it to V y, so the steps
       // must have applied the same one)
-      BResult g = use32 ? gmres_batched(bw, A64, rr, ldN, dd, ldN, Rc, gtol, budget, st, Pm64, &A32, Pm64, relax)
-                        : gmres_batched(bw, A64, rr, ldN, dd, ldN, Rc, gtol, budget, st, Pm64);
+      BResult g = use32 ? gmres_batched(bw, A64, rr, ldN, dd, ldN, Rc, gtol, budget, st, Pm64, &A32, Pm64, relax,
+                                        graphs)
+                        : gmres_batched(bw, A64, rr, ldN, dd, ldN, Rc, gtol, budget, st, Pm64, nullptr, nullptr, 0.0,
+                                        graphs);
       bool sweep_failed = false;
       for (int c = 0; c < Rc; ++c) sweep_failed |= !g.converged[c];
       int most = 0;
@@ -2195,6 +2284,7 @@ int solve_op(OpObj& op, const bem_excitation* exc, int64_t nexc, const bem_solve
       }
       left -= most;
       inf.n_products += g.products;
+      inf.graph_steps += g.graph_steps;
       if (s > 0 || use32) ++inf.refine_steps;
       // x += d ; float64 residual of the updated columns
       launch_scatter_cols(dd, ldN, xs, ldN, didx, N, Rc, 1, st);

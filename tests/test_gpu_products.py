@@ -1,7 +1,9 @@
 """Dense products through bem_apply against numpy on the exported blocks, for every column count
-that selects a different kernel (grouped GEMV for 1-2 columns; matrix-core GEMMs with 32-, 64- and
-128-wide real N tiles, with and without the split-K sum), in float64 and in float32 storage
-(BEM_FP32: float32 vectors in and out), and the BEM_FP32 precision's solve against the oracle.
+that selects a different kernel (grouped GEMV for 1-2 columns; matrix-core GEMMs with real N tiles
+of 16, 32, 48, 64, 96 and 128 columns in float64 and 32, 64, 96 and 128 in float32, with and
+without the split-K sum), in float64 and in float32 storage (BEM_FP32: float32 vectors in and
+out); the launch variants the tuner chooses between give bitwise the same products; and the
+BEM_FP32 precision's solve against the oracle.
 
 Blocks: L^A at the background wavenumber of a 1280-triangle sphere (1920 x 1920: tall enough for
 the split-K path) and of an 80-triangle sphere (120 x 120: one tile, ragged)."""
@@ -17,7 +19,7 @@ from tests.bemutil import edge_perm, rel
 
 pytestmark = pytest.mark.gpu
 
-COLS = [1, 2, 3, 8, 16, 17, 32, 33, 64, 65, 130]
+COLS = [1, 2, 3, 8, 9, 16, 17, 24, 25, 32, 33, 48, 49, 64, 65, 130]
 
 
 @pytest.fixture(scope="module")
@@ -93,6 +95,33 @@ def test_float32_products(torch_mod, ops, R, level):
     ref = X.astype(np.complex128) @ A32.T
     err = np.linalg.norm(Y - ref) / np.linalg.norm(ref)
     assert err < 2e-6, err
+
+
+@pytest.mark.parametrize("R", [1, 5, 12, 20, 30, 40, 60, 70])
+def test_launch_variants_agree_bitwise(torch_mod, ops, R):
+    """The same product repeated 14 times: the first launches of a shape class are the tuner's
+    timed trials of every candidate (rows per workgroup of the GEMV; tile shape and tile-to-XCD
+    mapping of the GEMMs), the later ones its choice; every result is bitwise the first, in both
+    storage precisions (1280-triangle sphere: split-K and single-split shapes)."""
+    torch = torch_mod
+    ctx, out = ops
+    w, mesh, info, op64, op32, A, A32 = out[3]
+    ne = A.shape[0]
+    X = _x(ne, R, 300 + R)
+    for op, dt, tol, ref_A in ((op64, torch.complex128, 1e-13, A), (op32, torch.complex64, 2e-6, A32)):
+        xd = torch.tensor(X.astype(np.complex64) if dt == torch.complex64 else X, dtype=dt, device="cuda")
+        first = None
+        for it in range(14):
+            yd = torch.zeros((R, ne), dtype=dt, device="cuda")
+            B.bem_apply(ctx, op, B.BEM_BLOCK_LA_BG, xd.data_ptr(), yd.data_ptr(), R)
+            torch.cuda.synchronize()
+            Y = yd.cpu().numpy()
+            if first is None:
+                first = Y
+                ref = xd.cpu().numpy().astype(np.complex128) @ ref_A.T
+                assert np.linalg.norm(Y - ref) / np.linalg.norm(ref) < tol
+            else:
+                assert np.array_equal(Y, first), (R, it)
 
 
 def test_fp32_solve_matches_oracle():
