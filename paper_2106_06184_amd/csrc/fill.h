@@ -53,6 +53,7 @@ struct FillKArgs {
   double2* Kc;            // rows 3*(T-t0)+i, cols = object-local (cell, BC) columns
   int64_t ldK;
   int sub;                // 1: some source sub-triangle needs its rule subdivided
+  int valence = 0;        // largest valence of the cells (0: not known, the padded one is assumed)
 };
 
 // Source-rule subdivision for highly conductive objects: a source piece of longest edge h is

@@ -110,7 +110,7 @@ __global__ void __launch_bounds__(256) k_fill_L_far(FillLArgs a) {
         subdiv_corners(lev, jp, c);
         for (int l = 0; l < 7; ++l) dl[l] = subdiv_point(c, cB7[l], pj);
       }
-#pragma unroll
+#pragma unroll 1
       for (int k = 0; k < 7; ++k) {
         const v3 dk = G3(geo, nt, kGeoQ + 3 * k, t);
         const v3 base = d + dk;
@@ -270,8 +270,10 @@ __global__ void __launch_bounds__(256) k_gather_K(const double2* __restrict__ Kc
 //   R = sum_k w_k d_k x u_k,       S = sum_k w_k u_k
 // SUB: the inner rule of a sub-triangle is Q3 on each piece of its level-L split (L from |Re k|
 // and the sub-triangle's longest edge); otherwise plain Q3.
-template <bool LOSSY, int MAXV, bool SUB>
-__global__ void __launch_bounds__(128) k_fill_K_far(FillKArgs a) {
+// NACC <= MAXV: accumulators per thread, at least the largest valence of the launch's cells
+// (MAXV is the padded layout of the cell tables; a smaller NACC frees registers).
+template <bool LOSSY, int MAXV, bool SUB, int NACC>
+__global__ void __launch_bounds__(128, 2) k_fill_K_far(FillKArgs a) {
   const int64_t cl = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (cl >= a.ncells) return;
   const int32_t v = a.cells[cl];
@@ -286,9 +288,9 @@ __global__ void __launch_bounds__(128) k_fill_K_far(FillKArgs a) {
   for (int64_t tl = tbeg; tl < tend; ++tl) {
     const int64_t t = a.t0 + tl;
     const v3 d = G3(geo, nt, kGeoC, t) - pv;
-    cz acc[MAXV][3];
+    cz acc[NACC][3];
 #pragma unroll
-    for (int b = 0; b < MAXV; ++b)
+    for (int b = 0; b < NACC; ++b)
 #pragma unroll
       for (int i = 0; i < 3; ++i) acc[b][i] = {0, 0};
     for (int sidx = 0; sidx < 2 * nval; ++sidx) {
@@ -304,7 +306,7 @@ __global__ void __launch_bounds__(128) k_fill_K_far(FillKArgs a) {
       const v3 sv3[3] = {mk(0, 0, 0), sm, sc};
       cz P = {0, 0};
       cv3 Q = cvzero(), Rm = cvzero(), S = cvzero();
-#pragma unroll
+#pragma unroll 1
       for (int k = 0; k < 7; ++k) {
         const v3 dk = G3(geo, nt, kGeoQ + 3 * k, t);
         const v3 Dk = d + dk;
@@ -349,7 +351,7 @@ __global__ void __launch_bounds__(128) k_fill_K_far(FillKArgs a) {
         Y[i].x = csub(Rm.x, pxS.x); Y[i].y = csub(Rm.y, pxS.y); Y[i].z = csub(Rm.z, pxS.z);
       }
 #pragma unroll
-      for (int b = 0; b < MAXV; ++b) {
+      for (int b = 0; b < NACC; ++b) {
         if (b < nval) {
           const double al = 0.25 * a.alpha[size_t(b) * nc + v];
           const size_t bo = (size_t(b) * (2 * MAXV) + sidx) * nc + v;
@@ -361,7 +363,7 @@ __global__ void __launch_bounds__(128) k_fill_K_far(FillKArgs a) {
     }
     double2* out = a.Kc + (3 * tl) * a.ldK + col0;
 #pragma unroll
-    for (int b = 0; b < MAXV; ++b)
+    for (int b = 0; b < NACC; ++b)
       if (b < nval)
 #pragma unroll
         for (int i = 0; i < 3; ++i) out[i * a.ldK + b] = make_double2(acc[b][i].re, acc[b][i].im);
@@ -877,8 +879,13 @@ void launch_fill_K(const FillKArgs& a, const int32_t* near_t, const int32_t* nea
 #define BEM_KLAUNCH(L, MV)                                                                            \
   {                                                                                                   \
     ProfScope ps(st, KC_FILL_K, kbytes, kwork);                                                       \
-    if (a.sub) hipLaunchKernelGGL((dev::k_fill_K_far<L, MV, true>), grid, dim3(128), 0, st, a);      \
-    else hipLaunchKernelGGL((dev::k_fill_K_far<L, MV, false>), grid, dim3(128), 0, st, a);           \
+    if (MV == 8 && a.valence > 0 && a.valence <= 6) {                                                \
+      if (a.sub) hipLaunchKernelGGL((dev::k_fill_K_far<L, MV, true, 6>), grid, dim3(128), 0, st, a);  \
+      else hipLaunchKernelGGL((dev::k_fill_K_far<L, MV, false, 6>), grid, dim3(128), 0, st, a);       \
+    } else {                                                                                          \
+      if (a.sub) hipLaunchKernelGGL((dev::k_fill_K_far<L, MV, true, MV>), grid, dim3(128), 0, st, a); \
+      else hipLaunchKernelGGL((dev::k_fill_K_far<L, MV, false, MV>), grid, dim3(128), 0, st, a);      \
+    }                                                                                                 \
     BEM_HIP(hipGetLastError());                                                                       \
   }                                                                                                   \
   if (npairs > 0) {                                                                                   \

@@ -650,6 +650,7 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
                    d_cells + cdat.obj_cell_ptr[o], ncell_o, cdat.ncell, d_nval, d_vpos, d_col0, d_sub_m, d_sub_c,
                    d_sub_area, d_sub_parent, d_alpha, d_beta, H, cdat.obj_ncol[o]};
       ka.sub = needs_sub(k, t0, nto);
+      ka.valence = m.max_valence;
       launch_fill_K(ka, pct, pcc, int64_t(nc_t[o].size()), d_near_ptr, d_near_idx, cdat.maxv, st);
       launch_gather_K(H, cdat.obj_ncol[o], d_hp + e0, d_hm + e0, 3 * t0, neo, d_cS + e0, d_cT + e0, neo, dst.d64,
                       dst.ld, st);
@@ -667,6 +668,7 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
                    d_cells + cdat.obj_cell_ptr[o], ncell_o, cdat.ncell, d_nval, d_vpos, d_col0, d_sub_m, d_sub_c,
                    d_sub_area, d_sub_parent, d_alpha, d_beta, H, cdat.obj_ncol[o]};
       ka.sub = needs_sub(op.kbg, m.obj_tri[o], m.obj_tri[o + 1] - m.obj_tri[o]);
+      ka.valence = m.max_valence;
       launch_fill_K(ka, pct, pcc, int64_t(ncm_t[o].size()), d_near_ptr, d_near_idx, cdat.maxv, st);
       launch_gather_K(H, cdat.obj_ncol[o], d_hp, d_hm, 0, m.ne, d_cS + e0, d_cT + e0, neo, op.Km.d64 + e0, op.Km.ld,
                       st);
