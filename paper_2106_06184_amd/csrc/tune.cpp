@@ -23,11 +23,17 @@ Tuner& Tuner::get() {
 }
 
 hipEvent_t Tuner::take_event() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
   {
     std::lock_guard<std::mutex> g(mu_);
-    if (!pool_.empty()) {
-      hipEvent_t e = pool_.back();
-      pool_.pop_back();
+    auto& pool = pool_[dev];
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
       return e;
     }
   }
@@ -56,8 +62,8 @@ void Tuner::harvest_locked() {
     } else {
       (void)hipGetLastError();
     }
-    pool_.push_back(t.a);
-    pool_.push_back(t.b);
+    pool_[t.dev].push_back(t.a);
+    pool_[t.dev].push_back(t.b);
     pending_.pop_front();
   }
 }
@@ -114,13 +120,19 @@ int Tuner::pick(uint64_t key, int n, hipStream_t st, bool* trial) {
 }
 
 void Tuner::submit(uint64_t key, int cand, hipEvent_t a, hipEvent_t b) {
+  int dev = int((key >> 56) & 0xff);
   std::lock_guard<std::mutex> g(mu_);
-  pending_.push_back({key, cand, a, b});
+  pending_.push_back({key, cand, dev, a, b});
 }
 
 void Tuner::give_back(hipEvent_t e) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return;
+  }
   std::lock_guard<std::mutex> g(mu_);
-  pool_.push_back(e);
+  pool_[dev].push_back(e);
 }
 
 int Tuner::decided(uint64_t key) {
@@ -131,7 +143,14 @@ int Tuner::decided(uint64_t key) {
 }
 
 TuneScope::TuneScope(uint64_t key, int n, hipStream_t st) : key_(key), st_(st) {
-  cand_ = Tuner::get().pick(key, n, st, &trial_);
+  // classes are per device (its events time its own launches)
+  int dev = 0;
+  if (n > 1 && hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    dev = 0;
+  }
+  key_ = key ^ (uint64_t(dev & 0xff) << 56);
+  cand_ = Tuner::get().pick(key_, n, st, &trial_);
   if (trial_) {
     a_ = Tuner::get().take_event();
     if (!a_ || hipEventRecord(a_, st_) != hipSuccess) {

@@ -1,4 +1,4 @@
-// Online launch-variant selection.  Some kernels come in variants that compute bitwise the same
+// Online launch-variant selection (one tuner per process, classes kept per device).  Some kernels come in variants that compute bitwise the same
 // result (the same products summed in the same order; only the workgroup tile shape, the rows
 // per workgroup or the tile-to-XCD mapping differ).  For every problem class (a key built from
 // the shape) the first launches try each candidate twice, timed with HIP events on the launch
@@ -38,14 +38,14 @@ class Tuner {
   };
   struct Trial {
     uint64_t key;
-    int cand;
+    int cand, dev;
     hipEvent_t a, b;
   };
   void harvest_locked();
   std::mutex mu_;
   std::unordered_map<uint64_t, Entry> map_;
   std::deque<Trial> pending_;
-  std::vector<hipEvent_t> pool_;
+  std::unordered_map<int, std::vector<hipEvent_t>> pool_;  // per device
   int enabled_ = -1;
 };
 
@@ -64,7 +64,8 @@ class TuneScope {
   hipEvent_t a_ = nullptr;
 };
 
-// Key helpers: a class id and fields packed 8 bits each (log2 buckets for sizes).
+// Key helpers: a class id and up to six fields packed 8 bits each (log2 buckets for sizes); the
+// top byte is the device's.
 inline int log2_bucket(int64_t v) {
   int b = 0;
   while (v > 1 && b < 62) {
@@ -79,7 +80,7 @@ inline uint64_t tune_key(uint32_t cls, std::initializer_list<int64_t> fields) {
   for (int64_t f : fields) {
     k |= (uint64_t(f) & 0xff) << sh;
     sh += 8;
-    if (sh >= 64) break;
+    if (sh >= 56) break;
   }
   return k;
 }
