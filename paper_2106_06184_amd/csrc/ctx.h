@@ -16,6 +16,9 @@ class Server;
 // Pinned host staging per stream owner (context or serving slot): the first 64 doubles hold
 // convergence scalars; the rest stages the per-column Krylov scalars and index lists.
 constexpr size_t kPinnedBytes = 64 * 1024;
+// largest half-row scratch of one fill chunk
+constexpr size_t kFillScratchBytes = size_t(4) << 30;
+int64_t fill_chunk_triangles(int64_t nt, int64_t row_len);
 constexpr size_t kPinnedScalars = 64;
 constexpr int kInnerNone = -1;  // operator without an equivalent-configuration solve
 

@@ -150,5 +150,15 @@ void launch_fill_K(const FillKArgs& a, const int32_t* near_t, const int32_t* nea
 // edges whose BC functions sit in the cell-expanded columns cS/cT of Kc.
 void launch_gather_K(const double2* Kc, int64_t ldK, const int32_t* hp, const int32_t* hm, int64_t off, int64_t nrow,
                      const int32_t* cS, const int32_t* cT, int64_t ncol, double2* out, int64_t ldo, hipStream_t st);
+// Chunked gathers: the listed edge rows `rows` (indices into hp/hm) with a half-RWG in the chunk's
+// half-rows [rlo, rhi) (half-row matrix row h - rlo); a row with both halves in the chunk is
+// written whole, a half alone is written by the first chunk (in chunk order) holding a half of the
+// row and added by the second.  L: columns n < ncol at half-columns hp[n] - coff, hm[n] - coff.
+void launch_gather_LA_rows(const double2* H, int64_t ldH, const int32_t* hp, const int32_t* hm, int64_t rlo,
+                           int64_t rhi, int64_t coff, int64_t ncol, const int32_t* rows, int64_t nrows, double2* out,
+                           int64_t ldo, hipStream_t st);
+void launch_gather_K_rows(const double2* Kc, int64_t ldK, const int32_t* hp, const int32_t* hm, int64_t rlo, int64_t rhi,
+                          const int32_t* cS, const int32_t* cT, int64_t ncol, const int32_t* rows, int64_t nrows,
+                          double2* out, int64_t ldo, hipStream_t st);
 
 }  // namespace bem

@@ -268,6 +268,81 @@ __global__ void __launch_bounds__(256) k_gather_K(const double2* __restrict__ Kc
 //   m0_k = sum_j w_j g(R_kj),  m1_k = sum_j w_j g(R_kj) d'_j,  u_k = m1_k - Delta_k m0_k
 //   P = sum_k w_k d_k.(d x m1_k),  Q = sum_k w_k Delta_k x m1_k,
 //   R = sum_k w_k d_k x u_k,       S = sum_k w_k u_k
+// Chunked gathers.  The half-row matrices hold the test half-RWGs [rlo, rhi) of one chunk of
+// test triangles (row h - rlo).  For every listed edge row m with a half in the chunk: both halves
+// there give the whole entry (the same sums as one pass over all rows); a half alone gives its
+// part, which the first chunk (in chunk order) holding a half of m writes and the second adds.
+// Two parts add exactly the same whichever comes first, so the result depends only on the
+// chunk boundaries, which the caller fixes from the mesh.
+__global__ void __launch_bounds__(256) k_gather_LA_rows(const double2* __restrict__ H, int64_t ldH,
+                                                        const int32_t* __restrict__ hp, const int32_t* __restrict__ hm,
+                                                        int64_t rlo, int64_t rhi, int64_t coff, int64_t ncol,
+                                                        const int32_t* __restrict__ rows, int64_t nrows,
+                                                        double2* __restrict__ out, int64_t ldo) {
+  const int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (n >= ncol) return;
+  const int64_t cp = hp[n] - coff, cm = hm[n] - coff;
+  for (int64_t r = blockIdx.y; r < nrows; r += gridDim.y) {
+    const int64_t m = rows[r];
+    const int64_t hpm = hp[m], hmm = hm[m];
+    const bool inp = hpm >= rlo && hpm < rhi, inm = hmm >= rlo && hmm < rhi;
+    double2* o = out + m * ldo + n;
+    if (inp && inm) {
+      const double2* rp = H + (hpm - rlo) * ldH;
+      const double2* rm = H + (hmm - rlo) * ldH;
+      const double2 a = rp[cp], b = rp[cm], c = rm[cp], d = rm[cm];
+      *o = make_double2(a.x - b.x - c.x + d.x, a.y - b.y - c.y + d.y);
+    } else if (inp) {
+      const double2* rp = H + (hpm - rlo) * ldH;
+      const double2 a = rp[cp], b = rp[cm];
+      double2 v = make_double2(a.x - b.x, a.y - b.y);
+      if (hmm < rlo) v = make_double2(o->x + v.x, o->y + v.y);
+      *o = v;
+    } else if (inm) {
+      const double2* rm = H + (hmm - rlo) * ldH;
+      const double2 c = rm[cp], d = rm[cm];
+      double2 v = make_double2(d.x - c.x, d.y - c.y);
+      if (hpm < rlo) v = make_double2(o->x + v.x, o->y + v.y);
+      *o = v;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) k_gather_K_rows(const double2* __restrict__ Kc, int64_t ldK,
+                                                       const int32_t* __restrict__ hp, const int32_t* __restrict__ hm,
+                                                       int64_t rlo, int64_t rhi, const int32_t* __restrict__ cS,
+                                                       const int32_t* __restrict__ cT, int64_t ncol,
+                                                       const int32_t* __restrict__ rows, int64_t nrows,
+                                                       double2* __restrict__ out, int64_t ldo) {
+  const int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (n >= ncol) return;
+  const int32_t s = cS[n], u = cT[n];
+  for (int64_t r = blockIdx.y; r < nrows; r += gridDim.y) {
+    const int64_t m = rows[r];
+    const int64_t hpm = hp[m], hmm = hm[m];
+    const bool inp = hpm >= rlo && hpm < rhi, inm = hmm >= rlo && hmm < rhi;
+    double2* o = out + m * ldo + n;
+    if (inp && inm) {
+      const double2* rp = Kc + (hpm - rlo) * ldK;
+      const double2* rm = Kc + (hmm - rlo) * ldK;
+      const double2 a = rp[s], b = rp[u], c = rm[s], d = rm[u];
+      *o = make_double2(a.x + b.x - c.x - d.x, a.y + b.y - c.y - d.y);
+    } else if (inp) {
+      const double2* rp = Kc + (hpm - rlo) * ldK;
+      const double2 a = rp[s], b = rp[u];
+      double2 v = make_double2(a.x + b.x, a.y + b.y);
+      if (hmm < rlo) v = make_double2(o->x + v.x, o->y + v.y);
+      *o = v;
+    } else if (inm) {
+      const double2* rm = Kc + (hmm - rlo) * ldK;
+      const double2 c = rm[s], d = rm[u];
+      double2 v = make_double2(-(c.x + d.x), -(c.y + d.y));
+      if (hpm < rlo) v = make_double2(o->x + v.x, o->y + v.y);
+      *o = v;
+    }
+  }
+}
+
 // SUB: the inner rule of a sub-triangle is Q3 on each piece of its level-L split (L from |Re k|
 // and the sub-triangle's longest edge); otherwise plain Q3.
 // NACC <= MAXV: accumulators per thread, at least the largest valence of the launch's cells
@@ -910,6 +985,28 @@ void launch_gather_K(const double2* Kc, int64_t ldK, const int32_t* hp, const in
   dim3 grid(unsigned((ncol + 255) / 256), unsigned(std::min<int64_t>(nrow, 32768)));
   ProfScope ps(st, KC_GATHER, double(nrow) * ncol * 5 * 16, double(nrow) * ncol);
   hipLaunchKernelGGL(dev::k_gather_K, grid, dim3(256), 0, st, Kc, ldK, hp, hm, off, nrow, cS, cT, ncol, out, ldo);
+  BEM_HIP(hipGetLastError());
+}
+
+void launch_gather_LA_rows(const double2* H, int64_t ldH, const int32_t* hp, const int32_t* hm, int64_t rlo,
+                           int64_t rhi, int64_t coff, int64_t ncol, const int32_t* rows, int64_t nrows, double2* out,
+                           int64_t ldo, hipStream_t st) {
+  if (nrows <= 0 || ncol <= 0) return;
+  dim3 grid(unsigned((ncol + 255) / 256), unsigned(std::min<int64_t>(nrows, 32768)));
+  ProfScope ps(st, KC_GATHER, double(nrows) * ncol * 5 * 16, double(nrows) * ncol);
+  hipLaunchKernelGGL(dev::k_gather_LA_rows, grid, dim3(256), 0, st, H, ldH, hp, hm, rlo, rhi, coff, ncol, rows, nrows,
+                     out, ldo);
+  BEM_HIP(hipGetLastError());
+}
+
+void launch_gather_K_rows(const double2* Kc, int64_t ldK, const int32_t* hp, const int32_t* hm, int64_t rlo, int64_t rhi,
+                          const int32_t* cS, const int32_t* cT, int64_t ncol, const int32_t* rows, int64_t nrows,
+                          double2* out, int64_t ldo, hipStream_t st) {
+  if (nrows <= 0 || ncol <= 0) return;
+  dim3 grid(unsigned((ncol + 255) / 256), unsigned(std::min<int64_t>(nrows, 32768)));
+  ProfScope ps(st, KC_GATHER, double(nrows) * ncol * 5 * 16, double(nrows) * ncol);
+  hipLaunchKernelGGL(dev::k_gather_K_rows, grid, dim3(256), 0, st, Kc, ldK, hp, hm, rlo, rhi, cS, cT, ncol, rows,
+                     nrows, out, ldo);
   BEM_HIP(hipGetLastError());
 }
 

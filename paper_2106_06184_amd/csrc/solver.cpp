@@ -15,6 +15,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <deque>
 #include <map>
 
 #include "ctx.h"
@@ -252,6 +253,16 @@ void drop_f64_blocks(OpObj& op) {
     }
   }
   for (Dense* d : all) d->d64 = nullptr;
+}
+
+// Test triangles per fill chunk: the half-row scratch of a chunk (3 rows per triangle, row_len
+// complex entries each) stays within kFillScratchBytes, and the chunks of nt triangles are of
+// equal size (no short last chunk).  A function of the mesh alone.
+int64_t fill_chunk_triangles(int64_t nt, int64_t row_len) {
+  const int64_t per_tri = 3 * row_len * int64_t(sizeof(double2));
+  const int64_t most = std::max<int64_t>(1, std::min<int64_t>(nt, int64_t(kFillScratchBytes) / std::max<int64_t>(per_tri, 1)));
+  const int64_t nchunk = (nt + most - 1) / most;
+  return (nt + nchunk - 1) / nchunk;
 }
 
 void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
@@ -573,12 +584,13 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
     }
   }
 
-  // scratch for the half-RWG and cell-expanded matrices
-  int64_t scratch_elems = 9 * nt * nt;
-  for (int64_t o = 0; o < m.nobj; ++o) {
-    const int64_t nto = m.obj_tri[o + 1] - m.obj_tri[o];
-    scratch_elems = std::max(scratch_elems, 3 * (eaefie ? nt : nto) * cdat.obj_ncol[o]);
-  }
+  // scratch for the half-RWG and cell-expanded matrices of one chunk of test triangles: every
+  // fill runs over chunks of at most ct test triangles of its test range (boundaries fixed by
+  // the mesh alone, so every assembly of a mesh sums its entries the same way)
+  int64_t row_len = 3 * nt;
+  for (int64_t o = 0; o < m.nobj; ++o) row_len = std::max<int64_t>(row_len, cdat.obj_ncol[o]);
+  const int64_t ct = fill_chunk_triangles(nt, row_len);
+  const int64_t scratch_elems = 3 * ct * row_len;
   double2* H = op.mem.alloc<double2>(size_t(scratch_elems));
   // BEM_POISON=1 fills the fill scratch with NaN first, so that a read of an entry the fill
   // kernels did not write shows up in the blocks (a check used by the tests)
@@ -609,16 +621,47 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
     for (int64_t t = s0; t < s0 + ns; ++t) h = std::max(h, m.hmax[t]);
     return subdiv_level_host(k.real(), h) > 0 ? 1 : 0;
   };
+  // near pairs of a list sorted by test triangle whose test triangle lies in [lo, hi)
+  auto pair_span = [](const std::vector<int32_t>& tl, int64_t lo, int64_t hi) {
+    const auto b = std::lower_bound(tl.begin(), tl.end(), int32_t(lo));
+    const auto e = std::lower_bound(b, tl.end(), int32_t(hi));
+    return std::make_pair(int64_t(b - tl.begin()), int64_t(e - b));
+  };
+  // rows (edges e0 + r, r < nrow) with a half-RWG on a test triangle in [lo, hi), uploaded without
+  // waiting for the stream (the host copies live until the fills have run), so that the launches
+  // of the chunks follow each other and the host work below overlaps them
+  std::deque<std::vector<int32_t>> row_lists;
+  auto chunk_rows = [&](int64_t e0, int64_t nrow, int64_t lo, int64_t hi, int64_t* count) -> int32_t* {
+    std::vector<int32_t> r;
+    for (int64_t n = 0; n < nrow; ++n) {
+      const int64_t tp = m.tp[e0 + n], tm = m.tm[e0 + n];
+      if ((tp >= lo && tp < hi) || (tm >= lo && tm < hi)) r.push_back(int32_t(n));
+    }
+    *count = int64_t(r.size());
+    if (r.empty()) return nullptr;
+    row_lists.push_back(std::move(r));
+    const std::vector<int32_t>& h = row_lists.back();
+    int32_t* d = op.mem.alloc<int32_t>(h.size());
+    tmp_dev.push_back(d);
+    BEM_HIP(hipMemcpyAsync(d, h.data(), sizeof(int32_t) * h.size(), hipMemcpyHostToDevice, st));
+    return d;
+  };
   // background L^A, L^phi (the coupling blocks; the nested-solve inverses are formed from them)
   {
     int32_t* pt = up32(na_t);
     int32_t* ps = up32(na_s);
-    FillLArgs la{op.geo, nt, 0, nt, 0, nt, tchunk_for(nt, 256, nt), op.kbg.real(), op.kbg.imag(), H, 3 * nt,
-                 op.Lphi_bg.d64,
-                 op.Lphi_bg.ld};
-    la.sub = needs_sub(op.kbg, 0, nt);
-    launch_fill_L(la, pt, ps, int64_t(na_t.size()), st);
-    launch_gather_LA(H, 3 * nt, d_hp, d_hm, 0, m.ne, op.LA_bg.d64, op.LA_bg.ld, st);
+    const int sub = needs_sub(op.kbg, 0, nt);
+    for (int64_t c0 = 0; c0 < nt; c0 += ct) {
+      const int64_t c1 = std::min(nt, c0 + ct);
+      const auto [p0, np] = pair_span(na_t, c0, c1);
+      FillLArgs la{op.geo, nt, c0, c1 - c0, 0, nt, tchunk_for(nt, 256, c1 - c0), op.kbg.real(), op.kbg.imag(), H,
+                   3 * nt, op.Lphi_bg.d64 + c0 * op.Lphi_bg.ld, op.Lphi_bg.ld};
+      la.sub = sub;
+      launch_fill_L(la, pt + p0, ps + p0, np, st);
+      int64_t nr = 0;
+      const int32_t* rows = chunk_rows(0, m.ne, c0, c1, &nr);
+      launch_gather_LA_rows(H, 3 * nt, d_hp, d_hm, 3 * c0, 3 * c1, 0, m.ne, rows, nr, op.LA_bg.d64, op.LA_bg.ld, st);
+    }
   }
   for (int64_t o = 0; o < m.nobj; ++o) {
     const int64_t t0 = m.obj_tri[o], nto = m.obj_tri[o + 1] - t0;
@@ -629,12 +672,20 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
     if (own_int) {
       int32_t* pt = up32(no_t[o]);
       int32_t* ps = up32(no_s[o]);
-      FillLArgs la{op.geo, nt, t0, nto, t0, nto, tchunk_for(nto, 256, nto), op.kint[o].real(), op.kint[o].imag(), H,
-                   3 * nto,
-                   op.Lphi_int[o].d64, op.Lphi_int[o].ld};
-      la.sub = needs_sub(op.kint[o], t0, nto);
-      launch_fill_L(la, pt, ps, int64_t(no_t[o].size()), st);
-      launch_gather_LA(H, 3 * nto, d_hp + e0, d_hm + e0, 3 * t0, neo, op.LA_int[o].d64, op.LA_int[o].ld, st);
+      const int sub = needs_sub(op.kint[o], t0, nto);
+      for (int64_t c0 = t0; c0 < t0 + nto; c0 += ct) {
+        const int64_t c1 = std::min(t0 + nto, c0 + ct);
+        const auto [p0, np] = pair_span(no_t[o], c0, c1);
+        FillLArgs la{op.geo, nt, c0, c1 - c0, t0, nto, tchunk_for(nto, 256, c1 - c0), op.kint[o].real(),
+                     op.kint[o].imag(), H, 3 * nto, op.Lphi_int[o].d64 + (c0 - t0) * op.Lphi_int[o].ld,
+                     op.Lphi_int[o].ld};
+        la.sub = sub;
+        launch_fill_L(la, pt + p0, ps + p0, np, st);
+        int64_t nr = 0;
+        const int32_t* rows = chunk_rows(e0, neo, c0, c1, &nr);
+        launch_gather_LA_rows(H, 3 * nto, d_hp + e0, d_hm + e0, 3 * c0, 3 * c1, 3 * t0, neo, rows, nr,
+                              op.LA_int[o].d64, op.LA_int[o].ld, st);
+      }
     }
     // K~ at k_int and at k_bg (object-local blocks)
     int32_t* pct = up32(nc_t[o]);
@@ -646,14 +697,21 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
       const cd k = which == 0 ? op.kint[o] : op.kbg;
       Dense& dst = which == 0 ? op.K_int[o] : op.K_bg[o];
       const int64_t ncell_o = cdat.obj_cell_ptr[o + 1] - cdat.obj_cell_ptr[o];
-      FillKArgs ka{op.geo, nt, t0, nto, tchunk_for(ncell_o, 128, nto), k.real(), k.imag(),
-                   d_cells + cdat.obj_cell_ptr[o], ncell_o, cdat.ncell, d_nval, d_vpos, d_col0, d_sub_m, d_sub_c,
-                   d_sub_area, d_sub_parent, d_alpha, d_beta, H, cdat.obj_ncol[o]};
-      ka.sub = needs_sub(k, t0, nto);
-      ka.valence = m.max_valence;
-      launch_fill_K(ka, pct, pcc, int64_t(nc_t[o].size()), d_near_ptr, d_near_idx, cdat.maxv, st);
-      launch_gather_K(H, cdat.obj_ncol[o], d_hp + e0, d_hm + e0, 3 * t0, neo, d_cS + e0, d_cT + e0, neo, dst.d64,
-                      dst.ld, st);
+      const int sub = needs_sub(k, t0, nto);
+      for (int64_t c0 = t0; c0 < t0 + nto; c0 += ct) {
+        const int64_t c1 = std::min(t0 + nto, c0 + ct);
+        const auto [p0, np] = pair_span(nc_t[o], c0, c1);
+        FillKArgs ka{op.geo, nt, c0, c1 - c0, tchunk_for(ncell_o, 128, c1 - c0), k.real(), k.imag(),
+                     d_cells + cdat.obj_cell_ptr[o], ncell_o, cdat.ncell, d_nval, d_vpos, d_col0, d_sub_m, d_sub_c,
+                     d_sub_area, d_sub_parent, d_alpha, d_beta, H, cdat.obj_ncol[o]};
+        ka.sub = sub;
+        ka.valence = m.max_valence;
+        launch_fill_K(ka, pct + p0, pcc + p0, np, d_near_ptr, d_near_idx, cdat.maxv, st);
+        int64_t nr = 0;
+        const int32_t* rows = chunk_rows(e0, neo, c0, c1, &nr);
+        launch_gather_K_rows(H, cdat.obj_ncol[o], d_hp + e0, d_hm + e0, 3 * c0, 3 * c1, d_cS + e0, d_cT + e0, neo,
+                             rows, nr, dst.d64, dst.ld, st);
+      }
     }
   }
   if (eaefie) {
@@ -664,14 +722,21 @@ void assemble_op(OpObj& op, MeshObj& mo, const bem_problem& prob) {
       int32_t* pct = up32(ncm_t[o]);
       int32_t* pcc = up32(ncm_c[o]);
       const int64_t ncell_o = cdat.obj_cell_ptr[o + 1] - cdat.obj_cell_ptr[o];
-      FillKArgs ka{op.geo, nt, 0, nt, tchunk_for(ncell_o, 128, nt), op.kbg.real(), op.kbg.imag(),
-                   d_cells + cdat.obj_cell_ptr[o], ncell_o, cdat.ncell, d_nval, d_vpos, d_col0, d_sub_m, d_sub_c,
-                   d_sub_area, d_sub_parent, d_alpha, d_beta, H, cdat.obj_ncol[o]};
-      ka.sub = needs_sub(op.kbg, m.obj_tri[o], m.obj_tri[o + 1] - m.obj_tri[o]);
-      ka.valence = m.max_valence;
-      launch_fill_K(ka, pct, pcc, int64_t(ncm_t[o].size()), d_near_ptr, d_near_idx, cdat.maxv, st);
-      launch_gather_K(H, cdat.obj_ncol[o], d_hp, d_hm, 0, m.ne, d_cS + e0, d_cT + e0, neo, op.Km.d64 + e0, op.Km.ld,
-                      st);
+      const int sub = needs_sub(op.kbg, m.obj_tri[o], m.obj_tri[o + 1] - m.obj_tri[o]);
+      for (int64_t c0 = 0; c0 < nt; c0 += ct) {
+        const int64_t c1 = std::min(nt, c0 + ct);
+        const auto [p0, np] = pair_span(ncm_t[o], c0, c1);
+        FillKArgs ka{op.geo, nt, c0, c1 - c0, tchunk_for(ncell_o, 128, c1 - c0), op.kbg.real(), op.kbg.imag(),
+                     d_cells + cdat.obj_cell_ptr[o], ncell_o, cdat.ncell, d_nval, d_vpos, d_col0, d_sub_m, d_sub_c,
+                     d_sub_area, d_sub_parent, d_alpha, d_beta, H, cdat.obj_ncol[o]};
+        ka.sub = sub;
+        ka.valence = m.max_valence;
+        launch_fill_K(ka, pct + p0, pcc + p0, np, d_near_ptr, d_near_idx, cdat.maxv, st);
+        int64_t nr = 0;
+        const int32_t* rows = chunk_rows(0, m.ne, c0, c1, &nr);
+        launch_gather_K_rows(H, cdat.obj_ncol[o], d_hp, d_hm, 3 * c0, 3 * c1, d_cS + e0, d_cT + e0, neo, rows, nr,
+                             op.Km.d64 + e0, op.Km.ld, st);
+      }
     }
   }
   if (f32) {
@@ -2093,7 +2158,7 @@ size_t estimate_request_bytes(int64_t nt, int64_t nobj, int precision, int resta
   const double entries = ((eaefie ? 2 : 3) * ne * ne + double(nt) * nt) / no + (eaefie ? 2 : 1) * ne * ne +
                          double(nt) * nt;
   const double dense = per * entries, dense_fill = per_fill * entries;
-  const double fill_scratch = 16.0 * 9.0 * double(nt) * nt;
+  const double fill_scratch = 16.0 * 9.0 * double(nt) * double(fill_chunk_triangles(nt, 3 * nt));
   // augmented inverse (not for the eAEFIE) + Sigma_P^-1 (formed in float64 before the drop)
   const double inv_entries = (eaefie ? 0.0 : (neq * neq) / no) + (nq * nq) / no;
   const double inner = per * inv_entries;

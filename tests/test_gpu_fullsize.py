@@ -201,13 +201,21 @@ def test_ellipsoid_full_size_rows_and_batched_product():
     """The 12288-triangle jittered ellipsoid with 256 plane waves: sampled rows of L^A, K~ and
     L^phi at the object wavenumber against the oracle (1e-12), and the 256-column product of
     each dense block (float64 matrix-core GEMM) against the float64 product of the exported
-    block on the host (1e-12), a property that holds at any size."""
+    block on the host (1e-12), a property that holds at any size.  At this size the fill runs in
+    equal chunks of test triangles (a half-row scratch of at most 4 GiB: at most
+    floor(2^32 / (144 N_T)) triangles per chunk); the sampled rows include two edges whose triangles lie in different chunks, whose
+    entries the chunked gathers assemble from two passes."""
     import torch
     w = meshgen.config_c3()
     topo = OM.build_topology(w.xyz, w.tri, w.obj)
     rng = np.random.default_rng(29)
     ne, nt = len(topo.edges), len(topo.tri)
-    edges_o = rng.choice(ne, size=2, replace=False)
+    most = 2 ** 32 // (144 * nt)
+    nchunk = -(-nt // most)
+    ct = -(-nt // nchunk)
+    split = np.nonzero(topo.tplus // ct != topo.tminus // ct)[0]
+    assert ct < nt and len(split) > 0
+    edges_o = np.concatenate([rng.choice(ne, size=2, replace=False), rng.choice(split, size=2, replace=False)])
     tris = np.unique(np.concatenate([topo.tplus[edges_o], topo.tminus[edges_o]]))
     k0 = OC.k0_of(w.freq_hz)
     k_int = OC.wavenumber(k0, OC.eps_c(w.eps_r[0], w.sigma[0], w.freq_hz), w.mu_r[0])
