@@ -141,19 +141,14 @@ void launch_near_field(const NearArgs& a, hipStream_t st);
 void fill_set_rules(const double w7[7], const double b7[7][3], const double b3[3][3], hipStream_t st);
 void launch_fill_L(const FillLArgs& a, const int32_t* near_t, const int32_t* near_s, int64_t npairs,
                    hipStream_t st);
-// Half-row indices hp/hm are global (3 T + i); `off` = 3 * first triangle of the block.
-void launch_gather_LA(const double2* H, int64_t ldH, const int32_t* hp, const int32_t* hm, int64_t off, int64_t ne,
-                      double2* out, int64_t ldo, hipStream_t st);
 void launch_fill_K(const FillKArgs& a, const int32_t* near_t, const int32_t* near_c, int64_t npairs,
                    const int64_t* near_ptr, const int32_t* near_idx, int maxv, hipStream_t st);
-// Rows: the nrow test edges of hp/hm (half-rows 3 T + i - off of Kc); columns: the ncol source
-// edges whose BC functions sit in the cell-expanded columns cS/cT of Kc.
-void launch_gather_K(const double2* Kc, int64_t ldK, const int32_t* hp, const int32_t* hm, int64_t off, int64_t nrow,
-                     const int32_t* cS, const int32_t* cT, int64_t ncol, double2* out, int64_t ldo, hipStream_t st);
 // Chunked gathers: the listed edge rows `rows` (indices into hp/hm) with a half-RWG in the chunk's
 // half-rows [rlo, rhi) (half-row matrix row h - rlo); a row with both halves in the chunk is
 // written whole, a half alone is written by the first chunk (in chunk order) holding a half of the
-// row and added by the second.  L: columns n < ncol at half-columns hp[n] - coff, hm[n] - coff.
+// row and added by the second.  hp/hm hold the global half-RWG indices 3 T + i of the block's
+// edges.  L: columns n < ncol at half-columns hp[n] - coff, hm[n] - coff (coff = 3 x the first
+// source triangle).  K~: columns n < ncol from the cell-expanded columns cS[n], cT[n].
 void launch_gather_LA_rows(const double2* H, int64_t ldH, const int32_t* hp, const int32_t* hm, int64_t rlo,
                            int64_t rhi, int64_t coff, int64_t ncol, const int32_t* rows, int64_t nrows, double2* out,
                            int64_t ldo, hipStream_t st);

@@ -229,45 +229,8 @@ __global__ void __launch_bounds__(128) k_fill_L_near(FillLArgs a, const int32_t*
 }
 
 // ------------------------------------------------------------ gathers
-// out[m][n] = sum_{a in {+,-}} sum_{b in {+,-}} s_a s_b H[row_a(m)][row_b(n)]
-__global__ void __launch_bounds__(256) k_gather_LA(const double2* __restrict__ H, int64_t ldH,
-                                                   const int32_t* __restrict__ hp, const int32_t* __restrict__ hm,
-                                                   int64_t off, int64_t ne, double2* __restrict__ out, int64_t ldo) {
-  const int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (n >= ne) return;
-  const int64_t cp = hp[n] - off, cm = hm[n] - off;
-  for (int64_t m = blockIdx.y; m < ne; m += gridDim.y) {
-    const double2* rp = H + (int64_t(hp[m]) - off) * ldH;
-    const double2* rm = H + (int64_t(hm[m]) - off) * ldH;
-    double2 a = rp[cp], b = rp[cm], c = rm[cp], d = rm[cm];
-    out[m * ldo + n] = make_double2(a.x - b.x - c.x + d.x, a.y - b.y - c.y + d.y);
-  }
-}
-
-// out[m][n] = sum_{a in {+,-}} s_a (Kc[row_a(m)][colS(n)] + Kc[row_a(m)][colT(n)])
-__global__ void __launch_bounds__(256) k_gather_K(const double2* __restrict__ Kc, int64_t ldK,
-                                                  const int32_t* __restrict__ hp, const int32_t* __restrict__ hm,
-                                                  int64_t off, int64_t nrow, const int32_t* __restrict__ cS,
-                                                  const int32_t* __restrict__ cT, int64_t ncol,
-                                                  double2* __restrict__ out, int64_t ldo) {
-  const int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (n >= ncol) return;
-  const int32_t s = cS[n], u = cT[n];
-  for (int64_t m = blockIdx.y; m < nrow; m += gridDim.y) {
-    const double2* rp = Kc + (int64_t(hp[m]) - off) * ldK;
-    const double2* rm = Kc + (int64_t(hm[m]) - off) * ldK;
-    double2 a = rp[s], b = rp[u], c = rm[s], d = rm[u];
-    out[m * ldo + n] = make_double2(a.x + b.x - c.x - d.x, a.y + b.y - c.y - d.y);
-  }
-}
-
-// ------------------------------------------------------------------ K far
-// Contribution of one far sub-triangle to the accumulators acc[b][i] (i = test half-RWG):
-//   1/4 [alpha_b (P - p_i.Q) + beta_b . (R - p_i x S)]
-// with, over the outer points k (Delta_k = d + d_k, d = test centroid - v):
-//   m0_k = sum_j w_j g(R_kj),  m1_k = sum_j w_j g(R_kj) d'_j,  u_k = m1_k - Delta_k m0_k
-//   P = sum_k w_k d_k.(d x m1_k),  Q = sum_k w_k Delta_k x m1_k,
-//   R = sum_k w_k d_k x u_k,       S = sum_k w_k u_k
+// L^A: out[m][n] = sum_{a in {+,-}} sum_{b in {+,-}} s_a s_b H[row_a(m)][row_b(n)];
+// K~: out[m][n] = sum_{a in {+,-}} s_a (Kc[row_a(m)][colS(n)] + Kc[row_a(m)][colT(n)]).
 // Chunked gathers.  The half-row matrices hold the test half-RWGs [rlo, rhi) of one chunk of
 // test triangles (row h - rlo).  For every listed edge row m with a half in the chunk: both halves
 // there give the whole entry (the same sums as one pass over all rows); a half alone gives its
@@ -933,15 +896,6 @@ void launch_fill_L(const FillLArgs& a, const int32_t* near_t, const int32_t* nea
   }
 }
 
-void launch_gather_LA(const double2* H, int64_t ldH, const int32_t* hp, const int32_t* hm, int64_t off, int64_t ne,
-                      double2* out, int64_t ldo, hipStream_t st) {
-  if (ne <= 0) return;
-  dim3 grid(unsigned((ne + 255) / 256), unsigned(std::min<int64_t>(ne, 32768)));
-  ProfScope ps(st, KC_GATHER, double(ne) * ne * 5 * 16, double(ne) * ne);
-  hipLaunchKernelGGL(dev::k_gather_LA, grid, dim3(256), 0, st, H, ldH, hp, hm, off, ne, out, ldo);
-  BEM_HIP(hipGetLastError());
-}
-
 void launch_fill_K(const FillKArgs& a, const int32_t* near_t, const int32_t* near_c, int64_t npairs,
                    const int64_t* near_ptr, const int32_t* near_idx, int maxv, hipStream_t st) {
   if (a.ncells <= 0 || a.nt_test <= 0) return;
@@ -977,15 +931,6 @@ void launch_fill_K(const FillKArgs& a, const int32_t* near_t, const int32_t* nea
     throw Error(BEM_E_INVALID, "unsupported padded valence");
   }
 #undef BEM_KLAUNCH
-}
-
-void launch_gather_K(const double2* Kc, int64_t ldK, const int32_t* hp, const int32_t* hm, int64_t off, int64_t nrow,
-                     const int32_t* cS, const int32_t* cT, int64_t ncol, double2* out, int64_t ldo, hipStream_t st) {
-  if (nrow <= 0 || ncol <= 0) return;
-  dim3 grid(unsigned((ncol + 255) / 256), unsigned(std::min<int64_t>(nrow, 32768)));
-  ProfScope ps(st, KC_GATHER, double(nrow) * ncol * 5 * 16, double(nrow) * ncol);
-  hipLaunchKernelGGL(dev::k_gather_K, grid, dim3(256), 0, st, Kc, ldK, hp, hm, off, nrow, cS, cT, ncol, out, ldo);
-  BEM_HIP(hipGetLastError());
 }
 
 void launch_gather_LA_rows(const double2* H, int64_t ldH, const int32_t* hp, const int32_t* hm, int64_t rlo,
