@@ -9,7 +9,10 @@
 namespace bem {
 
 namespace {
-constexpr int kTrials = 2;  // timed launches per candidate; the faster of the two counts
+constexpr int kTrials = 3;  // timed launches per candidate; the fastest counts
+// another candidate replaces the first only when it is faster by this factor (launches that
+// overlap other work, as in serving, time noisily)
+constexpr float kMargin = 0.97f;
 
 bool verbose_env() {
   const char* v = std::getenv("BEM_VERBOSE");
@@ -101,6 +104,7 @@ int Tuner::pick(uint64_t key, int n, hipStream_t st, bool* trial) {
     int best = 0;
     for (int c = 1; c < e.n; ++c)
       if (e.best[c] < e.best[best]) best = c;
+    if (best != 0 && !(e.best[best] < kMargin * e.best[0])) best = 0;
     e.choice = best;
     if (verbose_env()) {
       std::fprintf(stderr, "[bem] tuned class %016llx: candidate %d of %d (", (unsigned long long)key, best, e.n);

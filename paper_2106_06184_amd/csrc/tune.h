@@ -1,9 +1,10 @@
 // Online launch-variant selection (one tuner per process, classes kept per device).  Some kernels come in variants that compute bitwise the same
 // result (the same products summed in the same order; only the workgroup tile shape, the rows
 // per workgroup or the tile-to-XCD mapping differ).  For every problem class (a key built from
-// the shape) the first launches try each candidate twice, timed with HIP events on the launch
-// stream; once every trial has completed, the fastest candidate is used for that class for the
-// rest of the process.  Because the candidates agree bitwise, results do not depend on which
+// the shape) the first launches try each candidate three times, timed with HIP events on the
+// launch stream; once every trial has completed, the fastest candidate (by its fastest trial,
+// and by at least 3% over the first candidate) is used for that class for the rest of the
+// process.  Because the candidates agree bitwise, results do not depend on which
 // one runs.  Launches into a capturing stream never time (they take the decided candidate, or
 // the first).  BEM_TUNE=0 in the environment always takes the first candidate.
 #pragma once
