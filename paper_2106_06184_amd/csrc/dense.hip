@@ -249,18 +249,21 @@ __global__ void __launch_bounds__(256) k_gj_panels(const double2* __restrict__ A
 // XCD gets a band of nby/8 row tiles, cut into balanced sub-bands of at most 10 row tiles, and
 // walks one sub-band after the other column tile by column tile (rows fastest), so the
 // sub-band's rows of the column panels C (at most 10 x 64 rows x 4 panels x 1 KiB = 2.5 MB) and
-// the few R columns in flight stay in its L2 (4 MB).  Mode 1 is the column of tiles
-// tj = fix (one block per tile row), mode 2 the row of tiles ti = fix without its tile in
-// column fix.
+// the few R columns in flight stay in its L2 (4 MB).  Mode 3 is the strip pair of tile fix: the
+// column of tiles tj = fix and the row of tiles ti = fix (without the tile the column has).
 __device__ __forceinline__ void update_tile(int mode, int fix, unsigned& ti, unsigned& tj) {
-  if (mode == 1) {
-    ti = blockIdx.x;
-    tj = unsigned(fix);
-    return;
-  }
-  if (mode == 2) {
-    ti = unsigned(fix);
-    tj = blockIdx.x + (blockIdx.x >= unsigned(fix) ? 1u : 0u);
+  if (mode == 3) {
+    // both strips of tile row / column fix: blocks [0, nt) the column strip (every tile row),
+    // blocks [nt, 2 nt - 1) the row strip (every tile column but fix); disjoint tiles
+    const unsigned nt = (gridDim.x + 1) / 2;
+    if (blockIdx.x < nt) {
+      ti = blockIdx.x;
+      tj = unsigned(fix);
+    } else {
+      const unsigned b = blockIdx.x - nt;
+      ti = unsigned(fix);
+      tj = b + (b >= unsigned(fix) ? 1u : 0u);
+    }
     return;
   }
   const unsigned nbx = gridDim.x, nby = gridDim.y;
@@ -595,11 +598,11 @@ void launch_peq_stage2(const double2* d, const double2* t, const double2* v, con
 static void launch_update(double2* A, int64_t ld, int64_t n, int mode, int fix, int b, const double2* R,
                           const double2* C, hipStream_t st) {
   const unsigned nt = unsigned((n + 63) / 64);
-  const dim3 g = mode == 0 ? dim3(nt, nt) : dim3(mode == 1 ? nt : nt - 1);
+  const dim3 g = mode == 0 ? dim3(nt, nt) : dim3(2 * nt - 1);
   if (g.x == 0) return;
   const double ntile = double(g.x) * g.y, elems = ntile * 64.0 * 64.0;
-  ProfScope ps(st, KC_DENSE_INV, 32.0 * std::min(elems, mode == 0 ? double(n) * n : 64.0 * n),
-               8.0 * b * std::min(elems, mode == 0 ? double(n) * n : 64.0 * n));
+  const double alg = std::min(elems, mode == 0 ? double(n) * n : 2.0 * 64.0 * n);
+  ProfScope ps(st, KC_DENSE_INV, 32.0 * alg, 8.0 * b * alg);
   hipLaunchKernelGGL(dev::k_gj_update_mfma4, g, dim3(256), 0, st, reinterpret_cast<double*>(A), ld, n, mode, fix, b,
                      R, C);
   BEM_HIP(hipGetLastError());  // before the profiler's scope ends (it clears event-query status)
@@ -623,10 +626,7 @@ void dense_invert(double2* A, int64_t n, int64_t ld, DenseScratch& ws, hipStream
     for (int mp = 0; mp < npan; ++mp) {
       const int64_t km = k0 + int64_t(mp) * dev::NB;
       const int bm = int(std::min<int64_t>(dev::NB, n - km));
-      if (mp > 0) {
-        launch_update(A, ld, n, 1, int(km / 64), mp * dev::NB, ws.R, ws.C, st);
-        launch_update(A, ld, n, 2, int(km / 64), mp * dev::NB, ws.R, ws.C, st);
-      }
+      if (mp > 0) launch_update(A, ld, n, 3, int(km / 64), mp * dev::NB, ws.R, ws.C, st);
       double2* Rm = ws.R + int64_t(mp) * dev::NB * n;
       double2* Cm = ws.C + mp * dev::NB;
       hipLaunchKernelGGL(dev::k_gj_diag, dim3(1), dim3(dev::kDiagThreads), 0, st, A, ld, km, bm, ws.P, ws.health);
