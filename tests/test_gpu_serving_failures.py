@@ -1,4 +1,4 @@
-"""Failure paths and guarantees of the solve and serving calls (SURVEY-style: admission refusal,
+"""Failure paths and guarantees of the solve and serving calls (admission refusal,
 iteration limit with the best iterate, non-finite input, a failing request among healthy ones),
 the serving loop's results against the oracle, real sharing of grouped launches by concurrent
 requests, and the opt-in kernel timer left on while serving.  Every failure is forced from the
