@@ -312,11 +312,9 @@ def _profiled_pass(B, timed, args, prec):
     return prof
 
 
-def _roofline(B, prof) -> dict:
-    names = dict(enumerate(B.KC_NAMES))
-    dom = max(prof, key=lambda k: prof[k]["ms"])
-    p = prof[dom]
-    avg_ms = p["ms"] / max(p["launches"], 1)
+def _class_roofline(B, dom, p) -> dict:
+    """Bound, achieved rate (algorithmic bytes or flops over the class's event-timed launch
+    time), peak and fraction of one kernel class."""
     if dom in (B.KC_GEMV_F64, B.KC_GEMV_F32, B.KC_GATHER):
         achieved = p["bytes"] / (p["ms"] * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
@@ -330,10 +328,33 @@ def _roofline(B, prof) -> dict:
         roof = {"bound": "mfma", "achieved": achieved, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / FP64_MFMA_PEAK_TFLOPS}
     else:
-        # fill: ~ 64 float64 vector operations per kernel evaluation (see the design notes)
+        # fill: about 64 float64 vector operations per Green's-function evaluation
         achieved = p["work"] * 64 / (p["ms"] * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / FP64_VECTOR_PEAK_TFLOPS}
+    return roof
+
+
+def _kernel_classes(B, prof) -> dict:
+    """Every timed kernel class of a profiled pass: its time, launches and roofline."""
+    out = {}
+    for k, p in prof.items():
+        if k == B.KC_FILL_NEAR and p["launches"] > 0:
+            # (its work count is near pairs, not kernel evaluations: time only)
+            out[B.KC_NAMES[k]] = {"ms": round(p["ms"], 2), "launches": p["launches"]}
+        elif p["launches"] > 0 and p["ms"] > 0:
+            r = _class_roofline(B, k, p)
+            out[B.KC_NAMES[k]] = {"ms": round(p["ms"], 2), "launches": p["launches"], "bound": r["bound"],
+                                  "achieved": round(r["achieved"], 3), "unit": r["unit"], "frac": round(r["frac"], 4)}
+    return out
+
+
+def _roofline(B, prof) -> dict:
+    names = dict(enumerate(B.KC_NAMES))
+    dom = max(prof, key=lambda k: prof[k]["ms"])
+    p = prof[dom]
+    avg_ms = p["ms"] / max(p["launches"], 1)
+    roof = _class_roofline(B, dom, p)
     roof.update({"kernel": names[dom], "avg_launch_ms": avg_ms, "launches": p["launches"],
                  "traffic": measured_traffic(names[dom]),
                  "algorithmic_bytes_per_launch": p["bytes"] / max(p["launches"], 1), "traffic_unit": "bytes/launch"})
@@ -411,6 +432,7 @@ def run_serve(args) -> int:
         "matvec_frac_hbm": (gemv_b / (gemv_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS) if gemv_ms > 0 else None,
         "combined_launches": m["combined_launches"], "combined_products": m["combined_products"],
         "roofline": _roofline(B, prof),
+        "kernel_classes": _kernel_classes(B, prof),
     }
     failed = {k: v["failed"] for k, v in runs.items() if v["failed"]}
     if failed:
@@ -557,7 +579,7 @@ def main() -> int:
         roof = {"bound": "mfma", "achieved": achieved, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / FP64_MFMA_PEAK_TFLOPS, "traffic": None}
     else:
-        # fill: ~ 64 float64 vector operations per kernel evaluation (see the design notes)
+        # fill: about 64 float64 vector operations per Green's-function evaluation
         achieved = p["work"] * 64 / (p["ms"] * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None}
