@@ -8,7 +8,7 @@
 //   P = A_kb,kb^-1 ;  R = P A_kb,j (j outside kb) ;  C = A_i,kb (i outside kb)
 //   A_i,j -= C_i R_j ;  A_kb,j = R_j ;  A_i,kb = -C_i P ;  A_kb,kb = P
 // The update is a rank-b complex product over the whole matrix (64 x 64 output tiles per
-// workgroup, K staged through LDS in chunks of 16).  Without pivoting the elimination needs
+// workgroup, K staged through LDS in chunks of 16, three real products per complex one).  Without pivoting the elimination needs
 // non-singular leading blocks; for the matrices it is used on (near-field dominated BEM blocks
 // and their charge Schur complements) this holds and round-off growth stays small.
 #include <hip/hip_runtime.h>
@@ -284,31 +284,28 @@ __device__ __forceinline__ void update_tile(int mode, int fix, unsigned& ti, uns
 // A[i][j] -= sum_s C[i][s] R[s][j] over the tiles of the launch (C: ld LDC, R: ld n) on the
 // float64 matrix cores.  Whole tiles are updated: rows and columns of the pivot blocks are
 // overwritten afterwards, and where a tile holds an earlier pivot block's rows or columns, that
-// panel's C rows and R columns there are zero.  Real embedding of the complex product: the rows
-// of C (interleaved re/im, 2b reals) times the 2b x 2n real matrix with 2x2 blocks
-// [[Re R, Im R], [-Im R, Re R]] give the interleaved rows of C R.  Workgroup tile 64 x 64
-// complex (64 x 128 reals), four waves of 32 x 64 reals, K staged through LDS 32 reals at a
-// time (A k-major so that operand reads are conflict-free).  The float64 4x4x4 four-block
-// instruction (alone, on gfx950, about 1.45x the float64 16x16x4 one).  Lane l
-// of one instruction supplies A_q[l % 4][l / 16] and B_q[l / 16][l % 4] of block
-// q = (l % 16) / 4 and receives D_q[l / 16][l % 4].  All four blocks
-// of an instruction share the rows (4 rows of the wave tile) and take four consecutive 4-column
-// groups, so a lane's A value serves the four column groups and its B value the eight row
-// groups: per 4 reals of K a wave issues 32 instructions on 8 A and 4 B values from LDS.
-// Output of instruction (bi, g), lane l: row 4 bi + l / 16, column 16 g + l % 16 of the wave tile
-// (32 x 64 reals).
-__global__ void __launch_bounds__(256, 2) k_gj_update_mfma4(double* __restrict__ A, int64_t ld, int64_t n,
-                                                         int mode, int fix, int b, const double2* __restrict__ R,
-                                                         const double2* __restrict__ Cp) {
-  constexpr int KC = 32;  // reals of K per stage (16 complex)
-  __shared__ double As[KC][64 + 1];
-  __shared__ __align__(16) double Bs[KC][128 + 2];
+// panel's C rows and R columns there are zero.  3M form (Gauss's trick, three real products per
+// complex product): with c = cr + j ci and r = rr + j ri,
+//   P1 = cr rr,  P2 = ci ri,  P3 = (cr + ci)(rr + ri);   Re(c r) = P1 - P2,  Im(c r) = P3 - P1 - P2,
+// each summed over the panel columns on the float64 4x4x4 four-block instruction (alone, on
+// gfx950, about 1.45x the float64 16x16x4 one): 6 real flops per complex multiply-add where the
+// real embedding of the complex product takes 8.  Tile 64 x 64 complex, four waves of 32 x 32
+// complex; C and R staged through LDS as complex pairs, 16 panel columns at a time.  Lane l of
+// instruction (bi, g) supplies C[4 bi + l % 4][l / 16] (the four blocks share the rows) and
+// R[l / 16][16 g + l % 16] and receives row 4 bi + l / 16, column 16 g + l % 16 of the wave tile:
+// each lane holds P1, P2 and P3 of whole complex outputs and updates them itself.  The tile's
+// old values are read after the products (the registers go to the three accumulators).
+__global__ void __launch_bounds__(256, 2) k_gj_update_3m(double2* __restrict__ A, int64_t ld, int64_t n, int mode,
+                                                      int fix, int b, const double2* __restrict__ R,
+                                                      const double2* __restrict__ Cp) {
+  constexpr int KCC = 16;  // complex panel columns per stage
+  __shared__ double2 Cs[KCC][64 + 1];
+  __shared__ double2 Rs[KCC][64 + 1];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wm = wave >> 1, wn = wave & 1;
   unsigned ti, tj;
   update_tile(mode, fix, ti, tj);
-  const int64_t i0 = int64_t(ti) * 64;  // complex rows
-  const int64_t j0 = int64_t(tj) * 64;  // complex columns
+  const int64_t i0 = int64_t(ti) * 64, j0 = int64_t(tj) * 64;
   const int sr = tid & 63, sg = (tid >> 6) * 4;
   double2 pc[4], pr[4];
   auto fetch = [&](int s0) {
@@ -323,59 +320,62 @@ __global__ void __launch_bounds__(256, 2) k_gj_update_mfma4(double* __restrict__
   auto stage = [&]() {
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const int k = 2 * (sg + e);
-      As[k][sr] = pc[e].x;
-      As[k + 1][sr] = pc[e].y;
-      *reinterpret_cast<double2*>(&Bs[k][2 * sr]) = pr[e];
-      *reinterpret_cast<double2*>(&Bs[k + 1][2 * sr]) = make_double2(-pr[e].y, pr[e].x);
+      Cs[sg + e][sr] = pc[e];
+      Rs[sg + e][sr] = pr[e];
     }
   };
   fetch(0);
-  // old values of the tile (rows and columns of the pivot block are overwritten afterwards)
-  const int orow = lane >> 4, ocol = lane & 15;
-  double apre[8][4];
+  double p1[8][2], p2[8][2], p3[8][2];
 #pragma unroll
   for (int bi = 0; bi < 8; ++bi)
 #pragma unroll
-    for (int g = 0; g < 4; ++g) {
-      const int64_t gi = i0 + wm * 32 + 4 * bi + orow;
-      const int64_t rc = 2 * j0 + wn * 64 + 16 * g + ocol;
-      // (the tile is read once and written once per pass: non-temporal, so that the panels
-      // keep the L2)
-      apre[bi][g] = (gi < n && (rc >> 1) < n) ? __builtin_nontemporal_load(&A[gi * 2 * ld + rc]) : 0.0;
-    }
-  double acc[8][4];
-#pragma unroll
-  for (int bi = 0; bi < 8; ++bi)
-#pragma unroll
-    for (int g = 0; g < 4; ++g) acc[bi][g] = 0.0;
-  const int ai = lane & 3, ak = lane >> 4, bc = lane & 15;
-  const int K = 2 * b;
-  for (int k0r = 0; k0r < K; k0r += KC) {
+    for (int g = 0; g < 2; ++g) p1[bi][g] = p2[bi][g] = p3[bi][g] = 0.0;
+  const int ar_ = lane & 3, ak = lane >> 4, bc = lane & 15;
+  for (int k0 = 0; k0 < b; k0 += KCC) {
     stage();
     __syncthreads();
-    if (k0r + KC < K) fetch((k0r + KC) / 2);  // next chunk streams in during the MFMAs
+    if (k0 + KCC < b) fetch(k0 + KCC);  // next stage streams in during the MFMAs
 #pragma unroll
-    for (int kk = 0; kk < KC; kk += 4) {
-      double av[8], bv[4];
+    for (int kk = 0; kk < KCC; kk += 4) {
+      double cr[8], ci[8], rr[2], ri[2];
 #pragma unroll
-      for (int bi = 0; bi < 8; ++bi) av[bi] = As[kk + ak][wm * 32 + 4 * bi + ai];
+      for (int bi = 0; bi < 8; ++bi) {
+        const double2 u = Cs[kk + ak][wm * 32 + 4 * bi + ar_];
+        cr[bi] = u.x;
+        ci[bi] = u.y;
+      }
 #pragma unroll
-      for (int g = 0; g < 4; ++g) bv[g] = Bs[kk + ak][wn * 64 + 16 * g + bc];
+      for (int g = 0; g < 2; ++g) {
+        const double2 u = Rs[kk + ak][wn * 32 + 16 * g + bc];
+        rr[g] = u.x;
+        ri[g] = u.y;
+      }
 #pragma unroll
       for (int bi = 0; bi < 8; ++bi)
 #pragma unroll
-        for (int g = 0; g < 4; ++g) acc[bi][g] = __builtin_amdgcn_mfma_f64_4x4x4f64(av[bi], bv[g], acc[bi][g], 0, 0, 0);
+        for (int g = 0; g < 2; ++g) {
+          p1[bi][g] = __builtin_amdgcn_mfma_f64_4x4x4f64(cr[bi], rr[g], p1[bi][g], 0, 0, 0);
+          p2[bi][g] = __builtin_amdgcn_mfma_f64_4x4x4f64(ci[bi], ri[g], p2[bi][g], 0, 0, 0);
+          p3[bi][g] = __builtin_amdgcn_mfma_f64_4x4x4f64(cr[bi] + ci[bi], rr[g] + ri[g], p3[bi][g], 0, 0, 0);
+        }
     }
     __syncthreads();
   }
+  double* Ad = reinterpret_cast<double*>(A);
 #pragma unroll
   for (int bi = 0; bi < 8; ++bi)
 #pragma unroll
-    for (int g = 0; g < 4; ++g) {
-      const int64_t gi = i0 + wm * 32 + 4 * bi + orow;
-      const int64_t rc = 2 * j0 + wn * 64 + 16 * g + ocol;
-      if (gi < n && (rc >> 1) < n) __builtin_nontemporal_store(apre[bi][g] - acc[bi][g], &A[gi * 2 * ld + rc]);
+    for (int g = 0; g < 2; ++g) {
+      const int64_t gi = i0 + wm * 32 + 4 * bi + (lane >> 4);
+      const int64_t gj = j0 + wn * 32 + 16 * g + (lane & 15);
+      if (gi < n && gj < n) {
+        // (read once and written once per pass: non-temporal, so that the panels keep the L2)
+        double* a = Ad + 2 * (gi * ld + gj);
+        const double re = p1[bi][g] - p2[bi][g], im = (p3[bi][g] - p1[bi][g]) - p2[bi][g];
+        const double ox = __builtin_nontemporal_load(a), oy = __builtin_nontemporal_load(a + 1);
+        __builtin_nontemporal_store(ox - re, a);
+        __builtin_nontemporal_store(oy - im, a + 1);
+      }
     }
 }
 
@@ -603,8 +603,7 @@ static void launch_update(double2* A, int64_t ld, int64_t n, int mode, int fix, 
   const double ntile = double(g.x) * g.y, elems = ntile * 64.0 * 64.0;
   const double alg = std::min(elems, mode == 0 ? double(n) * n : 2.0 * 64.0 * n);
   ProfScope ps(st, KC_DENSE_INV, 32.0 * alg, 8.0 * b * alg);
-  hipLaunchKernelGGL(dev::k_gj_update_mfma4, g, dim3(256), 0, st, reinterpret_cast<double*>(A), ld, n, mode, fix, b,
-                     R, C);
+  hipLaunchKernelGGL(dev::k_gj_update_3m, g, dim3(256), 0, st, A, ld, n, mode, fix, b, R, C);
   BEM_HIP(hipGetLastError());  // before the profiler's scope ends (it clears event-query status)
 }
 

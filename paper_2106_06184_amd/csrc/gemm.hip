@@ -9,6 +9,10 @@
 // 2r+1 = x_im' of excitation r gives Re and Im of Y in adjacent columns.  8 real flops per
 // complex multiply-add, as the 4M method.
 //
+// float64 arithmetic above 8 columns (except 17-24) instead takes three real products per complex
+// one (3M, k_gemm3m_f64 below): 6 real flops per complex multiply-add.  The float32 path keeps
+// the embedding (3M's cancellation in Im would cost float32 accuracy).
+//
 // Kernels: 256-thread workgroups of four waves; float32 MFMA 32x32x2 (wave tile 64 x 32 JN) or
 // float64 MFMA 4x4x4 four-block (wave tile 32 x 16 JN), K step 16, double-buffered LDS (A stored
 // k-major so that MFMA operand reads are conflict-free).  The N tile (real columns) is the
@@ -364,6 +368,157 @@ __global__ void __launch_bounds__(256) k_gemm_f64(const TA* __restrict__ A, int6
     }
 }
 
+// ---- float64, three real products per complex product (3M, Gauss's trick): for a = ar + j ai
+// and x = xr + j xi,
+//   P1 = ar xr,  P2 = ai xi,  P3 = (ar + ai)(xr + xi);   Re(a x) = P1 - P2,  Im(a x) = P3 - P1 - P2,
+// summed over k as three real products on the 4x4x4 four-block instruction: 6 real flops per
+// complex multiply-add instead of the embedding's 8.  The operands stay complex: A tiles and the
+// right-hand sides are staged as (re, im) pairs straight from their complex storage (no
+// embedded copy of X), and the sums ar + ai, xr + xi are formed as the operands are read.
+// Wave tile 32 rows x 16 JN complex columns, each lane holding P1, P2 and P3 of its outputs
+// (the instruction's result layout as above, columns now complex), so every lane completes its
+// own outputs.  Split s covers complex K [s kc, (s + 1) kc); partials are written as (Re, Im)
+// pairs in the embedding's layout, so the split-K sum is shared.
+constexpr int CK = 8, CPAD = 1;  // complex k per K step; LDS row padding (complex entries)
+
+template <typename TA, bool ALIGNED, int WN, int JN>
+__global__ void __launch_bounds__(256, 2) k_gemm3m_f64(const TA* __restrict__ A, int64_t lda,
+                                                       const double2* __restrict__ X, int64_t ldx, int64_t M,
+                                                       int64_t K, int64_t kc, int64_t ntn, int64_t S,
+                                                       double* __restrict__ P, int64_t ldb, double2* __restrict__ Y,
+                                                       int64_t ldy, int64_t R, double2 alpha, int accumulate,
+                                                       int xcd) {
+  constexpr int WM = 4 / WN, TM = WM * 32, TN = WN * JN * 16;  // rows, complex columns
+  constexpr int EA = TM * CK / 256;                             // complex A entries per thread
+  constexpr int NB = (TN * CK + 255) / 256;                      // complex X entries per thread
+  __shared__ double2 As[2][CK][TM + CPAD];
+  __shared__ double2 Bs[2][CK][TN + CPAD];
+  const TileIdx ti = tile_of(ntn, S, xcd);
+  const int64_t m0 = ti.tm * TM, n0 = ti.tn * TN;
+  const int64_t kbeg = ti.ks * kc, kend = min(K, kbeg + kc);
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wm = wave / WN, wn = wave % WN;
+
+  const int a_row = tid / (CK / EA), a_k = (tid % (CK / EA)) * EA;
+  const int64_t gm = m0 + a_row;
+
+  double p1[8][JN], p2[8][JN], p3[8][JN];
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int j = 0; j < JN; ++j) p1[i][j] = p2[i][j] = p3[i][j] = 0.0;
+
+  double2 ra[EA], rb[NB];
+  auto load_tile = [&](int64_t k0) {
+    const int64_t kk = k0 + a_k;
+    if (gm < M) {
+      const TA* src = A + (gm * lda + kk) * 2;
+      if (ALIGNED && kk + EA <= K) {
+        if constexpr (sizeof(TA) == 8) {
+#pragma unroll
+          for (int e = 0; e < EA; ++e) ra[e] = *reinterpret_cast<const double2*>(src + 2 * e);
+        } else if constexpr (EA % 2 == 0) {
+#pragma unroll
+          for (int e = 0; e < EA; e += 2) {
+            const float4 u = *reinterpret_cast<const float4*>(src + 2 * e);
+            ra[e] = make_double2(double(u.x), double(u.y));
+            ra[e + 1] = make_double2(double(u.z), double(u.w));
+          }
+        } else {
+#pragma unroll
+          for (int e = 0; e < EA; ++e) {
+            const float2 u = *reinterpret_cast<const float2*>(src + 2 * e);
+            ra[e] = make_double2(double(u.x), double(u.y));
+          }
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < EA; ++e)
+          ra[e] = (kk + e < K) ? make_double2(double(src[2 * e]), double(src[2 * e + 1])) : make_double2(0.0, 0.0);
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < EA; ++e) ra[e] = make_double2(0.0, 0.0);
+    }
+    // X entries: consecutive threads take consecutive k of one column (coalesced along k)
+#pragma unroll
+    for (int e = 0; e < NB; ++e) {
+      const int v = tid + 256 * e, bk = v % CK, bc = v / CK;
+      const int64_t k = k0 + bk, c = n0 + bc;
+      rb[e] = (v < TN * CK && k < K && c < R) ? X[c * ldx + k] : make_double2(0.0, 0.0);
+    }
+  };
+  auto store_tile = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < EA; ++e) As[buf][a_k + e][a_row] = ra[e];
+#pragma unroll
+    for (int e = 0; e < NB; ++e) {
+      const int v = tid + 256 * e;
+      if (v < TN * CK) Bs[buf][v % CK][v / CK] = rb[e];
+    }
+  };
+
+  const int64_t nk = (kend - kbeg + CK - 1) / CK;
+  if (nk > 0) {
+    load_tile(kbeg);
+    store_tile(0);
+  }
+  __syncthreads();
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    const int buf = int(kt & 1);
+    if (kt + 1 < nk) load_tile(kbeg + (kt + 1) * CK);
+#pragma unroll
+    for (int s = 0; s < CK / 4; ++s) {
+      const int kr = 4 * s + (lane >> 4);
+      double ar[8], ai[8], br[JN], bi[JN];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const double2 u = As[buf][kr][wm * 32 + 4 * i + (lane & 3)];
+        ar[i] = u.x;
+        ai[i] = u.y;
+      }
+#pragma unroll
+      for (int j = 0; j < JN; ++j) {
+        const double2 u = Bs[buf][kr][wn * JN * 16 + j * 16 + (lane & 15)];
+        br[j] = u.x;
+        bi[j] = u.y;
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int j = 0; j < JN; ++j) {
+          p1[i][j] = __builtin_amdgcn_mfma_f64_4x4x4f64(ar[i], br[j], p1[i][j], 0, 0, 0);
+          p2[i][j] = __builtin_amdgcn_mfma_f64_4x4x4f64(ai[i], bi[j], p2[i][j], 0, 0, 0);
+          p3[i][j] = __builtin_amdgcn_mfma_f64_4x4x4f64(ar[i] + ai[i], br[j] + bi[j], p3[i][j], 0, 0, 0);
+        }
+    }
+    if (kt + 1 < nk) store_tile(buf ^ 1);
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int j = 0; j < JN; ++j) {
+      const int64_t row = m0 + wm * 32 + 4 * i + (lane >> 4);
+      const int64_t col = n0 + wn * JN * 16 + j * 16 + (lane & 15);
+      if (row >= M) continue;
+      const double re = p1[i][j] - p2[i][j], im = (p3[i][j] - p1[i][j]) - p2[i][j];
+      if (S > 1) {
+        *reinterpret_cast<double2*>(P + (size_t(ti.ks) * M + row) * ldb + 2 * col) = make_double2(re, im);
+      } else if (col < R) {
+        double yr = alpha.x * re - alpha.y * im, yi = alpha.x * im + alpha.y * re;
+        double2* y = Y + col * ldy + row;
+        if (accumulate) {
+          yr += y->x;
+          yi += y->y;
+        }
+        *y = make_double2(yr, yi);
+      }
+    }
+}
+
 }  // namespace dev
 
 namespace {
@@ -418,6 +573,24 @@ std::vector<Var> vars_f32(int tn) {
   }
 }
 
+// 3M path (float64 arithmetic): complex column tiles of 16, 32, 48 or 64.  Up to 8 columns and
+// from 17 to 24 the embedding's tiles of 16 and 48 real columns pad less than 3M's 16 and 32
+// complex ones (at 17-24 columns the two cost the same matrix-core work; measured 4% faster).
+bool use_3m(int64_t nrhs) { return nrhs >= 9 && !(nrhs >= 17 && nrhs <= 24); }
+int ntile_3m(int64_t nrhs) {
+  for (int t : {16, 32, 48})
+    if (nrhs <= t) return t;
+  return 64;
+}
+std::vector<Var> vars_3m(int tn) {
+  switch (tn) {
+    case 16: return {{1, 1}};
+    case 32: return {{1, 2}, {2, 1}};
+    case 48: return {{1, 3}};
+    default: return {{2, 2}, {4, 1}};
+  }
+}
+
 struct GemmLaunch {
   dim3 g;
   int64_t lda, ldb, K, K16, kc, ntn, S;
@@ -457,6 +630,83 @@ void launch_f64_variant(const Var& v, const GemmLaunch& l, const GemmDesc& d, co
     }
   }
 #undef BEM_G64
+}
+
+template <typename TA, bool AL>
+void launch_3m_variant(const Var& v, const GemmLaunch& l, const GemmDesc& d, hipStream_t st) {
+  const TA* A = static_cast<const TA*>(d.A);
+#define BEM_G3M(WN, JN)                                                                                        \
+  hipLaunchKernelGGL((dev::k_gemm3m_f64<TA, AL, WN, JN>), l.g, dim3(256), 0, st, A, d.lda, d.X, d.ldx, d.rows, \
+                     d.cols, l.kc, l.ntn, l.S, l.P, l.ldb, d.Y, d.ldy, d.nrhs, d.alpha, d.accumulate, l.xcd)
+  const int code = v.wn * 10 + v.jn;
+  if constexpr (AL) {
+    switch (code) {
+      case 11: BEM_G3M(1, 1); break;
+      case 12: BEM_G3M(1, 2); break;
+      case 21: BEM_G3M(2, 1); break;
+      case 13: BEM_G3M(1, 3); break;
+      case 22: BEM_G3M(2, 2); break;
+      case 41: BEM_G3M(4, 1); break;
+      default: throw Error(BEM_E_INVALID, "no such 3M GEMM variant");
+    }
+  } else {
+    switch (code) {  // unaligned operands: canonical variants only
+      case 11: BEM_G3M(1, 1); break;
+      case 12: BEM_G3M(1, 2); break;
+      case 13: BEM_G3M(1, 3); break;
+      case 22: BEM_G3M(2, 2); break;
+      default: throw Error(BEM_E_INVALID, "no such 3M GEMM variant");
+    }
+  }
+#undef BEM_G3M
+}
+
+// The float64-arithmetic product on the 3M kernel (d.fp32 = 0: float64 entries, 2: float32).
+void launch_gemm3m(const GemmDesc& d, void* ws, size_t ws_bytes, hipStream_t st) {
+  const int tn = ntile_3m(d.nrhs);
+  const bool f32e = d.fp32 != 0;
+  GemmLaunch l;
+  l.ldb = 2 * ((d.nrhs + tn - 1) / tn * tn);  // real leading dimension of the partials
+  l.ntn = l.ldb / (2 * tn);
+  l.K = d.cols;
+  l.K16 = (2 * d.cols + dev::BK - 1) / dev::BK * dev::BK;
+  l.lda = d.lda;
+  const uintptr_t ab = reinterpret_cast<uintptr_t>(d.A);
+  const bool aligned = f32e ? ((ab & 15) == 0 && (d.lda & 1) == 0) : (ab & 15) == 0;
+  std::vector<Var> vars = vars_3m(tn);
+  if (!aligned) vars.resize(1);
+  auto tm_of = [](const Var& v) -> int64_t { return (4 / v.wn) * 32; };
+  const int64_t ntm0 = (d.rows + tm_of(vars[0]) - 1) / tm_of(vars[0]);
+  l.S = split_for(ntm0 * l.ntn, l.K16);
+  l.kc = ((d.cols + l.S - 1) / l.S + dev::CK - 1) / dev::CK * dev::CK;
+  const size_t need = l.S > 1 ? size_t(l.S) * d.rows * l.ldb * sizeof(double) : 0;
+  if (need > ws_bytes) throw Error(BEM_E_INVALID, "GEMM workspace too small");
+  l.P = static_cast<double*>(ws);
+  const int nx = l.S == 1 ? 2 : 1;
+  const int ncand = int(vars.size()) * nx;
+  const uint64_t key = tune_key(f32e ? 5 : 4, {tn, l.S, aligned ? 1 : 0, log2_bucket(d.rows), log2_bucket(l.K16)});
+  ProfScope ps(st, KC_GEMM_F64, double(d.rows) * d.cols * (f32e ? 8.0 : 16.0), 8.0 * double(d.rows) * d.cols * d.nrhs);
+  {
+    TuneScope ts(key, ncand, st);
+    const int cand = ts.variant();
+    const Var& v = vars[cand / nx];
+    l.xcd = (cand % nx) == 0 ? 1 : 0;
+    l.g = dim3(unsigned(((d.rows + tm_of(v) - 1) / tm_of(v)) * l.ntn * l.S));
+    if (f32e) {
+      if (aligned) launch_3m_variant<float, true>(v, l, d, st);
+      else launch_3m_variant<float, false>(v, l, d, st);
+    } else {
+      if (aligned) launch_3m_variant<double, true>(v, l, d, st);
+      else launch_3m_variant<double, false>(v, l, d, st);
+    }
+    BEM_HIP(hipGetLastError());
+  }
+  if (l.S > 1) {
+    const int64_t n = d.rows * d.nrhs;
+    hipLaunchKernelGGL(dev::k_splitk_reduce, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, l.P, d.rows, l.ldb,
+                       l.S, d.nrhs, d.Y, d.ldy, d.alpha, d.accumulate);
+    BEM_HIP(hipGetLastError());
+  }
 }
 
 template <bool AL>
@@ -503,6 +753,10 @@ void launch_gemm(const GemmDesc& d, void* ws, size_t ws_bytes, hipStream_t st) {
   if (d.rows <= 0 || d.nrhs <= 0) return;
   // fp32 == 2: float32 entries on the float64 kernel (float64 arithmetic)
   const bool mfma32 = d.fp32 == 1;
+  if (!mfma32 && use_3m(d.nrhs)) {
+    launch_gemm3m(d, ws, ws_bytes, st);
+    return;
+  }
   const int tn = mfma32 ? ntile_f32(d.nrhs) : ntile_f64(d.nrhs);
   GemmLaunch l;
   l.K = 2 * d.cols;
