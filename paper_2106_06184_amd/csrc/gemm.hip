@@ -9,8 +9,8 @@
 // 2r+1 = x_im' of excitation r gives Re and Im of Y in adjacent columns.  8 real flops per
 // complex multiply-add, as the 4M method.
 //
-// float64 arithmetic above 8 columns (except 17-24) instead takes three real products per complex
-// one (3M, k_gemm3m_f64 below): 6 real flops per complex multiply-add.  The float32 path keeps
+// float64 arithmetic above 8 columns instead takes three real products per complex one (3M,
+// k_gemm3m_f64 below): 6 real flops per complex multiply-add.  The float32 path keeps
 // the embedding (3M's cancellation in Im would cost float32 accuracy).
 //
 // Kernels: 256-thread workgroups of four waves; float32 MFMA 32x32x2 (wave tile 64 x 32 JN) or
@@ -375,22 +375,31 @@ __global__ void __launch_bounds__(256) k_gemm_f64(const TA* __restrict__ A, int6
 // complex multiply-add instead of the embedding's 8.  The operands stay complex: A tiles and the
 // right-hand sides are staged as (re, im) pairs straight from their complex storage (no
 // embedded copy of X), and the sums ar + ai, xr + xi are formed as the operands are read.
-// Wave tile 32 rows x 16 JN complex columns, each lane holding P1, P2 and P3 of its outputs
-// (the instruction's result layout as above, columns now complex), so every lane completes its
-// own outputs.  Split s covers complex K [s kc, (s + 1) kc); partials are written as (Re, Im)
+// Lane l of an instruction supplies A_q[l % 4][l / 16] and B_q[l / 16][l % 4] of block
+// q = (l % 16) / 4 and receives D_q[l / 16][l % 4].  Two operand layouts:
+//   BSH = false: the four blocks share 4 rows and take 16 consecutive columns; a wave holds NI
+//     row groups of 4 and NJ column groups of 16 (result: row 4 i + l / 16, column 16 j + l % 16);
+//   BSH = true: the four blocks share 4 columns and take 16 consecutive rows; NI row groups of 16
+//     and NJ column groups of 4 (result: row 16 i + 4 ((l % 16) / 4) + l / 16, column 4 j + l % 4),
+//     for column tiles in steps of 4.
+// Each lane holds P1, P2 and P3 of whole complex outputs, so every lane completes its own.  WN
+// waves along N.  Split s covers complex K [s kc, (s + 1) kc); partials are written as (Re, Im)
 // pairs in the embedding's layout, so the split-K sum is shared.
 constexpr int CK = 8, CPAD = 1;  // complex k per K step; LDS row padding (complex entries)
 
-template <typename TA, bool ALIGNED, int WN, int JN>
+template <typename TA, bool ALIGNED, int WN, int NI, int NJ, bool BSH>
 __global__ void __launch_bounds__(256, 2) k_gemm3m_f64(const TA* __restrict__ A, int64_t lda,
                                                        const double2* __restrict__ X, int64_t ldx, int64_t M,
                                                        int64_t K, int64_t kc, int64_t ntn, int64_t S,
                                                        double* __restrict__ P, int64_t ldb, double2* __restrict__ Y,
                                                        int64_t ldy, int64_t R, double2 alpha, int accumulate,
                                                        int xcd) {
-  constexpr int WM = 4 / WN, TM = WM * 32, TN = WN * JN * 16;  // rows, complex columns
-  constexpr int EA = TM * CK / 256;                             // complex A entries per thread
-  constexpr int NB = (TN * CK + 255) / 256;                      // complex X entries per thread
+  constexpr int RS = BSH ? 16 : 4, CS = BSH ? 4 : 16;  // row / column group sizes of an instruction
+  constexpr int WTM = NI * RS, WTN = NJ * CS;           // wave tile (rows, complex columns)
+  constexpr int WM = 4 / WN, TM = WM * WTM, TN = WN * WTN;
+  constexpr int EA = TM * CK / 256;                      // complex A entries per thread
+  constexpr int NB = (TN * CK + 255) / 256;              // complex X entries per thread
+  static_assert(EA >= 1 && CK % EA == 0, "row tile");
   __shared__ double2 As[2][CK][TM + CPAD];
   __shared__ double2 Bs[2][CK][TN + CPAD];
   const TileIdx ti = tile_of(ntn, S, xcd);
@@ -399,15 +408,16 @@ __global__ void __launch_bounds__(256, 2) k_gemm3m_f64(const TA* __restrict__ A,
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int wm = wave / WN, wn = wave % WN;
+  const int a_lane = BSH ? (lane & 15) : (lane & 3), b_lane = BSH ? (lane & 3) : (lane & 15);
 
   const int a_row = tid / (CK / EA), a_k = (tid % (CK / EA)) * EA;
   const int64_t gm = m0 + a_row;
 
-  double p1[8][JN], p2[8][JN], p3[8][JN];
+  double p1[NI][NJ], p2[NI][NJ], p3[NI][NJ];
 #pragma unroll
-  for (int i = 0; i < 8; ++i)
+  for (int i = 0; i < NI; ++i)
 #pragma unroll
-    for (int j = 0; j < JN; ++j) p1[i][j] = p2[i][j] = p3[i][j] = 0.0;
+    for (int j = 0; j < NJ; ++j) p1[i][j] = p2[i][j] = p3[i][j] = 0.0;
 
   double2 ra[EA], rb[NB];
   auto load_tile = [&](int64_t k0) {
@@ -471,23 +481,23 @@ __global__ void __launch_bounds__(256, 2) k_gemm3m_f64(const TA* __restrict__ A,
 #pragma unroll
     for (int s = 0; s < CK / 4; ++s) {
       const int kr = 4 * s + (lane >> 4);
-      double ar[8], ai[8], br[JN], bi[JN];
+      double ar[NI], ai[NI], br[NJ], bi[NJ];
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const double2 u = As[buf][kr][wm * 32 + 4 * i + (lane & 3)];
+      for (int i = 0; i < NI; ++i) {
+        const double2 u = As[buf][kr][wm * WTM + RS * i + a_lane];
         ar[i] = u.x;
         ai[i] = u.y;
       }
 #pragma unroll
-      for (int j = 0; j < JN; ++j) {
-        const double2 u = Bs[buf][kr][wn * JN * 16 + j * 16 + (lane & 15)];
+      for (int j = 0; j < NJ; ++j) {
+        const double2 u = Bs[buf][kr][wn * WTN + CS * j + b_lane];
         br[j] = u.x;
         bi[j] = u.y;
       }
 #pragma unroll
-      for (int i = 0; i < 8; ++i)
+      for (int i = 0; i < NI; ++i)
 #pragma unroll
-        for (int j = 0; j < JN; ++j) {
+        for (int j = 0; j < NJ; ++j) {
           p1[i][j] = __builtin_amdgcn_mfma_f64_4x4x4f64(ar[i], br[j], p1[i][j], 0, 0, 0);
           p2[i][j] = __builtin_amdgcn_mfma_f64_4x4x4f64(ai[i], bi[j], p2[i][j], 0, 0, 0);
           p3[i][j] = __builtin_amdgcn_mfma_f64_4x4x4f64(ar[i] + ai[i], br[j] + bi[j], p3[i][j], 0, 0, 0);
@@ -497,12 +507,13 @@ __global__ void __launch_bounds__(256, 2) k_gemm3m_f64(const TA* __restrict__ A,
     __syncthreads();
   }
 
+  const int o_row = BSH ? 4 * ((lane & 15) >> 2) + (lane >> 4) : (lane >> 4);
 #pragma unroll
-  for (int i = 0; i < 8; ++i)
+  for (int i = 0; i < NI; ++i)
 #pragma unroll
-    for (int j = 0; j < JN; ++j) {
-      const int64_t row = m0 + wm * 32 + 4 * i + (lane >> 4);
-      const int64_t col = n0 + wn * JN * 16 + j * 16 + (lane & 15);
+    for (int j = 0; j < NJ; ++j) {
+      const int64_t row = m0 + wm * WTM + RS * i + o_row;
+      const int64_t col = n0 + wn * WTN + CS * j + b_lane;
       if (row >= M) continue;
       const double re = p1[i][j] - p2[i][j], im = (p3[i][j] - p1[i][j]) - p2[i][j];
       if (S > 1) {
@@ -573,23 +584,34 @@ std::vector<Var> vars_f32(int tn) {
   }
 }
 
-// 3M path (float64 arithmetic): complex column tiles of 16, 32, 48 or 64.  Up to 8 columns and
-// from 17 to 24 the embedding's tiles of 16 and 48 real columns pad less than 3M's 16 and 32
-// complex ones (at 17-24 columns the two cost the same matrix-core work; measured 4% faster).
-bool use_3m(int64_t nrhs) { return nrhs >= 9 && !(nrhs >= 17 && nrhs <= 24); }
+// 3M path (float64 arithmetic, 9 columns and more): complex column tiles of 16, 24, 32, 48 or
+// 64.  Up to 8 columns the embedding's 16-real-column tile pads less (and those products are
+// bound by the matrix read).
+constexpr int kMin3M = 9;
 int ntile_3m(int64_t nrhs) {
-  for (int t : {16, 32, 48})
+  for (int t : {16, 24, 32, 48})
     if (nrhs <= t) return t;
-  return 64;
+  // above 64 columns: the tile of 64, 48 or 32 that pads least (ties to the wider)
+  int best = 64;
+  for (int t : {48, 32})
+    if ((nrhs + t - 1) / t * t < (nrhs + best - 1) / best * best) best = t;
+  return best;
 }
-std::vector<Var> vars_3m(int tn) {
+struct Var3 {
+  int wn, ni, nj;
+  bool bsh;
+};
+// variants per tile, canonical first (its row tile sets the K split)
+std::vector<Var3> vars_3m(int tn) {
   switch (tn) {
-    case 16: return {{1, 1}};
-    case 32: return {{1, 2}, {2, 1}};
-    case 48: return {{1, 3}};
-    default: return {{2, 2}, {4, 1}};
+    case 16: return {{1, 8, 1, false}, {1, 2, 4, true}};
+    case 24: return {{1, 2, 6, true}, {2, 4, 3, true}};
+    case 32: return {{1, 8, 2, false}, {2, 8, 1, false}, {1, 2, 8, true}};
+    case 48: return {{1, 8, 3, false}, {2, 4, 6, true}};
+    default: return {{2, 8, 2, false}, {4, 8, 1, false}, {2, 2, 8, true}, {4, 4, 4, true}};
   }
 }
+int64_t tm_3m(const Var3& v) { return (4 / v.wn) * v.ni * (v.bsh ? 16 : 4); }
 
 struct GemmLaunch {
   dim3 g;
@@ -633,28 +655,36 @@ void launch_f64_variant(const Var& v, const GemmLaunch& l, const GemmDesc& d, co
 }
 
 template <typename TA, bool AL>
-void launch_3m_variant(const Var& v, const GemmLaunch& l, const GemmDesc& d, hipStream_t st) {
+void launch_3m_variant(const Var3& v, const GemmLaunch& l, const GemmDesc& d, hipStream_t st) {
   const TA* A = static_cast<const TA*>(d.A);
-#define BEM_G3M(WN, JN)                                                                                        \
-  hipLaunchKernelGGL((dev::k_gemm3m_f64<TA, AL, WN, JN>), l.g, dim3(256), 0, st, A, d.lda, d.X, d.ldx, d.rows, \
-                     d.cols, l.kc, l.ntn, l.S, l.P, l.ldb, d.Y, d.ldy, d.nrhs, d.alpha, d.accumulate, l.xcd)
-  const int code = v.wn * 10 + v.jn;
+#define BEM_G3M(WN, NI, NJ, BS)                                                                                \
+  hipLaunchKernelGGL((dev::k_gemm3m_f64<TA, AL, WN, NI, NJ, BS>), l.g, dim3(256), 0, st, A, d.lda, d.X, d.ldx, \
+                     d.rows, d.cols, l.kc, l.ntn, l.S, l.P, l.ldb, d.Y, d.ldy, d.nrhs, d.alpha, d.accumulate, l.xcd)
+  const int code = v.wn * 1000 + v.ni * 100 + v.nj * 10 + (v.bsh ? 1 : 0);
   if constexpr (AL) {
     switch (code) {
-      case 11: BEM_G3M(1, 1); break;
-      case 12: BEM_G3M(1, 2); break;
-      case 21: BEM_G3M(2, 1); break;
-      case 13: BEM_G3M(1, 3); break;
-      case 22: BEM_G3M(2, 2); break;
-      case 41: BEM_G3M(4, 1); break;
+      case 1810: BEM_G3M(1, 8, 1, false); break;
+      case 1241: BEM_G3M(1, 2, 4, true); break;
+      case 1261: BEM_G3M(1, 2, 6, true); break;
+      case 2431: BEM_G3M(2, 4, 3, true); break;
+      case 1820: BEM_G3M(1, 8, 2, false); break;
+      case 2810: BEM_G3M(2, 8, 1, false); break;
+      case 1281: BEM_G3M(1, 2, 8, true); break;
+      case 1830: BEM_G3M(1, 8, 3, false); break;
+      case 2461: BEM_G3M(2, 4, 6, true); break;
+      case 2820: BEM_G3M(2, 8, 2, false); break;
+      case 4810: BEM_G3M(4, 8, 1, false); break;
+      case 2281: BEM_G3M(2, 2, 8, true); break;
+      case 4441: BEM_G3M(4, 4, 4, true); break;
       default: throw Error(BEM_E_INVALID, "no such 3M GEMM variant");
     }
   } else {
     switch (code) {  // unaligned operands: canonical variants only
-      case 11: BEM_G3M(1, 1); break;
-      case 12: BEM_G3M(1, 2); break;
-      case 13: BEM_G3M(1, 3); break;
-      case 22: BEM_G3M(2, 2); break;
+      case 1810: BEM_G3M(1, 8, 1, false); break;
+      case 1261: BEM_G3M(1, 2, 6, true); break;
+      case 1820: BEM_G3M(1, 8, 2, false); break;
+      case 1830: BEM_G3M(1, 8, 3, false); break;
+      case 2820: BEM_G3M(2, 8, 2, false); break;
       default: throw Error(BEM_E_INVALID, "no such 3M GEMM variant");
     }
   }
@@ -673,10 +703,9 @@ void launch_gemm3m(const GemmDesc& d, void* ws, size_t ws_bytes, hipStream_t st)
   l.lda = d.lda;
   const uintptr_t ab = reinterpret_cast<uintptr_t>(d.A);
   const bool aligned = f32e ? ((ab & 15) == 0 && (d.lda & 1) == 0) : (ab & 15) == 0;
-  std::vector<Var> vars = vars_3m(tn);
+  std::vector<Var3> vars = vars_3m(tn);
   if (!aligned) vars.resize(1);
-  auto tm_of = [](const Var& v) -> int64_t { return (4 / v.wn) * 32; };
-  const int64_t ntm0 = (d.rows + tm_of(vars[0]) - 1) / tm_of(vars[0]);
+  const int64_t ntm0 = (d.rows + tm_3m(vars[0]) - 1) / tm_3m(vars[0]);
   l.S = split_for(ntm0 * l.ntn, l.K16);
   l.kc = ((d.cols + l.S - 1) / l.S + dev::CK - 1) / dev::CK * dev::CK;
   const size_t need = l.S > 1 ? size_t(l.S) * d.rows * l.ldb * sizeof(double) : 0;
@@ -689,9 +718,9 @@ void launch_gemm3m(const GemmDesc& d, void* ws, size_t ws_bytes, hipStream_t st)
   {
     TuneScope ts(key, ncand, st);
     const int cand = ts.variant();
-    const Var& v = vars[cand / nx];
+    const Var3& v = vars[cand / nx];
     l.xcd = (cand % nx) == 0 ? 1 : 0;
-    l.g = dim3(unsigned(((d.rows + tm_of(v) - 1) / tm_of(v)) * l.ntn * l.S));
+    l.g = dim3(unsigned(((d.rows + tm_3m(v) - 1) / tm_3m(v)) * l.ntn * l.S));
     if (f32e) {
       if (aligned) launch_3m_variant<float, true>(v, l, d, st);
       else launch_3m_variant<float, false>(v, l, d, st);
@@ -753,7 +782,7 @@ void launch_gemm(const GemmDesc& d, void* ws, size_t ws_bytes, hipStream_t st) {
   if (d.rows <= 0 || d.nrhs <= 0) return;
   // fp32 == 2: float32 entries on the float64 kernel (float64 arithmetic)
   const bool mfma32 = d.fp32 == 1;
-  if (!mfma32 && use_3m(d.nrhs)) {
+  if (!mfma32 && d.nrhs >= kMin3M) {
     launch_gemm3m(d, ws, ws_bytes, st);
     return;
   }

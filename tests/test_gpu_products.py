@@ -99,10 +99,11 @@ def test_float32_products(torch_mod, ops, R, level):
 
 @pytest.mark.parametrize("R", [1, 5, 12, 20, 30, 40, 60, 70])
 def test_launch_variants_agree_bitwise(torch_mod, ops, R):
-    """The same product repeated 14 times: the first launches of a shape class are the tuner's
-    timed trials of every candidate (rows per workgroup of the GEMV; tile shape and tile-to-XCD
-    mapping of the GEMMs), the later ones its choice; every result is bitwise the first, in both
-    storage precisions (1280-triangle sphere: split-K and single-split shapes)."""
+    """The same product repeated 28 times: the first launches of a shape class are the tuner's
+    timed trials of every candidate (rows per workgroup of the GEMV; tile shape, operand layout
+    and tile-to-XCD mapping of the GEMMs: at most 8 candidates of 3 trials), the later ones its
+    choice; every result is bitwise the first, in both storage precisions (1280-triangle sphere:
+    split-K and single-split shapes)."""
     torch = torch_mod
     ctx, out = ops
     w, mesh, info, op64, op32, A, A32 = out[3]
@@ -111,7 +112,7 @@ def test_launch_variants_agree_bitwise(torch_mod, ops, R):
     for op, dt, tol, ref_A in ((op64, torch.complex128, 1e-13, A), (op32, torch.complex64, 2e-6, A32)):
         xd = torch.tensor(X.astype(np.complex64) if dt == torch.complex64 else X, dtype=dt, device="cuda")
         first = None
-        for it in range(14):
+        for it in range(28):
             yd = torch.zeros((R, ne), dtype=dt, device="cuda")
             B.bem_apply(ctx, op, B.BEM_BLOCK_LA_BG, xd.data_ptr(), yd.data_ptr(), R)
             torch.cuda.synchronize()
