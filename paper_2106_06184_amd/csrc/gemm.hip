@@ -28,6 +28,9 @@
 
 #include <algorithm>
 #include <cstdlib>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 #include "linalg.h"
 #include "prof.h"
@@ -691,6 +694,65 @@ void launch_3m_variant(const Var3& v, const GemmLaunch& l, const GemmDesc& d, hi
 #undef BEM_G3M
 }
 
+// Workgroups of the canonical variant of tile tn that fit on the device at once (compute units
+// x workgroups per unit), queried once per device, entry type, alignment and tile.
+template <typename TA, bool AL>
+const void* canonical_3m(int tn) {
+  switch (tn) {
+    case 16: return reinterpret_cast<const void*>(&dev::k_gemm3m_f64<TA, AL, 1, 8, 1, false>);
+    case 24: return reinterpret_cast<const void*>(&dev::k_gemm3m_f64<TA, AL, 1, 2, 6, true>);
+    case 32: return reinterpret_cast<const void*>(&dev::k_gemm3m_f64<TA, AL, 1, 8, 2, false>);
+    case 48: return reinterpret_cast<const void*>(&dev::k_gemm3m_f64<TA, AL, 1, 8, 3, false>);
+    default: return reinterpret_cast<const void*>(&dev::k_gemm3m_f64<TA, AL, 2, 8, 2, false>);
+  }
+}
+int64_t resident_3m(int tn, bool f32e, bool aligned) {
+  static std::mutex mu;
+  static std::map<std::tuple<int, int, int, int>, int64_t> cache;
+  int dev = 0;
+  BEM_HIP(hipGetDevice(&dev));
+  const auto key = std::make_tuple(dev, tn, f32e ? 1 : 0, aligned ? 1 : 0);
+  std::lock_guard<std::mutex> g(mu);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  const void* fn = f32e ? (aligned ? canonical_3m<float, true>(tn) : canonical_3m<float, false>(tn))
+                        : (aligned ? canonical_3m<double, true>(tn) : canonical_3m<double, false>(tn));
+  int per_cu = 0, cus = 0;
+  BEM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0));
+  BEM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  const int64_t r = std::max<int64_t>(1, int64_t(per_cu) * cus);
+  cache[key] = r;
+  return r;
+}
+// K split of a 3M product.  The workgroups run in waves of `resident`; a last wave that is
+// nearly empty leaves most of the device idle for a whole workgroup's time.  The smallest split
+// that gives at least four waves is taken (its last wave is then at most a fifth of the time);
+// where no split reaches four waves, the split whose last wave is fullest (ties to the larger
+// split).  Where the right-hand sides exceed 8 MiB only powers of two are taken: workgroups go
+// round-robin over the 8 XCDs, so split s then stays on XCDs s mod 8 and each XCD's L2 holds
+// only its splits' slices (other splits scatter every slice over every XCD).  S <= 16, at
+// least 64 complex K per split, the partials within the workspace.  It depends only on the
+// shape and the device, so results stay bitwise reproducible.
+int64_t split_3m(int64_t tiles, int64_t K, int64_t R, int64_t resident, int64_t smax) {
+  const int64_t top = std::max<int64_t>(1, std::min<int64_t>({kMaxSplit, smax, K / 64}));
+  const bool pow2 = double(K) * double(R) * 16.0 > double(8 << 20);
+  auto allowed = [&](int64_t S) { return !pow2 || (S & (S - 1)) == 0; };
+  for (int64_t S = 1; S <= top; ++S)
+    if (allowed(S) && tiles * S >= 4 * resident) return S;
+  int64_t best = 1;
+  double best_f = 0;
+  for (int64_t S = 1; S <= top; ++S) {
+    if (!allowed(S)) continue;
+    const int64_t W = tiles * S, waves = (W + resident - 1) / resident;
+    const double f = double(W) / double(waves * resident);
+    if (f >= best_f - 1e-9) {
+      best = S;
+      best_f = f;
+    }
+  }
+  return best;
+}
+
 // The float64-arithmetic product on the 3M kernel (d.fp32 = 0: float64 entries, 2: float32).
 void launch_gemm3m(const GemmDesc& d, void* ws, size_t ws_bytes, hipStream_t st) {
   const int tn = ntile_3m(d.nrhs);
@@ -706,7 +768,8 @@ void launch_gemm3m(const GemmDesc& d, void* ws, size_t ws_bytes, hipStream_t st)
   std::vector<Var3> vars = vars_3m(tn);
   if (!aligned) vars.resize(1);
   const int64_t ntm0 = (d.rows + tm_3m(vars[0]) - 1) / tm_3m(vars[0]);
-  l.S = split_for(ntm0 * l.ntn, l.K16);
+  const int64_t smax = std::max<int64_t>(1, int64_t(ws_bytes / (sizeof(double) * size_t(d.rows) * l.ldb)));
+  l.S = split_3m(ntm0 * l.ntn, d.cols, d.nrhs, resident_3m(tn, f32e, aligned), smax);
   l.kc = ((d.cols + l.S - 1) / l.S + dev::CK - 1) / dev::CK * dev::CK;
   const size_t need = l.S > 1 ? size_t(l.S) * d.rows * l.ldb * sizeof(double) : 0;
   if (need > ws_bytes) throw Error(BEM_E_INVALID, "GEMM workspace too small");
