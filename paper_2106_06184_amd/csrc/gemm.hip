@@ -18,12 +18,13 @@
 // k-major so that MFMA operand reads are conflict-free).  The N tile (real columns) is the
 // smallest of 32, 64 and 128 that holds the 2R columns, so a few excitations do not pay for a
 // wide tile of zero columns, and the waves not needed along N go along M.  Where the row and
-// column tiles give fewer than ~2048 workgroups (tall matrices with few columns), K is split S
-// ways: split s of every tile writes its partial product to a workspace and a second kernel sums
-// the S partials in a fixed order (deterministic), applies alpha and accumulates into Y.  With
-// S > 1, split s runs on XCD s mod 8 (workgroups are dealt round-robin), so the slice of the
-// embedded right-hand sides it reads stays in that XCD's L2; with S = 1 the column tiles of one
-// row tile are given to the same XCD and share its L2 copy of the A rows.
+// column tiles give fewer than four waves of the workgroups the device holds at once (tall
+// matrices with few columns), K is split S ways (split_waves): split s of every tile writes its
+// partial product to a workspace and a second kernel sums the S partials in a fixed order
+// (deterministic), applies alpha and accumulates into Y.  With S a power of two, split s runs on
+// XCDs s mod 8 (workgroups are dealt round-robin), so the slice of the right-hand sides it reads
+// stays in those XCDs' L2; with S = 1 the column tiles of one row tile are given to the same XCD
+// and share its L2 copy of the A rows.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -558,12 +559,6 @@ int ntile_f32(int64_t nrhs) {
 int64_t ldb_of(int64_t nrhs, int tn) { return (2 * nrhs + tn - 1) / tn * tn; }
 // the larger leading dimension of the two paths (workspace sizing)
 int64_t ldb_for(int64_t nrhs) { return ldb_of(nrhs, ntile_f32(nrhs)); }
-int64_t split_for(int64_t tiles, int64_t K16) {
-  int64_t S = 1;
-  // at least 8 K steps of 16 per split
-  while (S < kMaxSplit && tiles * S < kTargetWorkgroups && K16 / (2 * S * dev::BK) >= 8) S *= 2;
-  return S;
-}
 struct Var {
   int wn, jn;
 };
@@ -706,36 +701,38 @@ const void* canonical_3m(int tn) {
     default: return reinterpret_cast<const void*>(&dev::k_gemm3m_f64<TA, AL, 2, 8, 2, false>);
   }
 }
-int64_t resident_3m(int tn, bool f32e, bool aligned) {
+// Workgroups of 256 threads of kernel fn that fit on the current device at once.
+int64_t resident_of(const void* fn) {
   static std::mutex mu;
-  static std::map<std::tuple<int, int, int, int>, int64_t> cache;
+  static std::map<std::pair<int, const void*>, int64_t> cache;
   int dev = 0;
   BEM_HIP(hipGetDevice(&dev));
-  const auto key = std::make_tuple(dev, tn, f32e ? 1 : 0, aligned ? 1 : 0);
   std::lock_guard<std::mutex> g(mu);
-  auto it = cache.find(key);
+  auto it = cache.find({dev, fn});
   if (it != cache.end()) return it->second;
-  const void* fn = f32e ? (aligned ? canonical_3m<float, true>(tn) : canonical_3m<float, false>(tn))
-                        : (aligned ? canonical_3m<double, true>(tn) : canonical_3m<double, false>(tn));
   int per_cu = 0, cus = 0;
   BEM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0));
   BEM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   const int64_t r = std::max<int64_t>(1, int64_t(per_cu) * cus);
-  cache[key] = r;
+  cache[{dev, fn}] = r;
   return r;
 }
-// K split of a 3M product.  The workgroups run in waves of `resident`; a last wave that is
+int64_t resident_3m(int tn, bool f32e, bool aligned) {
+  return resident_of(f32e ? (aligned ? canonical_3m<float, true>(tn) : canonical_3m<float, false>(tn))
+                          : (aligned ? canonical_3m<double, true>(tn) : canonical_3m<double, false>(tn)));
+}
+// K split of a product.  The workgroups run in waves of `resident`; a last wave that is
 // nearly empty leaves most of the device idle for a whole workgroup's time.  The smallest split
 // that gives at least four waves is taken (its last wave is then at most a fifth of the time);
 // where no split reaches four waves, the split whose last wave is fullest (ties to the larger
 // split).  Where the right-hand sides exceed 8 MiB only powers of two are taken: workgroups go
 // round-robin over the 8 XCDs, so split s then stays on XCDs s mod 8 and each XCD's L2 holds
-// only its splits' slices (other splits scatter every slice over every XCD).  S <= 16, at
-// least 64 complex K per split, the partials within the workspace.  It depends only on the
-// shape and the device, so results stay bitwise reproducible.
-int64_t split_3m(int64_t tiles, int64_t K, int64_t R, int64_t resident, int64_t smax) {
-  const int64_t top = std::max<int64_t>(1, std::min<int64_t>({kMaxSplit, smax, K / 64}));
-  const bool pow2 = double(K) * double(R) * 16.0 > double(8 << 20);
+// only its splits' slices (other splits scatter every slice over every XCD).  S <= 16 and at
+// most `top` (at least 64 complex K per split, the partials within the workspace).  It depends
+// only on the shape and the device, so results stay bitwise reproducible.
+int64_t split_waves(int64_t tiles, int64_t top, double rhs_bytes, int64_t resident) {
+  top = std::max<int64_t>(1, std::min(top, kMaxSplit));
+  const bool pow2 = rhs_bytes > double(8 << 20);
   auto allowed = [&](int64_t S) { return !pow2 || (S & (S - 1)) == 0; };
   for (int64_t S = 1; S <= top; ++S)
     if (allowed(S) && tiles * S >= 4 * resident) return S;
@@ -751,6 +748,28 @@ int64_t split_3m(int64_t tiles, int64_t K, int64_t R, int64_t resident, int64_t 
     }
   }
   return best;
+}
+
+// Canonical variant of an embedding tile: float32 MFMA (tn real columns) or, up to 8 columns,
+// the float64 kernel's 16-column tile.
+const void* canonical_4m(int tn, bool mfma32, bool f32e, bool aligned) {
+  if (mfma32) {
+    switch (tn) {
+      case 32: return aligned ? reinterpret_cast<const void*>(&dev::k_gemm_f32<true, 1, 1>)
+                              : reinterpret_cast<const void*>(&dev::k_gemm_f32<false, 1, 1>);
+      case 64: return aligned ? reinterpret_cast<const void*>(&dev::k_gemm_f32<true, 1, 2>)
+                              : reinterpret_cast<const void*>(&dev::k_gemm_f32<false, 1, 2>);
+      case 96: return aligned ? reinterpret_cast<const void*>(&dev::k_gemm_f32<true, 1, 3>)
+                              : reinterpret_cast<const void*>(&dev::k_gemm_f32<false, 1, 3>);
+      default: return aligned ? reinterpret_cast<const void*>(&dev::k_gemm_f32<true, 2, 2>)
+                              : reinterpret_cast<const void*>(&dev::k_gemm_f32<false, 2, 2>);
+    }
+  }
+  if (f32e)
+    return aligned ? reinterpret_cast<const void*>(&dev::k_gemm_f64<float, true, 1, 1>)
+                   : reinterpret_cast<const void*>(&dev::k_gemm_f64<float, false, 1, 1>);
+  return aligned ? reinterpret_cast<const void*>(&dev::k_gemm_f64<double, true, 1, 1>)
+                 : reinterpret_cast<const void*>(&dev::k_gemm_f64<double, false, 1, 1>);
 }
 
 // The float64-arithmetic product on the 3M kernel (d.fp32 = 0: float64 entries, 2: float32).
@@ -769,7 +788,8 @@ void launch_gemm3m(const GemmDesc& d, void* ws, size_t ws_bytes, hipStream_t st)
   if (!aligned) vars.resize(1);
   const int64_t ntm0 = (d.rows + tm_3m(vars[0]) - 1) / tm_3m(vars[0]);
   const int64_t smax = std::max<int64_t>(1, int64_t(ws_bytes / (sizeof(double) * size_t(d.rows) * l.ldb)));
-  l.S = split_3m(ntm0 * l.ntn, d.cols, d.nrhs, resident_3m(tn, f32e, aligned), smax);
+  l.S = split_waves(ntm0 * l.ntn, std::min<int64_t>(smax, d.cols / 64), 16.0 * double(d.cols) * double(d.nrhs),
+                    resident_3m(tn, f32e, aligned));
   l.kc = ((d.cols + l.S - 1) / l.S + dev::CK - 1) / dev::CK * dev::CK;
   const size_t need = l.S > 1 ? size_t(l.S) * d.rows * l.ldb * sizeof(double) : 0;
   if (need > ws_bytes) throw Error(BEM_E_INVALID, "GEMM workspace too small");
@@ -833,8 +853,8 @@ void launch_f32_variant(const Var& v, const GemmLaunch& l, const GemmDesc& d, co
 
 size_t gemm_workspace_bytes(int64_t n, int64_t nrhs) {
   // the float64 embedding of the right-hand sides (K16 x ldb doubles, the larger of the two),
-  // then the split-K partials: S M ldb doubles for blocks of up to n rows (S tiles x splits is
-  // at most about kTargetWorkgroups, the tile at most 256 x 128)
+  // then the split-K partials: S M ldb doubles for blocks of up to n rows (the split is capped
+  // by the space given here)
   const int64_t K16 = (2 * n + dev::BK - 1) / dev::BK * dev::BK;
   const int64_t ldb = ldb_for(nrhs);
   const int64_t partial = std::min<int64_t>(kMaxSplit * n * ldb, 2 * kTargetWorkgroups * 256 * 128 + n * ldb);
@@ -863,10 +883,15 @@ void launch_gemm(const GemmDesc& d, void* ws, size_t ws_bytes, hipStream_t st) {
   if (!aligned) vars.resize(1);
   auto tm_of = [&](const Var& v) -> int64_t { return (4 / v.wn) * (mfma32 ? 64 : 32); };
   const int64_t ntm0 = (d.rows + tm_of(vars[0]) - 1) / tm_of(vars[0]);
-  l.S = split_for(ntm0 * l.ntn, l.K16);
-  l.kc = (l.K16 / l.S + dev::BK - 1) / dev::BK * dev::BK;
   const size_t bbytes = size_t(l.K16) * l.ldb * (mfma32 ? sizeof(float) : sizeof(double));
   const size_t poff = (bbytes + 255) / 256 * 256;
+  {
+    const void* fn = canonical_4m(tn, mfma32, d.fp32 != 0, aligned);
+    const int64_t smax =
+        ws_bytes > poff ? int64_t((ws_bytes - poff) / (sizeof(double) * size_t(d.rows) * size_t(l.ldb))) : 1;
+    l.S = split_waves(ntm0 * l.ntn, std::min<int64_t>(smax, l.K16 / 128), double(bbytes), resident_of(fn));
+  }
+  l.kc = ((l.K16 + l.S - 1) / l.S + dev::BK - 1) / dev::BK * dev::BK;
   const size_t need = poff + (l.S > 1 ? size_t(l.S) * d.rows * l.ldb * sizeof(double) : 0);
   if (need > ws_bytes) throw Error(BEM_E_INVALID, "GEMM workspace too small");
   l.P = reinterpret_cast<double*>(static_cast<char*>(ws) + poff);
