@@ -15,9 +15,9 @@
 //
 // Kernels: 256-thread workgroups of four waves; float32 MFMA 32x32x2 (wave tile 64 x 32 JN) or
 // float64 MFMA 4x4x4 four-block (wave tile 32 x 16 JN), K step 16, double-buffered LDS (A stored
-// k-major so that MFMA operand reads are conflict-free).  The N tile (real columns) is the
-// smallest of 32, 64 and 128 that holds the 2R columns, so a few excitations do not pay for a
-// wide tile of zero columns, and the waves not needed along N go along M.  Where the row and
+// k-major so that MFMA operand reads are conflict-free).  The N tile is the smallest of the
+// path's tiles that holds the R columns, so a few excitations do not pay for a wide tile of
+// zero columns, and the waves not needed along N go along M.  Where the row and
 // column tiles give fewer than four waves of the workgroups the device holds at once (tall
 // matrices with few columns), K is split S ways (split_waves): split s of every tile writes its
 // partial product to a workspace and a second kernel sums the S partials in a fixed order
@@ -537,18 +537,17 @@ __global__ void __launch_bounds__(256, 2) k_gemm3m_f64(const TA* __restrict__ A,
 }  // namespace dev
 
 namespace {
-// Work decomposition of one product.  The N tile (real columns) is the smallest one of the path
-// that holds the 2R columns (float64: multiples of 16 up to 128 except 80 and 112; float32:
-// 32, 64, 96, 128).  Each N tile has one or two variants (waves along N x MFMA blocks per
-// wave, so different row tiles); the first is canonical and its row tile alone sets the K
-// split, so all variants sum the same partial products in the same order and agree bitwise.
+// Work decomposition of one product.  The embedding's N tile (real columns) is the smallest one
+// of the path that holds the 2R columns (float32: 32, 64, 96, 128; float64, 3-8 columns: 16).
+// Each N tile has one or more variants (waves along N x MFMA blocks per wave, so different row
+// tiles; for 3M also the operand layout); the first is canonical and its row tile alone sets
+// the K split, so all variants sum the same partial products in the same order and agree
+// bitwise.
 constexpr int64_t kTargetWorkgroups = 2048;
 constexpr int64_t kMaxSplit = 16;
 int ntile_f64(int64_t nrhs) {
-  const int64_t c = 2 * nrhs;
-  for (int t : {16, 32, 48, 64, 96})
-    if (c <= t) return t;
-  return 128;
+  (void)nrhs;  // 3-8 columns (more take the 3M path)
+  return 16;
 }
 int ntile_f32(int64_t nrhs) {
   const int64_t c = 2 * nrhs;
@@ -564,14 +563,8 @@ struct Var {
 };
 // variants per N tile, canonical first
 std::vector<Var> vars_f64(int tn) {
-  switch (tn) {
-    case 16: return {{1, 1}};
-    case 32: return {{1, 2}, {2, 1}};
-    case 48: return {{1, 3}};
-    case 64: return {{1, 4}, {2, 2}};
-    case 96: return {{2, 3}};
-    default: return {{2, 4}, {4, 2}};
-  }
+  (void)tn;
+  return {{1, 1}};
 }
 std::vector<Var> vars_f32(int tn) {
   switch (tn) {
@@ -618,38 +611,12 @@ struct GemmLaunch {
   int xcd;
 };
 
+// The embedding's float64 kernel serves 3-8 columns only (one 16-real-column tile, one variant).
 template <typename TA, bool AL>
-void launch_f64_variant(const Var& v, const GemmLaunch& l, const GemmDesc& d, const double* Bm, hipStream_t st) {
+void launch_f64_variant(const GemmLaunch& l, const GemmDesc& d, const double* Bm, hipStream_t st) {
   const TA* A = static_cast<const TA*>(d.A);
-#define BEM_G64(WN, JN)                                                                                              \
-  hipLaunchKernelGGL((dev::k_gemm_f64<TA, AL, WN, JN>), l.g, dim3(256), 0, st, A, l.lda, Bm, l.ldb, d.rows, l.K,  \
-                     l.K16, l.kc, l.ntn, l.S, l.P, d.Y, d.ldy, d.nrhs, d.alpha, d.accumulate, l.xcd)
-  const int code = v.wn * 10 + v.jn;
-  if constexpr (AL) {
-    switch (code) {
-      case 11: BEM_G64(1, 1); break;
-      case 12: BEM_G64(1, 2); break;
-      case 21: BEM_G64(2, 1); break;
-      case 13: BEM_G64(1, 3); break;
-      case 14: BEM_G64(1, 4); break;
-      case 22: BEM_G64(2, 2); break;
-      case 23: BEM_G64(2, 3); break;
-      case 24: BEM_G64(2, 4); break;
-      case 42: BEM_G64(4, 2); break;
-      default: throw Error(BEM_E_INVALID, "no such float64 GEMM variant");
-    }
-  } else {
-    switch (code) {  // unaligned operands: canonical variants only
-      case 11: BEM_G64(1, 1); break;
-      case 12: BEM_G64(1, 2); break;
-      case 13: BEM_G64(1, 3); break;
-      case 14: BEM_G64(1, 4); break;
-      case 23: BEM_G64(2, 3); break;
-      case 24: BEM_G64(2, 4); break;
-      default: throw Error(BEM_E_INVALID, "no such float64 GEMM variant");
-    }
-  }
-#undef BEM_G64
+  hipLaunchKernelGGL((dev::k_gemm_f64<TA, AL, 1, 1>), l.g, dim3(256), 0, st, A, l.lda, Bm, l.ldb, d.rows, l.K, l.K16,
+                     l.kc, l.ntn, l.S, l.P, d.Y, d.ldy, d.nrhs, d.alpha, d.accumulate, l.xcd);
 }
 
 template <typename TA, bool AL>
@@ -925,12 +892,13 @@ void launch_gemm(const GemmDesc& d, void* ws, size_t ws_bytes, hipStream_t st) {
     {
       TuneScope ts(key, ncand, st);
       const Var v = shape(ts.variant());
+      (void)v;
       if (!d.fp32) {
-        if (aligned) launch_f64_variant<double, true>(v, l, d, Bm, st);
-        else launch_f64_variant<double, false>(v, l, d, Bm, st);
+        if (aligned) launch_f64_variant<double, true>(l, d, Bm, st);
+        else launch_f64_variant<double, false>(l, d, Bm, st);
       } else {
-        if (aligned) launch_f64_variant<float, true>(v, l, d, Bm, st);
-        else launch_f64_variant<float, false>(v, l, d, Bm, st);
+        if (aligned) launch_f64_variant<float, true>(l, d, Bm, st);
+        else launch_f64_variant<float, false>(l, d, Bm, st);
       }
       BEM_HIP(hipGetLastError());
     }
