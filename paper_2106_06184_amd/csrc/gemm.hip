@@ -10,8 +10,8 @@
 // complex multiply-add, as the 4M method.
 //
 // float64 arithmetic above 8 columns instead takes three real products per complex one (3M,
-// k_gemm3m_f64 below): 6 real flops per complex multiply-add.  The float32 path keeps
-// the embedding (3M's cancellation in Im would cost float32 accuracy).
+// k_gemm3m_f64 below): 6 real flops per complex multiply-add.  The float32 path keeps the
+// embedding (in float32 a 3M form would round the operand sums, which float64 holds exactly).
 //
 // Kernels: 256-thread workgroups of four waves; float32 MFMA 32x32x2 (wave tile 64 x 32 JN) or
 // float64 MFMA 4x4x4 four-block (wave tile 32 x 16 JN), K step 16, double-buffered LDS (A stored
