@@ -81,6 +81,15 @@ int bkry_chunks(int64_t n);
 void launch_bmdot(const double2* V, int64_t ldv, int R, int j1, const double2* W, int64_t ldw, int64_t n,
                   double2* part, double2* h, int64_t hstride, hipStream_t st);
 // w_c += sign sum_{i < j_c} V_i,c h[c hstride + i], j_c = jr ? jr[c] : j1
+// Step j >= 1 of Gram-Schmidt with delayed reorthogonalisation (see k_bdcgs2_coef): one pass
+// over V_0..V_j for both projections (into part1 / part2, R (j + 1) bkry_chunks(n) entries each),
+// the per-column coefficients (H columns j - 1 corrected and j written; coef: 2 (j + 1) entries
+// per column at c cstride; rinv: R), and, with update, one pass for v_j <- (V_j - V a) / r and
+// Y <- (Y - V cf) / r.  Without update only the column j - 1 correction is wanted (the last step
+// of a cycle; Y unused).
+void launch_bdcgs2(double2* V, int64_t ldv, int R, int j, double2* Y, int64_t ldy, int64_t n, double2* part1,
+                   double2* part2, double2* H, int64_t hs, int64_t ldh, double2* coef, int64_t cstride, double* rinv,
+                   const int* frozen, bool update, hipStream_t st);
 void launch_bmupdate(const double2* V, int64_t ldv, int R, int j1, const int* jr, const double2* h, int64_t hstride,
                      double sign, double2* W, int64_t ldw, int64_t n, hipStream_t st);
 // out[c ostride] = (||w_c||_2, 0)
@@ -89,10 +98,11 @@ void launch_bnorm(const double2* W, int64_t ldw, int R, int64_t n, double2* part
 // w_c = w_c / nrm[c nstride] (0 when the norm is 0 or frozen[c] is set; frozen may be null)
 void launch_bscale_inv(double2* W, int64_t ldw, int R, int64_t n, const double2* nrm, int64_t nstride,
                        const int* frozen, hipStream_t st);
-// Givens step j of every column: Hessenberg column j of column c at H + c hs + j ldh; cs, sn, y
-// with stride m+1, g and h2 with stride m+2; res[c] = |g_c[j+1]|.
-void launch_bgivens(double2* H, int64_t hs, int64_t ldh, int j, double2* cs, double2* sn, double2* g, double* res,
-                    const double2* h2, int m, int R, hipStream_t st);
+// Givens step j of every column: Hessenberg column j of column c at H + c hs + j ldh, rotated
+// into the same place of HR (HR = H: in place); cs, sn, y with stride m+1, g and h2 with stride
+// m+2; res[c] = |g_c[j+1]|.
+void launch_bgivens(const double2* H, double2* HR, int64_t hs, int64_t ldh, int j, double2* cs, double2* sn,
+                    double2* g, double* res, const double2* h2, int m, int R, hipStream_t st);
 // y_c = R_c^{-1} g_c over the leading jr[c] x jr[c] block
 void launch_bbacksolve(const double2* H, int64_t hs, int64_t ldh, const int* jr, const double2* g, double2* y, int m,
                        int R, hipStream_t st);

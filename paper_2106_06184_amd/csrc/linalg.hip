@@ -467,7 +467,7 @@ __global__ void k_scale_inv(const double2* __restrict__ w, int64_t n, const doub
 // |g_{j+1}| is the residual norm.  Run by one wave: the rotations and the column are staged
 // through LDS in chunks with coalesced loads, so the serial recurrence of lane 0 (the rotated
 // entry carried in registers) reads only LDS.
-__device__ void givens_step(double2* __restrict__ Hcol, int j, const double2* __restrict__ cs_in,
+__device__ void givens_step(const double2* Hcol, double2* Rcol, int j, const double2* __restrict__ cs_in,
                             const double2* __restrict__ sn_in, double2* __restrict__ cs, double2* __restrict__ sn,
                             double2* __restrict__ g, double* __restrict__ res, const double2* __restrict__ h2) {
   constexpr int CH = 256;
@@ -499,7 +499,7 @@ __device__ void givens_step(double2* __restrict__ Hcol, int j, const double2* __
       }
     }
     __syncthreads();
-    for (int e = t; e < cnt; e += nth) Hcol[i0 + e] = sh[e];
+    for (int e = t; e < cnt; e += nth) Rcol[i0 + e] = sh[e];
     __syncthreads();
   }
   if (t != 0) return;
@@ -522,9 +522,9 @@ __device__ void givens_step(double2* __restrict__ Hcol, int j, const double2* __
   }
   cs[j] = make_double2(c, 0);
   sn[j] = s;
-  // new Hcol[j] = c a + s b ; Hcol[j+1] = 0
-  Hcol[j] = make_double2(c * a.x + (s.x * b.x - s.y * b.y), c * a.y + (s.x * b.y + s.y * b.x));
-  Hcol[j + 1] = make_double2(0, 0);
+  // rotated column: R[j] = c a + s b ; R[j+1] = 0
+  Rcol[j] = make_double2(c * a.x + (s.x * b.x - s.y * b.y), c * a.y + (s.x * b.y + s.y * b.x));
+  Rcol[j + 1] = make_double2(0, 0);
   const double2 gj = g[j];
   g[j] = make_double2(c * gj.x, c * gj.y);
   // g[j+1] = -conj(s) g_j
@@ -534,7 +534,7 @@ __device__ void givens_step(double2* __restrict__ Hcol, int j, const double2* __
 
 __global__ void __launch_bounds__(64) k_givens(double2* Hcol, int j, double2* cs, double2* sn, double2* g,
                                                double* res, const double2* h2) {
-  givens_step(Hcol, j, cs, sn, cs, sn, g, res, h2);
+  givens_step(Hcol, Hcol, j, cs, sn, cs, sn, g, res, h2);
 }
 
 // y = R^{-1} g for the leading j x j upper-triangular block of H (column-major, ldh)
@@ -681,6 +681,235 @@ __global__ void __launch_bounds__(256) k_bmupdate(const double2* __restrict__ V,
   }
 }
 
+// ---- Gram-Schmidt with delayed reorthogonalisation (one read of the basis for the two
+// projections of a step, one for the two updates).  Step j holds the basis V_0..V_{j-1}
+// (final) and V_j, the previous step's vector after one projection (tentative), and the
+// product Y = A V_j.
+
+// part1 / part2[(c j1 + i) nch + ch] = chunk sums of conj(V_i,c) X_c and conj(V_i,c) Y_c
+// (j1 = j + 1 basis vectors, X_c = V_j,c): each basis chunk is read once for both.
+__global__ void __launch_bounds__(256) k_bmdot2_part(const double2* __restrict__ V, int64_t ldv, int R, int j1,
+                                                     const double2* __restrict__ X, const double2* __restrict__ Y,
+                                                     int64_t ldy, int64_t n, int nch, double2* __restrict__ part1,
+                                                     double2* __restrict__ part2) {
+  const int ch = blockIdx.x, c = blockIdx.y;
+  const int64_t k0 = int64_t(ch) * kChunk + threadIdx.x;
+  const double2* x = X + int64_t(c) * ldv;
+  const double2* y = Y + int64_t(c) * ldy;
+  double2 xl[kPer], yl[kPer];
+#pragma unroll
+  for (int s = 0; s < kPer; ++s) {
+    const int64_t k = k0 + 256 * s;
+    xl[s] = k < n ? x[k] : make_double2(0, 0);
+    yl[s] = k < n ? y[k] : make_double2(0, 0);
+  }
+  __shared__ double2 red[2][4];
+  const int wv = threadIdx.x / kWave;
+  for (int i = 0; i < j1; ++i) {
+    const double2* v = V + (int64_t(i) * R + c) * ldv;
+    double xr = 0, xi = 0, yr = 0, yi = 0;
+#pragma unroll
+    for (int s = 0; s < kPer; ++s) {
+      const int64_t k = k0 + 256 * s;
+      if (k < n) {
+        const double2 a = v[k];
+        xr += a.x * xl[s].x + a.y * xl[s].y;
+        xi += a.x * xl[s].y - a.y * xl[s].x;
+        yr += a.x * yl[s].x + a.y * yl[s].y;
+        yi += a.x * yl[s].y - a.y * yl[s].x;
+      }
+    }
+    xr = wave_sum(xr);
+    xi = wave_sum(xi);
+    yr = wave_sum(yr);
+    yi = wave_sum(yi);
+    if (threadIdx.x % kWave == 0) {
+      red[0][wv] = make_double2(xr, xi);
+      red[1][wv] = make_double2(yr, yi);
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+      const double2* q = red[threadIdx.x];
+      double2* out = threadIdx.x == 0 ? part1 : part2;
+      out[(int64_t(c) * j1 + i) * nch + ch] = make_double2(q[0].x + q[1].x + q[2].x + q[3].x, q[0].y + q[1].y + q[2].y + q[3].y);
+    }
+    __syncthreads();
+  }
+}
+
+// Same with one block per (chunk, basis vector, column).  Identical summation order.
+__global__ void __launch_bounds__(256) k_bmdot2_part3(const double2* __restrict__ V, int64_t ldv, int R, int j1,
+                                                      const double2* __restrict__ X, const double2* __restrict__ Y,
+                                                      int64_t ldy, int64_t n, int nch, double2* __restrict__ part1,
+                                                      double2* __restrict__ part2) {
+  const int ch = blockIdx.x, i = blockIdx.y, c = blockIdx.z;
+  const int64_t k0 = int64_t(ch) * kChunk + threadIdx.x;
+  const double2* x = X + int64_t(c) * ldv;
+  const double2* y = Y + int64_t(c) * ldy;
+  const double2* v = V + (int64_t(i) * R + c) * ldv;
+  double xr = 0, xi = 0, yr = 0, yi = 0;
+#pragma unroll
+  for (int s = 0; s < kPer; ++s) {
+    const int64_t k = k0 + 256 * s;
+    if (k < n) {
+      const double2 a = v[k], xl = x[k], yl = y[k];
+      xr += a.x * xl.x + a.y * xl.y;
+      xi += a.x * xl.y - a.y * xl.x;
+      yr += a.x * yl.x + a.y * yl.y;
+      yi += a.x * yl.y - a.y * yl.x;
+    }
+  }
+  __shared__ double2 red[2][4];
+  xr = wave_sum(xr);
+  xi = wave_sum(xi);
+  yr = wave_sum(yr);
+  yi = wave_sum(yi);
+  const int wv = threadIdx.x / kWave;
+  if (threadIdx.x % kWave == 0) {
+    red[0][wv] = make_double2(xr, xi);
+    red[1][wv] = make_double2(yr, yi);
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    const double2* q = red[threadIdx.x];
+    double2* out = threadIdx.x == 0 ? part1 : part2;
+    out[(int64_t(c) * j1 + i) * nch + ch] = make_double2(q[0].x + q[1].x + q[2].x + q[3].x, q[0].y + q[1].y + q[2].y + q[3].y);
+  }
+}
+
+// Per column (one block): d1 = V^H V_j and d2 = V^H Y summed over the chunks (j1 = j + 1 entries
+// each), then with a = d1[0..j), alpha = d1[j] the reorthogonalisation of V_j:
+//   r = sqrt(alpha - |a|^2)     (the norm of V_j - V a, the basis before V_j orthonormal)
+//   column j - 1 of H (tentative: its last entry is rho_j, the norm V_j was scaled by):
+//     H[i][j-1] += rho_j a_i,  H[j][j-1] = rho_j r
+//   the new column j: the final v_j = (V_j - V a) / r has the product (Y - V g) / r with
+//     g = H a (A V = V H over the finished columns), so its projection is
+//     H[i][j] = (d_i - g_i) / r,  d = (d2_0, .., d2_{j-1}, (d2_j - a^H d2) / r),
+// and the update coefficients a (coef[0..j)), cf = d (coef[j+1 .. 2j+1], as V g lies in the
+// span the projection removes, the new vector is (Y - V cf) / r) and 1/r.  Frozen columns get
+// a = 0, cf = 0, 1/r = 1, column j zero and column j - 1 untouched.  Sums in a fixed order
+// (deterministic).
+__global__ void __launch_bounds__(64) k_bdcgs2_coef(const double2* __restrict__ part1,
+                                                    const double2* __restrict__ part2, int nch, int j,
+                                                    double2* __restrict__ H, int64_t hs, int64_t ldh,
+                                                    double2* __restrict__ coef, int64_t cstride,
+                                                    double* __restrict__ rinv, const int* __restrict__ frozen) {
+  const int c = blockIdx.x, t = threadIdx.x, j1 = j + 1;
+  double2* cc = coef + int64_t(c) * cstride;
+  double2* d2 = cc + j1;  // scratch for the summed d2 (coef[j1 .. 2 j1))
+  double2* Hc = H + int64_t(c) * hs;
+  const bool fz = frozen && frozen[c];
+  // chunk sums: d1 into coef[0..j1), d2 into coef[j1..2 j1)
+  for (int i = t; i < j1; i += 64) {
+    double ar = 0, ai = 0, br = 0, bi = 0;
+    const double2* p = part1 + (int64_t(c) * j1 + i) * nch;
+    const double2* q = part2 + (int64_t(c) * j1 + i) * nch;
+    for (int ch = 0; ch < nch; ++ch) {
+      ar += p[ch].x;
+      ai += p[ch].y;
+      br += q[ch].x;
+      bi += q[ch].y;
+    }
+    cc[i] = make_double2(ar, ai);
+    d2[i] = make_double2(br, bi);
+  }
+  __syncthreads();
+  // |a|^2 and a^H d2 over i < j, per-lane strided partials then a fixed butterfly
+  double na = 0, pr = 0, pi = 0;
+  for (int i = t; i < j; i += 64) {
+    const double2 a = cc[i], z = d2[i];
+    na += a.x * a.x + a.y * a.y;
+    pr += a.x * z.x + a.y * z.y;
+    pi += a.x * z.y - a.y * z.x;
+  }
+  na = wave_sum(na);
+  pr = wave_sum(pr);
+  pi = wave_sum(pi);
+  const double alpha = cc[j].x;
+  const double r2 = alpha - na;
+  const bool ok = !fz && j > 0 && r2 > 0.0;
+  const double r = ok ? sqrt(r2) : 1.0;
+  const double ir = 1.0 / r;
+  if (!fz && j > 0) {
+    double2* Hp = Hc + int64_t(j - 1) * ldh;
+    const double rho = Hp[j].x;
+    for (int i = t; i < j; i += 64) Hp[i] = make_double2(Hp[i].x + rho * cc[i].x, Hp[i].y + rho * cc[i].y);
+    if (t == 0) Hp[j] = make_double2(rho * r, 0.0);
+  }
+  __syncthreads();
+  double2* Hj = Hc + int64_t(j) * ldh;
+  const double2 zj = d2[j];
+  const double2 last = make_double2((zj.x - pr) * ir * ir, (zj.y - pi) * ir * ir);
+  // H[k][j] = (d_k - g_k) / r with d = (d2_0 .. d2_{j-1}, r last) and g = H a over the finished
+  // columns 0..j-1 (rows k <= j; column i holds rows 0..i+1), each row summed in column order
+  for (int k = t; k <= j; k += 64) {
+    double gr = 0, gi = 0;
+    if (!fz)
+      for (int i = k > 0 ? k - 1 : 0; i < j; ++i) {
+        const double2 h = Hc[int64_t(i) * ldh + k], av = cc[i];
+        gr += h.x * av.x - h.y * av.y;
+        gi += h.x * av.y + h.y * av.x;
+      }
+    const double2 d = k < j ? d2[k] : make_double2(last.x * r, last.y * r);
+    Hj[k] = fz ? make_double2(0, 0) : make_double2((d.x - gr) * ir, (d.y - gi) * ir);
+  }
+  __syncthreads();
+  // update coefficients: cf_i = r H[i][j] = d2_i (i < j), cf_j = r H[j][j]; a zeroed when frozen
+  for (int i = t; i < j; i += 64) {
+    if (fz || j == 0) {
+      cc[i] = make_double2(0, 0);
+      d2[i] = make_double2(0, 0);
+    }
+  }
+  if (t == 0) {
+    d2[j] = fz ? make_double2(0, 0) : make_double2(last.x * r, last.y * r);
+    rinv[c] = ir;
+  }
+}
+
+// v_j <- (V_j - sum_{i<j} V_i a_i) / r;  Y <- (Y - sum_{i<j} V_i cf_i - v_j cf_j) / r, in place
+// (V_j is slot j of V; Y the product).  A block owns 64 consecutive elements; its four waves
+// take the basis vectors i = wave, wave + 4, ... and their partial sums are added in LDS in a
+// fixed order.
+__global__ void __launch_bounds__(256) k_bdcgs2_update(double2* __restrict__ V, int64_t ldv, int R, int j,
+                                                       const double2* __restrict__ coef, int64_t cstride,
+                                                       const double* __restrict__ rinv, double2* __restrict__ Y,
+                                                       int64_t ldy, int64_t n) {
+  const int c = blockIdx.y, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t k = int64_t(blockIdx.x) * 64 + lane;
+  const double2* a = coef + int64_t(c) * cstride;
+  const double2* cf = a + (j + 1);
+  double sa_r = 0, sa_i = 0, sc_r = 0, sc_i = 0;
+  if (k < n) {
+#pragma unroll 4
+    for (int i = wv; i < j; i += 4) {
+      const double2 v = V[(int64_t(i) * R + c) * ldv + k], p = a[i], q = cf[i];
+      sa_r += v.x * p.x - v.y * p.y;
+      sa_i += v.x * p.y + v.y * p.x;
+      sc_r += v.x * q.x - v.y * q.y;
+      sc_i += v.x * q.y + v.y * q.x;
+    }
+  }
+  __shared__ double2 red[2][4][64];
+  red[0][wv][lane] = make_double2(sa_r, sa_i);
+  red[1][wv][lane] = make_double2(sc_r, sc_i);
+  __syncthreads();
+  if (wv == 0 && k < n) {
+    const double ar = ((red[0][0][lane].x + red[0][1][lane].x) + red[0][2][lane].x) + red[0][3][lane].x;
+    const double ai = ((red[0][0][lane].y + red[0][1][lane].y) + red[0][2][lane].y) + red[0][3][lane].y;
+    const double cr = ((red[1][0][lane].x + red[1][1][lane].x) + red[1][2][lane].x) + red[1][3][lane].x;
+    const double ci = ((red[1][0][lane].y + red[1][1][lane].y) + red[1][2][lane].y) + red[1][3][lane].y;
+    const double ir = rinv[c];
+    double2* vj = V + (int64_t(j) * R + c) * ldv + k;
+    const double2 vf = make_double2((vj->x - ar) * ir, (vj->y - ai) * ir);
+    const double2 q = cf[j];
+    double2* y = Y + int64_t(c) * ldy + k;
+    const double yr = y->x - cr - (vf.x * q.x - vf.y * q.y), yi = y->y - ci - (vf.x * q.y + vf.y * q.x);
+    *y = make_double2(yr * ir, yi * ir);
+    *vj = vf;
+  }
+}
+
 __global__ void __launch_bounds__(256) k_bnorm_part(const double2* __restrict__ W, int64_t ldw, int64_t n, int nch,
                                                     double* __restrict__ part) {
   const int ch = blockIdx.x, c = blockIdx.y;
@@ -721,13 +950,16 @@ __global__ void k_bscale_inv(double2* __restrict__ W, int64_t ldw, int64_t n, co
   w[k] = make_double2(w[k].x * s, w[k].y * s);
 }
 
-// one wave per column c
-__global__ void __launch_bounds__(64) k_bgivens(double2* H, int64_t hs, int64_t ldh, int j, double2* cs, double2* sn,
-                                                double2* g, double* res, const double2* h2, int m, int R) {
+// one wave per column c: the raw Hessenberg column j of H rotated into column j of HR (HR = H:
+// in place)
+__global__ void __launch_bounds__(64) k_bgivens(const double2* H, double2* HR, int64_t hs, int64_t ldh, int j,
+                                                double2* cs, double2* sn, double2* g, double* res, const double2* h2,
+                                                int m, int R) {
   const int c = blockIdx.x;
   double2* csc = cs + int64_t(c) * (m + 1);
   double2* snc = sn + int64_t(c) * (m + 1);
-  givens_step(H + int64_t(c) * hs + int64_t(j) * ldh, j, csc, snc, csc, snc, g + int64_t(c) * (m + 2), res + c,
+  const int64_t off = int64_t(c) * hs + int64_t(j) * ldh;
+  givens_step(H + off, HR + off, j, csc, snc, csc, snc, g + int64_t(c) * (m + 2), res + c,
               h2 ? h2 + int64_t(c) * (m + 2) : nullptr);
 }
 
@@ -926,6 +1158,28 @@ void launch_bmdot(const double2* V, int64_t ldv, int R, int j1, const double2* W
   BEM_HIP(hipGetLastError());
 }
 
+void launch_bdcgs2(double2* V, int64_t ldv, int R, int j, double2* Y, int64_t ldy, int64_t n, double2* part1,
+                   double2* part2, double2* H, int64_t hs, int64_t ldh, double2* coef, int64_t cstride, double* rinv,
+                   const int* frozen, bool update, hipStream_t st) {
+  if (R <= 0 || n <= 0) return;
+  const int nch = bkry_chunks(n), j1 = j + 1;
+  const double2* X = V + int64_t(j) * R * ldv;
+  if (int64_t(nch) * R >= 1024)
+    hipLaunchKernelGGL(dev::k_bmdot2_part, dim3(unsigned(nch), unsigned(R)), dim3(256), 0, st, V, ldv, R, j1, X, Y, ldy,
+                       n, nch, part1, part2);
+  else
+    hipLaunchKernelGGL(dev::k_bmdot2_part3, dim3(unsigned(nch), unsigned(j1), unsigned(R)), dim3(256), 0, st, V, ldv,
+                       R, j1, X, Y, ldy, n, nch, part1, part2);
+  BEM_HIP(hipGetLastError());
+  hipLaunchKernelGGL(dev::k_bdcgs2_coef, dim3(unsigned(R)), dim3(64), 0, st, part1, part2, nch, j, H, hs, ldh, coef,
+                     cstride, rinv, frozen);
+  BEM_HIP(hipGetLastError());
+  if (!update) return;
+  hipLaunchKernelGGL(dev::k_bdcgs2_update, dim3(unsigned((n + 63) / 64), unsigned(R)), dim3(256), 0, st, V, ldv, R, j,
+                     coef, cstride, rinv, Y, ldy, n);
+  BEM_HIP(hipGetLastError());
+}
+
 void launch_bmupdate(const double2* V, int64_t ldv, int R, int j1, const int* jr, const double2* h, int64_t hstride,
                      double sign, double2* W, int64_t ldw, int64_t n, hipStream_t st) {
   if (R <= 0 || n <= 0 || (j1 <= 0 && !jr)) return;
@@ -953,10 +1207,11 @@ void launch_bscale_inv(double2* W, int64_t ldw, int R, int64_t n, const double2*
   BEM_HIP(hipGetLastError());
 }
 
-void launch_bgivens(double2* H, int64_t hs, int64_t ldh, int j, double2* cs, double2* sn, double2* g, double* res,
-                    const double2* h2, int m, int R, hipStream_t st) {
+void launch_bgivens(const double2* H, double2* HR, int64_t hs, int64_t ldh, int j, double2* cs, double2* sn,
+                    double2* g, double* res, const double2* h2, int m, int R, hipStream_t st) {
   if (R <= 0) return;
-  hipLaunchKernelGGL(dev::k_bgivens, dim3(unsigned(R)), dim3(64), 0, st, H, hs, ldh, j, cs, sn, g, res, h2, m, R);
+  hipLaunchKernelGGL(dev::k_bgivens, dim3(unsigned(R)), dim3(64), 0, st, H, HR, hs, ldh, j, cs, sn, g, res, h2, m,
+                     R);
   BEM_HIP(hipGetLastError());
 }
 

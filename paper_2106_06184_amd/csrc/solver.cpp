@@ -1726,9 +1726,10 @@ using BApplyFn = std::function<void(const double2* x, int64_t ldx, double2* y, i
 struct BGmres {
   int64_t n = 0, ldv = 0, hs = 0, ldh = 0;
   int m = 0, Rmax = 0;
-  double2 *V = nullptr, *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr, *y = nullptr, *h2 = nullptr;
-  double2 *nrm = nullptr, *part = nullptr, *Z = nullptr, *U = nullptr, *T = nullptr;
-  double* res = nullptr;
+  double2 *V = nullptr, *H = nullptr, *HR = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr, *y = nullptr;
+  double2 *nrm = nullptr, *part = nullptr, *part2 = nullptr, *coef = nullptr, *Z = nullptr, *U = nullptr, *T = nullptr;
+  int64_t cstride = 0;  // per-column coefficients of the delayed reorthogonalisation
+  double *res = nullptr, *rinv = nullptr;
   int *d_frozen = nullptr, *d_jr = nullptr, *d_idx = nullptr;
   // pinned host mirrors
   double2* h_nrm = nullptr;
@@ -1744,14 +1745,18 @@ struct BGmres {
     ldh = m + 2;
     hs = int64_t(m + 1) * ldh;
     V = mem.alloc<double2>(size_t(m + 1) * R * ldv);
-    H = mem.alloc<double2>(size_t(R) * hs);
+    H = mem.alloc<double2>(size_t(R) * hs);   // Hessenberg columns as finished
+    HR = mem.alloc<double2>(size_t(R) * hs);  // the same rotated to triangular (Givens)
     cs = mem.alloc<double2>(size_t(R) * (m + 1));
     sn = mem.alloc<double2>(size_t(R) * (m + 1));
     y = mem.alloc<double2>(size_t(R) * (m + 1));
     g = mem.alloc<double2>(size_t(R) * (m + 2));
-    h2 = mem.alloc<double2>(size_t(R) * (m + 2));
     nrm = mem.alloc<double2>(R);
     part = mem.alloc<double2>(size_t(R) * (m + 1) * bkry_chunks(n));
+    part2 = mem.alloc<double2>(size_t(R) * (m + 1) * bkry_chunks(n));
+    cstride = 2 * int64_t(m + 2);
+    coef = mem.alloc<double2>(size_t(R) * cstride);
+    rinv = mem.alloc<double>(R);
     Z = mem.alloc<double2>(size_t(R) * ldv);
     U = mem.alloc<double2>(size_t(R) * ldv);
     T = mem.alloc<double2>(size_t(R) * ldv);
@@ -1957,6 +1962,13 @@ BResult gmres_batched(BGmres& w, const BApplyFn& A, const double2* B, int64_t ld
       worst_est = worst;
       return changed;
     };
+    // Givens rotation of the finished Hessenberg column s and the copy of its residual estimates
+    auto estimate = [&](int s) {
+      launch_bgivens(w.H, w.HR, w.hs, w.ldh, s, w.cs, w.sn, w.g, w.res, nullptr, m, Rc, st);
+      BEM_HIP(hipMemcpyAsync(w.h_res + size_t(s & 1) * w.Rmax, w.res, sizeof(double) * Rc, hipMemcpyDeviceToHost,
+                             st));
+      BEM_HIP(hipEventRecord(w.ev[s & 1], st));
+    };
     bool lo = false;
     for (; j < m && total < maxit; ++j) {
       double2* Vj = w.V + int64_t(j) * Rc * ldv;
@@ -1991,19 +2003,23 @@ BResult gmres_batched(BGmres& w, const BApplyFn& A, const double2* B, int64_t ld
         Aj(Vj, ldv, Vn, ldv, Rc);
       }
       ++out.products;
-      launch_bmdot(w.V, ldv, Rc, j + 1, Vn, ldv, n, w.part, Hj, w.hs, st);
-      launch_bmupdate(w.V, ldv, Rc, j + 1, nullptr, Hj, w.hs, -1.0, Vn, ldv, n, st);
-      launch_bmdot(w.V, ldv, Rc, j + 1, Vn, ldv, n, w.part, w.h2, m + 2, st);
-      launch_bmupdate(w.V, ldv, Rc, j + 1, nullptr, w.h2, m + 2, -1.0, Vn, ldv, n, st);
+      // Gram-Schmidt with delayed reorthogonalisation: V_j left the previous step after one
+      // projection; this step's single pass over the basis reorthogonalises V_j (finishing
+      // Hessenberg column j - 1, whose Givens rotation and residual estimate follow) and
+      // projects the product, which then also leaves after one projection.
+      if (j == 0) {
+        launch_bmdot(w.V, ldv, Rc, 1, Vn, ldv, n, w.part, Hj, w.hs, st);
+        launch_bmupdate(w.V, ldv, Rc, 1, nullptr, Hj, w.hs, -1.0, Vn, ldv, n, st);
+      } else {
+        launch_bdcgs2(w.V, ldv, Rc, j, Vn, ldv, n, w.part, w.part2, w.H, w.hs, w.ldh, w.coef, w.cstride, w.rinv,
+                      w.d_frozen, true, st);
+        estimate(j - 1);
+      }
       launch_bnorm(Vn, ldv, Rc, n, w.part, Hj + j + 1, w.hs, st);
       launch_bscale_inv(Vn, ldv, Rc, n, Hj + j + 1, w.hs, w.d_frozen, st);
-      launch_bgivens(w.H, w.hs, w.ldh, j, w.cs, w.sn, w.g, w.res, w.h2, m, Rc, st);
       ++total;
-      BEM_HIP(hipMemcpyAsync(w.h_res + size_t(j & 1) * w.Rmax, w.res, sizeof(double) * Rc, hipMemcpyDeviceToHost,
-                             st));
-      BEM_HIP(hipEventRecord(w.ev[j & 1], st));
-      if (j >= 1) {
-        if (examine(j - 1)) {
+      if (j >= 2) {
+        if (examine(j - 2)) {
           // stage the new flags in this step's slot (the slot of step j - 2 is free: its copy
           // was enqueued before the event just waited for)
           int* fz = w.h_fz + size_t(j & 1) * w.Rmax;
@@ -2016,11 +2032,18 @@ BResult gmres_batched(BGmres& w, const BApplyFn& A, const double2* B, int64_t ld
         }
       }
     }
-    if (live > 0 && j >= 1) examine(j - 1);  // the last step's estimates
+    if (live > 0 && j >= 1) {
+      // the last column: reorthogonalise the last vector against the basis (no new product)
+      launch_bdcgs2(w.V, ldv, Rc, j, w.V + int64_t(j) * Rc * ldv, ldv, n, w.part, w.part2, w.H, w.hs, w.ldh, w.coef,
+                    w.cstride, w.rinv, w.d_frozen, false, st);
+      estimate(j - 1);
+      if (j >= 2) examine(j - 2);
+      if (live > 0) examine(j - 1);
+    }
     for (int c = 0; c < Rc; ++c)
       if (!frozen[c]) w.h_jr[c] = j;
     w.upload(w.d_jr, w.h_jr, Rc, st);
-    launch_bbacksolve(w.H, w.hs, w.ldh, w.d_jr, w.g, w.y, m, Rc, st);
+    launch_bbacksolve(w.HR, w.hs, w.ldh, w.d_jr, w.g, w.y, m, Rc, st);
     // X[:, active] += M (V y)
     launch_axpby(n, c2(0.0), nullptr, c2(0.0), nullptr, w.U, st, Rc, 0, 0, ldv);
     launch_bmupdate(w.V, ldv, Rc, 0, w.d_jr, w.y, m + 1, +1.0, w.U, ldv, n, st);
@@ -2164,7 +2187,9 @@ size_t estimate_request_bytes(int64_t nt, int64_t nobj, int precision, int resta
   const double inner = per * inv_entries;
   const double R = double(std::min<int64_t>(std::max<int64_t>(nexc, 1), kMaxBatch));
   const double ldN = double(pad64(int64_t(N)));
-  const double solve = 16.0 * R * (ldN * (restart + 1 + 3 + 4) + double(kWorkFields) * pad64(int64_t(neq))) +
+  const double m = restart;
+  const double solve = 16.0 * R * (ldN * (m + 1 + 3 + 4) + double(kWorkFields) * pad64(int64_t(neq)) +
+                                   2.0 * (m + 1) * (m + 2)) +
                        double(gemm_workspace_bytes(int64_t(std::max(ne, double(nt))), int64_t(R))) +
                        16.0 * (ne * (nexc + 1) + 2 * 64.0 * neq);
   const double assembly = std::max(dense_fill + fill_scratch, dense_fill + per_fill * inv_entries);
@@ -2211,7 +2236,8 @@ int solve_op(OpObj& op, const bem_excitation* exc, int64_t nexc, const bem_solve
   {
     auto est = [&](int R) {
       const double ldN = double(pad64(N)), m = opts.restart;
-      return 16.0 * R * (ldN * (m + 1 + 3 + 5) + double(kWorkFields) * work_ld(op)) +
+      // basis, work columns, Hessenberg matrices (as finished and rotated)
+      return 16.0 * R * (ldN * (m + 1 + 3 + 5) + double(kWorkFields) * work_ld(op) + 2.0 * (m + 1) * (m + 2)) +
              double(gemm_workspace_bytes(std::max(ne, nt), R));
     };
     size_t avail;
