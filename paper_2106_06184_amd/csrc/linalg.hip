@@ -687,12 +687,14 @@ __global__ void __launch_bounds__(256) k_bmupdate(const double2* __restrict__ V,
 // product Y = A V_j.
 
 // part1 / part2[(c j1 + i) nch + ch] = chunk sums of conj(V_i,c) X_c and conj(V_i,c) Y_c
-// (j1 = j + 1 basis vectors, X_c = V_j,c): each basis chunk is read once for both.
+// (j1 = j + 1 basis vectors, X_c = V_j,c): each basis chunk is read once for both.  Block
+// (ch, c, q) takes basis vectors [q G, (q + 1) G) with its chunk of X and Y held in registers.
 __global__ void __launch_bounds__(256) k_bmdot2_part(const double2* __restrict__ V, int64_t ldv, int R, int j1,
-                                                     const double2* __restrict__ X, const double2* __restrict__ Y,
-                                                     int64_t ldy, int64_t n, int nch, double2* __restrict__ part1,
-                                                     double2* __restrict__ part2) {
+                                                     int G, const double2* __restrict__ X,
+                                                     const double2* __restrict__ Y, int64_t ldy, int64_t n, int nch,
+                                                     double2* __restrict__ part1, double2* __restrict__ part2) {
   const int ch = blockIdx.x, c = blockIdx.y;
+  const int ib = int(blockIdx.z) * G, ie = min(j1, ib + G);
   const int64_t k0 = int64_t(ch) * kChunk + threadIdx.x;
   const double2* x = X + int64_t(c) * ldv;
   const double2* y = Y + int64_t(c) * ldy;
@@ -705,7 +707,7 @@ __global__ void __launch_bounds__(256) k_bmdot2_part(const double2* __restrict__
   }
   __shared__ double2 red[2][4];
   const int wv = threadIdx.x / kWave;
-  for (int i = 0; i < j1; ++i) {
+  for (int i = ib; i < ie; ++i) {
     const double2* v = V + (int64_t(i) * R + c) * ldv;
     double xr = 0, xi = 0, yr = 0, yi = 0;
 #pragma unroll
@@ -737,46 +739,6 @@ __global__ void __launch_bounds__(256) k_bmdot2_part(const double2* __restrict__
   }
 }
 
-// Same with one block per (chunk, basis vector, column).  Identical summation order.
-__global__ void __launch_bounds__(256) k_bmdot2_part3(const double2* __restrict__ V, int64_t ldv, int R, int j1,
-                                                      const double2* __restrict__ X, const double2* __restrict__ Y,
-                                                      int64_t ldy, int64_t n, int nch, double2* __restrict__ part1,
-                                                      double2* __restrict__ part2) {
-  const int ch = blockIdx.x, i = blockIdx.y, c = blockIdx.z;
-  const int64_t k0 = int64_t(ch) * kChunk + threadIdx.x;
-  const double2* x = X + int64_t(c) * ldv;
-  const double2* y = Y + int64_t(c) * ldy;
-  const double2* v = V + (int64_t(i) * R + c) * ldv;
-  double xr = 0, xi = 0, yr = 0, yi = 0;
-#pragma unroll
-  for (int s = 0; s < kPer; ++s) {
-    const int64_t k = k0 + 256 * s;
-    if (k < n) {
-      const double2 a = v[k], xl = x[k], yl = y[k];
-      xr += a.x * xl.x + a.y * xl.y;
-      xi += a.x * xl.y - a.y * xl.x;
-      yr += a.x * yl.x + a.y * yl.y;
-      yi += a.x * yl.y - a.y * yl.x;
-    }
-  }
-  __shared__ double2 red[2][4];
-  xr = wave_sum(xr);
-  xi = wave_sum(xi);
-  yr = wave_sum(yr);
-  yi = wave_sum(yi);
-  const int wv = threadIdx.x / kWave;
-  if (threadIdx.x % kWave == 0) {
-    red[0][wv] = make_double2(xr, xi);
-    red[1][wv] = make_double2(yr, yi);
-  }
-  __syncthreads();
-  if (threadIdx.x < 2) {
-    const double2* q = red[threadIdx.x];
-    double2* out = threadIdx.x == 0 ? part1 : part2;
-    out[(int64_t(c) * j1 + i) * nch + ch] = make_double2(q[0].x + q[1].x + q[2].x + q[3].x, q[0].y + q[1].y + q[2].y + q[3].y);
-  }
-}
-
 // Per column (one block): d1 = V^H V_j and d2 = V^H Y summed over the chunks (j1 = j + 1 entries
 // each), then with a = d1[0..j), alpha = d1[j] the reorthogonalisation of V_j:
 //   r = sqrt(alpha - |a|^2)     (the norm of V_j - V a, the basis before V_j orthonormal)
@@ -789,18 +751,21 @@ __global__ void __launch_bounds__(256) k_bmdot2_part3(const double2* __restrict_
 // span the projection removes, the new vector is (Y - V cf) / r) and 1/r.  Frozen columns get
 // a = 0, cf = 0, 1/r = 1, column j zero and column j - 1 untouched.  Sums in a fixed order
 // (deterministic).
-__global__ void __launch_bounds__(64) k_bdcgs2_coef(const double2* __restrict__ part1,
-                                                    const double2* __restrict__ part2, int nch, int j,
-                                                    double2* __restrict__ H, int64_t hs, int64_t ldh,
-                                                    double2* __restrict__ coef, int64_t cstride,
-                                                    double* __restrict__ rinv, const int* __restrict__ frozen) {
+constexpr int kCoefThreads = 256;
+__global__ void __launch_bounds__(kCoefThreads) k_bdcgs2_coef(const double2* __restrict__ part1,
+                                                              const double2* __restrict__ part2, int nch, int j,
+                                                              double2* __restrict__ H, int64_t hs, int64_t ldh,
+                                                              double2* __restrict__ coef, int64_t cstride,
+                                                              double* __restrict__ rinv,
+                                                              const int* __restrict__ frozen) {
+  constexpr int NT = kCoefThreads;
   const int c = blockIdx.x, t = threadIdx.x, j1 = j + 1;
   double2* cc = coef + int64_t(c) * cstride;
-  double2* d2 = cc + j1;  // scratch for the summed d2 (coef[j1 .. 2 j1))
+  double2* d2 = cc + j1;  // the summed d2 (coef[j1 .. 2 j1)), then the update coefficients
   double2* Hc = H + int64_t(c) * hs;
   const bool fz = frozen && frozen[c];
   // chunk sums: d1 into coef[0..j1), d2 into coef[j1..2 j1)
-  for (int i = t; i < j1; i += 64) {
+  for (int i = t; i < j1; i += NT) {
     double ar = 0, ai = 0, br = 0, bi = 0;
     const double2* p = part1 + (int64_t(c) * j1 + i) * nch;
     const double2* q = part2 + (int64_t(c) * j1 + i) * nch;
@@ -814,9 +779,10 @@ __global__ void __launch_bounds__(64) k_bdcgs2_coef(const double2* __restrict__ 
     d2[i] = make_double2(br, bi);
   }
   __syncthreads();
-  // |a|^2 and a^H d2 over i < j, per-lane strided partials then a fixed butterfly
+  // |a|^2 and a^H d2 over i < j: strided partials, a fixed butterfly per wave, the four waves in
+  // order
   double na = 0, pr = 0, pi = 0;
-  for (int i = t; i < j; i += 64) {
+  for (int i = t; i < j; i += NT) {
     const double2 a = cc[i], z = d2[i];
     na += a.x * a.x + a.y * a.y;
     pr += a.x * z.x + a.y * z.y;
@@ -825,6 +791,16 @@ __global__ void __launch_bounds__(64) k_bdcgs2_coef(const double2* __restrict__ 
   na = wave_sum(na);
   pr = wave_sum(pr);
   pi = wave_sum(pi);
+  __shared__ double red[3][NT / kWave];
+  if (t % kWave == 0) {
+    red[0][t / kWave] = na;
+    red[1][t / kWave] = pr;
+    red[2][t / kWave] = pi;
+  }
+  __syncthreads();
+  na = ((red[0][0] + red[0][1]) + red[0][2]) + red[0][3];
+  pr = ((red[1][0] + red[1][1]) + red[1][2]) + red[1][3];
+  pi = ((red[2][0] + red[2][1]) + red[2][2]) + red[2][3];
   const double alpha = cc[j].x;
   const double r2 = alpha - na;
   const bool ok = !fz && j > 0 && r2 > 0.0;
@@ -833,7 +809,7 @@ __global__ void __launch_bounds__(64) k_bdcgs2_coef(const double2* __restrict__ 
   if (!fz && j > 0) {
     double2* Hp = Hc + int64_t(j - 1) * ldh;
     const double rho = Hp[j].x;
-    for (int i = t; i < j; i += 64) Hp[i] = make_double2(Hp[i].x + rho * cc[i].x, Hp[i].y + rho * cc[i].y);
+    for (int i = t; i < j; i += NT) Hp[i] = make_double2(Hp[i].x + rho * cc[i].x, Hp[i].y + rho * cc[i].y);
     if (t == 0) Hp[j] = make_double2(rho * r, 0.0);
   }
   __syncthreads();
@@ -842,7 +818,7 @@ __global__ void __launch_bounds__(64) k_bdcgs2_coef(const double2* __restrict__ 
   const double2 last = make_double2((zj.x - pr) * ir * ir, (zj.y - pi) * ir * ir);
   // H[k][j] = (d_k - g_k) / r with d = (d2_0 .. d2_{j-1}, r last) and g = H a over the finished
   // columns 0..j-1 (rows k <= j; column i holds rows 0..i+1), each row summed in column order
-  for (int k = t; k <= j; k += 64) {
+  for (int k = t; k <= j; k += NT) {
     double gr = 0, gi = 0;
     if (!fz)
       for (int i = k > 0 ? k - 1 : 0; i < j; ++i) {
@@ -854,8 +830,9 @@ __global__ void __launch_bounds__(64) k_bdcgs2_coef(const double2* __restrict__ 
     Hj[k] = fz ? make_double2(0, 0) : make_double2((d.x - gr) * ir, (d.y - gi) * ir);
   }
   __syncthreads();
-  // update coefficients: cf_i = r H[i][j] = d2_i (i < j), cf_j = r H[j][j]; a zeroed when frozen
-  for (int i = t; i < j; i += 64) {
+  // update coefficients: cf = d (cf_i = d2_i for i < j, cf_j = r last); a and cf zeroed when
+  // frozen
+  for (int i = t; i < j; i += NT) {
     if (fz || j == 0) {
       cc[i] = make_double2(0, 0);
       d2[i] = make_double2(0, 0);
@@ -1164,15 +1141,15 @@ void launch_bdcgs2(double2* V, int64_t ldv, int R, int j, double2* Y, int64_t ld
   if (R <= 0 || n <= 0) return;
   const int nch = bkry_chunks(n), j1 = j + 1;
   const double2* X = V + int64_t(j) * R * ldv;
-  if (int64_t(nch) * R >= 1024)
-    hipLaunchKernelGGL(dev::k_bmdot2_part, dim3(unsigned(nch), unsigned(R)), dim3(256), 0, st, V, ldv, R, j1, X, Y, ldy,
-                       n, nch, part1, part2);
-  else
-    hipLaunchKernelGGL(dev::k_bmdot2_part3, dim3(unsigned(nch), unsigned(j1), unsigned(R)), dim3(256), 0, st, V, ldv,
-                       R, j1, X, Y, ldy, n, nch, part1, part2);
+  // basis vectors per block: enough blocks (about 2048) to fill the device, few re-reads of X, Y
+  const int64_t want = std::max<int64_t>(1, (2048 + int64_t(nch) * R - 1) / (int64_t(nch) * R));
+  const int G = int((j1 + std::min<int64_t>(want, j1) - 1) / std::min<int64_t>(want, j1));
+  const int ng = (j1 + G - 1) / G;
+  hipLaunchKernelGGL(dev::k_bmdot2_part, dim3(unsigned(nch), unsigned(R), unsigned(ng)), dim3(256), 0, st, V, ldv, R,
+                     j1, G, X, Y, ldy, n, nch, part1, part2);
   BEM_HIP(hipGetLastError());
-  hipLaunchKernelGGL(dev::k_bdcgs2_coef, dim3(unsigned(R)), dim3(64), 0, st, part1, part2, nch, j, H, hs, ldh, coef,
-                     cstride, rinv, frozen);
+  hipLaunchKernelGGL(dev::k_bdcgs2_coef, dim3(unsigned(R)), dim3(dev::kCoefThreads), 0, st, part1, part2, nch, j, H,
+                     hs, ldh, coef, cstride, rinv, frozen);
   BEM_HIP(hipGetLastError());
   if (!update) return;
   hipLaunchKernelGGL(dev::k_bdcgs2_update, dim3(unsigned((n + 63) / 64), unsigned(R)), dim3(256), 0, st, V, ldv, R, j,
