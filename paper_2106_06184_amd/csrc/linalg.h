@@ -131,6 +131,10 @@ void launch_FD(const double2* u, const int32_t* tri_edge, const int8_t* tri_sign
 // y (+)= s * S x for a CSR real sparse matrix S
 void launch_spmv(const int64_t* ptr, const int32_t* idx, const double* val, int64_t rows, const double2* x,
                  double2 s, double2* y, int accumulate, hipStream_t st, int R = 1, int64_t ldx = 0, int64_t ldy = 0);
+// y1 (+)= s1 A x and y2 (+)= s2 A x (acc1, acc2: accumulate) in one pass, R columns.
+void launch_spmv2(const int64_t* ptr, const int32_t* idx, const double* val, int64_t rows, const double2* x,
+                  int64_t ldx, double2 s1, double2* y1, int64_t ldy1, int acc1, double2 s2, double2* y2, int64_t ldy2,
+                  int acc2, hipStream_t st, int R);
 // z = a*x + b*y (elementwise, n; x or y may be null)
 void launch_axpby(int64_t n, double2 a, const double2* x, double2 b, const double2* y, double2* z,
                   hipStream_t st, int R = 1, int64_t ldx = 0, int64_t ldy = 0, int64_t ldz = 0);

@@ -358,6 +358,32 @@ __global__ void k_spmv(const int64_t* __restrict__ ptr, const int32_t* __restric
   y[r] = make_double2(yr, yi);
 }
 
+// The same product added to two outputs with their own scales: y1 (+)= s1 A x, y2 (+)= s2 A x
+// (one pass over A and x).
+__global__ void k_spmv2(const int64_t* __restrict__ ptr, const int32_t* __restrict__ idx,
+                        const double* __restrict__ val, int64_t rows, const double2* __restrict__ x, int64_t ldx,
+                        double2 s1, double2* __restrict__ y1, int64_t ldy1, int acc1, double2 s2,
+                        double2* __restrict__ y2, int64_t ldy2, int acc2) {
+  const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  x += int64_t(blockIdx.y) * ldx;
+  y1 += int64_t(blockIdx.y) * ldy1;
+  y2 += int64_t(blockIdx.y) * ldy2;
+  double ar = 0, ai = 0;
+  for (int64_t p = ptr[r]; p < ptr[r + 1]; ++p) {
+    const double2 v = x[idx[p]];
+    ar += val[p] * v.x;
+    ai += val[p] * v.y;
+  }
+  double yr = s1.x * ar - s1.y * ai, yi = s1.x * ai + s1.y * ar;
+  if (acc1) { yr += y1[r].x; yi += y1[r].y; }
+  y1[r] = make_double2(yr, yi);
+  yr = s2.x * ar - s2.y * ai;
+  yi = s2.x * ai + s2.y * ar;
+  if (acc2) { yr += y2[r].x; yi += y2[r].y; }
+  y2[r] = make_double2(yr, yi);
+}
+
 __global__ void k_axpby(int64_t n, double2 a, const double2* __restrict__ x, double2 b, const double2* __restrict__ y,
                         double2* __restrict__ z, int64_t ldx, int64_t ldy, int64_t ldz) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -1037,6 +1063,15 @@ void launch_spmv(const int64_t* ptr, const int32_t* idx, const double* val, int6
   if (R <= 0) return;
   hipLaunchKernelGGL(dev::k_spmv, dim3(unsigned((rows + 255) / 256), unsigned(R)), dim3(256), 0, st, ptr, idx, val,
                      rows, x, s, y, accumulate, ldx, ldy);
+  BEM_HIP(hipGetLastError());
+}
+
+void launch_spmv2(const int64_t* ptr, const int32_t* idx, const double* val, int64_t rows, const double2* x,
+                  int64_t ldx, double2 s1, double2* y1, int64_t ldy1, int acc1, double2 s2, double2* y2, int64_t ldy2,
+                  int acc2, hipStream_t st, int R) {
+  if (R <= 0 || rows <= 0) return;
+  hipLaunchKernelGGL(dev::k_spmv2, dim3(unsigned((rows + 255) / 256), unsigned(R)), dim3(256), 0, st, ptr, idx, val,
+                     rows, x, ldx, s1, y1, ldy1, acc1, s2, y2, ldy2, acc2);
   BEM_HIP(hipGetLastError());
 }
 

@@ -1251,9 +1251,8 @@ void eaefie_cols(OpObj& op, const WorkView& wv, const double2* x, int64_t ldx, d
   ds.push_back(with_ld(d1, ldx, ldy, ldx));
   ds.push_back(with_ld(desc(op.Lphi_bg, fp32, 0, 0, op.nt, op.nt, wv.t1, wv.z2, c2(1.0), 0), L, L));
   products(op, ds, wv, st);
-  launch_spmv(op.ix_ptr, op.ix_idx, op.ix_val, ne, e, c2(-0.5), y2, 1, st, R, ldx, ldy);
+  launch_spmv2(op.ix_ptr, op.ix_idx, op.ix_val, ne, e, ldx, c2(-0.5), y2, ldy, 1, c2(0.5), y1, ldy, 1, st, R);
   launch_DT(wv.z1, op.tp, op.tm, ne, c2(1.0), op.eps_inv_edge, y2, 1, st, R, L, ldy);
-  launch_spmv(op.ix_ptr, op.ix_idx, op.ix_val, ne, e, c2(0.5), y1, 1, st, R, ldx, ldy);
   launch_DT(wv.z2, op.tp, op.tm, ne, c2(1.0 / op.eps_bg), nullptr, y1, 1, st, R, L, ldy);
   launch_FD(a, op.tri_edge, op.tri_sign, op.kept, op.nq, c2(1.0), x3, c2(op.k0 * op.k0), y3, st, R, ldx, ldx, ldy);
   op.last_inner_iters = 0;
@@ -1290,8 +1289,7 @@ void final_cols(OpObj& op, const WorkView& wv, const double2* x, int64_t ldx, do
   }
   products(op, ds, wv, st);
   // r_in += I_x e / 2 ; y2 += -I_x e / 2 + eps_c^-1 D^T z1
-  launch_spmv(op.ix_ptr, op.ix_idx, op.ix_val, ne, e, c2(0.5), wv.rin, 1, st, R, ldx, L);
-  launch_spmv(op.ix_ptr, op.ix_idx, op.ix_val, ne, e, c2(-0.5), y2, 1, st, R, ldx, ldy);
+  launch_spmv2(op.ix_ptr, op.ix_idx, op.ix_val, ne, e, ldx, c2(0.5), wv.rin, L, 1, c2(-0.5), y2, ldy, 1, st, R);
   launch_DT(wv.z1, op.tp, op.tm, ne, c2(1.0), op.eps_inv_edge, y2, 1, st, R, L, ldy);
   nested_from_rin(op, wv, fp32, inner_tol, st);
   const double2* u = wv.sol;
