@@ -59,11 +59,45 @@ __device__ __forceinline__ void cv_add(cv3& a, cv3 b) {
   a.x = cadd(a.x, b.x); a.y = cadd(a.y, b.y); a.z = cadd(a.z, b.z);
 }
 
+// sin and cos of x for |x| < 2^20: x = n pi/2 + r with n = rint(2x / pi) and r reduced by the
+// three-part split of pi/2 (Cody and Waite), each part subtracted by a fused multiply-add;
+// Taylor polynomials of sin and cos on |r| <= pi/4 (truncation below 7e-17 relative); the
+// quadrant n mod 4 picks and signs the pair.
+__device__ __forceinline__ void sincos_reduced(double x, double* s, double* c) {
+  constexpr double kTwoOverPi = 0x1.45f306dc9c883p-1;
+  constexpr double kP1 = 0x1.921fb54442d18p+0, kP2 = 0x1.1a62633145c07p-54, kP3 = -0x1.f1976b7ed8fbcp-110;
+  const double n = rint(x * kTwoOverPi);
+  const double r = fma(-n, kP3, fma(-n, kP2, fma(-n, kP1, x)));
+  const double r2 = r * r;
+  // sin r = r (1 - r^2/3! + r^4/5! - ... - r^14/15!),  cos r = 1 - r^2/2! + ... + r^16/16!
+  double ps = -7.6471637318198164759e-13;              // -1/15!
+  ps = fma(ps, r2, 1.6059043836821614599e-10);        //  1/13!
+  ps = fma(ps, r2, -2.5052108385441718775e-08);       // -1/11!
+  ps = fma(ps, r2, 2.7557319223985890653e-06);        //  1/9!
+  ps = fma(ps, r2, -1.9841269841269841270e-04);       // -1/7!
+  ps = fma(ps, r2, 8.3333333333333333333e-03);        //  1/5!
+  ps = fma(ps, r2, -1.6666666666666666667e-01);       // -1/3!
+  const double sr = fma(r * r2, ps, r);
+  double pc = 4.7794773323873852974e-14;               //  1/16!
+  pc = fma(pc, r2, -1.1470745597729724714e-11);       // -1/14!
+  pc = fma(pc, r2, 2.0876756987868098979e-09);        //  1/12!
+  pc = fma(pc, r2, -2.7557319223985890653e-07);       // -1/10!
+  pc = fma(pc, r2, 2.4801587301587301587e-05);        //  1/8!
+  pc = fma(pc, r2, -1.3888888888888888889e-03);       // -1/6!
+  pc = fma(pc, r2, 4.1666666666666666667e-02);        //  1/4!
+  pc = fma(pc, r2, -0.5);                              // -1/2!
+  const double cr = fma(r2, pc, 1.0);
+  const int q = int(int64_t(n) & 3);
+  const double ss = (q & 1) ? cr : sr, cc = (q & 1) ? sr : cr;
+  *s = (q & 2) ? -ss : ss;
+  *c = ((q + 1) & 2) ? -cc : cc;
+}
+
 // e^{-jkR} for k = kr + j ki  ->  e^{ki R} (cos kr R - j sin kr R)
 template <bool LOSSY>
 __device__ __forceinline__ cz expjkr(double kr, double ki, double R) {
   double s, c;
-  sincos(kr * R, &s, &c);
+  sincos_reduced(kr * R, &s, &c);
   if (LOSSY) {
     double a = exp(ki * R);
     return {a * c, -a * s};
