@@ -131,7 +131,7 @@ __device__ inline cz green_rem(double kr, double ki, double R) {
   double az = sqrt(z.re * z.re + z.im * z.im);
   if (az >= kSeriesKR) {
     double ea = exp(z.re), s, c;
-    sincos(z.im, &s, &c);
+    sincos_reduced(z.im, &s, &c);
     cz em1 = {ea * c - 1.0, ea * s};
     double w = kInv4Pi / R;
     return {w * em1.re, w * em1.im};
