@@ -267,7 +267,9 @@ typedef struct {
   double tol;                   /* relative residual ||b - A x|| / ||b|| in float64 */
   int restart;                  /* GMRES restart length; <= 0: automatic, the longest cycle (100 to
                                    1000 steps) whose Krylov basis for the batch of excitations
-                                   stays under 8 GB */
+                                   stays under 8 GB, lengthened (up to 1000 steps, the basis
+                                   within a quarter of the free budget) for the later sweeps when
+                                   a sweep runs out of steps */
   int maxit;                    /* total outer iteration limit */
   double inner_tol;             /* relative tolerance of the equivalent-configuration solve;
                                    <= 0 selects 0.1 * tol */
@@ -285,6 +287,7 @@ typedef struct {
   int graph_steps;              /* Arnoldi steps whose product was replayed from a captured HIP
                                    graph (small operators without a nested GMRES; BEM_GRAPH=0
                                    in the environment turns the capture off) */
+  int cycle_growths;            /* times the automatic restart cycle was lengthened */
 } bem_solve_info;
 
 /* Solve eq. finalsystem for nexc excitations (right-hand side of eq.

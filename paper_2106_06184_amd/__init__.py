@@ -74,7 +74,7 @@ class bem_solve_opts(C.Structure):
 class bem_solve_info(C.Structure):
     _fields_ = [("outer_iters", C.c_int), ("inner_iters_max", C.c_int), ("refine_steps", C.c_int),
                 ("n_products", C.c_int), ("rel_residual", C.c_double), ("seconds", C.c_double),
-                ("graph_steps", C.c_int)]
+                ("graph_steps", C.c_int), ("cycle_growths", C.c_int)]
 
 
 class bem_request(C.Structure):

@@ -174,9 +174,17 @@ void* DevArena::raw(size_t bytes) {
     }
     ctx_->used += bytes;
   }
+  const auto t0 = std::chrono::steady_clock::now();
   for (void* q : evict) (void)hipFree(q);
+  if (verbose() && !evict.empty())
+    std::fprintf(stderr, "[bem] alloc: evicted %zu idle blocks in %.2f ms\n", evict.size(),
+                 std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
   if (!p) {
+    const auto t1 = std::chrono::steady_clock::now();
     hipError_t e = hipMalloc(&p, bytes);
+    if (verbose())
+      std::fprintf(stderr, "[bem] alloc: hipMalloc %.1f MB in %.2f ms\n", double(bytes) / 1e6,
+                   std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t1).count());
     if (e != hipSuccess) {
       (void)hipGetLastError();
       // the device may hold idle blocks of other contexts' sizes: drop ours and retry once
@@ -1740,20 +1748,8 @@ struct BGmres {
   }
   BGmres(DevArena& mem, int64_t n_, int m_, int R, void* pin) : n(n_), m(m_), Rmax(R) {
     ldv = pad64(n);
-    ldh = m + 2;
-    hs = int64_t(m + 1) * ldh;
-    V = mem.alloc<double2>(size_t(m + 1) * R * ldv);
-    H = mem.alloc<double2>(size_t(R) * hs);   // Hessenberg columns as finished
-    HR = mem.alloc<double2>(size_t(R) * hs);  // the same rotated to triangular (Givens)
-    cs = mem.alloc<double2>(size_t(R) * (m + 1));
-    sn = mem.alloc<double2>(size_t(R) * (m + 1));
-    y = mem.alloc<double2>(size_t(R) * (m + 1));
-    g = mem.alloc<double2>(size_t(R) * (m + 2));
+    alloc_cycle(mem);
     nrm = mem.alloc<double2>(R);
-    part = mem.alloc<double2>(size_t(R) * (m + 1) * bkry_chunks(n));
-    part2 = mem.alloc<double2>(size_t(R) * (m + 1) * bkry_chunks(n));
-    cstride = 2 * int64_t(m + 2);
-    coef = mem.alloc<double2>(size_t(R) * cstride);
     rinv = mem.alloc<double>(R);
     Z = mem.alloc<double2>(size_t(R) * ldv);
     U = mem.alloc<double2>(size_t(R) * ldv);
@@ -1772,6 +1768,34 @@ struct BGmres {
     h_idx = h_jr + R;
     h_fz = h_idx + R;  // two slots of R
     for (auto& e : ev) BEM_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
+  // the arrays whose size follows the cycle length m: basis, Hessenberg matrices, rotations,
+  // projections and reorthogonalisation coefficients
+  void alloc_cycle(DevArena& mem) {
+    const int R = Rmax;
+    ldh = m + 2;
+    hs = int64_t(m + 1) * ldh;
+    V = mem.alloc<double2>(size_t(m + 1) * R * ldv);
+    H = mem.alloc<double2>(size_t(R) * hs);   // Hessenberg columns as finished
+    HR = mem.alloc<double2>(size_t(R) * hs);  // the same rotated to triangular (Givens)
+    cs = mem.alloc<double2>(size_t(R) * (m + 1));
+    sn = mem.alloc<double2>(size_t(R) * (m + 1));
+    y = mem.alloc<double2>(size_t(R) * (m + 1));
+    g = mem.alloc<double2>(size_t(R) * (m + 2));
+    part = mem.alloc<double2>(size_t(R) * (m + 1) * bkry_chunks(n));
+    part2 = mem.alloc<double2>(size_t(R) * (m + 1) * bkry_chunks(n));
+    cstride = 2 * int64_t(m + 2);
+    coef = mem.alloc<double2>(size_t(R) * cstride);
+  }
+  // A longer cycle for the same columns (between GMRES calls): the cycle's arrays are made anew
+  // for m_ steps and the old ones returned to the arena.
+  void grow(DevArena& mem, int m_) {
+    for (void* p : {static_cast<void*>(V), static_cast<void*>(H), static_cast<void*>(HR), static_cast<void*>(cs),
+                    static_cast<void*>(sn), static_cast<void*>(y), static_cast<void*>(g), static_cast<void*>(part),
+                    static_cast<void*>(part2), static_cast<void*>(coef)})
+      mem.release(p);
+    m = m_;
+    alloc_cycle(mem);
   }
   ~BGmres() {
     for (auto& e : ev)
@@ -2194,13 +2218,15 @@ size_t estimate_request_bytes(int64_t nt, int64_t nobj, int precision, int resta
   return size_t(std::max(assembly, dense + inner + solve) + 64.0 * 1024 * 1024);
 }
 
+constexpr int kMaxAutoRestart = 1000;
+
 int auto_restart(int64_t N, int64_t nexc) {
   // the longest cycle (at most 1000 steps, at least 100) whose Krylov basis of the batch stays
   // under kAutoKrylovBytes: restarts discard the Krylov space, and the hard (electrically large,
   // high-contrast) problems converge in far fewer steps with long cycles
   const double per_step = 16.0 * double(std::min<int64_t>(std::max<int64_t>(nexc, 1), kMaxBatch)) * double(pad64(N));
   const double m = std::floor(kAutoKrylovBytes / per_step) - 1.0;
-  return int(std::max(100.0, std::min(1000.0, m)));
+  return int(std::max(100.0, std::min(double(kMaxAutoRestart), m)));
 }
 
 int solve_op(OpObj& op, const bem_excitation* exc, int64_t nexc, const bem_solve_opts& opts_in, bem_c64* Hout,
@@ -2395,7 +2421,30 @@ int solve_op(OpObj& op, const bem_excitation* exc, int64_t nexc, const bem_solve
         else next.push_back(active[c]);
       }
       active.swap(next);
-      if (use32 && (stalled || sweep_failed) && !active.empty()) {
+      // A sweep that ran out of steps on an automatic cycle shortened by the basis budget: the
+      // next sweeps get a longer one (up to 1000 steps, the basis within a quarter of the
+      // context's free budget), in the same precision.  Restarted GMRES can stall on a short
+      // cycle where a long one converges (a 14700-triangle ellipsoid at k0 a = 9.35 with 53 plane
+      // waves: 1e-3 after 3000 steps of 159-step cycles, 1e-6 after 535 steps of one cycle).
+      bool grown = false;
+      if (sweep_failed && !active.empty() && opts_in.restart <= 0 && bw.m < kMaxAutoRestart) {
+        size_t avail;
+        {
+          std::lock_guard<std::mutex> g(op.ctx->mu);
+          avail = op.ctx->budget > op.ctx->used ? op.ctx->budget - op.ctx->used : 0;
+        }
+        const double per_step = 16.0 * double(Rb) * double(ldN);
+        const int m2 = int(std::min(double(kMaxAutoRestart), std::floor(0.25 * double(avail) / per_step) - 1.0));
+        if (m2 >= bw.m + bw.m / 2) {
+          if (verbose()) std::fprintf(stderr, "[bem] sweep ran out on %d-step cycles: %d-step cycles from here on\n",
+                                      bw.m, m2);
+          bw.grow(tmp, m2);
+          opts.restart = m2;
+          grown = true;
+          ++inf.cycle_growths;
+        }
+      }
+      if (use32 && (stalled || sweep_failed) && !active.empty() && !grown) {
         use32 = false;
         if (verbose()) std::fprintf(stderr, "[bem] mixed sweep stalled: float64 products from here on\n");
       }

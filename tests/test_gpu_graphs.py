@@ -1,6 +1,7 @@
 """Captured Arnoldi step products (HIP graphs): solves whose step products are replayed from a
 captured graph give bitwise the currents of the same solves with direct launches (BEM_GRAPH=0),
-in float64, mixed precision (a second graph for the relaxed products) and the eAEFIE
+in float64, mixed precision (a second graph for the relaxed products), BEM_FP32 (float32
+entries in float64 arithmetic, then float32 products) and the eAEFIE
 formulation, for one and for five plane waves with restarts short enough that the batch is
 compacted (a graph per column count).  Every replay sits between eager launches and host
 synchronisations of the Krylov loop, and each is checked through the final currents.  A nested
@@ -45,6 +46,7 @@ CASES = [
     ("mixed_direct", B.BEM_MIXED, B.BEM_FORM_SLDM, B.BEM_INNER_DIRECT, 1, 100),
     ("fp64_5waves_restart8", B.BEM_FP64, B.BEM_FORM_SLDM, B.BEM_INNER_SCHUR, 5, 8),
     ("mixed_5waves_restart8", B.BEM_MIXED, B.BEM_FORM_SLDM, B.BEM_INNER_SCHUR, 5, 8),
+    ("fp32_5waves_restart8", B.BEM_FP32, B.BEM_FORM_SLDM, B.BEM_INNER_SCHUR, 5, 8),
     ("eaefie", B.BEM_FP64, B.BEM_FORM_EAEFIE, B.BEM_INNER_AUTO, 3, 100),
 ]
 
