@@ -1,21 +1,26 @@
-"""Benchmark: solves/s (and p50/p99 latency) of the whole dense BEM hot path on one MI355X.
+"""Benchmark: requests/s (and request p50/p99 latency) of the whole dense BEM hot path on one MI355X.
 
-One step = load the mesh (host topology), assemble every operator on the device (L^A, L^phi,
-K~ at the object and background wavenumbers, near corrections, gathers, the nested-solve
-inverse and the block preconditioner), and solve the final system for the plane-wave
-excitation to a 1e-6 relative float64 residual; the operator is released at the end of the
-step.  Workload: 5120-triangle dielectric sphere (icosphere level 4, radius 1 m, k0 a = 5,
-eps_r = 2.5 - 0.1j), x-polarised plane wave along -z - seeded synthetic input.
+Default workload: the serving mix (`meshgen.mixed_stream`, seed 5, Poisson arrivals at 2
+requests/s): spheres, 1.0/0.6/0.4 ellipsoids and cubes of 320-20000 triangles, eps_r 1.5-10,
+k0 a 0.5-10, 1-64 random plane waves each - seeded synthetic input.  One step = one request:
+load the mesh (host topology), assemble every operator on the device (L^A, L^phi, K~ at the
+object and background wavenumbers, near corrections, gathers, the nested-solve inverse and the
+block preconditioner) and solve the final system for all its plane waves to a 1e-6 relative
+float64 residual, the requests admitted by the HBM budget and overlapping on the device.  The
+same stream is served in BEM_FP32 (the headline), mixed precision and float64.  `--workload`
+selects one problem solved per step instead (c1, c2, c2x256, c3, spharr, c4), and
+`--serve-sweep` an arrival-rate sweep of the mix.
 
 Reported beside the throughput:
-  roofline      the dominant kernel class over the timed region, measured with HIP events on
-                its launch stream (library profiler): achieved algorithmic GB/s vs 8 TB/s HBM
-                for the GEMV, TFLOP/s vs the matrix peak for the Gauss-Jordan update and the
-                GEMMs, with the measured HBM bytes per launch (rocprofv3 counters) beside it;
+  roofline      the dominant kernel class of a sequential pass over the timed requests,
+                measured with HIP events on its launch stream (library profiler): achieved
+                algorithmic TFLOP/s vs the matrix peak for the GEMMs and the Gauss-Jordan
+                update, GB/s vs 8 TB/s HBM for the GEMV, with the HBM bytes per launch from
+                rocprofv3 counters beside it;
   fill_GBps     bytes of the float64 dense blocks written / device fill time;
-  cpu_baseline  the float64 CPU oracle on a bounded sample of the same workload (a subset of
-                test triangles of every fill, and a dense LU of a smaller matrix), scaled to
-                solves/s.
+  cpu_baseline  the float64 CPU oracle solving whole requests of the stream, smallest first,
+                for about 20 s of host time (fills over every host core, augmented system by
+                LAPACK LU), as solves/s.
 """
 from __future__ import annotations
 
@@ -274,7 +279,8 @@ def _serve_once(B, stream, prec, args):
             try:
                 rc, info = B.bem_poll(ctx, tk)
             except B.BemError as e:
-                rc, info = e.args[0], None
+                rc, info = e.code, None
+                log(f"  {pending[tk][2].name}: {e}")
             if rc != B.BEM_PENDING:
                 _, r, w = pending.pop(tk)
                 recs.append({"name": w.name, "nt": len(w.tri), "nexc": len(w.khat), "status": int(rc) if isinstance(rc, int) else -99,
@@ -367,7 +373,8 @@ def run_serve(args) -> int:
     GMRES to the residual tolerance for all its plane waves), admitted by the HBM budget and
     overlapping on the device.  value = completed requests per second of wall time from the
     first timed arrival to the last completion; p50/p99 = request latency (submit to result).
-    The same stream is served in mixed precision (the headline) and in float64."""
+    The same stream is served in each precision of --serve-precisions, the first being the
+    headline (BEM_FP32 by default, then mixed and float64)."""
     import numpy as np
 
     import meshgen
@@ -389,7 +396,7 @@ def run_serve(args) -> int:
         log(f"serving {len(timed)} requests ({prec_name}) after {args.warmup} warm-up requests ...")
         recs, wall, comb = _serve_once(B, stream, prec, args)
         ok = [r for r in recs if r["status"] == B.BEM_OK]
-        lat = [r["latency"] for r in recs]
+        lat = [r["latency"] for r in recs if math.isfinite(r["latency"])] or [float("nan")]
         runs[prec_name] = {"value": len(ok) / wall, "wall_s": wall, "converged": len(ok), "requests": len(recs),
                            "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
                            "excitation_solves_per_s": sum(r["nexc"] for r in ok) / wall,
@@ -444,6 +451,60 @@ def run_serve(args) -> int:
     return 0 if not m["failed"] else 1
 
 
+def run_serve_sweep(args) -> int:
+    """Arrival-rate sweep of the serving mix: the same W + K requests (the Poisson draws of
+    `--serve-seed`) first all at once (saturated throughput: K over the wall time to the last
+    completion), then at each factor of `--serve-sweep` times that rate, the arrival times
+    rescaled (the same requests in the same order).  Prints one JSON line with throughput and
+    request-latency percentiles per rate; no profiled pass, no CPU baseline."""
+    import numpy as np
+
+    import meshgen
+    import paper_2106_06184_amd as B
+
+    stream = meshgen.mixed_stream(args.warmup + args.steps, rate_hz=args.serve_rate, seed=args.serve_seed)
+    precs = {"fp32": B.BEM_FP32, "mixed": B.BEM_MIXED, "fp64": B.BEM_FP64}
+    head = args.serve_precisions.split(",")[0]
+    prec = precs[head]
+
+    def one(rescaled, label):
+        log(f"serving {args.steps} requests ({head}, {label}) after {args.warmup} warm-up requests ...")
+        recs, wall, _ = _serve_once(B, rescaled, prec, args)
+        ok = [r for r in recs if r["status"] == B.BEM_OK]
+        lat = [r["latency"] for r in recs if math.isfinite(r["latency"])] or [float("nan")]
+        row = {"requests_per_s": len(ok) / wall, "wall_s": wall, "converged": len(ok), "requests": len(recs),
+               "p50_s": float(np.percentile(lat, 50)), "p90_s": float(np.percentile(lat, 90)),
+               "p99_s": float(np.percentile(lat, 99)),
+               "excitation_solves_per_s": sum(r["nexc"] for r in ok) / wall}
+        log(f"  {label}: {row['requests_per_s']:.3f} requests/s, p50 {row['p50_s']:.2f} s, "
+            f"p99 {row['p99_s']:.2f} s, {len(ok)}/{len(recs)} converged")
+        return row
+
+    if args.serve_sat > 0:
+        sat = args.serve_sat
+        sat_row = None
+    else:
+        t0 = stream[args.warmup][0]
+        sat_row = one([(t0, w) for _, w in stream], "all at once")
+        sat = sat_row["requests_per_s"]
+    t0 = stream[args.warmup][0]
+    rows = []
+    for f in [float(x) for x in args.serve_sweep.split(",") if x and x != "sat"]:
+        rate = f * sat
+        scale = args.serve_rate / rate
+        rescaled = [(t0 + (at - t0) * scale, w) for at, w in stream]
+        row = one(rescaled, f"{f:.2f} x saturation = {rate:.3f} requests/s")
+        row.update({"factor": f, "arrival_rate_per_s": rate})
+        rows.append(row)
+    timed = [w for _, w in stream[args.warmup:]]
+    print(json.dumps({"sweep": "serving mix arrival rate", "precision": head, "requests": args.steps,
+                      "warmup": args.warmup, "seed": args.serve_seed, "tol": args.tol,
+                      "saturated_requests_per_s": sat, "saturated": sat_row, "rates": rows,
+                      "triangles": [len(w.tri) for w in timed], "plane_waves": [len(w.khat) for w in timed]}),
+          flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -476,6 +537,12 @@ def main() -> int:
                          "for rocprofv3 kernel traces and counters of the roofline's launches)")
     ap.add_argument("--serve-precisions", default="fp32,mixed,fp64",
                     help="precisions the serving mix is run in, the first one being the headline")
+    ap.add_argument("--serve-sweep", default="",
+                    help="comma-separated factors of the saturated throughput: serve the mix at each of "
+                         "those arrival rates (after one run with every request arriving at once) and print "
+                         "the sweep instead of the benchmark line ('sat': only the run all at once)")
+    ap.add_argument("--serve-sat", type=float, default=0.0,
+                    help="saturated throughput (requests/s) for --serve-sweep instead of measuring it")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the plain copy used to calibrate the HBM byte counters")
     args = ap.parse_args()
@@ -486,7 +553,7 @@ def main() -> int:
               f"design note, not a run.", file=sys.stderr)
         return 2
     if args.workload == "serve":
-        return run_serve(args)
+        return run_serve_sweep(args) if args.serve_sweep else run_serve(args)
 
     import numpy as np
     import torch

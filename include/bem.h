@@ -85,7 +85,8 @@ enum {
 /* Context.  device >= 0 selects a HIP device; device = -1 gives a host-only
  * context on which mesh loading, validation and the mesh queries work but
  * assemble/apply/solve return BEM_E_DEVICE.  hbm_budget_bytes = 0 means the
- * whole free device memory.  Errors: BEM_E_DEVICE (no such device). */
+ * free device memory less a reserve for the HIP runtime (1/32 of the device, at
+ * least 4 GiB).  Errors: BEM_E_DEVICE (no such device). */
 int bem_create(int device, size_t hbm_budget_bytes, bem_ctx** out);
 void bem_destroy(bem_ctx* ctx);
 /* Message of the last failing call on this thread; valid until the next call. */

@@ -89,7 +89,11 @@ int bem_create(int device, size_t hbm_budget_bytes, bem_ctx** out) {
       BEM_HIP(hipHostMalloc(reinterpret_cast<void**>(&ctx->pinned), bem::kPinnedBytes, hipHostMallocDefault));
       size_t fr = 0, tot = 0;
       BEM_HIP(hipMemGetInfo(&fr, &tot));
-      ctx->budget = hbm_budget_bytes ? hbm_budget_bytes : fr;
+      // the default leaves the HIP runtime its own room (scratch of the queues, kernel
+      // arguments, other libraries): the block cache keeps freed blocks up to the budget, and a
+      // budget of all free memory has starved the runtime of queue resources
+      const size_t headroom = std::max<size_t>(size_t(4) << 30, tot / 32);
+      ctx->budget = hbm_budget_bytes ? hbm_budget_bytes : (fr > 2 * headroom ? fr - headroom : fr / 2);
     } else {
       ctx->budget = hbm_budget_bytes;
     }

@@ -158,6 +158,9 @@ struct OpObj {
   double2* work = nullptr;  // vector workspace
   int64_t work_len = 0;
   ProductCombiner* comb = nullptr;  // set by the serving loop
+  // set by the serving loop: adds bytes to the request's admitted reservation, false when they
+  // do not fit next to the other admitted requests (memory a solve takes beyond its estimate)
+  std::function<bool(size_t)> reserve;
   hipStream_t stream = nullptr;  // stream of the operator's work
   double* pinned = nullptr;      // pinned host scalars for convergence checks
 

@@ -8,6 +8,7 @@
 namespace bem {
 
 constexpr int kSlots = 4;
+constexpr int kNomemRetries = 2;  // reruns of a request that ran out of device memory beside others
 
 struct Request {
   // owned copies of the caller's inputs
@@ -20,7 +21,9 @@ struct Request {
   bem_solve_opts opts{};
   bem_c64 *H = nullptr, *E = nullptr, *rho = nullptr;
   // state
-  size_t bytes = 0;
+  size_t bytes = 0;   // admitted reservation (the estimate, plus what the solve added)
+  size_t bytes0 = 0;  // the estimate
+  int nomem_retries = 0;
   int status = BEM_PENDING;
   std::string msg;
   bem_solve_info info{};
@@ -165,6 +168,7 @@ bem_ticket Server::submit(const bem_request& r) {
                                     r.opts.restart > 0 ? r.opts.restart : auto_restart(nunk, r.nexc),
                                     r.nexc, r.prob.formulation);
   if (q->bytes > ctx_->budget) throw Error(BEM_E_NOMEM, "request can never fit the device budget");
+  q->bytes0 = q->bytes;
   q->t_submit = std::chrono::steady_clock::now();
   std::lock_guard<std::mutex> g(mu_);
   const bem_ticket t = next_++;
@@ -202,21 +206,23 @@ void Server::worker(int slot) {
     {
       std::unique_lock<std::mutex> lk(mu_);
       // admit the oldest request whose estimate fits next to the running ones (first-fit
-      // from the head keeps small requests moving while a large one waits for memory)
-      cv_.wait(lk, [&] {
-        if (stop_) return true;
-        for (auto& r : queue_)
-          if (reserved_ + r->bytes <= ctx_->budget) return true;
-        return false;
-      });
-      if (stop_) break;
-      for (auto it = queue_.begin(); it != queue_.end(); ++it) {
-        if (reserved_ + (*it)->bytes <= ctx_->budget) {
-          q = *it;
-          queue_.erase(it);
-          break;
+      // from the head keeps small requests moving while a large one waits for memory); a
+      // request that ran out of device memory beside others runs alone, and nothing queued
+      // behind it starts before it
+      auto pick = [&]() {
+        if (exclusive_) return queue_.end();
+        for (auto it = queue_.begin(); it != queue_.end(); ++it) {
+          if ((*it)->nomem_retries > 0) return active_ == 0 ? it : queue_.end();
+          if (reserved_ + (*it)->bytes <= ctx_->budget) return it;
         }
-      }
+        return queue_.end();
+      };
+      cv_.wait(lk, [&] { return stop_ || pick() != queue_.end(); });
+      if (stop_) break;
+      const auto it = pick();
+      q = *it;
+      queue_.erase(it);
+      if (q->nomem_retries > 0) exclusive_ = true;
       reserved_ += q->bytes;
       ++active_;
     }
@@ -239,8 +245,16 @@ void Server::worker(int slot) {
         ~Joined() { c.leave(); }
       } joined(comb_);
       op.comb = &comb_;
+      op.reserve = [this, &q](size_t extra) {
+        std::lock_guard<std::mutex> g(mu_);
+        if (reserved_ + extra > ctx_->budget) return false;
+        reserved_ += extra;
+        q->bytes += extra;  // released with the rest of the request's reservation
+        return true;
+      };
       status = solve_op(op, q->exc.data(), int64_t(q->exc.size()), q->opts, q->H, q->E, q->rho, &info, st);
       op.comb = nullptr;
+      op.reserve = nullptr;
       info.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - q->t_submit).count();
     } catch (const Error& e) {
       status = e.code;
@@ -251,11 +265,20 @@ void Server::worker(int slot) {
     }
     {
       std::lock_guard<std::mutex> g(mu_);
-      q->status = status;
-      q->msg = msg;
-      q->info = info;
       reserved_ -= q->bytes;
       --active_;
+      if (q->nomem_retries > 0) exclusive_ = false;
+      if (status == BEM_E_NOMEM && active_ > 0 && q->nomem_retries < kNomemRetries) {
+        // the estimates let the device fill beyond what was free: the request waits at the
+        // head of the queue and runs again alone
+        ++q->nomem_retries;
+        q->bytes = q->bytes0;
+        queue_.push_front(q);
+      } else {
+        q->status = status;
+        q->msg = msg;
+        q->info = info;
+      }
     }
     cv_.notify_all();
     done_cv_.notify_all();

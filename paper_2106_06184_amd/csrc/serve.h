@@ -80,6 +80,7 @@ class Server {
   std::vector<std::thread> threads_;
   size_t reserved_ = 0;
   int active_ = 0;
+  bool exclusive_ = false;  // a request rerun after running out of device memory is solving alone
   bool stop_ = false;
   bem_ticket next_ = 1;
 };

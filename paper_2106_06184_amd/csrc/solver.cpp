@@ -2423,9 +2423,10 @@ int solve_op(OpObj& op, const bem_excitation* exc, int64_t nexc, const bem_solve
       active.swap(next);
       // A sweep that ran out of steps on an automatic cycle shortened by the basis budget: the
       // next sweeps get a longer one (up to 1000 steps, the basis within a quarter of the
-      // context's free budget), in the same precision.  Restarted GMRES can stall on a short
-      // cycle where a long one converges (a 14700-triangle ellipsoid at k0 a = 9.35 with 53 plane
-      // waves: 1e-3 after 3000 steps of 159-step cycles, 1e-6 after 535 steps of one cycle).
+      // context's free budget and, when serving, within what the other admitted requests leave),
+      // in the same precision.  Restarted GMRES can stall on a short cycle where a long one
+      // converges (a 14700-triangle ellipsoid at k0 a = 9.35 with 53 plane waves: 1e-3 after
+      // 3000 steps of 159-step cycles, 1e-6 after 535 steps of one cycle).
       bool grown = false;
       if (sweep_failed && !active.empty() && opts_in.restart <= 0 && bw.m < kMaxAutoRestart) {
         size_t avail;
@@ -2433,8 +2434,11 @@ int solve_op(OpObj& op, const bem_excitation* exc, int64_t nexc, const bem_solve
           std::lock_guard<std::mutex> g(op.ctx->mu);
           avail = op.ctx->budget > op.ctx->used ? op.ctx->budget - op.ctx->used : 0;
         }
-        const double per_step = 16.0 * double(Rb) * double(ldN);
-        const int m2 = int(std::min(double(kMaxAutoRestart), std::floor(0.25 * double(avail) / per_step) - 1.0));
+        // per step: a basis vector, two projection rows and the Hessenberg entries per column
+        const double per_step = 16.0 * double(Rb) * (double(ldN) + 2.0 * double(bkry_chunks(N)) + 4.0 * 1002.0);
+        int m2 = int(std::min(double(kMaxAutoRestart), std::floor(0.25 * double(avail) / per_step) - 1.0));
+        while (m2 >= bw.m + bw.m / 2 && op.reserve && !op.reserve(size_t(per_step * double(m2 - bw.m))))
+          m2 = bw.m + (m2 - bw.m) / 2;
         if (m2 >= bw.m + bw.m / 2) {
           if (verbose()) std::fprintf(stderr, "[bem] sweep ran out on %d-step cycles: %d-step cycles from here on\n",
                                       bw.m, m2);
