@@ -575,14 +575,14 @@ std::vector<Var> vars_f32(int tn) {
   }
 }
 
-// 3M path (float64 arithmetic, 9 columns and more): complex column tiles of 16, 24, 32, 48 or
-// 64.  Up to 8 columns the embedding's 16-real-column tile pads less (and those products are
-// bound by the matrix read).
+// 3M path (float64 arithmetic, 9 columns and more): complex column tiles in steps of 4 up to 32
+// columns and of 8 up to 64 (at most 3 or 7 padding columns).  Up to 8 columns the embedding's
+// 16-real-column tile pads less (and those products are bound by the matrix read).
 constexpr int kMin3M = 9;
 int ntile_3m(int64_t nrhs) {
-  for (int t : {16, 24, 32, 48})
+  for (int t : {12, 16, 20, 24, 28, 32, 40, 48, 56})
     if (nrhs <= t) return t;
-  // above 64 columns: the tile of 64, 48 or 32 that pads least (ties to the wider)
+  // above 56 columns: the tile of 64, 48 or 32 that pads least (ties to the wider)
   int best = 64;
   for (int t : {48, 32})
     if ((nrhs + t - 1) / t * t < (nrhs + best - 1) / best * best) best = t;
@@ -595,10 +595,15 @@ struct Var3 {
 // variants per tile, canonical first (its row tile sets the K split)
 std::vector<Var3> vars_3m(int tn) {
   switch (tn) {
+    case 12: return {{1, 2, 3, true}, {1, 4, 3, true}};
     case 16: return {{1, 8, 1, false}, {1, 2, 4, true}};
+    case 20: return {{1, 2, 5, true}, {1, 4, 5, true}};
     case 24: return {{1, 2, 6, true}, {2, 4, 3, true}};
+    case 28: return {{1, 2, 7, true}};
     case 32: return {{1, 8, 2, false}, {2, 8, 1, false}, {1, 2, 8, true}};
+    case 40: return {{1, 2, 10, true}, {2, 2, 5, true}};
     case 48: return {{1, 8, 3, false}, {2, 4, 6, true}};
+    case 56: return {{2, 2, 7, true}};
     default: return {{2, 8, 2, false}, {4, 8, 1, false}, {2, 2, 8, true}, {4, 4, 4, true}};
   }
 }
@@ -619,37 +624,52 @@ void launch_f64_variant(const GemmLaunch& l, const GemmDesc& d, const double* Bm
                      l.kc, l.ntn, l.S, l.P, d.Y, d.ldy, d.nrhs, d.alpha, d.accumulate, l.xcd);
 }
 
+constexpr int code3m(int wn, int ni, int nj, bool bsh) { return ((wn * 16 + ni) * 32 + nj) * 2 + (bsh ? 1 : 0); }
+
 template <typename TA, bool AL>
 void launch_3m_variant(const Var3& v, const GemmLaunch& l, const GemmDesc& d, hipStream_t st) {
   const TA* A = static_cast<const TA*>(d.A);
 #define BEM_G3M(WN, NI, NJ, BS)                                                                                \
   hipLaunchKernelGGL((dev::k_gemm3m_f64<TA, AL, WN, NI, NJ, BS>), l.g, dim3(256), 0, st, A, d.lda, d.X, d.ldx, \
                      d.rows, d.cols, l.kc, l.ntn, l.S, l.P, l.ldb, d.Y, d.ldy, d.nrhs, d.alpha, d.accumulate, l.xcd)
-  const int code = v.wn * 1000 + v.ni * 100 + v.nj * 10 + (v.bsh ? 1 : 0);
+  const int code = code3m(v.wn, v.ni, v.nj, v.bsh);
   if constexpr (AL) {
     switch (code) {
-      case 1810: BEM_G3M(1, 8, 1, false); break;
-      case 1241: BEM_G3M(1, 2, 4, true); break;
-      case 1261: BEM_G3M(1, 2, 6, true); break;
-      case 2431: BEM_G3M(2, 4, 3, true); break;
-      case 1820: BEM_G3M(1, 8, 2, false); break;
-      case 2810: BEM_G3M(2, 8, 1, false); break;
-      case 1281: BEM_G3M(1, 2, 8, true); break;
-      case 1830: BEM_G3M(1, 8, 3, false); break;
-      case 2461: BEM_G3M(2, 4, 6, true); break;
-      case 2820: BEM_G3M(2, 8, 2, false); break;
-      case 4810: BEM_G3M(4, 8, 1, false); break;
-      case 2281: BEM_G3M(2, 2, 8, true); break;
-      case 4441: BEM_G3M(4, 4, 4, true); break;
+      case code3m(1, 2, 3, true): BEM_G3M(1, 2, 3, true); break;
+      case code3m(1, 4, 3, true): BEM_G3M(1, 4, 3, true); break;
+      case code3m(1, 8, 1, false): BEM_G3M(1, 8, 1, false); break;
+      case code3m(1, 2, 4, true): BEM_G3M(1, 2, 4, true); break;
+      case code3m(1, 2, 5, true): BEM_G3M(1, 2, 5, true); break;
+      case code3m(1, 4, 5, true): BEM_G3M(1, 4, 5, true); break;
+      case code3m(1, 2, 6, true): BEM_G3M(1, 2, 6, true); break;
+      case code3m(2, 4, 3, true): BEM_G3M(2, 4, 3, true); break;
+      case code3m(1, 2, 7, true): BEM_G3M(1, 2, 7, true); break;
+      case code3m(1, 8, 2, false): BEM_G3M(1, 8, 2, false); break;
+      case code3m(2, 8, 1, false): BEM_G3M(2, 8, 1, false); break;
+      case code3m(1, 2, 8, true): BEM_G3M(1, 2, 8, true); break;
+      case code3m(1, 2, 10, true): BEM_G3M(1, 2, 10, true); break;
+      case code3m(2, 2, 5, true): BEM_G3M(2, 2, 5, true); break;
+      case code3m(1, 8, 3, false): BEM_G3M(1, 8, 3, false); break;
+      case code3m(2, 4, 6, true): BEM_G3M(2, 4, 6, true); break;
+      case code3m(2, 2, 7, true): BEM_G3M(2, 2, 7, true); break;
+      case code3m(2, 8, 2, false): BEM_G3M(2, 8, 2, false); break;
+      case code3m(4, 8, 1, false): BEM_G3M(4, 8, 1, false); break;
+      case code3m(2, 2, 8, true): BEM_G3M(2, 2, 8, true); break;
+      case code3m(4, 4, 4, true): BEM_G3M(4, 4, 4, true); break;
       default: throw Error(BEM_E_INVALID, "no such 3M GEMM variant");
     }
   } else {
     switch (code) {  // unaligned operands: canonical variants only
-      case 1810: BEM_G3M(1, 8, 1, false); break;
-      case 1261: BEM_G3M(1, 2, 6, true); break;
-      case 1820: BEM_G3M(1, 8, 2, false); break;
-      case 1830: BEM_G3M(1, 8, 3, false); break;
-      case 2820: BEM_G3M(2, 8, 2, false); break;
+      case code3m(1, 2, 3, true): BEM_G3M(1, 2, 3, true); break;
+      case code3m(1, 8, 1, false): BEM_G3M(1, 8, 1, false); break;
+      case code3m(1, 2, 5, true): BEM_G3M(1, 2, 5, true); break;
+      case code3m(1, 2, 6, true): BEM_G3M(1, 2, 6, true); break;
+      case code3m(1, 2, 7, true): BEM_G3M(1, 2, 7, true); break;
+      case code3m(1, 8, 2, false): BEM_G3M(1, 8, 2, false); break;
+      case code3m(1, 2, 10, true): BEM_G3M(1, 2, 10, true); break;
+      case code3m(1, 8, 3, false): BEM_G3M(1, 8, 3, false); break;
+      case code3m(2, 2, 7, true): BEM_G3M(2, 2, 7, true); break;
+      case code3m(2, 8, 2, false): BEM_G3M(2, 8, 2, false); break;
       default: throw Error(BEM_E_INVALID, "no such 3M GEMM variant");
     }
   }
@@ -661,10 +681,15 @@ void launch_3m_variant(const Var3& v, const GemmLaunch& l, const GemmDesc& d, hi
 template <typename TA, bool AL>
 const void* canonical_3m(int tn) {
   switch (tn) {
+    case 12: return reinterpret_cast<const void*>(&dev::k_gemm3m_f64<TA, AL, 1, 2, 3, true>);
     case 16: return reinterpret_cast<const void*>(&dev::k_gemm3m_f64<TA, AL, 1, 8, 1, false>);
+    case 20: return reinterpret_cast<const void*>(&dev::k_gemm3m_f64<TA, AL, 1, 2, 5, true>);
     case 24: return reinterpret_cast<const void*>(&dev::k_gemm3m_f64<TA, AL, 1, 2, 6, true>);
+    case 28: return reinterpret_cast<const void*>(&dev::k_gemm3m_f64<TA, AL, 1, 2, 7, true>);
     case 32: return reinterpret_cast<const void*>(&dev::k_gemm3m_f64<TA, AL, 1, 8, 2, false>);
+    case 40: return reinterpret_cast<const void*>(&dev::k_gemm3m_f64<TA, AL, 1, 2, 10, true>);
     case 48: return reinterpret_cast<const void*>(&dev::k_gemm3m_f64<TA, AL, 1, 8, 3, false>);
+    case 56: return reinterpret_cast<const void*>(&dev::k_gemm3m_f64<TA, AL, 2, 2, 7, true>);
     default: return reinterpret_cast<const void*>(&dev::k_gemm3m_f64<TA, AL, 2, 8, 2, false>);
   }
 }

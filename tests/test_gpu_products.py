@@ -1,7 +1,9 @@
 """Dense products through bem_apply against numpy on the exported blocks, for every column count
-that selects a different kernel (grouped GEMV for 1-2 columns; matrix-core GEMMs with real N tiles
-of 16, 32, 48, 64, 96 and 128 columns in float64 and 32, 64, 96 and 128 in float32, with and
-without the split-K sum), in float64 and in float32 storage (BEM_FP32: float32 vectors in and
+that selects a different kernel (grouped GEMV for 1-2 columns; matrix-core GEMMs: in float64
+arithmetic the embedding's 16-real-column tile for 3-8 columns and 3M tiles of 12, 16, 20, 24,
+28, 32, 40, 48, 56 and 64 complex columns above, each at its full width and one column past it;
+in float32 real N tiles of 32, 64, 96 and 128 columns; with and without the split-K sum), in
+float64 and in float32 storage (BEM_FP32: float32 vectors in and
 out); the launch variants the tuner chooses between give bitwise the same products; and the
 BEM_FP32 precision's solve against the oracle.
 
@@ -19,7 +21,7 @@ from tests.bemutil import edge_perm, rel
 
 pytestmark = pytest.mark.gpu
 
-COLS = [1, 2, 3, 8, 9, 16, 17, 24, 25, 32, 33, 48, 49, 64, 65, 130]
+COLS = [1, 2, 3, 8, 9, 12, 13, 16, 17, 20, 21, 24, 25, 28, 29, 32, 33, 40, 41, 48, 49, 56, 57, 64, 65, 130]
 
 
 @pytest.fixture(scope="module")
@@ -97,7 +99,7 @@ def test_float32_products(torch_mod, ops, R, level):
     assert err < 2e-6, err
 
 
-@pytest.mark.parametrize("R", [1, 5, 12, 20, 30, 40, 60, 70])
+@pytest.mark.parametrize("R", [1, 5, 12, 20, 28, 30, 40, 56, 60, 70])
 def test_launch_variants_agree_bitwise(torch_mod, ops, R):
     """The same product repeated 28 times: the first launches of a shape class are the tuner's
     timed trials of every candidate (rows per workgroup of the GEMV; tile shape, operand layout
