@@ -2435,7 +2435,8 @@ int solve_op(OpObj& op, const bem_excitation* exc, int64_t nexc, const bem_solve
           avail = op.ctx->budget > op.ctx->used ? op.ctx->budget - op.ctx->used : 0;
         }
         // per step: a basis vector, two projection rows and the Hessenberg entries per column
-        const double per_step = 16.0 * double(Rb) * (double(ldN) + 2.0 * double(bkry_chunks(N)) + 4.0 * 1002.0);
+        const double per_step =
+            16.0 * double(Rb) * (double(ldN) + 2.0 * double(bkry_chunks(N)) + 4.0 * (kMaxAutoRestart + 2));
         int m2 = int(std::min(double(kMaxAutoRestart), std::floor(0.25 * double(avail) / per_step) - 1.0));
         while (m2 >= bw.m + bw.m / 2 && op.reserve && !op.reserve(size_t(per_step * double(m2 - bw.m))))
           m2 = bw.m + (m2 - bw.m) / 2;
