@@ -451,6 +451,14 @@ def run_serve(args) -> int:
     return 0 if not m["failed"] else 1
 
 
+def rescale_arrivals(stream, t0: float, rate_from: float, rate_to: float):
+    """The same requests in the same order arriving at `rate_to` instead of `rate_from`: every
+    arrival's offset from t0 (the first timed arrival) scaled by rate_from / rate_to, which turns
+    Poisson arrivals of one mean rate into those of the other."""
+    scale = rate_from / rate_to
+    return [(t0 + (at - t0) * scale, w) for at, w in stream]
+
+
 def run_serve_sweep(args) -> int:
     """Arrival-rate sweep of the serving mix: the same W + K requests (the Poisson draws of
     `--serve-seed`) first all at once (saturated throughput: K over the wall time to the last
@@ -491,8 +499,7 @@ def run_serve_sweep(args) -> int:
     rows = []
     for f in [float(x) for x in args.serve_sweep.split(",") if x and x != "sat"]:
         rate = f * sat
-        scale = args.serve_rate / rate
-        rescaled = [(t0 + (at - t0) * scale, w) for at, w in stream]
+        rescaled = rescale_arrivals(stream, t0, args.serve_rate, rate)
         row = one(rescaled, f"{f:.2f} x saturation = {rate:.3f} requests/s")
         row.update({"factor": f, "arrival_rate_per_s": rate})
         rows.append(row)

@@ -1,5 +1,6 @@
 """CPU tests of bench.py's host logic: the key under which measured HBM traffic is kept
-(a digest of a kernel's code regions) and the refusal of more than one GPU."""
+(a digest of a kernel's code regions), the arrival times of the rate sweep and the refusal of
+more than one GPU."""
 from __future__ import annotations
 
 import importlib.util
@@ -55,3 +56,24 @@ def test_more_than_one_gpu_is_refused():
                        timeout=120)
     assert r.returncode != 0
     assert "one GPU" in (r.stdout + r.stderr)
+
+
+def test_rescaled_arrivals_keep_the_requests_and_scale_the_rate():
+    """The sweep's streams: the same requests in the same order, the warm-up ones (before t0)
+    kept ahead, the gaps after the first timed arrival scaled so that the mean rate is the new
+    one (Poisson draws of mean gap 1/2 s at 2 requests/s become mean gap 1/0.5 s at 0.5)."""
+    import numpy as np
+
+    b = _bench()
+    rng = np.random.default_rng(1)
+    times = np.cumsum(rng.exponential(0.5, 2000))
+    stream = [(float(t), i) for i, t in enumerate(times)]
+    t0 = stream[4][0]
+    out = b.rescale_arrivals(stream, t0, 2.0, 0.5)
+    assert [w for _, w in out] == list(range(2000))
+    assert out[4][0] == t0
+    assert all(out[i][0] <= t0 for i in range(4))
+    gaps = np.diff([t for t, _ in out[4:]])
+    assert np.all(gaps > 0)
+    assert abs(gaps.mean() - 2.0) < 0.1
+    assert np.allclose(gaps, 4.0 * np.diff(times[4:]))
