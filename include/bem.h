@@ -305,7 +305,9 @@ int bem_solve(bem_ctx* ctx, bem_op_h op, const bem_excitation* exc, int64_t nexc
  * the output buffers (host), which must stay valid until bem_poll returns
  * something other than BEM_PENDING.  Requests are admitted while their
  * estimated device footprint fits the HBM budget; admitted requests progress
- * together and share batched product launches. */
+ * together and share batched product launches.  A request that runs out of
+ * device memory while others are solving is queued again at the head and rerun
+ * alone (at most twice) before BEM_E_NOMEM is reported for it. */
 typedef struct {
   const double* xyz; int64_t nv;
   const int32_t* tri; int64_t nt;
