@@ -1,6 +1,7 @@
 """CPU tests of the C ABI and the library's host logic (no device compute).
 
-The library must load and export every function include/bem.h declares; a host-only
+The library must load and export every function include/bem.h declares, and the binding's
+structs must have the header's fields, order, offsets and sizes; a host-only
 context (device = -1) validates meshes and builds the topology, which is compared with the
 oracle's independently built one (edge table, T+/T-, near pairs) on several mesh families.
 """
@@ -133,3 +134,56 @@ def test_translated_copies_detected(host_ctx):
         got = B.bem_mesh_copies(host_ctx, h)
         assert got.tolist() == want, (name, got)
         B.bem_release(host_ctx, h)
+
+
+def test_binding_structs_match_the_header_layout(tmp_path):
+    """Every struct the binding passes through the ABI has the header's size and field offsets:
+    a small C program built with the host compiler from include/bem.h prints them (a field
+    added on one side only would shift the others)."""
+    import ctypes as C
+    import shutil
+    import subprocess
+
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    structs = {"bem_c64": B.c64, "bem_material": B.bem_material, "bem_problem": B.bem_problem,
+               "bem_excitation": B.bem_excitation, "bem_solve_opts": B.bem_solve_opts,
+               "bem_solve_info": B.bem_solve_info, "bem_request": B.bem_request, "bem_op_stats": B.bem_op_stats}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "bem.h"', "int main(void) {"]
+    for cname, cls in structs.items():
+        lines.append(f'  printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", str(HEADER.parent), str(src), "-o", str(exe)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        cname, key, val = line.split()
+        got[(cname, key)] = int(val)
+    for cname, cls in structs.items():
+        assert got[(cname, "sizeof")] == C.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
+        # and the same fields in the same order (a trailing one could hide in the padding)
+        assert _header_fields(cname) == [f for f, _ in cls._fields_], cname
+
+
+def _header_fields(cname):
+    """Field names of `typedef struct { ... } cname;` in include/bem.h, in order."""
+    text = re.sub(r"/\*.*?\*/", "", HEADER.read_text(), flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    m = re.search(r"typedef struct \{([^{}]*)\}\s*" + cname + r"\s*;", text)
+    assert m, cname
+    names = []
+    for stmt in m.group(1).split(";"):
+        parts = [p.strip() for p in stmt.split(",") if p.strip()]
+        for i, part in enumerate(parts):
+            part = re.sub(r"\[[^\]]*\]", "", part)
+            ids = re.findall(r"[A-Za-z_][A-Za-z_0-9]*", part)
+            if ids:
+                names.append(ids[-1] if i == 0 else ids[0])
+    return names
